@@ -1,0 +1,226 @@
+"""ctypes front end of the serial FP64 CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU-baseline
+leg of the benchmark, never by the product package.  All arrays are host numpy
+float64 arrays in the r-fastest layout c = i + N_r (j + N_theta k).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so (serial, -O2, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-std=c99", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Grid(C.Structure):
+    _fields_ = [("nr", C.c_int), ("nt", C.c_int), ("np", C.c_int),
+                ("rf", C.POINTER(C.c_double)), ("tf", C.POINTER(C.c_double)),
+                ("pf", C.POINTER(C.c_double))]
+
+
+class _Opac(C.Structure):
+    _fields_ = [("nT", C.c_int), ("nnu", C.c_int), ("T", C.POINTER(C.c_double)),
+                ("kap", C.POINTER(C.c_double)), ("kapP", C.POINTER(C.c_double)),
+                ("kapR", C.POINTER(C.c_double))]
+
+
+class _Star(C.Structure):
+    _fields_ = [("R", C.c_double), ("Teff", C.c_double), ("F0", C.POINTER(C.c_double))]
+
+
+class _Fld(C.Structure):
+    _fields_ = [("dt", C.c_double), ("cV", C.c_double), ("Tbc", C.c_double),
+                ("Efloor", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB)
+        P = C.POINTER
+        dp = P(C.c_double)
+        L.og_star_bins.argtypes = [C.c_double, C.c_int, dp, dp]
+        L.og_raytrace.argtypes = [P(_Grid), P(_Opac), P(_Star), dp, dp, dp, dp, dp]
+        L.og_energy.argtypes = [P(_Grid), P(_Opac), P(_Fld), dp, dp, dp]
+        L.og_assemble.argtypes = [P(_Grid), P(_Opac), P(_Fld), dp, dp, dp, dp, dp,
+                                  dp, dp, dp, dp, dp, dp]
+        L.og_spmv.argtypes = [P(_Grid), dp, dp, dp]
+        L.og_relres.argtypes = [P(_Grid), dp, dp, dp]
+        L.og_relres.restype = C.c_double
+        L.og_cg.argtypes = [P(_Grid), dp, dp, dp, C.c_double, C.c_int, P(C.c_int), dp]
+        L.og_dense_solve.argtypes = [P(_Grid), dp, dp, dp]
+        L.og_newton.argtypes = [P(_Grid), P(_Opac), dp, dp, dp]
+        L.og_force.argtypes = [P(_Grid), P(_Opac), P(_Fld), dp, dp, dp, dp, dp, dp]
+        L.og_step.argtypes = [P(_Grid), P(_Opac), P(_Star), P(_Fld), dp, dp, dp, dp,
+                              C.c_double, C.c_int, C.c_int, P(C.c_int), dp]
+        L.og_kappa_nu.argtypes = [P(_Opac), C.c_double, C.c_int]
+        L.og_kappa_nu.restype = C.c_double
+        L.og_kappa_P.argtypes = [P(_Opac), C.c_double]
+        L.og_kappa_P.restype = C.c_double
+        L.og_kappa_R.argtypes = [P(_Opac), C.c_double]
+        L.og_kappa_R.restype = C.c_double
+        L.og_const_a.restype = C.c_double
+        L.og_const_c.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Problem:
+    """Holds the ctypes views of grid / opacity / star / FLD parameters for one problem."""
+
+    def __init__(self, r_face, th_face, ph_face, T_tab, kappa, kappa_P, kappa_R,
+                 R_star=None, F0=None, T_star=None, dt=1e9, c_V=None, T_bc=14.7, E_floor=None):
+        self._keep = [_f64(x) for x in (r_face, th_face, ph_face, T_tab, kappa, kappa_P, kappa_R)]
+        rf, tf, pf, Tt, kap, kP, kR = self._keep
+        self.shape = (len(rf) - 1, len(tf) - 1, len(pf) - 1)
+        self.n = int(np.prod(self.shape))
+        self.g = _Grid(self.shape[0], self.shape[1], self.shape[2], _p(rf), _p(tf), _p(pf))
+        self.op = _Opac(len(Tt), kap.shape[1], _p(Tt), _p(kap), _p(kP), _p(kR))
+        self.nnu = kap.shape[1]
+        a = lib().og_const_a()
+        self.F0 = None if F0 is None else _f64(F0)
+        self.st = _Star(R_star or 0.0, T_star or 0.0, _p(self.F0))
+        self.fld = _Fld(dt, c_V if c_V is not None else 0.0, T_bc,
+                        E_floor if E_floor is not None else a * 1.0)
+
+    @classmethod
+    def from_workload(cls, wl, F0=None):
+        if F0 is None:
+            F0 = star_bins(wl.T_star, wl.opacity.nu)
+        g, op = wl.grid, wl.opacity
+        return cls(g.r_face, g.th_face, g.ph_face, op.T, op.kappa, op.kappa_P, op.kappa_R,
+                   R_star=wl.R_star, F0=F0, T_star=wl.T_star, dt=wl.dt, c_V=wl.c_V,
+                   T_bc=wl.T_bc, E_floor=wl.E_floor)
+
+    # --- per-step pieces -------------------------------------------------
+    def raytrace(self, rho, T, want_faces=True):
+        rho, T = _f64(rho).ravel(), _f64(T).ravel()
+        q = np.empty(self.n); S = np.empty(self.n)
+        nr, nt, npp = self.shape
+        F = np.empty((nr + 1) * nt * npp) if want_faces else None
+        lib().og_raytrace(C.byref(self.g), C.byref(self.op), C.byref(self.st), _p(rho), _p(T),
+                          _p(q), _p(S), _p(F))
+        return q, S, F
+
+    def energy(self, T, S):
+        T, S = _f64(T).ravel(), _f64(S).ravel()
+        E = np.empty(self.n)
+        lib().og_energy(C.byref(self.g), C.byref(self.op), C.byref(self.fld), _p(T), _p(S), _p(E))
+        return E
+
+    def assemble(self, rho, T, En, q, Q=None):
+        args = [_f64(x).ravel() for x in (rho, T, En, q)]
+        Qa = None if Q is None else _f64(Q).ravel()
+        n = self.n
+        out = dict(w=np.empty(3 * n), d=np.empty(n), b=np.empty(n), s=np.empty(n),
+                   ahat=np.empty(3 * n), bhat=np.empty(n))
+        lib().og_assemble(C.byref(self.g), C.byref(self.op), C.byref(self.fld),
+                          *[_p(a) for a in args], _p(Qa), _p(out["w"]), _p(out["d"]),
+                          _p(out["b"]), _p(out["s"]), _p(out["ahat"]), _p(out["bhat"]))
+        return out
+
+    def spmv(self, ahat, x):
+        ahat, x = _f64(ahat).ravel(), _f64(x).ravel()
+        y = np.empty(self.n)
+        lib().og_spmv(C.byref(self.g), _p(ahat), _p(x), _p(y))
+        return y
+
+    def relres(self, ahat, bhat, y):
+        return lib().og_relres(C.byref(self.g), _p(_f64(ahat).ravel()), _p(_f64(bhat).ravel()),
+                               _p(_f64(y).ravel()))
+
+    def cg(self, ahat, bhat, y0, tol, max_iter):
+        ahat, bhat = _f64(ahat).ravel(), _f64(bhat).ravel()
+        y = _f64(y0).ravel().copy()
+        it = C.c_int(0); rr = C.c_double(0)
+        st = lib().og_cg(C.byref(self.g), _p(ahat), _p(bhat), _p(y), tol, max_iter,
+                         C.byref(it), C.byref(rr))
+        return y, st, it.value, rr.value
+
+    def dense_solve(self, ahat, bhat):
+        ahat, bhat = _f64(ahat).ravel(), _f64(bhat).ravel()
+        y = np.empty(self.n)
+        st = lib().og_dense_solve(C.byref(self.g), _p(ahat), _p(bhat), _p(y))
+        if st != 0:
+            raise RuntimeError(f"dense solve failed ({st})")
+        return y
+
+    def newton(self, E, S, T_start):
+        E, S = _f64(E).ravel(), _f64(S).ravel()
+        T = _f64(T_start).ravel().copy()
+        lib().og_newton(C.byref(self.g), C.byref(self.op), _p(E), _p(S), _p(T))
+        return T
+
+    def force(self, rho, T, w, E, q):
+        out = np.empty(4 * self.n)
+        args = [_f64(x).ravel() for x in (rho, T, w, E, q)]
+        lib().og_force(C.byref(self.g), C.byref(self.op), C.byref(self.fld),
+                       *[_p(a) for a in args], _p(out))
+        return out
+
+    def step(self, rho, T, tol=1e-10, max_iter=100000, dense=False, want_force=True):
+        rho = _f64(rho).ravel()
+        T = _f64(T).ravel().copy()
+        E = np.empty(self.n)
+        f = np.empty(4 * self.n) if want_force else None
+        it = C.c_int(0); rr = C.c_double(0)
+        st = lib().og_step(C.byref(self.g), C.byref(self.op), C.byref(self.st), C.byref(self.fld),
+                           _p(rho), _p(T), _p(E), _p(f), tol, max_iter, int(dense),
+                           C.byref(it), C.byref(rr))
+        return dict(T=T, E=E, force=f, status=st, iters=it.value, relres=rr.value)
+
+    # --- table lookups (for pins) ----------------------------------------
+    def kappa_nu(self, T, b):
+        return lib().og_kappa_nu(C.byref(self.op), float(T), int(b))
+
+    def kappa_P(self, T):
+        return lib().og_kappa_P(C.byref(self.op), float(T))
+
+    def kappa_R(self, T):
+        return lib().og_kappa_R(C.byref(self.op), float(T))
+
+
+def star_bins(T_star, nu):
+    nu = _f64(nu)
+    F = np.empty(len(nu))
+    st = lib().og_star_bins(float(T_star), len(nu), _p(nu), _p(F))
+    if st != 0:
+        raise ValueError("bad star parameters")
+    return F
+
+
+def const_a():
+    return lib().og_const_a()
+
+
+def const_c():
+    return lib().og_const_c()
