@@ -1,0 +1,193 @@
+"""Benchmark of the radiation step on one MI355X.
+
+A step is one pass of the main loop (ray trace, E^n, FLD assembly, implicit solve to
+a relative residual of 1e-8, Newton temperature update, radiative force) on the
+512x256x512-cell, 64-bin workload (tau550 = 100 with lognormal clumps, seed 5000);
+successive steps evolve the temperature with dt = 1e9 s.  The headline mode is timed
+first, then the plain float64 solve from the same start for comparison.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "FLD solve s/step @1e-8 resid, plain FP64 vs learned-precond; ray-trace Gcell·ν/s"
+PEAK_HBM_GBS = 8000.0
+# Algorithmic bytes per cell of one launch of each solver kernel (see the kernel comments):
+# dir: read r, p_old and the three off-diagonals, write p and q; upd: read y, p, r, q, write y, r.
+BYTES_PER_CELL = {"fp64": {"dir": 7 * 8, "upd": 6 * 8}, "mixed": {"dir": 7 * 4, "upd": 6 * 4}}
+KERNEL_NAMES = {"fp64": "k_cg_dir<double>", "mixed": "k_cg_dir<float>"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_mode(ctx, rt, torch, rho, T0, mode, steps, warmup, tol, inner_tol):
+    n = ctx.n
+    m = {"fp64": rt.MODE_FP64, "mixed": rt.MODE_MIXED}[mode]
+    opts = rt.solve_opts(m, tol=tol, max_iter=500000, check_every=32, inner_tol=inner_tol)
+    T = T0.clone()
+    E = torch.empty(n, dtype=torch.float64, device="cuda")
+    f = torch.empty(4 * n, dtype=torch.float64, device="cuda")
+    for w in range(warmup):
+        rc, st = ctx.step(rho, T, E, opts, f_rad=f)
+        log(f"[{mode}] warmup step {w}: solve {st['solve']['ms']:.1f} ms, {st['solve']['iters']} it, "
+            f"relres {st['solve']['relres']:.2e}")
+    T.copy_(T0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(steps):
+        rc, st = ctx.step(rho, T, E, opts, f_rad=f)
+        stats.append(st)
+        log(f"[{mode}] step {k}: total {st['ms_total']:.1f} ms, raytrace {st['ms_raytrace']:.2f} ms, "
+            f"solve {st['solve']['ms']:.1f} ms ({st['solve']['iters']} it, {st['solve']['outer_iters']} outer, "
+            f"relres {st['solve']['relres']:.2e}), dir {st['solve']['ms_dir']*1e3:.1f} us")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return dict(wall_s=t1 - t0, stats=stats, T=T, E=E)
+
+
+def oracle_baseline(wl, gpu_fp64_iters, slab=8, cg_iters=200):
+    """The oracle on a phi-slab of the workload: ray trace and a fixed number of CG
+    iterations, scaled to the full grid and to the GPU float64 iteration count."""
+    import numpy as np
+
+    import oracle
+    from paper_1001_3301_amd import synth as sy
+    g = wl.grid
+    slab = min(slab, g.shape[2])
+    P = oracle.Problem(g.r_face, g.th_face, g.ph_face[: slab + 1], wl.opacity.T, wl.opacity.kappa,
+                       wl.opacity.kappa_P, wl.opacity.kappa_R, R_star=wl.R_star,
+                       F0=oracle.star_bins(wl.T_star, wl.opacity.nu), dt=wl.dt, c_V=wl.c_V,
+                       T_bc=wl.T_bc, E_floor=wl.E_floor)
+    rho = np.ascontiguousarray(wl.rho[:slab])
+    T = np.full(P.n, wl.T_bc)
+    t = time.perf_counter()
+    q, S, _ = P.raytrace(rho, T, want_faces=False)
+    t_rt = time.perf_counter() - t
+    T = P.newton(np.full(P.n, sy.A_RAD * wl.T_bc ** 4), S, T)
+    En = P.energy(T, S)
+    sysd = P.assemble(rho, T, En, q)
+    t = time.perf_counter()
+    _, _, it, _ = P.cg(sysd["ahat"], sysd["bhat"], En / sysd["s"], 1e-30, cg_iters)
+    t_cg = time.perf_counter() - t
+    scale = g.ncell / P.n
+    per_iter_full = t_cg / max(it, 1) * scale
+    return dict(solve_s_per_step=per_iter_full * gpu_fp64_iters,
+                raytrace_gcell_nu=P.n * wl.opacity.kappa.shape[1] / t_rt / 1e9,
+                sample=f"oracle on a {g.shape[0]}x{g.shape[1]}x{slab} phi-slab of the workload "
+                       f"({P.n} cells, 1/{scale:.0f} of the grid): one ray trace ({t_rt:.1f} s) and "
+                       f"{it} float64 CG iterations ({t_cg:.1f} s); solve s/step = time per iteration "
+                       f"x {scale:.0f} x the GPU float64 iteration count ({gpu_fp64_iters})")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="clumpy-512x256x512-nu64")
+    ap.add_argument("--modes", default="mixed,fp64", help="comma list; the first is the headline")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--inner-tol", type=float, default=1e-4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the radiation step is built and measured on a "
+              "single MI355X (no multi-GPU path in this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1001_3301_amd import rt, synth as sy
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    c = sy.CONFIGS[args.config]
+    wl = sy.make_workload(args.config, c["nr"], c["nt"], c["nph"], c["n_nu"], c["taus"][-1],
+                          c["seeds"][-1])
+    log(f"workload {args.config}: {wl.grid.shape}, {c['n_nu']} bins, tau550={wl.tau550}, "
+        f"generated in {time.perf_counter() - t:.1f} s")
+    ctx = rt.Context.from_workload(wl)
+    n = ctx.n
+    rho = torch.tensor(wl.rho.ravel(), device="cuda")
+    # initial temperature: irradiation at T_bc, then Eq. 16 with E = a T_bc^4 (all on the GPU)
+    T0 = torch.full((n,), wl.T_bc, dtype=torch.float64, device="cuda")
+    q = torch.empty(n, dtype=torch.float64, device="cuda")
+    S = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.raytrace(rho, T0, q, S)
+    E0 = torch.full((n,), sy.A_RAD * wl.T_bc ** 4, dtype=torch.float64, device="cuda")
+    ctx.temperature(E0, S, T0)
+    del q, S, E0
+    torch.cuda.synchronize()
+
+    modes = [m.strip() for m in args.modes.split(",") if m.strip()]
+    results = {}
+    for mode in modes:
+        results[mode] = run_mode(ctx, rt, torch, rho, T0, mode, args.steps, args.warmup, args.tol,
+                                 args.inner_tol)
+
+    head = modes[0]
+    R = results[head]
+    solve_s = [s["solve"]["ms"] / 1e3 for s in R["stats"]]
+    rt_ms = [s["ms_raytrace"] for s in R["stats"]]
+    value = statistics.median(solve_s)
+    samples = sum(s["solve"]["kernel_samples"] for s in R["stats"])
+    ms_dir = sum(s["solve"]["ms_dir"] * s["solve"]["kernel_samples"] for s in R["stats"]) / max(samples, 1)
+    ms_upd = sum(s["solve"]["ms_upd"] * s["solve"]["kernel_samples"] for s in R["stats"]) / max(samples, 1)
+    bpc = BYTES_PER_CELL[head]
+    achieved = bpc["dir"] * n / (ms_dir / 1e3) / 1e9 if ms_dir > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "s/step",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": R["wall_s"] / args.steps * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "mixed": "f32+f64"}[head],
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {wl.grid.shape[0]}x{wl.grid.shape[1]}x{wl.grid.shape[2]} cells, "
+                               f"{c['n_nu']} bins, tau550={wl.tau550:g}, clumps seed {c['seeds'][-1]}",
+                   "solve_mode": head, "tol": args.tol, "dt": wl.dt, "successive_steps": args.steps},
+        "raytrace_gcell_nu_per_s": statistics.median([n * c["n_nu"] / (x / 1e3) / 1e9 for x in rt_ms]),
+        "solve_iters_per_step": statistics.median([s["solve"]["iters"] for s in R["stats"]]),
+        "kernel_ms": {"dir": ms_dir, "upd": ms_upd, "samples": samples},
+        "roofline": {"kernel": KERNEL_NAMES[head], "bound": "hbm", "achieved": achieved,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": None, "bytes_per_cell": bpc["dir"], "cells_per_launch": n},
+    }
+    for mode in modes[1:]:
+        Rm = results[mode]
+        out[f"{mode}_solve_s_per_step"] = statistics.median([s["solve"]["ms"] / 1e3 for s in Rm["stats"]])
+        out[f"{mode}_iters_per_step"] = statistics.median([s["solve"]["iters"] for s in Rm["stats"]])
+    if len(modes) > 1:
+        Ta, Tb = results[modes[0]]["T"], results[modes[-1]]["T"]
+        out["T_rel_diff_vs_" + modes[-1]] = float(((Ta - Tb).abs() / Tb).max())
+    if not args.no_cpu_baseline:
+        fp64_iters = out.get("fp64_iters_per_step", out["solve_iters_per_step"])
+        t = time.perf_counter()
+        cb = oracle_baseline(wl, fp64_iters)
+        log(f"cpu baseline took {time.perf_counter() - t:.1f} s")
+        out["cpu_baseline"] = {"value": cb["solve_s_per_step"], "unit": "s/step", "cores": 1,
+                               "kind": "oracle", "sample": cb["sample"],
+                               "raytrace_gcell_nu_per_s": cb["raytrace_gcell_nu"]}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

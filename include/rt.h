@@ -1,0 +1,218 @@
+/*
+ * rt.h - C-ABI of librtmi, the MI355X (gfx950) radiation step of Kuiper et al.,
+ * "Fast and accurate frequency dependent radiation transport for hydrodynamics
+ * simulations in massive star formation".
+ *
+ * One call of rt_step is one pass of the main loop of the paper's Fig. 1:
+ * frequency-dependent ray trace of the stellar irradiation (Eqs. 17-20), radiation
+ * energy E^n from Eq. (16), implicit gray FLD solve for E^{n+1} (Eqs. 8-15), Newton
+ * update of the temperature (Eq. 16), and the radiative force (Eqs. 27-36).
+ *
+ * Conventions (all entry points):
+ *  - Grid: spherical-polar, N_r x N_theta x N_phi cells.  Cell (i, j, k) is stored at
+ *    c = i + N_r (j + N_theta k) (r fastest).  Radial face i (at r_face[i],
+ *    i = 0..N_r) of column (j, k) is stored at i + (N_r + 1)(j + N_theta k).
+ *  - Field arguments (rho, T, E, ...) are DEVICE pointers to contiguous float64 arrays
+ *    in that layout, owned by the caller; the library never frees or retains them.
+ *  - rt_grid / rt_opacity / rt_star describe the problem with HOST arrays that are
+ *    copied by the call that receives them.
+ *  - All work is enqueued on the stream given to rt_create; calls return once the
+ *    work is enqueued, except where a call states that it synchronises (solves read
+ *    their convergence scalars back to the host).
+ *  - Units are CGS.  No exception crosses the ABI; a failing call returns a non-zero
+ *    rt_status and rt_last_error(ctx) describes it.  Arguments are validated on the
+ *    host before anything is launched.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef RTMI_RT_H
+#define RTMI_RT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RT_OK = 0,
+    RT_EINVAL = 1,     /* bad argument (size, NULL, inconsistent table) */
+    RT_EDEVICE = 2,    /* HIP runtime error */
+    RT_ENOMEM = 3,     /* device allocation failed */
+    RT_ENONFINITE = 4, /* NaN/Inf met in a residual or norm */
+    RT_ENOCONV = 5     /* iteration limit reached; outputs hold the last iterate */
+} rt_status;
+
+typedef struct rt_ctx rt_ctx;
+
+/* Grid faces (host arrays): r_face[nr+1] increasing and > 0, th_face[nt+1] within
+ * [0, pi], ph_face[np+1] increasing; phi is periodic over [ph_face[0], ph_face[np]]. */
+typedef struct {
+    int nr, nt, np;
+    const double *r_face, *th_face, *ph_face;
+} rt_grid;
+
+/* Opacity table (host arrays), Sect. "Frequency dependent irradiation": kappa[n_T][n_nu]
+ * is kappa_nu at the bin mid-frequencies nu[n_nu] for the temperatures T[n_T]
+ * (increasing); kappa_P / kappa_R are the Planck / Rosseland means at T[] (> 0).
+ * kappa_nu is interpolated linearly in T, the means log-log; values are clamped to
+ * the end nodes outside the table.  1 <= n_nu <= 64, 2 <= n_T <= 128. */
+typedef struct {
+    int n_T, n_nu;
+    const double *T, *nu, *kappa, *kappa_P, *kappa_R;
+} rt_opacity;
+
+/* Central star: radius, effective temperature and the flux per bin at the stellar
+ * surface, F_nu[n_nu] (host array, erg s^-1 cm^-2), e.g. from rt_star_bin_flux. */
+typedef struct {
+    double R_star, T_star;
+    const double *F_nu;
+} rt_star;
+
+/* Parameters of the implicit FLD step (Eqs. 9, 15, 16): time step dt [s], specific
+ * heat c_V [erg g^-1 K^-1], outer Dirichlet temperature T_bc [K] (E = a T_bc^4 in a
+ * ghost cell beyond the last radial face; zero flux through the inner radial face and
+ * the poles; phi periodic), and the floor applied to E^n. */
+typedef struct {
+    double dt, c_V, T_bc, E_floor;
+} rt_fld_params;
+
+/* Device view of the assembled Jacobi-scaled system A^ y = b^ (unit diagonal, A^ =
+ * S A S with S = diag(d)^-1/2, E = s * y).  Pointers are owned by the context and stay
+ * valid until the next rt_fld_assemble / rt_step / rt_destroy. */
+typedef struct {
+    long n;
+    const double *ahat;   /* [3][n] scaled off-diagonals of the outward r, theta, phi faces */
+    const float *ahat32;  /* [3][n] the same in float32 (inner solves of the mixed mode) */
+    const double *s;      /* [n] Jacobi scale d^-1/2 */
+    const double *bhat;   /* [n] scaled right-hand side */
+    const double *w;      /* [3][n] unscaled outward face weights A_f D_f / ds_f; the radial
+                             weight of the last cell is the Dirichlet face */
+    const double *chi;    /* [n] kappa_R(T^n) rho */
+} rt_system;
+
+typedef enum {
+    RT_SOLVE_FP64 = 0,    /* CG on A^ in float64 (the plain method; also the fallback) */
+    RT_SOLVE_MIXED = 1,   /* float64 iterative refinement around float32 inner CG */
+    RT_SOLVE_LEARNED = 2  /* refinement around flexible CG preconditioned by a network */
+} rt_solve_mode;
+
+typedef struct rt_net rt_net;
+
+typedef struct {
+    int mode;            /* rt_solve_mode */
+    double tol;          /* stop when ||b^ - A^ y|| / ||b^|| <= tol (float64, true residual) */
+    int max_iter;        /* limit on (inner) Krylov iterations in total */
+    int check_every;     /* iterations between host convergence polls (default 32) */
+    double inner_tol;    /* relative reduction asked of each inner solve (mixed / learned) */
+    int inner_max_iter;  /* limit per inner solve */
+    rt_net *net;         /* network for RT_SOLVE_LEARNED, else NULL */
+} rt_solve_opts;
+
+typedef struct {
+    int status;          /* rt_status of the solve */
+    int iters;           /* Krylov iterations (inner iterations in mixed / learned modes) */
+    int outer_iters;     /* float64 refinement steps (mixed / learned) */
+    int precond_applies; /* network applications (learned) */
+    int fallback;        /* 1 if the learned solve fell back to the float64 method */
+    double relres;       /* final true relative residual, computed in float64 */
+    double ms;           /* wall time of the solve (host clock, includes polls) */
+    double ms_dir;       /* mean device time of one direction+operator kernel (sampled once per poll) */
+    double ms_upd;       /* mean device time of one update kernel (sampled likewise) */
+    int kernel_samples;  /* number of samples behind ms_dir / ms_upd */
+} rt_solve_stats;
+
+typedef struct {
+    rt_solve_stats solve;
+    double ms_raytrace, ms_assemble, ms_solve, ms_newton, ms_total; /* device-event times */
+} rt_step_stats;
+
+/* ------------------------------------------------------------------ context */
+
+/* Creates a context for grid g and n_nu frequency bins, enqueuing on `stream`
+ * (a hipStream_t; NULL = the default stream).  Allocates every workspace of the
+ * radiation step (about 30 float64-equivalents per cell).  Select the device first
+ * (hipSetDevice); the context stays on it. */
+rt_status rt_create(rt_ctx **out, const rt_grid *g, int n_nu, void *stream);
+void rt_destroy(rt_ctx *ctx);
+/* Message of the last failing call on ctx (or of the last failing rt_create when ctx
+ * is NULL).  Valid until the next call. */
+const char *rt_last_error(const rt_ctx *ctx);
+/* Number of cells of the context's grid. */
+long rt_ncell(const rt_ctx *ctx);
+
+/* Eq. (20): flux of each frequency bin at the stellar surface, pi * int B_nu(T_star)
+ * d nu over the bin, whose edges are the midpoints between neighbouring mid-frequencies
+ * (0 and infinity at the ends), so the bins sum to sigma T_star^4 (Eq. 18).  Host
+ * arrays nu[n_nu] (increasing) and F_out[n_nu]. */
+rt_status rt_star_bin_flux(double T_star, int n_nu, const double *nu, double *F_out);
+
+/* Uploads the opacity table / stellar spectrum to the context (they are also taken by
+ * the calls below when their pointer argument is not NULL). */
+rt_status rt_set_opacity(rt_ctx *ctx, const rt_opacity *op);
+rt_status rt_set_star(rt_ctx *ctx, const rt_star *st);
+
+/* ------------------------------------------------------------ the step's calls */
+
+/* Ray trace (Eqs. 17-20, optical depth zero at the inner radial face).  Per radial
+ * column and bin: tau_nu grows by kappa_nu(T_i) rho_i dr_i through cell i (float64
+ * accumulation), F_nu(r) = F_nu(R_*) (R_* / r)^2 exp(-tau_nu).  Outputs (device):
+ *   q_star[n]  absorbed stellar power per volume, (A_- F_- - A_+ F_+)/V summed over
+ *              bins (the cell-integrated form of Eqs. 28-33, 36);
+ *   S_abs[n]   sum_nu kappa_nu Fbar_nu / c = q_nu / (rho c), the irradiation term of
+ *              Eq. (16) in the frequency-dependent form;
+ *   F_face     total stellar flux at every radial face, (N_r+1) N_theta N_phi, or NULL.
+ * op / st may be NULL to use the tables already on the context. */
+rt_status rt_raytrace(rt_ctx *ctx, const rt_opacity *op, const rt_star *st,
+                      const double *rho, const double *T, double *q_star, double *S_abs,
+                      double *F_face);
+
+/* Fig. 1 "Radiation Energy": E[n] = max(a T^4 - S_abs / kappa_P(T), E_floor). */
+rt_status rt_energy(rt_ctx *ctx, const rt_opacity *op, const rt_fld_params *p,
+                    const double *T, const double *S_abs, double *E);
+
+/* Backward-Euler finite-volume form of Eq. (15):
+ *   V/(dt f_c) (E - E^n) = sum_faces w_f (E_nb - E) + V (q_star + Q_plus),
+ * f_c from Eq. (9), w_f = A_f D_f / ds_f with D from Eqs. (11)-(13) at each face
+ * (kappa_R rho and E arithmetic means of the two cells, coefficients at (E^n, T^n)).
+ * Writes the Jacobi-scaled system into the context; *sys receives its device view.
+ * Q_plus may be NULL (static problem). */
+rt_status rt_fld_assemble(rt_ctx *ctx, const rt_opacity *op, const rt_fld_params *p,
+                          const double *rho, const double *T, const double *E_n,
+                          const double *q_star, const double *Q_plus, rt_system *sys);
+
+/* y = A^ x with the context's current system (float64), device arrays of n. */
+rt_status rt_spmv(rt_ctx *ctx, const double *x, double *y);
+
+/* Implicit solve of the assembled system (the paper's implicit Krylov step).  E holds
+ * the start value on entry (normally E^n) and E^{n+1} = s * y on exit.  Synchronises
+ * with the stream to poll convergence.  Returns RT_ENOCONV (E still written) when the
+ * iteration limit is met, RT_ENONFINITE on NaN/Inf. */
+rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_stats *st);
+
+/* Newton-Raphson on Eq. (16), a T^4 = E + S_abs / kappa_P(T), per cell; T holds the
+ * start value (T^n) on entry and the root on exit.  The root returned is the smallest
+ * one (the table's sublimation drop can make Eq. (16) non-monotone). */
+rt_status rt_temperature(rt_ctx *ctx, const rt_opacity *op, const double *E,
+                         const double *S_abs, double *T);
+
+/* Radiative force density (Eq. 27) per cell, f[4][n] (device): component 0 is the
+ * stellar part q_star / c (Eq. 36 in the cell-integrated form of Eq. 33); 1-3 are the
+ * thermal part kappa_R rho F / c along r, theta, phi, with the FLD flux F = -D grad E
+ * (Eq. 10) of the context's current system evaluated at the faces with E and averaged
+ * over the two faces of each direction. */
+rt_status rt_force(rt_ctx *ctx, const double *E, const double *q_star, double *f);
+
+/* One main-loop pass of Fig. 1 for the given density: rt_raytrace(rho, T^n) ->
+ * rt_energy -> rt_fld_assemble -> rt_fld_solve (start E^n) -> rt_temperature ->
+ * rt_force.  T: T^n in, T^{n+1} out.  E: E^{n+1} out.  f_rad (4 n) may be NULL.
+ * The stellar quantities of the step stay on the context (rt_step_fields). */
+rt_status rt_step(rt_ctx *ctx, const rt_opacity *op, const rt_star *st,
+                  const rt_fld_params *p, const rt_solve_opts *o, const double *rho,
+                  double *T, double *E, double *f_rad, rt_step_stats *stats);
+
+/* Device views of the last step's q_star, S_abs and E^n (n each). */
+rt_status rt_step_fields(rt_ctx *ctx, const double **q_star, const double **S_abs,
+                         const double **E_n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTMI_RT_H */

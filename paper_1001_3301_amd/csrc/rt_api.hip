@@ -1,0 +1,717 @@
+// Host side of the librtmi C-ABI: argument checks, context and workspaces, the
+// problem tables, Eq. (20) bin fluxes, and the solver drivers that sequence the
+// kernels of the radiation step (Fig. 1 of Kuiper et al.).
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "rt_internal.h"
+
+using namespace rt;
+
+namespace rt {
+void raytrace_prepare(size_t lds_bytes);
+}
+
+namespace {
+
+thread_local std::string g_err;  // errors of rt_create (no context yet)
+
+rt_status fail(rt_ctx *ctx, rt_status s, const std::string &m)
+{
+    if (ctx) ctx->err = m; else g_err = m;
+    return s;
+}
+
+#define RT_HIP(ctx, call)                                                                         \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail((ctx), RT_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+#define RT_CHECK(ctx, cond, msg)                                                                  \
+    do {                                                                                          \
+        if (!(cond)) return fail((ctx), RT_EINVAL, (msg));                                        \
+    } while (0)
+
+template <class T>
+T *dalloc(rt_ctx *ctx, size_t n)
+{
+    void *p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return nullptr;
+    ctx->allocs.push_back(p);
+    return static_cast<T *>(p);
+}
+
+bool isfin(double x) { return std::isfinite(x); }
+
+// log-log interpolation of a mean-opacity column on the host (used once per system
+// for kappa_R at the boundary temperature).
+double host_mean(const std::vector<double> &T, const std::vector<double> &tab, double t)
+{
+    size_t n = T.size();
+    if (t <= T[0]) return tab[0];
+    if (t >= T[n - 1]) return tab[n - 1];
+    size_t k = 0;
+    while (T[k + 1] <= t) k++;
+    double l0 = std::log(T[k]), l1 = std::log(T[k + 1]);
+    double lw = (std::log(t) - l0) / (l1 - l0);
+    return std::exp((1.0 - lw) * std::log(tab[k]) + lw * std::log(tab[k + 1]));
+}
+
+rt_status read_scalars(rt_ctx *ctx)
+{
+    RT_HIP(ctx, hipMemcpyAsync(ctx->h_sc, ctx->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, ctx->stream));
+    RT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return RT_OK;
+}
+
+rt_status write_scalars(rt_ctx *ctx)
+{
+    RT_HIP(ctx, hipMemcpyAsync(ctx->sc, ctx->h_sc, sizeof(DevScalars), hipMemcpyHostToDevice, ctx->stream));
+    RT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return RT_OK;
+}
+
+rt_status check_fld(rt_ctx *ctx, const rt_fld_params *p)
+{
+    RT_CHECK(ctx, p, "rt_fld_params is NULL");
+    RT_CHECK(ctx, p->dt > 0.0 && isfin(p->dt), "dt must be positive");
+    RT_CHECK(ctx, p->c_V >= 0.0 && isfin(p->c_V), "c_V must be >= 0");
+    RT_CHECK(ctx, p->T_bc > 0.0 && isfin(p->T_bc), "T_bc must be positive");
+    RT_CHECK(ctx, p->E_floor >= 0.0 && isfin(p->E_floor), "E_floor must be >= 0");
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------- Eq. (20)
+
+// Planck integrals in x = h nu / (k T):
+//   P(x) = int_0^x t^3/(e^t - 1) dt = sum_n c_n x^{n+3}/(n+3) for x <= 1, with
+//          t/(e^t - 1) = sum_n c_n t^n (c_n = B_n / n!: c_0 = 1, sum_{k<=n} c_k/(n+1-k)! = 0);
+//   Q(x) = int_x^inf = sum_m e^{-m x}(x^3/m + 3x^2/m^2 + 6x/m^3 + 6/m^4) for x > 1;
+// each extended to the other side with P + Q = pi^4/15.
+const double kPi4_15 = 6.4939394022668291491;  // pi^4 / 15
+
+double planck_P_series(double x)
+{
+    static double c[48];
+    static bool init = false;
+    if (!init) {
+        double fact[50];
+        fact[0] = 1.0;
+        for (int i = 1; i < 50; i++) fact[i] = fact[i - 1] * i;
+        c[0] = 1.0;
+        for (int n = 1; n < 48; n++) {
+            double s = 0.0;
+            for (int k = 0; k < n; k++) s += c[k] / fact[n + 1 - k];
+            c[n] = -s;
+        }
+        init = true;
+    }
+    double P = 0.0, xp = x * x * x;
+    for (int n = 0; n < 48; n++) {
+        P += c[n] * xp / (n + 3);
+        xp *= x;
+    }
+    return P;
+}
+
+double planck_Q_series(double x)
+{
+    double s = 0.0;
+    for (int m = 1; m < 400; m++) {
+        double e = std::exp(-m * x);
+        double t = e * (x * x * x / m + 3.0 * x * x / ((double)m * m) + 6.0 * x / ((double)m * m * m) +
+                        6.0 / ((double)m * m * m * m));
+        s += t;
+        if (t < 1e-19 * s) break;
+    }
+    return s;
+}
+
+double planck_P(double x) { return x <= 0.0 ? 0.0 : (x <= 1.0 ? planck_P_series(x) : kPi4_15 - planck_Q_series(x)); }
+double planck_Q(double x) { return x <= 1.0 ? kPi4_15 - planck_P(x) : planck_Q_series(x); }
+
+// int_lo^hi t^3/(e^t - 1) dt without cancellation: below x = 1 from P, above from Q.
+double planck_band(double lo, double hi)
+{
+    if (hi <= 1.0) return planck_P(hi) - planck_P(lo);
+    if (lo >= 1.0) return planck_Q(lo) - (std::isinf(hi) ? 0.0 : planck_Q(hi));
+    return (planck_P(1.0) - planck_P(lo)) + (planck_Q(1.0) - (std::isinf(hi) ? 0.0 : planck_Q(hi)));
+}
+
+}  // namespace
+
+// ==================================================================== C-ABI
+
+extern "C" {
+
+const char *rt_last_error(const rt_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+long rt_ncell(const rt_ctx *ctx) { return ctx ? ctx->d.n : 0; }
+
+rt_status rt_star_bin_flux(double T_star, int n_nu, const double *nu, double *F_out)
+{
+    if (!(T_star > 0.0) || n_nu < 1 || !nu || !F_out) return fail(nullptr, RT_EINVAL, "rt_star_bin_flux: bad arguments");
+    for (int i = 1; i < n_nu; i++)
+        if (!(nu[i] > nu[i - 1])) return fail(nullptr, RT_EINVAL, "rt_star_bin_flux: nu must increase");
+    if (!(nu[0] > 0.0)) return fail(nullptr, RT_EINVAL, "rt_star_bin_flux: nu must be positive");
+    const double xs = kH / (kBoltz * T_star);
+    const double norm = kSigma * std::pow(T_star, 4) * 15.0 / std::pow(M_PI, 4);
+    for (int i = 0; i < n_nu; i++) {
+        double lo = (i == 0) ? 0.0 : 0.5 * (nu[i - 1] + nu[i]) * xs;
+        double hi = (i == n_nu - 1) ? INFINITY : 0.5 * (nu[i] + nu[i + 1]) * xs;
+        F_out[i] = norm * planck_band(lo, hi);
+    }
+    return RT_OK;
+}
+
+rt_status rt_create(rt_ctx **out, const rt_grid *g, int n_nu, void *stream)
+{
+    if (!out) return fail(nullptr, RT_EINVAL, "rt_create: out is NULL");
+    *out = nullptr;
+    if (!g || !g->r_face || !g->th_face || !g->ph_face) return fail(nullptr, RT_EINVAL, "rt_create: grid arrays missing");
+    if (g->nr < 2 || g->nt < 1 || g->np < 1) return fail(nullptr, RT_EINVAL, "rt_create: need nr >= 2, nt >= 1, np >= 1");
+    if (n_nu < 1 || n_nu > kMaxNu) return fail(nullptr, RT_EINVAL, "rt_create: n_nu must be in [1, 64]");
+    long n = (long)g->nr * g->nt * g->np;
+    if (n > (1L << 40)) return fail(nullptr, RT_EINVAL, "rt_create: grid too large");
+    for (int i = 0; i < g->nr; i++)
+        if (!(g->r_face[i + 1] > g->r_face[i]) || !(g->r_face[i] > 0.0))
+            return fail(nullptr, RT_EINVAL, "rt_create: r_face must be positive and increasing");
+    for (int j = 0; j < g->nt; j++)
+        if (!(g->th_face[j + 1] > g->th_face[j]) || g->th_face[j] < 0.0 || g->th_face[j + 1] > M_PI + 1e-12)
+            return fail(nullptr, RT_EINVAL, "rt_create: th_face must increase within [0, pi]");
+    for (int k = 0; k < g->np; k++)
+        if (!(g->ph_face[k + 1] > g->ph_face[k]))
+            return fail(nullptr, RT_EINVAL, "rt_create: ph_face must increase");
+
+    rt_ctx *ctx = new (std::nothrow) rt_ctx();
+    if (!ctx) return fail(nullptr, RT_ENOMEM, "rt_create: out of host memory");
+    auto bail = [&](rt_status s, const std::string &m) {
+        g_err = m;
+        rt_destroy(ctx);
+        return s;
+    };
+    if (hipGetDevice(&ctx->device) != hipSuccess) return bail(RT_EDEVICE, "rt_create: no HIP device");
+    ctx->stream = (hipStream_t)stream;
+    ctx->d = Dims{g->nr, g->nt, g->np, n, (long)g->nr * g->nt};
+    ctx->n_nu = n_nu;
+    const int nr = g->nr, nt = g->nt, np = g->np;
+    ctx->h_rf.assign(g->r_face, g->r_face + nr + 1);
+    ctx->h_tf.assign(g->th_face, g->th_face + nt + 1);
+    ctx->h_pf.assign(g->ph_face, g->ph_face + np + 1);
+
+    // 1-D geometry factors
+    std::vector<double> rf2(nr + 1), rc(nr), dr(nr), shell(nr), volr(nr), hr2(nr), dsr(nr);
+    std::vector<double> dcos(nt), sinf(nt + 1), dth(nt), dtc(nt), sinc(nt), tc(nt), dph(np), dpc(np), pc(np);
+    const double *rf = g->r_face, *tf = g->th_face, *pf = g->ph_face;
+    for (int i = 0; i <= nr; i++) rf2[i] = rf[i] * rf[i];
+    for (int i = 0; i < nr; i++) {
+        double r0 = rf[i], r1 = rf[i + 1];
+        rc[i] = 0.5 * (r0 + r1);
+        dr[i] = r1 - r0;
+        shell[i] = r1 * r1 * r1 - r0 * r0 * r0;
+        volr[i] = shell[i] / 3.0;
+        hr2[i] = 0.5 * (r1 * r1 - r0 * r0);
+    }
+    for (int i = 0; i + 1 < nr; i++) dsr[i] = rc[i + 1] - rc[i];
+    {
+        double rl = rf[nr], rp = rf[nr - 1];
+        double rg = rl * (rl / rp);
+        dsr[nr - 1] = 0.5 * (rl + rg) - rc[nr - 1];
+    }
+    for (int j = 0; j < nt; j++) {
+        dcos[j] = std::cos(tf[j]) - std::cos(tf[j + 1]);
+        dth[j] = tf[j + 1] - tf[j];
+        tc[j] = 0.5 * (tf[j] + tf[j + 1]);
+        sinc[j] = std::sin(tc[j]);
+    }
+    for (int j = 0; j <= nt; j++) sinf[j] = std::sin(tf[j]);
+    for (int j = 0; j < nt; j++) dtc[j] = (j + 1 < nt) ? tc[j + 1] - tc[j] : 0.0;
+    for (int k = 0; k < np; k++) {
+        dph[k] = pf[k + 1] - pf[k];
+        pc[k] = 0.5 * (pf[k] + pf[k + 1]);
+    }
+    for (int k = 0; k < np; k++)
+        dpc[k] = (k + 1 < np) ? pc[k + 1] - pc[k] : (pf[np] - pc[np - 1]) + (pc[0] - pf[0]);
+
+    auto up = [&](const std::vector<double> &h) -> const double * {
+        double *p = dalloc<double>(ctx, h.size());
+        if (!p || hipMemcpy(p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+            return nullptr;
+        return p;
+    };
+    std::vector<double> rfv(rf, rf + nr + 1);
+    Geo &G = ctx->geo;
+    if (!(G.rf = up(rfv)) || !(G.rf2 = up(rf2)) || !(G.rc = up(rc)) || !(G.dr = up(dr)) ||
+        !(G.shell = up(shell)) || !(G.vol_r = up(volr)) || !(G.hr2 = up(hr2)) || !(G.dsr = up(dsr)) ||
+        !(G.dcos = up(dcos)) || !(G.sinf = up(sinf)) || !(G.dth = up(dth)) || !(G.dtc = up(dtc)) ||
+        !(G.sinc = up(sinc)) || !(G.dph = up(dph)) || !(G.dpc = up(dpc)))
+        return bail(RT_ENOMEM, "rt_create: geometry upload failed");
+
+    // opacity table (max size) and star
+    Opac &O = ctx->op;
+    double *ot = dalloc<double>(ctx, (size_t)kMaxT * (kMaxNu + 6));
+    ctx->F0 = dalloc<double>(ctx, kMaxNu);
+    if (!ot || !ctx->F0) return bail(RT_ENOMEM, "rt_create: table allocation failed");
+    O.T = ot;
+    O.kap = ot + kMaxT;
+    O.kP = O.kap + (size_t)kMaxT * kMaxNu;
+    O.kR = O.kP + kMaxT;
+    O.lnT = O.kR + kMaxT;
+    O.lnP = O.lnT + kMaxT;
+    O.lnR = O.lnP + kMaxT;
+    O.nnu = n_nu;
+
+    // fields, system, Krylov vectors
+    size_t N = (size_t)n;
+    ctx->q = dalloc<double>(ctx, N);
+    ctx->S = dalloc<double>(ctx, N);
+    ctx->En = dalloc<double>(ctx, N);
+    ctx->w = dalloc<double>(ctx, 3 * N);
+    ctx->ahat = dalloc<double>(ctx, 3 * N);
+    ctx->ahat32 = dalloc<float>(ctx, 3 * N);
+    ctx->s = dalloc<double>(ctx, N);
+    ctx->b = dalloc<double>(ctx, N);
+    ctx->bhat = dalloc<double>(ctx, N);
+    ctx->chi = dalloc<double>(ctx, N);
+    ctx->y = dalloc<double>(ctx, N);
+    ctx->r = dalloc<double>(ctx, N);
+    ctx->p0 = dalloc<double>(ctx, N);
+    ctx->p1 = dalloc<double>(ctx, N);
+    ctx->qv = dalloc<double>(ctx, N);
+    ctx->r32 = dalloc<float>(ctx, N);
+    ctx->p32a = dalloc<float>(ctx, N);
+    ctx->p32b = dalloc<float>(ctx, N);
+    ctx->q32 = dalloc<float>(ctx, N);
+    ctx->x32 = dalloc<float>(ctx, N);
+    if (!ctx->q || !ctx->S || !ctx->En || !ctx->w || !ctx->ahat || !ctx->ahat32 || !ctx->s || !ctx->b ||
+        !ctx->bhat || !ctx->chi || !ctx->y || !ctx->r || !ctx->p0 || !ctx->p1 || !ctx->qv || !ctx->r32 ||
+        !ctx->p32a || !ctx->p32b || !ctx->q32 || !ctx->x32)
+        return bail(RT_ENOMEM, "rt_create: out of device memory");
+
+    // reduction layout: a multiple of 8 blocks (one share per XCD), contiguous ranges
+    long want = (n + 255) / 256;
+    const char *env = std::getenv("RTMI_REDUCE_BLOCKS");
+    long cap = env ? std::max(8L, std::atol(env)) : 2048L;
+    long nb = std::min(std::max(want, 8L), cap);
+    nb = (nb + 7) / 8 * 8;
+    long chunk = (n + nb - 1) / nb;
+    chunk = (chunk + 63) / 64 * 64;
+    ctx->nblk = (int)nb;
+    ctx->chunk = chunk;
+    ctx->partials = dalloc<double>(ctx, nb);
+    ctx->counter = dalloc<unsigned>(ctx, 4);
+    ctx->sc = dalloc<DevScalars>(ctx, 1);
+    if (!ctx->partials || !ctx->counter || !ctx->sc) return bail(RT_ENOMEM, "rt_create: out of device memory");
+    if (hipMemset(ctx->counter, 0, 4 * sizeof(unsigned)) != hipSuccess ||
+        hipMemset(ctx->sc, 0, sizeof(DevScalars)) != hipSuccess)
+        return bail(RT_EDEVICE, "rt_create: memset failed");
+    if (hipHostMalloc((void **)&ctx->h_sc, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess)
+        return bail(RT_ENOMEM, "rt_create: pinned allocation failed");
+    std::memset(ctx->h_sc, 0, sizeof(DevScalars));
+    for (auto &e : ctx->ev)
+        if (hipEventCreate(&e) != hipSuccess) return bail(RT_EDEVICE, "rt_create: event creation failed");
+    raytrace_prepare(raytrace_lds_bytes(kMaxT, kMaxNu));
+    *out = ctx;
+    return RT_OK;
+}
+
+void rt_destroy(rt_ctx *ctx)
+{
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    for (void *p : ctx->allocs) (void)hipFree(p);
+    if (ctx->h_sc) (void)hipHostFree(ctx->h_sc);
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+rt_status rt_set_opacity(rt_ctx *ctx, const rt_opacity *op)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    RT_CHECK(ctx, op && op->T && op->kappa && op->kappa_P && op->kappa_R, "opacity arrays missing");
+    RT_CHECK(ctx, op->n_T >= 2 && op->n_T <= kMaxT, "n_T must be in [2, 128]");
+    RT_CHECK(ctx, op->n_nu == ctx->n_nu, "opacity n_nu differs from the context's");
+    const int nT = op->n_T, nnu = op->n_nu;
+    for (int k = 0; k < nT; k++) {
+        RT_CHECK(ctx, op->T[k] > 0.0 && (k == 0 || op->T[k] > op->T[k - 1]), "table T must be positive and increasing");
+        RT_CHECK(ctx, op->kappa_P[k] > 0.0 && op->kappa_R[k] > 0.0 && isfin(op->kappa_P[k]) && isfin(op->kappa_R[k]),
+                 "mean opacities must be positive");
+        for (int b = 0; b < nnu; b++)
+            RT_CHECK(ctx, op->kappa[(size_t)k * nnu + b] >= 0.0 && isfin(op->kappa[(size_t)k * nnu + b]),
+                     "kappa_nu must be finite and >= 0");
+    }
+    std::vector<double> pack;
+    pack.reserve((size_t)nT * (nnu + 3) + 1);
+    pack.push_back(nT);
+    pack.insert(pack.end(), op->T, op->T + nT);
+    pack.insert(pack.end(), op->kappa, op->kappa + (size_t)nT * nnu);
+    pack.insert(pack.end(), op->kappa_P, op->kappa_P + nT);
+    pack.insert(pack.end(), op->kappa_R, op->kappa_R + nT);
+    if (ctx->have_opac && pack == ctx->h_opac) return RT_OK;
+    std::vector<double> lnT(nT), lnP(nT), lnR(nT);
+    for (int k = 0; k < nT; k++) {
+        lnT[k] = std::log(op->T[k]);
+        lnP[k] = std::log(op->kappa_P[k]);
+        lnR[k] = std::log(op->kappa_R[k]);
+    }
+    RT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    Opac &O = ctx->op;
+    RT_HIP(ctx, hipMemcpy((void *)O.T, op->T, nT * sizeof(double), hipMemcpyHostToDevice));
+    RT_HIP(ctx, hipMemcpy((void *)O.kap, op->kappa, (size_t)nT * nnu * sizeof(double), hipMemcpyHostToDevice));
+    RT_HIP(ctx, hipMemcpy((void *)O.kP, op->kappa_P, nT * sizeof(double), hipMemcpyHostToDevice));
+    RT_HIP(ctx, hipMemcpy((void *)O.kR, op->kappa_R, nT * sizeof(double), hipMemcpyHostToDevice));
+    RT_HIP(ctx, hipMemcpy((void *)O.lnT, lnT.data(), nT * sizeof(double), hipMemcpyHostToDevice));
+    RT_HIP(ctx, hipMemcpy((void *)O.lnP, lnP.data(), nT * sizeof(double), hipMemcpyHostToDevice));
+    RT_HIP(ctx, hipMemcpy((void *)O.lnR, lnR.data(), nT * sizeof(double), hipMemcpyHostToDevice));
+    O.nT = nT;
+    ctx->nT = nT;
+    ctx->h_opac.swap(pack);
+    ctx->have_opac = true;
+    return RT_OK;
+}
+
+rt_status rt_set_star(rt_ctx *ctx, const rt_star *st)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    RT_CHECK(ctx, st && st->F_nu, "star flux array missing");
+    RT_CHECK(ctx, st->R_star > 0.0 && isfin(st->R_star), "R_star must be positive");
+    RT_CHECK(ctx, st->R_star <= ctx->h_rf[0], "R_star must not exceed the inner radial face");
+    for (int b = 0; b < ctx->n_nu; b++)
+        RT_CHECK(ctx, st->F_nu[b] >= 0.0 && isfin(st->F_nu[b]), "F_nu must be finite and >= 0");
+    std::vector<double> pack(st->F_nu, st->F_nu + ctx->n_nu);
+    pack.push_back(st->R_star);
+    pack.push_back(st->T_star);
+    if (ctx->have_star && pack == ctx->h_star) return RT_OK;
+    RT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    RT_HIP(ctx, hipMemcpy(ctx->F0, st->F_nu, ctx->n_nu * sizeof(double), hipMemcpyHostToDevice));
+    ctx->R_star = st->R_star;
+    ctx->T_star = st->T_star;
+    ctx->h_star.swap(pack);
+    ctx->have_star = true;
+    return RT_OK;
+}
+
+rt_status rt_raytrace(rt_ctx *ctx, const rt_opacity *op, const rt_star *st, const double *rho, const double *T,
+                      double *q_star, double *S_abs, double *F_face)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    if (op) { rt_status s = rt_set_opacity(ctx, op); if (s) return s; }
+    if (st) { rt_status s = rt_set_star(ctx, st); if (s) return s; }
+    RT_CHECK(ctx, ctx->have_opac, "no opacity table on the context");
+    RT_CHECK(ctx, ctx->have_star, "no star on the context");
+    RT_CHECK(ctx, rho && T && q_star && S_abs, "rt_raytrace: NULL field pointer");
+    launch_raytrace(ctx->d, ctx->op, ctx->geo, ctx->F0, ctx->R_star * ctx->R_star, rho, T, q_star, S_abs, F_face,
+                    ctx->stream);
+    RT_HIP(ctx, hipGetLastError());
+    return RT_OK;
+}
+
+rt_status rt_energy(rt_ctx *ctx, const rt_opacity *op, const rt_fld_params *p, const double *T, const double *S_abs,
+                    double *E)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    if (op) { rt_status s = rt_set_opacity(ctx, op); if (s) return s; }
+    RT_CHECK(ctx, ctx->have_opac, "no opacity table on the context");
+    if (rt_status s = check_fld(ctx, p)) return s;
+    RT_CHECK(ctx, T && S_abs && E, "rt_energy: NULL field pointer");
+    launch_energy(ctx->d, ctx->op, T, S_abs, p->E_floor, E, ctx->stream);
+    RT_HIP(ctx, hipGetLastError());
+    return RT_OK;
+}
+
+rt_status rt_fld_assemble(rt_ctx *ctx, const rt_opacity *op, const rt_fld_params *p, const double *rho,
+                          const double *T, const double *E_n, const double *q_star, const double *Q_plus,
+                          rt_system *sys)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    if (op) { rt_status s = rt_set_opacity(ctx, op); if (s) return s; }
+    RT_CHECK(ctx, ctx->have_opac, "no opacity table on the context");
+    if (rt_status s = check_fld(ctx, p)) return s;
+    RT_CHECK(ctx, rho && T && E_n && q_star, "rt_fld_assemble: NULL field pointer");
+    std::vector<double> Tt(ctx->h_opac.begin() + 1, ctx->h_opac.begin() + 1 + ctx->nT);
+    std::vector<double> kR(ctx->h_opac.end() - ctx->nT, ctx->h_opac.end());
+    double kR_bc = host_mean(Tt, kR, p->T_bc);
+    double Eb = kA * std::pow(p->T_bc, 4);
+    ctx->Eb = Eb;
+    launch_assemble(ctx->d, ctx->geo, ctx->op, rho, T, E_n, q_star, Q_plus, p->c_V, p->dt, Eb, kR_bc, ctx->chi,
+                    ctx->w, ctx->s, ctx->b, ctx->bhat, ctx->ahat, ctx->ahat32, ctx->stream);
+    RT_HIP(ctx, hipGetLastError());
+    ctx->have_system = true;
+    if (sys) {
+        sys->n = ctx->d.n;
+        sys->ahat = ctx->ahat;
+        sys->ahat32 = ctx->ahat32;
+        sys->s = ctx->s;
+        sys->bhat = ctx->bhat;
+        sys->w = ctx->w;
+        sys->chi = ctx->chi;
+    }
+    return RT_OK;
+}
+
+rt_status rt_spmv(rt_ctx *ctx, const double *x, double *y)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    RT_CHECK(ctx, ctx->have_system, "no assembled system");
+    RT_CHECK(ctx, x && y && x != y, "rt_spmv: bad vectors");
+    launch_spmv(ctx->d, ctx->ahat, x, y, ctx->stream);
+    RT_HIP(ctx, hipGetLastError());
+    return RT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct Clock {
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double ms() const
+    {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+// Adds the device times of the sampled iteration (events 8, 9, 10) to the stats.
+void add_kernel_sample(rt_ctx *ctx, rt_solve_stats *st)
+{
+    float a = 0.f, b = 0.f;
+    if (hipEventElapsedTime(&a, ctx->ev[8], ctx->ev[9]) != hipSuccess) return;
+    if (hipEventElapsedTime(&b, ctx->ev[9], ctx->ev[10]) != hipSuccess) return;
+    int n = st->kernel_samples;
+    st->ms_dir = (st->ms_dir * n + a) / (n + 1);
+    st->ms_upd = (st->ms_upd * n + b) / (n + 1);
+    st->kernel_samples = n + 1;
+}
+
+// ||bhat||^2 on the device, read back.
+rt_status norm_b(rt_ctx *ctx, double &bb)
+{
+    launch_norm2(ctx->d, ctx->nblk, ctx->chunk, ctx->bhat, ctx->partials, ctx->counter, ctx->sc, ctx->stream);
+    RT_HIP(ctx, hipGetLastError());
+    if (rt_status s = read_scalars(ctx)) return s;
+    bb = ctx->h_sc->res2;
+    return RT_OK;
+}
+
+// Plain float64 CG on A^ (the method; also the fallback and the judge of the others).
+rt_status solve_fp64(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb)
+{
+    const Dims &d = ctx->d;
+    hipStream_t s = ctx->stream;
+    DevScalars *h = ctx->h_sc;
+    h->thresh2 = o->tol * o->tol * bb;
+    h->done = 0;
+    h->iters = 0;
+    h->beta = 0.0;
+    if (rt_status e = write_scalars(ctx)) return e;
+    launch_resid(d, ctx->nblk, ctx->chunk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials, ctx->counter,
+                 ctx->sc, 1, s);
+    if (rt_status e = read_scalars(ctx)) return e;
+    double *pold = ctx->p0, *pnew = ctx->p1;
+    const int every = o->check_every > 0 ? o->check_every : 32;
+    rt_status status = RT_OK;
+    double res = std::sqrt(h->res2 / bb);  // true residual of the start guess
+    for (;;) {
+        st->relres = res;
+        if (!isfin(res)) { status = RT_ENONFINITE; break; }
+        if (res <= o->tol) break;
+        if (h->iters >= o->max_iter) { status = RT_ENOCONV; break; }
+        int m = std::min(every, o->max_iter - h->iters);
+        for (int k = 0; k < m; k++) {
+            launch_cg_iter64(d, ctx->nblk, ctx->chunk, ctx->ahat, ctx->y, ctx->r, pold, pnew, ctx->qv, ctx->partials,
+                             ctx->counter, ctx->sc, s, k == 0 ? &ctx->ev[8] : nullptr);
+            std::swap(pold, pnew);
+        }
+        RT_HIP(ctx, hipGetLastError());
+        if (rt_status e = read_scalars(ctx)) return e;
+        add_kernel_sample(ctx, st);
+        if (!isfin(h->rr)) { status = RT_ENONFINITE; st->relres = NAN; break; }
+        if (h->done || h->iters >= o->max_iter) {
+            // the recurrence met the tolerance (or the budget ran out): judge by the true
+            // residual, and restart CG from it if it is still above the tolerance
+            launch_resid(d, ctx->nblk, ctx->chunk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials,
+                         ctx->counter, ctx->sc, 1, s);
+            if (rt_status e = read_scalars(ctx)) return e;
+            res = std::sqrt(h->res2 / bb);
+        }
+    }
+    st->iters = h->iters;
+    return status;
+}
+
+// Float64 iterative refinement around float32 inner CG (all dots in float64).
+rt_status solve_mixed(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb)
+{
+    const Dims &d = ctx->d;
+    hipStream_t s = ctx->stream;
+    DevScalars *h = ctx->h_sc;
+    h->iters = 0;
+    h->done = 0;
+    if (rt_status e = write_scalars(ctx)) return e;
+    const double inner_tol = o->inner_tol > 0.0 ? o->inner_tol : 1e-4;
+    const int inner_max = o->inner_max_iter > 0 ? o->inner_max_iter : o->max_iter;
+    const int every = o->check_every > 0 ? o->check_every : 32;
+    int total = 0;
+    rt_status status = RT_OK;
+    for (;;) {
+        launch_resid(d, ctx->nblk, ctx->chunk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials, ctx->counter,
+                     ctx->sc, 0, s);
+        if (rt_status e = read_scalars(ctx)) return e;
+        double res = std::sqrt(h->res2 / bb);
+        st->relres = res;
+        if (!isfin(res)) { status = RT_ENONFINITE; break; }
+        if (res <= o->tol) break;
+        if (total >= o->max_iter) { status = RT_ENOCONV; break; }
+        st->outer_iters++;
+        launch_cast_residual(d, ctx->nblk, ctx->chunk, ctx->r, ctx->r32, ctx->x32, ctx->partials, ctx->counter,
+                             ctx->sc, inner_tol, s);
+        if (rt_status e = read_scalars(ctx)) return e;
+        int it0 = h->iters;
+        float *pold = ctx->p32a, *pnew = ctx->p32b;
+        for (;;) {
+            int done_here = h->iters - it0;
+            int m = std::min({every, inner_max - done_here, o->max_iter - total - done_here});
+            if (m <= 0) break;
+            for (int k = 0; k < m; k++) {
+                launch_cg_iter32(d, ctx->nblk, ctx->chunk, ctx->ahat32, ctx->x32, ctx->r32, pold, pnew, ctx->q32,
+                                 ctx->partials, ctx->counter, ctx->sc, s, k == 0 ? &ctx->ev[8] : nullptr);
+                std::swap(pold, pnew);
+            }
+            RT_HIP(ctx, hipGetLastError());
+            if (rt_status e = read_scalars(ctx)) return e;
+            add_kernel_sample(ctx, st);
+            if (h->done || !isfin(h->rr)) break;
+        }
+        total += h->iters - it0;
+        if (!isfin(h->rr)) { status = RT_ENONFINITE; st->relres = NAN; break; }
+        launch_refine(d.n, ctx->x32, ctx->sc, ctx->y, s);
+        RT_HIP(ctx, hipGetLastError());
+    }
+    st->iters = total;
+    return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_stats *st)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    RT_CHECK(ctx, ctx->have_system, "no assembled system");
+    RT_CHECK(ctx, o && E, "rt_fld_solve: NULL argument");
+    RT_CHECK(ctx, o->tol > 0.0 && o->tol < 1.0, "tol must be in (0, 1)");
+    RT_CHECK(ctx, o->max_iter > 0, "max_iter must be positive");
+    RT_CHECK(ctx, o->mode == RT_SOLVE_FP64 || o->mode == RT_SOLVE_MIXED || o->mode == RT_SOLVE_LEARNED,
+             "unknown solve mode");
+    RT_CHECK(ctx, o->mode != RT_SOLVE_LEARNED || o->net, "learned mode needs a network");
+    rt_solve_stats local{};
+    rt_solve_stats *S = st ? st : &local;
+    *S = rt_solve_stats{};
+    Clock clk;
+    double bb = 0.0;
+    if (rt_status e = norm_b(ctx, bb)) return e;
+    if (!isfin(bb)) {
+        S->status = RT_ENONFINITE;
+        return fail(ctx, RT_ENONFINITE, "right-hand side is not finite");
+    }
+    if (bb == 0.0) bb = 1.0;
+    launch_scale_div(ctx->d.n, ctx->s, E, ctx->y, ctx->stream);  // y0 = E / s
+    rt_status status;
+    if (o->mode == RT_SOLVE_FP64) status = solve_fp64(ctx, o, S, bb);
+    else if (o->mode == RT_SOLVE_MIXED) status = solve_mixed(ctx, o, S, bb);
+    else return fail(ctx, RT_EINVAL, "learned mode is not available in this build");
+    if (status == RT_EDEVICE) return status;
+    launch_scale_mul(ctx->d.n, ctx->s, ctx->y, E, ctx->stream);  // E = s y
+    RT_HIP(ctx, hipGetLastError());
+    RT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    S->status = status;
+    S->ms = clk.ms();
+    if (status == RT_ENOCONV) return fail(ctx, status, "iteration limit reached");
+    if (status == RT_ENONFINITE) return fail(ctx, status, "non-finite residual");
+    return status;
+}
+
+rt_status rt_temperature(rt_ctx *ctx, const rt_opacity *op, const double *E, const double *S_abs, double *T)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    if (op) { rt_status s = rt_set_opacity(ctx, op); if (s) return s; }
+    RT_CHECK(ctx, ctx->have_opac, "no opacity table on the context");
+    RT_CHECK(ctx, E && S_abs && T, "rt_temperature: NULL field pointer");
+    launch_newton(ctx->d, ctx->op, E, S_abs, T, ctx->stream);
+    RT_HIP(ctx, hipGetLastError());
+    return RT_OK;
+}
+
+rt_status rt_force(rt_ctx *ctx, const double *E, const double *q_star, double *f)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    RT_CHECK(ctx, ctx->have_system, "no assembled system");
+    RT_CHECK(ctx, E && q_star && f, "rt_force: NULL field pointer");
+    launch_force(ctx->d, ctx->geo, ctx->w, ctx->chi, E, q_star, ctx->Eb, f, ctx->stream);
+    RT_HIP(ctx, hipGetLastError());
+    return RT_OK;
+}
+
+rt_status rt_step(rt_ctx *ctx, const rt_opacity *op, const rt_star *st, const rt_fld_params *p,
+                  const rt_solve_opts *o, const double *rho, double *T, double *E, double *f_rad,
+                  rt_step_stats *stats)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    RT_CHECK(ctx, rho && T && E && o, "rt_step: NULL argument");
+    if (rt_status s = check_fld(ctx, p)) return s;
+    hipStream_t s = ctx->stream;
+    Clock clk;
+    RT_HIP(ctx, hipEventRecord(ctx->ev[0], s));
+    if (rt_status e = rt_raytrace(ctx, op, st, rho, T, ctx->q, ctx->S, nullptr)) return e;
+    RT_HIP(ctx, hipEventRecord(ctx->ev[1], s));
+    if (rt_status e = rt_energy(ctx, nullptr, p, T, ctx->S, ctx->En)) return e;
+    if (rt_status e = rt_fld_assemble(ctx, nullptr, p, rho, T, ctx->En, ctx->q, nullptr, nullptr)) return e;
+    RT_HIP(ctx, hipMemcpyAsync(E, ctx->En, ctx->d.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    RT_HIP(ctx, hipEventRecord(ctx->ev[2], s));
+    rt_solve_stats sst{};
+    rt_status solve_status = rt_fld_solve(ctx, o, E, &sst);
+    if (solve_status != RT_OK && solve_status != RT_ENOCONV) return solve_status;
+    RT_HIP(ctx, hipEventRecord(ctx->ev[3], s));
+    if (rt_status e = rt_temperature(ctx, nullptr, E, ctx->S, T)) return e;
+    RT_HIP(ctx, hipEventRecord(ctx->ev[4], s));
+    if (f_rad)
+        if (rt_status e = rt_force(ctx, E, ctx->q, f_rad)) return e;
+    RT_HIP(ctx, hipEventRecord(ctx->ev[5], s));
+    if (stats) {
+        RT_HIP(ctx, hipEventSynchronize(ctx->ev[5]));
+        float t01, t12, t23, t34, t05;
+        RT_HIP(ctx, hipEventElapsedTime(&t01, ctx->ev[0], ctx->ev[1]));
+        RT_HIP(ctx, hipEventElapsedTime(&t12, ctx->ev[1], ctx->ev[2]));
+        RT_HIP(ctx, hipEventElapsedTime(&t23, ctx->ev[2], ctx->ev[3]));
+        RT_HIP(ctx, hipEventElapsedTime(&t34, ctx->ev[3], ctx->ev[4]));
+        RT_HIP(ctx, hipEventElapsedTime(&t05, ctx->ev[0], ctx->ev[5]));
+        stats->solve = sst;
+        stats->ms_raytrace = t01;
+        stats->ms_assemble = t12;
+        stats->ms_solve = t23;
+        stats->ms_newton = t34;
+        stats->ms_total = t05;
+        (void)clk;
+    }
+    if (solve_status == RT_ENOCONV) return fail(ctx, RT_ENOCONV, "iteration limit reached");
+    return RT_OK;
+}
+
+rt_status rt_step_fields(rt_ctx *ctx, const double **q_star, const double **S_abs, const double **E_n)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    if (q_star) *q_star = ctx->q;
+    if (S_abs) *S_abs = ctx->S;
+    if (E_n) *E_n = ctx->En;
+    return RT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,256 @@
+// Internal declarations of librtmi: device helpers, the context, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rt.h"
+
+namespace rt {
+
+// CGS constants (CODATA 2018).
+constexpr double kC = 2.99792458e10;
+constexpr double kSigma = 5.670374419e-5;
+constexpr double kA = 4.0 * kSigma / kC;  // radiation constant, sigma = a c / 4 (Eq. 18)
+constexpr double kH = 6.62607015e-27;
+constexpr double kBoltz = 1.380649e-16;
+
+constexpr int kMaxNu = 64;    // bins per ray trace wavefront (lanes = bins)
+constexpr int kMaxT = 128;    // opacity-table temperatures held in LDS
+
+// Grid dimensions; cell c = i + nr (j + nt k).
+struct Dims {
+    int nr, nt, np;
+    long n;      // nr * nt * np
+    long plane;  // nr * nt
+};
+
+// 1-D geometry factors on the device (products of them give every volume, area and
+// centre distance of the spherical-polar cells).
+struct Geo {
+    const double *rf;      // [nr+1] radial faces
+    const double *rf2;     // [nr+1] r_face^2
+    const double *rc;      // [nr]   radial centres (arithmetic midpoints)
+    const double *dr;      // [nr]   r_+ - r_-
+    const double *shell;   // [nr]   r_+^3 - r_-^3
+    const double *vol_r;   // [nr]   (r_+^3 - r_-^3) / 3
+    const double *hr2;     // [nr]   (r_+^2 - r_-^2) / 2
+    const double *dsr;     // [nr]   centre distance to the next cell (last: ghost centre)
+    const double *dcos;    // [nt]   cos(th_-) - cos(th_+)
+    const double *sinf;    // [nt+1] sin(th_face)
+    const double *dth;     // [nt]   th_+ - th_-
+    const double *dtc;     // [nt]   tc[j+1] - tc[j] (last unused)
+    const double *sinc;    // [nt]   sin(tc)
+    const double *dph;     // [np]   ph_+ - ph_-
+    const double *dpc;     // [np]   centre distance to the next cell, periodic
+};
+
+// Opacity table on the device.
+struct Opac {
+    int nT, nnu;
+    const double *T;     // [nT]
+    const double *kap;   // [nT][nnu]
+    const double *kP;    // [nT] Planck means
+    const double *kR;    // [nT] Rosseland means
+    const double *lnT;   // [nT]
+    const double *lnP;   // [nT]
+    const double *lnR;   // [nT]
+};
+
+// ---------------------------------------------------------------- device helpers
+
+// Largest node k in [0, nT-2] with T[k] <= t (caller has handled t outside the table).
+__device__ __forceinline__ int find_node(const double *__restrict__ Tt, int nT, double t)
+{
+    int lo = 0, hi = nT - 1;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (Tt[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Node and linear weight of t in the table (kappa_nu is linear in T), clamped.
+__device__ __forceinline__ void lin_node(const double *__restrict__ Tt, int nT, double t, int &k, double &w)
+{
+    if (t <= Tt[0]) { k = 0; w = 0.0; return; }
+    if (t >= Tt[nT - 1]) { k = nT - 2; w = 1.0; return; }
+    k = find_node(Tt, nT, t);
+    w = (t - Tt[k]) / (Tt[k + 1] - Tt[k]);
+}
+
+// Mean opacity interpolated log-log in T; *slope = d ln kappa / d ln T (0 when clamped).
+__device__ __forceinline__ double mean_opacity(const double *__restrict__ Tt, const double *__restrict__ lnT,
+                                               const double *__restrict__ tab, const double *__restrict__ lnY,
+                                               int nT, double t, double *slope)
+{
+    if (t <= Tt[0]) { if (slope) *slope = 0.0; return tab[0]; }
+    if (t >= Tt[nT - 1]) { if (slope) *slope = 0.0; return tab[nT - 1]; }
+    int k = find_node(Tt, nT, t);
+    double l0 = lnT[k], l1 = lnT[k + 1];
+    double lw = (log(t) - l0) / (l1 - l0);
+    if (slope) *slope = (lnY[k + 1] - lnY[k]) / (l1 - l0);
+    return exp((1.0 - lw) * lnY[k] + lw * lnY[k + 1]);
+}
+
+// FLD diffusion coefficient at a face between cells a and b: Eqs. (11)-(13) with
+// (kappa_R rho) and E averaged over the two cells and R from the normal difference;
+// above R = 1e100 the limiter (2+R)/(6+3R+R^2) is replaced by its limit 1/R.
+__device__ __forceinline__ double face_D(double chi_a, double chi_b, double Ea, double Eb, double ds)
+{
+    double chi = 0.5 * (chi_a + chi_b);
+    double Ef = 0.5 * (Ea + Eb);
+    double R = fabs(Eb - Ea) / (ds * chi * Ef);
+    double lam = R < 1e100 ? (2.0 + R) / (6.0 + 3.0 * R + R * R) : 1.0 / R;
+    return kC * lam / chi;
+}
+
+// e = exp(-x) and m = 1 - exp(-x) for x >= 0 from one range reduction: x = k ln2 + r
+// with |r| <= ln2/2 (Cody-Waite split of ln2), p = expm1(-r) by its Taylor series to
+// degree 13 (truncation < 4e-18 relative on that interval), then e = 2^-k (1 + p) and
+// m = (1 - 2^-k) - 2^-k p, which keeps full relative accuracy for small and large x.
+__device__ __forceinline__ void exp_pair(double x, double &e, double &m)
+{
+    constexpr double kInvLn2 = 1.4426950408889634074;
+    constexpr double kLn2Hi = 6.93147180369123816490e-01;
+    constexpr double kLn2Lo = 1.90821492927058770002e-10;
+    x = x > 2000.0 ? 2000.0 : x;
+    double kf = rint(x * kInvLn2);
+    double r = fma(-kf, kLn2Hi, x);
+    r = fma(-kf, kLn2Lo, r);
+    double u = -r;
+    double p = 1.0 / 6227020800.0;                 // 1/13!
+    p = fma(p, u, 1.0 / 479001600.0);              // 1/12!
+    p = fma(p, u, 1.0 / 39916800.0);               // 1/11!
+    p = fma(p, u, 1.0 / 3628800.0);                // 1/10!
+    p = fma(p, u, 1.0 / 362880.0);                 // 1/9!
+    p = fma(p, u, 1.0 / 40320.0);                  // 1/8!
+    p = fma(p, u, 1.0 / 5040.0);                   // 1/7!
+    p = fma(p, u, 1.0 / 720.0);                    // 1/6!
+    p = fma(p, u, 1.0 / 120.0);                    // 1/5!
+    p = fma(p, u, 1.0 / 24.0);                     // 1/4!
+    p = fma(p, u, 1.0 / 6.0);                      // 1/3!
+    p = fma(p, u, 0.5);                            // 1/2!
+    p = fma(p, u, 1.0);
+    p = p * u;                                     // expm1(u)
+    int k = (int)kf;
+    double s = ldexp(1.0, -k);
+    e = fma(s, p, s);
+    m = (k == 0) ? -p : fma(-s, p, 1.0 - s);
+}
+
+// Orders LDS traffic between the lanes of one wavefront.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane)
+{
+    int2 t = *reinterpret_cast<int2 *>(&v);
+    t.x = __builtin_amdgcn_readlane(t.x, lane);
+    t.y = __builtin_amdgcn_readlane(t.y, lane);
+    return *reinterpret_cast<double *>(&t);
+}
+
+// ------------------------------------------------------------------- context
+
+// Krylov scalars kept in device memory and updated by the last block of each
+// reduction kernel; the host reads them back only to poll convergence.
+struct DevScalars {
+    double rr;       // r.r of the current residual (recurrence)
+    double pq;       // p.q
+    double alpha, beta;
+    double thresh2;  // stop when rr <= thresh2
+    double res2;     // last reduction of the residual kernel
+    double inv_norm; // 1 / sqrt(res2)
+    int done;
+    int iters;
+};
+
+struct Net;
+
+// ------------------------------------------------------------------ launchers
+void launch_raytrace(const Dims &d, const Opac &op, const Geo &g, const double *F0, double R2,
+                     const double *rho, const double *T, double *q, double *S, double *Fface,
+                     hipStream_t st);
+size_t raytrace_lds_bytes(int nT, int nnu);
+void launch_energy(const Dims &d, const Opac &op, const double *T, const double *S, double Efloor,
+                   double *E, hipStream_t st);
+void launch_assemble(const Dims &d, const Geo &g, const Opac &op, const double *rho, const double *T,
+                     const double *En, const double *q, const double *Q, double cV, double dt,
+                     double Eb, double kR_bc, double *chi, double *w, double *s, double *b,
+                     double *bhat, double *ahat, float *ahat32, hipStream_t st);
+void launch_newton(const Dims &d, const Opac &op, const double *E, const double *S, double *T,
+                   hipStream_t st);
+void launch_force(const Dims &d, const Geo &g, const double *w, const double *chi, const double *E,
+                  const double *q, double Eb, double *f, hipStream_t st);
+void launch_scale_mul(long n, const double *s, const double *x, double *y, hipStream_t st);
+void launch_scale_div(long n, const double *s, const double *x, double *y, hipStream_t st);
+void launch_spmv(const Dims &d, const double *a, const double *x, double *y, hipStream_t st);
+void launch_norm2(const Dims &d, int nblk, long chunk, const double *x, double *partials, unsigned *counter,
+                  DevScalars *sc, hipStream_t st);
+void launch_resid(const Dims &d, int nblk, long chunk, const double *a, const double *b, const double *y,
+                  double *r, double *partials, unsigned *counter, DevScalars *sc, int restart, hipStream_t st);
+// One CG iteration (direction+operator kernel, then update kernel).  When ev is given,
+// ev[0], ev[1], ev[2] are recorded before, between and after the two kernels.
+void launch_cg_iter64(const Dims &d, int nblk, long chunk, const double *a, double *y, double *r,
+                      double *pold, double *pnew, double *q, double *partials, unsigned *counter,
+                      DevScalars *sc, hipStream_t st, const hipEvent_t *ev = nullptr);
+void launch_cg_iter32(const Dims &d, int nblk, long chunk, const float *a, float *x, float *r, float *pold,
+                      float *pnew, float *q, double *partials, unsigned *counter, DevScalars *sc,
+                      hipStream_t st, const hipEvent_t *ev = nullptr);
+void launch_cast_residual(const Dims &d, int nblk, long chunk, const double *r, float *r32, float *x32,
+                          double *partials, unsigned *counter, DevScalars *sc, double inner_tol, hipStream_t st);
+void launch_refine(long n, const float *x32, const DevScalars *sc, double *y, hipStream_t st);
+
+}  // namespace rt
+
+struct rt_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    rt::Dims d{};
+    int n_nu = 0;
+    std::string err;
+
+    // host copies of the problem description
+    std::vector<double> h_rf, h_tf, h_pf;
+    std::vector<double> h_opac;  // packed copy of the last uploaded table (change detection)
+    std::vector<double> h_star;  // packed copy of the last uploaded star
+    bool have_opac = false, have_star = false;
+    double R_star = 0.0, T_star = 0.0;
+    int nT = 0;
+
+    // device memory: one arena per kind, freed at destroy
+    std::vector<void *> allocs;
+    rt::Geo geo{};
+    rt::Opac op{};
+    double *F0 = nullptr;  // [n_nu] star flux per bin at R_*
+
+    // step fields
+    double *q = nullptr, *S = nullptr, *En = nullptr, *Tn = nullptr;
+    // system
+    double *w = nullptr, *ahat = nullptr, *s = nullptr, *b = nullptr, *bhat = nullptr, *chi = nullptr;
+    float *ahat32 = nullptr;
+    bool have_system = false;
+    double Eb = 0.0;  // a T_bc^4 of the assembled system
+    // Krylov vectors
+    double *y = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *qv = nullptr, *tmp = nullptr;
+    float *r32 = nullptr, *z32 = nullptr, *p32a = nullptr, *p32b = nullptr, *q32 = nullptr, *x32 = nullptr;
+    // reductions
+    int nblk = 0;             // blocks of the reduction kernels (multiple of 8)
+    long chunk = 0;           // cells per block
+    double *partials = nullptr;
+    unsigned *counter = nullptr;
+    rt::DevScalars *sc = nullptr;   // device
+    rt::DevScalars *h_sc = nullptr; // pinned host mirror
+    hipEvent_t ev[12] = {};
+
+    rt::Net *net_scratch = nullptr;
+};

@@ -1,0 +1,311 @@
+"""ctypes binding of librtmi (include/rt.h): argument marshalling only.
+
+Every step of the radiation step runs in the HIP library; this module checks tensor
+arguments (device, dtype, size, contiguity), passes their device pointers, and turns
+non-zero rt_status codes into RtError.  torch provides device memory and the stream.
+If librtmi.so is missing, loading fails loudly (build it with
+`python -m paper_1001_3301_amd.build`).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtmi.so")
+
+RT_OK, RT_EINVAL, RT_EDEVICE, RT_ENOMEM, RT_ENONFINITE, RT_ENOCONV = range(6)
+STATUS_NAMES = {0: "RT_OK", 1: "RT_EINVAL", 2: "RT_EDEVICE", 3: "RT_ENOMEM", 4: "RT_ENONFINITE",
+                5: "RT_ENOCONV"}
+MODE_FP64, MODE_MIXED, MODE_LEARNED = 0, 1, 2
+
+dp = C.POINTER(C.c_double)
+
+
+class RtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Grid(C.Structure):
+    _fields_ = [("nr", C.c_int), ("nt", C.c_int), ("np", C.c_int),
+                ("r_face", dp), ("th_face", dp), ("ph_face", dp)]
+
+
+class Opacity(C.Structure):
+    _fields_ = [("n_T", C.c_int), ("n_nu", C.c_int), ("T", dp), ("nu", dp), ("kappa", dp),
+                ("kappa_P", dp), ("kappa_R", dp)]
+
+
+class Star(C.Structure):
+    _fields_ = [("R_star", C.c_double), ("T_star", C.c_double), ("F_nu", dp)]
+
+
+class FldParams(C.Structure):
+    _fields_ = [("dt", C.c_double), ("c_V", C.c_double), ("T_bc", C.c_double),
+                ("E_floor", C.c_double)]
+
+
+class System(C.Structure):
+    _fields_ = [("n", C.c_long), ("ahat", C.c_void_p), ("ahat32", C.c_void_p), ("s", C.c_void_p),
+                ("bhat", C.c_void_p), ("w", C.c_void_p), ("chi", C.c_void_p)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("mode", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
+                ("check_every", C.c_int), ("inner_tol", C.c_double), ("inner_max_iter", C.c_int),
+                ("net", C.c_void_p)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("status", C.c_int), ("iters", C.c_int), ("outer_iters", C.c_int),
+                ("precond_applies", C.c_int), ("fallback", C.c_int), ("relres", C.c_double),
+                ("ms", C.c_double), ("ms_dir", C.c_double), ("ms_upd", C.c_double),
+                ("kernel_samples", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class StepStats(C.Structure):
+    _fields_ = [("solve", SolveStats), ("ms_raytrace", C.c_double), ("ms_assemble", C.c_double),
+                ("ms_solve", C.c_double), ("ms_newton", C.c_double), ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "solve"}
+        d["solve"] = self.solve.as_dict()
+        return d
+
+
+# Every symbol include/rt.h declares (checked by the tests).
+EXPORTS = ["rt_create", "rt_destroy", "rt_last_error", "rt_ncell", "rt_star_bin_flux",
+           "rt_set_opacity", "rt_set_star", "rt_raytrace", "rt_energy", "rt_fld_assemble",
+           "rt_spmv", "rt_fld_solve", "rt_temperature", "rt_force", "rt_step", "rt_step_fields"]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1001_3301_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    P, vp = C.POINTER, C.c_void_p
+    L.rt_create.argtypes = [P(vp), P(Grid), C.c_int, vp]
+    L.rt_destroy.argtypes = [vp]
+    L.rt_destroy.restype = None
+    L.rt_last_error.argtypes = [vp]
+    L.rt_last_error.restype = C.c_char_p
+    L.rt_ncell.argtypes = [vp]
+    L.rt_ncell.restype = C.c_long
+    L.rt_star_bin_flux.argtypes = [C.c_double, C.c_int, dp, dp]
+    L.rt_set_opacity.argtypes = [vp, P(Opacity)]
+    L.rt_set_star.argtypes = [vp, P(Star)]
+    L.rt_raytrace.argtypes = [vp, P(Opacity), P(Star), vp, vp, vp, vp, vp]
+    L.rt_energy.argtypes = [vp, P(Opacity), P(FldParams), vp, vp, vp]
+    L.rt_fld_assemble.argtypes = [vp, P(Opacity), P(FldParams), vp, vp, vp, vp, vp, P(System)]
+    L.rt_spmv.argtypes = [vp, vp, vp]
+    L.rt_fld_solve.argtypes = [vp, P(SolveOpts), vp, P(SolveStats)]
+    L.rt_temperature.argtypes = [vp, P(Opacity), vp, vp, vp]
+    L.rt_force.argtypes = [vp, vp, vp, vp]
+    L.rt_step.argtypes = [vp, P(Opacity), P(Star), P(FldParams), P(SolveOpts), vp, vp, vp, vp,
+                          P(StepStats)]
+    L.rt_step_fields.argtypes = [vp, P(vp), P(vp), P(vp)]
+    _lib = L
+    return L
+
+
+def _host(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _hp(a):
+    return a.ctypes.data_as(dp)
+
+
+def star_bin_flux(T_star: float, nu) -> np.ndarray:
+    """Eq. (20) bin fluxes (host computation in the library)."""
+    nu = _host(nu)
+    out = np.empty_like(nu)
+    st = lib().rt_star_bin_flux(float(T_star), len(nu), _hp(nu), _hp(out))
+    if st != RT_OK:
+        raise RtError(st, lib().rt_last_error(None).decode())
+    return out
+
+
+def solve_opts(mode=MODE_FP64, tol=1e-8, max_iter=100000, check_every=32, inner_tol=1e-4,
+               inner_max_iter=0, net=None) -> SolveOpts:
+    return SolveOpts(mode, tol, max_iter, check_every, inner_tol, inner_max_iter, net)
+
+
+class Context:
+    """One rt_ctx bound to torch's current stream on the current device."""
+
+    def __init__(self, r_face, th_face, ph_face, n_nu: int, stream=None):
+        import torch
+        self._torch = torch
+        self._faces = [_host(x) for x in (r_face, th_face, ph_face)]
+        rf, tf, pf = self._faces
+        self.shape = (len(rf) - 1, len(tf) - 1, len(pf) - 1)
+        self.n = int(np.prod(self.shape))
+        self.n_nu = n_nu
+        g = Grid(self.shape[0], self.shape[1], self.shape[2], _hp(rf), _hp(tf), _hp(pf))
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = C.c_void_p()
+        st = lib().rt_create(C.byref(h), C.byref(g), n_nu, C.c_void_p(stream))
+        if st != RT_OK:
+            raise RtError(st, lib().rt_last_error(None).decode())
+        self.h = h
+        self._op = None
+        self._star = None
+        self._keep = []
+
+    @classmethod
+    def from_workload(cls, wl, stream=None):
+        g = wl.grid
+        ctx = cls(g.r_face, g.th_face, g.ph_face, len(wl.opacity.nu), stream)
+        ctx.set_opacity(wl.opacity)
+        ctx.set_star(wl.R_star, wl.T_star, star_bin_flux(wl.T_star, wl.opacity.nu))
+        ctx.params = FldParams(wl.dt, wl.c_V, wl.T_bc, wl.E_floor)
+        return ctx
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- helpers -----------------------------------------------------------
+    def _chk(self, st):
+        if st != RT_OK:
+            raise RtError(st, lib().rt_last_error(self.h).decode())
+
+    def _dev(self, t, n, name, dtype=None, allow_none=False):
+        torch = self._torch
+        if t is None:
+            if allow_none:
+                return None
+            raise ValueError(f"{name} is required")
+        dtype = dtype or torch.float64
+        if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name}: need a contiguous {dtype} CUDA tensor of {n} elements, got "
+                             f"{t.dtype} {tuple(t.shape)} on {t.device}")
+        return C.c_void_p(t.data_ptr())
+
+    def set_opacity(self, op):
+        arrs = [_host(op.T), _host(op.nu), _host(op.kappa), _host(op.kappa_P), _host(op.kappa_R)]
+        o = Opacity(len(arrs[0]), len(arrs[1]), *[_hp(a) for a in arrs])
+        self._chk(lib().rt_set_opacity(self.h, C.byref(o)))
+        self._op = (o, arrs)
+
+    def set_star(self, R_star, T_star, F_nu):
+        F = _host(F_nu)
+        s = Star(float(R_star), float(T_star), _hp(F))
+        self._chk(lib().rt_set_star(self.h, C.byref(s)))
+        self._star = (s, F)
+
+    # --- the step's calls --------------------------------------------------
+    def raytrace(self, rho, T, q, S, F_face=None):
+        nr, nt, npp = self.shape
+        args = [self._dev(rho, self.n, "rho"), self._dev(T, self.n, "T"), self._dev(q, self.n, "q"),
+                self._dev(S, self.n, "S"),
+                self._dev(F_face, (nr + 1) * nt * npp, "F_face", allow_none=True)]
+        self._chk(lib().rt_raytrace(self.h, None, None, *args))
+
+    def energy(self, T, S, E, params=None):
+        p = params or self.params
+        self._chk(lib().rt_energy(self.h, None, C.byref(p), self._dev(T, self.n, "T"),
+                                  self._dev(S, self.n, "S"), self._dev(E, self.n, "E")))
+
+    def assemble(self, rho, T, En, q, Q=None, params=None):
+        p = params or self.params
+        sysv = System()
+        self._chk(lib().rt_fld_assemble(self.h, None, C.byref(p), self._dev(rho, self.n, "rho"),
+                                        self._dev(T, self.n, "T"), self._dev(En, self.n, "E_n"),
+                                        self._dev(q, self.n, "q"),
+                                        self._dev(Q, self.n, "Q", allow_none=True), C.byref(sysv)))
+        return sysv
+
+    def system_tensors(self, sysv):
+        """Copies of the assembled system (ahat [3n], ahat32 [3n], s, bhat, w [3n], chi)."""
+        torch = self._torch
+        n = self.n
+        out = {}
+        for name, cnt, dt in (("ahat", 3 * n, torch.float64), ("ahat32", 3 * n, torch.float32),
+                              ("s", n, torch.float64), ("bhat", n, torch.float64),
+                              ("w", 3 * n, torch.float64), ("chi", n, torch.float64)):
+            t = torch.empty(cnt, dtype=dt, device="cuda")
+            _memcpy_d2d(t.data_ptr(), getattr(sysv, name), t.numel() * t.element_size())
+            out[name] = t
+        return out
+
+    def spmv(self, x, y):
+        self._chk(lib().rt_spmv(self.h, self._dev(x, self.n, "x"), self._dev(y, self.n, "y")))
+
+    def solve(self, E, opts: SolveOpts, raise_on_error=True):
+        st = SolveStats()
+        rc = lib().rt_fld_solve(self.h, C.byref(opts), self._dev(E, self.n, "E"), C.byref(st))
+        if raise_on_error:
+            self._chk(rc)
+        return rc, st.as_dict()
+
+    def temperature(self, E, S, T):
+        self._chk(lib().rt_temperature(self.h, None, self._dev(E, self.n, "E"),
+                                       self._dev(S, self.n, "S"), self._dev(T, self.n, "T")))
+
+    def force(self, E, q, f):
+        self._chk(lib().rt_force(self.h, self._dev(E, self.n, "E"), self._dev(q, self.n, "q"),
+                                 self._dev(f, 4 * self.n, "f")))
+
+    def step(self, rho, T, E, opts: SolveOpts, f_rad=None, params=None, raise_on_error=True):
+        p = params or self.params
+        st = StepStats()
+        rc = lib().rt_step(self.h, None, None, C.byref(p), C.byref(opts),
+                           self._dev(rho, self.n, "rho"), self._dev(T, self.n, "T"),
+                           self._dev(E, self.n, "E"),
+                           self._dev(f_rad, 4 * self.n, "f_rad", allow_none=True), C.byref(st))
+        if raise_on_error:
+            self._chk(rc)
+        return rc, st.as_dict()
+
+    def step_fields(self):
+        """Copies of the last step's q_star, S_abs and E^n."""
+        torch = self._torch
+        ptrs = [C.c_void_p() for _ in range(3)]
+        self._chk(lib().rt_step_fields(self.h, *[C.byref(p) for p in ptrs]))
+        out = []
+        for p in ptrs:
+            t = torch.empty(self.n, dtype=torch.float64, device="cuda")
+            _memcpy_d2d(t.data_ptr(), p.value, t.numel() * 8)
+            out.append(t)
+        return out
+
+
+_hip = None
+
+
+def _memcpy_d2d(dst: int, src: int, nbytes: int):
+    """Device-to-device copy through the HIP runtime (synchronises the device first)."""
+    global _hip
+    import torch
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.hipDeviceSynchronize.argtypes = []
+    torch.cuda.synchronize()
+    rc = _hip.hipMemcpy(C.c_void_p(dst), C.c_void_p(src), C.c_size_t(nbytes), 3)  # device to device
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")
+    torch.cuda.synchronize()

@@ -1,0 +1,246 @@
+"""Parity of the HIP radiation step (through the C-ABI) with the CPU oracle.
+
+Every comparison feeds both sides the same seeded inputs from the generators; no
+expected value comes from the HIP path.  Tolerances: float64 kernels 1e-11 relative
+(rel = max |x - y| / max(|y|, 1e-30 max |y|)); solves are compared through the
+oracle's own residual of the GPU answer and against an oracle solve.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1001_3301_amd import synth as sy
+from _util import rel, small_workload, initial_temperature, seeded_temperature
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+A = sy.A_RAD
+
+
+def _ctx(wl):
+    from paper_1001_3301_amd import rt
+    return rt.Context.from_workload(wl)
+
+
+def _d(x):
+    return torch.tensor(np.ascontiguousarray(x, dtype=np.float64).ravel(), device="cuda")
+
+
+def _h(t):
+    return t.detach().cpu().numpy()
+
+
+CASES = {
+    "ragged-67x13x5-nu61": lambda: small_workload(),
+    "axisym-64x16x1-nu32": lambda: sy.config_workloads("axisym-64x16x1-nu32")[0],
+    "gray-33x7x3-nu1": lambda: sy.make_workload("gray", 33, 7, 3, 1, 30.0, clump_seed=2),
+    "thick-40x9x4-nu64": lambda: sy.make_workload("thick", 40, 9, 4, 64, 100.0, clump_seed=3),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_raytrace_parity(case):
+    wl = CASES[case]()
+    P = oracle.Problem.from_workload(wl)
+    ctx = _ctx(wl)
+    T = seeded_temperature(P.n, 5, 10.0, 2500.0)  # spans the sublimation drop
+    q0, S0, F0 = P.raytrace(wl.rho, T)
+    nr, nt, npp = wl.grid.shape
+    q, S, F = (torch.empty(P.n, dtype=torch.float64, device="cuda") for _ in range(3))
+    Ff = torch.empty((nr + 1) * nt * npp, dtype=torch.float64, device="cuda")
+    ctx.raytrace(_d(wl.rho), _d(T), q, S, Ff)
+    torch.cuda.synchronize()
+    assert rel(_h(q), q0) < 1e-11
+    assert rel(_h(S), S0) < 1e-11
+    assert rel(_h(Ff), F0) < 1e-11
+
+
+def test_raytrace_c2_tau100_full():
+    wl = sy.config_workloads("clumpy-128x64x128-nu64")[3]
+    P = oracle.Problem.from_workload(wl)
+    ctx = _ctx(wl)
+    T = seeded_temperature(P.n, 6, 14.0, 800.0)
+    q0, S0, F0 = P.raytrace(wl.rho, T)
+    q, S = (torch.empty(P.n, dtype=torch.float64, device="cuda") for _ in range(2))
+    Ff = torch.empty(129 * 64 * 128, dtype=torch.float64, device="cuda")
+    ctx.raytrace(_d(wl.rho), _d(T), q, S, Ff)
+    assert rel(_h(q), q0) < 1e-11
+    assert rel(_h(S), S0) < 1e-11
+    assert rel(_h(Ff), F0) < 1e-11
+
+
+def test_energy_and_newton_parity():
+    wl = small_workload()
+    P = oracle.Problem.from_workload(wl)
+    ctx = _ctx(wl)
+    rng = np.random.Generator(np.random.PCG64(9))
+    T = seeded_temperature(P.n, 8, 5.0, 3000.0)
+    S = 10 ** rng.uniform(-9, -1, P.n)
+    E0 = P.energy(T, S)
+    E = torch.empty(P.n, dtype=torch.float64, device="cuda")
+    ctx.energy(_d(T), _d(S), E)
+    assert rel(_h(E), E0) < 1e-12
+    Ein = A * seeded_temperature(P.n, 10, 10.0, 900.0) ** 4
+    Tst = seeded_temperature(P.n, 11, 10.0, 900.0)
+    T0 = P.newton(Ein, S, Tst)
+    Td = _d(Tst)
+    ctx.temperature(_d(Ein), _d(S), Td)
+    assert rel(_h(Td), T0) < 1e-12
+
+
+def _assembled(wl, P, ctx):
+    T = initial_temperature(P, wl)
+    q, S, _ = P.raytrace(wl.rho, T, want_faces=False)
+    En = P.energy(T, S)
+    ref = P.assemble(wl.rho, T, En, q)
+    sysv = ctx.assemble(_d(wl.rho), _d(T), _d(En), _d(q))
+    return T, q, S, En, ref, ctx.system_tensors(sysv)
+
+
+@pytest.mark.parametrize("case", ["ragged-67x13x5-nu61", "axisym-64x16x1-nu32"])
+def test_assembly_and_spmv_parity(case):
+    wl = CASES[case]()
+    P = oracle.Problem.from_workload(wl)
+    ctx = _ctx(wl)
+    T, q, S, En, ref, got = _assembled(wl, P, ctx)
+    for k in ("w", "s", "bhat", "ahat"):
+        assert rel(_h(got[k]), ref[k]) < 1e-12, k
+    a32 = _h(got["ahat32"]).astype(np.float64)
+    assert np.max(np.abs(a32 - ref["ahat"].astype(np.float32))) <= 1e-7 * np.max(np.abs(ref["ahat"]))
+    x = np.random.Generator(np.random.PCG64(4)).standard_normal(P.n)
+    y = torch.empty(P.n, dtype=torch.float64, device="cuda")
+    ctx.spmv(_d(x), y)
+    assert np.max(np.abs(_h(y) - P.spmv(ref["ahat"], x))) < 1e-13 * np.max(np.abs(x))
+
+
+def test_solve_fp64_against_dense_oracle():
+    from paper_1001_3301_amd import rt
+    wl = CASES["axisym-64x16x1-nu32"]()
+    P = oracle.Problem.from_workload(wl)
+    ctx = _ctx(wl)
+    T, q, S, En, ref, got = _assembled(wl, P, ctx)
+    yd = P.dense_solve(ref["ahat"], ref["bhat"])
+    E = _d(En)
+    rc, st = ctx.solve(E, rt.solve_opts(rt.MODE_FP64, tol=1e-14, max_iter=5000, check_every=8))
+    assert st["relres"] <= 1e-14
+    y = _h(E) / ref["s"]
+    assert P.relres(ref["ahat"], ref["bhat"], y) <= 1.01e-14
+    assert rel(y, yd) < 1e-9
+    # the temperature it implies agrees with the dense answer to the float64 bar
+    Td = P.newton(yd * ref["s"], S, T)
+    Tg = P.newton(_h(E), S, T)
+    assert rel(Tg, Td) < 1e-11
+
+
+@pytest.mark.parametrize("case", ["ragged-67x13x5-nu61", "axisym-64x16x1-nu32", "thick-40x9x4-nu64"])
+def test_step_fp64_parity(case):
+    from paper_1001_3301_amd import rt
+    wl = CASES[case]()
+    P = oracle.Problem.from_workload(wl)
+    ctx = _ctx(wl)
+    T0 = initial_temperature(P, wl)
+    ref = P.step(wl.rho, T0, tol=1e-13, max_iter=100000)
+    Td, E, f = _d(T0), torch.empty(P.n, dtype=torch.float64, device="cuda"), \
+        torch.empty(4 * P.n, dtype=torch.float64, device="cuda")
+    rc, st = ctx.step(_d(wl.rho), Td, E, rt.solve_opts(rt.MODE_FP64, tol=1e-13, max_iter=100000),
+                      f_rad=f)
+    assert st["solve"]["relres"] <= 1e-13
+    assert rel(_h(Td), ref["T"]) < 1e-11
+    assert rel(_h(E), ref["E"]) < 1e-7
+    fr = ref["force"].reshape(4, P.n)
+    fg = _h(f).reshape(4, P.n)
+    assert rel(fg[0], fr[0]) < 1e-11
+    # the thermal force differentiates E, so its error follows the solve's; measure it
+    # against the magnitude of the thermal force vector
+    scale = np.max(np.sqrt(fr[1] ** 2 + fr[2] ** 2 + fr[3] ** 2)) + 1e-300
+    for c in (1, 2, 3):
+        assert np.max(np.abs(fg[c] - fr[c])) <= 1e-6 * scale, c
+
+
+def test_force_kernel_parity():
+    wl = small_workload()
+    P = oracle.Problem.from_workload(wl)
+    ctx = _ctx(wl)
+    T, q, S, En, ref, got = _assembled(wl, P, ctx)
+    E = A * seeded_temperature(P.n, 12, 14.0, 300.0) ** 4
+    f0 = P.force(wl.rho, T, ref["w"], E, q)
+    f = torch.empty(4 * P.n, dtype=torch.float64, device="cuda")
+    ctx.force(_d(E), _d(q), f)
+    fr, fg = f0.reshape(4, -1), _h(f).reshape(4, -1)
+    for c in range(4):
+        assert np.max(np.abs(fg[c] - fr[c])) <= 1e-11 * np.max(np.abs(fr[c])), c
+
+
+def test_step_c2_tau100_fp64_and_mixed():
+    """128x64x128, 64 bins, tau550 = 100 with clumps: the float64 step at 1e-8 and the
+    mixed-precision step at 1e-8 against the oracle step at 1e-10."""
+    from paper_1001_3301_amd import rt
+    wl = sy.config_workloads("clumpy-128x64x128-nu64")[3]
+    P = oracle.Problem.from_workload(wl)
+    ctx = _ctx(wl)
+    T0 = initial_temperature(P, wl)
+    ref = P.step(wl.rho, T0, tol=1e-10, max_iter=100000, want_force=False)
+    rho = _d(wl.rho)
+    for mode in (rt.MODE_FP64, rt.MODE_MIXED):
+        Td, E = _d(T0), torch.empty(P.n, dtype=torch.float64, device="cuda")
+        rc, st = ctx.step(rho, Td, E, rt.solve_opts(mode, tol=1e-8, max_iter=200000))
+        assert st["solve"]["relres"] <= 1e-8
+        errT = rel(_h(Td), ref["T"])
+        assert errT < (1e-6 if mode == rt.MODE_FP64 else 1e-3), (mode, errT)
+        assert rel(_h(E), ref["E"]) < 1e-3
+
+
+def test_mixed_solve_matches_fp64_solution():
+    from paper_1001_3301_amd import rt
+    wl = small_workload(tau=100.0)
+    P = oracle.Problem.from_workload(wl)
+    ctx = _ctx(wl)
+    T, q, S, En, ref, got = _assembled(wl, P, ctx)
+    y, st0, it, res = P.cg(ref["ahat"], ref["bhat"], En / ref["s"], 1e-12, 100000)
+    E = _d(En)
+    rc, st = ctx.solve(E, rt.solve_opts(rt.MODE_MIXED, tol=1e-10, max_iter=100000, inner_tol=1e-3))
+    assert st["relres"] <= 1e-10 and st["outer_iters"] >= 2
+    assert P.relres(ref["ahat"], ref["bhat"], _h(E) / ref["s"]) <= 1.01e-10
+    Tg = P.newton(_h(E), S, T)
+    Tr = P.newton(y * ref["s"], S, T)
+    assert rel(Tg, Tr) < 1e-8
+
+
+def test_deterministic_bitwise():
+    from paper_1001_3301_amd import rt
+    wl = small_workload()
+    P = oracle.Problem.from_workload(wl)
+    ctx = _ctx(wl)
+    T0 = initial_temperature(P, wl)
+    outs = []
+    for _ in range(2):
+        Td, E = _d(T0), torch.empty(P.n, dtype=torch.float64, device="cuda")
+        ctx.step(_d(wl.rho), Td, E, rt.solve_opts(rt.MODE_FP64, tol=1e-10))
+        outs.append((_h(Td), _h(E)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_error_paths():
+    from paper_1001_3301_amd import rt
+    wl = small_workload()
+    P = oracle.Problem.from_workload(wl)
+    ctx = _ctx(wl)
+    T0 = initial_temperature(P, wl)
+    # iteration limit: RT_ENOCONV with the last iterate written
+    Td, E = _d(T0), torch.empty(P.n, dtype=torch.float64, device="cuda")
+    rc, st = ctx.step(_d(wl.rho), Td, E, rt.solve_opts(rt.MODE_FP64, tol=1e-12, max_iter=1),
+                      raise_on_error=False)
+    assert rc == rt.RT_ENOCONV and st["solve"]["iters"] >= 1
+    assert np.all(np.isfinite(_h(E)))
+    # non-finite input: RT_ENONFINITE
+    rho = wl.rho.ravel().copy()
+    rho[123] = np.nan
+    rc, st = ctx.step(_d(rho), _d(T0), E, rt.solve_opts(rt.MODE_FP64, tol=1e-8), raise_on_error=False)
+    assert rc == rt.RT_ENONFINITE
+    # bad arguments never reach the device
+    with pytest.raises(ValueError):
+        ctx.raytrace(_d(wl.rho)[:-1], _d(T0), E, E)
+    with pytest.raises(rt.RtError) as ei:
+        ctx.solve(E, rt.solve_opts(rt.MODE_FP64, tol=2.0))
+    assert ei.value.status == rt.RT_EINVAL
