@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="copy a buffer of this size once before timing (HBM-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the radiation step is built and measured on a "
@@ -131,6 +133,14 @@ def main():
     ctx.temperature(E0, S, T0)
     del q, S, E0
     torch.cuda.synchronize()
+
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"calibration copy of {args.calib_copy_mib} MiB done")
 
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
     results = {}

@@ -7,22 +7,30 @@
 // One CG iteration is two kernels:
 //   dir : p = r + beta p_old (recomputed for the six neighbours), q = A p, dot p.q
 //   upd : y += alpha p, r -= alpha q, dot r.r
+// Work layout: the unit of work is a radial row (one (theta, phi) column of N_r cells,
+// contiguous in memory); a thread owns VW consecutive cells of a row and moves them
+// with 16-byte vector loads (VW = 2 doubles or 4 floats; 1 when N_r is not a multiple
+// of VW).  Each XCD owns a theta-band of rows over all phi-planes and sweeps it in
+// windows (see for_segments), so the stencil's +-theta and +-phi neighbour rows are
+// re-read from that XCD's L2 instead of HBM.  Row index arithmetic is incremental, so
+// no division happens per cell.
 // Every dot product is accumulated in float64 and reduced deterministically: a fixed
 // tree inside each block, one partial per block, and the last block to finish sums
 // the partials in index order and updates the scalars (alpha, beta, convergence
-// flag) in device memory, so the host only polls every few iterations.  Blocks own
-// contiguous cell ranges, and consecutive ranges are placed on the same XCD so that
-// the +-1 plane neighbours of a range are read through that XCD's L2.
+// flag) in device memory, so the host only polls every few iterations.
+#include <cstdlib>
+
 #include "rt_internal.h"
 
 namespace rt {
 
 constexpr int kKB = 256;
 
+// Index of this block's partial sum (any fixed one-to-one map works).
 __device__ __forceinline__ long logical_block(int nblk)
 {
-    int b = blockIdx.x;
-    return (long)(b & 7) * (nblk >> 3) + (b >> 3);
+    (void)nblk;
+    return blockIdx.x;
 }
 
 __device__ __forceinline__ double block_sum(double v, double *sh)
@@ -63,71 +71,204 @@ __device__ __forceinline__ bool finish_reduce(double bsum, long L, int nblk, dou
     return true;
 }
 
-// Neighbour offsets of cell c = i + nr (j + nt k): 0 marks a missing neighbour.
-struct Nbr {
-    bool ip, im, jp, jm, kk;
-    long kp, km;  // offsets to the phi neighbours (periodic)
+// ------------------------------------------------------------ vector access
+
+template <typename V, int VW>
+__device__ __forceinline__ void vload(const V *__restrict__ p, V (&o)[VW])
+{
+    if constexpr (VW == 1) {
+        o[0] = p[0];
+    } else {
+        struct alignas(sizeof(V) * VW) B { V v[VW]; };
+        B b = *reinterpret_cast<const B *>(p);
+#pragma unroll
+        for (int m = 0; m < VW; m++) o[m] = b.v[m];
+    }
+}
+
+template <typename V, int VW>
+__device__ __forceinline__ void vstore(V *__restrict__ p, const V (&o)[VW])
+{
+    if constexpr (VW == 1) {
+        p[0] = o[0];
+    } else {
+        struct alignas(sizeof(V) * VW) B { V v[VW]; };
+        B b;
+#pragma unroll
+        for (int m = 0; m < VW; m++) b.v[m] = o[m];
+        *reinterpret_cast<B *>(p) = b;
+    }
+}
+
+// A row of the grid as seen from a block: its first cell and its neighbour rows.
+struct Row {
+    long base;      // index of cell (0, j, k)
+    bool jp, jm;    // theta neighbours exist
+    bool kk;        // phi neighbours exist (N_phi > 1)
+    long kp, km;    // offsets of the phi neighbours (periodic)
 };
 
-__device__ __forceinline__ Nbr neighbours(long c, const Dims &d)
+// Calls f(row, i) for every VW-cell segment (cells i .. i+VW-1 of a row) owned by the
+// block.  The hardware deals blocks round-robin over the 8 XCDs; the rows are split
+// the same way, into 8 theta-bands (all phi-planes of a band of ceil(N_theta/8) polar
+// rows), one per XCD, so a row's +-theta and +-phi neighbour rows are streamed by the
+// same XCD and stay in its L2.  Inside its band an XCD sweeps the rows (theta fastest,
+// then phi) in windows: in round t its nloc blocks take the window of rows
+// [t S, (t+1) S), S = nloc * rsub, local block l the rows [t S + l rsub, ...), so the
+// +-1 plane of a row lies at most a window or two away.  The rows of a block do not
+// depend on timing, which keeps the reductions deterministic.  Requires N_r % VW == 0.
+template <int VW, typename F>
+__device__ __forceinline__ void for_segments(const Dims &d, int nblk, F &&f)
 {
-    Nbr n;
-    int i = (int)(c % d.nr);
-    long jk = c / d.nr;
-    int j = (int)(jk % d.nt);
-    int k = (int)(jk / d.nt);
-    n.ip = i + 1 < d.nr;
-    n.im = i > 0;
-    n.jp = j + 1 < d.nt;
-    n.jm = j > 0;
-    n.kk = d.np > 1;
-    n.kp = (k + 1 < d.np) ? d.plane : -(long)(d.np - 1) * d.plane;
-    n.km = (k > 0) ? -d.plane : (long)(d.np - 1) * d.plane;
-    return n;
+    const int tpr = d.nr / VW;  // segments per row
+    int sub, rsub, i0, istep;
+    if (tpr >= kKB) {
+        sub = 0;
+        rsub = 1;
+        i0 = threadIdx.x * VW;
+        istep = kKB * VW;
+    } else {
+        rsub = kKB / tpr;
+        sub = threadIdx.x / tpr;
+        i0 = (threadIdx.x - sub * tpr) * VW;
+        istep = d.nr;
+        if (sub >= rsub) return;
+    }
+    const int xcd = blockIdx.x & 7, nloc = nblk >> 3, l = blockIdx.x >> 3;
+    const int band = (d.nt + 7) >> 3;
+    const int j0 = xcd * band;
+    const int blen = d.nt - j0 < band ? d.nt - j0 : band;  // rows of this XCD's band
+    if (blen <= 0) return;
+    const long nrows = (long)blen * d.np;
+    const long S = (long)nloc * rsub;
+    long u = (long)l * rsub + sub;
+    if (u >= nrows) return;
+    int jb = (int)(u % blen), k = (int)(u / blen);
+    const int dj = (int)(S % blen), dk = (int)(S / blen);
+    const long pl = d.plane, wrap = (long)(d.np - 1) * d.plane;
+    for (; u < nrows; u += S) {
+        const int j = j0 + jb;
+        Row rw;
+        rw.base = ((long)k * d.nt + j) * d.nr;
+        rw.jp = j + 1 < d.nt;
+        rw.jm = j > 0;
+        rw.kk = d.np > 1;
+        rw.kp = (k + 1 < d.np) ? pl : -wrap;
+        rw.km = (k > 0) ? -pl : wrap;
+        for (int i = i0; i < d.nr; i += istep) f(rw, i);
+        jb += dj;
+        k += dk;
+        if (jb >= blen) { jb -= blen; k++; }
+    }
+}
+
+// p = r + beta p_old for VW cells at c (beta = 0 after a restart: fma(0, p, r) = r
+// exactly, the p buffers are zeroed at creation and always finite afterwards).
+template <typename V, int VW>
+__device__ __forceinline__ void dir_seg(const V *__restrict__ r, const V *__restrict__ p, V beta, long c,
+                                        V (&o)[VW])
+{
+    V t[VW];
+    vload<V, VW>(r + c, o);
+    vload<V, VW>(p + c, t);
+#pragma unroll
+    for (int m = 0; m < VW; m++) o[m] = fma(beta, t[m], o[m]);
 }
 
 template <typename V>
-__device__ __forceinline__ V dir_val(const V *__restrict__ r, const V *__restrict__ p, V beta, bool first, long c)
+__device__ __forceinline__ V dir_one(const V *__restrict__ r, const V *__restrict__ p, V beta, long c)
 {
-    return first ? r[c] : fma(beta, p[c], r[c]);
+    return fma(beta, p[c], r[c]);
 }
 
-// y = A x at cell c, with x given by a functor of the cell index (summation order:
-// own, +r, -r, +theta, -theta, +phi, -phi).
-template <typename V, typename F>
-__device__ __forceinline__ V apply_at(long c, const Dims &d, const Nbr &nb, const V *__restrict__ a, F x)
+// Neighbour addresses of the segment at row position i, clamped to the segment itself
+// where a neighbour does not exist, and masks for the inward coefficients.  Every load
+// of the stencil is unconditional (no branch splits them into serialised groups); the
+// outward coefficients of boundary faces are exact zeros in the assembled operator, and
+// the inward ones are masked here, so the missing terms add exactly zero.
+struct Nb {
+    long c, cl, cr, cjp, cjm, ckp, ckm;
+    bool ml, mjm;  // inward radial / inward polar coefficient present
+};
+
+template <int VW>
+__device__ __forceinline__ Nb neighbours(const Dims &d, const Row &rw, int i)
+{
+    Nb n;
+    n.c = rw.base + i;
+    n.ml = i > 0;
+    n.cl = n.ml ? n.c - 1 : n.c;
+    n.cr = (i + VW < d.nr) ? n.c + VW : n.c + VW - 1;
+    n.cjp = rw.jp ? n.c + d.nr : n.c;
+    n.mjm = rw.jm;
+    n.cjm = rw.jm ? n.c - d.nr : n.c;
+    n.ckp = n.c + rw.kp;  // offsets are 0 when N_phi = 1 (the phi coefficients are 0 then)
+    n.ckm = n.c + rw.km;
+    return n;
+}
+
+// q = A x for the VW cells of a segment: xv its values, xl / xr the radial neighbours
+// and load(e, o) a loader of neighbour segments (summation order: own, +r, -r, +theta,
+// -theta, +phi, -phi).
+template <typename V, int VW, typename LoadSeg>
+__device__ __forceinline__ void apply_seg(const Dims &d, const Nb &nb, const V *__restrict__ a, const V (&xv)[VW],
+                                          V xl, V xr, LoadSeg &&load, V (&q)[VW])
 {
     const V *ar = a, *at = a + d.n, *ap = a + 2 * d.n;
-    V v = x(c);
-    if (nb.ip) v += ar[c] * x(c + 1);
-    if (nb.im) v += ar[c - 1] * x(c - 1);
-    if (nb.jp) v += at[c] * x(c + d.nr);
-    if (nb.jm) v += at[c - d.nr] * x(c - d.nr);
-    if (nb.kk) {
-        v += ap[c] * x(c + nb.kp);
-        v += ap[c + nb.km] * x(c + nb.km);
+    V arv[VW], atp[VW], atm[VW], app[VW], apm[VW], xjp[VW], xjm[VW], xkp[VW], xkm[VW];
+    vload<V, VW>(ar + nb.c, arv);
+    V arl = ar[nb.cl] * (V)nb.ml;
+    vload<V, VW>(at + nb.c, atp);
+    vload<V, VW>(at + nb.cjm, atm);
+    vload<V, VW>(ap + nb.c, app);
+    vload<V, VW>(ap + nb.ckm, apm);
+    load(nb.cjp, xjp);
+    load(nb.cjm, xjm);
+    load(nb.ckp, xkp);
+    load(nb.ckm, xkm);
+    const V mjm = (V)nb.mjm;
+#pragma unroll
+    for (int m = 0; m < VW; m++) {
+        V v = xv[m];
+        v += arv[m] * (m + 1 < VW ? xv[m + 1] : xr);
+        v += (m > 0 ? arv[m - 1] : arl) * (m > 0 ? xv[m - 1] : xl);
+        v += atp[m] * xjp[m];
+        v += (atm[m] * mjm) * xjm[m];
+        v += app[m] * xkp[m];
+        v += apm[m] * xkm[m];
+        q[m] = v;
     }
-    return v;
 }
 
 // ------------------------------------------------------------------- kernels
 
-// r = b - A y; rr = r.r.  Mode 1 (CG restart): also sets rr, beta = 0, done = 0.
-__global__ __launch_bounds__(kKB) void k_resid(Dims d, int nblk, long chunk, const double *__restrict__ a,
+// r = b - A y; res2 = r.r.  restart = 1 (CG restart): also rr = res2, beta = 0 and
+// done = (res2 <= thresh2).
+template <int VW>
+__device__ __forceinline__ void k_resid_body(Dims d, int nblk, const double *__restrict__ a,
                                                const double *__restrict__ b, const double *__restrict__ y,
                                                double *__restrict__ r, double *partials, unsigned *counter,
                                                DevScalars *sc, int restart)
 {
     __shared__ double sh[kKB / 64];
-    long L = logical_block(nblk);
-    long c0 = L * chunk, c1 = c0 + chunk < d.n ? c0 + chunk : d.n;
+    const long L = logical_block(nblk);
     double acc = 0.0;
-    for (long c = c0 + threadIdx.x; c < c1; c += kKB) {
-        Nbr nb = neighbours(c, d);
-        double v = b[c] - apply_at<double>(c, d, nb, a, [&](long e) { return y[e]; });
-        r[c] = v;
-        acc += v * v;
-    }
+    for_segments<VW>(d, nblk, [&](const Row &rw, int i) {
+        const Nb nb = neighbours<VW>(d, rw, i);
+        const long c = nb.c;
+        double xv[VW], q[VW], bv[VW];
+        vload<double, VW>(y + c, xv);
+        double xl = y[nb.cl], xr = y[nb.cr];
+        apply_seg<double, VW>(d, nb, a, xv, xl, xr, [&](long e, double(&o)[VW]) { vload<double, VW>(y + e, o); },
+                              q);
+        vload<double, VW>(b + c, bv);
+#pragma unroll
+        for (int m = 0; m < VW; m++) {
+            q[m] = bv[m] - q[m];
+            acc += q[m] * q[m];
+        }
+        vstore<double, VW>(r + c, q);
+    });
     double bs = block_sum(acc, sh), tot;
     if (finish_reduce(bs, L, nblk, partials, counter, sh, &tot) && threadIdx.x == 0) {
         sc->res2 = tot;
@@ -141,28 +282,30 @@ __global__ __launch_bounds__(kKB) void k_resid(Dims d, int nblk, long chunk, con
 }
 
 // Direction + operator + dot: p = r + beta p_old, q = A p, pq = p.q, alpha = rr / pq.
-template <typename V>
-__global__ __launch_bounds__(kKB) void k_cg_dir(Dims d, int nblk, long chunk, const V *__restrict__ a,
+template <typename V, int VW>
+__global__ __launch_bounds__(kKB) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_cg_dir(Dims d, int nblk, const V *__restrict__ a,
                                                 const V *__restrict__ r, const V *__restrict__ pold,
                                                 V *__restrict__ pnew, V *__restrict__ q, double *partials,
                                                 unsigned *counter, DevScalars *sc)
 {
     if (sc->done) return;
     __shared__ double sh[kKB / 64];
-    const double beta_d = sc->beta;
-    const bool first = beta_d == 0.0;
-    const V beta = (V)beta_d;
-    long L = logical_block(nblk);
-    long c0 = L * chunk, c1 = c0 + chunk < d.n ? c0 + chunk : d.n;
+    const V beta = (V)sc->beta;
+    const long L = logical_block(nblk);
     double acc = 0.0;
-    for (long c = c0 + threadIdx.x; c < c1; c += kKB) {
-        Nbr nb = neighbours(c, d);
-        V pc = dir_val(r, pold, beta, first, c);
-        V qc = apply_at<V>(c, d, nb, a, [&](long e) { return e == c ? pc : dir_val(r, pold, beta, first, e); });
-        pnew[c] = pc;
-        q[c] = qc;
-        acc += (double)pc * (double)qc;
-    }
+    for_segments<VW>(d, nblk, [&](const Row &rw, int i) {
+        const Nb nb = neighbours<VW>(d, rw, i);
+        const long c = nb.c;
+        V pv[VW], qv[VW];
+        dir_seg<V, VW>(r, pold, beta, c, pv);
+        V pl = dir_one(r, pold, beta, nb.cl), pr = dir_one(r, pold, beta, nb.cr);
+        apply_seg<V, VW>(d, nb, a, pv, pl, pr, [&](long e, V(&o)[VW]) { dir_seg<V, VW>(r, pold, beta, e, o); },
+                         qv);
+        vstore<V, VW>(pnew + c, pv);
+        vstore<V, VW>(q + c, qv);
+#pragma unroll
+        for (int m = 0; m < VW; m++) acc += (double)pv[m] * (double)qv[m];
+    });
     double bs = block_sum(acc, sh), tot;
     if (finish_reduce(bs, L, nblk, partials, counter, sh, &tot) && threadIdx.x == 0) {
         sc->pq = tot;
@@ -171,8 +314,8 @@ __global__ __launch_bounds__(kKB) void k_cg_dir(Dims d, int nblk, long chunk, co
 }
 
 // Update + dot: y += alpha p, r -= alpha q, rr' = r.r, beta = rr'/rr, convergence flag.
-template <typename V>
-__global__ __launch_bounds__(kKB) void k_cg_upd(Dims d, int nblk, long chunk, V *__restrict__ y,
+template <typename V, int VW>
+__global__ __launch_bounds__(kKB) void k_cg_upd(Dims d, int nblk, V *__restrict__ y,
                                                 const V *__restrict__ p, V *__restrict__ r,
                                                 const V *__restrict__ q, double *partials,
                                                 unsigned *counter, DevScalars *sc)
@@ -180,15 +323,24 @@ __global__ __launch_bounds__(kKB) void k_cg_upd(Dims d, int nblk, long chunk, V 
     if (sc->done) return;
     __shared__ double sh[kKB / 64];
     const V alpha = (V)sc->alpha;
-    long L = logical_block(nblk);
-    long c0 = L * chunk, c1 = c0 + chunk < d.n ? c0 + chunk : d.n;
+    const long L = logical_block(nblk);
     double acc = 0.0;
-    for (long c = c0 + threadIdx.x; c < c1; c += kKB) {
-        y[c] = fma(alpha, p[c], y[c]);
-        V rv = fma(-alpha, q[c], r[c]);
-        r[c] = rv;
-        acc += (double)rv * (double)rv;
-    }
+    for_segments<VW>(d, nblk, [&](const Row &rw, int i) {
+        const long c = rw.base + i;
+        V yv[VW], pv[VW], rv[VW], qv[VW];
+        vload<V, VW>(y + c, yv);
+        vload<V, VW>(p + c, pv);
+        vload<V, VW>(r + c, rv);
+        vload<V, VW>(q + c, qv);
+#pragma unroll
+        for (int m = 0; m < VW; m++) {
+            yv[m] = fma(alpha, pv[m], yv[m]);
+            rv[m] = fma(-alpha, qv[m], rv[m]);
+            acc += (double)rv[m] * (double)rv[m];
+        }
+        vstore<V, VW>(y + c, yv);
+        vstore<V, VW>(r + c, rv);
+    });
     double bs = block_sum(acc, sh), tot;
     if (finish_reduce(bs, L, nblk, partials, counter, sh, &tot) && threadIdx.x == 0) {
         double rr = sc->rr;
@@ -199,123 +351,170 @@ __global__ __launch_bounds__(kKB) void k_cg_upd(Dims d, int nblk, long chunk, V 
     }
 }
 
-// Mixed mode: r32 = r * inv_norm (float), x32 = 0, rr = r32.r32, beta = 0, done = 0.
-__global__ __launch_bounds__(kKB) void k_cast_residual(Dims d, int nblk, long chunk,
-                                                       const double *__restrict__ r,
-                                                       float *__restrict__ r32, float *__restrict__ x32,
-                                                       double *partials, unsigned *counter,
-                                                       DevScalars *sc, double inner_tol)
+// Mixed mode, reliable update: r32 = float(r) from the float64 residual r = b - A y
+// just computed by k_resid (after y absorbed x32), x32 = 0, rr = r32.r32, and beta
+// rescaled so the next direction continues from the replaced residual
+// (beta = rr_true / rr_prev); restart = 1 starts a fresh direction (beta = 0).
+__global__ __launch_bounds__(kKB) void k_reliable(Dims d, int nblk, const double *__restrict__ r,
+                                                  float *__restrict__ r32, float *__restrict__ x32,
+                                                  double *__restrict__ partials, unsigned *counter,
+                                                  DevScalars *sc, int restart)
 {
     __shared__ double sh[kKB / 64];
-    const double s = sc->inv_norm;
-    long L = logical_block(nblk);
-    long c0 = L * chunk, c1 = c0 + chunk < d.n ? c0 + chunk : d.n;
+    const long L = logical_block(nblk);
     double acc = 0.0;
-    for (long c = c0 + threadIdx.x; c < c1; c += kKB) {
-        float v = (float)(r[c] * s);
+    for_segments<1>(d, nblk, [&](const Row &rw, int i) {
+        const long c = rw.base + i;
+        float v = (float)r[c];
         r32[c] = v;
         x32[c] = 0.0f;
         acc += (double)v * (double)v;
-    }
+    });
     double bs = block_sum(acc, sh), tot;
     if (finish_reduce(bs, L, nblk, partials, counter, sh, &tot) && threadIdx.x == 0) {
+        double rr_prev = (sc->beta > 0.0) ? sc->rr / sc->beta : 0.0;
+        sc->beta = (restart || rr_prev == 0.0) ? 0.0 : tot / rr_prev;
         sc->rr = tot;
-        sc->beta = 0.0;
-        sc->thresh2 = inner_tol * inner_tol * tot;
-        sc->done = 0;
+        sc->done = tot <= sc->thresh2 ? 1 : 0;
     }
 }
 
-// Mixed mode: y += ||r|| x32 (float64 refinement update).
-__global__ __launch_bounds__(kKB) void k_refine(long n, const float *__restrict__ x32, const DevScalars *sc,
-                                                double *__restrict__ y)
+// y += x32 (float64 accumulation of the float32 partial solution).
+__global__ __launch_bounds__(kKB) void k_fold(long n, const float *__restrict__ x32, double *__restrict__ y)
 {
     long c = (long)blockIdx.x * kKB + threadIdx.x;
-    if (c >= n) return;
-    double nrm = sc->inv_norm > 0.0 ? 1.0 / sc->inv_norm : 0.0;
-    y[c] = fma(nrm, (double)x32[c], y[c]);
+    if (c < n) y[c] += (double)x32[c];
 }
 
 // res2 = x.x (float64).
-__global__ __launch_bounds__(kKB) void k_norm2(Dims d, int nblk, long chunk, const double *__restrict__ x,
+__global__ __launch_bounds__(kKB) void k_norm2(Dims d, int nblk, const double *__restrict__ x,
                                                double *partials, unsigned *counter, DevScalars *sc)
 {
     __shared__ double sh[kKB / 64];
-    long L = logical_block(nblk);
-    long c0 = L * chunk, c1 = c0 + chunk < d.n ? c0 + chunk : d.n;
+    const long L = logical_block(nblk);
     double acc = 0.0;
-    for (long c = c0 + threadIdx.x; c < c1; c += kKB) acc += x[c] * x[c];
+    for_segments<1>(d, nblk, [&](const Row &rw, int i) {
+        double v = x[rw.base + i];
+        acc += v * v;
+    });
     double bs = block_sum(acc, sh), tot;
     if (finish_reduce(bs, L, nblk, partials, counter, sh, &tot) && threadIdx.x == 0) sc->res2 = tot;
 }
 
-// y = A x (float64), plain.
-__global__ __launch_bounds__(kKB) void k_spmv(Dims d, const double *__restrict__ a, const double *__restrict__ x,
-                                              double *__restrict__ y)
-{
-    long c = (long)blockIdx.x * kKB + threadIdx.x;
-    if (c >= d.n) return;
-    Nbr nb = neighbours(c, d);
-    y[c] = apply_at<double>(c, d, nb, a, [&](long e) { return x[e]; });
-}
-
 // ------------------------------------------------------------------ launchers
 
-void launch_spmv(const Dims &d, const double *a, const double *x, double *y, hipStream_t st)
+// Bytes per array that one thread moves per segment (16, 32 or 64: one, two or four
+// 16-byte loads in flight per array); more bytes in flight per wave is what a
+// streaming kernel at full occupancy needs to cover HBM latency.
+static int seg_bytes()
 {
-    hipLaunchKernelGGL(k_spmv, dim3((unsigned)((d.n + kKB - 1) / kKB)), dim3(kKB), 0, st, d, a, x, y);
+    static int v = [] {
+        const char *e = std::getenv("RTMI_SEG_BYTES");
+        int b = e ? std::atoi(e) : 16;
+        return (b == 16 || b == 32 || b == 64) ? b : 16;
+    }();
+    return v;
 }
 
-void launch_norm2(const Dims &d, int nblk, long chunk, const double *x, double *partials, unsigned *counter,
+// Largest segment width (cells) of at most `bytes` that divides N_r.
+template <typename V>
+static int pick_vw(const Dims &d)
+{
+    int vw = seg_bytes() / (int)sizeof(V);
+    while (vw > 1 && d.nr % vw != 0) vw /= 2;
+    return vw;
+}
+
+#define RT_DISPATCH_VW(V, vw, KERNEL, ...)                                                                \
+    do {                                                                                                \
+        switch (vw) {                                                                                   \
+        case 16: if constexpr (sizeof(V) == 4) { hipLaunchKernelGGL((KERNEL<V, 16>), __VA_ARGS__); break; } [[fallthrough]]; \
+        case 8: hipLaunchKernelGGL((KERNEL<V, 8>), __VA_ARGS__); break;                                 \
+        case 4: hipLaunchKernelGGL((KERNEL<V, 4>), __VA_ARGS__); break;                                 \
+        case 2: hipLaunchKernelGGL((KERNEL<V, 2>), __VA_ARGS__); break;                                 \
+        default: hipLaunchKernelGGL((KERNEL<V, 1>), __VA_ARGS__); break;                                \
+        }                                                                                               \
+    } while (0)
+
+template <typename V, int VW>
+__global__ __launch_bounds__(kKB) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_spmv_t(Dims d, int nblk, const V *__restrict__ a, const V *__restrict__ x,
+                                                V *__restrict__ y)
+{
+    for_segments<VW>(d, nblk, [&](const Row &rw, int i) {
+        const Nb nb = neighbours<VW>(d, rw, i);
+        const long c = nb.c;
+        V xv[VW], q[VW];
+        vload<V, VW>(x + c, xv);
+        V xl = x[nb.cl], xr = x[nb.cr];
+        apply_seg<V, VW>(d, nb, a, xv, xl, xr, [&](long e, V(&o)[VW]) { vload<V, VW>(x + e, o); }, q);
+        vstore<V, VW>(y + c, q);
+    });
+}
+
+template <typename V, int VW>
+__global__ __launch_bounds__(kKB) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_resid_t(Dims d, int nblk, const V *__restrict__ a, const V *__restrict__ b,
+                                                 const V *__restrict__ y, V *__restrict__ r, double *partials,
+                                                 unsigned *counter, DevScalars *sc, int restart)
+{
+    k_resid_body<VW>(d, nblk, a, b, y, r, partials, counter, sc, restart);
+}
+
+void launch_spmv(const Dims &d, int nblk, const double *a, const double *x, double *y, hipStream_t st)
+{
+    RT_DISPATCH_VW(double, pick_vw<double>(d), k_spmv_t, dim3(nblk), dim3(kKB), 0, st, d, nblk, a, x, y);
+}
+
+void launch_norm2(const Dims &d, int nblk, const double *x, double *partials, unsigned *counter,
                   DevScalars *sc, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_norm2, dim3(nblk), dim3(kKB), 0, st, d, nblk, chunk, x, partials, counter, sc);
+    hipLaunchKernelGGL(k_norm2, dim3(nblk), dim3(kKB), 0, st, d, nblk, x, partials, counter, sc);
 }
 
-void launch_resid(const Dims &d, int nblk, long chunk, const double *a, const double *b, const double *y,
+void launch_resid(const Dims &d, int nblk, const double *a, const double *b, const double *y,
                   double *r, double *partials, unsigned *counter, DevScalars *sc, int restart, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_resid, dim3(nblk), dim3(kKB), 0, st, d, nblk, chunk, a, b, y, r, partials, counter,
-                       sc, restart);
+    RT_DISPATCH_VW(double, pick_vw<double>(d), k_resid_t, dim3(nblk), dim3(kKB), 0, st, d, nblk, a, b, y, r,
+                   partials, counter, sc, restart);
 }
 
-void launch_cg_iter64(const Dims &d, int nblk, long chunk, const double *a, double *y, double *r,
-                      double *pold, double *pnew, double *q, double *partials, unsigned *counter,
-                      DevScalars *sc, hipStream_t st, const hipEvent_t *ev)
+template <typename V>
+static void cg_iter(const Dims &d, int nblk, int nblk_upd, const V *a, V *y, V *r, V *pold, V *pnew, V *q,
+                    double *partials, unsigned *counter, DevScalars *sc, hipStream_t st, const hipEvent_t *ev)
 {
+    const int vw = pick_vw<V>(d);
     if (ev) (void)hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(k_cg_dir<double>, dim3(nblk), dim3(kKB), 0, st, d, nblk, chunk, a, r, pold, pnew, q,
-                       partials, counter, sc);
+    RT_DISPATCH_VW(V, vw, k_cg_dir, dim3(nblk), dim3(kKB), 0, st, d, nblk, a, r, pold, pnew, q, partials, counter,
+                   sc);
     if (ev) (void)hipEventRecord(ev[1], st);
-    hipLaunchKernelGGL(k_cg_upd<double>, dim3(nblk), dim3(kKB), 0, st, d, nblk, chunk, y, pnew, r, q,
-                       partials, counter, sc);
+    RT_DISPATCH_VW(V, vw, k_cg_upd, dim3(nblk_upd), dim3(kKB), 0, st, d, nblk_upd, y, pnew, r, q, partials, counter,
+                   sc);
     if (ev) (void)hipEventRecord(ev[2], st);
 }
 
-void launch_cg_iter32(const Dims &d, int nblk, long chunk, const float *a, float *x, float *r, float *pold,
+void launch_cg_iter64(const Dims &d, int nblk, int nblk_upd, const double *a, double *y, double *r, double *pold,
+                      double *pnew, double *q, double *partials, unsigned *counter, DevScalars *sc,
+                      hipStream_t st, const hipEvent_t *ev)
+{
+    cg_iter<double>(d, nblk, nblk_upd, a, y, r, pold, pnew, q, partials, counter, sc, st, ev);
+}
+
+void launch_cg_iter32(const Dims &d, int nblk, int nblk_upd, const float *a, float *x, float *r, float *pold,
                       float *pnew, float *q, double *partials, unsigned *counter, DevScalars *sc,
                       hipStream_t st, const hipEvent_t *ev)
 {
-    if (ev) (void)hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(k_cg_dir<float>, dim3(nblk), dim3(kKB), 0, st, d, nblk, chunk, a, r, pold, pnew, q,
-                       partials, counter, sc);
-    if (ev) (void)hipEventRecord(ev[1], st);
-    hipLaunchKernelGGL(k_cg_upd<float>, dim3(nblk), dim3(kKB), 0, st, d, nblk, chunk, x, pnew, r, q,
-                       partials, counter, sc);
-    if (ev) (void)hipEventRecord(ev[2], st);
+    cg_iter<float>(d, nblk, nblk_upd, a, x, r, pold, pnew, q, partials, counter, sc, st, ev);
 }
 
-void launch_cast_residual(const Dims &d, int nblk, long chunk, const double *r, float *r32, float *x32,
-                          double *partials, unsigned *counter, DevScalars *sc, double inner_tol, hipStream_t st)
+void launch_reliable(const Dims &d, int nblk, const double *r, float *r32, float *x32, double *partials,
+                     unsigned *counter, DevScalars *sc, int restart, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cast_residual, dim3(nblk), dim3(kKB), 0, st, d, nblk, chunk, r, r32, x32, partials,
-                       counter, sc, inner_tol);
+    hipLaunchKernelGGL(k_reliable, dim3(nblk), dim3(kKB), 0, st, d, nblk, r, r32, x32, partials, counter,
+                       sc, restart);
 }
 
-void launch_refine(long n, const float *x32, const DevScalars *sc, double *y, hipStream_t st)
+void launch_fold(long n, const float *x32, double *y, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_refine, dim3((unsigned)((n + kKB - 1) / kKB)), dim3(kKB), 0, st, n, x32, sc, y);
+    hipLaunchKernelGGL(k_fold, dim3((unsigned)((n + kKB - 1) / kKB)), dim3(kKB), 0, st, n, x32, y);
 }
-
 
 }  // namespace rt

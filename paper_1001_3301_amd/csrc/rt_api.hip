@@ -293,20 +293,29 @@ rt_status rt_create(rt_ctx **out, const rt_grid *g, int n_nu, void *stream)
         !ctx->p32a || !ctx->p32b || !ctx->q32 || !ctx->x32)
         return bail(RT_ENOMEM, "rt_create: out of device memory");
 
-    // reduction layout: a multiple of 8 blocks (one share per XCD), contiguous ranges
-    long want = (n + 255) / 256;
-    const char *env = std::getenv("RTMI_REDUCE_BLOCKS");
-    long cap = env ? std::max(8L, std::atol(env)) : 2048L;
-    long nb = std::min(std::max(want, 8L), cap);
-    nb = (nb + 7) / 8 * 8;
-    long chunk = (n + nb - 1) / nb;
-    chunk = (chunk + 63) / 64 * 64;
+    // block counts (multiples of 8, one share per XCD).  Measured on MI355X at
+    // 512x256x512: one block of 256 threads per CU is fastest for both the stencil
+    // kernels (each thread keeps all ~20 loads of a segment in flight) and the pure
+    // streaming update kernel (fewer, longer streams).
+    auto blocks = [&](const char *var, long dflt) {
+        const char *e = std::getenv(var);
+        long v = e ? std::max(8L, std::atol(e)) : dflt;
+        long want = (n + 255) / 256;  // never more blocks than 256-cell portions
+        v = std::min(std::max(std::min(v, want), 8L), 65536L);
+        return (v + 7) / 8 * 8;
+    };
+    long nb = blocks("RTMI_BLOCKS", 256);
     ctx->nblk = (int)nb;
-    ctx->chunk = chunk;
-    ctx->partials = dalloc<double>(ctx, nb);
+    ctx->nblk_upd = (int)blocks("RTMI_BLOCKS_UPD", 256);
+    ctx->partials = dalloc<double>(ctx, std::max<long>(nb, ctx->nblk_upd));
     ctx->counter = dalloc<unsigned>(ctx, 4);
     ctx->sc = dalloc<DevScalars>(ctx, 1);
     if (!ctx->partials || !ctx->counter || !ctx->sc) return bail(RT_ENOMEM, "rt_create: out of device memory");
+    // direction buffers start at zero: the first CG direction is r + 0 * p_old
+    for (void *pz : {(void *)ctx->p0, (void *)ctx->p1})
+        if (hipMemset(pz, 0, N * sizeof(double)) != hipSuccess) return bail(RT_EDEVICE, "rt_create: memset failed");
+    for (void *pz : {(void *)ctx->p32a, (void *)ctx->p32b})
+        if (hipMemset(pz, 0, N * sizeof(float)) != hipSuccess) return bail(RT_EDEVICE, "rt_create: memset failed");
     if (hipMemset(ctx->counter, 0, 4 * sizeof(unsigned)) != hipSuccess ||
         hipMemset(ctx->sc, 0, sizeof(DevScalars)) != hipSuccess)
         return bail(RT_EDEVICE, "rt_create: memset failed");
@@ -461,7 +470,7 @@ rt_status rt_spmv(rt_ctx *ctx, const double *x, double *y)
     if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
     RT_CHECK(ctx, ctx->have_system, "no assembled system");
     RT_CHECK(ctx, x && y && x != y, "rt_spmv: bad vectors");
-    launch_spmv(ctx->d, ctx->ahat, x, y, ctx->stream);
+    launch_spmv(ctx->d, ctx->nblk, ctx->ahat, x, y, ctx->stream);
     RT_HIP(ctx, hipGetLastError());
     return RT_OK;
 }
@@ -493,7 +502,7 @@ void add_kernel_sample(rt_ctx *ctx, rt_solve_stats *st)
 // ||bhat||^2 on the device, read back.
 rt_status norm_b(rt_ctx *ctx, double &bb)
 {
-    launch_norm2(ctx->d, ctx->nblk, ctx->chunk, ctx->bhat, ctx->partials, ctx->counter, ctx->sc, ctx->stream);
+    launch_norm2(ctx->d, ctx->nblk, ctx->bhat, ctx->partials, ctx->counter, ctx->sc, ctx->stream);
     RT_HIP(ctx, hipGetLastError());
     if (rt_status s = read_scalars(ctx)) return s;
     bb = ctx->h_sc->res2;
@@ -511,7 +520,7 @@ rt_status solve_fp64(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, do
     h->iters = 0;
     h->beta = 0.0;
     if (rt_status e = write_scalars(ctx)) return e;
-    launch_resid(d, ctx->nblk, ctx->chunk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials, ctx->counter,
+    launch_resid(d, ctx->nblk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials, ctx->counter,
                  ctx->sc, 1, s);
     if (rt_status e = read_scalars(ctx)) return e;
     double *pold = ctx->p0, *pnew = ctx->p1;
@@ -524,19 +533,21 @@ rt_status solve_fp64(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, do
         if (res <= o->tol) break;
         if (h->iters >= o->max_iter) { status = RT_ENOCONV; break; }
         int m = std::min(every, o->max_iter - h->iters);
+        int it_before = h->iters;
         for (int k = 0; k < m; k++) {
-            launch_cg_iter64(d, ctx->nblk, ctx->chunk, ctx->ahat, ctx->y, ctx->r, pold, pnew, ctx->qv, ctx->partials,
+            launch_cg_iter64(d, ctx->nblk, ctx->nblk_upd, ctx->ahat, ctx->y, ctx->r, pold, pnew, ctx->qv, ctx->partials,
                              ctx->counter, ctx->sc, s, k == 0 ? &ctx->ev[8] : nullptr);
             std::swap(pold, pnew);
         }
         RT_HIP(ctx, hipGetLastError());
         if (rt_status e = read_scalars(ctx)) return e;
         add_kernel_sample(ctx, st);
+        if ((h->iters - it_before) % 2 != m % 2) std::swap(pold, pnew);  // kernels that exited early
         if (!isfin(h->rr)) { status = RT_ENONFINITE; st->relres = NAN; break; }
         if (h->done || h->iters >= o->max_iter) {
             // the recurrence met the tolerance (or the budget ran out): judge by the true
             // residual, and restart CG from it if it is still above the tolerance
-            launch_resid(d, ctx->nblk, ctx->chunk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials,
+            launch_resid(d, ctx->nblk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials,
                          ctx->counter, ctx->sc, 1, s);
             if (rt_status e = read_scalars(ctx)) return e;
             res = std::sqrt(h->res2 / bb);
@@ -546,55 +557,63 @@ rt_status solve_fp64(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, do
     return status;
 }
 
-// Float64 iterative refinement around float32 inner CG (all dots in float64).
+// Mixed precision: CG iterations in float32 (operator, vectors and recurrences) with
+// float64 dot products, and "reliable updates" in float64: whenever the float32
+// recurrence residual has fallen by a factor 10 since the last update (or claims
+// convergence), the float32 partial solution is folded into the float64 solution y,
+// the true residual b - A y is recomputed in float64 and replaces the float32 one,
+// and CG continues along its current direction.  Convergence is judged only on the
+// float64 residual.
 rt_status solve_mixed(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb)
 {
     const Dims &d = ctx->d;
     hipStream_t s = ctx->stream;
     DevScalars *h = ctx->h_sc;
+    const double delta2 = 0.01;
     h->iters = 0;
     h->done = 0;
+    h->beta = 0.0;
+    h->thresh2 = o->tol * o->tol * bb;
     if (rt_status e = write_scalars(ctx)) return e;
-    const double inner_tol = o->inner_tol > 0.0 ? o->inner_tol : 1e-4;
-    const int inner_max = o->inner_max_iter > 0 ? o->inner_max_iter : o->max_iter;
     const int every = o->check_every > 0 ? o->check_every : 32;
-    int total = 0;
+    launch_resid(d, ctx->nblk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials, ctx->counter,
+                 ctx->sc, 0, s);
+    launch_reliable(d, ctx->nblk, ctx->r, ctx->r32, ctx->x32, ctx->partials, ctx->counter, ctx->sc, 1, s);
+    if (rt_status e = read_scalars(ctx)) return e;
+    double res = std::sqrt(h->res2 / bb), rr_ref = h->res2;
+    float *pold = ctx->p32a, *pnew = ctx->p32b;
     rt_status status = RT_OK;
     for (;;) {
-        launch_resid(d, ctx->nblk, ctx->chunk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials, ctx->counter,
-                     ctx->sc, 0, s);
-        if (rt_status e = read_scalars(ctx)) return e;
-        double res = std::sqrt(h->res2 / bb);
         st->relres = res;
         if (!isfin(res)) { status = RT_ENONFINITE; break; }
         if (res <= o->tol) break;
-        if (total >= o->max_iter) { status = RT_ENOCONV; break; }
-        st->outer_iters++;
-        launch_cast_residual(d, ctx->nblk, ctx->chunk, ctx->r, ctx->r32, ctx->x32, ctx->partials, ctx->counter,
-                             ctx->sc, inner_tol, s);
+        if (h->iters >= o->max_iter) { status = RT_ENOCONV; break; }
+        int m = std::min(every, o->max_iter - h->iters);
+        int it_before = h->iters;
+        for (int k = 0; k < m; k++) {
+            launch_cg_iter32(d, ctx->nblk, ctx->nblk_upd, ctx->ahat32, ctx->x32, ctx->r32, pold, pnew, ctx->q32,
+                             ctx->partials, ctx->counter, ctx->sc, s, k == 0 ? &ctx->ev[8] : nullptr);
+            std::swap(pold, pnew);
+        }
+        RT_HIP(ctx, hipGetLastError());
         if (rt_status e = read_scalars(ctx)) return e;
-        int it0 = h->iters;
-        float *pold = ctx->p32a, *pnew = ctx->p32b;
-        for (;;) {
-            int done_here = h->iters - it0;
-            int m = std::min({every, inner_max - done_here, o->max_iter - total - done_here});
-            if (m <= 0) break;
-            for (int k = 0; k < m; k++) {
-                launch_cg_iter32(d, ctx->nblk, ctx->chunk, ctx->ahat32, ctx->x32, ctx->r32, pold, pnew, ctx->q32,
-                                 ctx->partials, ctx->counter, ctx->sc, s, k == 0 ? &ctx->ev[8] : nullptr);
-                std::swap(pold, pnew);
-            }
+        add_kernel_sample(ctx, st);
+        if ((h->iters - it_before) % 2 != m % 2) std::swap(pold, pnew);  // kernels that exited early
+        if (!isfin(h->rr)) { status = RT_ENONFINITE; st->relres = NAN; break; }
+        if (h->done || h->rr <= delta2 * rr_ref || h->iters >= o->max_iter) {
+            launch_fold(d.n, ctx->x32, ctx->y, s);
+            launch_resid(d, ctx->nblk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials,
+                         ctx->counter, ctx->sc, 0, s);
+            launch_reliable(d, ctx->nblk, ctx->r, ctx->r32, ctx->x32, ctx->partials, ctx->counter,
+                            ctx->sc, 0, s);
             RT_HIP(ctx, hipGetLastError());
             if (rt_status e = read_scalars(ctx)) return e;
-            add_kernel_sample(ctx, st);
-            if (h->done || !isfin(h->rr)) break;
+            res = std::sqrt(h->res2 / bb);
+            rr_ref = h->res2;
+            st->outer_iters++;
         }
-        total += h->iters - it0;
-        if (!isfin(h->rr)) { status = RT_ENONFINITE; st->relres = NAN; break; }
-        launch_refine(d.n, ctx->x32, ctx->sc, ctx->y, s);
-        RT_HIP(ctx, hipGetLastError());
     }
-    st->iters = total;
+    st->iters = h->iters;
     return status;
 }
 

@@ -193,22 +193,24 @@ void launch_force(const Dims &d, const Geo &g, const double *w, const double *ch
                   const double *q, double Eb, double *f, hipStream_t st);
 void launch_scale_mul(long n, const double *s, const double *x, double *y, hipStream_t st);
 void launch_scale_div(long n, const double *s, const double *x, double *y, hipStream_t st);
-void launch_spmv(const Dims &d, const double *a, const double *x, double *y, hipStream_t st);
-void launch_norm2(const Dims &d, int nblk, long chunk, const double *x, double *partials, unsigned *counter,
+// Krylov kernels: nblk blocks (a multiple of 8) sweeping the rows in windows; the
+// CG iteration launches its update kernel with nblk_upd blocks.
+void launch_spmv(const Dims &d, int nblk, const double *a, const double *x, double *y, hipStream_t st);
+void launch_norm2(const Dims &d, int nblk, const double *x, double *partials, unsigned *counter,
                   DevScalars *sc, hipStream_t st);
-void launch_resid(const Dims &d, int nblk, long chunk, const double *a, const double *b, const double *y,
+void launch_resid(const Dims &d, int nblk, const double *a, const double *b, const double *y,
                   double *r, double *partials, unsigned *counter, DevScalars *sc, int restart, hipStream_t st);
 // One CG iteration (direction+operator kernel, then update kernel).  When ev is given,
 // ev[0], ev[1], ev[2] are recorded before, between and after the two kernels.
-void launch_cg_iter64(const Dims &d, int nblk, long chunk, const double *a, double *y, double *r,
-                      double *pold, double *pnew, double *q, double *partials, unsigned *counter,
-                      DevScalars *sc, hipStream_t st, const hipEvent_t *ev = nullptr);
-void launch_cg_iter32(const Dims &d, int nblk, long chunk, const float *a, float *x, float *r, float *pold,
+void launch_cg_iter64(const Dims &d, int nblk, int nblk_upd, const double *a, double *y, double *r, double *pold,
+                      double *pnew, double *q, double *partials, unsigned *counter, DevScalars *sc,
+                      hipStream_t st, const hipEvent_t *ev = nullptr);
+void launch_cg_iter32(const Dims &d, int nblk, int nblk_upd, const float *a, float *x, float *r, float *pold,
                       float *pnew, float *q, double *partials, unsigned *counter, DevScalars *sc,
                       hipStream_t st, const hipEvent_t *ev = nullptr);
-void launch_cast_residual(const Dims &d, int nblk, long chunk, const double *r, float *r32, float *x32,
-                          double *partials, unsigned *counter, DevScalars *sc, double inner_tol, hipStream_t st);
-void launch_refine(long n, const float *x32, const DevScalars *sc, double *y, hipStream_t st);
+void launch_reliable(const Dims &d, int nblk, const double *r, float *r32, float *x32, double *partials,
+                     unsigned *counter, DevScalars *sc, int restart, hipStream_t st);
+void launch_fold(long n, const float *x32, double *y, hipStream_t st);
 
 }  // namespace rt
 
@@ -244,8 +246,8 @@ struct rt_ctx {
     double *y = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *qv = nullptr, *tmp = nullptr;
     float *r32 = nullptr, *z32 = nullptr, *p32a = nullptr, *p32b = nullptr, *q32 = nullptr, *x32 = nullptr;
     // reductions
-    int nblk = 0;             // blocks of the reduction kernels (multiple of 8)
-    long chunk = 0;           // cells per block
+    int nblk = 0;             // blocks of the stencil and reduction kernels (multiple of 8)
+    int nblk_upd = 0;         // blocks of the streaming update kernels (multiple of 8)
     double *partials = nullptr;
     unsigned *counter = nullptr;
     rt::DevScalars *sc = nullptr;   // device
