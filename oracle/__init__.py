@@ -14,6 +14,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRC_NN = os.path.join(_HERE, "oracle_nn.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 
@@ -22,7 +23,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-std=c99", "-Wall", "-o", tmp, _SRC, "-lm"])
+                               "-std=c99", "-Wall", "-o", tmp, _SRC, _SRC_NN, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -54,7 +55,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                                                   os.path.getmtime(_SRC_NN)):
             build()
         L = C.CDLL(_LIB)
         P = C.POINTER
@@ -80,6 +82,23 @@ def lib():
         L.og_kappa_R.argtypes = [P(_Opac), C.c_double]
         L.og_kappa_R.restype = C.c_double
         L.og_const_a.restype = C.c_double
+        ip = C.c_int
+        L.ognn_conv_fwd.argtypes = [ip, ip, ip, dp, ip, dp, dp, ip, ip, dp]
+        L.ognn_conv_bwd_data.argtypes = [ip, ip, ip, dp, ip, dp, ip, dp]
+        L.ognn_conv_bwd_weight.argtypes = [ip, ip, ip, dp, ip, dp, ip, dp, dp]
+        L.ognn_pool.argtypes = [ip, ip, ip, dp, ip, dp]
+        L.ognn_up.argtypes = [ip, ip, ip, dp, ip, dp]
+        L.ognn_param_offset.argtypes = [ip]
+        L.ognn_param_offset.restype = C.c_long
+        L.ognn_param_count.restype = C.c_long
+        for f in ("ognn_cin", "ognn_cout", "ognn_taps"):
+            getattr(L, f).argtypes = [ip]
+        L.ognn_loss_grad.argtypes = [ip, ip, ip, dp, dp, dp, dp, dp]
+        L.ognn_loss_grad.restype = C.c_double
+        L.ognn_loss.argtypes = [C.c_long, dp, dp, dp]
+        L.ognn_loss.restype = C.c_double
+        L.ognn_adam.argtypes = [C.c_long, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double,
+                                C.c_double, ip]
         L.og_const_c.restype = C.c_double
         _lib = L
     return _lib
@@ -224,3 +243,77 @@ def const_a():
 
 def const_c():
     return lib().og_const_c()
+
+
+# ----------------------------------------------------------------- network oracle
+
+class NN:
+    """Float64 oracle of the U-Net (channels-last tensors, numpy float64)."""
+
+    @staticmethod
+    def conv_fwd(shape, x, cin, w, b, cout, relu):
+        nr, nt, npp = shape
+        x = _f64(x).ravel(); w = _f64(w).ravel()
+        b = None if b is None else _f64(b).ravel()
+        y = np.empty(nr * nt * npp * cout)
+        lib().ognn_conv_fwd(nr, nt, npp, _p(x), cin, _p(w), _p(b), cout, int(relu), _p(y))
+        return y
+
+    @staticmethod
+    def conv_bwd_data(shape, dy, cout, w, cin):
+        nr, nt, npp = shape
+        dy = _f64(dy).ravel(); w = _f64(w).ravel()
+        dx = np.empty(nr * nt * npp * cin)
+        lib().ognn_conv_bwd_data(nr, nt, npp, _p(dy), cout, _p(w), cin, _p(dx))
+        return dx
+
+    @staticmethod
+    def conv_bwd_weight(shape, x, cin, dy, cout):
+        nr, nt, npp = shape
+        x = _f64(x).ravel(); dy = _f64(dy).ravel()
+        dw = np.empty(27 * cout * cin); db = np.empty(cout)
+        lib().ognn_conv_bwd_weight(nr, nt, npp, _p(x), cin, _p(dy), cout, _p(dw), _p(db))
+        return dw, db
+
+    @staticmethod
+    def pool(shape, x, C):
+        nr, nt, npp = shape
+        x = _f64(x).ravel()
+        y = np.empty((nr // 2) * (nt // 2) * (npp // 2) * C)
+        lib().ognn_pool(nr, nt, npp, _p(x), C, _p(y))
+        return y
+
+    @staticmethod
+    def up(shape, xc, C):
+        nr, nt, npp = shape
+        xc = _f64(xc).ravel()
+        y = np.empty(nr * nt * npp * C)
+        lib().ognn_up(nr, nt, npp, _p(xc), C, _p(y))
+        return y
+
+    @staticmethod
+    def param_count():
+        return lib().ognn_param_count()
+
+    @staticmethod
+    def param_offset(layer):
+        return lib().ognn_param_offset(layer)
+
+    @staticmethod
+    def layer_shapes():
+        L = lib()
+        return [(L.ognn_taps(l), L.ognn_cout(l), L.ognn_cin(l)) for l in range(11)]
+
+    @staticmethod
+    def loss_grad(shape, params, X, e):
+        nr, nt, npp = shape
+        params = _f64(params).ravel(); X = _f64(X).ravel(); e = _f64(e).ravel()
+        grad = np.empty_like(params); z = np.empty(nr * nt * npp)
+        L = lib().ognn_loss_grad(nr, nt, npp, _p(params), _p(X), _p(e), _p(grad), _p(z))
+        return L, grad, z
+
+    @staticmethod
+    def adam(p, g, m, v, lr, b1, b2, eps, t):
+        p = _f64(p).copy(); m = _f64(m).copy(); v = _f64(v).copy(); g = _f64(g)
+        lib().ognn_adam(len(p), _p(p), _p(g), _p(m), _p(v), lr, b1, b2, eps, int(t))
+        return p, m, v

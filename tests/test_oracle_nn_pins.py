@@ -1,0 +1,144 @@
+"""Pins of the network oracle (oracle/oracle_nn.c): conv taps against shifted copies,
+adjoint (dot-product) identities for every backward routine, pooling/upsampling
+invariants, a finite-difference check of the whole U-Net loss gradient, and the Adam
+update against its closed form for a constant gradient."""
+import numpy as np
+import pytest
+
+from oracle import NN
+
+SHAPE = (6, 4, 4)
+N = 6 * 4 * 4
+
+
+def _rng(s):
+    return np.random.Generator(np.random.PCG64(s))
+
+
+def _shifted(x, C, di, dj, dk):
+    """x[i+di, j+dj, (k+dk) mod np] with zeros outside in r and theta (numpy roll + mask)."""
+    nr, nt, npp = SHAPE
+    a = x.reshape(npp, nt, nr, C)
+    out = np.zeros_like(a)
+    for k in range(npp):
+        for j in range(nt):
+            for i in range(nr):
+                ii, jj, kk = i + di, j + dj, (k + dk) % npp
+                if 0 <= ii < nr and 0 <= jj < nt:
+                    out[k, j, i] = a[kk, jj, ii]
+    return out.ravel()
+
+
+@pytest.mark.parametrize("tap", [0, 4, 13, 14, 16, 22, 26])
+def test_single_tap_kernel_is_a_shift(tap):
+    cin, cout = 3, 3
+    x = _rng(tap).standard_normal(N * cin)
+    w = np.zeros((27, cout, cin))
+    w[tap] = np.eye(3)
+    y = NN.conv_fwd(SHAPE, x, cin, w, None, cout, relu=False)
+    di, dj, dk = tap % 3 - 1, (tap // 3) % 3 - 1, tap // 9 - 1
+    assert np.array_equal(y, _shifted(x, cin, di, dj, dk))
+
+
+def test_bias_and_relu():
+    x = np.zeros(N * 2)
+    w = np.zeros((27, 2, 2))
+    y = NN.conv_fwd(SHAPE, x, 2, w, np.array([1.5, -2.0]), 2, relu=True).reshape(N, 2)
+    assert np.all(y[:, 0] == 1.5) and np.all(y[:, 1] == 0.0)
+
+
+def test_backward_data_is_the_adjoint():
+    r = _rng(1)
+    cin, cout = 5, 3
+    x = r.standard_normal(N * cin)
+    dy = r.standard_normal(N * cout)
+    w = r.standard_normal(27 * cout * cin)
+    lhs = np.dot(NN.conv_fwd(SHAPE, x, cin, w, None, cout, False), dy)
+    rhs = np.dot(x, NN.conv_bwd_data(SHAPE, dy, cout, w, cin))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_backward_weight_is_the_adjoint():
+    r = _rng(2)
+    cin, cout = 4, 2
+    x = r.standard_normal(N * cin)
+    dy = r.standard_normal(N * cout)
+    w = r.standard_normal(27 * cout * cin)
+    b = r.standard_normal(cout)
+    dw, db = NN.conv_bwd_weight(SHAPE, x, cin, dy, cout)
+    lhs = np.dot(NN.conv_fwd(SHAPE, x, cin, w, b, cout, False), dy)
+    rhs = np.dot(dw, w) + np.dot(db, b)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_pool_and_up_are_adjoint_up_to_eight():
+    r = _rng(3)
+    C = 3
+    xf = r.standard_normal(N * C)
+    xc = r.standard_normal(N // 8 * C)
+    # <pool(x), y> = <x, up(y)> / 8
+    assert abs(np.dot(NN.pool(SHAPE, xf, C), xc) - np.dot(xf, NN.up(SHAPE, xc, C)) / 8) < 1e-12
+    const = np.full(N * C, 2.5)
+    assert np.allclose(NN.pool(SHAPE, const, C), 2.5)
+    assert np.allclose(NN.up(SHAPE, np.full(N // 8 * C, -1.0), C), -1.0)
+
+
+def _random_params(seed, scale=0.3):
+    r = _rng(seed)
+    p = np.empty(NN.param_count())
+    for l, (taps, cout, cin) in enumerate(NN.layer_shapes()):
+        o = NN.param_offset(l)
+        nw = taps * cout * cin
+        p[o:o + nw] = r.standard_normal(nw) * scale * np.sqrt(2.0 / (taps * cin))
+        p[o + nw:o + nw + cout] = r.standard_normal(cout) * 0.1
+    return p
+
+
+def test_unet_gradient_matches_finite_differences():
+    shape = (8, 4, 4)
+    n = 8 * 4 * 4
+    r = _rng(4)
+    params = _random_params(5)
+    X = np.zeros((n, 16))
+    X[:, :4] = r.standard_normal((n, 4))
+    e = r.standard_normal(n)
+    L, grad, _ = NN.loss_grad(shape, params, X, e)
+    picks = []
+    for l, (taps, cout, cin) in enumerate(NN.layer_shapes()):
+        o = NN.param_offset(l)
+        nw = taps * cout * cin
+        picks += [o + int(r.integers(nw)), o + nw + int(r.integers(cout))]
+    for idx in picks:
+        h = 1e-6 * max(1.0, abs(params[idx]))
+        pp, pm = params.copy(), params.copy()
+        pp[idx] += h
+        pm[idx] -= h
+        fd = (NN.loss_grad(shape, pp, X, e)[0] - NN.loss_grad(shape, pm, X, e)[0]) / (2 * h)
+        # central differences carry a rounding error of ~eps * L / h ~ 1e-10 absolute;
+        # a wrong or missing backward term is off by O(1) relative
+        assert abs(fd - grad[idx]) <= 1e-5 * abs(grad[idx]) + 2e-9 * max(1.0, L), (idx, fd, grad[idx])
+
+
+def test_loss_is_relative_l2():
+    z = np.array([1.0, 2.0, 3.0])
+    e = np.array([1.0, 1.0, 1.0])
+    assert NN.loss_grad is not None
+    from oracle import lib, _p
+    gz = np.empty(3)
+    L = lib().ognn_loss(3, _p(z), _p(e), _p(gz))
+    assert abs(L - 5.0 / 3.0) < 1e-15
+    assert np.allclose(gz, 2 * (z - e) / 3.0)
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g, the bias-corrected moments are exactly g and g^2, so
+    every step moves the parameter by lr * g / (|g| + eps)."""
+    p0 = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    m = np.zeros(3); v = np.zeros(3)
+    p = p0.copy()
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    for t in range(1, 11):
+        p, m, v = NN.adam(p, g, m, v, lr, b1, b2, eps, t)
+    ref = p0 - 10 * lr * g / (np.abs(g) + eps)
+    assert np.max(np.abs(p - ref)) < 1e-12
