@@ -212,6 +212,87 @@ rt_status rt_step(rt_ctx *ctx, const rt_opacity *op, const rt_star *st,
 rt_status rt_step_fields(rt_ctx *ctx, const double **q_star, const double **S_abs,
                          const double **E_n);
 
+/* ------------------------------------------------ learned preconditioner (network) */
+
+/* The network is a 3-level 3-D convolutional U-Net (3x3x3 kernels, 16/32/64 channels,
+ * average pooling, nearest-neighbour upsampling with skip concatenation, ReLU, a final
+ * 1x1 convolution), evaluated and trained in bf16 on the matrix cores with fp32
+ * accumulation and fp32 master weights.  Its input has 16 channels per cell: the
+ * residual scaled to unit RMS, three operator features (log10 of minus the scaled
+ * off-diagonals of the outward faces, clipped to [-30, 0] and mapped to [-1, 1]) and
+ * zeros; its output approximates the scaled error A^-1 r.  Convolutions pad with zeros
+ * in r and theta and wrap in phi; grid dimensions must be divisible by 4.  Tensors are
+ * channels-last: x[c * C + ch].  Weights of layer l are w[(tap * Cout + co) * Cin + ci]
+ * with tap = (dk+1)*9 + (dj+1)*3 + (di+1); all parameters form one flat fp32 vector
+ * [w_0, b_0, w_1, b_1, ...]. */
+typedef struct {
+    unsigned seed; /* initialisation seed (counter-based hash, He-uniform weights) */
+} rt_net_config;
+
+/* Creates a network on the current device. */
+rt_status rt_net_create(const rt_net_config *cfg, rt_net **out);
+void rt_net_destroy(rt_net *net);
+const char *rt_net_last_error(const rt_net *net);
+long rt_net_param_count(const rt_net *net);
+/* Host copies of the fp32 master parameters / of the last gradient (n = param count). */
+rt_status rt_net_get_params(const rt_net *net, float *host, long n);
+rt_status rt_net_get_grads(const rt_net *net, float *host, long n);
+/* Replaces the parameters (resets the Adam state). */
+rt_status rt_net_set_params(rt_net *net, const float *host, long n);
+rt_status rt_net_save(const rt_net *net, const char *path);
+rt_status rt_net_load(rt_net *net, const char *path);
+
+/* z[n] (fp32, device) = network(X) for X[n][16] (bf16 bits, device) on the context's grid. */
+rt_status rt_net_forward(rt_ctx *ctx, rt_net *net, const void *X, float *z);
+/* Forward pass, loss L = ||z - e||^2 / ||e||^2 for the target e[n] (fp32, device) and
+ * backward pass; the gradient stays on the network for rt_net_adam.  z (device) and
+ * loss (host) may be NULL. */
+rt_status rt_net_loss_grad(rt_ctx *ctx, rt_net *net, const void *X, const float *e, float *z, double *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with learning rate lr. */
+rt_status rt_net_adam(rt_ctx *ctx, rt_net *net, double lr);
+
+/* Training pairs (residual -> error) made by the float64 method itself on the
+ * context's grid: rt_dataset_add runs float64 CG on the context's current system from
+ * E0 (device, E-space start value, normally E^n) to a relative residual of 1e-12 for
+ * the reference y*, then, for each iteration count k in iters, k CG iterations from
+ * E0 give y_k; the pair is (r_k = b - A y_k, e_k = y* - y_k), both scaled by
+ * sqrt(n) / ||r_k||, stored with the system's operator features.  Returns RT_EINVAL
+ * when the set is full. */
+typedef struct rt_dataset rt_dataset;
+rt_status rt_dataset_create(rt_ctx *ctx, int capacity, rt_dataset **out);
+void rt_dataset_destroy(rt_dataset *ds);
+int rt_dataset_size(const rt_dataset *ds);
+rt_status rt_dataset_add(rt_ctx *ctx, rt_dataset *ds, const double *E0, const int *iters, int n_iters);
+
+typedef struct {
+    int epochs;   /* passes over the set */
+    double lr;    /* peak learning rate (cosine decay to lr/10 over the run) */
+    unsigned seed; /* order of the pairs in each epoch */
+} rt_train_opts;
+typedef struct {
+    int steps;
+    double loss_first_epoch, loss_last_epoch; /* mean loss of the first / last epoch */
+    double ms;
+} rt_train_stats;
+/* Trains the network on the set (one pair per Adam step), on the context's stream. */
+rt_status rt_net_train(rt_ctx *ctx, rt_net *net, rt_dataset *ds, const rt_train_opts *o, rt_train_stats *st);
+
+/* Layer-level building blocks (bf16 tensors as raw 16-bit values, device pointers,
+ * enqueued on `stream`).  Forward: y = act(conv3x3x3([up?(x1), x2], w) + bias), x1 with
+ * c1 channels on the level of y (up1 = 0) or on the 2x coarser level read through
+ * nearest-neighbour upsampling (up1 = 1), x2 with c2 channels (may be 0); outputs bf16
+ * y and/or fp32 yf (either may be NULL); c1, c2, cout multiples of 16, cout <= 64. */
+rt_status rt_nn_conv3d_fwd(void *stream, int nr, int nt, int np, const void *x1, int c1, int up1, const void *x2,
+                           int c2, const void *w, const float *bias, int cout, int relu, void *y, float *yf);
+/* Data gradient: d[x1|x2] = conv^T(dy masked by yrelu > 0 when yrelu != NULL) with the
+ * transposed weights wt[(tap * Cin + ci) * Cout + co]; fp32 outputs on the level of dy
+ * (for an upsampled x1, the gradient of the upsampled tensor). */
+rt_status rt_nn_conv3d_bwd_data(void *stream, int nr, int nt, int np, const float *dy, const void *yrelu, int cout,
+                                const void *wt, int c1, float *d1, int c2, float *d2);
+/* Weight and bias gradients (fp32, dw[27][cout][c1+c2], db[cout]); synchronises. */
+rt_status rt_nn_conv3d_bwd_weight(void *stream, int nr, int nt, int np, const float *dy, const void *yrelu, int cout,
+                                  const void *x1, int c1, int up1, const void *x2, int c2, float *dw, float *db);
+
 #ifdef __cplusplus
 }
 #endif

@@ -379,6 +379,113 @@ __global__ __launch_bounds__(kKB) void k_reliable(Dims d, int nblk, const double
     }
 }
 
+// Like finish_reduce for two sums at once (partials hold pairs).
+__device__ __forceinline__ bool finish_reduce2(double a, double b, long L, int nblk, double *partials,
+                                               unsigned *counter, double *sh, double *ta, double *tb)
+{
+    __shared__ int s_last;
+    double ba = block_sum(a, sh), bb = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        partials[2 * L] = ba;
+        partials[2 * L + 1] = bb;
+        __threadfence();
+        unsigned prev = atomicAdd(counter, 1u);
+        s_last = (prev == (unsigned)(nblk - 1));
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __threadfence();
+    double x = 0.0, y = 0.0;
+    for (int t = threadIdx.x; t < nblk; t += kKB) {
+        x += partials[2 * t];
+        y += partials[2 * t + 1];
+    }
+    x = block_sum(x, sh);
+    y = block_sum(y, sh);
+    if (threadIdx.x == 0) {
+        *ta = x;
+        *tb = y;
+        *counter = 0u;
+    }
+    return true;
+}
+
+// Flexible CG (one A-orthogonalisation), float32 vectors, float64 dots:
+// p = z + beta p_old (recomputed at the neighbours), q = A p, pq = p.q, pr = p.r,
+// alpha = pr / pq.
+template <int VW>
+__global__ __launch_bounds__(kKB) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_fcg_dir(
+    Dims d, int nblk, const float *__restrict__ a, const float *__restrict__ z, const float *__restrict__ pold,
+    const float *__restrict__ r, float *__restrict__ pnew, float *__restrict__ q, double *partials, unsigned *counter,
+    DevScalars *sc)
+{
+    if (sc->done) return;
+    __shared__ double sh[kKB / 64];
+    const float beta = (float)sc->beta;
+    const long L = logical_block(nblk);
+    double acc = 0.0, acr = 0.0;
+    for_segments<VW>(d, nblk, [&](const Row &rw, int i) {
+        const Nb nb = neighbours<VW>(d, rw, i);
+        const long c = nb.c;
+        float pv[VW], qv[VW], rv[VW];
+        dir_seg<float, VW>(z, pold, beta, c, pv);
+        float pl = dir_one(z, pold, beta, nb.cl), pr = dir_one(z, pold, beta, nb.cr);
+        apply_seg<float, VW>(d, nb, a, pv, pl, pr, [&](long e, float(&o)[VW]) { dir_seg<float, VW>(z, pold, beta, e, o); },
+                             qv);
+        vstore<float, VW>(pnew + c, pv);
+        vstore<float, VW>(q + c, qv);
+        vload<float, VW>(r + c, rv);
+#pragma unroll
+        for (int m = 0; m < VW; m++) {
+            acc += (double)pv[m] * (double)qv[m];
+            acr += (double)pv[m] * (double)rv[m];
+        }
+    });
+    double pq, prr;
+    if (finish_reduce2(acc, acr, L, nblk, partials, counter, sh, &pq, &prr) && threadIdx.x == 0) {
+        sc->pq = pq;
+        sc->alpha = prr / pq;
+    }
+}
+
+// beta = -(z.q) / (p.q) for the next flexible-CG direction.
+__global__ __launch_bounds__(kKB) void k_fcg_beta(Dims d, int nblk, const float *__restrict__ z,
+                                                  const float *__restrict__ q, double *partials, unsigned *counter,
+                                                  DevScalars *sc)
+{
+    if (sc->done) return;
+    __shared__ double sh[kKB / 64];
+    const long L = logical_block(nblk);
+    double acc = 0.0;
+    for_segments<1>(d, nblk, [&](const Row &rw, int i) {
+        const long c = rw.base + i;
+        acc += (double)z[c] * (double)q[c];
+    });
+    double bs = block_sum(acc, sh), tot;
+    if (finish_reduce(bs, L, nblk, partials, counter, sh, &tot) && threadIdx.x == 0) sc->beta = -tot / sc->pq;
+}
+
+// scale = sqrt(n / rr) (the residual scaled to unit RMS enters the network), and its
+// inverse; both as float64 device scalars.
+__global__ void k_rms_scale(long n, const DevScalars *sc, double *scale)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double rr = sc->rr;
+        double s = rr > 0.0 ? sqrt((double)n / rr) : 1.0;
+        scale[0] = s;
+        scale[1] = 1.0 / s;
+    }
+}
+
+// z = zn * scale[1] (undo the input scaling; the network map is taken as positively
+// homogeneous of degree one).
+__global__ __launch_bounds__(kKB) void k_unscale(long n, const float *__restrict__ zn, const double *__restrict__ scale,
+                                                 float *__restrict__ z)
+{
+    long c = (long)blockIdx.x * kKB + threadIdx.x;
+    if (c < n) z[c] = (float)((double)zn[c] * scale[1]);
+}
+
 // y += x32 (float64 accumulation of the float32 partial solution).
 __global__ __launch_bounds__(kKB) void k_fold(long n, const float *__restrict__ x32, double *__restrict__ y)
 {
@@ -510,6 +617,40 @@ void launch_reliable(const Dims &d, int nblk, const double *r, float *r32, float
 {
     hipLaunchKernelGGL(k_reliable, dim3(nblk), dim3(kKB), 0, st, d, nblk, r, r32, x32, partials, counter,
                        sc, restart);
+}
+
+void launch_fcg_dir(const Dims &d, int nblk, const float *a, const float *z, const float *pold, const float *r,
+                    float *pnew, float *q, double *partials, unsigned *counter, DevScalars *sc, hipStream_t st)
+{
+    if (d.nr % 4 == 0)
+        hipLaunchKernelGGL(k_fcg_dir<4>, dim3(nblk), dim3(kKB), 0, st, d, nblk, a, z, pold, r, pnew, q, partials,
+                           counter, sc);
+    else
+        hipLaunchKernelGGL(k_fcg_dir<1>, dim3(nblk), dim3(kKB), 0, st, d, nblk, a, z, pold, r, pnew, q, partials,
+                           counter, sc);
+}
+
+void launch_fcg_beta(const Dims &d, int nblk, const float *z, const float *q, double *partials, unsigned *counter,
+                     DevScalars *sc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fcg_beta, dim3(nblk), dim3(kKB), 0, st, d, nblk, z, q, partials, counter, sc);
+}
+
+void launch_cg_upd32(const Dims &d, int nblk, float *x, const float *p, float *r, const float *q, double *partials,
+                     unsigned *counter, DevScalars *sc, hipStream_t st)
+{
+    const int vw = pick_vw<float>(d);
+    RT_DISPATCH_VW(float, vw, k_cg_upd, dim3(nblk), dim3(kKB), 0, st, d, nblk, x, p, r, q, partials, counter, sc);
+}
+
+void launch_rms_scale(long n, const DevScalars *sc, double *scale, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rms_scale, dim3(1), dim3(64), 0, st, n, sc, scale);
+}
+
+void launch_unscale(long n, const float *zn, const double *scale, float *z, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_unscale, dim3((unsigned)((n + kKB - 1) / kKB)), dim3(kKB), 0, st, n, zn, scale, z);
 }
 
 void launch_fold(long n, const float *x32, double *y, hipStream_t st)

@@ -288,9 +288,11 @@ rt_status rt_create(rt_ctx **out, const rt_grid *g, int n_nu, void *stream)
     ctx->p32b = dalloc<float>(ctx, N);
     ctx->q32 = dalloc<float>(ctx, N);
     ctx->x32 = dalloc<float>(ctx, N);
+    ctx->z32 = dalloc<float>(ctx, N);
+    ctx->nscale = dalloc<double>(ctx, 2);
     if (!ctx->q || !ctx->S || !ctx->En || !ctx->w || !ctx->ahat || !ctx->ahat32 || !ctx->s || !ctx->b ||
         !ctx->bhat || !ctx->chi || !ctx->y || !ctx->r || !ctx->p0 || !ctx->p1 || !ctx->qv || !ctx->r32 ||
-        !ctx->p32a || !ctx->p32b || !ctx->q32 || !ctx->x32)
+        !ctx->p32a || !ctx->p32b || !ctx->q32 || !ctx->x32 || !ctx->z32 || !ctx->nscale)
         return bail(RT_ENOMEM, "rt_create: out of device memory");
 
     // block counts (multiples of 8, one share per XCD).  Measured on MI355X at
@@ -617,6 +619,81 @@ rt_status solve_mixed(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, d
     return status;
 }
 
+// Learned mode: flexible CG (Notay's FCG with one A-orthogonalisation, since the
+// network is a nonlinear preconditioner) in float32 with float64 dots and the same
+// float64 reliable updates as the mixed mode; z = M(r) is the U-Net applied to the
+// residual scaled to unit RMS.  If the true residual is not below tol after
+// inner_max_iter network applications (default 400), or anything turns non-finite,
+// the solve falls back to float64 CG from the current iterate.
+rt_status solve_learned(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb)
+{
+    const Dims &d = ctx->d;
+    hipStream_t s = ctx->stream;
+    DevScalars *h = ctx->h_sc;
+    rt_net *net = o->net;
+    const double delta2 = 0.01;
+    const int budget = o->inner_max_iter > 0 ? o->inner_max_iter : 400;
+    if (rt_status e = net_prepare(net, ctx)) return fail(ctx, e, std::string("network: ") + rt_net_last_error(net));
+    h->iters = 0;
+    h->done = 0;
+    h->beta = 0.0;
+    h->thresh2 = o->tol * o->tol * bb;
+    if (rt_status e = write_scalars(ctx)) return e;
+    launch_resid(d, ctx->nblk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials, ctx->counter, ctx->sc, 0, s);
+    launch_reliable(d, ctx->nblk, ctx->r, ctx->r32, ctx->x32, ctx->partials, ctx->counter, ctx->sc, 1, s);
+    if (rt_status e = read_scalars(ctx)) return e;
+    double res = std::sqrt(h->res2 / bb), rr_ref = h->res2;
+    float *pold = ctx->p32a, *pnew = ctx->p32b;
+    rt_status status = RT_OK;
+    bool fallback = false, nonfinite = false;
+    for (;;) {
+        st->relres = res;
+        if (!isfin(res)) { fallback = nonfinite = true; break; }
+        if (res <= o->tol) break;
+        if (h->iters >= o->max_iter) { status = RT_ENOCONV; break; }
+        if (st->precond_applies >= budget) { fallback = true; break; }
+        // z = M(r); p = z + beta p_old, q = A p, alpha; x, r update; beta for the next step
+        if (rt_status e = net_precond(net, ctx, ctx->r32, ctx->z32))
+            return fail(ctx, e, std::string("network: ") + rt_net_last_error(net));
+        st->precond_applies++;
+        if (st->precond_applies > 1)
+            launch_fcg_beta(d, ctx->nblk, ctx->z32, ctx->q32, ctx->partials, ctx->counter, ctx->sc, s);
+        launch_fcg_dir(d, ctx->nblk, ctx->ahat32, ctx->z32, pold, ctx->r32, pnew, ctx->q32, ctx->partials,
+                       ctx->counter, ctx->sc, s);
+        launch_cg_upd32(d, ctx->nblk_upd, ctx->x32, pnew, ctx->r32, ctx->q32, ctx->partials, ctx->counter, ctx->sc, s);
+        std::swap(pold, pnew);
+        RT_HIP(ctx, hipGetLastError());
+        if (rt_status e = read_scalars(ctx)) return e;
+        if (!isfin(h->rr) || !isfin(h->alpha)) { fallback = nonfinite = true; break; }
+        if (h->done || h->rr <= delta2 * rr_ref || h->iters >= o->max_iter) {
+            launch_fold(d.n, ctx->x32, ctx->y, s);
+            launch_resid(d, ctx->nblk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials, ctx->counter,
+                         ctx->sc, 0, s);
+            launch_reliable(d, ctx->nblk, ctx->r, ctx->r32, ctx->x32, ctx->partials, ctx->counter, ctx->sc, 0, s);
+            RT_HIP(ctx, hipGetLastError());
+            if (rt_status e = read_scalars(ctx)) return e;
+            res = std::sqrt(h->res2 / bb);
+            rr_ref = h->res2;
+            st->outer_iters++;
+        }
+    }
+    st->iters = h->iters;
+    if (fallback) {
+        // keep what the float32 iterations gained (unless they went non-finite: then y is
+        // the iterate of the last reliable update), then finish with the float64 method
+        if (!nonfinite) launch_fold(d.n, ctx->x32, ctx->y, s);
+        st->fallback = 1;
+        rt_solve_stats s64{};
+        rt_solve_opts o64 = *o;
+        o64.mode = RT_SOLVE_FP64;
+        o64.max_iter = std::max(1, o->max_iter - st->iters);
+        status = solve_fp64(ctx, &o64, &s64, bb);
+        st->iters += s64.iters;
+        st->relres = s64.relres;
+    }
+    return status;
+}
+
 }  // namespace
 
 extern "C" {
@@ -646,7 +723,7 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
     rt_status status;
     if (o->mode == RT_SOLVE_FP64) status = solve_fp64(ctx, o, S, bb);
     else if (o->mode == RT_SOLVE_MIXED) status = solve_mixed(ctx, o, S, bb);
-    else return fail(ctx, RT_EINVAL, "learned mode is not available in this build");
+    else status = solve_learned(ctx, o, S, bb);
     if (status == RT_EDEVICE) return status;
     launch_scale_mul(ctx->d.n, ctx->s, ctx->y, E, ctx->stream);  // E = s y
     RT_HIP(ctx, hipGetLastError());
@@ -657,6 +734,33 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
     if (status == RT_ENONFINITE) return fail(ctx, status, "non-finite residual");
     return status;
 }
+
+}  // extern "C"
+
+namespace rt {
+rt_status solve_fp64_from(rt_ctx *ctx, double tol, int max_iter, double *y, rt_solve_stats *st)
+{
+    if (!ctx->have_system) return fail(ctx, RT_EINVAL, "no assembled system");
+    rt_solve_stats local{};
+    rt_solve_stats *S = st ? st : &local;
+    *S = rt_solve_stats{};
+    double bb = 0.0;
+    if (rt_status e = norm_b(ctx, bb)) return e;
+    if (!(bb > 0.0) || !isfin(bb)) return fail(ctx, RT_ENONFINITE, "right-hand side is zero or not finite");
+    RT_HIP(ctx, hipMemcpyAsync(ctx->y, y, ctx->d.n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    rt_solve_opts o{};
+    o.mode = RT_SOLVE_FP64;
+    o.tol = tol;
+    o.max_iter = max_iter;
+    o.check_every = std::min(32, max_iter);
+    rt_status status = solve_fp64(ctx, &o, S, bb);
+    RT_HIP(ctx, hipMemcpyAsync(y, ctx->y, ctx->d.n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    RT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return status == RT_ENOCONV ? RT_OK : status;
+}
+}  // namespace rt
+
+extern "C" {
 
 rt_status rt_temperature(rt_ctx *ctx, const rt_opacity *op, const double *E, const double *S_abs, double *T)
 {

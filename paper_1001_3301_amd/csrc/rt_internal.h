@@ -211,6 +211,51 @@ void launch_cg_iter32(const Dims &d, int nblk, int nblk_upd, const float *a, flo
 void launch_reliable(const Dims &d, int nblk, const double *r, float *r32, float *x32, double *partials,
                      unsigned *counter, DevScalars *sc, int restart, hipStream_t st);
 void launch_fold(long n, const float *x32, double *y, hipStream_t st);
+// Flexible CG for the learned mode (float32 vectors, float64 dots).
+void launch_fcg_dir(const Dims &d, int nblk, const float *a, const float *z, const float *pold, const float *r,
+                    float *pnew, float *q, double *partials, unsigned *counter, DevScalars *sc, hipStream_t st);
+void launch_fcg_beta(const Dims &d, int nblk, const float *z, const float *q, double *partials, unsigned *counter,
+                     DevScalars *sc, hipStream_t st);
+void launch_cg_upd32(const Dims &d, int nblk, float *x, const float *p, float *r, const float *q, double *partials,
+                     unsigned *counter, DevScalars *sc, hipStream_t st);
+void launch_rms_scale(long n, const DevScalars *sc, double *scale, hipStream_t st);
+void launch_unscale(long n, const float *zn, const double *scale, float *z, hipStream_t st);
+
+// U-Net kernels (k_unet.hip): bf16 tensors as raw 16-bit values.
+namespace nn {
+typedef unsigned short bf16;
+struct Lv {
+    int nr, nt, np;
+    long n;
+};
+bool launch_conv_fwd(const Lv &L, const bf16 *x1, int c1, int up1, const bf16 *x2, int c2, const bf16 *w,
+                     const float *b, int cout, int relu, bf16 *y, float *yf, hipStream_t s);
+bool launch_conv_bwd_data(const Lv &L, const float *dy, const bf16 *y, int cout, const bf16 *wt, int c1, float *d1,
+                          int c2, float *d2, hipStream_t s);
+void launch_conv_bwd_weight(const Lv &L, const float *dy, const bf16 *y, int cout, const bf16 *x1, int c1, int up1,
+                            const bf16 *x2, int c2, float *part, float *dw, float *db, hipStream_t s);
+void launch_pool(const Lv &Lc, int C, const bf16 *x, bf16 *y, hipStream_t s);
+void launch_pool_bwd_add(const Lv &Lf, int C, const float *dyc, float *dxf, hipStream_t s);
+void launch_up_bwd(const Lv &Lc, int C, const float *dyf, float *dxc, hipStream_t s);
+void launch_out_fwd(long n, const bf16 *x, const bf16 *w, const float *b, float *z, hipStream_t s);
+void launch_out_bwd(long n, const bf16 *x, const bf16 *w, const float *gz, float *dx, float *part, float *dwb,
+                    hipStream_t s);
+void launch_features(long n, const double *ahat, bf16 *X, hipStream_t s);
+void launch_set_input(long n, const float *r, const double *scale, bf16 *X, hipStream_t s);
+void launch_set_input(long n, const double *r, const double *scale, bf16 *X, hipStream_t s);
+void launch_loss(long n, const float *z, const float *e, double *part, double *res, float *gz, hipStream_t s);
+void launch_adam(long np_, float *p, const float *g, float *m, float *v, float lr, float b1, float b2, float eps,
+                 float c1, float c2, hipStream_t s);
+void launch_cast_weights(int taps, int cout, int cin, const float *p, bf16 *w, bf16 *wt, hipStream_t s);
+void launch_pair(long n, const DevScalars *sc, const double *ystar, const double *y, double *scale, float *e,
+                 hipStream_t s);
+}  // namespace nn
+
+// Network hooks used by the learned solve and the training set (rt_net.hip).
+rt_status net_prepare(rt_net *net, rt_ctx *ctx);                       // workspace + operator features
+rt_status net_precond(rt_net *net, rt_ctx *ctx, const float *r, float *z); // z = M(r); uses sc->rr
+// Float64 CG on the context's current system from y (in/out), tol and iteration cap.
+rt_status solve_fp64_from(rt_ctx *ctx, double tol, int max_iter, double *y, rt_solve_stats *st);
 
 }  // namespace rt
 
@@ -245,6 +290,7 @@ struct rt_ctx {
     // Krylov vectors
     double *y = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *qv = nullptr, *tmp = nullptr;
     float *r32 = nullptr, *z32 = nullptr, *p32a = nullptr, *p32b = nullptr, *q32 = nullptr, *x32 = nullptr;
+    double *nscale = nullptr;  // [2] network input scale and its inverse
     // reductions
     int nblk = 0;             // blocks of the stencil and reduction kernels (multiple of 8)
     int nblk_upd = 0;         // blocks of the streaming update kernels (multiple of 8)

@@ -83,7 +83,28 @@ class StepStats(C.Structure):
 # Every symbol include/rt.h declares (checked by the tests).
 EXPORTS = ["rt_create", "rt_destroy", "rt_last_error", "rt_ncell", "rt_star_bin_flux",
            "rt_set_opacity", "rt_set_star", "rt_raytrace", "rt_energy", "rt_fld_assemble",
-           "rt_spmv", "rt_fld_solve", "rt_temperature", "rt_force", "rt_step", "rt_step_fields"]
+           "rt_spmv", "rt_fld_solve", "rt_temperature", "rt_force", "rt_step", "rt_step_fields",
+           "rt_net_create", "rt_net_destroy", "rt_net_last_error", "rt_net_param_count",
+           "rt_net_get_params", "rt_net_get_grads", "rt_net_set_params", "rt_net_save", "rt_net_load",
+           "rt_net_forward", "rt_net_loss_grad", "rt_net_adam", "rt_dataset_create",
+           "rt_dataset_destroy", "rt_dataset_size", "rt_dataset_add", "rt_net_train",
+           "rt_nn_conv3d_fwd", "rt_nn_conv3d_bwd_data", "rt_nn_conv3d_bwd_weight"]
+
+
+class NetConfig(C.Structure):
+    _fields_ = [("seed", C.c_uint)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("lr", C.c_double), ("seed", C.c_uint)]
+
+
+class TrainStats(C.Structure):
+    _fields_ = [("steps", C.c_int), ("loss_first_epoch", C.c_double), ("loss_last_epoch", C.c_double),
+                ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 _lib = None
 
@@ -116,6 +137,32 @@ def lib():
     L.rt_step.argtypes = [vp, P(Opacity), P(Star), P(FldParams), P(SolveOpts), vp, vp, vp, vp,
                           P(StepStats)]
     L.rt_step_fields.argtypes = [vp, P(vp), P(vp), P(vp)]
+    fp = P(C.c_float)
+    L.rt_net_create.argtypes = [P(NetConfig), P(vp)]
+    L.rt_net_destroy.argtypes = [vp]
+    L.rt_net_destroy.restype = None
+    L.rt_net_last_error.argtypes = [vp]
+    L.rt_net_last_error.restype = C.c_char_p
+    L.rt_net_param_count.argtypes = [vp]
+    L.rt_net_param_count.restype = C.c_long
+    L.rt_net_get_params.argtypes = [vp, fp, C.c_long]
+    L.rt_net_get_grads.argtypes = [vp, fp, C.c_long]
+    L.rt_net_set_params.argtypes = [vp, fp, C.c_long]
+    L.rt_net_save.argtypes = [vp, C.c_char_p]
+    L.rt_net_load.argtypes = [vp, C.c_char_p]
+    L.rt_net_forward.argtypes = [vp, vp, vp, vp]
+    L.rt_net_loss_grad.argtypes = [vp, vp, vp, vp, vp, P(C.c_double)]
+    L.rt_net_adam.argtypes = [vp, vp, C.c_double]
+    L.rt_dataset_create.argtypes = [vp, C.c_int, P(vp)]
+    L.rt_dataset_destroy.argtypes = [vp]
+    L.rt_dataset_destroy.restype = None
+    L.rt_dataset_size.argtypes = [vp]
+    L.rt_dataset_add.argtypes = [vp, vp, vp, P(C.c_int), C.c_int]
+    L.rt_net_train.argtypes = [vp, vp, vp, P(TrainOpts), P(TrainStats)]
+    ip = C.c_int
+    L.rt_nn_conv3d_fwd.argtypes = [vp, ip, ip, ip, vp, ip, ip, vp, ip, vp, vp, ip, ip, vp, vp]
+    L.rt_nn_conv3d_bwd_data.argtypes = [vp, ip, ip, ip, vp, vp, ip, vp, ip, vp, ip, vp]
+    L.rt_nn_conv3d_bwd_weight.argtypes = [vp, ip, ip, ip, vp, vp, ip, vp, ip, ip, vp, ip, vp, vp]
     _lib = L
     return L
 
@@ -140,7 +187,8 @@ def star_bin_flux(T_star: float, nu) -> np.ndarray:
 
 def solve_opts(mode=MODE_FP64, tol=1e-8, max_iter=100000, check_every=32, inner_tol=1e-4,
                inner_max_iter=0, net=None) -> SolveOpts:
-    return SolveOpts(mode, tol, max_iter, check_every, inner_tol, inner_max_iter, net)
+    nh = None if net is None else (net.h if isinstance(net, Net) else net)
+    return SolveOpts(mode, tol, max_iter, check_every, inner_tol, inner_max_iter, nh)
 
 
 class Context:
@@ -291,6 +339,139 @@ class Context:
             _memcpy_d2d(t.data_ptr(), p.value, t.numel() * 8)
             out.append(t)
         return out
+
+
+class Net:
+    """The learned preconditioner's network (rt_net)."""
+
+    def __init__(self, seed=1):
+        h = C.c_void_p()
+        cfg = NetConfig(seed)
+        st = lib().rt_net_create(C.byref(cfg), C.byref(h))
+        if st != RT_OK:
+            raise RtError(st, lib().rt_net_last_error(None).decode())
+        self.h = h
+        self.n = lib().rt_net_param_count(h)
+
+    def _chk(self, st):
+        if st != RT_OK:
+            raise RtError(st, lib().rt_net_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rt_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        out = np.empty(self.n, dtype=np.float32)
+        self._chk(lib().rt_net_get_params(self.h, out.ctypes.data_as(C.POINTER(C.c_float)), self.n))
+        return out
+
+    def get_grads(self):
+        out = np.empty(self.n, dtype=np.float32)
+        self._chk(lib().rt_net_get_grads(self.h, out.ctypes.data_as(C.POINTER(C.c_float)), self.n))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        self._chk(lib().rt_net_set_params(self.h, p.ctypes.data_as(C.POINTER(C.c_float)), len(p)))
+
+    def save(self, path):
+        self._chk(lib().rt_net_save(self.h, str(path).encode()))
+
+    def load(self, path):
+        self._chk(lib().rt_net_load(self.h, str(path).encode()))
+
+    def forward(self, ctx, X, z):
+        self._chk(lib().rt_net_forward(ctx.h, self.h, ctx._dev(X, ctx.n * 16, "X", ctx._torch.bfloat16),
+                                       ctx._dev(z, ctx.n, "z", ctx._torch.float32)))
+
+    def loss_grad(self, ctx, X, e, z=None):
+        L = C.c_double()
+        self._chk(lib().rt_net_loss_grad(ctx.h, self.h, ctx._dev(X, ctx.n * 16, "X", ctx._torch.bfloat16),
+                                         ctx._dev(e, ctx.n, "e", ctx._torch.float32),
+                                         ctx._dev(z, ctx.n, "z", ctx._torch.float32, allow_none=True),
+                                         C.byref(L)))
+        return L.value
+
+    def adam(self, ctx, lr):
+        self._chk(lib().rt_net_adam(ctx.h, self.h, float(lr)))
+
+    def train(self, ctx, ds, epochs, lr, seed=0):
+        o = TrainOpts(epochs, lr, seed)
+        st = TrainStats()
+        self._chk(lib().rt_net_train(ctx.h, self.h, ds.h, C.byref(o), C.byref(st)))
+        return st.as_dict()
+
+
+class Dataset:
+    """(residual -> error) training pairs made by the float64 method on a context's grid."""
+
+    def __init__(self, ctx, capacity):
+        h = C.c_void_p()
+        st = lib().rt_dataset_create(ctx.h, int(capacity), C.byref(h))
+        if st != RT_OK:
+            raise RtError(st, lib().rt_net_last_error(None).decode())
+        self.h = h
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rt_dataset_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return lib().rt_dataset_size(self.h)
+
+    def add(self, E0, iters):
+        it = (C.c_int * len(iters))(*iters)
+        st = lib().rt_dataset_add(self.ctx.h, self.h, self.ctx._dev(E0, self.ctx.n, "E0"), it, len(iters))
+        if st != RT_OK:
+            raise RtError(st, lib().rt_net_last_error(None).decode())
+
+
+def _vp(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def nn_conv_fwd(shape, x1, c1, up1, x2, c2, w, b, cout, relu, y=None, yf=None):
+    """Layer-level forward convolution (device tensors; bf16 x1 / x2 / w, fp32 b / yf)."""
+    import torch
+    nr, nt, npp = shape
+    st = lib().rt_nn_conv3d_fwd(C.c_void_p(torch.cuda.current_stream().cuda_stream), nr, nt, npp, _vp(x1), c1,
+                                int(up1), _vp(x2), c2, _vp(w), _vp(b), cout, int(relu), _vp(y), _vp(yf))
+    if st != RT_OK:
+        raise RtError(st, lib().rt_net_last_error(None).decode())
+
+
+def nn_conv_bwd_data(shape, dy, yrelu, cout, wt, c1, d1, c2=0, d2=None):
+    import torch
+    nr, nt, npp = shape
+    st = lib().rt_nn_conv3d_bwd_data(C.c_void_p(torch.cuda.current_stream().cuda_stream), nr, nt, npp, _vp(dy),
+                                     _vp(yrelu), cout, _vp(wt), c1, _vp(d1), c2, _vp(d2))
+    if st != RT_OK:
+        raise RtError(st, lib().rt_net_last_error(None).decode())
+
+
+def nn_conv_bwd_weight(shape, dy, yrelu, cout, x1, c1, up1, x2, c2, dw, db):
+    import torch
+    nr, nt, npp = shape
+    st = lib().rt_nn_conv3d_bwd_weight(C.c_void_p(torch.cuda.current_stream().cuda_stream), nr, nt, npp, _vp(dy),
+                                       _vp(yrelu), cout, _vp(x1), c1, int(up1), _vp(x2), c2, _vp(dw), _vp(db))
+    if st != RT_OK:
+        raise RtError(st, lib().rt_net_last_error(None).decode())
 
 
 _hip = None

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_library_exports_every_declared_symbol():
     L = rt.lib()
     hdr = open(os.path.join(ROOT, "include", "rt.h")).read()
-    declared = set(re.findall(r"^\s*(?:rt_status|void|const char \*|long)\s*\**(rt_\w+)\s*\(", hdr, re.M))
+    declared = set(re.findall(r"^\s*(?:rt_status|void|const char \*|long|int)\s*\**(rt_\w+)\s*\(", hdr, re.M))
     assert declared, "no declarations parsed"
     assert declared == set(rt.EXPORTS), declared ^ set(rt.EXPORTS)
     for name in declared:
