@@ -2,9 +2,13 @@
 
 A step is one pass of the main loop (ray trace, E^n, FLD assembly, implicit solve to
 a relative residual of 1e-8, Newton temperature update, radiative force) on the
-512x256x512-cell, 64-bin workload (tau550 = 100 with lognormal clumps, seed 5000);
-successive steps evolve the temperature with dt = 1e9 s.  The headline mode is timed
-first, then the plain float64 solve from the same start for comparison.
+512x256x512-cell, 64-bin workload (tau550 = 100 with lognormal clumps, seed 5000,
+dt = 1e9 s).  Every timed step starts from the same prepared state (the temperature
+in equilibrium with the stellar irradiation and E = a T_bc^4), so the K timed steps do
+identical work.  The headline solve mode is timed first, then the plain float64 solve
+for comparison.  With --successive N the headline mode also runs N successive steps
+(temperature carried over), whose per-step iteration counts are reported: the system
+gets harder as the radiation field evolves.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -27,39 +31,63 @@ PEAK_HBM_GBS = 8000.0
 # dir: read r, p_old and the three off-diagonals, write p and q; upd: read y, p, r, q, write y, r.
 BYTES_PER_CELL = {"fp64": {"dir": 7 * 8, "upd": 6 * 8}, "mixed": {"dir": 7 * 4, "upd": 6 * 4}}
 KERNEL_NAMES = {"fp64": "k_cg_dir<double>", "mixed": "k_cg_dir<float>"}
+# HBM bytes per launch of these kernels on the 512x256x512 workload, from rocprofv3
+# FETCH_SIZE (x2.0, calibrated on a kernel of known size) + WRITE_SIZE; the summary with
+# the commands is profiles/solver_kernels_clumpy-512x256x512-nu64.md.  Set to None when
+# the kernel changes.
+MEASURED_TRAFFIC = {("mixed", "clumpy-512x256x512-nu64"): 1.924e9, ("fp64", "clumpy-512x256x512-nu64"): 3.855e9}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_mode(ctx, rt, torch, rho, T0, mode, steps, warmup, tol, inner_tol):
+def run_mode(ctx, rt, torch, rho, T0, mode, steps, warmup, tol, inner_tol, max_iter):
     n = ctx.n
     m = {"fp64": rt.MODE_FP64, "mixed": rt.MODE_MIXED}[mode]
-    opts = rt.solve_opts(m, tol=tol, max_iter=500000, check_every=32, inner_tol=inner_tol)
+    opts = rt.solve_opts(m, tol=tol, max_iter=max_iter, check_every=32, inner_tol=inner_tol)
     T = T0.clone()
     E = torch.empty(n, dtype=torch.float64, device="cuda")
     f = torch.empty(4 * n, dtype=torch.float64, device="cuda")
     for w in range(warmup):
+        T.copy_(T0)
         rc, st = ctx.step(rho, T, E, opts, f_rad=f)
         log(f"[{mode}] warmup step {w}: solve {st['solve']['ms']:.1f} ms, {st['solve']['iters']} it, "
             f"relres {st['solve']['relres']:.2e}")
-    T.copy_(T0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     stats = []
+    wall = 0.0
     for k in range(steps):
+        T.copy_(T0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         rc, st = ctx.step(rho, T, E, opts, f_rad=f)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
         stats.append(st)
         log(f"[{mode}] step {k}: total {st['ms_total']:.1f} ms, raytrace {st['ms_raytrace']:.2f} ms, "
             f"solve {st['solve']['ms']:.1f} ms ({st['solve']['iters']} it, {st['solve']['outer_iters']} outer, "
             f"relres {st['solve']['relres']:.2e}), dir {st['solve']['ms_dir']*1e3:.1f} us")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    return dict(wall_s=t1 - t0, stats=stats, T=T, E=E)
+    return dict(wall_s=wall, stats=stats, T=T, E=E)
 
 
-def oracle_baseline(wl, gpu_fp64_iters, slab=8, cg_iters=200):
+def run_successive(ctx, rt, torch, rho, T0, mode, nsteps, tol, inner_tol, max_iter):
+    """nsteps steps carrying the temperature over; per-step solve statistics."""
+    m = {"fp64": rt.MODE_FP64, "mixed": rt.MODE_MIXED}[mode]
+    opts = rt.solve_opts(m, tol=tol, max_iter=max_iter, check_every=32, inner_tol=inner_tol)
+    T = T0.clone()
+    E = torch.empty(ctx.n, dtype=torch.float64, device="cuda")
+    out = []
+    for k in range(nsteps):
+        rc, st = ctx.step(rho, T, E, opts, raise_on_error=False)
+        s = st["solve"]
+        out.append({"iters": s["iters"], "solve_s": s["ms"] / 1e3, "relres": s["relres"],
+                    "fallback": s["fallback"], "status": rc})
+        log(f"[{mode}] successive step {k}: solve {s['ms']:.1f} ms, {s['iters']} it, relres {s['relres']:.2e}, "
+            f"status {rc}")
+    return out
+
+
+def oracle_baseline(wl, gpu_fp64_iters, slab=16, cg_iters=1000):
     """The oracle on a phi-slab of the workload: ray trace and a fixed number of CG
     iterations, scaled to the full grid and to the GPU float64 iteration count."""
     import numpy as np
@@ -102,6 +130,9 @@ def main():
     ap.add_argument("--modes", default="mixed,fp64", help="comma list; the first is the headline")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--inner-tol", type=float, default=1e-4)
+    ap.add_argument("--max-iter", type=int, default=200000)
+    ap.add_argument("--successive", type=int, default=0,
+                    help="also run this many successive steps of the headline mode (not timed for value)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy a buffer of this size once before timing (HBM-counter calibration)")
@@ -146,7 +177,7 @@ def main():
     results = {}
     for mode in modes:
         results[mode] = run_mode(ctx, rt, torch, rho, T0, mode, args.steps, args.warmup, args.tol,
-                                 args.inner_tol)
+                                 args.inner_tol, args.max_iter)
 
     head = modes[0]
     R = results[head]
@@ -173,13 +204,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {wl.grid.shape[0]}x{wl.grid.shape[1]}x{wl.grid.shape[2]} cells, "
                                f"{c['n_nu']} bins, tau550={wl.tau550:g}, clumps seed {c['seeds'][-1]}",
-                   "solve_mode": head, "tol": args.tol, "dt": wl.dt, "successive_steps": args.steps},
+                   "solve_mode": head, "tol": args.tol, "dt": wl.dt,
+                   "step": "first step from the prepared state, repeated K times"},
         "raytrace_gcell_nu_per_s": statistics.median([n * c["n_nu"] / (x / 1e3) / 1e9 for x in rt_ms]),
         "solve_iters_per_step": statistics.median([s["solve"]["iters"] for s in R["stats"]]),
         "kernel_ms": {"dir": ms_dir, "upd": ms_upd, "samples": samples},
         "roofline": {"kernel": KERNEL_NAMES[head], "bound": "hbm", "achieved": achieved,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": None, "bytes_per_cell": bpc["dir"], "cells_per_launch": n},
+                     "traffic": MEASURED_TRAFFIC.get((head, args.config)), "bytes_per_cell": bpc["dir"],
+                     "cells_per_launch": n},
     }
     for mode in modes[1:]:
         Rm = results[mode]
@@ -188,6 +221,9 @@ def main():
     if len(modes) > 1:
         Ta, Tb = results[modes[0]]["T"], results[modes[-1]]["T"]
         out["T_rel_diff_vs_" + modes[-1]] = float(((Ta - Tb).abs() / Tb).max())
+    if args.successive > 0:
+        out["successive_steps"] = run_successive(ctx, rt, torch, rho, T0, head, args.successive, args.tol,
+                                                 args.inner_tol, args.max_iter)
     if not args.no_cpu_baseline:
         fp64_iters = out.get("fp64_iters_per_step", out["solve_iters_per_step"])
         t = time.perf_counter()

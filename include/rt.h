@@ -90,7 +90,10 @@ typedef struct {
 
 typedef enum {
     RT_SOLVE_FP64 = 0,    /* CG on A^ in float64 (the plain method; also the fallback) */
-    RT_SOLVE_MIXED = 1,   /* float64 iterative refinement around float32 inner CG */
+    RT_SOLVE_MIXED = 1,   /* float64 iterative refinement around float32 inner CG; when a
+                             float32 cycle needs over 2048 iterations for a tenfold drop,
+                             or two cycles fail to halve the true residual (cond(A^) too
+                             large for float32), float64 CG finishes (fallback = 1) */
     RT_SOLVE_LEARNED = 2  /* refinement around flexible CG preconditioned by a network */
 } rt_solve_mode;
 
@@ -111,7 +114,7 @@ typedef struct {
     int iters;           /* Krylov iterations (inner iterations in mixed / learned modes) */
     int outer_iters;     /* float64 refinement steps (mixed / learned) */
     int precond_applies; /* network applications (learned) */
-    int fallback;        /* 1 if the learned solve fell back to the float64 method */
+    int fallback;        /* 1 if a learned or mixed solve finished with the float64 method */
     double relres;       /* final true relative residual, computed in float64 */
     double ms;           /* wall time of the solve (host clock, includes polls) */
     double ms_dir;       /* mean device time of one direction+operator kernel (sampled once per poll) */

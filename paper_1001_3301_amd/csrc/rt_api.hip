@@ -572,6 +572,13 @@ rt_status solve_mixed(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, d
     hipStream_t s = ctx->stream;
     DevScalars *h = ctx->h_sc;
     const double delta2 = 0.01;
+    // Precision guard.  CG needs about 1.15 sqrt(cond) iterations per tenfold residual
+    // reduction, so a float32 cycle that has not reached its tenfold drop after kCycle
+    // iterations means cond(A^) eps32 is no longer small (cond above ~3e6): float32
+    // iterations then lose conjugacy and need several times the float64 count.  Such a
+    // cycle is folded in and float64 CG finishes from that iterate; so does a solve
+    // whose cycles twice in a row fail to halve the true residual.
+    const int kCycle = 2048;
     h->iters = 0;
     h->done = 0;
     h->beta = 0.0;
@@ -585,11 +592,14 @@ rt_status solve_mixed(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, d
     double res = std::sqrt(h->res2 / bb), rr_ref = h->res2;
     float *pold = ctx->p32a, *pnew = ctx->p32b;
     rt_status status = RT_OK;
+    int cycle_start = 0, bad = 0;
+    bool fallback = false;
     for (;;) {
         st->relres = res;
         if (!isfin(res)) { status = RT_ENONFINITE; break; }
         if (res <= o->tol) break;
         if (h->iters >= o->max_iter) { status = RT_ENOCONV; break; }
+        if (bad >= 2) { fallback = true; break; }
         int m = std::min(every, o->max_iter - h->iters);
         int it_before = h->iters;
         for (int k = 0; k < m; k++) {
@@ -602,7 +612,8 @@ rt_status solve_mixed(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, d
         add_kernel_sample(ctx, st);
         if ((h->iters - it_before) % 2 != m % 2) std::swap(pold, pnew);  // kernels that exited early
         if (!isfin(h->rr)) { status = RT_ENONFINITE; st->relres = NAN; break; }
-        if (h->done || h->rr <= delta2 * rr_ref || h->iters >= o->max_iter) {
+        const bool capped = h->iters - cycle_start >= kCycle;
+        if (h->done || h->rr <= delta2 * rr_ref || h->iters >= o->max_iter || capped) {
             launch_fold(d.n, ctx->x32, ctx->y, s);
             launch_resid(d, ctx->nblk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials,
                          ctx->counter, ctx->sc, 0, s);
@@ -610,12 +621,26 @@ rt_status solve_mixed(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, d
                             ctx->sc, 0, s);
             RT_HIP(ctx, hipGetLastError());
             if (rt_status e = read_scalars(ctx)) return e;
-            res = std::sqrt(h->res2 / bb);
+            const double res_new = std::sqrt(h->res2 / bb);
+            bad = (res_new > 0.5 * res) ? bad + 1 : 0;
+            if (capped && res_new > o->tol) bad = 2;
+            res = res_new;
             rr_ref = h->res2;
+            cycle_start = h->iters;
             st->outer_iters++;
         }
     }
     st->iters = h->iters;
+    if (fallback) {
+        st->fallback = 1;
+        rt_solve_stats s64{};
+        rt_solve_opts o64 = *o;
+        o64.mode = RT_SOLVE_FP64;
+        o64.max_iter = std::max(1, o->max_iter - st->iters);
+        status = solve_fp64(ctx, &o64, &s64, bb);
+        st->iters += s64.iters;
+        st->relres = s64.relres;
+    }
     return status;
 }
 

@@ -188,7 +188,9 @@ def star_bin_flux(T_star: float, nu) -> np.ndarray:
 def solve_opts(mode=MODE_FP64, tol=1e-8, max_iter=100000, check_every=32, inner_tol=1e-4,
                inner_max_iter=0, net=None) -> SolveOpts:
     nh = None if net is None else (net.h if isinstance(net, Net) else net)
-    return SolveOpts(mode, tol, max_iter, check_every, inner_tol, inner_max_iter, nh)
+    o = SolveOpts(mode, tol, max_iter, check_every, inner_tol, inner_max_iter, nh)
+    o._net = net  # keeps the network alive as long as the options refer to it
+    return o
 
 
 class Context:
