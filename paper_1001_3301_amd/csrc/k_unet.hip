@@ -16,6 +16,8 @@
 // receives D[m = 4(l/16) .. +3][n = l%16].  A decoder convolution reads two sources
 // (the nearest-neighbour upsampled coarse tensor and the skip tensor) directly, so the
 // upsampled/concatenated tensor is never materialised.
+#include <type_traits>
+
 #include "rt_internal.h"
 
 namespace rt {
@@ -83,114 +85,266 @@ __device__ __forceinline__ bool tap_nb(const Lv &L, int i, int j, int k, int t, 
     return (unsigned)a < (unsigned)L.nr && (unsigned)b < (unsigned)L.nt;
 }
 
-// ------------------------------------------------------------- forward conv
+// Compile-time loop: f(std::integral_constant<int, i>{}) for i = B .. E-1.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// ------------------------------------------------------ tiled convolution
+
+// Forward and data-gradient convolutions share one LDS-tiled implicit GEMM.  A block
+// owns kTR x TJ x TK output cells (r x theta x phi).  For each 16-channel input slice
+// it stages the input tile with a one-cell halo (zeros outside r and theta, wrapped in
+// phi) and the slice's weights of all 27 taps in LDS, then runs
+// v_mfma_f32_16x16x32_bf16 with K = two taps x 16 channels:
+//   A[m = output channel][k] = weights, lane l holding 8 channels of tap 2p + l/32 for
+//     output channel l%16 (stored in LDS in exactly this fragment order; a 28th tap of
+//     zeros pads the last pair);
+//   B[k][n = cell] = activations, lane l holding 8 channels of the neighbour, through
+//     the same tap, of cell l%16 of a 16-cell row segment;
+//   D[m = 4(l/16) + i][n = l%16]: each lane ends with 4 consecutive output channels of
+//     one cell, stored as one vector.
+// Each wavefront owns Tile::per_wave row segments (adjacent in r and theta), so one A
+// fragment feeds that many MFMAs and one B fragment feeds NT output-channel tiles.
+// The LDS tile is stored half-major, xs[h][cell][8] with h the upper or lower 8
+// channels, so 8 lanes reading one half of 8 consecutive cells read 128 contiguous
+// bytes (conflict-free), and every fragment address is a per-lane base plus a
+// compile-time offset for the segment and the tap.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
+
+constexpr int kTR = 32;
+
+template <int TJ, int TK>
+struct Tile {
+    static constexpr int HR = kTR + 2, HJ = TJ + 2, HK = TK + 2;
+    static constexpr int cells = HR * HJ * HK;
+    static constexpr int segs = 2 * TJ * TK;  // 16-cell row segments
+    static constexpr int per_wave = segs / 4;
+    static_assert(per_wave % 2 == 0 && (2 * TJ) % per_wave == 0, "a wavefront's segments share one phi plane");
+};
+
+// LDS bytes of one block: input tile of one slice plus the slice's weights (28 taps).
+template <int NT, int TJ, int TK>
+constexpr size_t conv_lds_bytes() { return (size_t)Tile<TJ, TK>::cells * 32 + 28 * NT * 512; }
+
+// Two floats to two bf16 (round to nearest even, NaN stays NaN) packed in 32 bits.
+__device__ __forceinline__ unsigned pack_bf16(float a, float b)
+{
+    const bf16x2 h = __builtin_convertvector(float2v{a, b}, bf16x2);
+    return *reinterpret_cast<const unsigned *>(&h);
+}
+
+// Body shared by the forward (sign = +1) and data-gradient (sign = -1: the output cell
+// whose tap reads this cell) convolutions.  load(idx, a, b, c, ch) returns 8 bf16
+// channels ch .. ch + 7 of input cell idx = (a, b, c); store(idx, ch, v) writes output
+// channels ch .. ch + 3.  w is [tap][cout][cin] in bf16.
+//
+// Blocks are persistent: gridDim.x is a multiple of 8 and block b serves the tiles of
+// one eighth of the tile sequence (XCD b % 8 under round-robin dispatch, so the
+// concurrently resident blocks of an XCD work on neighbouring tiles and share halos
+// in that XCD's L2), stepping by gridDim.x / 8; a block whose input is a single slice
+// loads its weights once.
+template <int NT, int TJ, int TK, int SIGN, class Load, class Store>
+__device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__restrict__ w, Load load, Store store)
+{
+    using T = Tile<TJ, TK>;
+    constexpr int PW = T::per_wave;
+    extern __shared__ uint4 smem_u4[];
+    char *lds = reinterpret_cast<char *>(smem_u4);
+    char *ws = lds + T::cells * 32;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int cout = NT * 16;
+    const int nslice = cin / 16;
+    const int ntr = (L.nr + kTR - 1) / kTR, ntj = (L.nt + TJ - 1) / TJ;
+    const long ntiles = (long)ntr * ntj * ((L.np + TK - 1) / TK);
+    const int per = gridDim.x >> 3, xcd = blockIdx.x & 7;
+    const long t_end = ntiles * (xcd + 1) / 8;
+    long tile = ntiles * xcd / 8 + (blockIdx.x >> 3);
+    if (tile >= t_end) return;  // uniform over the block
+    constexpr int NL = (T::cells * 2 + kTB - 1) / kTB;   // 16-byte tile loads per thread
+    constexpr int NW = (27 * NT * 32 + kTB - 1) / kTB;   // 16-byte weight loads per thread
+    // the zero weights of the padding tap 27
+    if (tid < NT * 32) *reinterpret_cast<uint4 *>(ws + (27 * NT * 32 + tid) * 16) = make_uint4(0u, 0u, 0u, 0u);
+    // per-lane fragment bases: segment q of this wavefront is (rh = q & 1, jj = jw + q / 2, kw)
+    const int g0 = wv * PW, jw = (g0 >> 1) % TJ, kw = (g0 >> 1) / TJ;
+    const int half = (lane >> 4) & 1;
+    const int xbase = half * T::cells * 16 + (((kw + 1) * T::HJ + (jw + 1)) * T::HR + 1 + (lane & 15)) * 16;
+    const int wbase = ((lane >> 5) * NT * 32 + (lane & 31)) * 16;
+    float4v acc[PW][NT];
+#pragma unroll
+    for (int q = 0; q < PW; q++)
+#pragma unroll
+        for (int t = 0; t < NT; t++) acc[q][t] = float4v{0.f, 0.f, 0.f, 0.f};
+    int s = 0;
+    bool first = true;
+    for (;;) {
+        // global loads of the item (tile, slice s), all issued before the LDS stores;
+        // cells outside the grid read cell 0 and are replaced by zeros
+        const int tr = (int)(tile % ntr), tj = (int)((tile / ntr) % ntj), tk = (int)(tile / ((long)ntr * ntj));
+        const int r0 = tr * kTR, j0 = tj * TJ, k0 = tk * TK;
+        uint4 v[NL];
+#pragma unroll
+        for (int u = 0; u < NL; u++) {
+            const int q = tid + u * kTB;
+            const int cell = q >> 1, h = q & 1;
+            const int hr = cell % T::HR, hj = (cell / T::HR) % T::HJ, hk = cell / (T::HR * T::HJ);
+            int a = r0 + hr - 1, b = j0 + hj - 1, c = k0 + hk - 1;
+            c = (c == -1) ? L.np - 1 : (c == L.np ? 0 : c);
+            const bool ok = q < T::cells * 2 && (unsigned)a < (unsigned)L.nr && (unsigned)b < (unsigned)L.nt &&
+                            (unsigned)c < (unsigned)L.np;
+            if (!ok) a = b = c = 0;
+            const uint4 x = load(a + (long)L.nr * (b + (long)L.nt * c), a, b, c, s * 16 + h * 8);
+            v[u] = ok ? x : make_uint4(0u, 0u, 0u, 0u);
+        }
+        __syncthreads();  // the previous item's MFMAs are done with the LDS tiles
+#pragma unroll
+        for (int u = 0; u < NL; u++) {
+            const int q = tid + u * kTB;
+            if (q < T::cells * 2) *reinterpret_cast<uint4 *>(lds + ((q & 1) * T::cells + (q >> 1)) * 16) = v[u];
+        }
+        if (first || nslice > 1) {
+            uint4 wr[NW];
+#pragma unroll
+            for (int u = 0; u < NW; u++) {
+                const int q = min(tid + u * kTB, 27 * NT * 32 - 1);
+                const int l32 = q & 31, tt = (q >> 5) % NT, tap = q / (32 * NT);
+                const int co = tt * 16 + (l32 & 15), ci = s * 16 + (l32 >> 4) * 8;
+                wr[u] = *reinterpret_cast<const uint4 *>(w + ((long)tap * cout + co) * cin + ci);
+            }
+#pragma unroll
+            for (int u = 0; u < NW; u++) {
+                const int q = tid + u * kTB;
+                if (q < 27 * NT * 32) *reinterpret_cast<uint4 *>(ws + q * 16) = wr[u];
+            }
+        }
+        first = false;
+        __syncthreads();
+        // Tap pairs p = 0 .. 13, software-pipelined: the LDS fragments of pair p + 1 are
+        // requested before the MFMAs of pair p are issued.
+        auto frags = [&](auto pc, bf16x8 (&bf)[PW], bf16x8 (&af)[NT]) {
+            constexpr int p = decltype(pc)::value;
+            constexpr int ta = 2 * p, tb = (2 * p + 1 < 27) ? 2 * p + 1 : 13;
+            constexpr int oa = SIGN * (((ta / 9 - 1) * T::HJ + ((ta / 3) % 3 - 1)) * T::HR + (ta % 3 - 1)) * 16;
+            constexpr int ob = SIGN * (((tb / 9 - 1) * T::HJ + ((tb / 3) % 3 - 1)) * T::HR + (tb % 3 - 1)) * 16;
+            const char *xp = lds + xbase + ((lane < 32) ? oa : ob);
+#pragma unroll
+            for (int q = 0; q < PW; q++)
+                bf[q] = *reinterpret_cast<const bf16x8 *>(xp + ((q >> 1) * T::HR + (q & 1) * 16) * 16);
+            const char *wp = ws + wbase + 2 * p * NT * 32 * 16;
+#pragma unroll
+            for (int t = 0; t < NT; t++) af[t] = *reinterpret_cast<const bf16x8 *>(wp + t * 32 * 16);
+        };
+        auto mma = [&](const bf16x8 (&bf)[PW], const bf16x8 (&af)[NT]) {
+#pragma unroll
+            for (int q = 0; q < PW; q++)
+#pragma unroll
+                for (int t = 0; t < NT; t++)
+                    acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[t], bf[q], acc[q][t], 0, 0, 0);
+        };
+        bf16x8 b0[PW], a0[NT], b1[PW], a1[NT];
+        frags(std::integral_constant<int, 0>{}, b0, a0);
+        static_for<0, 7>([&](auto i) {
+            constexpr int p = 2 * decltype(i)::value;
+            frags(std::integral_constant<int, p + 1>{}, b1, a1);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(b0, a0);
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (p + 2 < 14) frags(std::integral_constant<int, p + 2>{}, b0, a0);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(b1, a1);
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        if (s == nslice - 1) {
+#pragma unroll
+            for (int q = 0; q < PW; q++) {
+                const int a = r0 + (q & 1) * 16 + (lane & 15), b = j0 + jw + (q >> 1), c = k0 + kw;
+                if (a < L.nr && b < L.nt && c < L.np) {
+                    const long idx = a + (long)L.nr * (b + (long)L.nt * c);
+#pragma unroll
+                    for (int t = 0; t < NT; t++) store(idx, t * 16 + 4 * (lane >> 4), acc[q][t]);
+                }
+#pragma unroll
+                for (int t = 0; t < NT; t++) acc[q][t] = float4v{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+        if (++s == nslice) {
+            s = 0;
+            tile += per;
+            if (tile >= t_end) break;
+        }
+    }
+}
 
 // y = act(conv([up?(x1), x2], w) + bias) with NT * 16 output channels.  x1 has c1
 // channels and lives on the level of y (up1 = 0) or on the next coarser level
 // (up1 = 1, read through nearest-neighbour upsampling); x2 (c2 channels, may be 0) on
 // the level of y.  Writes bf16 y and/or fp32 yf.
-template <int NT>
-__global__ __launch_bounds__(kTB) void k_conv_fwd(Lv L, const bf16 *__restrict__ x1, int c1, int up1,
-                                                  const bf16 *__restrict__ x2, int c2, const bf16 *__restrict__ w,
-                                                  const float *__restrict__ bias, int relu, bf16 *__restrict__ y,
-                                                  float *__restrict__ yf)
+template <int NT, int TJ, int TK>
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_conv_fwd(
+    Lv L, const bf16 *__restrict__ x1, int c1, int up1, const bf16 *__restrict__ x2, int c2,
+    const bf16 *__restrict__ w, const float *__restrict__ bias, int relu, bf16 *__restrict__ y, float *__restrict__ yf)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const long cell0 = ((long)blockIdx.x * (kTB / 64) + wv) * 16;
-    if (cell0 >= L.n) return;
-    const int m = lane & 15, kq = lane >> 4;
-    long cm = cell0 + m;
-    if (cm >= L.n) cm = L.n - 1;
-    int i, j, k;
-    cell_coords(L, cm, i, j, k);
-    const int cin = c1 + c2, cout = NT * 16;
     const int cr = L.nr >> 1, ct = L.nt >> 1;
-    float4v acc[NT];
-#pragma unroll
-    for (int t = 0; t < NT; t++) acc[t] = float4v{0.f, 0.f, 0.f, 0.f};
-    for (int tap = 0; tap < 27; tap++) {
-        int a, b, c;
-        const bool ok = tap_nb(L, i, j, k, tap, 1, a, b, c);
-        const long e = ok ? a + (long)L.nr * (b + (long)L.nt * c) : cm;
-        const long e1 = up1 ? (ok ? (a >> 1) + (long)cr * ((b >> 1) + (long)ct * (c >> 1)) : 0) : e;
-        const bf16 *wt = w + (long)tap * cout * cin;
-        for (int c0 = 0; c0 < cin; c0 += 16) {
-            const short4v av = (c0 < c1) ? ld4(x1 + e1 * c1 + c0 + 4 * kq, ok)
-                                         : ld4(x2 + e * c2 + (c0 - c1) + 4 * kq, ok);
-#pragma unroll
-            for (int t = 0; t < NT; t++) {
-                const short4v bv = ld4(wt + (long)(t * 16 + m) * cin + c0 + 4 * kq, true);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
-            }
+    auto load = [&](long idx, int a, int b, int c, int ch) -> uint4 {
+        if (ch < c1) {
+            const long e = up1 ? (a >> 1) + (long)cr * ((b >> 1) + (long)ct * (c >> 1)) : idx;
+            return *reinterpret_cast<const uint4 *>(x1 + e * c1 + ch);
         }
-    }
+        return *reinterpret_cast<const uint4 *>(x2 + idx * c2 + (ch - c1));
+    };
+    const int cout = NT * 16;
+    auto store = [&](long idx, int co, const float4v &v) {
+        const float4 bb = bias ? *reinterpret_cast<const float4 *>(bias + co) : make_float4(0.f, 0.f, 0.f, 0.f);
+        float o[4] = {v[0] + bb.x, v[1] + bb.y, v[2] + bb.z, v[3] + bb.w};
+        if (relu) {
 #pragma unroll
-    for (int t = 0; t < NT; t++) {
-        const float bb = bias ? bias[t * 16 + m] : 0.0f;
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const long cell = cell0 + 4 * kq + r;
-            if (cell < L.n) {
-                float v = acc[t][r] + bb;
-                if (relu && v < 0.0f) v = 0.0f;
-                const long o = cell * cout + t * 16 + m;
-                if (y) y[o] = f2bf(v);
-                if (yf) yf[o] = v;
-            }
+            for (int i = 0; i < 4; i++) o[i] = o[i] > 0.0f ? o[i] : (o[i] == o[i] ? 0.0f : o[i]);
         }
-    }
+        if (y) *reinterpret_cast<uint2 *>(y + idx * cout + co) = make_uint2(pack_bf16(o[0], o[1]), pack_bf16(o[2], o[3]));
+        if (yf) *reinterpret_cast<float4 *>(yf + idx * cout + co) = make_float4(o[0], o[1], o[2], o[3]);
+    };
+    conv_tiles<NT, TJ, TK, 1>(L, c1 + c2, w, load, store);
 }
 
-// --------------------------------------------------------- data gradient
+// ------------------------------------------------------------ data gradient
 
 // dX = conv^T(dYm, w) for the concatenated input [up?(x1), x2] of a convolution with
 // cout output channels (dYm = dY masked by the layer's ReLU output y when y != 0).
-// Output at the level of dY, NTI * 16 input channels: channels < c1 to d1 ([n][c1];
+// Output at the level of dY, NT * 16 input channels: channels < c1 to d1 ([n][c1];
 // for an upsampled x1 this is the gradient of the upsampled tensor, folded onto the
-// coarse level by k_up_bwd), the rest to d2 ([n][c2]).  Uses the transposed weights.
-template <int NTI>
-__global__ __launch_bounds__(kTB) void k_conv_bwd_data(Lv L, const float *__restrict__ dy, const bf16 *__restrict__ yout,
-                                                       int cout, const bf16 *__restrict__ wt, int c1,
-                                                       float *__restrict__ d1, int c2, float *__restrict__ d2)
+// coarse level by k_up_bwd), the rest to d2 ([n][c2]).  Uses the transposed weights
+// wt[tap][ci][co], i.e. the forward layout with the roles of ci and co exchanged.
+template <int NT, int TJ, int TK>
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_conv_bwd_data(
+    Lv L, const float *__restrict__ dy, const bf16 *__restrict__ yout, int cout, const bf16 *__restrict__ wt, int c1,
+    float *__restrict__ d1, int c2, float *__restrict__ d2)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const long cell0 = ((long)blockIdx.x * (kTB / 64) + wv) * 16;
-    if (cell0 >= L.n) return;
-    const int m = lane & 15, kq = lane >> 4;
-    long cm = cell0 + m;
-    if (cm >= L.n) cm = L.n - 1;
-    int i, j, k;
-    cell_coords(L, cm, i, j, k);
-    const int cin = c1 + c2;
-    float4v acc[NTI];
+    auto load = [&](long idx, int, int, int, int ch) -> uint4 {
+        const float4 g0 = *reinterpret_cast<const float4 *>(dy + idx * cout + ch);
+        const float4 g1 = *reinterpret_cast<const float4 *>(dy + idx * cout + ch + 4);
+        float f[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
+        if (yout) {
+            const uint4 u = *reinterpret_cast<const uint4 *>(yout + idx * cout + ch);
+            const bf16 *h = reinterpret_cast<const bf16 *>(&u);
 #pragma unroll
-    for (int t = 0; t < NTI; t++) acc[t] = float4v{0.f, 0.f, 0.f, 0.f};
-    for (int tap = 0; tap < 27; tap++) {
-        int a, b, c;
-        const bool ok = tap_nb(L, i, j, k, tap, -1, a, b, c);  // output cell whose tap reads this cell
-        const long o = ok ? a + (long)L.nr * (b + (long)L.nt * c) : cm;
-        const bf16 *wtt = wt + (long)tap * cin * cout;
-        for (int c0 = 0; c0 < cout; c0 += 16) {
-            const short4v av = ld4_grad(dy + o * cout + c0 + 4 * kq, yout ? yout + o * cout + c0 + 4 * kq : nullptr, ok);
-#pragma unroll
-            for (int t = 0; t < NTI; t++) {
-                const short4v bv = ld4(wtt + (long)(t * 16 + m) * cout + c0 + 4 * kq, true);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
-            }
+            for (int q = 0; q < 8; q++)
+                if (!(bf2f(h[q]) > 0.0f)) f[q] = 0.0f;
         }
-    }
-#pragma unroll
-    for (int t = 0; t < NTI; t++) {
-        const int ci = t * 16 + m;
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const long cell = cell0 + 4 * kq + r;
-            if (cell < L.n) {
-                if (ci < c1) d1[cell * c1 + ci] = acc[t][r];
-                else d2[cell * c2 + (ci - c1)] = acc[t][r];
-            }
-        }
-    }
+        return make_uint4(pack_bf16(f[0], f[1]), pack_bf16(f[2], f[3]), pack_bf16(f[4], f[5]), pack_bf16(f[6], f[7]));
+    };
+    auto store = [&](long idx, int ci, const float4v &v) {
+        const float4 o = make_float4(v[0], v[1], v[2], v[3]);
+        if (ci < c1) *reinterpret_cast<float4 *>(d1 + idx * c1 + ci) = o;
+        else *reinterpret_cast<float4 *>(d2 + idx * c2 + (ci - c1)) = o;
+    };
+    conv_tiles<NT, TJ, TK, -1>(L, cout, wt, load, store);
 }
 
 // -------------------------------------------------------- weight gradient
@@ -529,15 +683,54 @@ __global__ __launch_bounds__(kTB) void k_f2bf(long n, const float *__restrict__ 
 
 static unsigned nblk(long n) { return (unsigned)((n + kTB - 1) / kTB); }
 
+// Persistent grid: as many blocks as fit on the 256 compute units at once (by LDS),
+// but no more than there are tiles (rounded up to a multiple of 8).
+template <int TJ, int TK>
+unsigned conv_grid(const Lv &L, const void *kernel, size_t lds)
+{
+    const long ntiles = (long)((L.nr + kTR - 1) / kTR) * ((L.nt + TJ - 1) / TJ) * ((L.np + TK - 1) / TK);
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, kTB, lds) != hipSuccess || occ < 1) occ = 1;
+    const long per_cu = occ;
+    const long g = std::min<long>(256 * per_cu, (ntiles + 7) / 8 * 8);
+    return (unsigned)std::max<long>(8, g);
+}
+
+template <int NT, int TJ, int TK>
+void launch_fwd_t(const Lv &L, const bf16 *x1, int c1, int up1, const bf16 *x2, int c2, const bf16 *w, const float *b,
+                  int relu, bf16 *y, float *yf, hipStream_t s)
+{
+    constexpr size_t lds = conv_lds_bytes<NT, TJ, TK>();
+    static const bool attr = hipFuncSetAttribute((const void *)k_conv_fwd<NT, TJ, TK>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
+    (void)attr;
+    hipLaunchKernelGGL((k_conv_fwd<NT, TJ, TK>), dim3(conv_grid<TJ, TK>(L, (const void *)k_conv_fwd<NT, TJ, TK>, lds)), dim3(kTB), lds, s, L, x1, c1, up1, x2,
+                       c2, w, b, relu, y, yf);
+}
+
+template <int NT, int TJ, int TK>
+void launch_bwd_t(const Lv &L, const float *dy, const bf16 *y, int cout, const bf16 *wt, int c1, float *d1, int c2,
+                  float *d2, hipStream_t s)
+{
+    constexpr size_t lds = conv_lds_bytes<NT, TJ, TK>();
+    static const bool attr = hipFuncSetAttribute((const void *)k_conv_bwd_data<NT, TJ, TK>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
+    (void)attr;
+    hipLaunchKernelGGL((k_conv_bwd_data<NT, TJ, TK>), dim3(conv_grid<TJ, TK>(L, (const void *)k_conv_bwd_data<NT, TJ, TK>, lds)), dim3(kTB), lds, s, L, dy, y,
+                       cout, wt, c1, d1, c2, d2);
+}
+
+// Output-channel tiles NT = cout / 16; the theta x phi extent of a block's tile
+// shrinks as NT grows so that accumulators and LDS stay within budget.
 bool launch_conv_fwd(const Lv &L, const bf16 *x1, int c1, int up1, const bf16 *x2, int c2, const bf16 *w,
                      const float *b, int cout, int relu, bf16 *y, float *yf, hipStream_t s)
 {
-    const unsigned nb = (unsigned)((L.n + 63) / 64);
+    if ((c1 + c2) % 16 || c1 % 16) return false;
     switch (cout) {
-    case 16: hipLaunchKernelGGL(k_conv_fwd<1>, dim3(nb), dim3(kTB), 0, s, L, x1, c1, up1, x2, c2, w, b, relu, y, yf); return true;
-    case 32: hipLaunchKernelGGL(k_conv_fwd<2>, dim3(nb), dim3(kTB), 0, s, L, x1, c1, up1, x2, c2, w, b, relu, y, yf); return true;
-    case 48: hipLaunchKernelGGL(k_conv_fwd<3>, dim3(nb), dim3(kTB), 0, s, L, x1, c1, up1, x2, c2, w, b, relu, y, yf); return true;
-    case 64: hipLaunchKernelGGL(k_conv_fwd<4>, dim3(nb), dim3(kTB), 0, s, L, x1, c1, up1, x2, c2, w, b, relu, y, yf); return true;
+    case 16: launch_fwd_t<1, 4, 4>(L, x1, c1, up1, x2, c2, w, b, relu, y, yf, s); return true;
+    case 32: launch_fwd_t<2, 4, 4>(L, x1, c1, up1, x2, c2, w, b, relu, y, yf, s); return true;
+    case 48: launch_fwd_t<3, 4, 2>(L, x1, c1, up1, x2, c2, w, b, relu, y, yf, s); return true;
+    case 64: launch_fwd_t<4, 4, 2>(L, x1, c1, up1, x2, c2, w, b, relu, y, yf, s); return true;
     default: return false;
     }
 }
@@ -545,13 +738,13 @@ bool launch_conv_fwd(const Lv &L, const bf16 *x1, int c1, int up1, const bf16 *x
 bool launch_conv_bwd_data(const Lv &L, const float *dy, const bf16 *y, int cout, const bf16 *wt, int c1, float *d1,
                           int c2, float *d2, hipStream_t s)
 {
-    const unsigned nb = (unsigned)((L.n + 63) / 64);
+    if (cout % 16 || c1 % 16) return false;
     switch ((c1 + c2) / 16) {
-    case 1: hipLaunchKernelGGL(k_conv_bwd_data<1>, dim3(nb), dim3(kTB), 0, s, L, dy, y, cout, wt, c1, d1, c2, d2); return true;
-    case 2: hipLaunchKernelGGL(k_conv_bwd_data<2>, dim3(nb), dim3(kTB), 0, s, L, dy, y, cout, wt, c1, d1, c2, d2); return true;
-    case 3: hipLaunchKernelGGL(k_conv_bwd_data<3>, dim3(nb), dim3(kTB), 0, s, L, dy, y, cout, wt, c1, d1, c2, d2); return true;
-    case 4: hipLaunchKernelGGL(k_conv_bwd_data<4>, dim3(nb), dim3(kTB), 0, s, L, dy, y, cout, wt, c1, d1, c2, d2); return true;
-    case 6: hipLaunchKernelGGL(k_conv_bwd_data<6>, dim3(nb), dim3(kTB), 0, s, L, dy, y, cout, wt, c1, d1, c2, d2); return true;
+    case 1: launch_bwd_t<1, 4, 4>(L, dy, y, cout, wt, c1, d1, c2, d2, s); return true;
+    case 2: launch_bwd_t<2, 4, 4>(L, dy, y, cout, wt, c1, d1, c2, d2, s); return true;
+    case 3: launch_bwd_t<3, 4, 2>(L, dy, y, cout, wt, c1, d1, c2, d2, s); return true;
+    case 4: launch_bwd_t<4, 4, 2>(L, dy, y, cout, wt, c1, d1, c2, d2, s); return true;
+    case 6: launch_bwd_t<6, 2, 2>(L, dy, y, cout, wt, c1, d1, c2, d2, s); return true;
     default: return false;
     }
 }
