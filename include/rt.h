@@ -251,6 +251,14 @@ rt_status rt_net_forward(rt_ctx *ctx, rt_net *net, const void *X, float *z);
  * backward pass; the gradient stays on the network for rt_net_adam.  z (device) and
  * loss (host) may be NULL. */
 rt_status rt_net_loss_grad(rt_ctx *ctx, rt_net *net, const void *X, const float *e, float *z, double *loss);
+/* Residual loss of a preconditioner: L = ||A z - r||^2 / ||r||^2 with z = network(X),
+ * for the residual r[n] (fp32, device; normally the unit-RMS residual that channel 0 of
+ * X encodes) and the scaled operator a32[3n] (fp32, device, the layout of
+ * rt_system.ahat32: radial, polar and azimuthal outward coefficients per cell), then
+ * the backward pass with dL/dz = 2 A (A z - r) / ||r||^2 (A is symmetric).  The
+ * gradient stays on the network; z and loss may be NULL. */
+rt_status rt_net_loss_grad_resid(rt_ctx *ctx, rt_net *net, const void *X, const float *r, const float *a32, float *z,
+                                 double *loss);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with learning rate lr. */
 rt_status rt_net_adam(rt_ctx *ctx, rt_net *net, double lr);
 
@@ -259,18 +267,30 @@ rt_status rt_net_adam(rt_ctx *ctx, rt_net *net, double lr);
  * E0 (device, E-space start value, normally E^n) to a relative residual of 1e-12 for
  * the reference y*, then, for each iteration count k in iters, k CG iterations from
  * E0 give y_k; the pair is (r_k = b - A y_k, e_k = y* - y_k), both scaled by
- * sqrt(n) / ||r_k||, stored with the system's operator features.  Returns RT_EINVAL
+ * sqrt(n) / ||r_k||, stored with the system's operator features and (once per call)
+ * a float32 copy of the scaled operator for the residual loss.  Returns RT_EINVAL
  * when the set is full. */
 typedef struct rt_dataset rt_dataset;
 rt_status rt_dataset_create(rt_ctx *ctx, int capacity, rt_dataset **out);
 void rt_dataset_destroy(rt_dataset *ds);
 int rt_dataset_size(const rt_dataset *ds);
 rt_status rt_dataset_add(rt_ctx *ctx, rt_dataset *ds, const double *E0, const int *iters, int n_iters);
+/* Like rt_dataset_add, but y_k comes from k iterations of the learned flexible CG with
+ * the network net (no float64 fallback): pairs from the residuals that the learned
+ * solver itself produces, whose distribution differs from that of the plain CG
+ * iterates (training on both is what makes the network a usable preconditioner). */
+rt_status rt_dataset_add_learned(rt_ctx *ctx, rt_dataset *ds, rt_net *net, const double *E0, const int *iters,
+                                 int n_iters);
 
+typedef enum {
+    RT_LOSS_ERROR = 0,    /* ||z - e||^2 / ||e||^2 against the CG error e_k */
+    RT_LOSS_RESIDUAL = 1  /* ||A z - r||^2 / ||r||^2 (rt_net_loss_grad_resid) */
+} rt_loss;
 typedef struct {
     int epochs;   /* passes over the set */
     double lr;    /* peak learning rate (cosine decay to lr/10 over the run) */
     unsigned seed; /* order of the pairs in each epoch */
+    int loss;     /* rt_loss */
 } rt_train_opts;
 typedef struct {
     int steps;

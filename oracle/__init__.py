@@ -95,6 +95,8 @@ def lib():
             getattr(L, f).argtypes = [ip]
         L.ognn_loss_grad.argtypes = [ip, ip, ip, dp, dp, dp, dp, dp]
         L.ognn_loss_grad.restype = C.c_double
+        L.ognn_loss_grad_resid.argtypes = [ip, ip, ip, dp, dp, dp, dp, dp, dp]
+        L.ognn_loss_grad_resid.restype = C.c_double
         L.ognn_loss.argtypes = [C.c_long, dp, dp, dp]
         L.ognn_loss.restype = C.c_double
         L.ognn_adam.argtypes = [C.c_long, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double,
@@ -310,6 +312,15 @@ class NN:
         params = _f64(params).ravel(); X = _f64(X).ravel(); e = _f64(e).ravel()
         grad = np.empty_like(params); z = np.empty(nr * nt * npp)
         L = lib().ognn_loss_grad(nr, nt, npp, _p(params), _p(X), _p(e), _p(grad), _p(z))
+        return L, grad, z
+
+    @staticmethod
+    def loss_grad_resid(shape, params, X, r, ahat):
+        """Residual loss ||A z - r||^2 / ||r||^2 of z = U-Net(X) and its gradient."""
+        nr, nt, npp = shape
+        params = _f64(params).ravel(); X = _f64(X).ravel(); r = _f64(r).ravel(); ahat = _f64(ahat).ravel()
+        grad = np.empty_like(params); z = np.empty(nr * nt * npp)
+        L = lib().ognn_loss_grad_resid(nr, nt, npp, _p(params), _p(X), _p(r), _p(ahat), _p(grad), _p(z))
         return L, grad, z
 
     @staticmethod

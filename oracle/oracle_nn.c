@@ -382,3 +382,53 @@ double ognn_loss_grad(int nr, int nt, int np, const double *params, const double
     if (!z) free(zz);
     return L;
 }
+
+/* q = A z for the Jacobi-scaled operator: unit diagonal, ahat[c], ahat[n + c] and
+ * ahat[2n + c] the coefficients between cell c and its outward radial, polar and
+ * azimuthal (periodic) neighbours. */
+static void scaled_apply(int nr, int nt, int np, const double *ahat, const double *z, double *q)
+{
+    long n = (long)nr * nt * np;
+    const double *ar = ahat, *at = ahat + n, *ap = ahat + 2 * n;
+    for (int k = 0; k < np; k++)
+        for (int j = 0; j < nt; j++)
+            for (int i = 0; i < nr; i++) {
+                long c = i + (long)nr * (j + (long)nt * k);
+                double v = z[c];
+                if (i + 1 < nr) v += ar[c] * z[c + 1];
+                if (i > 0) v += ar[c - 1] * z[c - 1];
+                if (j + 1 < nt) v += at[c] * z[c + nr];
+                if (j > 0) v += at[c - nr] * z[c - nr];
+                if (np > 1) {
+                    long kp = i + (long)nr * (j + (long)nt * ((k + 1) % np));
+                    long km = i + (long)nr * (j + (long)nt * ((k + np - 1) % np));
+                    v += ap[c] * z[kp] + ap[km] * z[km];
+                }
+                q[c] = v;
+            }
+}
+
+/* Residual loss of the network as a preconditioner: L = ||A z - r||^2 / ||r||^2 with
+ * z = U-Net(X), and its parameter gradient: dL/d(Az) = 2 (A z - r) / ||r||^2, then
+ * dL/dz = A dL/d(Az) (A symmetric), then the backward pass. */
+double ognn_loss_grad_resid(int nr, int nt, int np, const double *params, const double *X, const double *r,
+                            const double *ahat, double *grad, double *z)
+{
+    long n = (long)nr * nt * np;
+    ognn_acts A;
+    double *zz = z ? z : (double *)malloc(sizeof(double) * n);
+    double *q = (double *)malloc(sizeof(double) * n);
+    double *gq = (double *)malloc(sizeof(double) * n);
+    double *gz = (double *)malloc(sizeof(double) * n);
+    ognn_forward(nr, nt, np, params, X, &A, zz);
+    scaled_apply(nr, nt, np, ahat, zz, q);
+    double L = ognn_loss(n, q, r, gq);
+    scaled_apply(nr, nt, np, ahat, gq, gz);
+    ognn_backward(nr, nt, np, params, X, &A, gz, grad, NULL);
+    ognn_free(&A);
+    free(q);
+    free(gq);
+    free(gz);
+    if (!z) free(zz);
+    return L;
+}

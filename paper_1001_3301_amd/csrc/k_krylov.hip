@@ -571,6 +571,11 @@ void launch_spmv(const Dims &d, int nblk, const double *a, const double *x, doub
     RT_DISPATCH_VW(double, pick_vw<double>(d), k_spmv_t, dim3(nblk), dim3(kKB), 0, st, d, nblk, a, x, y);
 }
 
+void launch_spmv32(const Dims &d, int nblk, const float *a, const float *x, float *y, hipStream_t st)
+{
+    RT_DISPATCH_VW(float, pick_vw<float>(d), k_spmv_t, dim3(nblk), dim3(kKB), 0, st, d, nblk, a, x, y);
+}
+
 void launch_norm2(const Dims &d, int nblk, const double *x, double *partials, unsigned *counter,
                   DevScalars *sc, hipStream_t st)
 {

@@ -672,6 +672,14 @@ __global__ void k_pair_scale(long n, const DevScalars *sc, double *scale)
     }
 }
 
+// out = float(r * scale[0]): the scaled residual of a training pair in fp32.
+__global__ __launch_bounds__(kTB) void k_scaled_f32(long n, const double *__restrict__ r,
+                                                    const double *__restrict__ scale, float *__restrict__ out)
+{
+    long c = (long)blockIdx.x * kTB + threadIdx.x;
+    if (c < n) out[c] = (float)(r[c] * scale[0]);
+}
+
 // fp32 -> bf16 and bf16 -> fp32 copies (tests, targets).
 __global__ __launch_bounds__(kTB) void k_f2bf(long n, const float *__restrict__ x, bf16 *__restrict__ y)
 {
@@ -828,6 +836,11 @@ void launch_adam(long np_, float *p, const float *g, float *m, float *v, float l
 void launch_cast_weights(int taps, int cout, int cin, const float *p, bf16 *w, bf16 *wt, hipStream_t s)
 {
     hipLaunchKernelGGL(k_cast_weights, dim3(nblk((long)taps * cout * cin)), dim3(kTB), 0, s, taps, cout, cin, p, w, wt);
+}
+
+void launch_scaled_f32(long n, const double *r, const double *scale, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scaled_f32, dim3(nblk(n)), dim3(kTB), 0, s, n, r, scale, out);
 }
 
 void launch_pair(long n, const DevScalars *sc, const double *ystar, const double *y, double *scale, float *e,

@@ -650,7 +650,7 @@ rt_status solve_mixed(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, d
 // residual scaled to unit RMS.  If the true residual is not below tol after
 // inner_max_iter network applications (default 400), or anything turns non-finite,
 // the solve falls back to float64 CG from the current iterate.
-rt_status solve_learned(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb)
+rt_status solve_learned(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb, bool allow_fallback = true)
 {
     const Dims &d = ctx->d;
     hipStream_t s = ctx->stream;
@@ -703,6 +703,11 @@ rt_status solve_learned(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
         }
     }
     st->iters = h->iters;
+    if (fallback && !allow_fallback) {
+        if (!nonfinite) launch_fold(d.n, ctx->x32, ctx->y, s);
+        RT_HIP(ctx, hipGetLastError());
+        return nonfinite ? RT_ENONFINITE : RT_OK;
+    }
     if (fallback) {
         // keep what the float32 iterations gained (unless they went non-finite: then y is
         // the iterate of the last reliable update), then finish with the float64 method
@@ -763,6 +768,31 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
 }  // extern "C"
 
 namespace rt {
+// `applies` iterations of the learned flexible CG from y (device, y-space, in/out), with
+// no float64 fallback (training-data generation: the residuals the learned solver
+// itself meets).  Stops early at the relative residual 1e-12.
+rt_status learned_from(rt_ctx *ctx, rt_net *net, int applies, double *y, rt_solve_stats *st)
+{
+    if (!ctx->have_system) return fail(ctx, RT_EINVAL, "no assembled system");
+    rt_solve_stats local{};
+    rt_solve_stats *S = st ? st : &local;
+    *S = rt_solve_stats{};
+    double bb = 0.0;
+    if (rt_status e = norm_b(ctx, bb)) return e;
+    if (!(bb > 0.0) || !isfin(bb)) return fail(ctx, RT_ENONFINITE, "right-hand side is zero or not finite");
+    RT_HIP(ctx, hipMemcpyAsync(ctx->y, y, ctx->d.n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    rt_solve_opts o{};
+    o.mode = RT_SOLVE_LEARNED;
+    o.tol = 1e-12;
+    o.max_iter = applies;
+    o.inner_max_iter = applies;
+    o.net = net;
+    rt_status status = applies > 0 ? solve_learned(ctx, &o, S, bb, false) : RT_OK;
+    RT_HIP(ctx, hipMemcpyAsync(y, ctx->y, ctx->d.n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    RT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return status == RT_ENOCONV ? RT_OK : status;
+}
+
 rt_status solve_fp64_from(rt_ctx *ctx, double tol, int max_iter, double *y, rt_solve_stats *st)
 {
     if (!ctx->have_system) return fail(ctx, RT_EINVAL, "no assembled system");

@@ -196,6 +196,7 @@ void launch_scale_div(long n, const double *s, const double *x, double *y, hipSt
 // Krylov kernels: nblk blocks (a multiple of 8) sweeping the rows in windows; the
 // CG iteration launches its update kernel with nblk_upd blocks.
 void launch_spmv(const Dims &d, int nblk, const double *a, const double *x, double *y, hipStream_t st);
+void launch_spmv32(const Dims &d, int nblk, const float *a, const float *x, float *y, hipStream_t st);
 void launch_norm2(const Dims &d, int nblk, const double *x, double *partials, unsigned *counter,
                   DevScalars *sc, hipStream_t st);
 void launch_resid(const Dims &d, int nblk, const double *a, const double *b, const double *y,
@@ -247,6 +248,7 @@ void launch_loss(long n, const float *z, const float *e, double *part, double *r
 void launch_adam(long np_, float *p, const float *g, float *m, float *v, float lr, float b1, float b2, float eps,
                  float c1, float c2, hipStream_t s);
 void launch_cast_weights(int taps, int cout, int cin, const float *p, bf16 *w, bf16 *wt, hipStream_t s);
+void launch_scaled_f32(long n, const double *r, const double *scale, float *out, hipStream_t s);
 void launch_pair(long n, const DevScalars *sc, const double *ystar, const double *y, double *scale, float *e,
                  hipStream_t s);
 }  // namespace nn
@@ -256,6 +258,7 @@ rt_status net_prepare(rt_net *net, rt_ctx *ctx);                       // worksp
 rt_status net_precond(rt_net *net, rt_ctx *ctx, const float *r, float *z); // z = M(r); uses sc->rr
 // Float64 CG on the context's current system from y (in/out), tol and iteration cap.
 rt_status solve_fp64_from(rt_ctx *ctx, double tol, int max_iter, double *y, rt_solve_stats *st);
+rt_status learned_from(rt_ctx *ctx, rt_net *net, int applies, double *y, rt_solve_stats *st);
 
 }  // namespace rt
 

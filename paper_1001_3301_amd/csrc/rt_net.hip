@@ -50,6 +50,7 @@ struct rt_net {
     Lv lv[3]{};
     bf16 *X = nullptr, *a[10] = {}, *p1 = nullptr, *p2 = nullptr;
     float *z = nullptr, *zin = nullptr;
+    float *rq = nullptr, *gq = nullptr;  // residual loss: A z and dL/d(A z)
     float *g9, *g8, *gU8, *gS1, *g7, *g6, *gU6, *gS2, *g5, *g4, *gp2, *g2, *gp1, *g0, *gz;
     float *part = nullptr;
     size_t part_cap = 0;
@@ -61,8 +62,12 @@ struct rt_dataset {
     long n = 0;
     int cap = 0, size = 0;
     int nr = 0, nt = 0, nph = 0;
-    bf16 *X = nullptr;   // [cap][n][16]
-    float *E = nullptr;  // [cap][n]
+    bf16 *X = nullptr;    // [cap][n][16]
+    float *E = nullptr;   // [cap][n] scaled errors e_k
+    float *R = nullptr;   // [cap][n] scaled residuals r_k (fp32)
+    float *A32 = nullptr; // [cap][3n] scaled operator of each added system
+    std::vector<int> field;  // pair -> its system in A32
+    int nfield = 0;
     double *ystar = nullptr, *y0 = nullptr;
     std::vector<void *> allocs;
 };
@@ -134,6 +139,9 @@ rt_status ensure_ws(rt_net *net, int nr, int nt, int np, bool train)
     bool ok = net->X && net->p1 && net->p2 && net->z && net->zin && net->lpart && net->lres && net->scale;
     for (int l = 0; l < 10; l++) ok = ok && net->a[l];
     if (train) {
+        net->rq = nalloc<float>(W, n0);
+        net->gq = nalloc<float>(W, n0);
+        ok = ok && net->rq && net->gq;
         net->g9 = nalloc<float>(W, n0 * 16); net->g8 = nalloc<float>(W, n0 * 16);
         net->gU8 = nalloc<float>(W, n0 * 32); net->gS1 = nalloc<float>(W, n0 * 16);
         net->g7 = nalloc<float>(W, n1 * 32); net->g6 = nalloc<float>(W, n1 * 32);
@@ -382,6 +390,30 @@ rt_status rt_net_loss_grad(rt_ctx *ctx, rt_net *net, const void *X, const float 
     return RT_OK;
 }
 
+rt_status rt_net_loss_grad_resid(rt_ctx *ctx, rt_net *net, const void *X, const float *r, const float *a32, float *z,
+                                 double *loss_out)
+{
+    if (!ctx || !net || !X || !r || !a32) return nfail(net, RT_EINVAL, "rt_net_loss_grad_resid: NULL argument");
+    if (rt_status er = ensure_ws(net, ctx->d.nr, ctx->d.nt, ctx->d.np, true)) return er;
+    hipStream_t s = ctx->stream;
+    const long n = net->lv[0].n;
+    NN_HIP(net, hipMemcpyAsync(net->X, X, n * 16 * sizeof(bf16), hipMemcpyDeviceToDevice, s));
+    forward(net, s);
+    launch_spmv32(ctx->d, ctx->nblk, a32, net->z, net->rq, s);                    // A z
+    nn::launch_loss(n, net->rq, r, net->lpart, net->lres, net->gq, s);           // L, dL/d(A z)
+    launch_spmv32(ctx->d, ctx->nblk, a32, net->gq, net->gz, s);                   // dL/dz = A^T dL/d(A z)
+    backward(net, s);
+    if (z) NN_HIP(net, hipMemcpyAsync(z, net->z, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+    NN_HIP(net, hipGetLastError());
+    if (loss_out) {
+        double h[2];
+        NN_HIP(net, hipMemcpyAsync(h, net->lres, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        NN_HIP(net, hipStreamSynchronize(s));
+        *loss_out = h[0];
+    }
+    return RT_OK;
+}
+
 rt_status rt_net_adam(rt_ctx *ctx, rt_net *net, double lr)
 {
     if (!ctx || !net || !(lr > 0.0)) return nfail(net, RT_EINVAL, "rt_net_adam: bad arguments");
@@ -483,9 +515,11 @@ rt_status rt_dataset_create(rt_ctx *ctx, int capacity, rt_dataset **out)
     ds->nr = ctx->d.nr; ds->nt = ctx->d.nt; ds->nph = ctx->d.np;
     ds->X = nalloc<bf16>(ds->allocs, (size_t)capacity * ds->n * 16);
     ds->E = nalloc<float>(ds->allocs, (size_t)capacity * ds->n);
+    ds->R = nalloc<float>(ds->allocs, (size_t)capacity * ds->n);
+    ds->A32 = nalloc<float>(ds->allocs, (size_t)capacity * 3 * ds->n);
     ds->ystar = nalloc<double>(ds->allocs, ds->n);
     ds->y0 = nalloc<double>(ds->allocs, ds->n);
-    if (!ds->X || !ds->E || !ds->ystar || !ds->y0) {
+    if (!ds->X || !ds->E || !ds->R || !ds->A32 || !ds->ystar || !ds->y0) {
         rt_dataset_destroy(ds);
         return nfail(nullptr, RT_ENOMEM, "rt_dataset_create: out of device memory");
     }
@@ -503,7 +537,13 @@ void rt_dataset_destroy(rt_dataset *ds)
 
 int rt_dataset_size(const rt_dataset *ds) { return ds ? ds->size : 0; }
 
-rt_status rt_dataset_add(rt_ctx *ctx, rt_dataset *ds, const double *E0, const int *iters, int n_iters)
+}  // extern "C"
+
+namespace {
+
+// Pairs from k iterations of the float64 CG (net == nullptr) or of the learned flexible
+// CG with the network net, for each k in iters, all from E0.
+rt_status add_pairs(rt_ctx *ctx, rt_dataset *ds, rt_net *net, const double *E0, const int *iters, int n_iters)
 {
     if (!ctx || !ds || !E0 || !iters || n_iters < 1) return nfail(nullptr, RT_EINVAL, "rt_dataset_add: bad arguments");
     if (ctx->d.nr != ds->nr || ctx->d.nt != ds->nt || ctx->d.np != ds->nph)
@@ -519,28 +559,53 @@ rt_status rt_dataset_add(rt_ctx *ctx, rt_dataset *ds, const double *E0, const in
     NN_HIP(nullptr, hipMemcpyAsync(ds->ystar, ds->y0, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (rt_status e = solve_fp64_from(ctx, 1e-12, 200000, ds->ystar, nullptr))
         return nfail(nullptr, e, std::string("reference solve: ") + rt_last_error(ctx));
+    const int fld = ds->nfield;
+    NN_HIP(nullptr, hipMemcpyAsync(ds->A32 + (size_t)fld * 3 * n, ctx->ahat32, 3 * n * sizeof(float),
+                                   hipMemcpyDeviceToDevice, s));
     double *y = ctx->qv;  // scratch: the Krylov q vector is free between solves
     for (int q = 0; q < n_iters; q++) {
         NN_HIP(nullptr, hipMemcpyAsync(y, ds->y0, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        if (iters[q] > 0)
-            if (rt_status e = solve_fp64_from(ctx, 1e-30, iters[q], y, nullptr))
-                return nfail(nullptr, e, std::string("partial solve: ") + rt_last_error(ctx));
+        if (iters[q] > 0) {
+            rt_status e = net ? learned_from(ctx, net, iters[q], y, nullptr)
+                              : solve_fp64_from(ctx, 1e-30, iters[q], y, nullptr);
+            if (e) return nfail(nullptr, e, std::string("partial solve: ") + rt_last_error(ctx));
+        }
         launch_resid(ctx->d, ctx->nblk, ctx->ahat, ctx->bhat, y, ctx->r, ctx->partials, ctx->counter, ctx->sc, 0, s);
         bf16 *X = ds->X + (size_t)ds->size * n * 16;
         float *E = ds->E + (size_t)ds->size * n;
         nn::launch_pair(n, ctx->sc, ds->ystar, y, ctx->nscale, E, s);
         nn::launch_features(n, ctx->ahat, X, s);
         nn::launch_set_input(n, (const double *)ctx->r, ctx->nscale, X, s);
+        nn::launch_scaled_f32(n, ctx->r, ctx->nscale, ds->R + (size_t)ds->size * n, s);
         NN_HIP(nullptr, hipGetLastError());
+        ds->field.push_back(fld);
         ds->size++;
     }
+    ds->nfield++;
     NN_HIP(nullptr, hipStreamSynchronize(s));
     return RT_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+rt_status rt_dataset_add(rt_ctx *ctx, rt_dataset *ds, const double *E0, const int *iters, int n_iters)
+{
+    return add_pairs(ctx, ds, nullptr, E0, iters, n_iters);
+}
+
+rt_status rt_dataset_add_learned(rt_ctx *ctx, rt_dataset *ds, rt_net *net, const double *E0, const int *iters,
+                                 int n_iters)
+{
+    if (!net) return nfail(nullptr, RT_EINVAL, "rt_dataset_add_learned: network is NULL");
+    return add_pairs(ctx, ds, net, E0, iters, n_iters);
+}
+
 rt_status rt_net_train(rt_ctx *ctx, rt_net *net, rt_dataset *ds, const rt_train_opts *o, rt_train_stats *st)
 {
-    if (!ctx || !net || !ds || !o || o->epochs < 1 || !(o->lr > 0.0))
+    if (!ctx || !net || !ds || !o || o->epochs < 1 || !(o->lr > 0.0) ||
+        (o->loss != RT_LOSS_ERROR && o->loss != RT_LOSS_RESIDUAL))
         return nfail(net, RT_EINVAL, "rt_net_train: bad arguments");
     if (ds->size < 1) return nfail(net, RT_EINVAL, "rt_net_train: empty set");
     if (ctx->d.nr != ds->nr || ctx->d.nt != ds->nt || ctx->d.np != ds->nph)
@@ -567,9 +632,12 @@ rt_status rt_net_train(rt_ctx *ctx, rt_net *net, rt_dataset *ds, const rt_train_
         for (int q = 0; q < ds->size; q++, step++) {
             const int idx = order[q];
             double L = 0.0;
-            if (rt_status e = rt_net_loss_grad(ctx, net, ds->X + (size_t)idx * n * 16, ds->E + (size_t)idx * n,
-                                               nullptr, &L))
-                return e;
+            const bf16 *Xi = ds->X + (size_t)idx * n * 16;
+            rt_status e = (o->loss == RT_LOSS_RESIDUAL)
+                              ? rt_net_loss_grad_resid(ctx, net, Xi, ds->R + (size_t)idx * n,
+                                                       ds->A32 + (size_t)ds->field[idx] * 3 * n, nullptr, &L)
+                              : rt_net_loss_grad(ctx, net, Xi, ds->E + (size_t)idx * n, nullptr, &L);
+            if (e) return e;
             if (!std::isfinite(L)) return nfail(net, RT_ENONFINITE, "rt_net_train: loss is not finite");
             sum += L;
             const double frac = total > 1 ? (double)step / (total - 1) : 0.0;

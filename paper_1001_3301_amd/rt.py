@@ -86,9 +86,12 @@ EXPORTS = ["rt_create", "rt_destroy", "rt_last_error", "rt_ncell", "rt_star_bin_
            "rt_spmv", "rt_fld_solve", "rt_temperature", "rt_force", "rt_step", "rt_step_fields",
            "rt_net_create", "rt_net_destroy", "rt_net_last_error", "rt_net_param_count",
            "rt_net_get_params", "rt_net_get_grads", "rt_net_set_params", "rt_net_save", "rt_net_load",
-           "rt_net_forward", "rt_net_loss_grad", "rt_net_adam", "rt_dataset_create",
-           "rt_dataset_destroy", "rt_dataset_size", "rt_dataset_add", "rt_net_train",
+           "rt_net_forward", "rt_net_loss_grad", "rt_net_loss_grad_resid", "rt_net_adam", "rt_dataset_create",
+           "rt_dataset_destroy", "rt_dataset_size", "rt_dataset_add", "rt_dataset_add_learned", "rt_net_train",
            "rt_nn_conv3d_fwd", "rt_nn_conv3d_bwd_data", "rt_nn_conv3d_bwd_weight"]
+
+
+LOSS_ERROR, LOSS_RESIDUAL = 0, 1
 
 
 class NetConfig(C.Structure):
@@ -96,7 +99,7 @@ class NetConfig(C.Structure):
 
 
 class TrainOpts(C.Structure):
-    _fields_ = [("epochs", C.c_int), ("lr", C.c_double), ("seed", C.c_uint)]
+    _fields_ = [("epochs", C.c_int), ("lr", C.c_double), ("seed", C.c_uint), ("loss", C.c_int)]
 
 
 class TrainStats(C.Structure):
@@ -152,12 +155,14 @@ def lib():
     L.rt_net_load.argtypes = [vp, C.c_char_p]
     L.rt_net_forward.argtypes = [vp, vp, vp, vp]
     L.rt_net_loss_grad.argtypes = [vp, vp, vp, vp, vp, P(C.c_double)]
+    L.rt_net_loss_grad_resid.argtypes = [vp, vp, vp, vp, vp, vp, P(C.c_double)]
     L.rt_net_adam.argtypes = [vp, vp, C.c_double]
     L.rt_dataset_create.argtypes = [vp, C.c_int, P(vp)]
     L.rt_dataset_destroy.argtypes = [vp]
     L.rt_dataset_destroy.restype = None
     L.rt_dataset_size.argtypes = [vp]
     L.rt_dataset_add.argtypes = [vp, vp, vp, P(C.c_int), C.c_int]
+    L.rt_dataset_add_learned.argtypes = [vp, vp, vp, vp, P(C.c_int), C.c_int]
     L.rt_net_train.argtypes = [vp, vp, vp, P(TrainOpts), P(TrainStats)]
     ip = C.c_int
     L.rt_nn_conv3d_fwd.argtypes = [vp, ip, ip, ip, vp, ip, ip, vp, ip, vp, vp, ip, ip, vp, vp]
@@ -402,11 +407,23 @@ class Net:
                                          C.byref(L)))
         return L.value
 
+    def loss_grad_resid(self, ctx, X, r, a32, z=None):
+        """Residual loss ||A z - r||^2 / ||r||^2 (a32: the scaled operator, 3n fp32) and
+        the backward pass."""
+        L = C.c_double()
+        self._chk(lib().rt_net_loss_grad_resid(ctx.h, self.h, ctx._dev(X, ctx.n * 16, "X", ctx._torch.bfloat16),
+                                               ctx._dev(r, ctx.n, "r", ctx._torch.float32),
+                                               ctx._dev(a32, 3 * ctx.n, "a32", ctx._torch.float32),
+                                               ctx._dev(z, ctx.n, "z", ctx._torch.float32, allow_none=True),
+                                               C.byref(L)))
+        return L.value
+
     def adam(self, ctx, lr):
         self._chk(lib().rt_net_adam(ctx.h, self.h, float(lr)))
 
-    def train(self, ctx, ds, epochs, lr, seed=0):
-        o = TrainOpts(epochs, lr, seed)
+    def train(self, ctx, ds, epochs, lr, seed=0, loss=0):
+        """loss: LOSS_ERROR (||z - e||^2 / ||e||^2) or LOSS_RESIDUAL (||A z - r||^2 / ||r||^2)."""
+        o = TrainOpts(epochs, lr, seed, int(loss))
         st = TrainStats()
         self._chk(lib().rt_net_train(ctx.h, self.h, ds.h, C.byref(o), C.byref(st)))
         return st.as_dict()
@@ -440,6 +457,14 @@ class Dataset:
     def add(self, E0, iters):
         it = (C.c_int * len(iters))(*iters)
         st = lib().rt_dataset_add(self.ctx.h, self.h, self.ctx._dev(E0, self.ctx.n, "E0"), it, len(iters))
+        if st != RT_OK:
+            raise RtError(st, lib().rt_net_last_error(None).decode())
+
+    def add_learned(self, net, E0, iters):
+        """Pairs from the residuals of k learned flexible-CG iterations with `net`."""
+        it = (C.c_int * len(iters))(*iters)
+        st = lib().rt_dataset_add_learned(self.ctx.h, self.h, net.h, self.ctx._dev(E0, self.ctx.n, "E0"), it,
+                                          len(iters))
         if st != RT_OK:
             raise RtError(st, lib().rt_net_last_error(None).decode())
 

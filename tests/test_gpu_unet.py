@@ -238,3 +238,53 @@ def test_learned_solve_falls_back_when_the_network_blows_up():
     rc, st = ctx.solve(E, rt.solve_opts(rt.MODE_LEARNED, tol=1e-8, net=net))
     assert st["fallback"] == 1 and st["relres"] <= 1e-8
     assert np.all(np.isfinite(E.cpu().numpy()))
+
+
+def test_residual_loss_gradient_against_oracle():
+    """rt_net_loss_grad_resid (forward, A z with the fp32 operator, loss, A^T, backward)
+    against the oracle's residual-loss gradient on the same bf16 weights and operator."""
+    from paper_1001_3301_amd import rt
+    shape = (16, 8, 8)
+    n = 16 * 8 * 8
+    wl, ctx = _ctx_for(shape)
+    net = rt.Net(seed=5)
+    p = net.get_params().astype(np.float64)
+    pq = p.copy()
+    for l, (taps, cout, cin) in enumerate(NN.layer_shapes()):
+        o = NN.param_offset(l)
+        nw = taps * cout * cin
+        pq[o:o + nw] = bits_to_f64(bf16_bits(p[o:o + nw]))
+    Xb = _net_input(n, 12)
+    X64 = bits_to_f64(Xb).reshape(n, 16)
+    g = _rng(13)
+    r = g.standard_normal(n).astype(np.float32)
+    a32 = (-0.16 * g.random(3 * n)).astype(np.float32)
+    a32.reshape(3, 8, 8, 16)[0][:, :, -1] = 0.0
+    a32.reshape(3, 8, 8, 16)[1][:, -1, :] = 0.0
+    L_ref, g_ref, z_ref = NN.loss_grad_resid(shape, pq, X64, r.astype(np.float64), a32.astype(np.float64))
+    z = torch.empty(n, dtype=torch.float32, device="cuda")
+    L = net.loss_grad_resid(ctx, dev_bf16(Xb), dev_f32(r), dev_f32(a32), z)
+    assert np.linalg.norm(z.cpu().numpy() - z_ref) <= 3e-2 * np.linalg.norm(z_ref)
+    assert abs(L - L_ref) <= 3e-2 * L_ref
+    gg = net.get_grads().astype(np.float64)
+    # bf16 activations (relative rounding 2^-9 per layer) and ReLU masks taken from
+    # them make the gradients of the layers far from the output differ from the float64
+    # ones by up to ~15 % in norm on this input (direction within ~9 degrees)
+    for l, (taps, cout, cin) in enumerate(NN.layer_shapes()):
+        o = NN.param_offset(l)
+        sl = slice(o, o + taps * cout * cin + cout)
+        a, b = gg[sl], g_ref[sl]
+        cos = np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300)
+        assert cos > 0.98, (l, cos)
+        assert np.linalg.norm(a - b) <= 0.2 * np.linalg.norm(b), l
+
+
+def test_training_with_residual_loss_lowers_it():
+    from paper_1001_3301_amd import rt
+    wl, ctx, rho, T, En, S = _small_problem()
+    ds = rt.Dataset(ctx, 8)
+    ds.add(En, [0, 5, 20, 60])
+    net = rt.Net(seed=11)
+    st = net.train(ctx, ds, epochs=25, lr=2e-3, seed=1, loss=rt.LOSS_RESIDUAL)
+    assert st["steps"] == 100
+    assert st["loss_last_epoch"] < 0.7 * st["loss_first_epoch"], st

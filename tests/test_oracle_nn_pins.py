@@ -142,3 +142,52 @@ def test_adam_constant_gradient_closed_form():
         p, m, v = NN.adam(p, g, m, v, lr, b1, b2, eps, t)
     ref = p0 - 10 * lr * g / (np.abs(g) + eps)
     assert np.max(np.abs(p - ref)) < 1e-12
+
+
+def _scaled_operator_sparse(shape, ahat):
+    """The scaled operator as a scipy sparse matrix (unit diagonal, symmetric outward
+    couplings, periodic in phi), built independently of the oracle's stencil loop."""
+    import scipy.sparse as sp
+    nr, nt, npp = shape
+    n = nr * nt * npp
+    a = np.asarray(ahat).reshape(3, npp, nt, nr)
+    idx = np.arange(n).reshape(npp, nt, nr)
+    rows, cols, vals = [np.arange(n)], [np.arange(n)], [np.ones(n)]
+    pairs = [(idx[:, :, :-1], idx[:, :, 1:], a[0][:, :, :-1]),
+             (idx[:, :-1, :], idx[:, 1:, :], a[1][:, :-1, :])]
+    if npp > 1:
+        pairs.append((idx, np.roll(idx, -1, axis=0), a[2]))
+    for i0, i1, v in pairs:
+        rows += [i0.ravel(), i1.ravel()]
+        cols += [i1.ravel(), i0.ravel()]
+        vals += [v.ravel(), v.ravel()]
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+
+
+def test_residual_loss_value_and_gradient():
+    shape = (8, 4, 4)
+    n = 8 * 4 * 4
+    r = _rng(6)
+    params = _random_params(7)
+    X = np.zeros((n, 16))
+    X[:, :4] = r.standard_normal((n, 4))
+    rr = r.standard_normal(n)
+    ahat = -0.15 * r.random(3 * n)
+    ahat.reshape(3, 4, 4, 8)[0][:, :, -1] = 0.0  # no coupling beyond the outer radial face
+    ahat.reshape(3, 4, 4, 8)[1][:, -1, :] = 0.0  # nor beyond the last polar face
+    L, grad, z = NN.loss_grad_resid(shape, params, X, rr, ahat)
+    A = _scaled_operator_sparse(shape, ahat)
+    q = A @ z
+    assert abs(L - np.sum((q - rr) ** 2) / np.sum(rr ** 2)) <= 1e-12 * L
+    picks = []
+    for l, (taps, cout, cin) in enumerate(NN.layer_shapes()):
+        o = NN.param_offset(l)
+        nw = taps * cout * cin
+        picks += [o + int(r.integers(nw)), o + nw + int(r.integers(cout))]
+    for idx in picks:
+        h = 1e-6 * max(1.0, abs(params[idx]))
+        pp, pm = params.copy(), params.copy()
+        pp[idx] += h
+        pm[idx] -= h
+        fd = (NN.loss_grad_resid(shape, pp, X, rr, ahat)[0] - NN.loss_grad_resid(shape, pm, X, rr, ahat)[0]) / (2 * h)
+        assert abs(fd - grad[idx]) <= 1e-5 * abs(grad[idx]) + 2e-9 * max(1.0, L), (idx, fd, grad[idx])
