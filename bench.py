@@ -42,10 +42,84 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_mode(ctx, rt, torch, rho, T0, mode, steps, warmup, tol, inner_tol, max_iter):
+# Multiply-adds x 2 per fine cell of one U-Net application: 3x3x3 layers (Cin x Cout)
+# 16x16, 16x16, 48x16, 16x16 on the fine level, 16x32, 32x32, 96x32, 32x32 on the 2x
+# coarser level (1/8 of the cells), 32x64, 64x64 on the 4x coarser level (1/64), and
+# the 1x1 16 -> 1 output.
+UNET_FLOP_PER_CELL = 54 * (256 + 256 + 768 + 256) + 54 * (512 + 1024 + 3072 + 1024) / 8 + 54 * (2048 + 4096) / 64 + 32
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def mode_opts(rt, mode, tol, max_iter, inner_tol, net=None, budget=0):
+    m = {"fp64": rt.MODE_FP64, "mixed": rt.MODE_MIXED, "learned": rt.MODE_LEARNED}[mode]
+    return rt.solve_opts(m, tol=tol, max_iter=max_iter, check_every=32, inner_tol=inner_tol,
+                         inner_max_iter=budget if mode == "learned" else 0, net=net if mode == "learned" else None)
+
+
+def train_network(rt, torch, sy, n_fields, epochs, seed=7):
+    """The learned preconditioner, trained on the GPU: n_fields seeded clumpy 128x64x64
+    fields (tau550 log-uniform in [0.1, 100]), pairs from 0/10/40/150 float64 CG
+    iterations, residual loss; then one round of pairs from the learned solver's own
+    residuals (1/3/8/20 iterations) and further epochs."""
+    import numpy as np
+    t0 = time.perf_counter()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    wls = [sy.make_workload("train", 128, 64, 64, 64, float(10 ** rng.uniform(-1, 2)), 2000 + f)
+           for f in range(n_fields)]
+    ctx = rt.Context.from_workload(wls[0])
     n = ctx.n
-    m = {"fp64": rt.MODE_FP64, "mixed": rt.MODE_MIXED}[mode]
-    opts = rt.solve_opts(m, tol=tol, max_iter=max_iter, check_every=32, inner_tol=inner_tol)
+
+    def system(wl):
+        rho = torch.tensor(wl.rho.ravel(), device="cuda")
+        T = torch.full((n,), wl.T_bc, dtype=torch.float64, device="cuda")
+        q = torch.empty(n, dtype=torch.float64, device="cuda")
+        S = torch.empty_like(q)
+        ctx.raytrace(rho, T, q, S)
+        ctx.temperature(torch.full((n,), sy.A_RAD * wl.T_bc ** 4, dtype=torch.float64, device="cuda"), S, T)
+        ctx.raytrace(rho, T, q, S)
+        En = torch.empty_like(q)
+        ctx.energy(T, S, En)
+        ctx.assemble(rho, T, En, q)
+        return En
+
+    ds = rt.Dataset(ctx, 8 * n_fields)
+    for wl in wls:
+        ds.add(system(wl), [0, 10, 40, 150])
+    net = rt.Net(seed=seed)
+    st0 = net.train(ctx, ds, epochs=epochs, lr=1e-3, seed=1, loss=rt.LOSS_RESIDUAL)
+    for wl in wls:
+        ds.add_learned(net, system(wl), [1, 3, 8, 20])
+    st1 = net.train(ctx, ds, epochs=max(1, epochs // 2), lr=5e-4, seed=2, loss=rt.LOSS_RESIDUAL)
+    torch.cuda.synchronize()
+    info = {"fields": n_fields, "grid": "128x64x64", "pairs": len(ds), "steps": st0["steps"] + st1["steps"],
+            "loss": "residual", "loss_first_epoch": st0["loss_first_epoch"], "loss_last_epoch": st1["loss_last_epoch"],
+            "train_s": time.perf_counter() - t0}
+    del ds, ctx
+    torch.cuda.empty_cache()
+    return net, info
+
+
+def unet_forward_ms(ctx, net, torch, reps=3):
+    """Average duration of one network application on the context's grid (HIP events on
+    the stream the kernels run on)."""
+    n = ctx.n
+    X = (torch.randn(n * 16, device="cuda") * 0.5).to(torch.bfloat16)
+    z = torch.empty(n, dtype=torch.float32, device="cuda")
+    net.forward(ctx, X, z)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        net.forward(ctx, X, z)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del X, z
+    return ms
+
+
+def run_mode(ctx, rt, torch, rho, T0, mode, steps, warmup, tol, inner_tol, max_iter, net=None, budget=0):
+    n = ctx.n
+    opts = mode_opts(rt, mode, tol, max_iter, inner_tol, net, budget)
     T = T0.clone()
     E = torch.empty(n, dtype=torch.float64, device="cuda")
     f = torch.empty(4 * n, dtype=torch.float64, device="cuda")
@@ -66,14 +140,14 @@ def run_mode(ctx, rt, torch, rho, T0, mode, steps, warmup, tol, inner_tol, max_i
         stats.append(st)
         log(f"[{mode}] step {k}: total {st['ms_total']:.1f} ms, raytrace {st['ms_raytrace']:.2f} ms, "
             f"solve {st['solve']['ms']:.1f} ms ({st['solve']['iters']} it, {st['solve']['outer_iters']} outer, "
+            f"{st['solve']['precond_applies']} network applications, fallback {st['solve']['fallback']}, "
             f"relres {st['solve']['relres']:.2e}), dir {st['solve']['ms_dir']*1e3:.1f} us")
     return dict(wall_s=wall, stats=stats, T=T, E=E)
 
 
-def run_successive(ctx, rt, torch, rho, T0, mode, nsteps, tol, inner_tol, max_iter):
+def run_successive(ctx, rt, torch, rho, T0, mode, nsteps, tol, inner_tol, max_iter, net=None, budget=0):
     """nsteps steps carrying the temperature over; per-step solve statistics."""
-    m = {"fp64": rt.MODE_FP64, "mixed": rt.MODE_MIXED}[mode]
-    opts = rt.solve_opts(m, tol=tol, max_iter=max_iter, check_every=32, inner_tol=inner_tol)
+    opts = mode_opts(rt, mode, tol, max_iter, inner_tol, net, budget)
     T = T0.clone()
     E = torch.empty(ctx.n, dtype=torch.float64, device="cuda")
     out = []
@@ -127,7 +201,12 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="clumpy-512x256x512-nu64")
-    ap.add_argument("--modes", default="mixed,fp64", help="comma list; the first is the headline")
+    ap.add_argument("--modes", default="mixed,fp64,learned", help="comma list; the first is the headline")
+    ap.add_argument("--net", default="", help="load the network from this file instead of training it")
+    ap.add_argument("--train-fields", type=int, default=24)
+    ap.add_argument("--train-epochs", type=int, default=6)
+    ap.add_argument("--learned-budget", type=int, default=50,
+                    help="network applications before the learned solve hands over to float64 CG")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=200000)
@@ -174,10 +253,19 @@ def main():
         log(f"calibration copy of {args.calib_copy_mib} MiB done")
 
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
+    net, train_info = None, None
+    if "learned" in modes:
+        if args.net:
+            net = rt.Net(seed=1)
+            net.load(args.net)
+            train_info = {"loaded": args.net}
+        else:
+            net, train_info = train_network(rt, torch, sy, args.train_fields, args.train_epochs)
+        log(f"network: {train_info}")
     results = {}
     for mode in modes:
         results[mode] = run_mode(ctx, rt, torch, rho, T0, mode, args.steps, args.warmup, args.tol,
-                                 args.inner_tol, args.max_iter)
+                                 args.inner_tol, args.max_iter, net, args.learned_budget)
 
     head = modes[0]
     R = results[head]
@@ -200,7 +288,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "mixed": "f32+f64"}[head],
+        "dtype": {"fp64": "f64", "mixed": "f32+f64", "learned": "bf16+f32+f64"}[head],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {wl.grid.shape[0]}x{wl.grid.shape[1]}x{wl.grid.shape[2]} cells, "
                                f"{c['n_nu']} bins, tau550={wl.tau550:g}, clumps seed {c['seeds'][-1]}",
@@ -218,12 +306,25 @@ def main():
         Rm = results[mode]
         out[f"{mode}_solve_s_per_step"] = statistics.median([s["solve"]["ms"] / 1e3 for s in Rm["stats"]])
         out[f"{mode}_iters_per_step"] = statistics.median([s["solve"]["iters"] for s in Rm["stats"]])
-    if len(modes) > 1:
-        Ta, Tb = results[modes[0]]["T"], results[modes[-1]]["T"]
-        out["T_rel_diff_vs_" + modes[-1]] = float(((Ta - Tb).abs() / Tb).max())
+    if "learned" in modes:
+        Rl = results["learned"]["stats"][-1]["solve"]
+        fwd_ms = unet_forward_ms(ctx, net, torch)
+        tflops = UNET_FLOP_PER_CELL * n / (fwd_ms / 1e3) / 1e12
+        out["learned"] = {"network_applications": Rl["precond_applies"], "fallback": Rl["fallback"],
+                          "total_iters": Rl["iters"], "budget": args.learned_budget, "training": train_info,
+                          "unet_forward_ms": fwd_ms,
+                          "unet_roofline": {"kernel": "U-Net forward (k_conv_fwd and pooling, whole network)",
+                                            "bound": "mfma", "achieved": tflops, "peak": PEAK_BF16_TFLOPS,
+                                            "unit": "TFLOP/s", "frac": tflops / PEAK_BF16_TFLOPS,
+                                            "flop_per_cell": UNET_FLOP_PER_CELL, "cells": n}}
+    if "fp64" in modes:
+        Tf = results["fp64"]["T"]
+        for mode in modes:
+            if mode != "fp64":
+                out[f"T_rel_diff_{mode}_vs_fp64"] = float(((results[mode]["T"] - Tf).abs() / Tf).max())
     if args.successive > 0:
         out["successive_steps"] = run_successive(ctx, rt, torch, rho, T0, head, args.successive, args.tol,
-                                                 args.inner_tol, args.max_iter)
+                                                 args.inner_tol, args.max_iter, net, args.learned_budget)
     if not args.no_cpu_baseline:
         fp64_iters = out.get("fp64_iters_per_step", out["solve_iters_per_step"])
         t = time.perf_counter()
