@@ -1,0 +1,191 @@
+"""Parity at the full 512x256x512-cell, 64-bin workload (tau550 = 100, clumps seed 5000)
+in the launch configuration the benchmark times, on sampled outputs that the oracle
+computes one by one:
+
+* the ray trace of a sample of whole radial columns (the oracle on a grid of that one
+  column: a column's optical depths, absorption and S depend only on its own cells);
+* E^n and the Newton temperature at sampled cells (both act cell by cell);
+* the assembled operator (face weights w, Jacobi scale s, scaled rhs and off-diagonals)
+  and the radiative force at sampled cells, from the oracle on the (up to) 5x5x5 block
+  of cells around each sample with the global faces: every quantity of a cell depends
+  only on cells at most two faces away and on the global boundary treatment, which the
+  block reproduces (a block that touches r_in, r_out or a pole has that boundary);
+* the float64 solve through its true residual, recomputed with float64 arithmetic
+  outside the solver.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1001_3301_amd import synth as sy
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+A = sy.A_RAD
+CONFIG = "clumpy-512x256x512-nu64"
+
+
+def _rel_each(got, ref):
+    return np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def fullsize():
+    from paper_1001_3301_amd import rt
+    c = sy.CONFIGS[CONFIG]
+    wl = sy.make_workload(CONFIG, c["nr"], c["nt"], c["nph"], c["n_nu"], c["taus"][-1], c["seeds"][-1])
+    ctx = rt.Context.from_workload(wl)
+    n = ctx.n
+    rho = torch.tensor(wl.rho.ravel(), device="cuda")
+    # the benchmark's prepared state: irradiation at T_bc, then Eq. 16 with E = a T_bc^4
+    T0 = torch.full((n,), wl.T_bc, dtype=torch.float64, device="cuda")
+    q = torch.empty(n, dtype=torch.float64, device="cuda")
+    S = torch.empty_like(q)
+    ctx.raytrace(rho, T0, q, S)
+    ctx.temperature(torch.full((n,), A * wl.T_bc ** 4, dtype=torch.float64, device="cuda"), S, T0)
+    # one radiation step, piece by piece
+    ctx.raytrace(rho, T0, q, S)
+    En = torch.empty_like(q)
+    ctx.energy(T0, S, En)
+    sysv = ctx.assemble(rho, T0, En, q)
+    sys_t = ctx.system_tensors(sysv)
+    E = En.clone()
+    rc, st = ctx.solve(E, rt.solve_opts(rt.MODE_FP64, tol=1e-8, max_iter=100000))
+    T1 = T0.clone()
+    ctx.temperature(E, S, T1)
+    f = torch.empty(4 * n, dtype=torch.float64, device="cuda")
+    ctx.force(E, q, f)
+    torch.cuda.synchronize()
+    fields = dict(rho=rho, T0=T0, q=q, S=S, En=En, E=E, T1=T1, f=f.view(4, n), **sys_t)
+    return wl, ctx, fields, st
+
+
+def _samples(shape, seed, count):
+    nr, nt, npp = shape
+    g = np.random.Generator(np.random.PCG64(seed))
+    pts = [(0, 0, 0), (nr - 1, nt - 1, npp - 1), (0, nt // 2, npp // 3), (nr - 1, 0, 5), (nr // 2, nt - 1, 0)]
+    while len(pts) < count:
+        pts.append((int(g.integers(nr)), int(g.integers(nt)), int(g.integers(npp))))
+    return pts
+
+
+def _cell(shape, i, j, k):
+    nr, nt, _ = shape
+    return i + nr * (j + nt * k)
+
+
+def test_fullsize_raytrace_columns(fullsize):
+    wl, ctx, F, st = fullsize
+    nr, nt, npp = wl.grid.shape
+    g = wl.grid
+    rho, T, q, S = (F[k].view(npp, nt, nr) for k in ("rho", "T0", "q", "S"))
+    op = wl.opacity
+    F0 = oracle.star_bins(wl.T_star, op.nu)
+    for (_, j, k) in _samples(wl.grid.shape, 51, 24):
+        P = oracle.Problem(g.r_face, g.th_face[j:j + 2], g.ph_face[k:k + 2], op.T, op.kappa, op.kappa_P,
+                           op.kappa_R, R_star=wl.R_star, F0=F0, T_star=wl.T_star, dt=wl.dt, c_V=wl.c_V,
+                           T_bc=wl.T_bc, E_floor=wl.E_floor)
+        q0, S0, _ = P.raytrace(rho[k, j].cpu().numpy(), T[k, j].cpu().numpy(), want_faces=False)
+        assert _rel_each(q[k, j].cpu().numpy(), q0) < 1e-11, (j, k)
+        assert _rel_each(S[k, j].cpu().numpy(), S0) < 1e-11, (j, k)
+
+
+def test_fullsize_energy_and_newton_cells(fullsize):
+    wl, ctx, F, st = fullsize
+    shape = wl.grid.shape
+    idx = torch.tensor([_cell(shape, *p) for p in _samples(shape, 52, 256)], device="cuda")
+    Ts, Ss, Ens, Es, T1s = (F[k][idx].cpu().numpy() for k in ("T0", "S", "En", "E", "T1"))
+    m = len(Ts)
+    op = wl.opacity
+    # a row of m independent cells: both functions act cell by cell
+    P = oracle.Problem(np.linspace(1.0, 2.0, m + 1), [0.0, 1.0], [0.0, 1.0], op.T, op.kappa, op.kappa_P,
+                       op.kappa_R, dt=wl.dt, c_V=wl.c_V, T_bc=wl.T_bc, E_floor=wl.E_floor)
+    # in the prepared state T0 solves a T^4 = a T_bc^4 + S / kappa_P(T), so E^n = a T0^4 -
+    # S / kappa_P(T0) cancels terms up to 1e7 times larger than itself: the bound is a
+    # few rounding units of the terms, not of the result
+    terms = A * Ts ** 4
+    assert np.all(np.abs(Ens - P.energy(Ts, Ss)) <= 1e-14 * terms + 1e-12 * np.abs(Ens))
+    assert _rel_each(T1s, P.newton(Es, Ss, Ts)) < 1e-12
+
+
+RB = 2  # block radius: a cell's off-diagonals use its neighbours' Jacobi scales, whose
+        # diagonals involve the neighbours' own faces
+
+
+def _block(shape, i, j, k):
+    nr, nt, npp = shape
+    ir = list(range(max(0, i - RB), min(nr, i + RB + 1)))
+    jr = list(range(max(0, j - RB), min(nt, j + RB + 1)))
+    kr = [(k + d) % npp for d in range(-RB, RB + 1)]
+    return ir, jr, kr
+
+
+def _phi_faces(ph, k, npp):
+    """Faces of the phi cells k - RB .. k + RB continued across the periodic seam."""
+    d = ph[1] - ph[0]
+    out = []
+    for m in range(k - RB, k + RB + 2):
+        out.append(ph[m] if 0 <= m <= npp else ph[m % npp] + (m // npp) * npp * d)
+    return np.array(out)
+
+
+def test_fullsize_assembly_and_force_cells(fullsize):
+    wl, ctx, F, st = fullsize
+    shape = wl.grid.shape
+    nr, nt, npp = shape
+    n = nr * nt * npp
+    g, op = wl.grid, wl.opacity
+    w3 = F["w"].view(3, n)
+    a3 = F["ahat"].view(3, n)
+    for (i, j, k) in _samples(shape, 53, 48):
+        ir, jr, kr = _block(shape, i, j, k)
+        cells = [_cell(shape, a, b, c) for c in kr for b in jr for a in ir]  # r fastest
+        idx = torch.tensor(cells, device="cuda")
+        rho, T, En, q, E = (F[key][idx].cpu().numpy() for key in ("rho", "T0", "En", "q", "E"))
+        phf = _phi_faces(g.ph_face, k, npp)
+        P = oracle.Problem(g.r_face[ir[0]:ir[-1] + 2], g.th_face[jr[0]:jr[-1] + 2], phf, op.T, op.kappa,
+                           op.kappa_P, op.kappa_R, dt=wl.dt, c_V=wl.c_V, T_bc=wl.T_bc, E_floor=wl.E_floor)
+        ref = P.assemble(rho, T, En, q)
+        mb = P.n
+        cen = ir.index(i) + len(ir) * (jr.index(j) + len(jr) * RB)
+        c = _cell(shape, i, j, k)
+        got_w = w3[:, c].cpu().numpy()
+        ref_w = ref["w"].reshape(3, mb)[:, cen]
+        # outward faces that leave the block only where the global grid ends
+        assert np.max(np.abs(got_w - ref_w)) <= 1e-12 * max(np.max(np.abs(ref_w)), 1e-300), (i, j, k)
+        assert abs(F["s"][c].item() - ref["s"][cen]) <= 1e-12 * abs(ref["s"][cen]), (i, j, k)
+        assert abs(F["bhat"][c].item() - ref["bhat"][cen]) <= 1e-12 * abs(ref["bhat"][cen]), (i, j, k)
+        ref_a = ref["ahat"].reshape(3, mb)[:, cen]
+        assert np.max(np.abs(a3[:, c].cpu().numpy() - ref_a)) <= 1e-12 * max(np.max(np.abs(ref_a)), 1e-300)
+        # radiative force of the cell from the solved E on the block
+        fr = P.force(rho, T, ref["w"], E, q).reshape(4, mb)[:, cen]
+        fg = F["f"][:, c].cpu().numpy()
+        assert abs(fg[0] - fr[0]) <= 1e-11 * abs(fr[0]) + 1e-300, (i, j, k)
+        mag = np.sqrt(fr[1] ** 2 + fr[2] ** 2 + fr[3] ** 2) + 1e-300
+        assert np.max(np.abs(fg[1:] - fr[1:])) <= 1e-10 * mag, (i, j, k)
+
+
+def test_fullsize_solve_true_residual(fullsize):
+    wl, ctx, F, st = fullsize
+    assert st["relres"] <= 1e-8
+    y = F["E"] / F["s"]
+    Ay = torch.empty_like(y)
+    ctx.spmv(y, Ay)  # float64 operator product (its parity is tested at small sizes)
+    r = F["bhat"] - Ay
+    relres = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(F["bhat"]))
+    assert relres <= 1.01e-8, relres
+    assert torch.isfinite(F["T1"]).all() and (F["T1"] > 0).all()
+
+
+def test_fullsize_mixed_solve_temperature(fullsize):
+    """The float32-inner / float64-refined solve at full size: its temperature against
+    the float64 solve's (both to the relative residual 1e-8)."""
+    from paper_1001_3301_amd import rt
+    wl, ctx, F, st = fullsize
+    E = F["En"].clone()
+    rc, sm = ctx.solve(E, rt.solve_opts(rt.MODE_MIXED, tol=1e-8, max_iter=100000))
+    assert sm["relres"] <= 1e-8
+    T = F["T0"].clone()
+    ctx.temperature(E, F["S"], T)
+    assert float(((T - F["T1"]).abs() / F["T1"]).max()) <= 1e-6
