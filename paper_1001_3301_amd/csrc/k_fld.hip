@@ -143,20 +143,40 @@ __global__ __launch_bounds__(kTB) void k_asm_scale(Dims d, const double *__restr
     ahat32[2 * d.n + c] = (float)ap;
 }
 
-// g(T) = a T^4 - E - S / kappa_P(T), the residual of Eq. (16), and g'(T).
-__device__ __forceinline__ double g16(const Opac &op, double E, double S, double t, double &dg)
+// g(T) = a T^4 - E - S / kappa_P(T), the residual of Eq. (16), and g'(T); kappa_P
+// interpolated log-log in the table interval k (the caller guarantees T[k] <= t <
+// T[k+1], or k = -1 / k = nT - 1 for t below / above the table, where kappa_P is the
+// end value).
+__device__ __forceinline__ double g16(const Opac &op, double E, double S, double t, int k, double &dg)
 {
-    double slope;
-    double kp = mean_opacity(op.T, op.lnT, op.kP, op.lnP, op.nT, t, &slope);
+    double kp, slope = 0.0;
+    if (k < 0) kp = op.kP[0];
+    else if (k >= op.nT - 1) kp = op.kP[op.nT - 1];
+    else {
+        const double l0 = op.lnT[k], l1 = op.lnT[k + 1];
+        const double lw = (log(t) - l0) / (l1 - l0);
+        slope = (op.lnP[k + 1] - op.lnP[k]) / (l1 - l0);
+        kp = exp((1.0 - lw) * op.lnP[k] + lw * op.lnP[k + 1]);
+    }
     dg = 4.0 * kA * t * t * t + (S / kp) * slope / t;
     return kA * t * t * t * t - E - S / kp;
 }
 
+// Table interval of t for g16.
+__device__ __forceinline__ int p_interval(const Opac &op, double t)
+{
+    if (t < op.T[0]) return -1;
+    if (t >= op.T[op.nT - 1]) return op.nT - 1;
+    return find_node(op.T, op.nT, t);
+}
+
 // Newton-Raphson on Eq. (16) per cell, safeguarded by a bracket that isolates the
 // smallest root: lo = (E/a)^(1/4) (g <= 0 there), then the table nodes above lo are
-// walked until g >= 0 (past the table kappa_P is constant, so doubling ends the walk).
-// Iterates from T^n; a step that leaves the bracket is replaced by bisection; stops
-// when the Newton step is below 1e-14 T or after 50 iterations.
+// walked until g >= 0 (at a node kappa_P is the tabulated value; past the table it is
+// constant, so doubling ends the walk).  The smallest root then lies in one table
+// interval (or beyond the table), so every Newton step evaluates kappa_P in a known
+// interval.  Iterates from T^n; a step that leaves the bracket is replaced by
+// bisection; stops when the Newton step is below 1e-14 T or after 50 iterations.
 __global__ __launch_bounds__(kTB) void k_newton(long n, Opac op, const double *__restrict__ E,
                                                 const double *__restrict__ S, double *__restrict__ T)
 {
@@ -168,18 +188,22 @@ __global__ __launch_bounds__(kTB) void k_newton(long n, Opac op, const double *_
     for (int m = m0; m < op.nT; m++) {
         double tm = op.T[m];
         if (tm <= lo) continue;
-        if (g16(op, e, sv, tm, dg) >= 0.0) { hi = tm; break; }
+        if (kA * tm * tm * tm * tm - e - sv / op.kP[m] >= 0.0) { hi = tm; break; }
         lo = tm;
     }
     if (hi < 0.0) {
         hi = 2.0 * lo;
-        for (int m = 0; m < 200 && g16(op, e, sv, hi, dg) < 0.0; m++) { lo = hi; hi = 2.0 * hi; }
+        for (int m = 0; m < 200 && g16(op, e, sv, hi, op.nT - 1, dg) < 0.0; m++) { lo = hi; hi = 2.0 * hi; }
     }
+    // the interval of the bracket: lo and hi are adjacent walk points, so [lo, hi) lies
+    // in the table interval of lo (or beyond the table)
+    const int k = p_interval(op, lo);
     double t = T[c];
     if (!(t >= lo)) t = lo;
     if (t > hi) t = hi;
     for (int it = 0; it < 50; it++) {
-        double gv = g16(op, e, sv, t, dg);
+        const int kt = (t >= hi && k >= 0 && k < op.nT - 1) ? p_interval(op, t) : k;
+        double gv = g16(op, e, sv, t, kt, dg);
         if (gv == 0.0) break;
         if (gv < 0.0) lo = t; else hi = t;
         double step = gv / dg;

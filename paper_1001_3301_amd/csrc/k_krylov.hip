@@ -24,7 +24,10 @@
 
 namespace rt {
 
-constexpr int kKB = 256;
+#ifndef RTMI_KRYLOV_BLOCK
+#define RTMI_KRYLOV_BLOCK 256
+#endif
+constexpr int kKB = RTMI_KRYLOV_BLOCK;  // threads per block of the Krylov kernels
 
 // Index of this block's partial sum (any fixed one-to-one map works).
 __device__ __forceinline__ long logical_block(int nblk)
