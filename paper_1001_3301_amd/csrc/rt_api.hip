@@ -511,7 +511,8 @@ rt_status norm_b(rt_ctx *ctx, double &bb)
     return RT_OK;
 }
 
-// Plain float64 CG on A^ (the method; also the fallback and the judge of the others).
+// Plain float64 CG on A^ (the method; also the fallback of the other modes and the
+// reference they are checked against).
 rt_status solve_fp64(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb)
 {
     const Dims &d = ctx->d;
