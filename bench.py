@@ -203,6 +203,7 @@ def main():
     ap.add_argument("--config", default="clumpy-512x256x512-nu64")
     ap.add_argument("--modes", default="mixed,fp64,learned", help="comma list; the first is the headline")
     ap.add_argument("--net", default="", help="load the network from this file instead of training it")
+    ap.add_argument("--save-net", default="", help="save the trained network to this file")
     ap.add_argument("--train-fields", type=int, default=24)
     ap.add_argument("--train-epochs", type=int, default=6)
     ap.add_argument("--learned-budget", type=int, default=50,
@@ -261,6 +262,8 @@ def main():
             train_info = {"loaded": args.net}
         else:
             net, train_info = train_network(rt, torch, sy, args.train_fields, args.train_epochs)
+            if args.save_net:
+                net.save(args.save_net)
         log(f"network: {train_info}")
     results = {}
     for mode in modes:
@@ -275,8 +278,8 @@ def main():
     samples = sum(s["solve"]["kernel_samples"] for s in R["stats"])
     ms_dir = sum(s["solve"]["ms_dir"] * s["solve"]["kernel_samples"] for s in R["stats"]) / max(samples, 1)
     ms_upd = sum(s["solve"]["ms_upd"] * s["solve"]["kernel_samples"] for s in R["stats"]) / max(samples, 1)
-    bpc = BYTES_PER_CELL[head]
-    achieved = bpc["dir"] * n / (ms_dir / 1e3) / 1e9 if ms_dir > 0 else 0.0
+    bpc = BYTES_PER_CELL.get(head)
+    achieved = bpc["dir"] * n / (ms_dir / 1e3) / 1e9 if (bpc and ms_dir > 0) else 0.0
     out = {
         "metric": METRIC,
         "value": value,
@@ -297,11 +300,12 @@ def main():
         "raytrace_gcell_nu_per_s": statistics.median([n * c["n_nu"] / (x / 1e3) / 1e9 for x in rt_ms]),
         "solve_iters_per_step": statistics.median([s["solve"]["iters"] for s in R["stats"]]),
         "kernel_ms": {"dir": ms_dir, "upd": ms_upd, "samples": samples},
-        "roofline": {"kernel": KERNEL_NAMES[head], "bound": "hbm", "achieved": achieved,
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": MEASURED_TRAFFIC.get((head, args.config)), "bytes_per_cell": bpc["dir"],
-                     "cells_per_launch": n},
     }
+    if bpc:
+        out["roofline"] = {"kernel": KERNEL_NAMES[head], "bound": "hbm", "achieved": achieved,
+                           "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                           "traffic": MEASURED_TRAFFIC.get((head, args.config)), "bytes_per_cell": bpc["dir"],
+                           "cells_per_launch": n}
     for mode in modes[1:]:
         Rm = results[mode]
         out[f"{mode}_solve_s_per_step"] = statistics.median([s["solve"]["ms"] / 1e3 for s in Rm["stats"]])
@@ -317,6 +321,8 @@ def main():
                                             "bound": "mfma", "achieved": tflops, "peak": PEAK_BF16_TFLOPS,
                                             "unit": "TFLOP/s", "frac": tflops / PEAK_BF16_TFLOPS,
                                             "flop_per_cell": UNET_FLOP_PER_CELL, "cells": n}}
+        if head == "learned":  # the network is the part of this mode the GPU is asked to run fast
+            out["roofline"] = dict(out["learned"]["unet_roofline"], traffic=None)
     if "fp64" in modes:
         Tf = results["fp64"]["T"]
         for mode in modes:

@@ -149,8 +149,8 @@ __device__ __forceinline__ unsigned pack_bf16(float a, float b)
 // Blocks are persistent: gridDim.x is a multiple of 8 and block b serves the tiles of
 // one eighth of the tile sequence (XCD b % 8 under round-robin dispatch, so the
 // concurrently resident blocks of an XCD work on neighbouring tiles and share halos
-// in that XCD's L2), stepping by gridDim.x / 8; a block whose input is a single slice
-// loads its weights once.
+// in that XCD's L2; theta fastest, then phi, then r), stepping by gridDim.x / 8; a block
+// whose input is a single slice loads its weights once.
 template <int NT, int TJ, int TK, int SIGN, class Load, class Store>
 __device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__restrict__ w, Load load, Store store)
 {
@@ -162,8 +162,8 @@ __device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__r
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int cout = NT * 16;
     const int nslice = cin / 16;
-    const int ntr = (L.nr + kTR - 1) / kTR, ntj = (L.nt + TJ - 1) / TJ;
-    const long ntiles = (long)ntr * ntj * ((L.np + TK - 1) / TK);
+    const int ntr = (L.nr + kTR - 1) / kTR, ntj = (L.nt + TJ - 1) / TJ, ntk = (L.np + TK - 1) / TK;
+    const long ntiles = (long)ntr * ntj * ntk;
     const int per = gridDim.x >> 3, xcd = blockIdx.x & 7;
     const long t_end = ntiles * (xcd + 1) / 8;
     long tile = ntiles * xcd / 8 + (blockIdx.x >> 3);
@@ -187,7 +187,9 @@ __device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__r
     for (;;) {
         // global loads of the item (tile, slice s), all issued before the LDS stores;
         // cells outside the grid read cell 0 and are replaced by zeros
-        const int tr = (int)(tile % ntr), tj = (int)((tile / ntr) % ntj), tk = (int)(tile / ((long)ntr * ntj));
+        // tile order: theta fastest, then phi, then r, so the blocks resident together
+        // share their theta halos and the next wave of blocks finds its phi halo plane in L2
+        const int tj = (int)(tile % ntj), tk = (int)((tile / ntj) % ntk), tr = (int)(tile / ((long)ntj * ntk));
         const int r0 = tr * kTR, j0 = tj * TJ, k0 = tk * TK;
         uint4 v[NL];
 #pragma unroll
