@@ -17,6 +17,16 @@ namespace rt {
 
 constexpr int kChunk = 4;          // cells per transpose
 constexpr int kWavesPerBlock = 16; // columns per block
+constexpr int kSlots = 8;          // cells per lane in one segment
+constexpr int kSeg = 64 * kSlots;  // cells per segment of a column
+
+// Per-cell quantities of a segment, held by the lane that owns the cell (cell
+// seg0 + lane + 64 s in slot s) and broadcast with readlane when the wavefront reaches
+// it: table node and weight, rho dr (floored).
+struct CellSlot {
+    int k;
+    double w, rdr;
+};
 
 __global__ __launch_bounds__(1024) void k_raytrace(
     int nr, long ncol, int nnu, int nT,
@@ -29,11 +39,19 @@ __global__ __launch_bounds__(1024) void k_raytrace(
     extern __shared__ double lds[];
     double *tab = lds;                       // [nT][nnu]
     double *Tt = tab + nT * nnu;             // [nT]
+    double *g_dr = Tt + nT;                  // [nr] dr
+    double *g_q = g_dr + nr;                 // [nr] 3 / shell volume
+    double *g_f = g_q + nr;                  // [nr] 1 / r_f^2 of the outer face
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double *red = Tt + nT + wave * (2 * kChunk * 64);  // [2][kChunk][64] for this wave
+    double *red = g_f + nr + wave * (2 * kChunk * 64);  // [2][kChunk][64] for this wave
 
     for (int t = threadIdx.x; t < nT * nnu; t += blockDim.x) tab[t] = kap_g[t];
     for (int t = threadIdx.x; t < nT; t += blockDim.x) Tt[t] = Ttab[t];
+    for (int t = threadIdx.x; t < nr; t += blockDim.x) {
+        g_dr[t] = dr[t];
+        g_q[t] = 3.0 / shell[t];
+        g_f[t] = 1.0 / rf2[t + 1];
+    }
     __syncthreads();
 
     const long col = (long)blockIdx.x * kWavesPerBlock + wave;
@@ -50,61 +68,73 @@ __global__ __launch_bounds__(1024) void k_raytrace(
         if (lane == 0 && Fface) Fface[fbase] = v / rf2[0];
     }
 
-    for (int i0 = 0; i0 < nr; i0 += kChunk) {
-        // table coordinates and rho*dr of the chunk's cells, one lane per cell
-        int kk = 0;
-        double ww = 0.0, rdr = 1e-250, rh = 0.0;
-        if (lane < kChunk && i0 + lane < nr) {
-            long c = cbase + i0 + lane;
-            double t = T[c];
-            rh = rho[c];
-            lin_node(Tt, nT, t, kk, ww);
-            double v = rh * dr[i0 + lane];
-            rdr = v > 1e-250 ? v : 1e-250;  // keeps S = q / (rho c) finite as rho -> 0
-        }
-        const int ncell = (nr - i0) < kChunk ? (nr - i0) : kChunk;
+    const int s8 = lane >> 3, part = lane & 7;  // reduction roles: sum s8 of 2 kChunk, part of 8
+    for (int seg0 = 0; seg0 < nr; seg0 += kSeg) {
+        // one coalesced batch of loads per segment: slot s holds cell seg0 + lane + 64 s
+        CellSlot cs[kSlots];
 #pragma unroll
-        for (int m = 0; m < kChunk; m++) {
-            if (m < ncell) {
-                int k = __builtin_amdgcn_readlane(kk, m);
-                double w = readlane_d(ww, m);
-                double rd = readlane_d(rdr, m);
-                double a0 = tab[k * nnu + lb], a1 = tab[(k + 1) * nnu + lb];
-                double kap = (1.0 - w) * a0 + w * a1;
-                double e, em;
-                exp_pair(kap * rd, e, em);
-                red[m * 64 + lane] = Phi * em;   // absorbed, before the 3/shell factor
-                Phi = Phi * e;
-                red[(kChunk + m) * 64 + lane] = Phi;  // through the outer face
-            }
+        for (int sl = 0; sl < kSlots; sl++) {
+            const int i = seg0 + lane + 64 * sl;
+            const bool in = i < nr;
+            const int ic = in ? i : nr - 1;
+            const long c = cbase + ic;
+            const double t = T[c], rh = rho[c];
+            lin_node(Tt, nT, t, cs[sl].k, cs[sl].w);
+            const double v = rh * g_dr[ic];
+            cs[sl].rdr = v > 1e-250 ? v : 1e-250;  // keeps S = q / (rho c) finite as rho -> 0
         }
-        wave_sync();
-        // 2*kChunk sums over the 64 lanes: lane -> (sum s, part), 8 values each
-        const int s = lane >> 3, part = lane & 7;
-        double acc = 0.0;
 #pragma unroll
-        for (int t = 0; t < 8; t++) acc += red[s * 64 + part + 8 * t];
-        acc += __shfl_xor(acc, 1);
-        acc += __shfl_xor(acc, 2);
-        acc += __shfl_xor(acc, 4);
-        wave_sync();
-        if (part == 0) {
-            if (s < kChunk) {
-                int i = i0 + s;
-                if (i < nr) {
-                    long c = cbase + i;
-                    double qv = 3.0 * acc / shell[i];
-                    q[c] = qv;
-                    double rdr_c = rho[c] * dr[i];
-                    rdr_c = rdr_c > 1e-250 ? rdr_c : 1e-250;
-                    S[c] = qv * dr[i] / (rdr_c * kC);
+        for (int sl = 0; sl < kSlots; sl++) {
+            const int sbase = seg0 + 64 * sl;
+            if (sbase >= nr) break;
+            for (int l0 = 0; l0 < 64; l0 += kChunk) {
+                const int i0 = sbase + l0;
+                if (i0 >= nr) break;
+                const int ncell = (nr - i0) < kChunk ? (nr - i0) : kChunk;
+#pragma unroll
+                for (int m = 0; m < kChunk; m++) {
+                    if (m < ncell) {
+                        const int k = __builtin_amdgcn_readlane(cs[sl].k, l0 + m);
+                        const double w = readlane_d(cs[sl].w, l0 + m);
+                        const double rd = readlane_d(cs[sl].rdr, l0 + m);
+                        const double a0 = tab[k * nnu + lb], a1 = tab[(k + 1) * nnu + lb];
+                        const double kap = (1.0 - w) * a0 + w * a1;
+                        double e, em;
+                        exp_pair(kap * rd, e, em);
+                        red[m * 64 + lane] = Phi * em;   // absorbed, before the 3/shell factor
+                        Phi = Phi * e;
+                        red[(kChunk + m) * 64 + lane] = Phi;  // through the outer face
+                    }
                 }
-            } else {
-                int i = i0 + (s - kChunk);
-                if (i < nr && Fface) Fface[fbase + i + 1] = acc / rf2[i + 1];
+                wave_sync();
+                // 2*kChunk sums over the 64 lanes: lane -> (sum s8, part), 8 values each
+                double acc = 0.0;
+#pragma unroll
+                for (int t = 0; t < 8; t++) acc += red[s8 * 64 + part + 8 * t];
+                acc += __shfl_xor(acc, 1);
+                acc += __shfl_xor(acc, 2);
+                acc += __shfl_xor(acc, 4);
+                // rho dr of the chunk's cells, uniform per cell
+                double rd4[kChunk];
+#pragma unroll
+                for (int m = 0; m < kChunk; m++) rd4[m] = readlane_d(cs[sl].rdr, l0 + m);
+                wave_sync();
+                if (part == 0) {
+                    const int mm = s8 < kChunk ? s8 : s8 - kChunk;
+                    const int i = i0 + mm;
+                    if (i < nr) {
+                        if (s8 < kChunk) {
+                            const double rdm = mm == 0 ? rd4[0] : (mm == 1 ? rd4[1] : (mm == 2 ? rd4[2] : rd4[3]));
+                            const double qv = g_q[i] * acc;
+                            q[cbase + i] = qv;
+                            S[cbase + i] = qv * g_dr[i] / (rdm * kC);
+                        } else if (Fface) {
+                            Fface[fbase + i + 1] = acc * g_f[i];
+                        }
+                    }
+                }
             }
         }
-        (void)rh;
     }
 }
 
@@ -114,7 +144,7 @@ void launch_raytrace(const Dims &d, const Opac &op, const Geo &g, const double *
 {
     long ncol = (long)d.nt * d.np;
     long nblk = (ncol + kWavesPerBlock - 1) / kWavesPerBlock;
-    size_t lds = sizeof(double) * ((size_t)op.nT * op.nnu + op.nT + (size_t)kWavesPerBlock * 2 * kChunk * 64);
+    size_t lds = raytrace_lds_bytes(op.nT, op.nnu, d.nr);
     hipLaunchKernelGGL(k_raytrace, dim3((unsigned)nblk), dim3(64 * kWavesPerBlock), lds, st,
                        d.nr, ncol, op.nnu, op.nT, rho, T, op.T, op.kap, F0, R2, g.rf2, g.dr, g.shell,
                        q, S, Fface);
@@ -125,9 +155,9 @@ void raytrace_prepare(size_t lds_bytes)
     (void)hipFuncSetAttribute((const void *)k_raytrace, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
 
-size_t raytrace_lds_bytes(int nT, int nnu)
+size_t raytrace_lds_bytes(int nT, int nnu, int nr)
 {
-    return sizeof(double) * ((size_t)nT * nnu + nT + (size_t)kWavesPerBlock * 2 * kChunk * 64);
+    return sizeof(double) * ((size_t)nT * nnu + nT + 3 * (size_t)nr + (size_t)kWavesPerBlock * 2 * kChunk * 64);
 }
 
 }  // namespace rt
