@@ -306,6 +306,11 @@ def main():
                            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                            "traffic": MEASURED_TRAFFIC.get((head, args.config)), "bytes_per_cell": bpc["dir"],
                            "cells_per_launch": n}
+        if ms_dir > 0 and ms_upd > 0:
+            # one whole Krylov iteration (both kernels): its algorithmic bytes over the two launch times
+            it_gbs = (bpc["dir"] + bpc["upd"]) * n / ((ms_dir + ms_upd) / 1e3) / 1e9
+            out["krylov_iteration"] = {"achieved": it_gbs, "unit": "GB/s", "frac": it_gbs / PEAK_HBM_GBS,
+                                       "bytes_per_cell": bpc["dir"] + bpc["upd"]}
     for mode in modes[1:]:
         Rm = results[mode]
         out[f"{mode}_solve_s_per_step"] = statistics.median([s["solve"]["ms"] / 1e3 for s in Rm["stats"]])

@@ -313,7 +313,7 @@ rt_status rt_nn_conv3d_fwd(void *stream, int nr, int nt, int np, const void *x1,
  * (for an upsampled x1, the gradient of the upsampled tensor). */
 rt_status rt_nn_conv3d_bwd_data(void *stream, int nr, int nt, int np, const float *dy, const void *yrelu, int cout,
                                 const void *wt, int c1, float *d1, int c2, float *d2);
-/* Weight and bias gradients (fp32, dw[27][cout][c1+c2], db[cout]); synchronises. */
+/* Weight and bias gradients (fp32, dw[27][cout][c1+c2], db[cout]); cout <= 64; synchronises. */
 rt_status rt_nn_conv3d_bwd_weight(void *stream, int nr, int nt, int np, const float *dy, const void *yrelu, int cout,
                                   const void *x1, int c1, int up1, const void *x2, int c2, float *dw, float *db);
 

@@ -351,71 +351,132 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 
 // -------------------------------------------------------- weight gradient
 
-// Partial dW over one chunk of cells and one tap: part[(chunk * 27 + tap) Cout Cin]
-// = sum_{cells} dYm[cell][co] x[nb(cell, tap)][ci], as MFMA tiles with M = co,
-// N = ci and K = cells (16 per MFMA).  Block: 4 wavefronts sharing the (co, ci) tile
-// pairs; chunk = blockIdx.x, tap = blockIdx.y.
-__global__ __launch_bounds__(kTB) void k_conv_bwd_weight(Lv L, const float *__restrict__ dy, const bf16 *__restrict__ yout,
-                                                         int cout, const bf16 *__restrict__ x1, int c1, int up1,
-                                                         const bf16 *__restrict__ x2, int c2, long chunk,
-                                                         float *__restrict__ part)
+// dW[tap][co][ci] = sum over cells of dYm[cell][co] x[nb(cell, tap)][ci], tiled: a block
+// owns a 16-channel input slice (blockIdx.y) and walks tiles of kTR x 2 x 2 output
+// cells (4 radial rows of 32 cells), blockIdx.x, blockIdx.x + gridDim.x, ...  Per tile
+// it stages in LDS the masked output gradient transposed, dyT[co][cell], and three
+// r-shifted transposed copies of the input slice, xsT[di][phi row][theta row][ci][i]
+// (zero outside r and theta, wrapped in phi), so every MFMA operand is an aligned
+// 16-byte read: v_mfma_f32_16x16x32_bf16 with M = co, N = ci, K = the 32 cells of one
+// radial row; A[co][cells] from dyT, B[cells][ci] from the copy of the tap's radial
+// shift at the tap's theta/phi row.  Wavefront w accumulates taps w, w + 4, ...; the
+// block's partial sums go to part[blockIdx.x][tap][co][ci] (summed in a fixed order
+// afterwards, so the result is deterministic).
+constexpr int kWRowCells = 4 * kTR;          // cells of a tile (2 x 2 rows)
+constexpr int kWLdy = kWRowCells + 8;        // dyT row length (bf16), padded against bank conflicts
+constexpr int kWLx = kTR + 8;                // xsT row length (bf16), padded
+constexpr int kWXRows = 3 * 4 * 4 * 16;      // (di, hk, hj, ci) rows of xsT
+
+template <int NTO>
+constexpr size_t wgrad_lds_bytes() { return ((size_t)NTO * 16 * kWLdy + (size_t)kWXRows * kWLx) * 2; }
+
+template <int NTO>
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_conv_wgrad(
+    Lv L, const float *__restrict__ dy, const bf16 *__restrict__ yout, const bf16 *__restrict__ x1, int c1,
+    int up1, const bf16 *__restrict__ x2, int c2, float *__restrict__ part)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int m = lane & 15, kq = lane >> 4;
-    const int tap = blockIdx.y;
-    const int cin = c1 + c2;
-    const int nco = cout / 16, nci = cin / 16, npair = nco * nci;
-    const long c_begin = (long)blockIdx.x * chunk;
-    const long c_end = c_begin + chunk < L.n ? c_begin + chunk : L.n;
+    extern __shared__ uint4 smem_u4[];
+    bf16 *dyT = reinterpret_cast<bf16 *>(smem_u4);
+    bf16 *xsT = dyT + NTO * 16 * kWLdy;
+    constexpr int cout = NTO * 16;
+    const int cin = c1 + c2, sl = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int cr = L.nr >> 1, ct = L.nt >> 1;
-    float *out = part + ((long)blockIdx.x * 27 + tap) * cout * cin;
-    for (int pr0 = wv; pr0 < npair; pr0 += 4 * 4) {
-        // up to 4 tile pairs per pass per wavefront: pairs pr0, pr0+4, pr0+8, pr0+12
-        float4v acc[4];
+    const int ntr = (L.nr + kTR - 1) / kTR, ntj = (L.nt + 1) / 2, ntk = (L.np + 1) / 2;
+    const long ntiles = (long)ntr * ntj * ntk;
+    float4v acc[7][NTO];
 #pragma unroll
-        for (int q = 0; q < 4; q++) acc[q] = float4v{0.f, 0.f, 0.f, 0.f};
-        for (long cb = c_begin; cb < c_end; cb += 16) {
-            // the four cells of this lane's K slice
-            long cells[4];
-            bool okc[4], okn[4];
-            long e[4], e1[4];
+    for (int q = 0; q < 7; q++)
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                long cc = cb + 4 * kq + q;
-                okc[q] = cc < c_end;
-                cells[q] = okc[q] ? cc : c_begin;
-                int i, j, k, a, b, c;
-                cell_coords(L, cells[q], i, j, k);
-                okn[q] = tap_nb(L, i, j, k, tap, 1, a, b, c) && okc[q];
-                e[q] = okn[q] ? a + (long)L.nr * (b + (long)L.nt * c) : cells[q];
-                e1[q] = up1 ? (okn[q] ? (a >> 1) + (long)cr * ((b >> 1) + (long)ct * (c >> 1)) : 0) : e[q];
+        for (int t = 0; t < NTO; t++) acc[q][t] = float4v{0.f, 0.f, 0.f, 0.f};
+    for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int tj = (int)(tile % ntj), tk = (int)((tile / ntj) % ntk), tr = (int)(tile / ((long)ntj * ntk));
+        const int r0 = tr * kTR, j0 = tj * 2, k0 = tk * 2;
+        __syncthreads();  // the previous tile's MFMAs are done with LDS
+        // dyT[co][row * 32 + i] = dY[cell][co] masked by y > 0 (bf16); i fastest over lanes
+        for (int it = tid; it < kWRowCells * (cout / 8); it += kTB) {
+            const int i = it % kTR, row = (it / kTR) % 4, cg = it / kWRowCells;
+            const int a = r0 + i, b = j0 + (row & 1), c = k0 + (row >> 1);
+            float f[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (a < L.nr && b < L.nt && c < L.np) {
+                const long idx = a + (long)L.nr * (b + (long)L.nt * c);
+                const float4 g0 = *reinterpret_cast<const float4 *>(dy + idx * cout + cg * 8);
+                const float4 g1 = *reinterpret_cast<const float4 *>(dy + idx * cout + cg * 8 + 4);
+                f[0] = g0.x; f[1] = g0.y; f[2] = g0.z; f[3] = g0.w; f[4] = g1.x; f[5] = g1.y; f[6] = g1.z; f[7] = g1.w;
+                if (yout) {
+                    const uint4 u = *reinterpret_cast<const uint4 *>(yout + idx * cout + cg * 8);
+                    const bf16 *h = reinterpret_cast<const bf16 *>(&u);
+#pragma unroll
+                    for (int e = 0; e < 8; e++)
+                        if (!(bf2f(h[e]) > 0.0f)) f[e] = 0.0f;
+                }
             }
 #pragma unroll
-            for (int q4 = 0; q4 < 4; q4++) {
-                const int pr = pr0 + 4 * q4;
-                if (pr >= npair) break;
-                const int ti = pr / nci, tj = pr % nci;  // co tile, ci tile
-                const int co = ti * 16 + m, ci = tj * 16 + m;
-                short4v av, bv;
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    float g = okc[q] ? dy[cells[q] * cout + co] : 0.0f;
-                    if (yout && !(bf2f(yout[cells[q] * cout + co]) > 0.0f)) g = 0.0f;
-                    av[q] = (short)f2bf(g);
-                    bf16 xv = 0;
-                    if (okn[q]) xv = (ci < c1) ? x1[e1[q] * c1 + ci] : x2[e[q] * c2 + (ci - c1)];
-                    bv[q] = (short)xv;
-                }
-                acc[q4] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[q4], 0, 0, 0);
+            for (int e = 0; e < 8; e += 2) {
+                const unsigned pk = pack_bf16(f[e], f[e + 1]);
+                dyT[(cg * 8 + e) * kWLdy + row * kTR + i] = (bf16)(pk & 0xFFFFu);
+                dyT[(cg * 8 + e + 1) * kWLdy + row * kTR + i] = (bf16)(pk >> 16);
             }
         }
+        // xsT[((di * 4 + hk) * 4 + hj) * 16 + ci][i] = x[r0 + i + di - 1][j0 + hj - 1][k0 + hk - 1][slice ci]
+        for (int it = tid; it < 3 * 4 * 4 * kTR * 2; it += kTB) {
+            const int i = it % kTR, h = (it / kTR) & 1, rest = it / (2 * kTR);
+            const int hj = rest % 4, hk = (rest / 4) % 4, di = rest / 16;
+            int a = r0 + i + di - 1, b = j0 + hj - 1, c = k0 + hk - 1;
+            c = (c < 0) ? c + L.np : (c >= L.np ? c - L.np : c);
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if ((unsigned)a < (unsigned)L.nr && (unsigned)b < (unsigned)L.nt && (unsigned)c < (unsigned)L.np) {
+                const int ch = sl * 16 + h * 8;
+                if (ch < c1) {
+                    const long e = up1 ? (a >> 1) + (long)cr * ((b >> 1) + (long)ct * (c >> 1))
+                                       : a + (long)L.nr * (b + (long)L.nt * c);
+                    v = *reinterpret_cast<const uint4 *>(x1 + e * c1 + ch);
+                } else {
+                    const long e = a + (long)L.nr * (b + (long)L.nt * c);
+                    v = *reinterpret_cast<const uint4 *>(x2 + e * c2 + (ch - c1));
+                }
+            }
+            const bf16 *hv = reinterpret_cast<const bf16 *>(&v);
+            bf16 *dst = xsT + (((di * 4 + hk) * 4 + hj) * 16 + h * 8) * kWLx + i;
 #pragma unroll
-        for (int q4 = 0; q4 < 4; q4++) {
-            const int pr = pr0 + 4 * q4;
-            if (pr >= npair) break;
-            const int ti = pr / nci, tj = pr % nci;
+            for (int e = 0; e < 8; e++) dst[e * kWLx] = hv[e];
+        }
+        __syncthreads();
+        // A fragments: co = t * 16 + lane % 16, cells row * 32 + 8 (lane / 16) .. + 7
+        bf16x8 af[NTO][4];
 #pragma unroll
-            for (int r = 0; r < 4; r++) out[(long)(ti * 16 + 4 * kq + r) * cin + tj * 16 + m] = acc[q4][r];
+        for (int t = 0; t < NTO; t++)
+#pragma unroll
+            for (int row = 0; row < 4; row++)
+                af[t][row] = *reinterpret_cast<const bf16x8 *>(dyT + (t * 16 + (lane & 15)) * kWLdy + row * kTR +
+                                                               8 * (lane >> 4));
+#pragma unroll
+        for (int q = 0; q < 7; q++) {
+            const int tap = wv + 4 * q;
+            if (tap < 27) {
+                const int di = tap % 3, dj = (tap / 3) % 3, dk = tap / 9;  // each in 0..2 (offset + 1)
+#pragma unroll
+                for (int row = 0; row < 4; row++) {
+                    const int hj = (row & 1) + dj, hk = (row >> 1) + dk;
+                    const bf16x8 bfr = *reinterpret_cast<const bf16x8 *>(
+                        xsT + (((di * 4 + hk) * 4 + hj) * 16 + (lane & 15)) * kWLx + 8 * (lane >> 4));
+#pragma unroll
+                    for (int t = 0; t < NTO; t++)
+                        acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[t][row], bfr, acc[q][t], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // partial sums of this block: part[blockIdx.x][tap][co][ci]
+#pragma unroll
+    for (int q = 0; q < 7; q++) {
+        const int tap = wv + 4 * q;
+        if (tap < 27) {
+            float *o = part + ((long)blockIdx.x * 27 + tap) * cout * cin + sl * 16 + (lane & 15);
+#pragma unroll
+            for (int t = 0; t < NTO; t++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) o[(long)(t * 16 + 4 * (lane >> 4) + i) * cin] = acc[q][t][i];
         }
     }
 }
@@ -761,17 +822,52 @@ bool launch_conv_bwd_data(const Lv &L, const float *dy, const bf16 *y, int cout,
 
 // Weight and bias gradients of one 3x3x3 layer: dw (27 Cout Cin), db (Cout); part holds
 // ceil(n / 2048) * 27 * Cout * Cin floats.
-void launch_conv_bwd_weight(const Lv &L, const float *dy, const bf16 *y, int cout, const bf16 *x1, int c1, int up1,
+// Blocks per input slice of the weight-gradient kernel (the number of partial sums).
+long wgrad_blocks(const Lv &L)
+{
+    const long ntiles = (long)((L.nr + kTR - 1) / kTR) * ((L.nt + 1) / 2) * ((L.np + 1) / 2);
+    return std::min<long>(256, ntiles);
+}
+
+// Floats of the partial-sum buffer one weight gradient needs (the bias partials fit too).
+long wgrad_part_floats(const Lv &L, int cout, int cin)
+{
+    const long nw = 27L * cout * cin;
+    return std::max<long>(wgrad_blocks(L) * nw, ((L.n + 2047) / 2048) * cout);
+}
+
+template <int NTO>
+void launch_wgrad_t(const Lv &L, const float *dy, const bf16 *y, const bf16 *x1, int c1, int up1, const bf16 *x2,
+                    int c2, float *part, hipStream_t s)
+{
+    constexpr size_t lds = wgrad_lds_bytes<NTO>();
+    static const bool attr = hipFuncSetAttribute((const void *)k_conv_wgrad<NTO>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
+    (void)attr;
+    hipLaunchKernelGGL(k_conv_wgrad<NTO>, dim3((unsigned)wgrad_blocks(L), (unsigned)((c1 + c2) / 16)), dim3(kTB), lds, s,
+                       L, dy, y, x1, c1, up1, x2, c2, part);
+}
+
+// Weight and bias gradients of one 3x3x3 layer: dw (27 Cout Cin), db (Cout); part holds
+// wgrad_part_floats(L, cout, c1 + c2) floats.
+bool launch_conv_bwd_weight(const Lv &L, const float *dy, const bf16 *y, int cout, const bf16 *x1, int c1, int up1,
                             const bf16 *x2, int c2, float *part, float *dw, float *db, hipStream_t s)
 {
+    if ((c1 + c2) % 16 || c1 % 16) return false;
+    switch (cout) {
+    case 16: launch_wgrad_t<1>(L, dy, y, x1, c1, up1, x2, c2, part, s); break;
+    case 32: launch_wgrad_t<2>(L, dy, y, x1, c1, up1, x2, c2, part, s); break;
+    case 48: launch_wgrad_t<3>(L, dy, y, x1, c1, up1, x2, c2, part, s); break;
+    case 64: launch_wgrad_t<4>(L, dy, y, x1, c1, up1, x2, c2, part, s); break;
+    default: return false;
+    }
+    const long nw = 27L * cout * (c1 + c2);
+    hipLaunchKernelGGL(k_sum_parts, dim3(nblk(nw)), dim3(kTB), 0, s, nw, (int)wgrad_blocks(L), part, dw);
     const long chunk = 2048;
     const int nc = (int)((L.n + chunk - 1) / chunk);
-    hipLaunchKernelGGL(k_conv_bwd_weight, dim3(nc, 27), dim3(kTB), 0, s, L, dy, y, cout, x1, c1, up1, x2, c2, chunk,
-                       part);
-    const long nw = 27L * cout * (c1 + c2);
-    hipLaunchKernelGGL(k_sum_parts, dim3(nblk(nw)), dim3(kTB), 0, s, nw, nc, part, dw);
     hipLaunchKernelGGL(k_bias_parts, dim3(nc), dim3(kTB), 0, s, L.n, cout, dy, y, chunk, part);
     hipLaunchKernelGGL(k_sum_parts, dim3(nblk(cout)), dim3(kTB), 0, s, (long)cout, nc, part, db);
+    return true;
 }
 
 void launch_pool(const Lv &Lc, int C, const bf16 *x, bf16 *y, hipStream_t s)

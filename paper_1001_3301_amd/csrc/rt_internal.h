@@ -233,8 +233,9 @@ bool launch_conv_fwd(const Lv &L, const bf16 *x1, int c1, int up1, const bf16 *x
                      const float *b, int cout, int relu, bf16 *y, float *yf, hipStream_t s);
 bool launch_conv_bwd_data(const Lv &L, const float *dy, const bf16 *y, int cout, const bf16 *wt, int c1, float *d1,
                           int c2, float *d2, hipStream_t s);
-void launch_conv_bwd_weight(const Lv &L, const float *dy, const bf16 *y, int cout, const bf16 *x1, int c1, int up1,
+bool launch_conv_bwd_weight(const Lv &L, const float *dy, const bf16 *y, int cout, const bf16 *x1, int c1, int up1,
                             const bf16 *x2, int c2, float *part, float *dw, float *db, hipStream_t s);
+long wgrad_part_floats(const Lv &L, int cout, int cin);
 void launch_pool(const Lv &Lc, int C, const bf16 *x, bf16 *y, hipStream_t s);
 void launch_pool_bwd_add(const Lv &Lf, int C, const float *dyc, float *dxf, hipStream_t s);
 void launch_up_bwd(const Lv &Lc, int C, const float *dyf, float *dxc, hipStream_t s);

@@ -152,10 +152,8 @@ rt_status ensure_ws(rt_net *net, int nr, int nt, int np, bool train)
         net->gz = nalloc<float>(W, n0);
         // partial weight gradients: chunks of 2048 cells x 27 taps x Cout x Cin (max over layers)
         size_t cap = 0;
-        for (int l = 0; l < NL - 1; l++) {
-            long nc = (net->lv[LEVEL[l]].n + 2047) / 2048;
-            cap = std::max(cap, (size_t)(nc * 27 * COUT[l] * CIN[l]));
-        }
+        for (int l = 0; l < NL - 1; l++)
+            cap = std::max(cap, (size_t)nn::wgrad_part_floats(net->lv[LEVEL[l]], COUT[l], CIN[l]));
         cap = std::max(cap, (size_t)((n0 + 2047) / 2048 * 17));
         net->part = nalloc<float>(W, cap);
         net->part_cap = cap;
@@ -182,10 +180,10 @@ bool conv_bwd_data(const Lv &L, const float *dy, const bf16 *y, int cout, const 
     return nn::launch_conv_bwd_data(L, dy, y, cout, wt, c1, d1, c2, d2, s);
 }
 
-void conv_bwd_weight(const Lv &L, const float *dy, const bf16 *y, int cout, const bf16 *x1, int c1, int up1,
+bool conv_bwd_weight(const Lv &L, const float *dy, const bf16 *y, int cout, const bf16 *x1, int c1, int up1,
                      const bf16 *x2, int c2, float *part, float *dw, float *db, hipStream_t s)
 {
-    nn::launch_conv_bwd_weight(L, dy, y, cout, x1, c1, up1, x2, c2, part, dw, db, s);
+    return nn::launch_conv_bwd_weight(L, dy, y, cout, x1, c1, up1, x2, c2, part, dw, db, s);
 }
 
 void pool(const Lv &Lc, int C, const bf16 *x, bf16 *y, hipStream_t s) { nn::launch_pool(Lc, C, x, y, s); }
@@ -487,16 +485,18 @@ rt_status rt_nn_conv3d_bwd_data(void *stream, int nr, int nt, int np, const floa
 rt_status rt_nn_conv3d_bwd_weight(void *stream, int nr, int nt, int np, const float *dy, const void *yrelu, int cout,
                                   const void *x1, int c1, int up1, const void *x2, int c2, float *dw, float *db)
 {
-    if (nr < 1 || nt < 1 || np < 1 || !dy || cout % 16 || cout < 16 || !x1 || c1 % 16 || c2 % 16 || c1 < 16 ||
-        (c2 && !x2) || !dw || !db || (up1 && (nr % 2 || nt % 2 || np % 2)))
+    if (nr < 1 || nt < 1 || np < 1 || !dy || cout % 16 || cout < 16 || cout > 64 || !x1 || c1 % 16 || c2 % 16 ||
+        c1 < 16 || (c2 && !x2) || !dw || !db || (up1 && (nr % 2 || nt % 2 || np % 2)))
         return nfail(nullptr, RT_EINVAL, "rt_nn_conv3d_bwd_weight: bad arguments");
     Lv L{nr, nt, np, (long)nr * nt * np};
-    const long nc = (L.n + 2047) / 2048;
     float *part = nullptr;
-    size_t cap = (size_t)nc * 27 * cout * (c1 + c2);
+    const size_t cap = (size_t)nn::wgrad_part_floats(L, cout, c1 + c2);
     NN_HIP(nullptr, hipMalloc(&part, cap * sizeof(float)));
-    conv_bwd_weight(L, dy, (const bf16 *)yrelu, cout, (const bf16 *)x1, c1, up1, (const bf16 *)x2, c2, part, dw, db,
-                    (hipStream_t)stream);
+    if (!conv_bwd_weight(L, dy, (const bf16 *)yrelu, cout, (const bf16 *)x1, c1, up1, (const bf16 *)x2, c2, part, dw,
+                         db, (hipStream_t)stream)) {
+        (void)hipFree(part);
+        return nfail(nullptr, RT_EINVAL, "rt_nn_conv3d_bwd_weight: unsupported channel counts");
+    }
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
     (void)hipFree(part);
     if (e != hipSuccess) return nfail(nullptr, RT_EDEVICE, hipGetErrorString(e));
