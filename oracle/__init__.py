@@ -66,6 +66,7 @@ def lib():
         L.og_energy.argtypes = [P(_Grid), P(_Opac), P(_Fld), dp, dp, dp]
         L.og_assemble.argtypes = [P(_Grid), P(_Opac), P(_Fld), dp, dp, dp, dp, dp,
                                   dp, dp, dp, dp, dp, dp]
+        L.og_gmres.argtypes = [P(_Grid), dp, dp, dp, C.c_int, C.c_double, C.c_int, P(C.c_int), P(C.c_double)]
         L.og_spmv.argtypes = [P(_Grid), dp, dp, dp]
         L.og_relres.argtypes = [P(_Grid), dp, dp, dp]
         L.og_relres.restype = C.c_double
@@ -185,6 +186,15 @@ class Problem:
         it = C.c_int(0); rr = C.c_double(0)
         st = lib().og_cg(C.byref(self.g), _p(ahat), _p(bhat), _p(y), tol, max_iter,
                          C.byref(it), C.byref(rr))
+        return y, st, it.value, rr.value
+
+    def gmres(self, ahat, bhat, y0, m, tol, max_iter):
+        """Restarted GMRES(m); returns (y, status, inner iterations, relative residual)."""
+        ahat, bhat = _f64(ahat).ravel(), _f64(bhat).ravel()
+        y = _f64(y0).ravel().copy()
+        it = C.c_int(0); rr = C.c_double(0)
+        st = lib().og_gmres(C.byref(self.g), _p(ahat), _p(bhat), _p(y), int(m), tol, max_iter,
+                            C.byref(it), C.byref(rr))
         return y, st, it.value, rr.value
 
     def dense_solve(self, ahat, bhat):

@@ -484,6 +484,87 @@ int og_cg(const og_grid *g, const double *ahat, const double *bhat, double *y,
     return status;
 }
 
+/*
+ * Restarted GMRES(m) on the Jacobi-scaled system (the "generalized minimal residual
+ * method" section: the iterate of step i minimises the residual norm over y0 + K_i
+ * with K_i = span{r0, A r0, ..., A^(i-1) r0}; after m steps the method starts again
+ * from the last iterate).  Arnoldi with modified Gram-Schmidt builds an orthonormal
+ * basis V and the Hessenberg matrix H (A V_i = V_(i+1) H_i); Givens rotations reduce H
+ * to triangular form, so |g_(i+1)| is the residual norm of the least-squares solution;
+ * at a restart or convergence y += V_i H_i^-1 g_i and the true residual is recomputed.
+ * Returns 0 when converged, 1 if max_iter inner steps were reached.
+ */
+int og_gmres(const og_grid *g, const double *ahat, const double *bhat, double *y, int m,
+             double tol, int max_iter, int *iters, double *relres)
+{
+    long n = (long)g->nr * g->nt * g->np;
+    if (m < 1) m = 1;
+    double *V = (double *)malloc(sizeof(double) * (size_t)n * (m + 1));
+    double *H = (double *)calloc((size_t)(m + 1) * m, sizeof(double));  /* H[i * m + j] */
+    double *cs = (double *)malloc(sizeof(double) * m);
+    double *sn = (double *)malloc(sizeof(double) * m);
+    double *gv = (double *)malloc(sizeof(double) * (m + 1));
+    double *w = (double *)malloc(sizeof(double) * n);
+    double bn = sqrt(dot(n, bhat, bhat));
+    if (bn == 0.0) bn = 1.0;
+    int it = 0, status = 1;
+    double res = og_relres(g, ahat, bhat, y);
+    if (res <= tol) status = 0;
+    while (status && it < max_iter) {
+        /* r0 = b - A y, v_0 = r0 / beta */
+        og_spmv(g, ahat, y, w);
+        for (long c = 0; c < n; c++) w[c] = bhat[c] - w[c];
+        double beta = sqrt(dot(n, w, w));
+        if (beta == 0.0) { status = 0; res = 0.0; break; }
+        for (long c = 0; c < n; c++) V[c] = w[c] / beta;
+        for (int i = 0; i <= m; i++) gv[i] = 0.0;
+        gv[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m && it < max_iter; j++) {
+            it++;
+            og_spmv(g, ahat, V + (size_t)j * n, w);
+            for (int i = 0; i <= j; i++) {          /* modified Gram-Schmidt */
+                double h = dot(n, w, V + (size_t)i * n);
+                H[i * m + j] = h;
+                for (long c = 0; c < n; c++) w[c] -= h * V[(size_t)i * n + c];
+            }
+            double hn = sqrt(dot(n, w, w));
+            H[(j + 1) * m + j] = hn;
+            if (hn > 0.0)
+                for (long c = 0; c < n; c++) V[(size_t)(j + 1) * n + c] = w[c] / hn;
+            for (int i = 0; i < j; i++) {            /* previous rotations on column j */
+                double a = H[i * m + j], b = H[(i + 1) * m + j];
+                H[i * m + j] = cs[i] * a + sn[i] * b;
+                H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+            }
+            double a = H[j * m + j], b = H[(j + 1) * m + j];
+            double d = sqrt(a * a + b * b);
+            cs[j] = d > 0.0 ? a / d : 1.0;
+            sn[j] = d > 0.0 ? b / d : 0.0;
+            H[j * m + j] = d;
+            H[(j + 1) * m + j] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            k = j + 1;
+            if (fabs(gv[j + 1]) / bn <= tol || hn == 0.0) break;
+        }
+        /* y += V_k z with H_k z = g_k (back substitution) */
+        for (int i = k - 1; i >= 0; i--) {
+            double t = gv[i];
+            for (int l = i + 1; l < k; l++) t -= H[i * m + l] * gv[l];
+            gv[i] = t / H[i * m + i];
+        }
+        for (int i = 0; i < k; i++)
+            for (long c = 0; c < n; c++) y[c] += gv[i] * V[(size_t)i * n + c];
+        res = og_relres(g, ahat, bhat, y);
+        if (res <= tol) status = 0;
+    }
+    if (iters) *iters = it;
+    if (relres) *relres = res;
+    free(V); free(H); free(cs); free(sn); free(gv); free(w);
+    return status;
+}
+
 /* Dense Cholesky solve of the scaled system for tiny grids (n <= 4096). */
 int og_dense_solve(const og_grid *g, const double *ahat, const double *bhat, double *y)
 {

@@ -383,6 +383,51 @@ def test_cg_matches_dense_solve():
     assert np.max(np.abs(y / yd - 1)) < 1e-11
 
 
+def _small_system(shape=(16, 8, 4), tau=100.0, seed=5):
+    wl = sy.make_workload("t", *shape, 16, tau, clump_seed=seed)
+    P = oracle.Problem.from_workload(wl)
+    rho = wl.rho.ravel()
+    T = np.full(P.n, 60.0)
+    q, S, _ = P.raytrace(rho, T)
+    T = P.newton(np.full(P.n, A * sy.T_BC ** 4), S, T)
+    En = P.energy(T, S)
+    return P, P.assemble(rho, T, En, q), En
+
+
+def test_gmres_finite_termination_and_dense_solve():
+    """Without restarts GMRES reaches the exact solution in at most n steps (the
+    Krylov space is then the whole space)."""
+    P, out, En = _small_system(shape=(8, 4, 2))
+    n = P.n
+    yd = P.dense_solve(out["ahat"], out["bhat"])
+    y, st, it, res = P.gmres(out["ahat"], out["bhat"], En / out["s"], n, 1e-13, n)
+    assert st == 0 and res <= 1e-13 and it <= n
+    assert np.max(np.abs(y / yd - 1)) < 1e-10
+
+
+def test_gmres_residual_not_above_cg():
+    """Both the k-th GMRES and the k-th CG iterate lie in y0 + K_k; GMRES minimises the
+    residual norm there, so its residual cannot exceed CG's."""
+    P, out, En = _small_system()
+    y0 = En / out["s"]
+    for k in (1, 2, 5, 12, 30):
+        _, _, itg, rg = P.gmres(out["ahat"], out["bhat"], y0, 64, 1e-30, k)
+        _, _, itc, rc = P.cg(out["ahat"], out["bhat"], y0, 1e-30, k)
+        assert itg == k and itc == k
+        assert rg <= rc * (1 + 1e-10), (k, rg, rc)
+
+
+def test_restarted_gmres_matches_dense_solve():
+    P, out, En = _small_system()
+    yd = P.dense_solve(out["ahat"], out["bhat"])
+    y, st, it, res = P.gmres(out["ahat"], out["bhat"], En / out["s"], 10, 1e-13, 100000)
+    assert st == 0 and res <= 1e-13
+    assert np.max(np.abs(y / yd - 1)) < 1e-10
+    # restarting costs iterations: GMRES(10) needs more steps than unrestarted GMRES
+    _, _, it_full, _ = P.gmres(out["ahat"], out["bhat"], En / out["s"], 400, 1e-13, 100000)
+    assert it >= it_full
+
+
 # ------------------------------------------------------------------ symmetries
 
 def test_axisymmetric_and_mirror_symmetric_step():
