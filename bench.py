@@ -50,10 +50,11 @@ UNET_FLOP_PER_CELL = 54 * (256 + 256 + 768 + 256) + 54 * (512 + 1024 + 3072 + 10
 PEAK_BF16_TFLOPS = 2500.0
 
 
-def mode_opts(rt, mode, tol, max_iter, inner_tol, net=None, budget=0):
-    m = {"fp64": rt.MODE_FP64, "mixed": rt.MODE_MIXED, "learned": rt.MODE_LEARNED}[mode]
+def mode_opts(rt, mode, tol, max_iter, inner_tol, net=None, budget=0, restart=30):
+    m = {"fp64": rt.MODE_FP64, "mixed": rt.MODE_MIXED, "learned": rt.MODE_LEARNED, "gmres": rt.MODE_GMRES}[mode]
     return rt.solve_opts(m, tol=tol, max_iter=max_iter, check_every=32, inner_tol=inner_tol,
-                         inner_max_iter=budget if mode == "learned" else 0, net=net if mode == "learned" else None)
+                         inner_max_iter=budget if mode == "learned" else 0, net=net if mode == "learned" else None,
+                         restart=restart)
 
 
 def train_network(rt, torch, sy, n_fields, epochs, seed=7):
@@ -291,7 +292,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "mixed": "f32+f64", "learned": "bf16+f32+f64"}[head],
+        "dtype": {"fp64": "f64", "mixed": "f32+f64", "learned": "bf16+f32+f64", "gmres": "f64"}[head],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {wl.grid.shape[0]}x{wl.grid.shape[1]}x{wl.grid.shape[2]} cells, "
                                f"{c['n_nu']} bins, tau550={wl.tau550:g}, clumps seed {c['seeds'][-1]}",

@@ -94,7 +94,9 @@ typedef enum {
                              float32 cycle needs over 2048 iterations for a tenfold drop,
                              or two cycles fail to halve the true residual (cond(A^) too
                              large for float32), float64 CG finishes (fallback = 1) */
-    RT_SOLVE_LEARNED = 2  /* refinement around flexible CG preconditioned by a network */
+    RT_SOLVE_LEARNED = 2, /* refinement around flexible CG preconditioned by a network */
+    RT_SOLVE_GMRES = 3    /* restarted GMRES(m) on A^ in float64 (the paper's solver class,
+                             Sect. "The generalized minimal residual method"; m = restart) */
 } rt_solve_mode;
 
 typedef struct rt_net rt_net;
@@ -107,6 +109,7 @@ typedef struct {
     double inner_tol;    /* relative reduction asked of each inner solve (mixed / learned) */
     int inner_max_iter;  /* limit per inner solve */
     rt_net *net;         /* network for RT_SOLVE_LEARNED, else NULL */
+    int restart;         /* RT_SOLVE_GMRES: Krylov steps per cycle, 1..63 (<= 0: 30) */
 } rt_solve_opts;
 
 typedef struct {

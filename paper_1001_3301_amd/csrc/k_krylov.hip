@@ -666,4 +666,80 @@ void launch_fold(long n, const float *x32, double *y, hipStream_t st)
     hipLaunchKernelGGL(k_fold, dim3((unsigned)((n + kKB - 1) / kKB)), dim3(kKB), 0, st, n, x32, y);
 }
 
+// ---------------------------------------------------------------- GMRES(m)
+
+// Partial inner products of w with the k basis vectors V_i = V + i n (k <= kMaxBasis),
+// eight per pass over the block's cells: partials[blockIdx.x * kMaxBasis + i].
+constexpr int kDotGroup = 8;
+
+__global__ __launch_bounds__(kKB) void k_mdot(Dims d, int nblk, const double *__restrict__ V, int k,
+                                              const double *__restrict__ w, double *__restrict__ partials)
+{
+    __shared__ double sh[kKB / 64];
+    for (int g0 = 0; g0 < k; g0 += kDotGroup) {
+        double acc[kDotGroup];
+#pragma unroll
+        for (int u = 0; u < kDotGroup; u++) acc[u] = 0.0;
+        for_segments<1>(d, nblk, [&](const Row &rw, int i) {
+            const long c = rw.base + i;
+            const double wv = w[c];
+#pragma unroll
+            for (int u = 0; u < kDotGroup; u++)
+                if (g0 + u < k) acc[u] += V[(long)(g0 + u) * d.n + c] * wv;
+        });
+#pragma unroll
+        for (int u = 0; u < kDotGroup; u++) {
+            const double bs = block_sum(acc[u], sh);
+            if (threadIdx.x == 0 && g0 + u < k) partials[(long)blockIdx.x * kMaxBasis + g0 + u] = bs;
+        }
+    }
+}
+
+// out[i] = sum over blocks b (in order) of partials[b * kMaxBasis + i]; one block per i.
+__global__ __launch_bounds__(kKB) void k_sum_cols(int nblk, const double *__restrict__ partials,
+                                                  double *__restrict__ out)
+{
+    __shared__ double sh[kKB / 64];
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kKB) a += partials[(long)b * kMaxBasis + blockIdx.x];
+    a = block_sum(a, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = a;
+}
+
+// w += sign * sum_i coef[i] V_i (coef on the device, i < k, ascending i).
+__global__ __launch_bounds__(kKB) void k_maxpy(long n, const double *__restrict__ V, int k,
+                                               const double *__restrict__ coef, double sign, double *__restrict__ w)
+{
+    const long c = (long)blockIdx.x * kKB + threadIdx.x;
+    if (c >= n) return;
+    double t = 0.0;
+    for (int i = 0; i < k; i++) t = fma(coef[i], V[(long)i * n + c], t);
+    w[c] = fma(sign, t, w[c]);
+}
+
+// y = s x.
+__global__ __launch_bounds__(kKB) void k_scale_into(long n, const double *__restrict__ x, double s,
+                                                    double *__restrict__ y)
+{
+    const long c = (long)blockIdx.x * kKB + threadIdx.x;
+    if (c < n) y[c] = s * x[c];
+}
+
+void launch_mdot(const Dims &d, int nblk, const double *V, int k, const double *w, double *partials, double *out,
+                 hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mdot, dim3(nblk), dim3(kKB), 0, st, d, nblk, V, k, w, partials);
+    hipLaunchKernelGGL(k_sum_cols, dim3(k), dim3(kKB), 0, st, nblk, partials, out);
+}
+
+void launch_maxpy(long n, const double *V, int k, const double *coef, double sign, double *w, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_maxpy, dim3((unsigned)((n + kKB - 1) / kKB)), dim3(kKB), 0, st, n, V, k, coef, sign, w);
+}
+
+void launch_scale_into(long n, const double *x, double s, double *y, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scale_into, dim3((unsigned)((n + kKB - 1) / kKB)), dim3(kKB), 0, st, n, x, s, y);
+}
+
 }  // namespace rt

@@ -729,6 +729,100 @@ rt_status solve_learned(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
     return status;
 }
 
+// Restarted GMRES(m) on A^ in float64 (the paper's solver class).  Arnoldi with
+// classical Gram-Schmidt applied twice (CGS2: the projections of each pass are one
+// deterministic batched reduction over the basis), Givens rotations of the Hessenberg
+// column on the host, |g_(j+1)| as the residual estimate; a cycle ends after m steps
+// or at the estimate tol, then y += V z (H z = g) and the true residual decides.
+rt_status solve_gmres(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb)
+{
+    const Dims &d = ctx->d;
+    const long n = d.n;
+    hipStream_t s = ctx->stream;
+    DevScalars *h = ctx->h_sc;
+    const int m = o->restart > 0 ? o->restart : 30;
+    if (m + 1 > kMaxBasis) return fail(ctx, RT_EINVAL, "restart must be at most 63");
+    if (ctx->gm_cap < m + 1) {
+        ctx->gmV = dalloc<double>(ctx, (size_t)(m + 1) * n);
+        if (!ctx->gmV) return fail(ctx, RT_ENOMEM, "GMRES basis: out of device memory");
+        ctx->gm_cap = m + 1;
+        if (!ctx->gm_part) {
+            ctx->gm_part = dalloc<double>(ctx, (size_t)ctx->nblk * kMaxBasis);
+            ctx->gm_coef = dalloc<double>(ctx, kMaxBasis);
+            if (!ctx->gm_part || !ctx->gm_coef) return fail(ctx, RT_ENOMEM, "GMRES workspace: out of device memory");
+        }
+    }
+    double *V = ctx->gmV;
+    const double bn = std::sqrt(bb);
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), hc(kMaxBasis), h2(kMaxBasis);
+    auto col = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+    h->thresh2 = 0.0;
+    if (rt_status e = write_scalars(ctx)) return e;
+    rt_status status = RT_OK;
+    int it = 0;
+    for (;;) {
+        // r0 = b - A y, its norm; v_0 = r0 / beta
+        launch_resid(d, ctx->nblk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials, ctx->counter, ctx->sc, 0, s);
+        RT_HIP(ctx, hipGetLastError());
+        if (rt_status e = read_scalars(ctx)) return e;
+        const double beta = std::sqrt(h->res2);
+        st->relres = beta / bn;
+        if (!isfin(beta)) { status = RT_ENONFINITE; break; }
+        if (st->relres <= o->tol) break;
+        if (it >= o->max_iter) { status = RT_ENOCONV; break; }
+        launch_scale_into(n, ctx->r, 1.0 / beta, V, s);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m && it < o->max_iter; j++) {
+            it++;
+            double *w = V + (size_t)(j + 1) * n;
+            launch_spmv(d, ctx->nblk, ctx->ahat, V + (size_t)j * n, w, s);
+            for (int pass = 0; pass < 2; pass++) {  // CGS2
+                launch_mdot(d, ctx->nblk, V, j + 1, w, ctx->gm_part, ctx->gm_coef, s);
+                RT_HIP(ctx, hipMemcpyAsync(pass ? h2.data() : hc.data(), ctx->gm_coef, (j + 1) * sizeof(double),
+                                           hipMemcpyDeviceToHost, s));
+                launch_maxpy(n, V, j + 1, ctx->gm_coef, -1.0, w, s);
+            }
+            launch_norm2(d, ctx->nblk, w, ctx->partials, ctx->counter, ctx->sc, s);
+            RT_HIP(ctx, hipGetLastError());
+            if (rt_status e = read_scalars(ctx)) return e;  // also completes the two copies above
+            const double hn = std::sqrt(h->res2);
+            if (!isfin(hn)) { status = RT_ENONFINITE; break; }
+            for (int i = 0; i <= j; i++) col(i, j) = hc[i] + h2[i];
+            col(j + 1, j) = hn;
+            if (hn > 0.0) launch_scale_into(n, w, 1.0 / hn, w, s);
+            for (int i = 0; i < j; i++) {
+                const double a = col(i, j), b = col(i + 1, j);
+                col(i, j) = cs[i] * a + sn[i] * b;
+                col(i + 1, j) = -sn[i] * a + cs[i] * b;
+            }
+            const double a = col(j, j), b = col(j + 1, j);
+            const double dd = std::sqrt(a * a + b * b);
+            cs[j] = dd > 0.0 ? a / dd : 1.0;
+            sn[j] = dd > 0.0 ? b / dd : 0.0;
+            col(j, j) = dd;
+            col(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            if (std::fabs(g[j + 1]) / bn <= o->tol || hn == 0.0) break;
+        }
+        if (status != RT_OK) break;
+        for (int i = k - 1; i >= 0; i--) {  // H_k z = g_k
+            double t = g[i];
+            for (int l = i + 1; l < k; l++) t -= col(i, l) * g[l];
+            g[i] = t / col(i, i);
+        }
+        RT_HIP(ctx, hipMemcpyAsync(ctx->gm_coef, g.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_maxpy(n, V, k, ctx->gm_coef, 1.0, ctx->y, s);
+        RT_HIP(ctx, hipStreamSynchronize(s));  // g is reused by the next cycle
+        st->outer_iters++;
+    }
+    st->iters = it;
+    return status;
+}
+
 }  // namespace
 
 extern "C" {
@@ -740,7 +834,8 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
     RT_CHECK(ctx, o && E, "rt_fld_solve: NULL argument");
     RT_CHECK(ctx, o->tol > 0.0 && o->tol < 1.0, "tol must be in (0, 1)");
     RT_CHECK(ctx, o->max_iter > 0, "max_iter must be positive");
-    RT_CHECK(ctx, o->mode == RT_SOLVE_FP64 || o->mode == RT_SOLVE_MIXED || o->mode == RT_SOLVE_LEARNED,
+    RT_CHECK(ctx, o->mode == RT_SOLVE_FP64 || o->mode == RT_SOLVE_MIXED || o->mode == RT_SOLVE_LEARNED ||
+                      o->mode == RT_SOLVE_GMRES,
              "unknown solve mode");
     RT_CHECK(ctx, o->mode != RT_SOLVE_LEARNED || o->net, "learned mode needs a network");
     rt_solve_stats local{};
@@ -758,6 +853,7 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
     rt_status status;
     if (o->mode == RT_SOLVE_FP64) status = solve_fp64(ctx, o, S, bb);
     else if (o->mode == RT_SOLVE_MIXED) status = solve_mixed(ctx, o, S, bb);
+    else if (o->mode == RT_SOLVE_GMRES) status = solve_gmres(ctx, o, S, bb);
     else status = solve_learned(ctx, o, S, bb);
     if (status == RT_EDEVICE) return status;
     launch_scale_mul(ctx->d.n, ctx->s, ctx->y, E, ctx->stream);  // E = s y

@@ -212,6 +212,13 @@ void launch_cg_iter32(const Dims &d, int nblk, int nblk_upd, const float *a, flo
 void launch_reliable(const Dims &d, int nblk, const double *r, float *r32, float *x32, double *partials,
                      unsigned *counter, DevScalars *sc, int restart, hipStream_t st);
 void launch_fold(long n, const float *x32, double *y, hipStream_t st);
+// GMRES(m): basis inner products (out[i] = V_i . w, i < k, deterministic), w += sign
+// sum coef_i V_i, y = s x.  At most kMaxBasis basis vectors.
+constexpr int kMaxBasis = 64;
+void launch_mdot(const Dims &d, int nblk, const double *V, int k, const double *w, double *partials, double *out,
+                 hipStream_t st);
+void launch_maxpy(long n, const double *V, int k, const double *coef, double sign, double *w, hipStream_t st);
+void launch_scale_into(long n, const double *x, double s, double *y, hipStream_t st);
 // Flexible CG for the learned mode (float32 vectors, float64 dots).
 void launch_fcg_dir(const Dims &d, int nblk, const float *a, const float *z, const float *pold, const float *r,
                     float *pnew, float *q, double *partials, unsigned *counter, DevScalars *sc, hipStream_t st);
@@ -299,6 +306,10 @@ struct rt_ctx {
     int nblk = 0;             // blocks of the stencil and reduction kernels (multiple of 8)
     int nblk_upd = 0;         // blocks of the streaming update kernels (multiple of 8)
     double *partials = nullptr;
+    // GMRES(m) workspace, allocated on first use: basis V (gm_cap vectors of n), the
+    // per-block partial inner products and the device copy of small coefficient arrays
+    double *gmV = nullptr, *gm_part = nullptr, *gm_coef = nullptr;
+    int gm_cap = 0;
     unsigned *counter = nullptr;
     rt::DevScalars *sc = nullptr;   // device
     rt::DevScalars *h_sc = nullptr; // pinned host mirror

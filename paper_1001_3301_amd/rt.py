@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librtmi.so")
 RT_OK, RT_EINVAL, RT_EDEVICE, RT_ENOMEM, RT_ENONFINITE, RT_ENOCONV = range(6)
 STATUS_NAMES = {0: "RT_OK", 1: "RT_EINVAL", 2: "RT_EDEVICE", 3: "RT_ENOMEM", 4: "RT_ENONFINITE",
                 5: "RT_ENOCONV"}
-MODE_FP64, MODE_MIXED, MODE_LEARNED = 0, 1, 2
+MODE_FP64, MODE_MIXED, MODE_LEARNED, MODE_GMRES = 0, 1, 2, 3
 
 dp = C.POINTER(C.c_double)
 
@@ -57,7 +57,7 @@ class System(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("check_every", C.c_int), ("inner_tol", C.c_double), ("inner_max_iter", C.c_int),
-                ("net", C.c_void_p)]
+                ("net", C.c_void_p), ("restart", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -191,9 +191,9 @@ def star_bin_flux(T_star: float, nu) -> np.ndarray:
 
 
 def solve_opts(mode=MODE_FP64, tol=1e-8, max_iter=100000, check_every=32, inner_tol=1e-4,
-               inner_max_iter=0, net=None) -> SolveOpts:
+               inner_max_iter=0, net=None, restart=30) -> SolveOpts:
     nh = None if net is None else (net.h if isinstance(net, Net) else net)
-    o = SolveOpts(mode, tol, max_iter, check_every, inner_tol, inner_max_iter, nh)
+    o = SolveOpts(mode, tol, max_iter, check_every, inner_tol, inner_max_iter, nh, restart)
     o._net = net  # keeps the network alive as long as the options refer to it
     return o
 
