@@ -66,6 +66,10 @@ def lib():
         L.og_energy.argtypes = [P(_Grid), P(_Opac), P(_Fld), dp, dp, dp]
         L.og_assemble.argtypes = [P(_Grid), P(_Opac), P(_Fld), dp, dp, dp, dp, dp,
                                   dp, dp, dp, dp, dp, dp]
+        L.og_relax.argtypes = [P(_Grid), P(_Opac), P(_Star), P(_Fld), dp, dp, dp, C.c_int, C.c_double, C.c_int,
+                               C.c_int, C.c_double, dp]
+        L.og_gray_table.argtypes = [P(_Opac), dp, dp]
+        L.og_gray_table.restype = C.c_double
         L.og_gmres.argtypes = [P(_Grid), dp, dp, dp, C.c_int, C.c_double, C.c_int, P(C.c_int), P(C.c_double)]
         L.og_spmv.argtypes = [P(_Grid), dp, dp, dp]
         L.og_relres.argtypes = [P(_Grid), dp, dp, dp]
@@ -218,16 +222,35 @@ class Problem:
                        *[_p(a) for a in args], _p(out))
         return out
 
-    def step(self, rho, T, tol=1e-10, max_iter=100000, dense=False, want_force=True):
+    def step(self, rho, T, tol=1e-10, max_iter=100000, dense=False, want_force=True, no_fld=False):
         rho = _f64(rho).ravel()
         T = _f64(T).ravel().copy()
         E = np.empty(self.n)
         f = np.empty(4 * self.n) if want_force else None
         it = C.c_int(0); rr = C.c_double(0)
         st = lib().og_step(C.byref(self.g), C.byref(self.op), C.byref(self.st), C.byref(self.fld),
-                           _p(rho), _p(T), _p(E), _p(f), tol, max_iter, int(dense),
+                           _p(rho), _p(T), _p(E), _p(f), tol, max_iter, 2 if no_fld else int(dense),
                            C.byref(it), C.byref(rr))
         return dict(T=T, E=E, force=f, status=st, iters=it.value, relres=rr.value)
+
+    def relax(self, rho, T, mode="cg", tol=1e-10, max_iter=100000, max_steps=1000, tol_change=1e-4):
+        """Steps until the largest relative temperature change is below tol_change.
+        mode: "cg", "dense" or "none" (no diffusion).  Returns (T, E, steps, last change)."""
+        m = {"cg": 0, "dense": 1, "none": 2}[mode]
+        rho = _f64(rho).ravel()
+        T = _f64(T).ravel().copy()
+        E = np.empty(self.n)
+        ch = C.c_double(0)
+        k = lib().og_relax(C.byref(self.g), C.byref(self.op), C.byref(self.st), C.byref(self.fld), _p(rho),
+                           _p(T), _p(E), m, tol, max_iter, max_steps, tol_change, C.byref(ch))
+        return T, E, k, ch.value
+
+    def gray_table(self, F):
+        """(kappa_gray[n_T], sum F): the one-bin opacity table of gray irradiation."""
+        F = _f64(F).ravel()
+        kg = np.empty(len(self._keep[3]))
+        Fs = lib().og_gray_table(C.byref(self.op), _p(F), _p(kg))
+        return kg, Fs
 
     # --- table lookups (for pins) ----------------------------------------
     def kappa_nu(self, T, b):

@@ -36,6 +36,14 @@
  *      stopped when the Newton step is <= 1e-14 T or after 50 iterations.
  *  R9  Thermal force at a cell: mean of the two face fluxes per direction times
  *      kappa_R rho / c (Eq. (27) with the FLD flux of Eq. (10)).
+ *  R20 Runs without diffusion (the pure-absorption rows of the run table): the thermal
+ *      radiation field is never transported and stays at the background a T_bc^4, so
+ *      Eq. (16) balances the absorbed stellar power against re-emission cell by cell.
+ *      Gray irradiation (Eqs. (18)-(19)) is the one-bin case with the total flux
+ *      sigma T_*^4 = sum_b F_b and, at each table temperature, the F_b-weighted mean of
+ *      the bin opacities (the Planck mean at T_*, keeping the table's dust-temperature
+ *      dependence).  The main iteration stops when the largest relative temperature
+ *      change of a step is below the threshold (0.01 % in the run setup).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -713,6 +721,10 @@ int og_step(const og_grid *g, const og_opac *op, const og_star *st, const og_fld
             const double *rho, double *T, double *E, double *fout, double tol, int max_iter,
             int dense, int *iters, double *relres)
 {
+    /* dense: 0 = CG, 1 = dense Cholesky, 2 = no diffusion: the pure-absorption runs of
+     * the run table, where the thermal radiation field is never transported and stays at
+     * the background a T_bc^4 of the initial state, so Eq. 16 balances the absorbed
+     * stellar power against re-emission cell by cell */
     long n = (long)g->nr * g->nt * g->np;
     double *q = (double *)malloc(sizeof(double) * n), *S = (double *)malloc(sizeof(double) * n);
     double *En = (double *)malloc(sizeof(double) * n), *w = (double *)malloc(sizeof(double) * 3 * n);
@@ -726,15 +738,68 @@ int og_step(const og_grid *g, const og_opac *op, const og_star *st, const og_fld
     og_assemble(g, op, f, rho, Tn, En, q, NULL, w, d, b, s, ah, bh);
     for (long c = 0; c < n; c++) y[c] = En[c] / s[c];
     int status;
-    if (dense) {
+    if (dense == 2) {
+        status = 0;
+        if (iters) *iters = 0;
+        if (relres) *relres = 0.0;
+    } else if (dense) {
         status = og_dense_solve(g, ah, bh, y);
         if (iters) *iters = 0;
         if (relres) *relres = og_relres(g, ah, bh, y);
     } else
         status = og_cg(g, ah, bh, y, tol, max_iter, iters, relres);
-    for (long c = 0; c < n; c++) E[c] = s[c] * y[c];
+    for (long c = 0; c < n; c++) E[c] = dense == 2 ? OG_A * pow(f->Tbc, 4) : s[c] * y[c];
     og_newton(g, op, E, S, T);
     if (fout) og_force(g, op, f, rho, Tn, w, E, q, fout);
     free(q); free(S); free(En); free(w); free(d); free(b); free(s); free(ah); free(bh); free(y); free(Tn);
     return status;
+}
+
+/*
+ * The main iteration of Fig. 1 run to a steady state: steps of og_step (mode as its
+ * `dense` argument) until the largest relative temperature change of a step is below
+ * tol_change (the run setup stops at 0.01 %) or max_steps.  Returns the number of steps
+ * taken; *last_change is the change of the last step.
+ */
+int og_relax(const og_grid *g, const og_opac *op, const og_star *st, const og_fld *f, const double *rho,
+             double *T, double *E, int mode, double tol, int max_iter, int max_steps, double tol_change,
+             double *last_change)
+{
+    long n = (long)g->nr * g->nt * g->np;
+    double *Told = (double *)malloc(sizeof(double) * n);
+    int k = 0;
+    double ch = INFINITY;
+    while (k < max_steps) {
+        memcpy(Told, T, sizeof(double) * n);
+        og_step(g, op, st, f, rho, T, E, NULL, tol, max_iter, mode, NULL, NULL);
+        k++;
+        ch = 0.0;
+        for (long c = 0; c < n; c++) {
+            double r = fabs(T[c] - Told[c]) / Told[c];
+            if (r > ch) ch = r;
+        }
+        if (ch < tol_change) break;
+    }
+    if (last_change) *last_change = ch;
+    free(Told);
+    return k;
+}
+
+/*
+ * Gray irradiation (Eqs. 18, 19): one bin with the stellar flux sigma T_*^4 = sum of the
+ * bin fluxes F_b and the opacity kappa_P(T_*), the Planck mean at the stellar
+ * temperature, here the F_b-weighted mean of the tabulated bin opacities at each table
+ * temperature (so the dust-temperature dependence of the table, e.g. sublimation, is
+ * kept).  kappa_gray[k] for the n_T table temperatures; returns sum_b F_b.
+ */
+double og_gray_table(const og_opac *op, const double *F, double *kappa_gray)
+{
+    double Fs = 0.0;
+    for (int b = 0; b < op->nnu; b++) Fs += F[b];
+    for (int k = 0; k < op->nT; k++) {
+        double t = 0.0;
+        for (int b = 0; b < op->nnu; b++) t += op->kap[k * op->nnu + b] * F[b];
+        kappa_gray[k] = t / Fs;
+    }
+    return Fs;
 }

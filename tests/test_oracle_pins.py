@@ -483,3 +483,81 @@ def test_density_normalisation_reproduces_paper_table():
         # cylindrical closed form of the disk mass: 4 pi rho0 r_d^2 z_d (r/r_d)^2.125 / 2.125
         m = 4 * math.pi * rho0 * sy.R_D ** 2 * sy.Z_D * ((sy.R_MAX / sy.R_D) ** 2.125 - (sy.R_MIN / sy.R_D) ** 2.125) / 2.125
         assert abs(m / sy.M_SUN / mtot - 1) < 0.05
+
+
+# ------------------------------------------------------- main iteration (next rows)
+
+def test_gray_path_equals_frequency_dependent_for_gray_dust():
+    """Eqs. 17-20: when every bin has the same opacity, the frequency-dependent ray trace
+    summed over bins is the gray ray trace with the total stellar flux and the
+    flux-weighted (Planck at T_*) mean opacity."""
+    wl = sy.make_workload("t", 24, 6, 3, 16, 30.0, clump_seed=2)
+    op = wl.opacity
+    kap_gray_dust = np.repeat(op.kappa_P[:, None], op.kappa.shape[1], axis=1)  # nu-independent
+    F = oracle.star_bins(wl.T_star, op.nu)
+    g = wl.grid
+    Pf = oracle.Problem(g.r_face, g.th_face, g.ph_face, op.T, kap_gray_dust, op.kappa_P, op.kappa_R,
+                        R_star=wl.R_star, F0=F, T_star=wl.T_star)
+    kg, Fs = Pf.gray_table(F)
+    assert np.allclose(kg, op.kappa_P, rtol=1e-14)
+    assert abs(Fs / (sy.SIGMA_SB * wl.T_star ** 4) - 1) < 1e-12
+    Pg = oracle.Problem(g.r_face, g.th_face, g.ph_face, op.T, kg[:, None], op.kappa_P, op.kappa_R,
+                        R_star=wl.R_star, F0=[Fs], T_star=wl.T_star)
+    T = np.random.Generator(np.random.PCG64(3)).uniform(10.0, 2500.0, Pf.n)
+    for a, b in zip(Pf.raytrace(wl.rho, T), Pg.raytrace(wl.rho, T)):
+        assert np.max(np.abs(b - a)) <= 1e-12 * np.max(np.abs(a))
+
+
+def test_irradiation_only_main_iteration_stops_after_two_steps():
+    """Without diffusion the radiation field stays at the background a T_bc^4, and below
+    sublimation the ray trace does not depend on T: the first step heats the cold start
+    to the irradiation equilibrium and the second changes nothing (the pure-absorption
+    runs need only a few main iterations)."""
+    wl = sy.make_workload("t", 32, 8, 1, 16, 0.1)
+    P = oracle.Problem.from_workload(wl)
+    T0 = np.full(P.n, wl.T_bc)
+    T, E, k, ch = P.relax(wl.rho, T0, mode="none", tol_change=1e-4)
+    assert T.max() < 1500.0  # no cell reaches sublimation
+    assert k == 2 and ch < 1e-12
+    T1, _, k1, ch1 = P.relax(wl.rho, T0, mode="none", max_steps=1, tol_change=1e-4)
+    assert k1 == 1 and ch1 > 1.0  # the first step is the big one
+    assert np.max(np.abs(T1 / T - 1)) < 1e-12
+
+
+def _gray_problem(wl):
+    """The gray (one-bin) irradiation of a workload: Eqs. 18-19 with the table's
+    flux-weighted mean opacity."""
+    F = oracle.star_bins(wl.T_star, wl.opacity.nu)
+    g, op = wl.grid, wl.opacity
+    kg, Fs = oracle.Problem.from_workload(wl).gray_table(F)
+    return oracle.Problem(g.r_face, g.th_face, g.ph_face, op.T, kg[:, None], op.kappa_P, op.kappa_R,
+                          R_star=wl.R_star, F0=[Fs], T_star=wl.T_star, dt=wl.dt, c_V=wl.c_V,
+                          T_bc=wl.T_bc, E_floor=wl.E_floor)
+
+
+@pytest.mark.parametrize("shape,gray", [((24, 8, 1), False), ((20, 8, 3), True)])
+def test_main_iteration_fixed_point_conserves_luminosity(shape, gray):
+    """Eq. 15 at a steady state: with E no longer changing, the divergence of the diffuse
+    flux cancels the absorbed stellar power in every cell, and summed over the domain
+    (no flux through r_in or the poles) the absorbed stellar luminosity leaves through
+    the Dirichlet face at r_out.  Run to a change below 1e-7 at dt = 1e4 s."""
+    wl = sy.make_workload("t", *shape, 16, 100.0, dt=1e4)
+    P = _gray_problem(wl) if gray else oracle.Problem.from_workload(wl)
+    rho = wl.rho.ravel()
+    T, E, k, ch = P.relax(rho, np.full(P.n, wl.T_bc), mode="cg", tol=1e-10, tol_change=1e-7,
+                          max_steps=5000)
+    assert ch < 1e-7 and 20 < k < 5000
+    q, S, _ = P.raytrace(rho, T)
+    En = P.energy(T, S)
+    w = P.assemble(rho, T, En, q)["w"].reshape(3, P.n)
+    g = wl.grid
+    vol = np.einsum("k,j,i->kji", np.diff(g.ph_face), -np.diff(np.cos(g.th_face)),
+                    np.diff(g.r_face ** 3) / 3).ravel()
+    nr, nt, npp = P.shape
+    outer = np.array([nr - 1 + nr * (j + nt * kk) for kk in range(npp) for j in range(nt)])
+    L_abs = np.sum(vol * q)
+    L_out = np.sum(w[0][outer] * (En[outer] - A * wl.T_bc ** 4))
+    assert abs(L_out / L_abs - 1) < 1e-4
+    # the pure-absorption run of the same disk is the first step's irradiation balance
+    Tn, _, kn, _ = P.relax(rho, np.full(P.n, wl.T_bc), mode="none", tol_change=1e-4)
+    assert kn == 2 and np.all(Tn <= T * (1 + 1e-12))  # re-emission only adds heat
