@@ -95,8 +95,11 @@ typedef enum {
                              or two cycles fail to halve the true residual (cond(A^) too
                              large for float32), float64 CG finishes (fallback = 1) */
     RT_SOLVE_LEARNED = 2, /* refinement around flexible CG preconditioned by a network */
-    RT_SOLVE_GMRES = 3    /* restarted GMRES(m) on A^ in float64 (the paper's solver class,
+    RT_SOLVE_GMRES = 3,   /* restarted GMRES(m) on A^ in float64 (the paper's solver class,
                              Sect. "The generalized minimal residual method"; m = restart) */
+    RT_SOLVE_NONE = 4     /* no diffusion: E^{n+1} = a T_bc^4 of the assembled system in every
+                             cell (the runs without FLD of the run table, where the thermal
+                             field is never transported); no other option is read */
 } rt_solve_mode;
 
 typedef struct rt_net rt_net;
@@ -218,6 +221,41 @@ rt_status rt_step(rt_ctx *ctx, const rt_opacity *op, const rt_star *st,
 /* Device views of the last step's q_star, S_abs and E^n (n each). */
 rt_status rt_step_fields(rt_ctx *ctx, const double **q_star, const double **S_abs,
                          const double **E_n);
+
+/* ------------------------------------------------------------ the main iteration */
+
+/* Gray irradiation (Eqs. 18, 19): the one-bin table whose opacity at each table
+ * temperature is the F_nu-weighted mean of the bins, sum_b kappa[k][b] F_nu[b] /
+ * sum_b F_nu[b] (the Planck mean at T_* when F_nu comes from rt_star_bin_flux, keeping
+ * the table's dust-temperature dependence), and the total flux sum_b F_nu[b] (sigma
+ * T_*^4).  Host arrays: op's table, F_nu[n_nu] (>= 0, positive sum), kappa_gray[n_T]
+ * out; *F_total out; *nu_gray (may be NULL) the flux-weighted mean frequency.  A
+ * context created with n_nu = 1 and given {kappa_gray} with that star flux runs the
+ * gray variant of every call above.  Host computation, no device work. */
+rt_status rt_gray_table(const rt_opacity *op, const double *F_nu, double *kappa_gray, double *F_total,
+                        double *nu_gray);
+
+typedef struct {
+    int steps;           /* main iterations taken */
+    double last_change;  /* largest relative temperature change of the last step */
+    long krylov_iters;   /* Krylov iterations summed over the steps */
+    double ms;           /* host wall time of the call */
+    double ms_device;    /* device time of the steps (sum of their ms_total) */
+    rt_step_stats last;  /* statistics of the last step */
+} rt_relax_stats;
+
+/* The main loop of Fig. 1 run to a steady state (Sect. "Numerical setup": the loop stops
+ * when the temperature of every cell changes by less than 0.01 % in one step, i.e.
+ * tol_change = 1e-4): rt_step until max_c |T^{n+1}_c - T^n_c| / T^n_c < tol_change or
+ * max_steps steps.  T: start temperature in, the last iterate out; E: E^{n+1} of the
+ * last step.  o->mode = RT_SOLVE_NONE runs the loop without diffusion.  Synchronises
+ * once per step to read the change back.  Returns RT_ENOCONV when max_steps pass
+ * without reaching tol_change or a step's solve hits its limit (outputs hold the last
+ * iterate), RT_ENONFINITE for a non-finite temperature.  Allocates one float64 field
+ * on the context at its first call. */
+rt_status rt_relax(rt_ctx *ctx, const rt_opacity *op, const rt_star *st, const rt_fld_params *p,
+                   const rt_solve_opts *o, const double *rho, double *T, double *E, double tol_change,
+                   int max_steps, rt_relax_stats *stats);
 
 /* ------------------------------------------------ learned preconditioner (network) */
 

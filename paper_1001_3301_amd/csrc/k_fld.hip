@@ -254,6 +254,55 @@ __global__ __launch_bounds__(kTB) void k_force(Dims d, Geo g, const double *__re
 }
 
 // y = s * x (E = s y) and y = x / s (start guess y0 = E^n / s).
+// E = v in every cell: the runs without diffusion keep the thermal radiation field at
+// the background a T_bc^4.
+__global__ __launch_bounds__(kTB) void k_fill(long n, double v, double *__restrict__ x)
+{
+    long c = (long)blockIdx.x * kTB + threadIdx.x;
+    if (c < n) x[c] = v;
+}
+
+// Stop test of the main iteration: max_c |T_c - Told_c| / Told_c over the grid (a
+// non-finite ratio counts as +inf).  Grid-stride per block, wave maxima by shuffles,
+// one partial per block, and the last block to finish folds the partials; a maximum
+// is exact in any order, so the result does not depend on the schedule.
+__global__ __launch_bounds__(kTB) void k_max_change(long n, const double *__restrict__ T,
+                                                    const double *__restrict__ Told, double *partials,
+                                                    unsigned *counter, double *out)
+{
+    __shared__ double sh[kTB / 64];
+    __shared__ int s_last;
+    double m = 0.0;
+    for (long c = (long)blockIdx.x * kTB + threadIdx.x; c < n; c += (long)gridDim.x * kTB) {
+        double r = fabs(T[c] - Told[c]) / Told[c];
+        m = r <= m ? m : (r == r ? r : INFINITY);
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = sh[0];
+        for (int w = 1; w < kTB / 64; w++) b = fmax(b, sh[w]);
+        partials[blockIdx.x] = b;
+        __threadfence();
+        s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    double t = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kTB) t = fmax(t, partials[b]);
+    for (int o = 32; o > 0; o >>= 1) t = fmax(t, __shfl_xor(t, o));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kTB / 64; w++) t = fmax(t, sh[w]);
+        *out = t;
+        *counter = 0u;
+    }
+}
+
 __global__ __launch_bounds__(kTB) void k_scale_mul(long n, const double *__restrict__ s,
                                                    const double *__restrict__ x, double *__restrict__ y)
 {
@@ -307,6 +356,17 @@ void launch_scale_mul(long n, const double *s, const double *x, double *y, hipSt
 void launch_scale_div(long n, const double *s, const double *x, double *y, hipStream_t st)
 {
     hipLaunchKernelGGL(k_scale_div, dim3(nb(n)), dim3(kTB), 0, st, n, s, x, y);
+}
+
+void launch_fill(long n, double v, double *x, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill, dim3(nb(n)), dim3(kTB), 0, st, n, v, x);
+}
+
+void launch_max_change(long n, int nblk, const double *T, const double *Told, double *partials,
+                       unsigned *counter, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_max_change, dim3(nblk), dim3(kTB), 0, st, n, T, Told, partials, counter, out);
 }
 
 }  // namespace rt

@@ -169,6 +169,30 @@ rt_status rt_star_bin_flux(double T_star, int n_nu, const double *nu, double *F_
     return RT_OK;
 }
 
+rt_status rt_gray_table(const rt_opacity *op, const double *F_nu, double *kappa_gray, double *F_total,
+                        double *nu_gray)
+{
+    if (!op || !op->T || !op->nu || !op->kappa || !F_nu || !kappa_gray || !F_total)
+        return fail(nullptr, RT_EINVAL, "rt_gray_table: NULL argument");
+    if (op->n_T < 2 || op->n_T > kMaxT || op->n_nu < 1 || op->n_nu > kMaxNu)
+        return fail(nullptr, RT_EINVAL, "rt_gray_table: need 2 <= n_T <= 128 and 1 <= n_nu <= 64");
+    double Fs = 0.0, nuF = 0.0;
+    for (int b = 0; b < op->n_nu; b++) {
+        if (!(F_nu[b] >= 0.0) || !isfin(F_nu[b])) return fail(nullptr, RT_EINVAL, "rt_gray_table: bad bin flux");
+        Fs += F_nu[b];
+        nuF += op->nu[b] * F_nu[b];
+    }
+    if (!(Fs > 0.0) || !isfin(Fs)) return fail(nullptr, RT_EINVAL, "rt_gray_table: total flux must be positive");
+    for (int k = 0; k < op->n_T; k++) {
+        double t = 0.0;
+        for (int b = 0; b < op->n_nu; b++) t += op->kappa[(long)k * op->n_nu + b] * F_nu[b];
+        kappa_gray[k] = t / Fs;
+    }
+    *F_total = Fs;
+    if (nu_gray) *nu_gray = nuF / Fs;
+    return RT_OK;
+}
+
 rt_status rt_create(rt_ctx **out, const rt_grid *g, int n_nu, void *stream)
 {
     if (!out) return fail(nullptr, RT_EINVAL, "rt_create: out is NULL");
@@ -832,6 +856,12 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
     if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
     RT_CHECK(ctx, ctx->have_system, "no assembled system");
     RT_CHECK(ctx, o && E, "rt_fld_solve: NULL argument");
+    if (o->mode == RT_SOLVE_NONE) {  // no transport: the background field of the boundary
+        if (st) *st = rt_solve_stats{};
+        launch_fill(ctx->d.n, ctx->Eb, E, ctx->stream);
+        RT_HIP(ctx, hipGetLastError());
+        return RT_OK;
+    }
     RT_CHECK(ctx, o->tol > 0.0 && o->tol < 1.0, "tol must be in (0, 1)");
     RT_CHECK(ctx, o->max_iter > 0, "max_iter must be positive");
     RT_CHECK(ctx, o->mode == RT_SOLVE_FP64 || o->mode == RT_SOLVE_MIXED || o->mode == RT_SOLVE_LEARNED ||
@@ -990,6 +1020,53 @@ rt_status rt_step_fields(rt_ctx *ctx, const double **q_star, const double **S_ab
     if (q_star) *q_star = ctx->q;
     if (S_abs) *S_abs = ctx->S;
     if (E_n) *E_n = ctx->En;
+    return RT_OK;
+}
+
+rt_status rt_relax(rt_ctx *ctx, const rt_opacity *op, const rt_star *st, const rt_fld_params *p,
+                   const rt_solve_opts *o, const double *rho, double *T, double *E, double tol_change,
+                   int max_steps, rt_relax_stats *stats)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    RT_CHECK(ctx, rho && T && E && o && p, "rt_relax: NULL argument");
+    RT_CHECK(ctx, tol_change > 0.0 && isfin(tol_change), "tol_change must be positive");
+    RT_CHECK(ctx, max_steps > 0, "max_steps must be positive");
+    const long n = ctx->d.n;
+    if (!ctx->Tn) {
+        ctx->Tn = dalloc<double>(ctx, n);
+        if (!ctx->Tn) return fail(ctx, RT_ENOMEM, "rt_relax: out of device memory");
+    }
+    rt_relax_stats local{};
+    rt_relax_stats *R = stats ? stats : &local;
+    *R = rt_relax_stats{};
+    R->last_change = INFINITY;
+    Clock clk;
+    hipStream_t s = ctx->stream;
+    rt_status status = RT_OK;
+    for (int k = 0; k < max_steps; k++) {
+        RT_HIP(ctx, hipMemcpyAsync(ctx->Tn, T, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        rt_step_stats ss{};
+        // the tables are uploaded by the first step only
+        status = rt_step(ctx, k == 0 ? op : nullptr, k == 0 ? st : nullptr, p, o, rho, T, E, nullptr, &ss);
+        R->steps = k + 1;
+        R->krylov_iters += ss.solve.iters;
+        R->ms_device += ss.ms_total;
+        R->last = ss;
+        if (status != RT_OK) break;
+        double *dchange = reinterpret_cast<double *>(reinterpret_cast<char *>(ctx->sc) + offsetof(DevScalars, change));
+        launch_max_change(n, ctx->nblk, T, ctx->Tn, ctx->partials, ctx->counter, dchange, s);
+        RT_HIP(ctx, hipGetLastError());
+        if (rt_status e = read_scalars(ctx)) return e;
+        R->last_change = ctx->h_sc->change;
+        if (!isfin(R->last_change)) {
+            status = fail(ctx, RT_ENONFINITE, "rt_relax: non-finite temperature");
+            break;
+        }
+        if (R->last_change < tol_change) break;
+    }
+    R->ms = clk.ms();
+    if (status != RT_OK) return status;
+    if (!(R->last_change < tol_change)) return fail(ctx, RT_ENOCONV, "rt_relax: max_steps reached");
     return RT_OK;
 }
 

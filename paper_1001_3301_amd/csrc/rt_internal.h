@@ -170,6 +170,7 @@ struct DevScalars {
     double thresh2;  // stop when rr <= thresh2
     double res2;     // last reduction of the residual kernel
     double inv_norm; // 1 / sqrt(res2)
+    double change;   // largest relative temperature change of the last main iteration
     int done;
     int iters;
 };
@@ -193,6 +194,10 @@ void launch_force(const Dims &d, const Geo &g, const double *w, const double *ch
                   const double *q, double Eb, double *f, hipStream_t st);
 void launch_scale_mul(long n, const double *s, const double *x, double *y, hipStream_t st);
 void launch_scale_div(long n, const double *s, const double *x, double *y, hipStream_t st);
+void launch_fill(long n, double v, double *x, hipStream_t st);
+// max_c |T_c - Told_c| / Told_c into *out (device); partials needs nblk entries.
+void launch_max_change(long n, int nblk, const double *T, const double *Told, double *partials,
+                       unsigned *counter, double *out, hipStream_t st);
 // Krylov kernels: nblk blocks (a multiple of 8) sweeping the rows in windows; the
 // CG iteration launches its update kernel with nblk_upd blocks.
 void launch_spmv(const Dims &d, int nblk, const double *a, const double *x, double *y, hipStream_t st);

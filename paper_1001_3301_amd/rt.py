@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librtmi.so")
 RT_OK, RT_EINVAL, RT_EDEVICE, RT_ENOMEM, RT_ENONFINITE, RT_ENOCONV = range(6)
 STATUS_NAMES = {0: "RT_OK", 1: "RT_EINVAL", 2: "RT_EDEVICE", 3: "RT_ENOMEM", 4: "RT_ENONFINITE",
                 5: "RT_ENOCONV"}
-MODE_FP64, MODE_MIXED, MODE_LEARNED, MODE_GMRES = 0, 1, 2, 3
+MODE_FP64, MODE_MIXED, MODE_LEARNED, MODE_GMRES, MODE_NONE = 0, 1, 2, 3, 4
 
 dp = C.POINTER(C.c_double)
 
@@ -80,10 +80,21 @@ class StepStats(C.Structure):
         return d
 
 
+class RelaxStats(C.Structure):
+    _fields_ = [("steps", C.c_int), ("last_change", C.c_double), ("krylov_iters", C.c_long),
+                ("ms", C.c_double), ("ms_device", C.c_double), ("last", StepStats)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "last"}
+        d["last"] = self.last.as_dict()
+        return d
+
+
 # Every symbol include/rt.h declares (checked by the tests).
 EXPORTS = ["rt_create", "rt_destroy", "rt_last_error", "rt_ncell", "rt_star_bin_flux",
            "rt_set_opacity", "rt_set_star", "rt_raytrace", "rt_energy", "rt_fld_assemble",
            "rt_spmv", "rt_fld_solve", "rt_temperature", "rt_force", "rt_step", "rt_step_fields",
+           "rt_gray_table", "rt_relax",
            "rt_net_create", "rt_net_destroy", "rt_net_last_error", "rt_net_param_count",
            "rt_net_get_params", "rt_net_get_grads", "rt_net_set_params", "rt_net_save", "rt_net_load",
            "rt_net_forward", "rt_net_loss_grad", "rt_net_loss_grad_resid", "rt_net_adam", "rt_dataset_create",
@@ -140,6 +151,9 @@ def lib():
     L.rt_step.argtypes = [vp, P(Opacity), P(Star), P(FldParams), P(SolveOpts), vp, vp, vp, vp,
                           P(StepStats)]
     L.rt_step_fields.argtypes = [vp, P(vp), P(vp), P(vp)]
+    L.rt_gray_table.argtypes = [P(Opacity), dp, dp, dp, dp]
+    L.rt_relax.argtypes = [vp, P(Opacity), P(Star), P(FldParams), P(SolveOpts), vp, vp, vp, C.c_double,
+                           C.c_int, P(RelaxStats)]
     fp = P(C.c_float)
     L.rt_net_create.argtypes = [P(NetConfig), P(vp)]
     L.rt_net_destroy.argtypes = [vp]
@@ -190,6 +204,29 @@ def star_bin_flux(T_star: float, nu) -> np.ndarray:
     return out
 
 
+def gray_table(op, F_nu):
+    """Eqs. (18)-(19) as a one-bin table (host computation in the library): returns
+    (kappa_gray[n_T], F_total, nu_gray)."""
+    arrs = [_host(op.T), _host(op.nu), _host(op.kappa), _host(op.kappa_P), _host(op.kappa_R)]
+    o = Opacity(len(arrs[0]), len(arrs[1]), *[_hp(a) for a in arrs])
+    F = _host(F_nu)
+    kg = np.empty(len(arrs[0]))
+    Ft, nug = C.c_double(), C.c_double()
+    st = lib().rt_gray_table(C.byref(o), _hp(F), _hp(kg), C.byref(Ft), C.byref(nug))
+    if st != RT_OK:
+        raise RtError(st, lib().rt_last_error(None).decode())
+    return kg, Ft.value, nug.value
+
+
+class GrayOpacity:
+    """The one-bin table of a gray run (same temperatures and mean opacities)."""
+
+    def __init__(self, op, kappa_gray, nu_gray):
+        self.T, self.kappa_P, self.kappa_R = op.T, op.kappa_P, op.kappa_R
+        self.kappa = np.asarray(kappa_gray, dtype=np.float64).reshape(-1, 1)
+        self.nu = np.array([nu_gray])
+
+
 def solve_opts(mode=MODE_FP64, tol=1e-8, max_iter=100000, check_every=32, inner_tol=1e-4,
                inner_max_iter=0, net=None, restart=30) -> SolveOpts:
     nh = None if net is None else (net.h if isinstance(net, Net) else net)
@@ -223,11 +260,18 @@ class Context:
         self._keep = []
 
     @classmethod
-    def from_workload(cls, wl, stream=None):
+    def from_workload(cls, wl, stream=None, gray=False):
+        """Context with the workload's tables; gray=True gives the gray-irradiation run
+        (one bin: the flux-weighted table and the total stellar flux)."""
         g = wl.grid
-        ctx = cls(g.r_face, g.th_face, g.ph_face, len(wl.opacity.nu), stream)
-        ctx.set_opacity(wl.opacity)
-        ctx.set_star(wl.R_star, wl.T_star, star_bin_flux(wl.T_star, wl.opacity.nu))
+        F = star_bin_flux(wl.T_star, wl.opacity.nu)
+        op = wl.opacity
+        if gray:
+            kg, Ft, nug = gray_table(op, F)
+            op, F = GrayOpacity(op, kg, nug), np.array([Ft])
+        ctx = cls(g.r_face, g.th_face, g.ph_face, len(op.nu), stream)
+        ctx.set_opacity(op)
+        ctx.set_star(wl.R_star, wl.T_star, F)
         ctx.params = FldParams(wl.dt, wl.c_V, wl.T_bc, wl.E_floor)
         return ctx
 
@@ -331,6 +375,19 @@ class Context:
                            self._dev(rho, self.n, "rho"), self._dev(T, self.n, "T"),
                            self._dev(E, self.n, "E"),
                            self._dev(f_rad, 4 * self.n, "f_rad", allow_none=True), C.byref(st))
+        if raise_on_error:
+            self._chk(rc)
+        return rc, st.as_dict()
+
+    def relax(self, rho, T, E, opts: SolveOpts, tol_change=1e-4, max_steps=10000, params=None,
+              raise_on_error=True):
+        """rt_relax: main iterations until the largest relative temperature change of a
+        step is below tol_change.  Returns (status, stats dict)."""
+        p = params or self.params
+        st = RelaxStats()
+        rc = lib().rt_relax(self.h, None, None, C.byref(p), C.byref(opts), self._dev(rho, self.n, "rho"),
+                            self._dev(T, self.n, "T"), self._dev(E, self.n, "E"), float(tol_change),
+                            int(max_steps), C.byref(st))
         if raise_on_error:
             self._chk(rc)
         return rc, st.as_dict()
