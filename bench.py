@@ -8,7 +8,9 @@ in equilibrium with the stellar irradiation and E = a T_bc^4), so the K timed st
 identical work.  The headline solve mode is timed first, then the plain float64 solve
 for comparison.  With --successive N the headline mode also runs N successive steps
 (temperature carried over), whose per-step iteration counts are reported: the system
-gets harder as the radiation field evolves.
+gets harder as the radiation field evolves.  Unless --no-main-loop, the main loop is
+also run to equilibrium (the run table's gray / frequency-dependent runs with and
+without diffusion) on a 2-D disk, reported under "main_iteration".
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -162,6 +164,41 @@ def run_successive(ctx, rt, torch, rho, T0, mode, nsteps, tol, inner_tol, max_it
     return out
 
 
+def run_main_loop(rt, torch, sy, shape=(64, 64, 1), n_nu=64, tol_change=1e-4):
+    """The run table's main-loop runs on a 2-D disk (the stand-in for the paper's 60x61
+    grid): gray (G) or frequency-dependent (F) irradiation, without or with diffusion
+    (D), from T_bc at dt = 1e4 s until the largest relative temperature change of a
+    step is below tol_change.  Also the gray/frequency-dependent midplane temperature
+    ratio of each pair (the analogue of the run table's deviation row)."""
+    runs, mid = {}, {}
+    for tau, gray, fld in ((0.1, True, False), (100.0, True, False), (100.0, False, False),
+                           (100.0, True, True), (100.0, False, True)):
+        name = ("G" if gray else "F") + ("D" if fld else "") + f"{tau:g}"
+        wl = sy.make_workload("disk-2d", *shape, n_nu, tau, None, dt=1e4)
+        ctx = rt.Context.from_workload(wl, gray=gray)
+        rho = torch.tensor(wl.rho.ravel(), device="cuda")
+        T = torch.full((ctx.n,), wl.T_bc, dtype=torch.float64, device="cuda")
+        E = torch.empty_like(T)
+        o = rt.solve_opts(rt.MODE_FP64, tol=1e-8) if fld else rt.solve_opts(rt.MODE_NONE)
+        t = time.perf_counter()
+        rc, st = ctx.relax(rho, T, E, o, tol_change=tol_change, max_steps=5000, raise_on_error=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        runs[name] = {"status": rc, "steps": st["steps"], "last_change": st["last_change"],
+                      "krylov_iters": st["krylov_iters"], "s": wall, "ms_per_step": wall / st["steps"] * 1e3}
+        j = shape[1] // 2  # the cell row just below the equator
+        mid[name] = T.view(shape[2], shape[1], shape[0])[0, j].cpu().numpy()
+        log(f"main loop {name}: {runs[name]}")
+        del ctx
+    cmp = {}
+    for g, f in (("G100", "F100"), ("GD100", "FD100")):
+        r = mid[g] / mid[f] - 1.0
+        cmp[f"{g}_vs_{f}"] = {"max_percent": float(r.max() * 100), "min_percent": float(r.min() * 100)}
+    return {"workload": f"disk-2d {shape[0]}x{shape[1]}x{shape[2]} cells, {n_nu} bins, no clumps, dt=1e4 s, "
+                        f"stop when max |dT/T| < {tol_change:g}; FLD solves float64 CG to 1e-8",
+            "runs": runs, "gray_vs_freq_midplane": cmp}
+
+
 def oracle_baseline(wl, gpu_fp64_iters, slab=16, cg_iters=1000):
     """The oracle on a phi-slab of the workload: ray trace and a fixed number of CG
     iterations, scaled to the full grid and to the GPU float64 iteration count."""
@@ -215,6 +252,7 @@ def main():
     ap.add_argument("--successive", type=int, default=0,
                     help="also run this many successive steps of the headline mode (not timed for value)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-main-loop", action="store_true", help="skip the main-loop runs to equilibrium")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy a buffer of this size once before timing (HBM-counter calibration)")
     args = ap.parse_args()
@@ -337,6 +375,8 @@ def main():
     if args.successive > 0:
         out["successive_steps"] = run_successive(ctx, rt, torch, rho, T0, head, args.successive, args.tol,
                                                  args.inner_tol, args.max_iter, net, args.learned_budget)
+    if not args.no_main_loop:
+        out["main_iteration"] = run_main_loop(rt, torch, sy)
     if not args.no_cpu_baseline:
         fp64_iters = out.get("fp64_iters_per_step", out["solve_iters_per_step"])
         t = time.perf_counter()
