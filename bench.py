@@ -31,8 +31,14 @@ METRIC = "FLD solve s/step @1e-8 resid, plain FP64 vs learned-precond; ray-trace
 PEAK_HBM_GBS = 8000.0
 # Algorithmic bytes per cell of one launch of each solver kernel (see the kernel comments):
 # dir: read r, p_old and the three off-diagonals, write p and q; upd: read y, p, r, q, write y, r.
-BYTES_PER_CELL = {"fp64": {"dir": 7 * 8, "upd": 6 * 8}, "mixed": {"dir": 7 * 4, "upd": 6 * 4}}
-KERNEL_NAMES = {"fp64": "k_cg_dir<double>", "mixed": "k_cg_dir<float>"}
+# Red-black reduced modes (-rb), per cell of the full grid: the red pass reads p's two
+# inputs at the black cells, every face coefficient once and writes t at the red cells
+# (36 / 18 B); the black pass reads the same plus t and writes p and q at the black cells
+# (44 / 22 B, i.e. 88 / 44 B per black cell); the update streams six half-size arrays.
+BYTES_PER_CELL = {"fp64": {"dir": 7 * 8, "upd": 6 * 8}, "mixed": {"dir": 7 * 4, "upd": 6 * 4},
+                  "fp64-rb": {"dir": 80, "upd": 24, "black": 44}, "mixed-rb": {"dir": 40, "upd": 12, "black": 22}}
+KERNEL_NAMES = {"fp64": "k_cg_dir<double>", "mixed": "k_cg_dir<float>", "fp64-rb": "k_rb_black_dir<double>",
+                "mixed-rb": "k_rb_black_dir<float>"}
 # HBM bytes per launch of these kernels on the 512x256x512 workload, from rocprofv3
 # FETCH_SIZE (x2.0, calibrated on a kernel of known size) + WRITE_SIZE; the summary with
 # the commands is profiles/solver_kernels_clumpy-512x256x512-nu64.md.  Set to None when
@@ -53,10 +59,12 @@ PEAK_BF16_TFLOPS = 2500.0
 
 
 def mode_opts(rt, mode, tol, max_iter, inner_tol, net=None, budget=0, restart=30):
-    m = {"fp64": rt.MODE_FP64, "mixed": rt.MODE_MIXED, "learned": rt.MODE_LEARNED, "gmres": rt.MODE_GMRES}[mode]
+    """Solve options of a bench mode; the suffix -rb solves the red-black reduced system."""
+    base = mode[:-3] if mode.endswith("-rb") else mode
+    m = {"fp64": rt.MODE_FP64, "mixed": rt.MODE_MIXED, "learned": rt.MODE_LEARNED, "gmres": rt.MODE_GMRES}[base]
     return rt.solve_opts(m, tol=tol, max_iter=max_iter, check_every=32, inner_tol=inner_tol,
-                         inner_max_iter=budget if mode == "learned" else 0, net=net if mode == "learned" else None,
-                         restart=restart)
+                         inner_max_iter=budget if base == "learned" else 0, net=net if base == "learned" else None,
+                         restart=restart, reduce=int(mode.endswith("-rb")))
 
 
 def train_network(rt, torch, sy, n_fields, epochs, seed=7):
@@ -144,7 +152,9 @@ def run_mode(ctx, rt, torch, rho, T0, mode, steps, warmup, tol, inner_tol, max_i
         log(f"[{mode}] step {k}: total {st['ms_total']:.1f} ms, raytrace {st['ms_raytrace']:.2f} ms, "
             f"solve {st['solve']['ms']:.1f} ms ({st['solve']['iters']} it, {st['solve']['outer_iters']} outer, "
             f"{st['solve']['precond_applies']} network applications, fallback {st['solve']['fallback']}, "
-            f"relres {st['solve']['relres']:.2e}), dir {st['solve']['ms_dir']*1e3:.1f} us")
+            f"relres {st['solve']['relres']:.2e}, reduced {st['solve']['reduced']}), "
+            f"dir {st['solve']['ms_dir']*1e3:.1f} us, black {st['solve']['ms_black']*1e3:.1f} us, "
+            f"upd {st['solve']['ms_upd']*1e3:.1f} us")
     return dict(wall_s=wall, stats=stats, T=T, E=E)
 
 
@@ -239,7 +249,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="clumpy-512x256x512-nu64")
-    ap.add_argument("--modes", default="mixed,fp64,learned", help="comma list; the first is the headline")
+    ap.add_argument("--modes", default="mixed-rb,fp64,mixed,fp64-rb,learned",
+                    help="comma list; the first is the headline (suffix -rb: red-black reduced system)")
     ap.add_argument("--net", default="", help="load the network from this file instead of training it")
     ap.add_argument("--save-net", default="", help="save the trained network to this file")
     ap.add_argument("--train-fields", type=int, default=24)
@@ -317,8 +328,12 @@ def main():
     samples = sum(s["solve"]["kernel_samples"] for s in R["stats"])
     ms_dir = sum(s["solve"]["ms_dir"] * s["solve"]["kernel_samples"] for s in R["stats"]) / max(samples, 1)
     ms_upd = sum(s["solve"]["ms_upd"] * s["solve"]["kernel_samples"] for s in R["stats"]) / max(samples, 1)
+    ms_black = sum(s["solve"]["ms_black"] * s["solve"]["kernel_samples"] for s in R["stats"]) / max(samples, 1)
     bpc = BYTES_PER_CELL.get(head)
-    achieved = bpc["dir"] * n / (ms_dir / 1e3) / 1e9 if (bpc and ms_dir > 0) else 0.0
+    # the dominant kernel: the direction kernel, or the black pass of a reduced solve
+    dom_b, dom_ms, dom_cells = (bpc["black"] * 2, ms_black, n // 2) if (bpc and "black" in bpc) else \
+        ((bpc["dir"], ms_dir, n) if bpc else (0, 0.0, n))
+    achieved = dom_b * dom_cells / (dom_ms / 1e3) / 1e9 if (bpc and dom_ms > 0) else 0.0
     out = {
         "metric": METRIC,
         "value": value,
@@ -330,7 +345,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "mixed": "f32+f64", "learned": "bf16+f32+f64", "gmres": "f64"}[head],
+        "dtype": {"fp64": "f64", "mixed": "f32+f64", "learned": "bf16+f32+f64", "gmres": "f64"}[head.replace("-rb", "")],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {wl.grid.shape[0]}x{wl.grid.shape[1]}x{wl.grid.shape[2]} cells, "
                                f"{c['n_nu']} bins, tau550={wl.tau550:g}, clumps seed {c['seeds'][-1]}",
@@ -338,13 +353,13 @@ def main():
                    "step": "first step from the prepared state, repeated K times"},
         "raytrace_gcell_nu_per_s": statistics.median([n * c["n_nu"] / (x / 1e3) / 1e9 for x in rt_ms]),
         "solve_iters_per_step": statistics.median([s["solve"]["iters"] for s in R["stats"]]),
-        "kernel_ms": {"dir": ms_dir, "upd": ms_upd, "samples": samples},
+        "kernel_ms": {"dir": ms_dir, "upd": ms_upd, "black": ms_black, "samples": samples},
     }
     if bpc:
         out["roofline"] = {"kernel": KERNEL_NAMES[head], "bound": "hbm", "achieved": achieved,
                            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                           "traffic": MEASURED_TRAFFIC.get((head, args.config)), "bytes_per_cell": bpc["dir"],
-                           "cells_per_launch": n}
+                           "traffic": MEASURED_TRAFFIC.get((head, args.config)), "bytes_per_cell": dom_b,
+                           "cells_per_launch": dom_cells}
         if ms_dir > 0 and ms_upd > 0:
             # one whole Krylov iteration (both kernels): its algorithmic bytes over the two launch times
             it_gbs = (bpc["dir"] + bpc["upd"]) * n / ((ms_dir + ms_upd) / 1e3) / 1e9

@@ -113,6 +113,12 @@ typedef struct {
     int inner_max_iter;  /* limit per inner solve */
     rt_net *net;         /* network for RT_SOLVE_LEARNED, else NULL */
     int restart;         /* RT_SOLVE_GMRES: Krylov steps per cycle, 1..63 (<= 0: 30) */
+    int reduce;          /* RT_SOLVE_FP64 / RT_SOLVE_MIXED: 1 = eliminate the red cells of the
+                            red-black colouring ((i + j + k) odd) and run CG on the Schur
+                            complement S = I - B^T B over the black cells, then recover the
+                            red ones (the same solution and stopping test, about half the
+                            iterations at the same bytes each); used when N_r is even and
+                            N_phi is even or 1, else the full system is solved */
 } rt_solve_opts;
 
 typedef struct {
@@ -126,6 +132,9 @@ typedef struct {
     double ms_dir;       /* mean device time of one direction+operator kernel (sampled once per poll) */
     double ms_upd;       /* mean device time of one update kernel (sampled likewise) */
     int kernel_samples;  /* number of samples behind ms_dir / ms_upd */
+    int reduced;         /* 1 if the red-black reduced system was solved (iters count its
+                            iterations; ms_dir then covers its red and black passes) */
+    double ms_black;     /* reduced solves: mean device time of the black pass alone */
 } rt_solve_stats;
 
 typedef struct {

@@ -109,6 +109,7 @@ struct Row {
     bool jp, jm;    // theta neighbours exist
     bool kk;        // phi neighbours exist (N_phi > 1)
     long kp, km;    // offsets of the phi neighbours (periodic)
+    int par;        // (j + k) & 1 (the colouring of the red-black kernels)
 };
 
 // Calls f(row, i) for every VW-cell segment (cells i .. i+VW-1 of a row) owned by the
@@ -158,6 +159,7 @@ __device__ __forceinline__ void for_segments(const Dims &d, int nblk, F &&f)
         rw.kk = d.np > 1;
         rw.kp = (k + 1 < d.np) ? pl : -wrap;
         rw.km = (k > 0) ? -pl : wrap;
+        rw.par = (j + k) & 1;
         for (int i = i0; i < d.nr; i += istep) f(rw, i);
         jb += dj;
         k += dk;
@@ -664,6 +666,305 @@ void launch_unscale(long n, const float *zn, const double *scale, float *z, hipS
 void launch_fold(long n, const float *x32, double *y, hipStream_t st)
 {
     hipLaunchKernelGGL(k_fold, dim3((unsigned)((n + kKB - 1) / kKB)), dim3(kKB), 0, st, n, x32, y);
+}
+
+
+// ------------------------------------------------------ red-black reduced system
+//
+// Colour the cells black ((i + j + k) even) and red (odd).  The 7-point operator only
+// couples cells of different colours (with N_phi even or 1, so that the periodic phi
+// seam also joins opposite colours), so in that ordering A^ = [I B; B^T I] with B the
+// red-black couplings.  Eliminating the red unknowns leaves
+//   S y_b = b_b - B^T b_r,   S = I - B^T B,   then   y_r = b_r - B y_b,
+// with S symmetric positive definite and cond(S) = cond(A^) / (1 + ||B||)^2, about a
+// quarter: CG on S needs about half the iterations of CG on A^, and one product with S
+// (a pass over the red cells, t = B p, then one over the black cells, q = p - B^T t)
+// moves about the bytes of one product with A^, because each pass reads every face
+// coefficient once and half of the vector entries.  The residual of S is the residual
+// of A^ once y_r is formed, so the stopping test is unchanged.
+// Layout: each colour is stored compactly with H = N_r / 2 cells per radial row; the
+// half index g = h + H (j + N_theta k) holds the cell i = 2h + par of row (j, k), par =
+// (j + k) & 1 for black and 1 - that for red.  ab[col][dir][g] is the outward r /
+// theta / phi coefficient of that cell (col 0 black, 1 red).  The kernels run over the
+// half grid Dims{H, N_theta, N_phi} with the row mapping of for_segments.
+
+// acc = sum over the six neighbours (all of the other colour) of coefficient x value,
+// for the VW cells h0 .. h0+VW-1 of row rw whose full radial index is 2h + par.  own /
+// oth are the outward coefficients ([3][n_half]) of this colour and of the other one;
+// seg(e, o) loads VW values of the other colour's vector at half index e, one(e) one
+// value.  Summation order: +r, -r, +theta, -theta, +phi, -phi.
+template <typename V, int VW, typename Seg, typename One>
+__device__ __forceinline__ void rb_couple(const Dims &dh, const Row &rw, int h0, int par, const V *__restrict__ own,
+                                          const V *__restrict__ oth, Seg &&seg, One &&one, V (&acc)[VW])
+{
+    const long nh = dh.n;
+    const int H = dh.nr;
+    const long g = rw.base + h0;
+    // radial: the right neighbour of cell m (i + 1) is the other colour's half h0+m+par,
+    // the left one (i - 1) is h0+m-1+par; the element beyond the aligned segment is
+    // h0+VW (par = 1, clamped at the row end where the own coefficient is 0) or h0-1
+    // (par = 0, absent at the row start, where the coefficient is masked)
+    V x[VW], co[VW], cl[VW];
+    seg(g, x);
+    vload<V, VW>(own + g, co);
+    vload<V, VW>(oth + g, cl);
+    const bool hasl = h0 > 0;
+    const long ge = par ? (h0 + VW < H ? g + VW : g + VW - 1) : (hasl ? g - 1 : g);
+    const V xe = one(ge);
+    const V ce = (!par && hasl) ? oth[ge] : V(0);
+    V xjp[VW], xjm[VW], xkp[VW], xkm[VW], ctp[VW], ctm[VW], cpp[VW], cpm[VW];
+    const long gjm = rw.jm ? g - H : g;
+    seg(rw.jp ? g + H : g, xjp);  // the own theta coefficient is 0 in the last polar row
+    seg(gjm, xjm);
+    seg(g + rw.kp, xkp);          // the offsets are 0 when N_phi = 1 (coefficients 0 then)
+    seg(g + rw.km, xkm);
+    vload<V, VW>(own + nh + g, ctp);
+    vload<V, VW>(oth + nh + gjm, ctm);
+    vload<V, VW>(own + 2 * nh + g, cpp);
+    vload<V, VW>(oth + 2 * nh + g + rw.km, cpm);
+    const V mjm = (V)rw.jm;
+#pragma unroll
+    for (int m = 0; m < VW; m++) {
+        const V right = par ? (m + 1 < VW ? x[m + 1] : xe) : x[m];
+        const V left = par ? x[m] : (m > 0 ? x[m - 1] : xe);
+        const V cleft = par ? cl[m] : (m > 0 ? cl[m - 1] : ce);
+        V v = co[m] * right;
+        v += cleft * left;
+        v += ctp[m] * xjp[m];
+        v += (ctm[m] * mjm) * xjm[m];
+        v += cpp[m] * xkp[m];
+        v += cpm[m] * xkm[m];
+        acc[m] = v;
+    }
+}
+
+// Red pass of a CG iteration on S: t_r = B p with p_b = r_b + beta p_old_b formed at
+// the neighbours (the black pass stores p_b).
+template <typename V, int VW>
+__global__ __launch_bounds__(kKB) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_rb_red_dir(
+    Dims dh, int nblk, const V *__restrict__ ab, const V *__restrict__ r, const V *__restrict__ pold,
+    V *__restrict__ t, DevScalars *sc)
+{
+    if (sc->done) return;
+    const V beta = (V)sc->beta;
+    const V *own = ab + 3 * dh.n, *oth = ab;
+    for_segments<VW>(dh, nblk, [&](const Row &rw, int h0) {
+        V acc[VW];
+        rb_couple<V, VW>(dh, rw, h0, 1 - rw.par, own, oth,
+                         [&](long e, V(&o)[VW]) { dir_seg<V, VW>(r, pold, beta, e, o); },
+                         [&](long e) { return dir_one(r, pold, beta, e); }, acc);
+        vstore<V, VW>(t + rw.base + h0, acc);
+    });
+}
+
+// Black pass: p_b = r_b + beta p_old_b, q_b = p_b - B^T t_r, pq = p.q, alpha = rr / pq.
+template <typename V, int VW>
+__global__ __launch_bounds__(kKB) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_rb_black_dir(
+    Dims dh, int nblk, const V *__restrict__ ab, const V *__restrict__ r, const V *__restrict__ pold,
+    const V *__restrict__ t, V *__restrict__ pnew, V *__restrict__ q, double *partials, unsigned *counter,
+    DevScalars *sc)
+{
+    if (sc->done) return;
+    __shared__ double sh[kKB / 64];
+    const V beta = (V)sc->beta;
+    const V *own = ab, *oth = ab + 3 * dh.n;
+    const long L = logical_block(nblk);
+    double acc = 0.0;
+    for_segments<VW>(dh, nblk, [&](const Row &rw, int h0) {
+        const long g = rw.base + h0;
+        V pv[VW], bt[VW], qv[VW];
+        dir_seg<V, VW>(r, pold, beta, g, pv);
+        rb_couple<V, VW>(dh, rw, h0, rw.par, own, oth, [&](long e, V(&o)[VW]) { vload<V, VW>(t + e, o); },
+                         [&](long e) { return t[e]; }, bt);
+#pragma unroll
+        for (int m = 0; m < VW; m++) qv[m] = pv[m] - bt[m];
+        vstore<V, VW>(pnew + g, pv);
+        vstore<V, VW>(q + g, qv);
+#pragma unroll
+        for (int m = 0; m < VW; m++) acc += (double)pv[m] * (double)qv[m];
+    });
+    double bs = block_sum(acc, sh), tot;
+    if (finish_reduce(bs, L, nblk, partials, counter, sh, &tot) && threadIdx.x == 0) {
+        sc->pq = tot;
+        sc->alpha = sc->rr / tot;
+    }
+}
+
+// Float64 red pass: out_r = u_r + sgn (B x_b) (u may be NULL): t = B y_b for a true
+// residual, y_r = b_r - B y_b for the back substitution.
+template <typename V, int VW>
+__global__ __launch_bounds__(kKB) void k_rb_red_apply(Dims dh, int nblk, const double *__restrict__ ab,
+                                                      const double *__restrict__ x, const double *__restrict__ u,
+                                                      double sgn, double *__restrict__ out)
+{
+    const double *own = ab + 3 * dh.n, *oth = ab;
+    for_segments<VW>(dh, nblk, [&](const Row &rw, int h0) {
+        const long g = rw.base + h0;
+        double acc[VW], uv[VW];
+        rb_couple<double, VW>(dh, rw, h0, 1 - rw.par, own, oth,
+                              [&](long e, double(&o)[VW]) { vload<double, VW>(x + e, o); },
+                              [&](long e) { return x[e]; }, acc);
+        if (u) vload<double, VW>(u + g, uv);
+#pragma unroll
+        for (int m = 0; m < VW; m++) acc[m] = (u ? uv[m] : 0.0) + sgn * acc[m];
+        vstore<double, VW>(out + g, acc);
+    });
+}
+
+// Float64 black pass: out_b = u_b - x_b + sgn (B^T t_r) (x may be NULL) and res2 =
+// out.out, with the restart semantics of k_resid.  r_b = bb - y_b + B^T (B y_b) is the
+// residual of S; bb = b_b - B^T b_r the reduced right-hand side.
+template <typename V, int VW>
+__global__ __launch_bounds__(kKB) void k_rb_black_apply(Dims dh, int nblk, const double *__restrict__ ab,
+                                                        const double *__restrict__ t, const double *__restrict__ u,
+                                                        const double *__restrict__ x, double sgn,
+                                                        double *__restrict__ out, double *partials, unsigned *counter,
+                                                        DevScalars *sc, int restart)
+{
+    __shared__ double sh[kKB / 64];
+    const double *own = ab, *oth = ab + 3 * dh.n;
+    const long L = logical_block(nblk);
+    double acc = 0.0;
+    for_segments<VW>(dh, nblk, [&](const Row &rw, int h0) {
+        const long g = rw.base + h0;
+        double bt[VW], uv[VW], xv[VW];
+        rb_couple<double, VW>(dh, rw, h0, rw.par, own, oth,
+                              [&](long e, double(&o)[VW]) { vload<double, VW>(t + e, o); },
+                              [&](long e) { return t[e]; }, bt);
+        vload<double, VW>(u + g, uv);
+        if (x) vload<double, VW>(x + g, xv);
+#pragma unroll
+        for (int m = 0; m < VW; m++) {
+            double v = uv[m] - (x ? xv[m] : 0.0);
+            v += sgn * bt[m];
+            uv[m] = v;
+            acc += v * v;
+        }
+        vstore<double, VW>(out + g, uv);
+    });
+    double bs = block_sum(acc, sh), tot;
+    if (finish_reduce(bs, L, nblk, partials, counter, sh, &tot) && threadIdx.x == 0) {
+        sc->res2 = tot;
+        sc->inv_norm = tot > 0.0 ? 1.0 / sqrt(tot) : 0.0;
+        if (restart) {
+            sc->rr = tot;
+            sc->beta = 0.0;
+            sc->done = tot <= sc->thresh2 ? 1 : 0;
+        }
+    }
+}
+
+// Colour split of the assembled operator: ab[col][dir][g] (and its float copy) from the
+// natural outward coefficients a[dir][c]; one thread per natural cell.
+__global__ __launch_bounds__(kKB) void k_rb_split(Dims d, const double *__restrict__ a, double *__restrict__ ab,
+                                                  float *__restrict__ ab32)
+{
+    const long c = (long)blockIdx.x * kKB + threadIdx.x;
+    if (c >= d.n) return;
+    const int i = (int)(c % d.nr);
+    const long row = c / d.nr;
+    const int j = (int)(row % d.nt), k = (int)(row / d.nt);
+    const int col = (i + j + k) & 1;
+    const long nh = d.n / 2, g = (i >> 1) + (long)(d.nr / 2) * row;
+#pragma unroll
+    for (int dir = 0; dir < 3; dir++) {
+        const double v = a[dir * d.n + c];
+        ab[(col * 3 + dir) * nh + g] = v;
+        ab32[(col * 3 + dir) * nh + g] = (float)v;
+    }
+}
+
+// Natural vector x <-> its black and red halves (xb / xr may be NULL when gathering).
+__global__ __launch_bounds__(kKB) void k_rb_gather(Dims d, const double *__restrict__ x, double *__restrict__ xb,
+                                                   double *__restrict__ xr)
+{
+    const long c = (long)blockIdx.x * kKB + threadIdx.x;
+    if (c >= d.n) return;
+    const int i = (int)(c % d.nr);
+    const long row = c / d.nr;
+    const int j = (int)(row % d.nt), k = (int)(row / d.nt);
+    const long g = (i >> 1) + (long)(d.nr / 2) * row;
+    double *dst = ((i + j + k) & 1) ? xr : xb;
+    if (dst) dst[g] = x[c];
+}
+
+__global__ __launch_bounds__(kKB) void k_rb_scatter(Dims d, const double *__restrict__ xb,
+                                                    const double *__restrict__ xr, double *__restrict__ x)
+{
+    const long c = (long)blockIdx.x * kKB + threadIdx.x;
+    if (c >= d.n) return;
+    const int i = (int)(c % d.nr);
+    const long row = c / d.nr;
+    const int j = (int)(row % d.nt), k = (int)(row / d.nt);
+    const long g = (i >> 1) + (long)(d.nr / 2) * row;
+    x[c] = ((i + j + k) & 1) ? xr[g] : xb[g];
+}
+
+Dims rb_half(const Dims &d)
+{
+    return Dims{d.nr / 2, d.nt, d.np, d.n / 2, (long)(d.nr / 2) * d.nt};
+}
+
+static unsigned grid1(long n) { return (unsigned)((n + kKB - 1) / kKB); }
+
+void launch_rb_split(const Dims &d, const double *a, double *ab, float *ab32, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rb_split, dim3(grid1(d.n)), dim3(kKB), 0, st, d, a, ab, ab32);
+}
+
+void launch_rb_gather(const Dims &d, const double *x, double *xb, double *xr, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rb_gather, dim3(grid1(d.n)), dim3(kKB), 0, st, d, x, xb, xr);
+}
+
+void launch_rb_scatter(const Dims &d, const double *xb, const double *xr, double *x, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rb_scatter, dim3(grid1(d.n)), dim3(kKB), 0, st, d, xb, xr, x);
+}
+
+void launch_rb_red_apply(const Dims &dh, int nblk, const double *ab, const double *x, const double *u, double sgn,
+                         double *out, hipStream_t st)
+{
+    RT_DISPATCH_VW(double, pick_vw<double>(dh), k_rb_red_apply, dim3(nblk), dim3(kKB), 0, st, dh, nblk, ab, x, u,
+                   sgn, out);
+}
+
+void launch_rb_black_apply(const Dims &dh, int nblk, const double *ab, const double *t, const double *u,
+                           const double *x, double sgn, double *out, double *partials, unsigned *counter,
+                           DevScalars *sc, int restart, hipStream_t st)
+{
+    RT_DISPATCH_VW(double, pick_vw<double>(dh), k_rb_black_apply, dim3(nblk), dim3(kKB), 0, st, dh, nblk, ab, t,
+                   u, x, sgn, out, partials, counter, sc, restart);
+}
+
+template <typename V>
+static void rb_iter(const Dims &dh, int nblk, int nblk_upd, const V *ab, V *y, V *r, V *pold, V *pnew, V *q, V *t,
+                    double *partials, unsigned *counter, DevScalars *sc, hipStream_t st, const hipEvent_t *ev)
+{
+    const int vw = pick_vw<V>(dh);
+    if (ev) (void)hipEventRecord(ev[0], st);
+    RT_DISPATCH_VW(V, vw, k_rb_red_dir, dim3(nblk), dim3(kKB), 0, st, dh, nblk, ab, r, pold, t, sc);
+    if (ev) (void)hipEventRecord(ev[3], st);
+    RT_DISPATCH_VW(V, vw, k_rb_black_dir, dim3(nblk), dim3(kKB), 0, st, dh, nblk, ab, r, pold, t, pnew, q, partials,
+                   counter, sc);
+    if (ev) (void)hipEventRecord(ev[1], st);
+    RT_DISPATCH_VW(V, vw, k_cg_upd, dim3(nblk_upd), dim3(kKB), 0, st, dh, nblk_upd, y, pnew, r, q, partials, counter,
+                   sc);
+    if (ev) (void)hipEventRecord(ev[2], st);
+}
+
+void launch_rb_iter64(const Dims &dh, int nblk, int nblk_upd, const double *ab, double *y, double *r, double *pold,
+                      double *pnew, double *q, double *t, double *partials, unsigned *counter, DevScalars *sc,
+                      hipStream_t st, const hipEvent_t *ev)
+{
+    rb_iter<double>(dh, nblk, nblk_upd, ab, y, r, pold, pnew, q, t, partials, counter, sc, st, ev);
+}
+
+void launch_rb_iter32(const Dims &dh, int nblk, int nblk_upd, const float *ab, float *x, float *r, float *pold,
+                      float *pnew, float *q, float *t, double *partials, unsigned *counter, DevScalars *sc,
+                      hipStream_t st, const hipEvent_t *ev)
+{
+    rb_iter<float>(dh, nblk, nblk_upd, ab, x, r, pold, pnew, q, t, partials, counter, sc, st, ev);
 }
 
 // ---------------------------------------------------------------- GMRES(m)

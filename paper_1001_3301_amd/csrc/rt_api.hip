@@ -483,6 +483,7 @@ rt_status rt_fld_assemble(rt_ctx *ctx, const rt_opacity *op, const rt_fld_params
                     ctx->w, ctx->s, ctx->b, ctx->bhat, ctx->ahat, ctx->ahat32, ctx->stream);
     RT_HIP(ctx, hipGetLastError());
     ctx->have_system = true;
+    ctx->rb_ready = false;
     if (sys) {
         sys->n = ctx->d.n;
         sys->ahat = ctx->ahat;
@@ -517,15 +518,18 @@ struct Clock {
     }
 };
 
-// Adds the device times of the sampled iteration (events 8, 9, 10) to the stats.
-void add_kernel_sample(rt_ctx *ctx, rt_solve_stats *st)
+// Adds the device times of the sampled iteration (events 8, 9, 10; 11 between the red
+// and black passes of a reduced solve) to the stats.
+void add_kernel_sample(rt_ctx *ctx, rt_solve_stats *st, bool rb = false)
 {
-    float a = 0.f, b = 0.f;
+    float a = 0.f, b = 0.f, c = 0.f;
     if (hipEventElapsedTime(&a, ctx->ev[8], ctx->ev[9]) != hipSuccess) return;
     if (hipEventElapsedTime(&b, ctx->ev[9], ctx->ev[10]) != hipSuccess) return;
+    if (rb && hipEventElapsedTime(&c, ctx->ev[11], ctx->ev[9]) != hipSuccess) return;
     int n = st->kernel_samples;
     st->ms_dir = (st->ms_dir * n + a) / (n + 1);
     st->ms_upd = (st->ms_upd * n + b) / (n + 1);
+    st->ms_black = (st->ms_black * n + c) / (n + 1);
     st->kernel_samples = n + 1;
 }
 
@@ -667,6 +671,189 @@ rt_status solve_mixed(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, d
         o64.mode = RT_SOLVE_FP64;
         o64.max_iter = std::max(1, o->max_iter - st->iters);
         status = solve_fp64(ctx, &o64, &s64, bb);
+        st->iters += s64.iters;
+        st->relres = s64.relres;
+    }
+    return status;
+}
+
+// The red-black reduced system (k_krylov.hip): CG on S = I - B^T B over the black
+// cells, then y_r = b_r - B y_b.  Needs N_r even (compact colour halves per radial
+// row) and N_phi even or 1 (the periodic seam joins opposite colours).
+bool rb_possible(const rt_ctx *ctx)
+{
+    return ctx->d.nr % 2 == 0 && (ctx->d.np == 1 || ctx->d.np % 2 == 0) && ctx->d.nr >= 2;
+}
+
+// Colour split of the current operator (once per assembled system), the reduced
+// right-hand side bb = b_b - B^T b_r and b_r in `rhs` ([bb | b_r], n/2 each), and y_b
+// gathered from the natural start vector ctx->y.  `tmp` (n/2) holds b_b on the way.
+rt_status rb_prepare(rt_ctx *ctx, double *rhs, double *yb, double *tmp)
+{
+    const Dims &d = ctx->d;
+    const long n = d.n, nh = n / 2;
+    if (!ctx->rb_a) {
+        ctx->rb_a = dalloc<double>(ctx, 3 * n);
+        ctx->rb_a32 = dalloc<float>(ctx, 3 * n);
+        if (!ctx->rb_a || !ctx->rb_a32) return fail(ctx, RT_ENOMEM, "red-black split: out of device memory");
+    }
+    hipStream_t s = ctx->stream;
+    if (!ctx->rb_ready) {
+        launch_rb_split(d, ctx->ahat, ctx->rb_a, ctx->rb_a32, s);
+        ctx->rb_ready = true;
+    }
+    const Dims dh = rb_half(d);
+    launch_rb_gather(d, ctx->bhat, tmp, rhs + nh, s);
+    launch_rb_black_apply(dh, ctx->nblk, ctx->rb_a, rhs + nh, tmp, nullptr, -1.0, rhs, ctx->partials, ctx->counter,
+                          ctx->sc, 0, s);
+    launch_rb_gather(d, ctx->y, yb, nullptr, s);
+    RT_HIP(ctx, hipGetLastError());
+    return RT_OK;
+}
+
+// r_b = bb - S y_b in float64 (t_r receives B y_b); restart as in k_resid.
+void rb_resid(rt_ctx *ctx, const double *rhs, const double *yb, double *rb, double *tr, int restart)
+{
+    const Dims dh = rb_half(ctx->d);
+    launch_rb_red_apply(dh, ctx->nblk, ctx->rb_a, yb, nullptr, 1.0, tr, ctx->stream);
+    launch_rb_black_apply(dh, ctx->nblk, ctx->rb_a, tr, rhs, yb, 1.0, rb, ctx->partials, ctx->counter, ctx->sc,
+                          restart, ctx->stream);
+}
+
+// y_r = b_r - B y_b, and the natural solution ctx->y from both halves.
+rt_status rb_finish(rt_ctx *ctx, const double *rhs, const double *yb, double *yr)
+{
+    const Dims dh = rb_half(ctx->d);
+    const long nh = ctx->d.n / 2;
+    launch_rb_red_apply(dh, ctx->nblk, ctx->rb_a, yb, rhs + nh, -1.0, yr, ctx->stream);
+    launch_rb_scatter(ctx->d, yb, yr, ctx->y, ctx->stream);
+    RT_HIP(ctx, hipGetLastError());
+    return RT_OK;
+}
+
+// Float64 CG on the reduced system (the same stopping test as solve_fp64: the true
+// residual of S is the residual of A^ after the back substitution).  Workspace: the
+// halves of the full-system Krylov vectors.
+rt_status solve_fp64_rb(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb)
+{
+    const Dims dh = rb_half(ctx->d);
+    const long nh = dh.n;
+    hipStream_t s = ctx->stream;
+    DevScalars *h = ctx->h_sc;
+    double *rb = ctx->r, *tr = ctx->r + nh, *pold = ctx->p0, *pnew = ctx->p0 + nh;
+    double *qb = ctx->qv, *yb = ctx->qv + nh, *rhs = ctx->p1;
+    if (rt_status e = rb_prepare(ctx, rhs, yb, rb)) return e;
+    h->thresh2 = o->tol * o->tol * bb;
+    h->done = 0;
+    h->iters = 0;
+    h->beta = 0.0;
+    if (rt_status e = write_scalars(ctx)) return e;
+    rb_resid(ctx, rhs, yb, rb, tr, 1);
+    if (rt_status e = read_scalars(ctx)) return e;
+    const int every = o->check_every > 0 ? o->check_every : 32;
+    rt_status status = RT_OK;
+    double res = std::sqrt(h->res2 / bb);
+    for (;;) {
+        st->relres = res;
+        if (!isfin(res)) { status = RT_ENONFINITE; break; }
+        if (res <= o->tol) break;
+        if (h->iters >= o->max_iter) { status = RT_ENOCONV; break; }
+        int m = std::min(every, o->max_iter - h->iters);
+        int it_before = h->iters;
+        for (int k = 0; k < m; k++) {
+            launch_rb_iter64(dh, ctx->nblk, ctx->nblk_upd, ctx->rb_a, yb, rb, pold, pnew, qb, tr, ctx->partials,
+                             ctx->counter, ctx->sc, s, k == 0 ? &ctx->ev[8] : nullptr);
+            std::swap(pold, pnew);
+        }
+        RT_HIP(ctx, hipGetLastError());
+        if (rt_status e = read_scalars(ctx)) return e;
+        add_kernel_sample(ctx, st, true);
+        if ((h->iters - it_before) % 2 != m % 2) std::swap(pold, pnew);  // kernels that exited early
+        if (!isfin(h->rr)) { status = RT_ENONFINITE; st->relres = NAN; break; }
+        if (h->done || h->iters >= o->max_iter) {
+            rb_resid(ctx, rhs, yb, rb, tr, 1);
+            if (rt_status e = read_scalars(ctx)) return e;
+            res = std::sqrt(h->res2 / bb);
+        }
+    }
+    st->iters = h->iters;
+    st->reduced = 1;
+    if (rt_status e = rb_finish(ctx, rhs, yb, tr)) return e;
+    return status;
+}
+
+// Mixed precision on the reduced system: float32 CG on S with float64 reliable updates
+// (the scheme and guards of solve_mixed, iterations counted on S); a guard that trips
+// hands over to float64 CG on S from the current iterate.
+rt_status solve_mixed_rb(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb)
+{
+    const Dims dh = rb_half(ctx->d);
+    const long nh = dh.n;
+    hipStream_t s = ctx->stream;
+    DevScalars *h = ctx->h_sc;
+    double *rb = ctx->r, *tr = ctx->r + nh, *yb = ctx->qv + nh, *rhs = ctx->p1;
+    float *r32 = ctx->r32, *t32 = ctx->r32 + nh, *q32 = ctx->q32, *x32 = ctx->q32 + nh;
+    float *pold = ctx->p32a, *pnew = ctx->p32a + nh;
+    if (rt_status e = rb_prepare(ctx, rhs, yb, rb)) return e;
+    const double delta2 = 0.01;
+    const int kCycle = 2048;
+    h->iters = 0;
+    h->done = 0;
+    h->beta = 0.0;
+    h->thresh2 = o->tol * o->tol * bb;
+    if (rt_status e = write_scalars(ctx)) return e;
+    const int every = o->check_every > 0 ? o->check_every : 32;
+    rb_resid(ctx, rhs, yb, rb, tr, 0);
+    launch_reliable(dh, ctx->nblk, rb, r32, x32, ctx->partials, ctx->counter, ctx->sc, 1, s);
+    if (rt_status e = read_scalars(ctx)) return e;
+    double res = std::sqrt(h->res2 / bb), rr_ref = h->res2;
+    rt_status status = RT_OK;
+    int cycle_start = 0, bad = 0;
+    bool fallback = false;
+    for (;;) {
+        st->relres = res;
+        if (!isfin(res)) { status = RT_ENONFINITE; break; }
+        if (res <= o->tol) break;
+        if (h->iters >= o->max_iter) { status = RT_ENOCONV; break; }
+        if (bad >= 2) { fallback = true; break; }
+        int m = std::min(every, o->max_iter - h->iters);
+        int it_before = h->iters;
+        for (int k = 0; k < m; k++) {
+            launch_rb_iter32(dh, ctx->nblk, ctx->nblk_upd, ctx->rb_a32, x32, r32, pold, pnew, q32, t32, ctx->partials,
+                             ctx->counter, ctx->sc, s, k == 0 ? &ctx->ev[8] : nullptr);
+            std::swap(pold, pnew);
+        }
+        RT_HIP(ctx, hipGetLastError());
+        if (rt_status e = read_scalars(ctx)) return e;
+        add_kernel_sample(ctx, st, true);
+        if ((h->iters - it_before) % 2 != m % 2) std::swap(pold, pnew);  // kernels that exited early
+        if (!isfin(h->rr)) { status = RT_ENONFINITE; st->relres = NAN; break; }
+        const bool capped = h->iters - cycle_start >= kCycle;
+        if (h->done || h->rr <= delta2 * rr_ref || h->iters >= o->max_iter || capped) {
+            launch_fold(nh, x32, yb, s);
+            rb_resid(ctx, rhs, yb, rb, tr, 0);
+            launch_reliable(dh, ctx->nblk, rb, r32, x32, ctx->partials, ctx->counter, ctx->sc, 0, s);
+            RT_HIP(ctx, hipGetLastError());
+            if (rt_status e = read_scalars(ctx)) return e;
+            const double res_new = std::sqrt(h->res2 / bb);
+            bad = (res_new > 0.5 * res) ? bad + 1 : 0;
+            if (capped && res_new > o->tol) bad = 2;
+            res = res_new;
+            rr_ref = h->res2;
+            cycle_start = h->iters;
+            st->outer_iters++;
+        }
+    }
+    st->iters = h->iters;
+    st->reduced = 1;
+    if (rt_status e = rb_finish(ctx, rhs, yb, tr)) return e;
+    if (fallback) {
+        st->fallback = 1;
+        rt_solve_stats s64{};
+        rt_solve_opts o64 = *o;
+        o64.mode = RT_SOLVE_FP64;
+        o64.max_iter = std::max(1, o->max_iter - st->iters);
+        status = solve_fp64_rb(ctx, &o64, &s64, bb);
         st->iters += s64.iters;
         st->relres = s64.relres;
     }
@@ -881,8 +1068,9 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
     if (bb == 0.0) bb = 1.0;
     launch_scale_div(ctx->d.n, ctx->s, E, ctx->y, ctx->stream);  // y0 = E / s
     rt_status status;
-    if (o->mode == RT_SOLVE_FP64) status = solve_fp64(ctx, o, S, bb);
-    else if (o->mode == RT_SOLVE_MIXED) status = solve_mixed(ctx, o, S, bb);
+    const bool rb = o->reduce && rb_possible(ctx);
+    if (o->mode == RT_SOLVE_FP64) status = rb ? solve_fp64_rb(ctx, o, S, bb) : solve_fp64(ctx, o, S, bb);
+    else if (o->mode == RT_SOLVE_MIXED) status = rb ? solve_mixed_rb(ctx, o, S, bb) : solve_mixed(ctx, o, S, bb);
     else if (o->mode == RT_SOLVE_GMRES) status = solve_gmres(ctx, o, S, bb);
     else status = solve_learned(ctx, o, S, bb);
     if (status == RT_EDEVICE) return status;

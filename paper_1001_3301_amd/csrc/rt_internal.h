@@ -195,6 +195,23 @@ void launch_force(const Dims &d, const Geo &g, const double *w, const double *ch
 void launch_scale_mul(long n, const double *s, const double *x, double *y, hipStream_t st);
 void launch_scale_div(long n, const double *s, const double *x, double *y, hipStream_t st);
 void launch_fill(long n, double v, double *x, hipStream_t st);
+// Red-black reduced system (k_krylov.hip): half-grid dims, colour split of the operator
+// and of vectors, the passes of one product with S = I - B^T B, and one CG iteration on S.
+Dims rb_half(const Dims &d);
+void launch_rb_split(const Dims &d, const double *a, double *ab, float *ab32, hipStream_t st);
+void launch_rb_gather(const Dims &d, const double *x, double *xb, double *xr, hipStream_t st);
+void launch_rb_scatter(const Dims &d, const double *xb, const double *xr, double *x, hipStream_t st);
+void launch_rb_red_apply(const Dims &dh, int nblk, const double *ab, const double *x, const double *u, double sgn,
+                         double *out, hipStream_t st);
+void launch_rb_black_apply(const Dims &dh, int nblk, const double *ab, const double *t, const double *u,
+                           const double *x, double sgn, double *out, double *partials, unsigned *counter,
+                           DevScalars *sc, int restart, hipStream_t st);
+void launch_rb_iter64(const Dims &dh, int nblk, int nblk_upd, const double *ab, double *y, double *r, double *pold,
+                      double *pnew, double *q, double *t, double *partials, unsigned *counter, DevScalars *sc,
+                      hipStream_t st, const hipEvent_t *ev);
+void launch_rb_iter32(const Dims &dh, int nblk, int nblk_upd, const float *ab, float *x, float *r, float *pold,
+                      float *pnew, float *q, float *t, double *partials, unsigned *counter, DevScalars *sc,
+                      hipStream_t st, const hipEvent_t *ev);
 // max_c |T_c - Told_c| / Told_c into *out (device); partials needs nblk entries.
 void launch_max_change(long n, int nblk, const double *T, const double *Told, double *partials,
                        unsigned *counter, double *out, hipStream_t st);
@@ -302,6 +319,11 @@ struct rt_ctx {
     double *w = nullptr, *ahat = nullptr, *s = nullptr, *b = nullptr, *bhat = nullptr, *chi = nullptr;
     float *ahat32 = nullptr;
     bool have_system = false;
+    // colour split of ahat / ahat32 for the red-black reduced solves ([2][3][n/2] each),
+    // allocated at the first such solve and refreshed once per assembled system
+    double *rb_a = nullptr;
+    float *rb_a32 = nullptr;
+    bool rb_ready = false;
     double Eb = 0.0;  // a T_bc^4 of the assembled system
     // Krylov vectors
     double *y = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *qv = nullptr, *tmp = nullptr;

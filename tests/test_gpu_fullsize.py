@@ -189,3 +189,25 @@ def test_fullsize_mixed_solve_temperature(fullsize):
     T = F["T0"].clone()
     ctx.temperature(E, F["S"], T)
     assert float(((T - F["T1"]).abs() / F["T1"]).max()) <= 1e-6
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_fullsize_reduced_solve(fullsize, mode):
+    """The red-black reduced solves at full size: the full-system residual recomputed
+    outside the solver meets the tolerance, and the temperature agrees with the float64
+    solve's."""
+    from paper_1001_3301_amd import rt
+    wl, ctx, F, st = fullsize
+    E = F["En"].clone()
+    m = rt.MODE_FP64 if mode == "fp64" else rt.MODE_MIXED
+    rc, sr = ctx.solve(E, rt.solve_opts(m, tol=1e-8, max_iter=100000, reduce=1))
+    assert sr["reduced"] == 1 and sr["relres"] <= 1e-8
+    assert sr["iters"] < 0.7 * st["iters"], (sr["iters"], st["iters"])
+    y = E / F["s"]
+    Ay = torch.empty_like(y)
+    ctx.spmv(y, Ay)
+    relres = float(torch.linalg.vector_norm(F["bhat"] - Ay) / torch.linalg.vector_norm(F["bhat"]))
+    assert relres <= 1.05e-8, relres
+    T = F["T0"].clone()
+    ctx.temperature(E, F["S"], T)
+    assert float(((T - F["T1"]).abs() / F["T1"]).max()) <= 1e-6
