@@ -43,7 +43,9 @@ KERNEL_NAMES = {"fp64": "k_cg_dir<double>", "mixed": "k_cg_dir<float>", "fp64-rb
 # FETCH_SIZE (x2.0, calibrated on a kernel of known size) + WRITE_SIZE; the summary with
 # the commands is profiles/solver_kernels_clumpy-512x256x512-nu64.md.  Set to None when
 # the kernel changes.
-MEASURED_TRAFFIC = {("mixed", "clumpy-512x256x512-nu64"): 1.924e9, ("fp64", "clumpy-512x256x512-nu64"): 3.855e9}
+# The -rb entries are for k_rb_black_dir: profiles/rb_solver_kernels_clumpy-512x256x512-nu64.md.
+MEASURED_TRAFFIC = {("mixed", "clumpy-512x256x512-nu64"): 1.924e9, ("fp64", "clumpy-512x256x512-nu64"): 3.855e9,
+                    ("mixed-rb", "clumpy-512x256x512-nu64"): 1.507e9, ("fp64-rb", "clumpy-512x256x512-nu64"): 3.083e9}
 
 
 def log(*a):
