@@ -244,6 +244,14 @@ rt_status rt_step_fields(rt_ctx *ctx, const double **q_star, const double **S_ab
 rt_status rt_gray_table(const rt_opacity *op, const double *F_nu, double *kappa_gray, double *F_total,
                         double *nu_gray);
 
+/* Diagnostic of Sect. "The Flux Limited Diffusion approximation" (Fig. 8): the optical
+ * depth of the thermal emission integrated inward from the outer edge along each radial
+ * ray, tau_R = sum of kappa_R(T) rho (r_{i+1} - r_i) over the cells between a radial
+ * face and r_out.  Device arrays rho[n], T[n] in, tau_R[(N_r + 1) N_theta N_phi] out at
+ * the radial faces (face layout of rt_raytrace's F_face; 0 at r_out).  op may be NULL
+ * to use the context's table. */
+rt_status rt_rosseland_depth(rt_ctx *ctx, const rt_opacity *op, const double *rho, const double *T, double *tau_R);
+
 typedef struct {
     int steps;           /* main iterations taken */
     double last_change;  /* largest relative temperature change of the last step */

@@ -69,6 +69,7 @@ def lib():
         L.og_relax.argtypes = [P(_Grid), P(_Opac), P(_Star), P(_Fld), dp, dp, dp, C.c_int, C.c_double, C.c_int,
                                C.c_int, C.c_double, dp]
         L.og_gray_table.argtypes = [P(_Opac), dp, dp]
+        L.og_tau_rosseland.argtypes = [P(_Grid), P(_Opac), dp, dp, dp]
         L.og_gray_table.restype = C.c_double
         L.og_gmres.argtypes = [P(_Grid), dp, dp, dp, C.c_int, C.c_double, C.c_int, P(C.c_int), P(C.c_double)]
         L.og_spmv.argtypes = [P(_Grid), dp, dp, dp]
@@ -244,6 +245,14 @@ class Problem:
         k = lib().og_relax(C.byref(self.g), C.byref(self.op), C.byref(self.st), C.byref(self.fld), _p(rho),
                            _p(T), _p(E), m, tol, max_iter, max_steps, tol_change, C.byref(ch))
         return T, E, k, ch.value
+
+    def tau_rosseland(self, rho, T):
+        """Inward Rosseland optical depth at the radial faces ((N_r + 1) per column, 0 at r_out)."""
+        rho, T = _f64(rho).ravel(), _f64(T).ravel()
+        nr, nt, npp = self.shape
+        tau = np.empty((nr + 1) * nt * npp)
+        lib().og_tau_rosseland(C.byref(self.g), C.byref(self.op), _p(rho), _p(T), _p(tau))
+        return tau
 
     def gray_table(self, F):
         """(kappa_gray[n_T], sum F): the one-bin opacity table of gray irradiation."""

@@ -708,6 +708,29 @@ void og_force(const og_grid *g, const og_opac *op, const og_fld *f, const double
             }
 }
 
+/* ------------------------------------- Rosseland optical depth, Fig. 8 diagnostic */
+
+/*
+ * The thermal-emission optical depth of Sect. "The Flux Limited Diffusion
+ * approximation" (Fig. 8): tau_R(r) = sum of kappa_R(T) rho dr over the cells between r
+ * and the outer edge, integrated inward along each radial ray.  tau[(N_r + 1) per
+ * column] at the radial faces: tau at r_out is 0 and tau[i] = tau[i + 1] +
+ * kappa_R(T_i) rho_i (r_{i+1} - r_i).
+ */
+void og_tau_rosseland(const og_grid *g, const og_opac *op, const double *rho, const double *T, double *tau)
+{
+    int nr = g->nr;
+    for (int k = 0; k < g->np; k++)
+        for (int j = 0; j < g->nt; j++) {
+            double *t = tau + (long)(nr + 1) * (j + (long)g->nt * k);
+            t[nr] = 0.0;
+            for (int i = nr - 1; i >= 0; i--) {
+                long c = cidx(g, i, j, k);
+                t[i] = t[i + 1] + og_kappa_R(op, T[c]) * rho[c] * (g->rf[i + 1] - g->rf[i]);
+            }
+        }
+}
+
 /* ------------------------------------------------------ one step (Fig. 1) */
 
 /*

@@ -254,6 +254,47 @@ __global__ __launch_bounds__(kTB) void k_force(Dims d, Geo g, const double *__re
 }
 
 // y = s * x (E = s y) and y = x / s (start guess y0 = E^n / s).
+// Rosseland optical depth of the thermal emission integrated inward from the outer edge
+// (the Fig. 8 diagnostic): tau[i] = sum over cells i' >= i of kappa_R(T) rho dr at the
+// radial faces, tau[N_r] = 0.  One wavefront per radial column walks it from the outer
+// end in chunks of 64 cells (coalesced loads and stores); inside a chunk a suffix scan
+// by shuffles, across chunks a running carry, all in float64 in a fixed order.
+__global__ __launch_bounds__(kTB) void k_tau_rosseland(Dims d, Opac op, const double *__restrict__ rf,
+                                                       const double *__restrict__ rho, const double *__restrict__ T,
+                                                       double *__restrict__ tau)
+{
+    const long col = (long)blockIdx.x * (kTB / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (col >= (long)d.nt * d.np) return;  // whole wavefronts leave together
+    const long c0 = col * d.nr, f0 = col * (d.nr + 1);
+    if (lane == 0) tau[f0 + d.nr] = 0.0;
+    double carry = 0.0;
+    for (int e = d.nr; e > 0; e -= 64) {
+        const int s = e - 64 > 0 ? e - 64 : 0;
+        const int i = s + lane;
+        double v = 0.0;
+        if (i < e) {
+            const double t = T[c0 + i];
+            v = mean_opacity(op.T, op.lnT, op.kR, op.lnR, op.nT, t, nullptr) * rho[c0 + i] * (rf[i + 1] - rf[i]);
+        }
+        // suffix sum over the lanes l' >= l of this chunk
+        for (int off = 1; off < 64; off <<= 1) {
+            const double u = __shfl_down(v, off);
+            if (lane + off < 64) v += u;
+        }
+        if (i < e) tau[f0 + i] = carry + v;
+        carry += __shfl(v, 0);
+    }
+}
+
+void launch_tau_rosseland(const Dims &d, const Opac &op, const double *rf, const double *rho, const double *T,
+                          double *tau, hipStream_t st)
+{
+    const long cols = (long)d.nt * d.np;
+    const unsigned blocks = (unsigned)((cols + kTB / 64 - 1) / (kTB / 64));
+    hipLaunchKernelGGL(k_tau_rosseland, dim3(blocks), dim3(kTB), 0, st, d, op, rf, rho, T, tau);
+}
+
 // E = v in every cell: the runs without diffusion keep the thermal radiation field at
 // the background a T_bc^4.
 __global__ __launch_bounds__(kTB) void k_fill(long n, double v, double *__restrict__ x)

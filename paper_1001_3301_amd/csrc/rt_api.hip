@@ -1211,6 +1211,17 @@ rt_status rt_step_fields(rt_ctx *ctx, const double **q_star, const double **S_ab
     return RT_OK;
 }
 
+rt_status rt_rosseland_depth(rt_ctx *ctx, const rt_opacity *op, const double *rho, const double *T, double *tau_R)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    if (op) { rt_status s = rt_set_opacity(ctx, op); if (s) return s; }
+    RT_CHECK(ctx, ctx->have_opac, "no opacity table on the context");
+    RT_CHECK(ctx, rho && T && tau_R, "rt_rosseland_depth: NULL field pointer");
+    launch_tau_rosseland(ctx->d, ctx->op, ctx->geo.rf, rho, T, tau_R, ctx->stream);
+    RT_HIP(ctx, hipGetLastError());
+    return RT_OK;
+}
+
 rt_status rt_relax(rt_ctx *ctx, const rt_opacity *op, const rt_star *st, const rt_fld_params *p,
                    const rt_solve_opts *o, const double *rho, double *T, double *E, double tol_change,
                    int max_steps, rt_relax_stats *stats)

@@ -195,6 +195,9 @@ void launch_force(const Dims &d, const Geo &g, const double *w, const double *ch
 void launch_scale_mul(long n, const double *s, const double *x, double *y, hipStream_t st);
 void launch_scale_div(long n, const double *s, const double *x, double *y, hipStream_t st);
 void launch_fill(long n, double v, double *x, hipStream_t st);
+// Inward Rosseland optical depth at the radial faces ((N_r + 1) per column).
+void launch_tau_rosseland(const Dims &d, const Opac &op, const double *rf, const double *rho, const double *T,
+                          double *tau, hipStream_t st);
 // Red-black reduced system (k_krylov.hip): half-grid dims, colour split of the operator
 // and of vectors, the passes of one product with S = I - B^T B, and one CG iteration on S.
 Dims rb_half(const Dims &d);

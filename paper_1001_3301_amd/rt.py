@@ -94,7 +94,7 @@ class RelaxStats(C.Structure):
 EXPORTS = ["rt_create", "rt_destroy", "rt_last_error", "rt_ncell", "rt_star_bin_flux",
            "rt_set_opacity", "rt_set_star", "rt_raytrace", "rt_energy", "rt_fld_assemble",
            "rt_spmv", "rt_fld_solve", "rt_temperature", "rt_force", "rt_step", "rt_step_fields",
-           "rt_gray_table", "rt_relax",
+           "rt_gray_table", "rt_relax", "rt_rosseland_depth",
            "rt_net_create", "rt_net_destroy", "rt_net_last_error", "rt_net_param_count",
            "rt_net_get_params", "rt_net_get_grads", "rt_net_set_params", "rt_net_save", "rt_net_load",
            "rt_net_forward", "rt_net_loss_grad", "rt_net_loss_grad_resid", "rt_net_adam", "rt_dataset_create",
@@ -152,6 +152,7 @@ def lib():
                           P(StepStats)]
     L.rt_step_fields.argtypes = [vp, P(vp), P(vp), P(vp)]
     L.rt_gray_table.argtypes = [P(Opacity), dp, dp, dp, dp]
+    L.rt_rosseland_depth.argtypes = [vp, P(Opacity), vp, vp, vp]
     L.rt_relax.argtypes = [vp, P(Opacity), P(Star), P(FldParams), P(SolveOpts), vp, vp, vp, C.c_double,
                            C.c_int, P(RelaxStats)]
     fp = P(C.c_float)
@@ -378,6 +379,12 @@ class Context:
         if raise_on_error:
             self._chk(rc)
         return rc, st.as_dict()
+
+    def rosseland_depth(self, rho, T, tau):
+        """rt_rosseland_depth: inward tau_R at the radial faces ((N_r + 1) per column)."""
+        nr, nt, npp = self.shape
+        self._chk(lib().rt_rosseland_depth(self.h, None, self._dev(rho, self.n, "rho"), self._dev(T, self.n, "T"),
+                                           self._dev(tau, (nr + 1) * nt * npp, "tau")))
 
     def relax(self, rho, T, E, opts: SolveOpts, tol_change=1e-4, max_steps=10000, params=None,
               raise_on_error=True):

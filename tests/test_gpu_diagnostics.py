@@ -1,0 +1,116 @@
+"""Diagnostics: the inward Rosseland optical depth (Fig. 8) and a hot-star case whose
+irradiation sublimates the inner dust (the sublimation branch of the opacity table and
+of the Newton update, inside the main iteration).
+
+Parity against the oracle on the same seeded inputs: tau_R to 1e-13 relative (a
+suffix scan in a different but fixed summation order), on ragged, short and full-size
+columns; the hot-star main iteration step by step.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1001_3301_amd import synth as sy
+from _util import rel, seeded_temperature
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _d(x):
+    return torch.tensor(np.ascontiguousarray(x, dtype=np.float64).ravel(), device="cuda")
+
+
+def _h(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("shape", [(67, 13, 5), (24, 8, 3), (128, 4, 2), (2, 3, 2)])
+def test_rosseland_depth_parity(shape):
+    from paper_1001_3301_amd import rt
+    wl = sy.make_workload("t", *shape, 16, 100.0, clump_seed=6)
+    P = oracle.Problem.from_workload(wl)
+    ctx = rt.Context.from_workload(wl)
+    T = seeded_temperature(P.n, 11, 10.0, 2500.0)  # spans the sublimation drop of kappa_R
+    ref = P.tau_rosseland(wl.rho, T)
+    nr, nt, npp = shape
+    tau = torch.full(((nr + 1) * nt * npp,), np.nan, dtype=torch.float64, device="cuda")
+    ctx.rosseland_depth(_d(wl.rho), _d(T), tau)
+    torch.cuda.synchronize()
+    got = _h(tau)
+    assert np.all(got.reshape(npp, nt, nr + 1)[..., -1] == 0.0)
+    assert rel(got, ref) < 1e-13
+
+
+def test_rosseland_depth_fullsize_columns():
+    """At 512x256x512 in the benchmark's prepared state, sampled whole columns against the
+    oracle run on that one column (a column's tau_R depends only on its own cells)."""
+    from paper_1001_3301_amd import rt
+    name = "clumpy-512x256x512-nu64"
+    c = sy.CONFIGS[name]
+    wl = sy.make_workload(name, c["nr"], c["nt"], c["nph"], c["n_nu"], c["taus"][-1], c["seeds"][-1])
+    ctx = rt.Context.from_workload(wl)
+    n = ctx.n
+    nr, nt, npp = wl.grid.shape
+    rho = _d(wl.rho)
+    T = torch.full((n,), wl.T_bc, dtype=torch.float64, device="cuda")
+    q, S = torch.empty_like(T), torch.empty_like(T)
+    ctx.raytrace(rho, T, q, S)
+    ctx.temperature(torch.full((n,), sy.A_RAD * wl.T_bc ** 4, dtype=torch.float64, device="cuda"), S, T)
+    tau = torch.empty((nr + 1) * nt * npp, dtype=torch.float64, device="cuda")
+    ctx.rosseland_depth(rho, T, tau)
+    torch.cuda.synchronize()
+    tau = tau.view(npp, nt, nr + 1)
+    Tv, rv = T.view(npp, nt, nr), rho.view(npp, nt, nr)
+    g, op = wl.grid, wl.opacity
+    rng = np.random.Generator(np.random.PCG64(61))
+    cols = [(0, 0), (nt - 1, npp - 1), (nt // 2, 0), (nt // 2 - 1, npp // 2)] + \
+        [(int(rng.integers(nt)), int(rng.integers(npp))) for _ in range(12)]
+    for j, k in cols:
+        P = oracle.Problem(g.r_face, g.th_face[j:j + 2], g.ph_face[k:k + 2], op.T, op.kappa, op.kappa_P,
+                           op.kappa_R, R_star=wl.R_star, T_star=wl.T_star)
+        ref = P.tau_rosseland(_h(rv[k, j]), _h(Tv[k, j]))
+        assert rel(_h(tau[k, j]), ref) < 1e-13, (j, k)
+
+
+def _hot(shape=(32, 8, 1)):
+    """A hot, large star (T_* = 2e4 K, R_* = 5 R_sun) irradiating the tau550 = 100 disk:
+    the first main iteration heats the innermost cells beyond the 1500 K sublimation
+    drop of the table."""
+    wl = sy.make_workload("hot", *shape, 16, 100.0, dt=1e4)
+    wl.T_star, wl.R_star = 2.0e4, 5.0 * sy.R_STAR
+    return wl
+
+
+def test_hot_star_sublimation_main_iteration():
+    """Main iterations without diffusion from T_bc under the hot star, step by step
+    against the oracle: the inner cells sublimate in the first step (their smallest
+    root of Eq. 16 lies above the drop), the now transparent cells let the irradiation
+    through to the next ones, and with the opacity lagged by one step the front
+    alternates between two states from the second step on (steps 4 and 5 repeat steps 2
+    and 3): the loop reports that it did not settle (RT_ENOCONV) instead of returning a
+    state."""
+    from paper_1001_3301_amd import rt
+    wl = _hot()
+    P = oracle.Problem.from_workload(wl)
+    ctx = rt.Context.from_workload(wl)
+    rho = _d(wl.rho)
+    T0 = np.full(P.n, wl.T_bc)
+    T = _d(T0)
+    E = torch.empty_like(T)
+    states = []
+    for k in range(1, 6):
+        rc, st = ctx.relax(rho, T, E, rt.solve_opts(rt.MODE_NONE), tol_change=1e-4, max_steps=1,
+                           raise_on_error=False)
+        assert rc == rt.RT_ENOCONV and st["steps"] == 1
+        Tr, _, _, _ = P.relax(wl.rho, T0, mode="none", max_steps=k, tol_change=1e-4)
+        Tg = _h(T)
+        assert rel(Tg, Tr) < 1e-10, k
+        assert np.array_equal(Tg >= 1500.0, Tr >= 1500.0), k
+        states.append(Tg)
+    assert np.sum(states[0] >= 1500.0) > 0  # the first step sublimates
+    assert rel(states[3], states[1]) < 1e-12 and rel(states[4], states[2]) < 1e-12
+    assert rel(states[2], states[1]) > 0.5
+    T = _d(T0)
+    rc, st = ctx.relax(rho, T, E, rt.solve_opts(rt.MODE_NONE), tol_change=1e-4, max_steps=50, raise_on_error=False)
+    assert rc == rt.RT_ENOCONV and st["steps"] == 50 and st["last_change"] > 1.0

@@ -561,3 +561,33 @@ def test_main_iteration_fixed_point_conserves_luminosity(shape, gray):
     # the pure-absorption run of the same disk is the first step's irradiation balance
     Tn, _, kn, _ = P.relax(rho, np.full(P.n, wl.T_bc), mode="none", tol_change=1e-4)
     assert kn == 2 and np.all(Tn <= T * (1 + 1e-12))  # re-emission only adds heat
+
+
+# ------------------------------------------------ Rosseland optical depth (Fig. 8)
+
+def test_rosseland_depth_closed_form():
+    """tau_R integrated inward from r_out: with a constant kappa_R and the cell-averaged
+    1/r density it is kappa rho0 r0 ln(r_out / r) at every face; with the power-law table
+    and a temperature that varies along the ray it is the sum of the Gamma-zeta closed
+    form of kappa_R(T) (log-log lookup exact below sublimation) times rho dr."""
+    g = sy.make_grid(40, 3, 2)
+    nu = sy.frequencies(8)
+    op = _gray_opacity(nu, kappa=7.0)
+    P = _problem(g, op)
+    rho = _powerlaw_column_density(g, 1e-19, sy.AU)
+    tau = P.tau_rosseland(rho, np.full(P.n, 100.0)).reshape(2, 3, 41)
+    rf = g.r_face
+    ref = 7.0 * 1e-19 * sy.AU * np.log(rf[-1] / rf)
+    assert np.all(tau[..., -1] == 0.0)
+    assert np.max(np.abs(tau[..., :-1] / ref[:-1] - 1)) < 1e-12
+    # varying T along the ray with the power-law table
+    op = sy.make_opacity(nu)
+    P = _problem(g, op)
+    T = np.broadcast_to(np.geomspace(1200.0, 20.0, 40), (2, 3, 40)).ravel()
+    rho = np.broadcast_to(np.geomspace(1e-16, 1e-20, 40), (2, 3, 40)).ravel()
+    x = sy.K_BOLTZ * T[:40] / (sy.H_PLANCK * sy.NU_550)
+    kR = sy.KAPPA0 * x ** 1.5 * gamma(5) * zeta(4) / (gamma(3.5) * zeta(2.5))
+    d = kR * rho[:40] * np.diff(rf)
+    ref = np.concatenate([np.cumsum(d[::-1])[::-1], [0.0]])
+    tau = P.tau_rosseland(rho, T).reshape(2, 3, 41)
+    assert np.max(np.abs(tau - ref) / np.maximum(ref, 1e-300)) < 1e-9
