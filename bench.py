@@ -191,7 +191,7 @@ def run_main_loop(rt, torch, sy, shape=(64, 64, 1), n_nu=64, tol_change=1e-4):
         rho = torch.tensor(wl.rho.ravel(), device="cuda")
         T = torch.full((ctx.n,), wl.T_bc, dtype=torch.float64, device="cuda")
         E = torch.empty_like(T)
-        o = rt.solve_opts(rt.MODE_FP64, tol=1e-8) if fld else rt.solve_opts(rt.MODE_NONE)
+        o = rt.solve_opts(rt.MODE_FP64, tol=1e-8, reduce=1) if fld else rt.solve_opts(rt.MODE_NONE)
         t = time.perf_counter()
         rc, st = ctx.relax(rho, T, E, o, tol_change=tol_change, max_steps=5000, raise_on_error=False)
         torch.cuda.synchronize()
@@ -200,6 +200,10 @@ def run_main_loop(rt, torch, sy, shape=(64, 64, 1), n_nu=64, tol_change=1e-4):
                       "krylov_iters": st["krylov_iters"], "s": wall, "ms_per_step": wall / st["steps"] * 1e3}
         j = shape[1] // 2  # the cell row just below the equator
         mid[name] = T.view(shape[2], shape[1], shape[0])[0, j].cpu().numpy()
+        if fld:  # Fig. 8: the Rosseland depth through the midplane, inward from r_out
+            tau = torch.empty((shape[0] + 1) * shape[1] * shape[2], dtype=torch.float64, device="cuda")
+            ctx.rosseland_depth(rho, T, tau)
+            runs[name]["tau_R_midplane_r_in"] = float(tau.view(shape[2], shape[1], shape[0] + 1)[0, j, 0])
         log(f"main loop {name}: {runs[name]}")
         del ctx
     cmp = {}
@@ -207,8 +211,28 @@ def run_main_loop(rt, torch, sy, shape=(64, 64, 1), n_nu=64, tol_change=1e-4):
         r = mid[g] / mid[f] - 1.0
         cmp[f"{g}_vs_{f}"] = {"max_percent": float(r.max() * 100), "min_percent": float(r.min() * 100)}
     return {"workload": f"disk-2d {shape[0]}x{shape[1]}x{shape[2]} cells, {n_nu} bins, no clumps, dt=1e4 s, "
-                        f"stop when max |dT/T| < {tol_change:g}; FLD solves float64 CG to 1e-8",
+                        f"stop when max |dT/T| < {tol_change:g}; FLD solves reduced float64 CG to 1e-8",
             "runs": runs, "gray_vs_freq_midplane": cmp}
+
+
+def rosseland_depth_rate(ctx, torch, rho, T, reps=5):
+    """Time rt_rosseland_depth (one kernel) on the prepared state: ms per launch, its
+    algorithmic bytes (T and rho in, tau_R out at the faces) per second, and the
+    midplane tau_R at r_in."""
+    nr, nt, npp = ctx.shape
+    tau = torch.empty((nr + 1) * nt * npp, dtype=torch.float64, device="cuda")
+    ctx.rosseland_depth(rho, T, tau)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        ctx.rosseland_depth(rho, T, tau)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    nbytes = 16 * nr * nt * npp + 8 * (nr + 1) * nt * npp
+    gbs = nbytes / (ms / 1e3) / 1e9
+    return {"kernel": "k_tau_rosseland", "ms": ms, "achieved_GBs": gbs, "frac_of_8TBs": gbs / PEAK_HBM_GBS,
+            "bytes": nbytes, "tau_R_midplane_r_in": float(tau.view(npp, nt, nr + 1)[0, nt // 2, 0])}
 
 
 def oracle_baseline(wl, gpu_fp64_iters, slab=16, cg_iters=1000):
@@ -392,6 +416,7 @@ def main():
     if args.successive > 0:
         out["successive_steps"] = run_successive(ctx, rt, torch, rho, T0, head, args.successive, args.tol,
                                                  args.inner_tol, args.max_iter, net, args.learned_budget)
+    out["rosseland_depth"] = rosseland_depth_rate(ctx, torch, rho, T0)
     if not args.no_main_loop:
         out["main_iteration"] = run_main_loop(rt, torch, sy)
     if not args.no_cpu_baseline:
