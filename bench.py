@@ -275,7 +275,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="clumpy-512x256x512-nu64")
-    ap.add_argument("--modes", default="mixed-rb,fp64,mixed,fp64-rb,learned",
+    ap.add_argument("--modes", default="mixed-rb,fp64,mixed,fp64-rb,learned,learned-rb",
                     help="comma list; the first is the headline (suffix -rb: red-black reduced system)")
     ap.add_argument("--net", default="", help="load the network from this file instead of training it")
     ap.add_argument("--save-net", default="", help="save the trained network to this file")
@@ -283,6 +283,8 @@ def main():
     ap.add_argument("--train-epochs", type=int, default=6)
     ap.add_argument("--learned-budget", type=int, default=50,
                     help="network applications before the learned solve hands over to float64 CG")
+    ap.add_argument("--learned-rb-budget", type=int, default=5,
+                    help="the same for learned-rb, which hands over to the reduced mixed solve")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=200000)
@@ -331,7 +333,8 @@ def main():
 
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
     net, train_info = None, None
-    if "learned" in modes:
+    learned_modes = [m for m in modes if m.startswith("learned")]
+    if learned_modes:
         if args.net:
             net = rt.Net(seed=1)
             net.load(args.net)
@@ -343,8 +346,9 @@ def main():
         log(f"network: {train_info}")
     results = {}
     for mode in modes:
+        budget = args.learned_rb_budget if mode == "learned-rb" else args.learned_budget
         results[mode] = run_mode(ctx, rt, torch, rho, T0, mode, args.steps, args.warmup, args.tol,
-                                 args.inner_tol, args.max_iter, net, args.learned_budget)
+                                 args.inner_tol, args.max_iter, net, budget)
 
     head = modes[0]
     R = results[head]
@@ -395,18 +399,24 @@ def main():
         Rm = results[mode]
         out[f"{mode}_solve_s_per_step"] = statistics.median([s["solve"]["ms"] / 1e3 for s in Rm["stats"]])
         out[f"{mode}_iters_per_step"] = statistics.median([s["solve"]["iters"] for s in Rm["stats"]])
-    if "learned" in modes:
-        Rl = results["learned"]["stats"][-1]["solve"]
+    if learned_modes:
+        lm = learned_modes[0]
+        Rl = results[lm]["stats"][-1]["solve"]
         fwd_ms = unet_forward_ms(ctx, net, torch)
         tflops = UNET_FLOP_PER_CELL * n / (fwd_ms / 1e3) / 1e12
-        out["learned"] = {"network_applications": Rl["precond_applies"], "fallback": Rl["fallback"],
-                          "total_iters": Rl["iters"], "budget": args.learned_budget, "training": train_info,
-                          "unet_forward_ms": fwd_ms,
+        out["learned"] = {"mode": lm, "network_applications": Rl["precond_applies"], "fallback": Rl["fallback"],
+                          "total_iters": Rl["iters"],
+                          "budget": args.learned_rb_budget if lm == "learned-rb" else args.learned_budget,
+                          "training": train_info, "unet_forward_ms": fwd_ms,
                           "unet_roofline": {"kernel": "U-Net forward (k_conv_fwd and pooling, whole network)",
                                             "bound": "mfma", "achieved": tflops, "peak": PEAK_BF16_TFLOPS,
                                             "unit": "TFLOP/s", "frac": tflops / PEAK_BF16_TFLOPS,
                                             "flop_per_cell": UNET_FLOP_PER_CELL, "cells": n}}
-        if head == "learned":  # the network is the part of this mode the GPU is asked to run fast
+        for m in learned_modes[1:]:
+            Rm = results[m]["stats"][-1]["solve"]
+            out["learned"][m] = {"network_applications": Rm["precond_applies"], "total_iters": Rm["iters"],
+                                 "reduced_finish": Rm["reduced"]}
+        if head.startswith("learned"):  # the network is the part of this mode the GPU is asked to run fast
             out["roofline"] = dict(out["learned"]["unet_roofline"], traffic=None)
     if "fp64" in modes:
         Tf = results["fp64"]["T"]

@@ -118,7 +118,9 @@ typedef struct {
                             complement S = I - B^T B over the black cells, then recover the
                             red ones (the same solution and stopping test, about half the
                             iterations at the same bytes each); used when N_r is even and
-                            N_phi is even or 1, else the full system is solved */
+                            N_phi is even or 1, else the full system is solved.
+                            RT_SOLVE_LEARNED: 1 = the finish after the network budget is
+                            the reduced mixed solve instead of full-system float64 CG */
 } rt_solve_opts;
 
 typedef struct {

@@ -931,11 +931,23 @@ rt_status solve_learned(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
         st->fallback = 1;
         rt_solve_stats s64{};
         rt_solve_opts o64 = *o;
-        o64.mode = RT_SOLVE_FP64;
         o64.max_iter = std::max(1, o->max_iter - st->iters);
-        status = solve_fp64(ctx, &o64, &s64, bb);
+        if (o->reduce && rb_possible(ctx)) {
+            // finish with the reduced mixed solve (its own guards hand over to reduced float64)
+            o64.mode = RT_SOLVE_MIXED;
+            status = solve_mixed_rb(ctx, &o64, &s64, bb);
+            st->reduced = 1;
+            st->outer_iters += s64.outer_iters;
+        } else {
+            o64.mode = RT_SOLVE_FP64;
+            status = solve_fp64(ctx, &o64, &s64, bb);
+        }
         st->iters += s64.iters;
         st->relres = s64.relres;
+        st->ms_dir = s64.ms_dir;
+        st->ms_upd = s64.ms_upd;
+        st->ms_black = s64.ms_black;
+        st->kernel_samples = s64.kernel_samples;
     }
     return status;
 }

@@ -345,3 +345,23 @@ def test_what_the_trained_network_gains():
     rc, sf = ctx.solve(E, rt.solve_opts(rt.MODE_FP64, tol=1e-8))
     print(f"to 1e-8: learned (20 applications, then float64 CG) {sl['iters']} it, Jacobi CG {sf['iters']} it")
     assert sl["relres"] <= 1e-8 and sl["iters"] <= 1.1 * sf["iters"]
+
+
+def test_learned_solve_with_reduced_mixed_finish():
+    """reduce = 1 in the learned mode: after the network budget the reduced mixed solve
+    finishes; the answer meets the tolerance and its temperature agrees with the float64
+    solve's."""
+    from paper_1001_3301_amd import rt
+    wl, ctx, rho, T, En, S = _small_problem()
+    assert ctx.shape[0] % 2 == 0 and ctx.shape[2] % 2 == 0
+    net = rt.Net(seed=3)
+    E = En.clone()
+    rc, sl = ctx.solve(E, rt.solve_opts(rt.MODE_LEARNED, tol=1e-8, net=net, inner_max_iter=3, reduce=1))
+    assert sl["fallback"] == 1 and sl["reduced"] == 1 and sl["precond_applies"] == 3
+    assert sl["relres"] <= 1e-8
+    E_f = En.clone()
+    rc, sf = ctx.solve(E_f, rt.solve_opts(rt.MODE_FP64, tol=1e-10))
+    Tl, Tf = T.clone(), T.clone()
+    ctx.temperature(E, S, Tl)
+    ctx.temperature(E_f, S, Tf)
+    assert float(((Tl - Tf).abs() / Tf).max()) < 1e-5
