@@ -9,8 +9,10 @@
 // 1 - exp(-dtau)).  Per cell, the per-bin absorbed power Phi_b (1 - exp(-dtau_b)) and
 // the outgoing Phi_b are parked in LDS; every kChunk cells the wavefront transposes
 // and sums them over bins, so q, S and the face flux leave as coalesced r-contiguous
-// stores.  The opacity table sits in LDS; per-cell table coordinates are computed by
-// kChunk lanes and broadcast with readlane.
+// stores.  The opacity table and the radial geometry factors of the column sit in LDS;
+// the column is read in segments of 512 cells, each lane loading T and rho of 8 cells
+// with coalesced loads and computing their table node, weight and rho dr, which the
+// wavefront broadcasts with readlane as it reaches each cell.
 #include "rt_internal.h"
 
 namespace rt {
