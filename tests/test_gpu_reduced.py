@@ -50,6 +50,7 @@ CASES = {
     "thick-40x9x4": lambda: sy.make_workload("t", 40, 9, 4, 64, 100.0, clump_seed=3),
     "clumpy-34x12x6": lambda: sy.make_workload("c", 34, 12, 6, 16, 10.0, clump_seed=8),   # H = 17: one-cell segments
     "one-theta-row-16x1x8": lambda: sy.make_workload("o", 16, 1, 8, 8, 10.0, clump_seed=9),
+    "two-phi-20x6x2": lambda: sy.make_workload("p", 20, 6, 2, 8, 10.0, clump_seed=10),  # both phi faces join the same pair
 }
 
 
