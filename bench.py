@@ -32,20 +32,21 @@ PEAK_HBM_GBS = 8000.0
 # Algorithmic bytes per cell of one launch of each solver kernel (see the kernel comments):
 # dir: read r, p_old and the three off-diagonals, write p and q; upd: read y, p, r, q, write y, r.
 # Red-black reduced modes (-rb), per cell of the full grid: the red pass reads p's two
-# inputs at the black cells, every face coefficient once and writes t at the red cells
-# (36 / 18 B); the black pass reads the same plus t and writes p and q at the black cells
-# (44 / 22 B, i.e. 88 / 44 B per black cell); the update streams six half-size arrays.
+# inputs at the black cells and every face coefficient once, writes p at the black cells
+# and t at the red cells (20 / 40 B); the black pass reads p, t and every face
+# coefficient once and writes q (18 / 36 B); the update streams six half-size arrays.
 BYTES_PER_CELL = {"fp64": {"dir": 7 * 8, "upd": 6 * 8}, "mixed": {"dir": 7 * 4, "upd": 6 * 4},
-                  "fp64-rb": {"dir": 80, "upd": 24, "black": 44}, "mixed-rb": {"dir": 40, "upd": 12, "black": 22}}
-KERNEL_NAMES = {"fp64": "k_cg_dir<double>", "mixed": "k_cg_dir<float>", "fp64-rb": "k_rb_black_dir<double>",
-                "mixed-rb": "k_rb_black_dir<float>"}
+                  "fp64-rb": {"dir": 76, "upd": 24, "red": 40, "black": 36},
+                  "mixed-rb": {"dir": 38, "upd": 12, "red": 20, "black": 18}}
+KERNEL_NAMES = {"fp64": "k_cg_dir<double>", "mixed": "k_cg_dir<float>", "fp64-rb": ("k_rb_red_dir<double>",
+                "k_rb_black_dir<double>"), "mixed-rb": ("k_rb_red_dir<float>", "k_rb_black_dir<float>")}
 # HBM bytes per launch of these kernels on the 512x256x512 workload, from rocprofv3
 # FETCH_SIZE (x2.0, calibrated on a kernel of known size) + WRITE_SIZE; the summary with
 # the commands is profiles/solver_kernels_clumpy-512x256x512-nu64.md.  Set to None when
 # the kernel changes.
-# The -rb entries are for k_rb_black_dir: profiles/rb_solver_kernels_clumpy-512x256x512-nu64.md.
-MEASURED_TRAFFIC = {("mixed", "clumpy-512x256x512-nu64"): 1.924e9, ("fp64", "clumpy-512x256x512-nu64"): 3.855e9,
-                    ("mixed-rb", "clumpy-512x256x512-nu64"): 1.507e9, ("fp64-rb", "clumpy-512x256x512-nu64"): 3.083e9}
+# Keyed by kernel; profiles/rb_solver_kernels_clumpy-512x256x512-nu64.md for the reduced passes.
+MEASURED_TRAFFIC = {("k_cg_dir<float>", "clumpy-512x256x512-nu64"): 1.924e9,
+                    ("k_cg_dir<double>", "clumpy-512x256x512-nu64"): 3.855e9}
 
 
 def log(*a):
@@ -360,9 +361,16 @@ def main():
     ms_upd = sum(s["solve"]["ms_upd"] * s["solve"]["kernel_samples"] for s in R["stats"]) / max(samples, 1)
     ms_black = sum(s["solve"]["ms_black"] * s["solve"]["kernel_samples"] for s in R["stats"]) / max(samples, 1)
     bpc = BYTES_PER_CELL.get(head)
-    # the dominant kernel: the direction kernel, or the black pass of a reduced solve
-    dom_b, dom_ms, dom_cells = (bpc["black"] * 2, ms_black, n // 2) if (bpc and "black" in bpc) else \
-        ((bpc["dir"], ms_dir, n) if bpc else (0, 0.0, n))
+    # the dominant kernel: the direction kernel, or the longer of the red and black passes
+    # of a reduced solve (bytes per half-grid cell = twice the per-full-cell figure)
+    kname = KERNEL_NAMES.get(head)
+    if bpc and "black" in bpc:
+        ms_red = ms_dir - ms_black
+        red_dom = ms_red > ms_black
+        dom_b, dom_ms, dom_cells = (2 * bpc["red"], ms_red, n // 2) if red_dom else (2 * bpc["black"], ms_black, n // 2)
+        kname = kname[0] if red_dom else kname[1]
+    else:
+        dom_b, dom_ms, dom_cells = (bpc["dir"], ms_dir, n) if bpc else (0, 0.0, n)
     achieved = dom_b * dom_cells / (dom_ms / 1e3) / 1e9 if (bpc and dom_ms > 0) else 0.0
     out = {
         "metric": METRIC,
@@ -386,9 +394,9 @@ def main():
         "kernel_ms": {"dir": ms_dir, "upd": ms_upd, "black": ms_black, "samples": samples},
     }
     if bpc:
-        out["roofline"] = {"kernel": KERNEL_NAMES[head], "bound": "hbm", "achieved": achieved,
+        out["roofline"] = {"kernel": kname, "bound": "hbm", "achieved": achieved,
                            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                           "traffic": MEASURED_TRAFFIC.get((head, args.config)), "bytes_per_cell": dom_b,
+                           "traffic": MEASURED_TRAFFIC.get((kname, args.config)), "bytes_per_cell": dom_b,
                            "cells_per_launch": dom_cells}
         if ms_dir > 0 and ms_upd > 0:
             # one whole Krylov iteration (both kernels): its algorithmic bytes over the two launch times

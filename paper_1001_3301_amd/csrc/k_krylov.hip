@@ -680,7 +680,8 @@ void launch_fold(long n, const float *x32, double *y, hipStream_t st)
 // quarter: CG on S needs about half the iterations of CG on A^, and one product with S
 // (a pass over the red cells, t = B p, then one over the black cells, q = p - B^T t)
 // moves about the bytes of one product with A^, because each pass reads every face
-// coefficient once and half of the vector entries.  The residual of S is the residual
+// coefficient once and half of the vector entries (the red pass forms p and stores it
+// for the black pass and the update).  The residual of S is the residual
 // of A^ once y_r is formed, so the stopping test is unchanged.
 // Layout: each colour is stored compactly with H = N_r / 2 cells per radial row; the
 // half index g = h + H (j + N_theta k) holds the cell i = 2h + par of row (j, k), par =
@@ -739,46 +740,48 @@ __device__ __forceinline__ void rb_couple(const Dims &dh, const Row &rw, int h0,
 }
 
 // Red pass of a CG iteration on S: t_r = B p with p_b = r_b + beta p_old_b formed at
-// the neighbours (the black pass stores p_b).
+// the neighbours.  The black segment at the same half indices as the red one (its
+// aligned radial neighbours) is stored as p_b: the segments of the pass cover every
+// black half index once, so the black pass reads p_b instead of forming it again.
 template <typename V, int VW>
 __global__ __launch_bounds__(kKB) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_rb_red_dir(
     Dims dh, int nblk, const V *__restrict__ ab, const V *__restrict__ r, const V *__restrict__ pold,
-    V *__restrict__ t, DevScalars *sc)
+    V *__restrict__ pnew, V *__restrict__ t, DevScalars *sc)
 {
     if (sc->done) return;
     const V beta = (V)sc->beta;
     const V *own = ab + 3 * dh.n, *oth = ab;
     for_segments<VW>(dh, nblk, [&](const Row &rw, int h0) {
-        V acc[VW];
+        const long g = rw.base + h0;
+        V ps[VW], acc[VW];
+        dir_seg<V, VW>(r, pold, beta, g, ps);
+        vstore<V, VW>(pnew + g, ps);
         rb_couple<V, VW>(dh, rw, h0, 1 - rw.par, own, oth,
                          [&](long e, V(&o)[VW]) { dir_seg<V, VW>(r, pold, beta, e, o); },
                          [&](long e) { return dir_one(r, pold, beta, e); }, acc);
-        vstore<V, VW>(t + rw.base + h0, acc);
+        vstore<V, VW>(t + g, acc);
     });
 }
 
-// Black pass: p_b = r_b + beta p_old_b, q_b = p_b - B^T t_r, pq = p.q, alpha = rr / pq.
+// Black pass: q_b = p_b - B^T t_r (p_b from the red pass), pq = p.q, alpha = rr / pq.
 template <typename V, int VW>
 __global__ __launch_bounds__(kKB) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_rb_black_dir(
-    Dims dh, int nblk, const V *__restrict__ ab, const V *__restrict__ r, const V *__restrict__ pold,
-    const V *__restrict__ t, V *__restrict__ pnew, V *__restrict__ q, double *partials, unsigned *counter,
-    DevScalars *sc)
+    Dims dh, int nblk, const V *__restrict__ ab, const V *__restrict__ p, const V *__restrict__ t,
+    V *__restrict__ q, double *partials, unsigned *counter, DevScalars *sc)
 {
     if (sc->done) return;
     __shared__ double sh[kKB / 64];
-    const V beta = (V)sc->beta;
     const V *own = ab, *oth = ab + 3 * dh.n;
     const long L = logical_block(nblk);
     double acc = 0.0;
     for_segments<VW>(dh, nblk, [&](const Row &rw, int h0) {
         const long g = rw.base + h0;
         V pv[VW], bt[VW], qv[VW];
-        dir_seg<V, VW>(r, pold, beta, g, pv);
+        vload<V, VW>(p + g, pv);
         rb_couple<V, VW>(dh, rw, h0, rw.par, own, oth, [&](long e, V(&o)[VW]) { vload<V, VW>(t + e, o); },
                          [&](long e) { return t[e]; }, bt);
 #pragma unroll
         for (int m = 0; m < VW; m++) qv[m] = pv[m] - bt[m];
-        vstore<V, VW>(pnew + g, pv);
         vstore<V, VW>(q + g, qv);
 #pragma unroll
         for (int m = 0; m < VW; m++) acc += (double)pv[m] * (double)qv[m];
@@ -943,10 +946,10 @@ static void rb_iter(const Dims &dh, int nblk, int nblk_upd, const V *ab, V *y, V
 {
     const int vw = pick_vw<V>(dh);
     if (ev) (void)hipEventRecord(ev[0], st);
-    RT_DISPATCH_VW(V, vw, k_rb_red_dir, dim3(nblk), dim3(kKB), 0, st, dh, nblk, ab, r, pold, t, sc);
+    RT_DISPATCH_VW(V, vw, k_rb_red_dir, dim3(nblk), dim3(kKB), 0, st, dh, nblk, ab, r, pold, pnew, t, sc);
     if (ev) (void)hipEventRecord(ev[3], st);
-    RT_DISPATCH_VW(V, vw, k_rb_black_dir, dim3(nblk), dim3(kKB), 0, st, dh, nblk, ab, r, pold, t, pnew, q, partials,
-                   counter, sc);
+    RT_DISPATCH_VW(V, vw, k_rb_black_dir, dim3(nblk), dim3(kKB), 0, st, dh, nblk, ab, (const V *)pnew, (const V *)t, q,
+                   partials, counter, sc);
     if (ev) (void)hipEventRecord(ev[1], st);
     RT_DISPATCH_VW(V, vw, k_cg_upd, dim3(nblk_upd), dim3(kKB), 0, st, dh, nblk_upd, y, pnew, r, q, partials, counter,
                    sc);
