@@ -66,12 +66,13 @@ PEAK_BF16_TFLOPS = 2500.0
 
 
 def mode_opts(rt, mode, tol, max_iter, inner_tol, net=None, budget=0, restart=30):
-    """Solve options of a bench mode; the suffix -rb solves the red-black reduced system."""
-    base = mode[:-3] if mode.endswith("-rb") else mode
+    """Solve options of a bench mode; the suffix -rb solves the red-black reduced system,
+    -line preconditions float64 CG with the radial-line block Jacobi."""
+    base = mode.split("-")[0]
     m = {"fp64": rt.MODE_FP64, "mixed": rt.MODE_MIXED, "learned": rt.MODE_LEARNED, "gmres": rt.MODE_GMRES}[base]
     return rt.solve_opts(m, tol=tol, max_iter=max_iter, check_every=32, inner_tol=inner_tol,
                          inner_max_iter=budget if base == "learned" else 0, net=net if base == "learned" else None,
-                         restart=restart, reduce=int(mode.endswith("-rb")))
+                         restart=restart, reduce=int(mode.endswith("-rb")), precond=int(mode.endswith("-line")))
 
 
 def train_network(rt, torch, sy, n_fields, epochs, seed=7):
@@ -387,7 +388,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "mixed": "f32+f64", "learned": "bf16+f32+f64", "gmres": "f64"}[head.replace("-rb", "")],
+        "dtype": {"fp64": "f64", "mixed": "f32+f64", "learned": "bf16+f32+f64", "gmres": "f64"}[head.split("-")[0]],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {wl.grid.shape[0]}x{wl.grid.shape[1]}x{wl.grid.shape[2]} cells, "
                                f"{c['n_nu']} bins, tau550={wl.tau550:g}, clumps seed {c['seeds'][-1]}",

@@ -121,6 +121,11 @@ typedef struct {
                             N_phi is even or 1, else the full system is solved.
                             RT_SOLVE_LEARNED: 1 = the finish after the network budget is
                             the reduced mixed solve instead of full-system float64 CG */
+    int precond;         /* RT_SOLVE_FP64 without reduce: 0 = the Jacobi scaling alone (the
+                            default), 1 = CG preconditioned by the radial-line block Jacobi:
+                            each radial row's tridiagonal block of A^ solved exactly (the
+                            block-Jacobi class of the paper's solver set-up, Sect. "Numerical
+                            setup", as a comparator) */
 } rt_solve_opts;
 
 typedef struct {
@@ -245,6 +250,11 @@ rt_status rt_step_fields(rt_ctx *ctx, const double **q_star, const double **S_ab
  * gray variant of every call above.  Host computation, no device work. */
 rt_status rt_gray_table(const rt_opacity *op, const double *F_nu, double *kappa_gray, double *F_total,
                         double *nu_gray);
+
+/* z = M^-1 r for the radial-line block-Jacobi preconditioner of the current system
+ * (precond = 1): per radial row, the tridiagonal block of A^ (unit diagonal, the radial
+ * off-diagonals) solved exactly.  Device arrays of n; r and z must not overlap. */
+rt_status rt_precond_apply(rt_ctx *ctx, const double *r, double *z);
 
 /* Diagnostic of Sect. "The Flux Limited Diffusion approximation" (Fig. 8): the optical
  * depth of the thermal emission integrated inward from the outer edge along each radial

@@ -970,6 +970,143 @@ void launch_rb_iter32(const Dims &dh, int nblk, int nblk_upd, const float *ab, f
     rb_iter<float>(dh, nblk, nblk_upd, ab, x, r, pold, pnew, q, t, partials, counter, sc, st, ev);
 }
 
+// --------------------------------------- radial-line block-Jacobi comparator
+//
+// The block-Jacobi class of preconditioner the paper uses (with ILU inside the blocks),
+// in the form that suits a GPU: the blocks are the radial rows, whose tridiagonal
+// couplings tridiag(a_r[i-1], 1, a_r[i]) are factorised exactly (Thomas: c_i and 1/m_i
+// once per system) and solved per application.  One thread per row walks it outward
+// and back; the rows of a wavefront are N_r apart in memory, so each lane streams its
+// own row through the caches (a comparator, not tuned).
+
+// c[i] = a_r[i] / m_i, im[i] = 1 / m_i with m_0 = 1, m_i = 1 - a_r[i-1] c[i-1].
+__global__ __launch_bounds__(kKB) void k_line_factor(Dims d, const double *__restrict__ a, double *__restrict__ c,
+                                                     double *__restrict__ im)
+{
+    const long rows = (long)d.nt * d.np;
+    for (long row = (long)blockIdx.x * kKB + threadIdx.x; row < rows; row += (long)gridDim.x * kKB) {
+        const long b = row * d.nr;
+        double cp = 0.0, ap = 0.0;
+        for (int i = 0; i < d.nr; i++) {
+            const double m = 1.0 - ap * cp;
+            const double ai = a[b + i];
+            cp = ai / m;
+            c[b + i] = cp;
+            im[b + i] = 1.0 / m;
+            ap = ai;
+        }
+    }
+}
+
+// z = M^-1 r (tridiagonal solve per radial row), rz = r.z; beta = rz / rz_prev (0 after
+// a restart), rr = rz for the direction kernel.
+__global__ __launch_bounds__(kKB) void k_line_solve(Dims d, int nblk, const double *__restrict__ a,
+                                                    const double *__restrict__ c, const double *__restrict__ im,
+                                                    const double *__restrict__ r, double *__restrict__ z,
+                                                    double *partials, unsigned *counter, DevScalars *sc, int restart)
+{
+    if (sc->done) return;
+    __shared__ double sh[kKB / 64];
+    const long rows = (long)d.nt * d.np;
+    double acc = 0.0;
+    for (long row = (long)blockIdx.x * kKB + threadIdx.x; row < rows; row += (long)nblk * kKB) {
+        const long b = row * d.nr;
+        double dp = 0.0, ap = 0.0;
+        for (int i = 0; i < d.nr; i++) {  // forward: d_i = (r_i - a_(i-1) d_(i-1)) / m_i
+            dp = (r[b + i] - ap * dp) * im[b + i];
+            z[b + i] = dp;
+            ap = a[b + i];
+        }
+        double zn = 0.0;
+        for (int i = d.nr - 1; i >= 0; i--) {  // backward: z_i = d_i - c_i z_(i+1)
+            zn = z[b + i] - c[b + i] * zn;
+            z[b + i] = zn;
+            acc += r[b + i] * zn;
+        }
+    }
+    const long L = logical_block(nblk);
+    double bs = block_sum(acc, sh), tot;
+    if (finish_reduce(bs, L, nblk, partials, counter, sh, &tot) && threadIdx.x == 0) {
+        sc->beta = (restart || !(sc->rr > 0.0)) ? 0.0 : tot / sc->rr;
+        sc->rr = tot;
+    }
+}
+
+// Preconditioned update: y += alpha p, r -= alpha q, res2 = r.r, done when res2 <= thresh2.
+template <int VW>
+__global__ __launch_bounds__(kKB) void k_pcg_upd(Dims d, int nblk, double *__restrict__ y,
+                                                 const double *__restrict__ p, double *__restrict__ r,
+                                                 const double *__restrict__ q, double *partials, unsigned *counter,
+                                                 DevScalars *sc)
+{
+    if (sc->done) return;
+    __shared__ double sh[kKB / 64];
+    const double alpha = sc->alpha;
+    const long L = logical_block(nblk);
+    double acc = 0.0;
+    for_segments<VW>(d, nblk, [&](const Row &rw, int i) {
+        const long c = rw.base + i;
+        double yv[VW], pv[VW], rv[VW], qv[VW];
+        vload<double, VW>(y + c, yv);
+        vload<double, VW>(p + c, pv);
+        vload<double, VW>(r + c, rv);
+        vload<double, VW>(q + c, qv);
+#pragma unroll
+        for (int m = 0; m < VW; m++) {
+            yv[m] = fma(alpha, pv[m], yv[m]);
+            rv[m] = fma(-alpha, qv[m], rv[m]);
+            acc += rv[m] * rv[m];
+        }
+        vstore<double, VW>(y + c, yv);
+        vstore<double, VW>(r + c, rv);
+    });
+    double bs = block_sum(acc, sh), tot;
+    if (finish_reduce(bs, L, nblk, partials, counter, sh, &tot) && threadIdx.x == 0) {
+        sc->res2 = tot;
+        sc->iters += 1;
+        if (tot <= sc->thresh2 || !(tot == tot)) sc->done = 1;
+    }
+}
+
+void launch_line_factor(const Dims &d, int nblk, const double *a, double *c, double *im, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_line_factor, dim3(nblk), dim3(kKB), 0, st, d, a, c, im);
+}
+
+void launch_line_solve(const Dims &d, int nblk, const double *a, const double *c, const double *im, const double *r,
+                       double *z, double *partials, unsigned *counter, DevScalars *sc, int restart, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_line_solve, dim3(nblk), dim3(kKB), 0, st, d, nblk, a, c, im, r, z, partials, counter, sc,
+                       restart);
+}
+
+// One preconditioned CG iteration: z = M^-1 r (and beta), p = z + beta p_old, q = A^ p,
+// alpha; y, r update and r.r.
+void launch_pcg_line_iter(const Dims &d, int nblk, int nblk_upd, const double *a, const double *lc, const double *lim,
+                          double *y, double *r, double *z, double *pold, double *pnew, double *q, double *partials,
+                          unsigned *counter, DevScalars *sc, int restart, hipStream_t st, const hipEvent_t *ev)
+{
+    const int vw = pick_vw<double>(d);
+    if (ev) (void)hipEventRecord(ev[0], st);
+    hipLaunchKernelGGL(k_line_solve, dim3(nblk), dim3(kKB), 0, st, d, nblk, a, lc, lim, r, z, partials, counter, sc,
+                       restart);
+    if (ev) (void)hipEventRecord(ev[3], st);
+    RT_DISPATCH_VW(double, vw, k_cg_dir, dim3(nblk), dim3(kKB), 0, st, d, nblk, a, (const double *)z, pold, pnew, q,
+                   partials, counter, sc);
+    if (ev) (void)hipEventRecord(ev[1], st);
+    switch (vw) {
+    case 8: hipLaunchKernelGGL(k_pcg_upd<8>, dim3(nblk_upd), dim3(kKB), 0, st, d, nblk_upd, y, pnew, r, q, partials,
+                               counter, sc); break;
+    case 4: hipLaunchKernelGGL(k_pcg_upd<4>, dim3(nblk_upd), dim3(kKB), 0, st, d, nblk_upd, y, pnew, r, q, partials,
+                               counter, sc); break;
+    case 2: hipLaunchKernelGGL(k_pcg_upd<2>, dim3(nblk_upd), dim3(kKB), 0, st, d, nblk_upd, y, pnew, r, q, partials,
+                               counter, sc); break;
+    default: hipLaunchKernelGGL(k_pcg_upd<1>, dim3(nblk_upd), dim3(kKB), 0, st, d, nblk_upd, y, pnew, r, q, partials,
+                                counter, sc); break;
+    }
+    if (ev) (void)hipEventRecord(ev[2], st);
+}
+
 // ---------------------------------------------------------------- GMRES(m)
 
 // Partial inner products of w with the k basis vectors V_i = V + i n (k <= kMaxBasis),

@@ -484,6 +484,7 @@ rt_status rt_fld_assemble(rt_ctx *ctx, const rt_opacity *op, const rt_fld_params
     RT_HIP(ctx, hipGetLastError());
     ctx->have_system = true;
     ctx->rb_ready = false;
+    ctx->ln_ready = false;
     if (sys) {
         sys->n = ctx->d.n;
         sys->ahat = ctx->ahat;
@@ -860,6 +861,67 @@ rt_status solve_mixed_rb(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st
     return status;
 }
 
+// Float64 CG preconditioned by the radial-line block Jacobi (the comparator for the
+// paper's block-Jacobi class): the same stopping test on the true residual as solve_fp64.
+rt_status solve_fp64_line(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb)
+{
+    const Dims &d = ctx->d;
+    const long n = d.n;
+    hipStream_t s = ctx->stream;
+    DevScalars *h = ctx->h_sc;
+    if (!ctx->ln_c) {
+        ctx->ln_c = dalloc<double>(ctx, n);
+        ctx->ln_im = dalloc<double>(ctx, n);
+        ctx->ln_z = dalloc<double>(ctx, n);
+        if (!ctx->ln_c || !ctx->ln_im || !ctx->ln_z) return fail(ctx, RT_ENOMEM, "line preconditioner: out of device memory");
+    }
+    if (!ctx->ln_ready) {
+        launch_line_factor(d, ctx->nblk, ctx->ahat, ctx->ln_c, ctx->ln_im, s);
+        ctx->ln_ready = true;
+    }
+    h->thresh2 = o->tol * o->tol * bb;
+    h->done = 0;
+    h->iters = 0;
+    h->beta = 0.0;
+    if (rt_status e = write_scalars(ctx)) return e;
+    launch_resid(d, ctx->nblk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials, ctx->counter, ctx->sc, 1, s);
+    if (rt_status e = read_scalars(ctx)) return e;
+    double *pold = ctx->p0, *pnew = ctx->p1;
+    const int every = o->check_every > 0 ? o->check_every : 32;
+    rt_status status = RT_OK;
+    double res = std::sqrt(h->res2 / bb);
+    bool restart = true;
+    for (;;) {
+        st->relres = res;
+        if (!isfin(res)) { status = RT_ENONFINITE; break; }
+        if (res <= o->tol) break;
+        if (h->iters >= o->max_iter) { status = RT_ENOCONV; break; }
+        int m = std::min(every, o->max_iter - h->iters);
+        int it_before = h->iters;
+        for (int k = 0; k < m; k++) {
+            launch_pcg_line_iter(d, ctx->nblk, ctx->nblk_upd, ctx->ahat, ctx->ln_c, ctx->ln_im, ctx->y, ctx->r,
+                                 ctx->ln_z, pold, pnew, ctx->qv, ctx->partials, ctx->counter, ctx->sc,
+                                 restart && k == 0, s, k == 0 ? &ctx->ev[8] : nullptr);
+            std::swap(pold, pnew);
+        }
+        restart = false;
+        RT_HIP(ctx, hipGetLastError());
+        if (rt_status e = read_scalars(ctx)) return e;
+        add_kernel_sample(ctx, st, true);
+        if ((h->iters - it_before) % 2 != m % 2) std::swap(pold, pnew);  // kernels that exited early
+        if (!isfin(h->res2)) { status = RT_ENONFINITE; st->relres = NAN; break; }
+        if (h->done || h->iters >= o->max_iter) {
+            launch_resid(d, ctx->nblk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials, ctx->counter,
+                         ctx->sc, 1, s);
+            if (rt_status e = read_scalars(ctx)) return e;
+            res = std::sqrt(h->res2 / bb);
+            restart = true;
+        }
+    }
+    st->iters = h->iters;
+    return status;
+}
+
 // Learned mode: flexible CG (Notay's FCG with one A-orthogonalisation, since the
 // network is a nonlinear preconditioner) in float32 with float64 dots and the same
 // float64 reliable updates as the mixed mode; z = M(r) is the U-Net applied to the
@@ -1067,6 +1129,8 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
                       o->mode == RT_SOLVE_GMRES,
              "unknown solve mode");
     RT_CHECK(ctx, o->mode != RT_SOLVE_LEARNED || o->net, "learned mode needs a network");
+    RT_CHECK(ctx, o->precond == 0 || (o->precond == 1 && o->mode == RT_SOLVE_FP64 && !o->reduce),
+             "precond = 1 (radial-line block Jacobi) needs RT_SOLVE_FP64 without reduce");
     rt_solve_stats local{};
     rt_solve_stats *S = st ? st : &local;
     *S = rt_solve_stats{};
@@ -1081,7 +1145,8 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
     launch_scale_div(ctx->d.n, ctx->s, E, ctx->y, ctx->stream);  // y0 = E / s
     rt_status status;
     const bool rb = o->reduce && rb_possible(ctx);
-    if (o->mode == RT_SOLVE_FP64) status = rb ? solve_fp64_rb(ctx, o, S, bb) : solve_fp64(ctx, o, S, bb);
+    if (o->mode == RT_SOLVE_FP64 && o->precond == 1) status = solve_fp64_line(ctx, o, S, bb);
+    else if (o->mode == RT_SOLVE_FP64) status = rb ? solve_fp64_rb(ctx, o, S, bb) : solve_fp64(ctx, o, S, bb);
     else if (o->mode == RT_SOLVE_MIXED) status = rb ? solve_mixed_rb(ctx, o, S, bb) : solve_mixed(ctx, o, S, bb);
     else if (o->mode == RT_SOLVE_GMRES) status = solve_gmres(ctx, o, S, bb);
     else status = solve_learned(ctx, o, S, bb);
@@ -1220,6 +1285,31 @@ rt_status rt_step_fields(rt_ctx *ctx, const double **q_star, const double **S_ab
     if (q_star) *q_star = ctx->q;
     if (S_abs) *S_abs = ctx->S;
     if (E_n) *E_n = ctx->En;
+    return RT_OK;
+}
+
+rt_status rt_precond_apply(rt_ctx *ctx, const double *r, double *z)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    RT_CHECK(ctx, ctx->have_system, "no assembled system");
+    RT_CHECK(ctx, r && z, "rt_precond_apply: NULL field pointer");
+    const long n = ctx->d.n;
+    if (!ctx->ln_c) {
+        ctx->ln_c = dalloc<double>(ctx, n);
+        ctx->ln_im = dalloc<double>(ctx, n);
+        ctx->ln_z = dalloc<double>(ctx, n);
+        if (!ctx->ln_c || !ctx->ln_im || !ctx->ln_z) return fail(ctx, RT_ENOMEM, "line preconditioner: out of device memory");
+    }
+    if (!ctx->ln_ready) {
+        launch_line_factor(ctx->d, ctx->nblk, ctx->ahat, ctx->ln_c, ctx->ln_im, ctx->stream);
+        ctx->ln_ready = true;
+    }
+    ctx->h_sc->done = 0;
+    ctx->h_sc->rr = 0.0;
+    if (rt_status e = write_scalars(ctx)) return e;
+    launch_line_solve(ctx->d, ctx->nblk, ctx->ahat, ctx->ln_c, ctx->ln_im, r, z, ctx->partials, ctx->counter, ctx->sc,
+                      1, ctx->stream);
+    RT_HIP(ctx, hipGetLastError());
     return RT_OK;
 }
 

@@ -198,6 +198,14 @@ void launch_fill(long n, double v, double *x, hipStream_t st);
 // Inward Rosseland optical depth at the radial faces ((N_r + 1) per column).
 void launch_tau_rosseland(const Dims &d, const Opac &op, const double *rf, const double *rho, const double *T,
                           double *tau, hipStream_t st);
+// Radial-line block-Jacobi preconditioner (k_krylov.hip): Thomas factors of each radial
+// row's tridiagonal block, z = M^-1 r with r.z, and one preconditioned CG iteration.
+void launch_line_factor(const Dims &d, int nblk, const double *a, double *c, double *im, hipStream_t st);
+void launch_line_solve(const Dims &d, int nblk, const double *a, const double *c, const double *im, const double *r,
+                       double *z, double *partials, unsigned *counter, DevScalars *sc, int restart, hipStream_t st);
+void launch_pcg_line_iter(const Dims &d, int nblk, int nblk_upd, const double *a, const double *lc, const double *lim,
+                          double *y, double *r, double *z, double *pold, double *pnew, double *q, double *partials,
+                          unsigned *counter, DevScalars *sc, int restart, hipStream_t st, const hipEvent_t *ev);
 // Red-black reduced system (k_krylov.hip): half-grid dims, colour split of the operator
 // and of vectors, the passes of one product with S = I - B^T B, and one CG iteration on S.
 Dims rb_half(const Dims &d);
@@ -327,6 +335,10 @@ struct rt_ctx {
     double *rb_a = nullptr;
     float *rb_a32 = nullptr;
     bool rb_ready = false;
+    // radial-line block-Jacobi factors (c, 1/m) and the preconditioned residual z,
+    // allocated at the first such solve, factors refreshed once per assembled system
+    double *ln_c = nullptr, *ln_im = nullptr, *ln_z = nullptr;
+    bool ln_ready = false;
     double Eb = 0.0;  // a T_bc^4 of the assembled system
     // Krylov vectors
     double *y = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *qv = nullptr, *tmp = nullptr;

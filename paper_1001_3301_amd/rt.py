@@ -57,7 +57,7 @@ class System(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("check_every", C.c_int), ("inner_tol", C.c_double), ("inner_max_iter", C.c_int),
-                ("net", C.c_void_p), ("restart", C.c_int), ("reduce", C.c_int)]
+                ("net", C.c_void_p), ("restart", C.c_int), ("reduce", C.c_int), ("precond", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -94,7 +94,7 @@ class RelaxStats(C.Structure):
 EXPORTS = ["rt_create", "rt_destroy", "rt_last_error", "rt_ncell", "rt_star_bin_flux",
            "rt_set_opacity", "rt_set_star", "rt_raytrace", "rt_energy", "rt_fld_assemble",
            "rt_spmv", "rt_fld_solve", "rt_temperature", "rt_force", "rt_step", "rt_step_fields",
-           "rt_gray_table", "rt_relax", "rt_rosseland_depth",
+           "rt_gray_table", "rt_relax", "rt_rosseland_depth", "rt_precond_apply",
            "rt_net_create", "rt_net_destroy", "rt_net_last_error", "rt_net_param_count",
            "rt_net_get_params", "rt_net_get_grads", "rt_net_set_params", "rt_net_save", "rt_net_load",
            "rt_net_forward", "rt_net_loss_grad", "rt_net_loss_grad_resid", "rt_net_adam", "rt_dataset_create",
@@ -153,6 +153,7 @@ def lib():
     L.rt_step_fields.argtypes = [vp, P(vp), P(vp), P(vp)]
     L.rt_gray_table.argtypes = [P(Opacity), dp, dp, dp, dp]
     L.rt_rosseland_depth.argtypes = [vp, P(Opacity), vp, vp, vp]
+    L.rt_precond_apply.argtypes = [vp, vp, vp]
     L.rt_relax.argtypes = [vp, P(Opacity), P(Star), P(FldParams), P(SolveOpts), vp, vp, vp, C.c_double,
                            C.c_int, P(RelaxStats)]
     fp = P(C.c_float)
@@ -229,9 +230,10 @@ class GrayOpacity:
 
 
 def solve_opts(mode=MODE_FP64, tol=1e-8, max_iter=100000, check_every=32, inner_tol=1e-4,
-               inner_max_iter=0, net=None, restart=30, reduce=0) -> SolveOpts:
+               inner_max_iter=0, net=None, restart=30, reduce=0, precond=0) -> SolveOpts:
     nh = None if net is None else (net.h if isinstance(net, Net) else net)
-    o = SolveOpts(mode, tol, max_iter, check_every, inner_tol, inner_max_iter, nh, restart, int(reduce))
+    o = SolveOpts(mode, tol, max_iter, check_every, inner_tol, inner_max_iter, nh, restart, int(reduce),
+                  int(precond))
     o._net = net  # keeps the network alive as long as the options refer to it
     return o
 
@@ -379,6 +381,10 @@ class Context:
         if raise_on_error:
             self._chk(rc)
         return rc, st.as_dict()
+
+    def precond_apply(self, r, z):
+        """rt_precond_apply: z = M^-1 r, radial-line block Jacobi of the current system."""
+        self._chk(lib().rt_precond_apply(self.h, self._dev(r, self.n, "r"), self._dev(z, self.n, "z")))
 
     def rosseland_depth(self, rho, T, tau):
         """rt_rosseland_depth: inward tau_R at the radial faces ((N_r + 1) per column)."""
