@@ -141,7 +141,9 @@ typedef struct {
     int kernel_samples;  /* number of samples behind ms_dir / ms_upd */
     int reduced;         /* 1 if the red-black reduced system was solved (iters count its
                             iterations; ms_dir then covers its red and black passes) */
-    double ms_black;     /* reduced solves: mean device time of the black pass alone */
+    double ms_black;     /* reduced solves: mean device time of the black pass alone (ms_dir -
+                            ms_black is the red pass); precond = 1: the direction kernel
+                            alone (ms_dir - ms_black is the block solve) */
 } rt_solve_stats;
 
 typedef struct {
