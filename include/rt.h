@@ -126,6 +126,10 @@ typedef struct {
                             each radial row's tridiagonal block of A^ solved exactly (the
                             block-Jacobi class of the paper's solver set-up, Sect. "Numerical
                             setup", as a comparator) */
+    int graphs;          /* float64 / mixed CG, reduced or not: the chunks of iterations between
+                            convergence polls run from HIP graphs captured once per context
+                            (0 = on grids of at most 4,194,304 cells, where launches dominate;
+                            1 = always; -1 = never).  Kernel times are sampled only without */
 } rt_solve_opts;
 
 typedef struct {

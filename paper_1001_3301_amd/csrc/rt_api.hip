@@ -364,6 +364,8 @@ void rt_destroy(rt_ctx *ctx)
     if (!ctx) return;
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (void *p : ctx->allocs) (void)hipFree(p);
     if (ctx->h_sc) (void)hipHostFree(ctx->h_sc);
     for (auto &e : ctx->ev)
@@ -534,6 +536,62 @@ void add_kernel_sample(rt_ctx *ctx, rt_solve_stats *st, bool rb = false)
     st->kernel_samples = n + 1;
 }
 
+// Grids up to this many cells run their Krylov iterations from HIP graphs by default:
+// their kernels take a few microseconds, so launches dominate.
+constexpr long kGraphCells = 1L << 22;
+constexpr size_t kMaxGraphs = 16;
+
+bool use_graphs(const rt_ctx *ctx, const rt_solve_opts *o)
+{
+    return o->graphs > 0 || (o->graphs == 0 && ctx->d.n <= kGraphCells);
+}
+
+// Enqueues m Krylov iterations on ctx->stream, each launched by iter(pold, pnew, stream,
+// ev) (ev: the events that time the first iteration's kernels, or NULL), swapping the
+// direction buffers after each.  With graphs the m launches are captured once per
+// (kind, pold, m) on a private stream and the instantiated graph is replayed (the
+// kernels read every scalar from device memory, so a replay is the same work as the
+// launches); *sampled tells whether the events were recorded.
+template <typename T, typename F>
+rt_status run_iters(rt_ctx *ctx, const rt_solve_opts *o, int kind, int m, T *&pold, T *&pnew, F &&iter,
+                    bool *sampled)
+{
+    hipGraphExec_t ex = nullptr;
+    if (use_graphs(ctx, o))
+        for (const auto &g : ctx->graphs)
+            if (g.kind == kind && g.pold == (const void *)pold && g.m == m) ex = g.exec;
+    // chunk lengths other than the polling interval (the last chunk before max_iter) are
+    // rare: at most kMaxGraphs graphs are kept, later new shapes launch directly
+    if (!ex && (!use_graphs(ctx, o) || ctx->graphs.size() >= kMaxGraphs)) {
+        for (int k = 0; k < m; k++) {
+            iter(pold, pnew, ctx->stream, k == 0 ? &ctx->ev[8] : nullptr);
+            std::swap(pold, pnew);
+        }
+        *sampled = true;
+        return RT_OK;
+    }
+    *sampled = false;
+    if (!ex) {
+        if (!ctx->cap_stream) RT_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        RT_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        T *a = pold, *b = pnew;
+        for (int k = 0; k < m; k++) {
+            iter(a, b, ctx->cap_stream, nullptr);
+            std::swap(a, b);
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (ec != hipSuccess || !g) return fail(ctx, RT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return fail(ctx, RT_EDEVICE, std::string("graph instantiation: ") + hipGetErrorString(ei));
+        ctx->graphs.push_back({kind, (const void *)pold, m, ex});
+    }
+    RT_HIP(ctx, hipGraphLaunch(ex, ctx->stream));
+    if (m % 2) std::swap(pold, pnew);
+    return RT_OK;
+}
+
 // ||bhat||^2 on the device, read back.
 rt_status norm_b(rt_ctx *ctx, double &bb)
 {
@@ -570,14 +628,15 @@ rt_status solve_fp64(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, do
         if (h->iters >= o->max_iter) { status = RT_ENOCONV; break; }
         int m = std::min(every, o->max_iter - h->iters);
         int it_before = h->iters;
-        for (int k = 0; k < m; k++) {
-            launch_cg_iter64(d, ctx->nblk, ctx->nblk_upd, ctx->ahat, ctx->y, ctx->r, pold, pnew, ctx->qv, ctx->partials,
-                             ctx->counter, ctx->sc, s, k == 0 ? &ctx->ev[8] : nullptr);
-            std::swap(pold, pnew);
-        }
+        bool sampled = false;
+        if (rt_status e = run_iters(ctx, o, 0, m, pold, pnew, [&](double *a, double *b, hipStream_t ss, const hipEvent_t *ev) {
+                launch_cg_iter64(d, ctx->nblk, ctx->nblk_upd, ctx->ahat, ctx->y, ctx->r, a, b, ctx->qv, ctx->partials,
+                                 ctx->counter, ctx->sc, ss, ev);
+            }, &sampled))
+            return e;
         RT_HIP(ctx, hipGetLastError());
         if (rt_status e = read_scalars(ctx)) return e;
-        add_kernel_sample(ctx, st);
+        if (sampled) add_kernel_sample(ctx, st);
         if ((h->iters - it_before) % 2 != m % 2) std::swap(pold, pnew);  // kernels that exited early
         if (!isfin(h->rr)) { status = RT_ENONFINITE; st->relres = NAN; break; }
         if (h->done || h->iters >= o->max_iter) {
@@ -636,14 +695,15 @@ rt_status solve_mixed(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, d
         if (bad >= 2) { fallback = true; break; }
         int m = std::min(every, o->max_iter - h->iters);
         int it_before = h->iters;
-        for (int k = 0; k < m; k++) {
-            launch_cg_iter32(d, ctx->nblk, ctx->nblk_upd, ctx->ahat32, ctx->x32, ctx->r32, pold, pnew, ctx->q32,
-                             ctx->partials, ctx->counter, ctx->sc, s, k == 0 ? &ctx->ev[8] : nullptr);
-            std::swap(pold, pnew);
-        }
+        bool sampled = false;
+        if (rt_status e = run_iters(ctx, o, 1, m, pold, pnew, [&](float *a, float *b, hipStream_t ss, const hipEvent_t *ev) {
+                launch_cg_iter32(d, ctx->nblk, ctx->nblk_upd, ctx->ahat32, ctx->x32, ctx->r32, a, b, ctx->q32,
+                                 ctx->partials, ctx->counter, ctx->sc, ss, ev);
+            }, &sampled))
+            return e;
         RT_HIP(ctx, hipGetLastError());
         if (rt_status e = read_scalars(ctx)) return e;
-        add_kernel_sample(ctx, st);
+        if (sampled) add_kernel_sample(ctx, st);
         if ((h->iters - it_before) % 2 != m % 2) std::swap(pold, pnew);  // kernels that exited early
         if (!isfin(h->rr)) { status = RT_ENONFINITE; st->relres = NAN; break; }
         const bool capped = h->iters - cycle_start >= kCycle;
@@ -739,7 +799,6 @@ rt_status solve_fp64_rb(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
 {
     const Dims dh = rb_half(ctx->d);
     const long nh = dh.n;
-    hipStream_t s = ctx->stream;
     DevScalars *h = ctx->h_sc;
     double *rb = ctx->r, *tr = ctx->r + nh, *pold = ctx->p0, *pnew = ctx->p0 + nh;
     double *qb = ctx->qv, *yb = ctx->qv + nh, *rhs = ctx->p1;
@@ -761,14 +820,15 @@ rt_status solve_fp64_rb(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
         if (h->iters >= o->max_iter) { status = RT_ENOCONV; break; }
         int m = std::min(every, o->max_iter - h->iters);
         int it_before = h->iters;
-        for (int k = 0; k < m; k++) {
-            launch_rb_iter64(dh, ctx->nblk, ctx->nblk_upd, ctx->rb_a, yb, rb, pold, pnew, qb, tr, ctx->partials,
-                             ctx->counter, ctx->sc, s, k == 0 ? &ctx->ev[8] : nullptr);
-            std::swap(pold, pnew);
-        }
+        bool sampled = false;
+        if (rt_status e = run_iters(ctx, o, 2, m, pold, pnew, [&](double *a, double *b, hipStream_t ss, const hipEvent_t *ev) {
+                launch_rb_iter64(dh, ctx->nblk, ctx->nblk_upd, ctx->rb_a, yb, rb, a, b, qb, tr, ctx->partials,
+                                 ctx->counter, ctx->sc, ss, ev);
+            }, &sampled))
+            return e;
         RT_HIP(ctx, hipGetLastError());
         if (rt_status e = read_scalars(ctx)) return e;
-        add_kernel_sample(ctx, st, true);
+        if (sampled) add_kernel_sample(ctx, st, true);
         if ((h->iters - it_before) % 2 != m % 2) std::swap(pold, pnew);  // kernels that exited early
         if (!isfin(h->rr)) { status = RT_ENONFINITE; st->relres = NAN; break; }
         if (h->done || h->iters >= o->max_iter) {
@@ -819,14 +879,15 @@ rt_status solve_mixed_rb(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st
         if (bad >= 2) { fallback = true; break; }
         int m = std::min(every, o->max_iter - h->iters);
         int it_before = h->iters;
-        for (int k = 0; k < m; k++) {
-            launch_rb_iter32(dh, ctx->nblk, ctx->nblk_upd, ctx->rb_a32, x32, r32, pold, pnew, q32, t32, ctx->partials,
-                             ctx->counter, ctx->sc, s, k == 0 ? &ctx->ev[8] : nullptr);
-            std::swap(pold, pnew);
-        }
+        bool sampled = false;
+        if (rt_status e = run_iters(ctx, o, 3, m, pold, pnew, [&](float *a, float *b, hipStream_t ss, const hipEvent_t *ev) {
+                launch_rb_iter32(dh, ctx->nblk, ctx->nblk_upd, ctx->rb_a32, x32, r32, a, b, q32, t32, ctx->partials,
+                                 ctx->counter, ctx->sc, ss, ev);
+            }, &sampled))
+            return e;
         RT_HIP(ctx, hipGetLastError());
         if (rt_status e = read_scalars(ctx)) return e;
-        add_kernel_sample(ctx, st, true);
+        if (sampled) add_kernel_sample(ctx, st, true);
         if ((h->iters - it_before) % 2 != m % 2) std::swap(pold, pnew);  // kernels that exited early
         if (!isfin(h->rr)) { status = RT_ENONFINITE; st->relres = NAN; break; }
         const bool capped = h->iters - cycle_start >= kCycle;

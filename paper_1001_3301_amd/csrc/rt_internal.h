@@ -339,6 +339,16 @@ struct rt_ctx {
     // allocated at the first such solve, factors refreshed once per assembled system
     double *ln_c = nullptr, *ln_im = nullptr, *ln_z = nullptr;
     bool ln_ready = false;
+    // HIP graphs of chunks of Krylov iterations (launch-bound small grids): one per
+    // (solver kind, start direction buffer, chunk length), replayed on `stream`
+    struct GraphEntry {
+        int kind;
+        const void *pold;
+        int m;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    hipStream_t cap_stream = nullptr;  // capture stream (non-blocking, default priority)
     double Eb = 0.0;  // a T_bc^4 of the assembled system
     // Krylov vectors
     double *y = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *qv = nullptr, *tmp = nullptr;

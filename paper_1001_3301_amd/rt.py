@@ -57,7 +57,8 @@ class System(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("check_every", C.c_int), ("inner_tol", C.c_double), ("inner_max_iter", C.c_int),
-                ("net", C.c_void_p), ("restart", C.c_int), ("reduce", C.c_int), ("precond", C.c_int)]
+                ("net", C.c_void_p), ("restart", C.c_int), ("reduce", C.c_int), ("precond", C.c_int),
+                ("graphs", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -230,10 +231,10 @@ class GrayOpacity:
 
 
 def solve_opts(mode=MODE_FP64, tol=1e-8, max_iter=100000, check_every=32, inner_tol=1e-4,
-               inner_max_iter=0, net=None, restart=30, reduce=0, precond=0) -> SolveOpts:
+               inner_max_iter=0, net=None, restart=30, reduce=0, precond=0, graphs=0) -> SolveOpts:
     nh = None if net is None else (net.h if isinstance(net, Net) else net)
     o = SolveOpts(mode, tol, max_iter, check_every, inner_tol, inner_max_iter, nh, restart, int(reduce),
-                  int(precond))
+                  int(precond), int(graphs))
     o._net = net  # keeps the network alive as long as the options refer to it
     return o
 

@@ -1,0 +1,110 @@
+"""Krylov iterations replayed from HIP graphs (rt_solve_opts.graphs = 1) against the same
+iterations launched one by one (graphs = -1).
+
+The kernels read every scalar from device memory and reduce in a fixed order, so a graph
+replay must reproduce the direct launches bit for bit: same iterate, same iteration
+count, same residual.  Each context solves several systems in a row (new coefficients
+from a re-assembly, eager torch work in between), so the cached graphs are replayed
+many times, from both direction buffers (odd polling intervals) and with a short last
+chunk before max_iter.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1001_3301_amd import synth as sy
+from _util import initial_temperature
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _d(x):
+    return torch.tensor(np.ascontiguousarray(x, dtype=np.float64).ravel(), device="cuda")
+
+
+def _h(t):
+    return t.detach().cpu().numpy()
+
+
+MODES = {  # name: (mode, reduce)
+    "fp64": (0, 0),
+    "mixed": (1, 0),
+    "fp64-rb": (0, 1),
+    "mixed-rb": (1, 1),
+}
+
+
+def _systems(wl, P, count):
+    """count assembled systems of one grid: the oracle's start state and its temperature
+    scaled by a few percent."""
+    T0 = initial_temperature(P, wl)
+    out = []
+    for k in range(count):
+        T = T0 * (1.0 + 0.03 * k)
+        q, S, _ = P.raytrace(wl.rho, T, want_faces=False)
+        out.append((T, P.energy(T, S), q))
+    return out
+
+
+def _run(wl, P, systems, mode, reduce, graphs, check_every, max_iter, tol):
+    from paper_1001_3301_amd import rt
+    ctx = rt.Context.from_workload(wl)
+    res = []
+    side = torch.zeros(1000, dtype=torch.float64, device="cuda")
+    for T, En, q in systems:
+        ctx.assemble(_d(wl.rho), _d(T), _d(En), _d(q))
+        for _ in range(2):  # the second solve replays every cached graph from the start
+            E = _d(En)
+            rc, st = ctx.solve(E, rt.solve_opts(mode, tol=tol, max_iter=max_iter, check_every=check_every,
+                                                reduce=reduce, graphs=graphs), raise_on_error=False)
+            side.add_(1.0).mul_(0.5)  # eager work on the current stream between solves
+            torch.cuda.synchronize()
+            res.append((rc, st["iters"], st["relres"], st["reduced"], _h(E)))
+    return res
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("check_every", [32, 7])
+def test_graph_replay_matches_direct_launches(mode, check_every):
+    wl = sy.make_workload("t", 40, 9, 4, 64, 100.0, clump_seed=3)
+    P = oracle.Problem.from_workload(wl)
+    systems = _systems(wl, P, 3)
+    m, rb = MODES[mode]
+    tol = 1e-10
+    g = _run(wl, P, systems, m, rb, 1, check_every, 100000, tol)
+    d = _run(wl, P, systems, m, rb, -1, check_every, 100000, tol)
+    for a, b in zip(g, d):
+        assert a[0] == b[0] == 0
+        assert a[1] == b[1] and a[2] == b[2] and a[3] == b[3] == rb
+        assert np.array_equal(a[4], b[4])
+        assert a[2] <= tol
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp64-rb"])
+def test_graph_short_last_chunk_and_no_convergence(mode):
+    """max_iter not a multiple of the polling interval: the last chunk is shorter (its
+    own graph) and the solve ends without convergence, identically."""
+    from paper_1001_3301_amd import rt
+    wl = sy.make_workload("t", 40, 9, 4, 64, 100.0, clump_seed=3)
+    P = oracle.Problem.from_workload(wl)
+    systems = _systems(wl, P, 2)
+    m, rb = MODES[mode]
+    g = _run(wl, P, systems, m, rb, 1, 16, 45, 1e-14)
+    d = _run(wl, P, systems, m, rb, -1, 16, 45, 1e-14)
+    for a, b in zip(g, d):
+        assert a[0] == b[0] == rt.RT_ENOCONV
+        assert a[1] == b[1] == 45
+        assert a[2] == b[2]
+        assert np.array_equal(a[4], b[4])
+
+
+def test_graphs_default_on_small_grids_only():
+    """graphs = 0 (the default) replays graphs on small grids: same bits as direct launches."""
+    wl = sy.make_workload("a", 64, 16, 1, 32, 1.0)
+    P = oracle.Problem.from_workload(wl)
+    systems = _systems(wl, P, 1)
+    a = _run(wl, P, systems, 0, 1, 0, 32, 100000, 1e-12)
+    b = _run(wl, P, systems, 0, 1, -1, 32, 100000, 1e-12)
+    for x, y in zip(a, b):
+        assert x[1] == y[1] and np.array_equal(x[4], y[4])
