@@ -216,9 +216,28 @@ def run_main_loop(rt, torch, sy, shape=(64, 64, 1), n_nu=64, tol_change=1e-4):
     for g, f in (("G100", "F100"), ("GD100", "FD100")):
         r = mid[g] / mid[f] - 1.0
         cmp[f"{g}_vs_{f}"] = {"max_percent": float(r.max() * 100), "min_percent": float(r.min() * 100)}
+    # the GD100 run again with the iterations launched kernel by kernel and from graphs
+    # (the runs above take the default: one workgroup for the reduced solve)
+    launch = {"block": {"s": runs["GD100"]["s"], "us_per_krylov_iter":
+                        runs["GD100"]["s"] / runs["GD100"]["krylov_iters"] * 1e6}}
+    wl = sy.make_workload("disk-2d", *shape, n_nu, 100.0, None, dt=1e4)
+    for name, lv in (("direct", rt.LAUNCH_DIRECT), ("graph", rt.LAUNCH_GRAPH)):
+        ctx = rt.Context.from_workload(wl, gray=True)
+        rho = torch.tensor(wl.rho.ravel(), device="cuda")
+        T = torch.full((ctx.n,), wl.T_bc, dtype=torch.float64, device="cuda")
+        E = torch.empty_like(T)
+        t = time.perf_counter()
+        rc, st = ctx.relax(rho, T, E, rt.solve_opts(rt.MODE_FP64, tol=1e-8, reduce=1, launch=lv),
+                           tol_change=tol_change, max_steps=5000, raise_on_error=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        launch[name] = {"s": wall, "us_per_krylov_iter": wall / max(st["krylov_iters"], 1) * 1e6,
+                        "steps": st["steps"], "status": rc}
+        log(f"main loop GD100, launch {name}: {launch[name]}")
+        del ctx
     return {"workload": f"disk-2d {shape[0]}x{shape[1]}x{shape[2]} cells, {n_nu} bins, no clumps, dt=1e4 s, "
                         f"stop when max |dT/T| < {tol_change:g}; FLD solves reduced float64 CG to 1e-8",
-            "runs": runs, "gray_vs_freq_midplane": cmp}
+            "runs": runs, "gray_vs_freq_midplane": cmp, "gd100_by_launch": launch}
 
 
 def rosseland_depth_rate(ctx, torch, rho, T, reps=5):

@@ -108,7 +108,8 @@ typedef struct {
     int mode;            /* rt_solve_mode */
     double tol;          /* stop when ||b^ - A^ y|| / ||b^|| <= tol (float64, true residual) */
     int max_iter;        /* limit on (inner) Krylov iterations in total */
-    int check_every;     /* iterations between host convergence polls (default 32) */
+    int check_every;     /* iterations between host convergence polls (default 32; the
+                            one-workgroup solve of RT_LAUNCH_BLOCK checks on the device) */
     double inner_tol;    /* relative reduction asked of each inner solve (mixed / learned) */
     int inner_max_iter;  /* limit per inner solve */
     rt_net *net;         /* network for RT_SOLVE_LEARNED, else NULL */
@@ -126,11 +127,24 @@ typedef struct {
                             each radial row's tridiagonal block of A^ solved exactly (the
                             block-Jacobi class of the paper's solver set-up, Sect. "Numerical
                             setup", as a comparator) */
-    int graphs;          /* float64 / mixed CG, reduced or not: the chunks of iterations between
-                            convergence polls run from HIP graphs captured once per context
-                            (0 = on grids of at most 4,194,304 cells, where launches dominate;
-                            1 = always; -1 = never).  Kernel times are sampled only without */
+    int launch;          /* rt_launch: how the CG iterations of RT_SOLVE_FP64 / RT_SOLVE_MIXED
+                            (reduced or not) reach the GPU; every choice computes the same
+                            method, DIRECT and GRAPH bit for bit alike */
 } rt_solve_opts;
+
+typedef enum {
+    RT_LAUNCH_AUTO = 0,   /* BLOCK where it applies, else GRAPH on grids of at most 4,194,304
+                             cells (where launches dominate), else DIRECT */
+    RT_LAUNCH_DIRECT = 1, /* every kernel launched from the host; the only choice that samples
+                             the kernel times of rt_solve_stats */
+    RT_LAUNCH_GRAPH = 2,  /* the chunks of iterations between convergence polls replayed from
+                             HIP graphs captured once per context */
+    RT_LAUNCH_BLOCK = 3   /* reduced float64 CG (reduce = 1, also the finish of the reduced
+                             mixed and learned solves) with at most 2048 black cells: all
+                             iterations inside one workgroup, the vectors whose neighbours are
+                             read kept in LDS (dot products summed in another order than the
+                             multi-block kernels); other solves as AUTO */
+} rt_launch;
 
 typedef struct {
     int status;          /* rt_status of the solve */

@@ -970,6 +970,203 @@ void launch_rb_iter32(const Dims &dh, int nblk, int nblk_upd, const float *ab, f
     rb_iter<float>(dh, nblk, nblk_upd, ab, x, r, pold, pnew, q, t, partials, counter, sc, st, ev);
 }
 
+// ------------------------------------------- one-workgroup reduced CG (small grids)
+//
+// On grids of a few thousand cells each kernel of an iteration lasts a few
+// microseconds and the launches, not the bytes, set the time (the paper's own runs are
+// 2-D grids of this size).  Here one workgroup of kSB threads runs the float64 CG
+// iterations on S by itself: the direction p (black) and the product t = B p (red) --
+// the two vectors whose neighbours are read -- live in LDS, the thread's own entries of
+// r, y and q and each of its cells' couplings (six coefficients and neighbour indices
+// per colour, read once per launch) in registers, and each iteration's two dot products
+// are workgroup sums in a fixed order.  Thread tid owns the half indices tid + c kSB,
+// c < CPT <= 2 (at most 2048 black cells: beyond that the couplings no longer fit the
+// registers, and from L2 a single CU streams them no faster than the multi-block
+// kernels run).  Every entry is summed as in rb_couple (same terms, same order); only
+// the summation order of the dot products differs from the multi-block kernels.  At
+// most m iterations per launch; the state (y, r, p and the scalars) is read at the
+// start and written back at the end, so launches chain like the multi-block chunks.
+constexpr int kSB = 1024;
+
+// Sum over the workgroup; the same value in every thread (the butterfly leaves the
+// wave total in every lane, and every thread adds the wave totals in index order).
+__device__ __forceinline__ double wg_sum(double v, double *sh)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kSB / 64; i++) t += sh[i];
+    return t;
+}
+
+// The couplings of one cell to its six neighbours of the other colour, in the terms and
+// order of rb_couple with VW = 1: right, left, +theta, -theta, +phi, -phi (an absent
+// neighbour has index g and coefficient 0).
+struct Cpl {
+    double w[6];
+    int e[6];
+};
+
+__device__ __forceinline__ Cpl couplings(const Dims &dh, const Row &rw, int h0, int par, const double *__restrict__ own,
+                                         const double *__restrict__ oth)
+{
+    const long nh = dh.n;
+    const int H = dh.nr;
+    const long g = rw.base + h0;
+    const bool hasl = h0 > 0;
+    const long ge = par ? (h0 + 1 < H ? g + 1 : g) : (hasl ? g - 1 : g);
+    const long gjm = rw.jm ? g - H : g;
+    Cpl c;
+    c.w[0] = own[g];
+    c.e[0] = (int)(par ? ge : g);
+    c.w[1] = par ? oth[g] : (hasl ? oth[ge] : 0.0);
+    c.e[1] = (int)(par ? g : ge);
+    c.w[2] = own[nh + g];
+    c.e[2] = (int)(rw.jp ? g + H : g);
+    c.w[3] = oth[nh + gjm] * (double)rw.jm;
+    c.e[3] = (int)gjm;
+    c.w[4] = own[2 * nh + g];
+    c.e[4] = (int)(g + rw.kp);
+    c.w[5] = oth[2 * nh + g + rw.km];
+    c.e[5] = (int)(g + rw.km);
+    return c;
+}
+
+__device__ __forceinline__ double couple(const Cpl &c, const double *x)
+{
+    double v = c.w[0] * x[c.e[0]];
+    v += c.w[1] * x[c.e[1]];
+    v += c.w[2] * x[c.e[2]];
+    v += c.w[3] * x[c.e[3]];
+    v += c.w[4] * x[c.e[4]];
+    v += c.w[5] * x[c.e[5]];
+    return v;
+}
+
+template <int CPT>
+__global__ __launch_bounds__(kSB) void k_rb_cg_block(Dims dh, const double *__restrict__ ab, double *__restrict__ y,
+                                                    double *__restrict__ r, double *__restrict__ p, int m,
+                                                    DevScalars *sc)
+{
+    extern __shared__ double lds[];
+    // two buffers for the two sums of an iteration: a thread can only overwrite one
+    // after every thread has passed the barrier of the other, i.e. has read it
+    __shared__ double sha[kSB / 64], shb[kSB / 64];
+    if (sc->done) return;
+    const long nh = dh.n;
+    const int H = dh.nr;
+    double *ps = lds, *ts = lds + nh;
+    const double *blk = ab, *red = ab + 3 * nh;
+    Cpl cr[CPT], cb[CPT];  // couplings of the red and of the black cell at half index g
+    int gi[CPT];
+    bool own[CPT];
+    double rv[CPT], yv[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; c++) {
+        const long g = threadIdx.x + (long)c * kSB;
+        own[c] = g < nh;
+        gi[c] = (int)g;
+        rv[c] = yv[c] = 0.0;
+        if (!own[c]) {
+            cr[c] = cb[c] = Cpl{};
+            continue;
+        }
+        const long row = g / H;
+        const int j = (int)(row % dh.nt), k = (int)(row / dh.nt);
+        Row rw;
+        rw.base = row * H;
+        rw.jp = j + 1 < dh.nt;
+        rw.jm = j > 0;
+        rw.kk = dh.np > 1;
+        rw.kp = (k + 1 < dh.np) ? dh.plane : -(long)(dh.np - 1) * dh.plane;
+        rw.km = (k > 0) ? -dh.plane : (long)(dh.np - 1) * dh.plane;
+        rw.par = (j + k) & 1;
+        const int h0 = (int)(g - rw.base);
+        cr[c] = couplings(dh, rw, h0, 1 - rw.par, red, blk);
+        cb[c] = couplings(dh, rw, h0, rw.par, blk, red);
+        rv[c] = r[g];
+        yv[c] = y[g];
+        ps[g] = p[g];
+    }
+    double rr = sc->rr, beta = sc->beta, pq = sc->pq, alpha = sc->alpha;
+    const double th = sc->thresh2;
+    int it = 0, done = 0;
+    while (it < m && !done) {
+        // p = r + beta p (each thread its own entries)
+#pragma unroll
+        for (int c = 0; c < CPT; c++)
+            if (own[c]) ps[gi[c]] = fma(beta, ps[gi[c]], rv[c]);
+        __syncthreads();
+        // red: t = B p
+#pragma unroll
+        for (int c = 0; c < CPT; c++)
+            if (own[c]) ts[gi[c]] = couple(cr[c], ps);
+        __syncthreads();
+        // black: q = p - B^T t, p.q
+        double qv[CPT], pv[CPT], part = 0.0;
+#pragma unroll
+        for (int c = 0; c < CPT; c++) {
+            qv[c] = pv[c] = 0.0;
+            if (own[c]) {
+                pv[c] = ps[gi[c]];
+                qv[c] = pv[c] - couple(cb[c], ts);
+                part += pv[c] * qv[c];
+            }
+        }
+        pq = wg_sum(part, sha);
+        alpha = rr / pq;
+        part = 0.0;
+#pragma unroll
+        for (int c = 0; c < CPT; c++)
+            if (own[c]) {
+                yv[c] = fma(alpha, pv[c], yv[c]);
+                rv[c] = fma(-alpha, qv[c], rv[c]);
+                part += rv[c] * rv[c];
+            }
+        const double rn = wg_sum(part, shb);
+        beta = rn / rr;
+        rr = rn;
+        it++;
+        if (rn <= th || !(rn == rn)) done = 1;
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; c++)
+        if (own[c]) {
+            r[gi[c]] = rv[c];
+            y[gi[c]] = yv[c];
+            p[gi[c]] = ps[gi[c]];
+        }
+    if (threadIdx.x == 0) {
+        sc->rr = rr;
+        sc->beta = beta;
+        sc->pq = pq;
+        sc->alpha = alpha;
+        sc->iters += it;
+        sc->done = done;
+    }
+}
+
+int rb_block_cpt(const Dims &dh)
+{
+    const long c = (dh.n + kSB - 1) / kSB;
+    return c <= 1 ? 1 : c <= 2 ? 2 : 0;
+}
+
+bool launch_rb_cg_block(const Dims &dh, const double *ab, double *y, double *r, double *p, int m, DevScalars *sc,
+                        hipStream_t st)
+{
+    const int cpt = rb_block_cpt(dh);
+    const size_t lds = 2 * (size_t)dh.n * sizeof(double);  // at most 32 KiB
+    if (cpt == 0 || m <= 0) return false;
+    if (cpt == 1)
+        hipLaunchKernelGGL(k_rb_cg_block<1>, dim3(1), dim3(kSB), lds, st, dh, ab, y, r, p, m, sc);
+    else
+        hipLaunchKernelGGL(k_rb_cg_block<2>, dim3(1), dim3(kSB), lds, st, dh, ab, y, r, p, m, sc);
+    return true;
+}
+
 // --------------------------------------- radial-line block-Jacobi comparator
 //
 // The block-Jacobi class of preconditioner the paper uses (with ILU inside the blocks),

@@ -543,7 +543,17 @@ constexpr size_t kMaxGraphs = 16;
 
 bool use_graphs(const rt_ctx *ctx, const rt_solve_opts *o)
 {
-    return o->graphs > 0 || (o->graphs == 0 && ctx->d.n <= kGraphCells);
+    return o->launch == RT_LAUNCH_GRAPH ||
+           ((o->launch == RT_LAUNCH_AUTO || o->launch == RT_LAUNCH_BLOCK) && ctx->d.n <= kGraphCells);
+}
+
+// The reduced float64 solve runs in one workgroup (launches of up to kBlockChunk
+// iterations, a few tens of ms each).
+constexpr int kBlockChunk = 16384;
+
+bool use_block(const rt_solve_opts *o, const Dims &dh)
+{
+    return (o->launch == RT_LAUNCH_AUTO || o->launch == RT_LAUNCH_BLOCK) && rb_block_cpt(dh) > 0;
 }
 
 // Enqueues m Krylov iterations on ctx->stream, each launched by iter(pold, pnew, stream,
@@ -811,6 +821,7 @@ rt_status solve_fp64_rb(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
     rb_resid(ctx, rhs, yb, rb, tr, 1);
     if (rt_status e = read_scalars(ctx)) return e;
     const int every = o->check_every > 0 ? o->check_every : 32;
+    const bool block = use_block(o, dh);
     rt_status status = RT_OK;
     double res = std::sqrt(h->res2 / bb);
     for (;;) {
@@ -818,18 +829,26 @@ rt_status solve_fp64_rb(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
         if (!isfin(res)) { status = RT_ENONFINITE; break; }
         if (res <= o->tol) break;
         if (h->iters >= o->max_iter) { status = RT_ENOCONV; break; }
-        int m = std::min(every, o->max_iter - h->iters);
-        int it_before = h->iters;
-        bool sampled = false;
-        if (rt_status e = run_iters(ctx, o, 2, m, pold, pnew, [&](double *a, double *b, hipStream_t ss, const hipEvent_t *ev) {
-                launch_rb_iter64(dh, ctx->nblk, ctx->nblk_upd, ctx->rb_a, yb, rb, a, b, qb, tr, ctx->partials,
-                                 ctx->counter, ctx->sc, ss, ev);
-            }, &sampled))
-            return e;
-        RT_HIP(ctx, hipGetLastError());
-        if (rt_status e = read_scalars(ctx)) return e;
-        if (sampled) add_kernel_sample(ctx, st, true);
-        if ((h->iters - it_before) % 2 != m % 2) std::swap(pold, pnew);  // kernels that exited early
+        if (block) {  // one direction buffer: the kernel updates p in place
+            const int m = std::min(kBlockChunk, o->max_iter - h->iters);
+            if (!launch_rb_cg_block(dh, ctx->rb_a, yb, rb, pold, m, ctx->sc, ctx->stream))
+                return fail(ctx, RT_EDEVICE, "one-workgroup CG: grid too large");
+            RT_HIP(ctx, hipGetLastError());
+            if (rt_status e = read_scalars(ctx)) return e;
+        } else {
+            int m = std::min(every, o->max_iter - h->iters);
+            int it_before = h->iters;
+            bool sampled = false;
+            if (rt_status e = run_iters(ctx, o, 2, m, pold, pnew, [&](double *a, double *b, hipStream_t ss, const hipEvent_t *ev) {
+                    launch_rb_iter64(dh, ctx->nblk, ctx->nblk_upd, ctx->rb_a, yb, rb, a, b, qb, tr, ctx->partials,
+                                     ctx->counter, ctx->sc, ss, ev);
+                }, &sampled))
+                return e;
+            RT_HIP(ctx, hipGetLastError());
+            if (rt_status e = read_scalars(ctx)) return e;
+            if (sampled) add_kernel_sample(ctx, st, true);
+            if ((h->iters - it_before) % 2 != m % 2) std::swap(pold, pnew);  // kernels that exited early
+        }
         if (!isfin(h->rr)) { status = RT_ENONFINITE; st->relres = NAN; break; }
         if (h->done || h->iters >= o->max_iter) {
             rb_resid(ctx, rhs, yb, rb, tr, 1);
@@ -1190,6 +1209,8 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
                       o->mode == RT_SOLVE_GMRES,
              "unknown solve mode");
     RT_CHECK(ctx, o->mode != RT_SOLVE_LEARNED || o->net, "learned mode needs a network");
+    RT_CHECK(ctx, o->launch >= RT_LAUNCH_AUTO && o->launch <= RT_LAUNCH_BLOCK,
+             "rt_fld_solve: launch must be an rt_launch value");
     RT_CHECK(ctx, o->precond == 0 || (o->precond == 1 && o->mode == RT_SOLVE_FP64 && !o->reduce),
              "precond = 1 (radial-line block Jacobi) needs RT_SOLVE_FP64 without reduce");
     rt_solve_stats local{};

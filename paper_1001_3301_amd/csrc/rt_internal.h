@@ -217,6 +217,11 @@ void launch_rb_red_apply(const Dims &dh, int nblk, const double *ab, const doubl
 void launch_rb_black_apply(const Dims &dh, int nblk, const double *ab, const double *t, const double *u,
                            const double *x, double sgn, double *out, double *partials, unsigned *counter,
                            DevScalars *sc, int restart, hipStream_t st);
+// One-workgroup float64 CG on S for at most 2048 black cells (rb_block_cpt > 0): up to
+// m iterations, stopping at convergence; false if the grid is too large.
+int rb_block_cpt(const Dims &dh);
+bool launch_rb_cg_block(const Dims &dh, const double *ab, double *y, double *r, double *p, int m, DevScalars *sc,
+                        hipStream_t st);
 void launch_rb_iter64(const Dims &dh, int nblk, int nblk_upd, const double *ab, double *y, double *r, double *pold,
                       double *pnew, double *q, double *t, double *partials, unsigned *counter, DevScalars *sc,
                       hipStream_t st, const hipEvent_t *ev);

@@ -20,6 +20,7 @@ RT_OK, RT_EINVAL, RT_EDEVICE, RT_ENOMEM, RT_ENONFINITE, RT_ENOCONV = range(6)
 STATUS_NAMES = {0: "RT_OK", 1: "RT_EINVAL", 2: "RT_EDEVICE", 3: "RT_ENOMEM", 4: "RT_ENONFINITE",
                 5: "RT_ENOCONV"}
 MODE_FP64, MODE_MIXED, MODE_LEARNED, MODE_GMRES, MODE_NONE = 0, 1, 2, 3, 4
+LAUNCH_AUTO, LAUNCH_DIRECT, LAUNCH_GRAPH, LAUNCH_BLOCK = 0, 1, 2, 3
 
 dp = C.POINTER(C.c_double)
 
@@ -58,7 +59,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("check_every", C.c_int), ("inner_tol", C.c_double), ("inner_max_iter", C.c_int),
                 ("net", C.c_void_p), ("restart", C.c_int), ("reduce", C.c_int), ("precond", C.c_int),
-                ("graphs", C.c_int)]
+                ("launch", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -231,10 +232,10 @@ class GrayOpacity:
 
 
 def solve_opts(mode=MODE_FP64, tol=1e-8, max_iter=100000, check_every=32, inner_tol=1e-4,
-               inner_max_iter=0, net=None, restart=30, reduce=0, precond=0, graphs=0) -> SolveOpts:
+               inner_max_iter=0, net=None, restart=30, reduce=0, precond=0, launch=0) -> SolveOpts:
     nh = None if net is None else (net.h if isinstance(net, Net) else net)
     o = SolveOpts(mode, tol, max_iter, check_every, inner_tol, inner_max_iter, nh, restart, int(reduce),
-                  int(precond), int(graphs))
+                  int(precond), int(launch))
     o._net = net  # keeps the network alive as long as the options refer to it
     return o
 

@@ -1,5 +1,5 @@
-"""Krylov iterations replayed from HIP graphs (rt_solve_opts.graphs = 1) against the same
-iterations launched one by one (graphs = -1).
+"""Krylov iterations replayed from HIP graphs (rt_solve_opts.launch = RT_LAUNCH_GRAPH) against the same
+iterations launched one by one (RT_LAUNCH_DIRECT).
 
 The kernels read every scalar from device memory and reduce in a fixed order, so a graph
 replay must reproduce the direct launches bit for bit: same iterate, same iteration
@@ -47,7 +47,7 @@ def _systems(wl, P, count):
     return out
 
 
-def _run(wl, P, systems, mode, reduce, graphs, check_every, max_iter, tol):
+def _run(wl, P, systems, mode, reduce, launch, check_every, max_iter, tol):
     from paper_1001_3301_amd import rt
     ctx = rt.Context.from_workload(wl)
     res = []
@@ -57,7 +57,7 @@ def _run(wl, P, systems, mode, reduce, graphs, check_every, max_iter, tol):
         for _ in range(2):  # the second solve replays every cached graph from the start
             E = _d(En)
             rc, st = ctx.solve(E, rt.solve_opts(mode, tol=tol, max_iter=max_iter, check_every=check_every,
-                                                reduce=reduce, graphs=graphs), raise_on_error=False)
+                                                reduce=reduce, launch=launch), raise_on_error=False)
             side.add_(1.0).mul_(0.5)  # eager work on the current stream between solves
             torch.cuda.synchronize()
             res.append((rc, st["iters"], st["relres"], st["reduced"], _h(E)))
@@ -72,8 +72,8 @@ def test_graph_replay_matches_direct_launches(mode, check_every):
     systems = _systems(wl, P, 3)
     m, rb = MODES[mode]
     tol = 1e-10
-    g = _run(wl, P, systems, m, rb, 1, check_every, 100000, tol)
-    d = _run(wl, P, systems, m, rb, -1, check_every, 100000, tol)
+    g = _run(wl, P, systems, m, rb, 2, check_every, 100000, tol)
+    d = _run(wl, P, systems, m, rb, 1, check_every, 100000, tol)
     for a, b in zip(g, d):
         assert a[0] == b[0] == 0
         assert a[1] == b[1] and a[2] == b[2] and a[3] == b[3] == rb
@@ -90,8 +90,8 @@ def test_graph_short_last_chunk_and_no_convergence(mode):
     P = oracle.Problem.from_workload(wl)
     systems = _systems(wl, P, 2)
     m, rb = MODES[mode]
-    g = _run(wl, P, systems, m, rb, 1, 16, 45, 1e-14)
-    d = _run(wl, P, systems, m, rb, -1, 16, 45, 1e-14)
+    g = _run(wl, P, systems, m, rb, 2, 16, 45, 1e-14)
+    d = _run(wl, P, systems, m, rb, 1, 16, 45, 1e-14)
     for a, b in zip(g, d):
         assert a[0] == b[0] == rt.RT_ENOCONV
         assert a[1] == b[1] == 45
@@ -99,12 +99,14 @@ def test_graph_short_last_chunk_and_no_convergence(mode):
         assert np.array_equal(a[4], b[4])
 
 
-def test_graphs_default_on_small_grids_only():
-    """graphs = 0 (the default) replays graphs on small grids: same bits as direct launches."""
+def test_graphs_by_default_on_small_grids():
+    """RT_LAUNCH_AUTO (the default) replays graphs on small grids (the full-system solve
+    here; the reduced float64 one would run in one workgroup): the same bits as direct
+    launches."""
     wl = sy.make_workload("a", 64, 16, 1, 32, 1.0)
     P = oracle.Problem.from_workload(wl)
     systems = _systems(wl, P, 1)
-    a = _run(wl, P, systems, 0, 1, 0, 32, 100000, 1e-12)
-    b = _run(wl, P, systems, 0, 1, -1, 32, 100000, 1e-12)
+    a = _run(wl, P, systems, 0, 0, 0, 32, 100000, 1e-12)
+    b = _run(wl, P, systems, 0, 0, 1, 32, 100000, 1e-12)
     for x, y in zip(a, b):
         assert x[1] == y[1] and np.array_equal(x[4], y[4])
