@@ -263,6 +263,10 @@ CONFIGS = {
                                     seeds=(1000, 1001, 1002, 1003)),
     "clumpy-256x128x256-nu64": dict(nr=256, nt=128, nph=256, n_nu=64, taus=(100.0,), seeds=(3000,)),
     "clumpy-512x256x512-nu64": dict(nr=512, nt=256, nph=512, n_nu=64, taus=(100.0,), seeds=(5000,)),
+    # one GPU's share of the 512x256x512 grid split into eight phi-slabs, at its shape
+    # (generated as a whole periodic grid, so kernel times carry over, iteration counts
+    # do not)
+    "clumpy-512x256x64-nu64": dict(nr=512, nt=256, nph=64, n_nu=64, taus=(100.0,), seeds=(5001,)),
 }
 
 
