@@ -988,12 +988,30 @@ void launch_rb_iter32(const Dims &dh, int nblk, int nblk_upd, const float *ab, f
 // start and written back at the end, so launches chain like the multi-block chunks.
 constexpr int kSB = 1024;
 
-// Sum over the workgroup; the same value in every thread (the butterfly leaves the
-// wave total in every lane, and every thread adds the wave totals in index order).
+// A lane permutation inside each row of 16 lanes (DPP), applied to a double.
+template <int Ctrl>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    int2 t = *reinterpret_cast<int2 *>(&v);
+    t.x = __builtin_amdgcn_update_dpp(0, t.x, Ctrl, 0xF, 0xF, false);
+    t.y = __builtin_amdgcn_update_dpp(0, t.y, Ctrl, 0xF, 0xF, false);
+    return *reinterpret_cast<double *>(&t);
+}
+
+// Sum over the workgroup; the same value in every thread.  Inside a wave: four DPP
+// butterfly steps inside each row of 16 lanes (swap neighbours, swap pairs, mirror
+// halves of 8, mirror the row; each step adds a lane and its partner, a + b = b + a,
+// so every lane of a row ends with the same row total), then the four row totals read
+// into scalars and added in a fixed order.  Across the workgroup every thread adds the
+// wave totals in index order, so the convergence test is uniform.
 __device__ __forceinline__ double wg_sum(double v, double *sh)
 {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_d<0x141>(v);  // row_half_mirror
+    v += dpp_d<0x140>(v);  // row_mirror
+    const double w = (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = w;
     __syncthreads();
     double t = 0.0;
 #pragma unroll
