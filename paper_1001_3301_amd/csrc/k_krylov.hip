@@ -359,7 +359,13 @@ __global__ __launch_bounds__(kKB) void k_cg_upd(Dims d, int nblk, V *__restrict_
 // Mixed mode, reliable update: r32 = float(r) from the float64 residual r = b - A y
 // just computed by k_resid (after y absorbed x32), x32 = 0, rr = r32.r32, and beta
 // rescaled so the next direction continues from the replaced residual
-// (beta = rr_true / rr_prev); restart = 1 starts a fresh direction (beta = 0).
+// (beta = rr_true / rr_prev); restart = 1 starts a fresh direction (beta = 0).  The
+// direction is also restarted when the true residual exceeds the recurrence residual
+// by more than a factor 2 in norm: the float32 recurrence then ran past the accuracy
+// float32 can reach (on a system of one or a few unknowns it reaches zero within a
+// chunk), the old direction says nothing about the replaced residual, and continuing
+// it sends the iteration off course.  On large systems the two residuals agree to a
+// few per cent at each update.
 __global__ __launch_bounds__(kKB) void k_reliable(Dims d, int nblk, const double *__restrict__ r,
                                                   float *__restrict__ r32, float *__restrict__ x32,
                                                   double *__restrict__ partials, unsigned *counter,
@@ -378,7 +384,8 @@ __global__ __launch_bounds__(kKB) void k_reliable(Dims d, int nblk, const double
     double bs = block_sum(acc, sh), tot;
     if (finish_reduce(bs, L, nblk, partials, counter, sh, &tot) && threadIdx.x == 0) {
         double rr_prev = (sc->beta > 0.0) ? sc->rr / sc->beta : 0.0;
-        sc->beta = (restart || rr_prev == 0.0) ? 0.0 : tot / rr_prev;
+        const bool off = !(tot <= 4.0 * sc->rr);
+        sc->beta = (restart || rr_prev == 0.0 || off) ? 0.0 : tot / rr_prev;
         sc->rr = tot;
         sc->done = tot <= sc->thresh2 ? 1 : 0;
     }

@@ -1239,7 +1239,16 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
     S->status = status;
     S->ms = clk.ms();
     if (status == RT_ENOCONV) return fail(ctx, status, "iteration limit reached");
-    if (status == RT_ENONFINITE) return fail(ctx, status, "non-finite residual");
+    if (status == RT_ENONFINITE) {
+        // a restart forms p = r + 0 * p_old, which a non-finite p_old would poison: the
+        // direction buffers start from zero again, as at creation
+        const size_t N = (size_t)ctx->d.n;
+        for (void *pz : {(void *)ctx->p0, (void *)ctx->p1})
+            RT_HIP(ctx, hipMemsetAsync(pz, 0, N * sizeof(double), ctx->stream));
+        for (void *pz : {(void *)ctx->p32a, (void *)ctx->p32b})
+            RT_HIP(ctx, hipMemsetAsync(pz, 0, N * sizeof(float), ctx->stream));
+        return fail(ctx, status, "non-finite residual");
+    }
     return status;
 }
 

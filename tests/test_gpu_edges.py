@@ -1,0 +1,78 @@
+"""Degenerate grids against the oracle: the fewest radial cells the library accepts
+(N_r = 2, one black and one red cell per radial row), a single polar row, a single
+column, N_phi = 2 (both phi faces of a cell join the same neighbour) and few bins.
+
+Every kernel of the step runs at these sizes with most of its threads idle or clamped:
+the ray trace (one partial segment per column), the assembly's boundary faces, the
+Krylov kernels with every neighbour a boundary (full system from graphs, the reduced
+system in one workgroup and from graphs in float32), Newton and the force.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1001_3301_amd import synth as sy
+from _util import rel, initial_temperature
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(2, 1, 1), (2, 3, 1), (4, 2, 2), (6, 1, 4), (10, 7, 2)]
+
+
+def _d(x):
+    return torch.tensor(np.ascontiguousarray(x, dtype=np.float64).ravel(), device="cuda")
+
+
+def _h(t):
+    return t.detach().cpu().numpy()
+
+
+def _wl(shape):
+    return sy.make_workload("edge", *shape, 4, 10.0, clump_seed=31)
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_tiny_raytrace_parity(shape):
+    from paper_1001_3301_amd import rt
+    wl = _wl(shape)
+    P = oracle.Problem.from_workload(wl)
+    ctx = rt.Context.from_workload(wl)
+    T = initial_temperature(P, wl) * np.linspace(0.9, 3.0, P.n)
+    q0, S0, F0 = P.raytrace(wl.rho, T)
+    nr, nt, npp = shape
+    q, S = (torch.empty(P.n, dtype=torch.float64, device="cuda") for _ in range(2))
+    Ff = torch.empty((nr + 1) * nt * npp, dtype=torch.float64, device="cuda")
+    ctx.raytrace(_d(wl.rho), _d(T), q, S, Ff)
+    torch.cuda.synchronize()
+    assert rel(_h(q), q0) < 1e-11
+    assert rel(_h(S), S0) < 1e-11
+    assert rel(_h(Ff), F0) < 1e-11
+
+
+MODES = {  # name: (mode, reduce, solve tol, T bar)
+    "fp64": (0, 0, 1e-13, 1e-11),
+    "fp64-rb": (0, 1, 1e-13, 1e-11),
+    "mixed-rb": (1, 1, 1e-12, 1e-9),
+}
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_tiny_step_parity(shape, mode):
+    from paper_1001_3301_amd import rt
+    m, rb, tol, bar = MODES[mode]
+    wl = _wl(shape)
+    P = oracle.Problem.from_workload(wl)
+    ctx = rt.Context.from_workload(wl)
+    T0 = initial_temperature(P, wl)
+    ref = P.step(wl.rho, T0, tol=1e-14, max_iter=100000)
+    Td = _d(T0)
+    E = torch.empty(P.n, dtype=torch.float64, device="cuda")
+    f = torch.empty(4 * P.n, dtype=torch.float64, device="cuda")
+    rc, st = ctx.step(_d(wl.rho), Td, E, rt.solve_opts(m, tol=tol, max_iter=100000, reduce=rb), f_rad=f)
+    assert rc == 0 and st["solve"]["relres"] <= tol
+    assert st["solve"]["reduced"] == rb
+    assert rel(_h(Td), ref["T"]) < bar
+    fr, fg = ref["force"].reshape(4, P.n), _h(f).reshape(4, P.n)
+    assert rel(fg[0], fr[0]) < 1e-11
