@@ -47,7 +47,9 @@ def test_create_rejects_bad_grids_before_device_use():
     pf = np.linspace(0, 2 * np.pi, 3)
     h = C.c_void_p()
     bad = [(rf[::-1].copy(), tf, pf, 8), (rf, tf, pf, 65), (rf, tf, pf, 0),
-           (rf, np.linspace(0, 4.0, 5), pf, 8)]
+           (rf, np.linspace(0, 4.0, 5), pf, 8),
+           (np.array([1.0, 2.0]), tf, pf, 8),           # one radial cell (the colouring needs two)
+           (np.geomspace(1, 10, 4001), tf, pf, 8)]      # a column too long for the ray trace's LDS
     for r_, t_, p_, nnu in bad:
         g = rt.Grid(len(r_) - 1, len(t_) - 1, len(p_) - 1, r_.ctypes.data_as(rt.dp),
                     t_.ctypes.data_as(rt.dp), p_.ctypes.data_as(rt.dp))

@@ -151,3 +151,12 @@ def test_relax_with_block_solve_matches_multiblock():
         out.append((st, _h(T)))
     assert out[0][0]["steps"] == out[1][0]["steps"]
     assert rel(out[0][1], out[1][1]) < 1e-6
+
+
+def test_launch_value_is_checked():
+    from paper_1001_3301_amd import rt
+    wl = DENSE["thick-40x9x4"]()
+    P, ctx, T, S, En, ref = _system(wl)
+    for bad in (-1, 4):
+        rc, st, E = _solve(ctx, En, bad, 1e-10)
+        assert rc == rt.RT_EINVAL
