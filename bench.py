@@ -321,8 +321,9 @@ def main():
                     help="copy a buffer of this size once before timing (HBM-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: the radiation step is built and measured on a "
-              "single MI355X (no multi-GPU path in this build)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the radiation step runs on a single MI355X; "
+              "splitting it over several GPUs (phi-slabs with halo planes) is designed, not implemented",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
