@@ -62,7 +62,7 @@ def lib():
         P = C.POINTER
         dp = P(C.c_double)
         L.og_star_bins.argtypes = [C.c_double, C.c_int, dp, dp]
-        L.og_raytrace.argtypes = [P(_Grid), P(_Opac), P(_Star), dp, dp, dp, dp, dp]
+        L.og_raytrace.argtypes = [P(_Grid), P(_Opac), P(_Star), dp, dp, dp, dp, dp, dp]
         L.og_energy.argtypes = [P(_Grid), P(_Opac), P(_Fld), dp, dp, dp]
         L.og_assemble.argtypes = [P(_Grid), P(_Opac), P(_Fld), dp, dp, dp, dp, dp,
                                   dp, dp, dp, dp, dp, dp]
@@ -149,14 +149,17 @@ class Problem:
                    T_bc=wl.T_bc, E_floor=wl.E_floor)
 
     # --- per-step pieces -------------------------------------------------
-    def raytrace(self, rho, T, want_faces=True):
+    def raytrace(self, rho, T, want_faces=True, want_bins=False):
+        """(q, S, F) with F the total flux at the radial faces (or None); with want_bins
+        also the flux of every bin at every face, bin fastest."""
         rho, T = _f64(rho).ravel(), _f64(T).ravel()
         q = np.empty(self.n); S = np.empty(self.n)
         nr, nt, npp = self.shape
         F = np.empty((nr + 1) * nt * npp) if want_faces else None
+        Fnu = np.empty((nr + 1) * nt * npp * self.op.nnu) if want_bins else None
         lib().og_raytrace(C.byref(self.g), C.byref(self.op), C.byref(self.st), _p(rho), _p(T),
-                          _p(q), _p(S), _p(F))
-        return q, S, F
+                          _p(q), _p(S), _p(F), _p(Fnu))
+        return (q, S, F, Fnu) if want_bins else (q, S, F)
 
     def energy(self, T, S):
         T, S = _f64(T).ravel(), _f64(S).ravel()

@@ -262,10 +262,13 @@ static double phi1(double x) { return x == 0.0 ? 1.0 : -expm1(-x) / x; }
  *           (1 - e^{-dtau}) / (r_+^3 - r_-^3);
  *   S     - sum_nu kappa_nu Fbar_nu / c = q_nu / (rho c) (reading R3), written with
  *           phi(dtau) so that it stays finite as rho -> 0;
- *   Fface - total stellar flux at every radial face (may be NULL).
+ *   Fface - total stellar flux at every radial face (may be NULL);
+ *   Fnu   - the flux of every bin at every radial face, F_nu(R_star) (R_star / r)^2 e^-tau_nu,
+ *           bin fastest: Fnu[face index * n_nu + bin] (may be NULL).
  */
 void og_raytrace(const og_grid *g, const og_opac *op, const og_star *st,
-                 const double *rho, const double *T, double *q, double *S, double *Fface)
+                 const double *rho, const double *T, double *q, double *S, double *Fface,
+                 double *Fnu)
 {
     int nr = g->nr, nt = g->nt, np = g->np, nnu = op->nnu;
     double R2 = st->R * st->R;
@@ -280,6 +283,7 @@ void og_raytrace(const og_grid *g, const og_opac *op, const og_star *st,
             for (int b = 0; b < nnu; b++) {
                 double tau = 0.0;
                 if (Fface) Fface[fidx(g, 0, j, k)] += st->F0[b] * R2 / (g->rf[0] * g->rf[0]);
+                if (Fnu) Fnu[fidx(g, 0, j, k) * nnu + b] = st->F0[b] * R2 / (g->rf[0] * g->rf[0]);
                 for (int i = 0; i < nr; i++) {
                     long c = cidx(g, i, j, k);
                     double r0 = g->rf[i], r1 = g->rf[i + 1], dr = r1 - r0;
@@ -291,6 +295,7 @@ void og_raytrace(const og_grid *g, const og_opac *op, const og_star *st,
                     q[c] += G * (-expm1(-dtau));
                     S[c] += G * kap * dr * phi1(dtau) / OG_C;
                     if (Fface) Fface[fidx(g, i + 1, j, k)] += st->F0[b] * R2 / (r1 * r1) * exp(-tau);
+                    if (Fnu) Fnu[fidx(g, i + 1, j, k) * nnu + b] = st->F0[b] * R2 / (r1 * r1) * exp(-tau);
                 }
             }
         }
@@ -756,7 +761,7 @@ int og_step(const og_grid *g, const og_opac *op, const og_star *st, const og_fld
     double *bh = (double *)malloc(sizeof(double) * n), *y = (double *)malloc(sizeof(double) * n);
     double *Tn = (double *)malloc(sizeof(double) * n);
     memcpy(Tn, T, sizeof(double) * n);
-    og_raytrace(g, op, st, rho, Tn, q, S, NULL);
+    og_raytrace(g, op, st, rho, Tn, q, S, NULL, NULL);
     og_energy(g, op, f, Tn, S, En);
     og_assemble(g, op, f, rho, Tn, En, q, NULL, w, d, b, s, ah, bh);
     for (long c = 0; c < n; c++) y[c] = En[c] / s[c];

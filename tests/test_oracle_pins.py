@@ -103,14 +103,17 @@ def test_tau_scan_matches_analytic_integral():
     P = _problem(g, op, F0)
     rho = _powerlaw_column_density(g, 1e-19, sy.AU)
     T = np.full(P.n, 50.0)
-    _, _, Ff = P.raytrace(rho, T)
+    _, _, Ff, Fnu = P.raytrace(rho, T, want_bins=True)
     rf = g.r_face
     kap = op.kappa[0]  # T-independent below sublimation
     tau = kap[None, :] * 1e-19 * sy.AU * np.log(rf[:, None] / rf[0])
-    ref = (F0[None, :] * (sy.R_STAR / rf[:, None]) ** 2 * np.exp(-tau)).sum(axis=1)
+    ref_nu = F0[None, :] * (sy.R_STAR / rf[:, None]) ** 2 * np.exp(-tau)  # [face][bin]
+    ref = ref_nu.sum(axis=1)
     got = Ff.reshape(1, 2, 41)[0]
+    got_nu = Fnu.reshape(1, 2, 41, 12)[0]
     for j in range(2):
         assert np.max(np.abs(got[j] / ref - 1)) < 1e-13
+        assert np.max(np.abs(got_nu[j] / ref_nu - 1)) < 1e-13
 
 
 def test_luminosity_conservation_per_ray():
