@@ -204,11 +204,15 @@ rt_status rt_set_star(rt_ctx *ctx, const rt_star *st);
  *              bins (the cell-integrated form of Eqs. 28-33, 36);
  *   S_abs[n]   sum_nu kappa_nu Fbar_nu / c = q_nu / (rho c), the irradiation term of
  *              Eq. (16) in the frequency-dependent form;
- *   F_face     total stellar flux at every radial face, (N_r+1) N_theta N_phi, or NULL.
+ *   F_face     total stellar flux at every radial face, (N_r+1) N_theta N_phi, or NULL;
+ *   F_face_nu  the flux of every bin at every radial face, F_nu(R_star) (R_star / r)^2 e^-tau_nu
+ *              (Eqs. 17, 19), (N_r+1) N_theta N_phi n_nu with the bin fastest:
+ *              F_face_nu[f * n_nu + b] for the face index f of F_face; or NULL (it is
+ *              n_nu times the size of F_face: 34 GB at 512x256x512 with 64 bins).
  * op / st may be NULL to use the tables already on the context. */
 rt_status rt_raytrace(rt_ctx *ctx, const rt_opacity *op, const rt_star *st,
                       const double *rho, const double *T, double *q_star, double *S_abs,
-                      double *F_face);
+                      double *F_face, double *F_face_nu);
 
 /* Fig. 1 "Radiation Energy": E[n] = max(a T^4 - S_abs / kappa_P(T), E_floor). */
 rt_status rt_energy(rt_ctx *ctx, const rt_opacity *op, const rt_fld_params *p,

@@ -30,13 +30,16 @@ struct CellSlot {
     double w, rdr;
 };
 
+// kBins: also write the per-bin face flux Fnu (a separate instantiation, so the plain
+// ray trace keeps its schedule).
+template <bool kBins>
 __global__ __launch_bounds__(1024) void k_raytrace(
     int nr, long ncol, int nnu, int nT,
     const double *__restrict__ rho, const double *__restrict__ T,
     const double *__restrict__ Ttab, const double *__restrict__ kap_g,
     const double *__restrict__ F0, double R2,
     const double *__restrict__ rf2, const double *__restrict__ dr, const double *__restrict__ shell,
-    double *__restrict__ q, double *__restrict__ S, double *__restrict__ Fface)
+    double *__restrict__ q, double *__restrict__ S, double *__restrict__ Fface, double *__restrict__ Fnu)
 {
     extern __shared__ double lds[];
     double *tab = lds;                       // [nT][nnu]
@@ -68,6 +71,7 @@ __global__ __launch_bounds__(1024) void k_raytrace(
         double v = Phi;
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
         if (lane == 0 && Fface) Fface[fbase] = v / rf2[0];
+        if (kBins && active) Fnu[fbase * nnu + lane] = Phi / rf2[0];
     }
 
     const int s8 = lane >> 3, part = lane & 7;  // reduction roles: sum s8 of 2 kChunk, part of 8
@@ -106,6 +110,8 @@ __global__ __launch_bounds__(1024) void k_raytrace(
                         red[m * 64 + lane] = Phi * em;   // absorbed, before the 3/shell factor
                         Phi = Phi * e;
                         red[(kChunk + m) * 64 + lane] = Phi;  // through the outer face
+                        // per-bin flux at that face: one 64-bin row per face, bin fastest
+                        if (kBins && active) Fnu[(fbase + i0 + m + 1) * nnu + lane] = Phi * g_f[i0 + m];
                     }
                 }
                 wave_sync();
@@ -142,19 +148,27 @@ __global__ __launch_bounds__(1024) void k_raytrace(
 
 void launch_raytrace(const Dims &d, const Opac &op, const Geo &g, const double *F0, double R2,
                      const double *rho, const double *T, double *q, double *S, double *Fface,
-                     hipStream_t st)
+                     double *Fnu, hipStream_t st)
 {
     long ncol = (long)d.nt * d.np;
     long nblk = (ncol + kWavesPerBlock - 1) / kWavesPerBlock;
     size_t lds = raytrace_lds_bytes(op.nT, op.nnu, d.nr);
-    hipLaunchKernelGGL(k_raytrace, dim3((unsigned)nblk), dim3(64 * kWavesPerBlock), lds, st,
-                       d.nr, ncol, op.nnu, op.nT, rho, T, op.T, op.kap, F0, R2, g.rf2, g.dr, g.shell,
-                       q, S, Fface);
+    if (Fnu)
+        hipLaunchKernelGGL(k_raytrace<true>, dim3((unsigned)nblk), dim3(64 * kWavesPerBlock), lds, st,
+                           d.nr, ncol, op.nnu, op.nT, rho, T, op.T, op.kap, F0, R2, g.rf2, g.dr, g.shell,
+                           q, S, Fface, Fnu);
+    else
+        hipLaunchKernelGGL(k_raytrace<false>, dim3((unsigned)nblk), dim3(64 * kWavesPerBlock), lds, st,
+                           d.nr, ncol, op.nnu, op.nT, rho, T, op.T, op.kap, F0, R2, g.rf2, g.dr, g.shell,
+                           q, S, Fface, Fnu);
 }
 
 void raytrace_prepare(size_t lds_bytes)
 {
-    (void)hipFuncSetAttribute((const void *)k_raytrace, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    (void)hipFuncSetAttribute((const void *)k_raytrace<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds_bytes);
+    (void)hipFuncSetAttribute((const void *)k_raytrace<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds_bytes);
 }
 
 size_t raytrace_lds_bytes(int nT, int nnu, int nr)

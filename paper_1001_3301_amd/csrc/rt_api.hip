@@ -440,7 +440,7 @@ rt_status rt_set_star(rt_ctx *ctx, const rt_star *st)
 }
 
 rt_status rt_raytrace(rt_ctx *ctx, const rt_opacity *op, const rt_star *st, const double *rho, const double *T,
-                      double *q_star, double *S_abs, double *F_face)
+                      double *q_star, double *S_abs, double *F_face, double *F_face_nu)
 {
     if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
     if (op) { rt_status s = rt_set_opacity(ctx, op); if (s) return s; }
@@ -449,7 +449,7 @@ rt_status rt_raytrace(rt_ctx *ctx, const rt_opacity *op, const rt_star *st, cons
     RT_CHECK(ctx, ctx->have_star, "no star on the context");
     RT_CHECK(ctx, rho && T && q_star && S_abs, "rt_raytrace: NULL field pointer");
     launch_raytrace(ctx->d, ctx->op, ctx->geo, ctx->F0, ctx->R_star * ctx->R_star, rho, T, q_star, S_abs, F_face,
-                    ctx->stream);
+                    F_face_nu, ctx->stream);
     RT_HIP(ctx, hipGetLastError());
     return RT_OK;
 }
@@ -1335,7 +1335,7 @@ rt_status rt_step(rt_ctx *ctx, const rt_opacity *op, const rt_star *st, const rt
     hipStream_t s = ctx->stream;
     Clock clk;
     RT_HIP(ctx, hipEventRecord(ctx->ev[0], s));
-    if (rt_status e = rt_raytrace(ctx, op, st, rho, T, ctx->q, ctx->S, nullptr)) return e;
+    if (rt_status e = rt_raytrace(ctx, op, st, rho, T, ctx->q, ctx->S, nullptr, nullptr)) return e;
     RT_HIP(ctx, hipEventRecord(ctx->ev[1], s));
     if (rt_status e = rt_energy(ctx, nullptr, p, T, ctx->S, ctx->En)) return e;
     if (rt_status e = rt_fld_assemble(ctx, nullptr, p, rho, T, ctx->En, ctx->q, nullptr, nullptr)) return e;

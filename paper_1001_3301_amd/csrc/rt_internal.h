@@ -180,7 +180,7 @@ struct Net;
 // ------------------------------------------------------------------ launchers
 void launch_raytrace(const Dims &d, const Opac &op, const Geo &g, const double *F0, double R2,
                      const double *rho, const double *T, double *q, double *S, double *Fface,
-                     hipStream_t st);
+                     double *Fnu, hipStream_t st);
 size_t raytrace_lds_bytes(int nT, int nnu, int nr);
 void launch_energy(const Dims &d, const Opac &op, const double *T, const double *S, double Efloor,
                    double *E, hipStream_t st);

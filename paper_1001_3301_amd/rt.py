@@ -143,7 +143,7 @@ def lib():
     L.rt_star_bin_flux.argtypes = [C.c_double, C.c_int, dp, dp]
     L.rt_set_opacity.argtypes = [vp, P(Opacity)]
     L.rt_set_star.argtypes = [vp, P(Star)]
-    L.rt_raytrace.argtypes = [vp, P(Opacity), P(Star), vp, vp, vp, vp, vp]
+    L.rt_raytrace.argtypes = [vp, P(Opacity), P(Star), vp, vp, vp, vp, vp, vp]
     L.rt_energy.argtypes = [vp, P(Opacity), P(FldParams), vp, vp, vp]
     L.rt_fld_assemble.argtypes = [vp, P(Opacity), P(FldParams), vp, vp, vp, vp, vp, P(System)]
     L.rt_spmv.argtypes = [vp, vp, vp]
@@ -321,11 +321,15 @@ class Context:
         self._star = (s, F)
 
     # --- the step's calls --------------------------------------------------
-    def raytrace(self, rho, T, q, S, F_face=None):
+    def raytrace(self, rho, T, q, S, F_face=None, F_face_nu=None):
+        """F_face_nu, if given, receives the flux of every bin at every radial face, bin
+        fastest ((N_r + 1) N_theta N_phi n_nu values)."""
         nr, nt, npp = self.shape
+        nf = (nr + 1) * nt * npp
         args = [self._dev(rho, self.n, "rho"), self._dev(T, self.n, "T"), self._dev(q, self.n, "q"),
                 self._dev(S, self.n, "S"),
-                self._dev(F_face, (nr + 1) * nt * npp, "F_face", allow_none=True)]
+                self._dev(F_face, nf, "F_face", allow_none=True),
+                self._dev(F_face_nu, nf * self.n_nu, "F_face_nu", allow_none=True)]
         self._chk(lib().rt_raytrace(self.h, None, None, *args))
 
     def energy(self, T, S, E, params=None):

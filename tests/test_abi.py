@@ -60,5 +60,5 @@ def test_create_rejects_bad_grids_before_device_use():
 
 def test_null_context_is_rejected():
     L = rt.lib()
-    assert L.rt_raytrace(None, None, None, None, None, None, None, None) == rt.RT_EINVAL
+    assert L.rt_raytrace(None, None, None, None, None, None, None, None, None) == rt.RT_EINVAL
     assert L.rt_fld_solve(None, None, None, None) == rt.RT_EINVAL

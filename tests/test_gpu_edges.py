@@ -39,15 +39,17 @@ def test_tiny_raytrace_parity(shape):
     P = oracle.Problem.from_workload(wl)
     ctx = rt.Context.from_workload(wl)
     T = initial_temperature(P, wl) * np.linspace(0.9, 3.0, P.n)
-    q0, S0, F0 = P.raytrace(wl.rho, T)
+    q0, S0, F0, Fnu0 = P.raytrace(wl.rho, T, want_bins=True)
     nr, nt, npp = shape
     q, S = (torch.empty(P.n, dtype=torch.float64, device="cuda") for _ in range(2))
     Ff = torch.empty((nr + 1) * nt * npp, dtype=torch.float64, device="cuda")
-    ctx.raytrace(_d(wl.rho), _d(T), q, S, Ff)
+    Fnu = torch.empty((nr + 1) * nt * npp * 4, dtype=torch.float64, device="cuda")
+    ctx.raytrace(_d(wl.rho), _d(T), q, S, Ff, Fnu)
     torch.cuda.synchronize()
     assert rel(_h(q), q0) < 1e-11
     assert rel(_h(S), S0) < 1e-11
     assert rel(_h(Ff), F0) < 1e-11
+    assert rel(_h(Fnu), Fnu0) < 1e-11
 
 
 MODES = {  # name: (mode, reduce, solve tol, T bar)

@@ -45,15 +45,24 @@ def test_raytrace_parity(case):
     P = oracle.Problem.from_workload(wl)
     ctx = _ctx(wl)
     T = seeded_temperature(P.n, 5, 10.0, 2500.0)  # spans the sublimation drop
-    q0, S0, F0 = P.raytrace(wl.rho, T)
+    q0, S0, F0, Fnu0 = P.raytrace(wl.rho, T, want_bins=True)
     nr, nt, npp = wl.grid.shape
     q, S, F = (torch.empty(P.n, dtype=torch.float64, device="cuda") for _ in range(3))
     Ff = torch.empty((nr + 1) * nt * npp, dtype=torch.float64, device="cuda")
-    ctx.raytrace(_d(wl.rho), _d(T), q, S, Ff)
+    Fnu = torch.empty((nr + 1) * nt * npp * ctx.n_nu, dtype=torch.float64, device="cuda")
+    ctx.raytrace(_d(wl.rho), _d(T), q, S, Ff, Fnu)
     torch.cuda.synchronize()
     assert rel(_h(q), q0) < 1e-11
     assert rel(_h(S), S0) < 1e-11
     assert rel(_h(Ff), F0) < 1e-11
+    # per-bin fluxes: relative to each face's total, since a bin deep in an optically
+    # thick column underflows toward 0 (e^-tau below 1e-300)
+    g, r = _h(Fnu).reshape(-1, ctx.n_nu), Fnu0.reshape(-1, ctx.n_nu)
+    assert np.max(np.abs(g - r) / np.maximum(F0[:, None], 1e-300)) < 1e-11
+    # and without it the other outputs are the same bits
+    q2, S2 = torch.empty_like(q), torch.empty_like(S)
+    ctx.raytrace(_d(wl.rho), _d(T), q2, S2)
+    assert torch.equal(q, q2) and torch.equal(S, S2)
 
 
 def test_raytrace_c2_tau100_full():
