@@ -342,6 +342,13 @@ rt_status rt_net_load(rt_net *net, const char *path);
 
 /* z[n] (fp32, device) = network(X) for X[n][16] (bf16 bits, device) on the context's grid. */
 rt_status rt_net_forward(rt_ctx *ctx, rt_net *net, const void *X, float *z);
+/* The learned preconditioner's action z = M(r) as RT_SOLVE_LEARNED applies it: the
+ * residual r[n] (fp32, device) scaled to unit RMS and the operator features of the
+ * context's assembled system form the input, and the output is scaled back by the same
+ * factor (z[n], fp32, device).  Needs an assembled system (RT_EINVAL otherwise) and grid
+ * dimensions divisible by 4; overwrites the context's Krylov scalars, so not during a
+ * solve on the same context. */
+rt_status rt_net_apply(rt_ctx *ctx, rt_net *net, const float *r, float *z);
 /* Forward pass, loss L = ||z - e||^2 / ||e||^2 for the target e[n] (fp32, device) and
  * backward pass; the gradient stays on the network for rt_net_adam.  z (device) and
  * loss (host) may be NULL. */

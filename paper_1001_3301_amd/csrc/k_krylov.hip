@@ -520,6 +520,22 @@ __global__ __launch_bounds__(kKB) void k_norm2(Dims d, int nblk, const double *_
     if (finish_reduce(bs, L, nblk, partials, counter, sh, &tot) && threadIdx.x == 0) sc->res2 = tot;
 }
 
+// rr = x.x for a float32 vector (float64 accumulation): the input scale of a standalone
+// application of the learned preconditioner.
+__global__ __launch_bounds__(kKB) void k_norm2_rr32(Dims d, int nblk, const float *__restrict__ x,
+                                                    double *partials, unsigned *counter, DevScalars *sc)
+{
+    __shared__ double sh[kKB / 64];
+    const long L = logical_block(nblk);
+    double acc = 0.0;
+    for_segments<1>(d, nblk, [&](const Row &rw, int i) {
+        const double v = x[rw.base + i];
+        acc += v * v;
+    });
+    double bs = block_sum(acc, sh), tot;
+    if (finish_reduce(bs, L, nblk, partials, counter, sh, &tot) && threadIdx.x == 0) sc->rr = tot;
+}
+
 // ------------------------------------------------------------------ launchers
 
 // Bytes per array that one thread moves per segment (16, 32 or 64: one, two or four
@@ -658,6 +674,12 @@ void launch_cg_upd32(const Dims &d, int nblk, float *x, const float *p, float *r
 {
     const int vw = pick_vw<float>(d);
     RT_DISPATCH_VW(float, vw, k_cg_upd, dim3(nblk), dim3(kKB), 0, st, d, nblk, x, p, r, q, partials, counter, sc);
+}
+
+void launch_norm2_rr32(const Dims &d, int nblk, const float *x, double *partials, unsigned *counter,
+                       DevScalars *sc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_norm2_rr32, dim3(nblk), dim3(kKB), 0, st, d, nblk, x, partials, counter, sc);
 }
 
 void launch_rms_scale(long n, const DevScalars *sc, double *scale, hipStream_t st)

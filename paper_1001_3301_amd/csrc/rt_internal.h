@@ -265,6 +265,8 @@ void launch_fcg_beta(const Dims &d, int nblk, const float *z, const float *q, do
 void launch_cg_upd32(const Dims &d, int nblk, float *x, const float *p, float *r, const float *q, double *partials,
                      unsigned *counter, DevScalars *sc, hipStream_t st);
 void launch_rms_scale(long n, const DevScalars *sc, double *scale, hipStream_t st);
+void launch_norm2_rr32(const Dims &d, int nblk, const float *x, double *partials, unsigned *counter,
+                       DevScalars *sc, hipStream_t st);
 void launch_unscale(long n, const float *zn, const double *scale, float *z, hipStream_t st);
 
 // U-Net kernels (k_unet.hip): bf16 tensors as raw 16-bit values.

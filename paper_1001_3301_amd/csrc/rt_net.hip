@@ -368,6 +368,15 @@ rt_status rt_net_forward(rt_ctx *ctx, rt_net *net, const void *X, float *z)
     return RT_OK;
 }
 
+rt_status rt_net_apply(rt_ctx *ctx, rt_net *net, const float *r, float *z)
+{
+    if (!ctx || !net || !r || !z) return nfail(net, RT_EINVAL, "rt_net_apply: NULL argument");
+    if (!ctx->have_system) return nfail(net, RT_EINVAL, "rt_net_apply: no assembled system on the context");
+    if (rt_status e = net_prepare(net, ctx)) return e;
+    launch_norm2_rr32(ctx->d, ctx->nblk, r, ctx->partials, ctx->counter, ctx->sc, ctx->stream);
+    return net_precond(net, ctx, r, z);
+}
+
 rt_status rt_net_loss_grad(rt_ctx *ctx, rt_net *net, const void *X, const float *e, float *z, double *loss_out)
 {
     if (!ctx || !net || !X || !e) return nfail(net, RT_EINVAL, "rt_net_loss_grad: NULL argument");

@@ -99,7 +99,7 @@ EXPORTS = ["rt_create", "rt_destroy", "rt_last_error", "rt_ncell", "rt_star_bin_
            "rt_gray_table", "rt_relax", "rt_rosseland_depth", "rt_precond_apply",
            "rt_net_create", "rt_net_destroy", "rt_net_last_error", "rt_net_param_count",
            "rt_net_get_params", "rt_net_get_grads", "rt_net_set_params", "rt_net_save", "rt_net_load",
-           "rt_net_forward", "rt_net_loss_grad", "rt_net_loss_grad_resid", "rt_net_adam", "rt_dataset_create",
+           "rt_net_forward", "rt_net_apply", "rt_net_loss_grad", "rt_net_loss_grad_resid", "rt_net_adam", "rt_dataset_create",
            "rt_dataset_destroy", "rt_dataset_size", "rt_dataset_add", "rt_dataset_add_learned", "rt_net_train",
            "rt_nn_conv3d_fwd", "rt_nn_conv3d_bwd_data", "rt_nn_conv3d_bwd_weight"]
 
@@ -172,6 +172,7 @@ def lib():
     L.rt_net_save.argtypes = [vp, C.c_char_p]
     L.rt_net_load.argtypes = [vp, C.c_char_p]
     L.rt_net_forward.argtypes = [vp, vp, vp, vp]
+    L.rt_net_apply.argtypes = [vp, vp, vp, vp]
     L.rt_net_loss_grad.argtypes = [vp, vp, vp, vp, vp, P(C.c_double)]
     L.rt_net_loss_grad_resid.argtypes = [vp, vp, vp, vp, vp, vp, P(C.c_double)]
     L.rt_net_adam.argtypes = [vp, vp, C.c_double]
@@ -474,6 +475,11 @@ class Net:
     def forward(self, ctx, X, z):
         self._chk(lib().rt_net_forward(ctx.h, self.h, ctx._dev(X, ctx.n * 16, "X", ctx._torch.bfloat16),
                                        ctx._dev(z, ctx.n, "z", ctx._torch.float32)))
+
+    def apply(self, ctx, r, z):
+        """z = M(r), the preconditioner's action on the fp32 residual r on ctx's system."""
+        self._chk(lib().rt_net_apply(ctx.h, self.h, ctx._dev(r, ctx.n, "r", ctx._torch.float32),
+                                     ctx._dev(z, ctx.n, "z", ctx._torch.float32)))
 
     def loss_grad(self, ctx, X, e, z=None):
         L = C.c_double()

@@ -365,3 +365,46 @@ def test_learned_solve_with_reduced_mixed_finish():
     ctx.temperature(E, S, Tl)
     ctx.temperature(E_f, S, Tf)
     assert float(((Tl - Tf).abs() / Tf).max()) < 1e-5
+
+
+def test_net_apply_is_the_scaled_forward_of_the_solver_input():
+    """rt_net_apply: the input the learned solve builds (residual at unit RMS, the scaled
+    operator's face features) through rt_net_forward, scaled back; positively homogeneous
+    bit for bit (2 r gives exactly 2 z); no system, no application."""
+    import oracle
+    from paper_1001_3301_amd import rt
+    from _util import initial_temperature
+    shape = (16, 8, 8)
+    n = 16 * 8 * 8
+    wl, ctx = _ctx_for(shape)
+    net = rt.Net(seed=11)
+    r = _rng(21).standard_normal(n).astype(np.float32)
+    z = torch.empty(n, dtype=torch.float32, device="cuda")
+    with pytest.raises(rt.RtError) as ei:
+        net.apply(ctx, dev_f32(r), z)
+    assert ei.value.status == rt.RT_EINVAL
+    P = oracle.Problem.from_workload(wl)
+    T = initial_temperature(P, wl)
+    q, S, _ = P.raytrace(wl.rho, T, want_faces=False)
+    En = P.energy(T, S)
+    ref = P.assemble(wl.rho, T, En, q)
+    d64 = lambda x: torch.tensor(np.ascontiguousarray(x, dtype=np.float64).ravel(), device="cuda")
+    ctx.assemble(d64(wl.rho), d64(T), d64(En), d64(q))
+    net.apply(ctx, dev_f32(r), z)
+    # the same input built on the host from the definition in rt.h
+    s = np.sqrt(n / np.sum(r.astype(np.float64) ** 2))
+    X = np.zeros((n, 16), dtype=np.float32)
+    X[:, 0] = (r.astype(np.float64) * s).astype(np.float32)
+    a = -ref["ahat"].reshape(3, n)
+    with np.errstate(divide="ignore"):
+        f = np.where(a > 1e-30, np.log10(np.maximum(a, 1e-300)), -30.0)
+    X[:, 1:4] = ((np.clip(f, -30.0, 0.0) + 15.0) / 15.0).T.astype(np.float32)
+    zf = torch.empty(n, dtype=torch.float32, device="cuda")
+    net.forward(ctx, dev_bf16(bf16_bits(X.ravel())), zf)
+    zref = (zf.cpu().numpy().astype(np.float64) / s).astype(np.float32)
+    zg = z.cpu().numpy()
+    assert np.all(np.isfinite(zg))
+    assert np.linalg.norm(zg - zref) <= 1e-2 * np.linalg.norm(zref)
+    z2 = torch.empty_like(z)
+    net.apply(ctx, dev_f32(2.0 * r), z2)
+    assert np.array_equal(z2.cpu().numpy(), 2.0 * zg)
