@@ -53,6 +53,16 @@ MEASURED_TRAFFIC = {("k_cg_dir<float>", "clumpy-512x256x512-nu64"): 1.924e9,
                     ("k_rb_black_dir<double>", "clumpy-512x256x512-nu64"): 2.560e9}
 
 
+# The ray trace is bound by float64 instruction issue: a wavefront handles one cell per
+# step with its lanes on the bins, so VALU wave-instructions per cell is a property of the
+# kernel (rocprofv3 SQ_INSTS_VALU on the 512x256x512 workload,
+# profiles/raytrace_counters_clumpy-512x256x512-nu64.md), and the chip issues at most one
+# float64 wave-instruction per CU per cycle (4 SIMDs, 4 cycles per wave64 instruction):
+# 256 CUs x 2.4 GHz.
+RAYTRACE_VALU_PER_CELL = 57.3
+PEAK_FP64_WAVE_INSTS = 256 * 2.4e9
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -415,6 +425,13 @@ def main():
                    "solve_mode": head, "tol": args.tol, "dt": wl.dt,
                    "step": "first step from the prepared state, repeated K times"},
         "raytrace_gcell_nu_per_s": statistics.median([n * c["n_nu"] / (x / 1e3) / 1e9 for x in rt_ms]),
+        "raytrace_roofline": {"kernel": "k_raytrace<false>", "bound": "alu",
+                              "unit": "float64 VALU wave-instructions/s",
+                              "achieved": RAYTRACE_VALU_PER_CELL * n / (statistics.median(rt_ms) / 1e3),
+                              "peak": PEAK_FP64_WAVE_INSTS,
+                              "frac": RAYTRACE_VALU_PER_CELL * n / (statistics.median(rt_ms) / 1e3)
+                              / PEAK_FP64_WAVE_INSTS,
+                              "valu_insts_per_cell": RAYTRACE_VALU_PER_CELL},
         "solve_iters_per_step": statistics.median([s["solve"]["iters"] for s in R["stats"]]),
         "kernel_ms": {"dir": ms_dir, "upd": ms_upd, "black": ms_black, "samples": samples},
     }
