@@ -173,7 +173,7 @@ def run_mode(ctx, rt, torch, rho, T0, mode, steps, warmup, tol, inner_tol, max_i
             f"relres {st['solve']['relres']:.2e}, reduced {st['solve']['reduced']}), "
             f"dir {st['solve']['ms_dir']*1e3:.1f} us, black {st['solve']['ms_black']*1e3:.1f} us, "
             f"upd {st['solve']['ms_upd']*1e3:.1f} us")
-    return dict(wall_s=wall, stats=stats, T=T, E=E)
+    return dict(wall_s=wall, stats=stats, T=T, E=E, f=f)
 
 
 def run_successive(ctx, rt, torch, rho, T0, mode, nsteps, tol, inner_tol, max_iter, net=None, budget=0):
@@ -469,10 +469,15 @@ def main():
         if head.startswith("learned"):  # the network is the part of this mode the GPU is asked to run fast
             out["roofline"] = dict(out["learned"]["unet_roofline"], traffic=None)
     if "fp64" in modes:
-        Tf = results["fp64"]["T"]
+        Tf, Ef, ff = results["fp64"]["T"], results["fp64"]["E"], results["fp64"]["f"].view(4, -1)
+        thermal = ff[1:].norm(dim=0).max()  # the thermal force differentiates E: judged on its scale
         for mode in modes:
             if mode != "fp64":
-                out[f"T_rel_diff_{mode}_vs_fp64"] = float(((results[mode]["T"] - Tf).abs() / Tf).max())
+                Rm = results[mode]
+                out[f"T_rel_diff_{mode}_vs_fp64"] = float(((Rm["T"] - Tf).abs() / Tf).max())
+                out[f"E_rel_diff_{mode}_vs_fp64"] = float(((Rm["E"] - Ef).abs() / Ef.abs()).max())
+                out[f"thermal_force_diff_{mode}_vs_fp64"] = float(
+                    (Rm["f"].view(4, -1)[1:] - ff[1:]).abs().max() / thermal)
     if args.successive > 0:
         out["successive_steps"] = run_successive(ctx, rt, torch, rho, T0, head, args.successive, args.tol,
                                                  args.inner_tol, args.max_iter, net, args.learned_budget)
