@@ -75,6 +75,10 @@ UNET_FLOP_PER_CELL = 54 * (256 + 256 + 768 + 256) + 54 * (512 + 1024 + 3072 + 10
 PEAK_BF16_TFLOPS = 2500.0
 
 
+LAUNCH = {"auto": 0, "direct": 1, "graph": 2, "block": 3}  # rt_launch
+_launch = 0
+
+
 def mode_opts(rt, mode, tol, max_iter, inner_tol, net=None, budget=0, restart=30):
     """Solve options of a bench mode; the suffix -rb solves the red-black reduced system,
     -line preconditions float64 CG with the radial-line block Jacobi."""
@@ -82,7 +86,8 @@ def mode_opts(rt, mode, tol, max_iter, inner_tol, net=None, budget=0, restart=30
     m = {"fp64": rt.MODE_FP64, "mixed": rt.MODE_MIXED, "learned": rt.MODE_LEARNED, "gmres": rt.MODE_GMRES}[base]
     return rt.solve_opts(m, tol=tol, max_iter=max_iter, check_every=32, inner_tol=inner_tol,
                          inner_max_iter=budget if base == "learned" else 0, net=net if base == "learned" else None,
-                         restart=restart, reduce=int(mode.endswith("-rb")), precond=int(mode.endswith("-line")))
+                         restart=restart, reduce=int(mode.endswith("-rb")), precond=int(mode.endswith("-line")),
+                         launch=_launch)
 
 
 def train_network(rt, torch, sy, n_fields, epochs, seed=7):
@@ -327,9 +332,14 @@ def main():
                     help="also run this many successive steps of the headline mode (not timed for value)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-main-loop", action="store_true", help="skip the main-loop runs to equilibrium")
+    ap.add_argument("--launch", choices=list(LAUNCH), default="auto",
+                    help="how the solver's iterations are launched (rt_launch); kernel times are sampled "
+                         "only with direct launches, which auto takes above 4,194,304 cells")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy a buffer of this size once before timing (HBM-counter calibration)")
     args = ap.parse_args()
+    global _launch
+    _launch = LAUNCH[args.launch]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the radiation step runs on a single MI355X; "
               "splitting it over several GPUs (phi-slabs with halo planes) is designed, not implemented",
