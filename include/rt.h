@@ -139,8 +139,8 @@ typedef enum {
                              the kernel times of rt_solve_stats */
     RT_LAUNCH_GRAPH = 2,  /* the chunks of iterations between convergence polls replayed from
                              HIP graphs captured once per context */
-    RT_LAUNCH_BLOCK = 3   /* reduced float64 CG (reduce = 1, also the finish of the reduced
-                             mixed and learned solves) with at most 2048 black cells: all
+    RT_LAUNCH_BLOCK = 3   /* reduced float64 CG (reduce = 1, also where a reduced mixed solve
+                             falls back to it) with at most 2048 black cells: all
                              iterations inside one workgroup, the vectors whose neighbours are
                              read kept in LDS (dot products summed in another order than the
                              multi-block kernels); other solves as AUTO */
