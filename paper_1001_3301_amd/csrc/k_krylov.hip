@@ -151,15 +151,17 @@ __device__ __forceinline__ void for_segments(const Dims &d, int nblk, F &&f)
     const int dj = (int)(S % blen), dk = (int)(S / blen);
     const long pl = d.plane, wrap = (long)(d.np - 1) * d.plane;
     for (; u < nrows; u += S) {
-        const int j = j0 + jb;
+        // d.rev mirrors the band (row u -> nrows - 1 - u): consecutive passes that sweep
+        // in opposite directions start on the rows the previous pass touched last
+        const int j = j0 + (d.rev ? blen - 1 - jb : jb), kq = d.rev ? d.np - 1 - k : k;
         Row rw;
-        rw.base = ((long)k * d.nt + j) * d.nr;
+        rw.base = ((long)kq * d.nt + j) * d.nr;
         rw.jp = j + 1 < d.nt;
         rw.jm = j > 0;
         rw.kk = d.np > 1;
-        rw.kp = (k + 1 < d.np) ? pl : -wrap;
-        rw.km = (k > 0) ? -pl : wrap;
-        rw.par = (j + k) & 1;
+        rw.kp = (kq + 1 < d.np) ? pl : -wrap;
+        rw.km = (kq > 0) ? -pl : wrap;
+        rw.par = (j + kq) & 1;
         for (int i = i0; i < d.nr; i += istep) f(rw, i);
         jb += dj;
         k += dk;
@@ -969,34 +971,44 @@ void launch_rb_black_apply(const Dims &dh, int nblk, const double *ab, const dou
                    u, x, sgn, out, partials, counter, sc, restart);
 }
 
+// The three passes of an iteration sweep the rows in alternating directions (red
+// forward on even iterations, black backward, update forward, the next red backward, ...)
+// so that each pass starts on what the previous one read and wrote last, which the
+// 256 MB Infinity Cache still holds: at 512x256x512 the black pass then takes 229 us
+// instead of 239 us (it rereads the red pass's six coefficient arrays and p and t), the
+// reduced mixed solve 0.899 s instead of 0.913 s.  The two passes of a full-system
+// iteration did not gain from it.
 template <typename V>
 static void rb_iter(const Dims &dh, int nblk, int nblk_upd, const V *ab, V *y, V *r, V *pold, V *pnew, V *q, V *t,
-                    double *partials, unsigned *counter, DevScalars *sc, hipStream_t st, const hipEvent_t *ev)
+                    double *partials, unsigned *counter, DevScalars *sc, hipStream_t st, const hipEvent_t *ev, int odd)
 {
     const int vw = pick_vw<V>(dh);
+    Dims da = dh, db = dh;
+    da.rev = odd;
+    db.rev = !odd;
     if (ev) (void)hipEventRecord(ev[0], st);
-    RT_DISPATCH_VW(V, vw, k_rb_red_dir, dim3(nblk), dim3(kKB), 0, st, dh, nblk, ab, r, pold, pnew, t, sc);
+    RT_DISPATCH_VW(V, vw, k_rb_red_dir, dim3(nblk), dim3(kKB), 0, st, da, nblk, ab, r, pold, pnew, t, sc);
     if (ev) (void)hipEventRecord(ev[3], st);
-    RT_DISPATCH_VW(V, vw, k_rb_black_dir, dim3(nblk), dim3(kKB), 0, st, dh, nblk, ab, (const V *)pnew, (const V *)t, q,
+    RT_DISPATCH_VW(V, vw, k_rb_black_dir, dim3(nblk), dim3(kKB), 0, st, db, nblk, ab, (const V *)pnew, (const V *)t, q,
                    partials, counter, sc);
     if (ev) (void)hipEventRecord(ev[1], st);
-    RT_DISPATCH_VW(V, vw, k_cg_upd, dim3(nblk_upd), dim3(kKB), 0, st, dh, nblk_upd, y, pnew, r, q, partials, counter,
+    RT_DISPATCH_VW(V, vw, k_cg_upd, dim3(nblk_upd), dim3(kKB), 0, st, da, nblk_upd, y, pnew, r, q, partials, counter,
                    sc);
     if (ev) (void)hipEventRecord(ev[2], st);
 }
 
 void launch_rb_iter64(const Dims &dh, int nblk, int nblk_upd, const double *ab, double *y, double *r, double *pold,
                       double *pnew, double *q, double *t, double *partials, unsigned *counter, DevScalars *sc,
-                      hipStream_t st, const hipEvent_t *ev)
+                      hipStream_t st, const hipEvent_t *ev, int odd)
 {
-    rb_iter<double>(dh, nblk, nblk_upd, ab, y, r, pold, pnew, q, t, partials, counter, sc, st, ev);
+    rb_iter<double>(dh, nblk, nblk_upd, ab, y, r, pold, pnew, q, t, partials, counter, sc, st, ev, odd);
 }
 
 void launch_rb_iter32(const Dims &dh, int nblk, int nblk_upd, const float *ab, float *x, float *r, float *pold,
                       float *pnew, float *q, float *t, double *partials, unsigned *counter, DevScalars *sc,
-                      hipStream_t st, const hipEvent_t *ev)
+                      hipStream_t st, const hipEvent_t *ev, int odd)
 {
-    rb_iter<float>(dh, nblk, nblk_upd, ab, x, r, pold, pnew, q, t, partials, counter, sc, st, ev);
+    rb_iter<float>(dh, nblk, nblk_upd, ab, x, r, pold, pnew, q, t, partials, counter, sc, st, ev, odd);
 }
 
 // ------------------------------------------- one-workgroup reduced CG (small grids)

@@ -557,8 +557,8 @@ bool use_block(const rt_solve_opts *o, const Dims &dh)
 }
 
 // Enqueues m Krylov iterations on ctx->stream, each launched by iter(pold, pnew, stream,
-// ev) (ev: the events that time the first iteration's kernels, or NULL), swapping the
-// direction buffers after each.  With graphs the m launches are captured once per
+// ev, k) (ev: the events that time the first iteration's kernels, or NULL; k: the
+// iteration's index in the chunk), swapping the direction buffers after each.  With graphs the m launches are captured once per
 // (kind, pold, m) on a private stream and the instantiated graph is replayed (the
 // kernels read every scalar from device memory, so a replay is the same work as the
 // launches); *sampled tells whether the events were recorded.
@@ -574,7 +574,7 @@ rt_status run_iters(rt_ctx *ctx, const rt_solve_opts *o, int kind, int m, T *&po
     // rare: at most kMaxGraphs graphs are kept, later new shapes launch directly
     if (!ex && (!use_graphs(ctx, o) || ctx->graphs.size() >= kMaxGraphs)) {
         for (int k = 0; k < m; k++) {
-            iter(pold, pnew, ctx->stream, k == 0 ? &ctx->ev[8] : nullptr);
+            iter(pold, pnew, ctx->stream, k == 0 ? &ctx->ev[8] : nullptr, k);
             std::swap(pold, pnew);
         }
         *sampled = true;
@@ -586,7 +586,7 @@ rt_status run_iters(rt_ctx *ctx, const rt_solve_opts *o, int kind, int m, T *&po
         RT_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
         T *a = pold, *b = pnew;
         for (int k = 0; k < m; k++) {
-            iter(a, b, ctx->cap_stream, nullptr);
+            iter(a, b, ctx->cap_stream, nullptr, k);
             std::swap(a, b);
         }
         hipGraph_t g = nullptr;
@@ -639,7 +639,7 @@ rt_status solve_fp64(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, do
         int m = std::min(every, o->max_iter - h->iters);
         int it_before = h->iters;
         bool sampled = false;
-        if (rt_status e = run_iters(ctx, o, 0, m, pold, pnew, [&](double *a, double *b, hipStream_t ss, const hipEvent_t *ev) {
+        if (rt_status e = run_iters(ctx, o, 0, m, pold, pnew, [&](double *a, double *b, hipStream_t ss, const hipEvent_t *ev, int) {
                 launch_cg_iter64(d, ctx->nblk, ctx->nblk_upd, ctx->ahat, ctx->y, ctx->r, a, b, ctx->qv, ctx->partials,
                                  ctx->counter, ctx->sc, ss, ev);
             }, &sampled))
@@ -706,7 +706,7 @@ rt_status solve_mixed(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, d
         int m = std::min(every, o->max_iter - h->iters);
         int it_before = h->iters;
         bool sampled = false;
-        if (rt_status e = run_iters(ctx, o, 1, m, pold, pnew, [&](float *a, float *b, hipStream_t ss, const hipEvent_t *ev) {
+        if (rt_status e = run_iters(ctx, o, 1, m, pold, pnew, [&](float *a, float *b, hipStream_t ss, const hipEvent_t *ev, int) {
                 launch_cg_iter32(d, ctx->nblk, ctx->nblk_upd, ctx->ahat32, ctx->x32, ctx->r32, a, b, ctx->q32,
                                  ctx->partials, ctx->counter, ctx->sc, ss, ev);
             }, &sampled))
@@ -839,9 +839,9 @@ rt_status solve_fp64_rb(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
             int m = std::min(every, o->max_iter - h->iters);
             int it_before = h->iters;
             bool sampled = false;
-            if (rt_status e = run_iters(ctx, o, 2, m, pold, pnew, [&](double *a, double *b, hipStream_t ss, const hipEvent_t *ev) {
+            if (rt_status e = run_iters(ctx, o, 2, m, pold, pnew, [&](double *a, double *b, hipStream_t ss, const hipEvent_t *ev, int k) {
                     launch_rb_iter64(dh, ctx->nblk, ctx->nblk_upd, ctx->rb_a, yb, rb, a, b, qb, tr, ctx->partials,
-                                     ctx->counter, ctx->sc, ss, ev);
+                                     ctx->counter, ctx->sc, ss, ev, k & 1);
                 }, &sampled))
                 return e;
             RT_HIP(ctx, hipGetLastError());
@@ -899,9 +899,9 @@ rt_status solve_mixed_rb(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st
         int m = std::min(every, o->max_iter - h->iters);
         int it_before = h->iters;
         bool sampled = false;
-        if (rt_status e = run_iters(ctx, o, 3, m, pold, pnew, [&](float *a, float *b, hipStream_t ss, const hipEvent_t *ev) {
+        if (rt_status e = run_iters(ctx, o, 3, m, pold, pnew, [&](float *a, float *b, hipStream_t ss, const hipEvent_t *ev, int k) {
                 launch_rb_iter32(dh, ctx->nblk, ctx->nblk_upd, ctx->rb_a32, x32, r32, a, b, q32, t32, ctx->partials,
-                                 ctx->counter, ctx->sc, ss, ev);
+                                 ctx->counter, ctx->sc, ss, ev, k & 1);
             }, &sampled))
             return e;
         RT_HIP(ctx, hipGetLastError());
