@@ -558,10 +558,11 @@ bool use_block(const rt_solve_opts *o, const Dims &dh)
 
 // Enqueues m Krylov iterations on ctx->stream, each launched by iter(pold, pnew, stream,
 // ev, k) (ev: the events that time the first iteration's kernels, or NULL; k: the
-// iteration's index in the chunk), swapping the direction buffers after each.  With graphs the m launches are captured once per
-// (kind, pold, m) on a private stream and the instantiated graph is replayed (the
-// kernels read every scalar from device memory, so a replay is the same work as the
-// launches); *sampled tells whether the events were recorded.
+// iteration's index in the chunk), swapping the direction buffers after each.  With
+// graphs the m launches are captured once per (kind, pold, m) on a private stream and
+// the instantiated graph is replayed (the kernels read every scalar from device memory,
+// so a replay is the same work as the launches); *sampled tells whether the events were
+// recorded.
 template <typename T, typename F>
 rt_status run_iters(rt_ctx *ctx, const rt_solve_opts *o, int kind, int m, T *&pold, T *&pnew, F &&iter,
                     bool *sampled)
