@@ -81,6 +81,9 @@ RUNS = {
     "FD100-24x8x1-gmres": ((24, 8, 1), 100.0, False, True, "gmres"),
     "FD100-64x16x1": ((64, 16, 1), 100.0, False, True, "fp64"),
     "GD100-64x16x1": ((64, 16, 1), 100.0, True, True, "fp64"),
+    # the solves of the benchmark's main-loop runs and of its headline
+    "GD100-64x16x1-fp64rb": ((64, 16, 1), 100.0, True, True, "fp64-rb"),
+    "FD100-20x8x3-mixedrb": ((20, 8, 3), 100.0, False, True, "mixed-rb"),
 }
 
 
@@ -100,6 +103,10 @@ def test_relax_against_oracle(run):
         opts = rt.solve_opts(rt.MODE_NONE)
     elif solver == "gmres":
         opts = rt.solve_opts(rt.MODE_GMRES, tol=1e-10, restart=30)
+    elif solver == "fp64-rb":  # one workgroup on this grid
+        opts = rt.solve_opts(rt.MODE_FP64, tol=1e-10, reduce=1)
+    elif solver == "mixed-rb":
+        opts = rt.solve_opts(rt.MODE_MIXED, tol=1e-10, reduce=1)
     else:
         opts = rt.solve_opts(rt.MODE_FP64, tol=1e-10)
     T = _d(T0)
