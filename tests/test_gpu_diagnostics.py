@@ -25,7 +25,7 @@ def _h(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("shape", [(67, 13, 5), (24, 8, 3), (128, 4, 2), (2, 3, 2)])
+@pytest.mark.parametrize("shape", [(67, 13, 5), (24, 8, 3), (128, 4, 2), (2, 3, 2), (130, 3, 2), (1280, 2, 1)])
 def test_rosseland_depth_parity(shape):
     from paper_1001_3301_amd import rt
     wl = sy.make_workload("t", *shape, 16, 100.0, clump_seed=6)
