@@ -1018,8 +1018,8 @@ void launch_rb_iter32(const Dims &dh, int nblk, int nblk_upd, const float *ab, f
 // 2-D grids of this size).  Here one workgroup of kSB threads runs the float64 CG
 // iterations on S by itself: the direction p (black) and the product t = B p (red) --
 // the two vectors whose neighbours are read -- live in LDS, the thread's own entries of
-// r, y and q and each of its cells' couplings (six coefficients and neighbour indices
-// per colour, read once per launch) in registers, and each iteration's two dot products
+// r, y, q, its own p and t and each of its cells' couplings (six coefficients and
+// neighbour indices per colour, read once per launch) in registers, and each iteration's two dot products
 // are workgroup sums in a fixed order.  Thread tid owns the half indices tid + c kSB,
 // c < CPT <= 2 (at most 2048 black cells: beyond that the couplings no longer fit the
 // registers, and from L2 a single CU streams them no faster than the multi-block
@@ -1044,7 +1044,8 @@ __device__ __forceinline__ double dpp_d(double v)
 // halves of 8, mirror the row; each step adds a lane and its partner, a + b = b + a,
 // so every lane of a row ends with the same row total), then the four row totals read
 // into scalars and added in a fixed order.  Across the workgroup every thread adds the
-// wave totals in index order, so the convergence test is uniform.
+// wave totals in index order, so the convergence test is uniform.  (A pairwise tree
+// over the 16 totals was slower: its 16 live doubles pushed the kernel's registers.)
 __device__ __forceinline__ double wg_sum(double v, double *sh)
 {
     v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
@@ -1062,10 +1063,14 @@ __device__ __forceinline__ double wg_sum(double v, double *sh)
 
 // The couplings of one cell to its six neighbours of the other colour, in the terms and
 // order of rb_couple with VW = 1: right, left, +theta, -theta, +phi, -phi (an absent
-// neighbour has index g and coefficient 0).
+// neighbour has index g and coefficient 0).  One of the two radial neighbours is the
+// other colour's cell at the same half index g, whose value the thread holds in a
+// register (it owns both cells at g); e[0] is the other one's index and `right` tells
+// which side it is on.
 struct Cpl {
     double w[6];
     int e[6];
+    bool right;
 };
 
 __device__ __forceinline__ Cpl couplings(const Dims &dh, const Row &rw, int h0, int par, const double *__restrict__ own,
@@ -1079,9 +1084,10 @@ __device__ __forceinline__ Cpl couplings(const Dims &dh, const Row &rw, int h0, 
     const long gjm = rw.jm ? g - H : g;
     Cpl c;
     c.w[0] = own[g];
-    c.e[0] = (int)(par ? ge : g);
     c.w[1] = par ? oth[g] : (hasl ? oth[ge] : 0.0);
-    c.e[1] = (int)(par ? g : ge);
+    c.e[0] = (int)ge;  // the radial neighbour that is not at g (at the row ends ge = g)
+    c.right = par != 0;
+    c.e[1] = (int)g;   // unused
     c.w[2] = own[nh + g];
     c.e[2] = (int)(rw.jp ? g + H : g);
     c.w[3] = oth[nh + gjm] * (double)rw.jm;
@@ -1093,10 +1099,12 @@ __device__ __forceinline__ Cpl couplings(const Dims &dh, const Row &rw, int h0, 
     return c;
 }
 
-__device__ __forceinline__ double couple(const Cpl &c, const double *x)
+// xg: the value at index g (from the register that holds it)
+__device__ __forceinline__ double couple(const Cpl &c, const double *x, double xg)
 {
-    double v = c.w[0] * x[c.e[0]];
-    v += c.w[1] * x[c.e[1]];
+    const double xo = x[c.e[0]];
+    double v = c.w[0] * (c.right ? xo : xg);
+    v += c.w[1] * (c.right ? xg : xo);
     v += c.w[2] * x[c.e[2]];
     v += c.w[3] * x[c.e[3]];
     v += c.w[4] * x[c.e[4]];
@@ -1121,13 +1129,13 @@ __global__ __launch_bounds__(kSB) void k_rb_cg_block(Dims dh, const double *__re
     Cpl cr[CPT], cb[CPT];  // couplings of the red and of the black cell at half index g
     int gi[CPT];
     bool own[CPT];
-    double rv[CPT], yv[CPT];
+    double rv[CPT], yv[CPT], pr[CPT], tr[CPT];  // r, y, p (black) and t (red) at g
 #pragma unroll
     for (int c = 0; c < CPT; c++) {
         const long g = threadIdx.x + (long)c * kSB;
         own[c] = g < nh;
         gi[c] = (int)g;
-        rv[c] = yv[c] = 0.0;
+        rv[c] = yv[c] = pr[c] = tr[c] = 0.0;
         if (!own[c]) {
             cr[c] = cb[c] = Cpl{};
             continue;
@@ -1147,31 +1155,36 @@ __global__ __launch_bounds__(kSB) void k_rb_cg_block(Dims dh, const double *__re
         cb[c] = couplings(dh, rw, h0, rw.par, blk, red);
         rv[c] = r[g];
         yv[c] = y[g];
-        ps[g] = p[g];
+        pr[c] = p[g];
     }
     double rr = sc->rr, beta = sc->beta, pq = sc->pq, alpha = sc->alpha;
     const double th = sc->thresh2;
     int it = 0, done = 0;
     while (it < m && !done) {
-        // p = r + beta p (each thread its own entries)
+        // p = r + beta p (each thread its own entries, kept in registers too)
 #pragma unroll
         for (int c = 0; c < CPT; c++)
-            if (own[c]) ps[gi[c]] = fma(beta, ps[gi[c]], rv[c]);
+            if (own[c]) {
+                pr[c] = fma(beta, pr[c], rv[c]);
+                ps[gi[c]] = pr[c];
+            }
         __syncthreads();
         // red: t = B p
 #pragma unroll
         for (int c = 0; c < CPT; c++)
-            if (own[c]) ts[gi[c]] = couple(cr[c], ps);
+            if (own[c]) {
+                tr[c] = couple(cr[c], ps, pr[c]);
+                ts[gi[c]] = tr[c];
+            }
         __syncthreads();
         // black: q = p - B^T t, p.q
-        double qv[CPT], pv[CPT], part = 0.0;
+        double qv[CPT], part = 0.0;
 #pragma unroll
         for (int c = 0; c < CPT; c++) {
-            qv[c] = pv[c] = 0.0;
+            qv[c] = 0.0;
             if (own[c]) {
-                pv[c] = ps[gi[c]];
-                qv[c] = pv[c] - couple(cb[c], ts);
-                part += pv[c] * qv[c];
+                qv[c] = pr[c] - couple(cb[c], ts, tr[c]);
+                part += pr[c] * qv[c];
             }
         }
         pq = wg_sum(part, sha);
@@ -1180,7 +1193,7 @@ __global__ __launch_bounds__(kSB) void k_rb_cg_block(Dims dh, const double *__re
 #pragma unroll
         for (int c = 0; c < CPT; c++)
             if (own[c]) {
-                yv[c] = fma(alpha, pv[c], yv[c]);
+                yv[c] = fma(alpha, pr[c], yv[c]);
                 rv[c] = fma(-alpha, qv[c], rv[c]);
                 part += rv[c] * rv[c];
             }
@@ -1195,7 +1208,7 @@ __global__ __launch_bounds__(kSB) void k_rb_cg_block(Dims dh, const double *__re
         if (own[c]) {
             r[gi[c]] = rv[c];
             y[gi[c]] = yv[c];
-            p[gi[c]] = ps[gi[c]];
+            p[gi[c]] = pr[c];
         }
     if (threadIdx.x == 0) {
         sc->rr = rr;
