@@ -1017,10 +1017,10 @@ void launch_rb_iter32(const Dims &dh, int nblk, int nblk_upd, const float *ab, f
 // microseconds and the launches, not the bytes, set the time (the paper's own runs are
 // 2-D grids of this size).  Here one workgroup of kSB threads runs the float64 CG
 // iterations on S by itself: the direction p (black) and the product t = B p (red) --
-// the two vectors whose neighbours are read -- live in LDS, the thread's own entries of
-// r, y, q, its own p and t and each of its cells' couplings (six coefficients and
-// neighbour indices per colour, read once per launch) in registers, and each iteration's two dot products
-// are workgroup sums in a fixed order.  Thread tid owns the half indices tid + c kSB,
+// the two vectors whose neighbours are read -- live in LDS; the thread's own entries of
+// r, y, q, p and t and each of its cells' couplings (six coefficients and neighbour
+// indices per colour, read once per launch) live in registers; and each iteration's two
+// dot products are workgroup sums in a fixed order.  Thread tid owns the half indices tid + c kSB,
 // c < CPT <= 2 (at most 2048 black cells: beyond that the couplings no longer fit the
 // registers, and from L2 a single CU streams them no faster than the multi-block
 // kernels run).  Every entry is summed as in rb_couple (same terms, same order); only
