@@ -6,7 +6,8 @@ columns near the longest the library accepts.
 Every kernel of the step runs at these sizes with most of its threads idle or clamped:
 the ray trace (one partial segment per column), the assembly's boundary faces, the
 Krylov kernels with every neighbour a boundary (full system from graphs, the reduced
-system in one workgroup and from graphs in float32), Newton and the force.
+system in one workgroup and from graphs in float32, GMRES(30) whose Krylov space fills
+up within one cycle), Newton and the force.
 """
 import numpy as np
 import pytest
@@ -58,6 +59,7 @@ MODES = {  # name: (mode, reduce, solve tol, T bar)
     "fp64": (0, 0, 1e-12, 1e-11),
     "fp64-rb": (0, 1, 1e-12, 1e-11),
     "mixed-rb": (1, 1, 1e-12, 1e-9),
+    "gmres": (3, 0, 1e-12, 1e-11),  # GMRES(30): on the smallest grids the Krylov space fills up within a cycle
 }
 
 
