@@ -293,9 +293,13 @@ def oracle_baseline(wl, gpu_fp64_iters, slab=16, cg_iters=1000):
     t = time.perf_counter()
     q, S, _ = P.raytrace(rho, T, want_faces=False)
     t_rt = time.perf_counter() - t
+    t = time.perf_counter()
     T = P.newton(np.full(P.n, sy.A_RAD * wl.T_bc ** 4), S, T)
+    t_nw = time.perf_counter() - t
     En = P.energy(T, S)
+    t = time.perf_counter()
     sysd = P.assemble(rho, T, En, q)
+    t_as = time.perf_counter() - t
     t = time.perf_counter()
     _, _, it, _ = P.cg(sysd["ahat"], sysd["bhat"], En / sysd["s"], 1e-30, cg_iters)
     t_cg = time.perf_counter() - t
@@ -303,6 +307,8 @@ def oracle_baseline(wl, gpu_fp64_iters, slab=16, cg_iters=1000):
     per_iter_full = t_cg / max(it, 1) * scale
     return dict(solve_s_per_step=per_iter_full * gpu_fp64_iters,
                 raytrace_gcell_nu=P.n * wl.opacity.kappa.shape[1] / t_rt / 1e9,
+                phases_s_full_grid={"raytrace": t_rt * scale, "assemble": t_as * scale, "newton": t_nw * scale,
+                                    "cg_iteration": per_iter_full},
                 sample=f"oracle on a {g.shape[0]}x{g.shape[1]}x{slab} phi-slab of the workload "
                        f"({P.n} cells, 1/{scale:.0f} of the grid): one ray trace ({t_rt:.1f} s) and "
                        f"{it} float64 CG iterations ({t_cg:.1f} s); solve s/step = time per iteration "
@@ -501,7 +507,8 @@ def main():
         log(f"cpu baseline took {time.perf_counter() - t:.1f} s")
         out["cpu_baseline"] = {"value": cb["solve_s_per_step"], "unit": "s/step", "cores": 1,
                                "kind": "oracle", "sample": cb["sample"],
-                               "raytrace_gcell_nu_per_s": cb["raytrace_gcell_nu"]}
+                               "raytrace_gcell_nu_per_s": cb["raytrace_gcell_nu"],
+                               "phases_s_full_grid": cb["phases_s_full_grid"]}
     print(json.dumps(out), flush=True)
 
 
