@@ -47,10 +47,10 @@ KERNEL_NAMES = {"fp64": "k_cg_dir<double>", "mixed": "k_cg_dir<float>", "fp64-rb
 # Keyed by kernel; profiles/rb_solver_kernels_clumpy-512x256x512-nu64.md for the reduced passes.
 MEASURED_TRAFFIC = {("k_cg_dir<float>", "clumpy-512x256x512-nu64"): 1.924e9,
                     ("k_cg_dir<double>", "clumpy-512x256x512-nu64"): 3.855e9,
-                    ("k_rb_red_dir<float>", "clumpy-512x256x512-nu64"): 1.356e9,
-                    ("k_rb_black_dir<float>", "clumpy-512x256x512-nu64"): 1.235e9,
-                    ("k_rb_red_dir<double>", "clumpy-512x256x512-nu64"): 2.737e9,
-                    ("k_rb_black_dir<double>", "clumpy-512x256x512-nu64"): 2.572e9}
+                    ("k_rb_red_dir<float>", "clumpy-512x256x512-nu64"): 1.355e9,
+                    ("k_rb_black_dir<float>", "clumpy-512x256x512-nu64"): 1.232e9,
+                    ("k_rb_red_dir<double>", "clumpy-512x256x512-nu64"): 2.734e9,
+                    ("k_rb_black_dir<double>", "clumpy-512x256x512-nu64"): 2.582e9}
 
 
 # The ray trace is bound by float64 instruction issue: a wavefront handles one cell per

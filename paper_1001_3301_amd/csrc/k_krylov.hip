@@ -103,6 +103,36 @@ __device__ __forceinline__ void vstore(V *__restrict__ p, const V (&o)[VW])
     }
 }
 
+// Non-temporal forms (the `nt` cache policy): the lines they touch are not kept for
+// reuse, so a pure streaming pass does not push out of the Infinity Cache what the pass
+// after it will read.
+template <typename V, int VW>
+__device__ __forceinline__ void vload_nt(const V *__restrict__ p, V (&o)[VW])
+{
+    if constexpr (VW == 1) {
+        o[0] = __builtin_nontemporal_load(p);
+    } else {
+        typedef V T __attribute__((ext_vector_type(VW)));
+        const T b = __builtin_nontemporal_load(reinterpret_cast<const T *>(p));
+#pragma unroll
+        for (int m = 0; m < VW; m++) o[m] = b[m];
+    }
+}
+
+template <typename V, int VW>
+__device__ __forceinline__ void vstore_nt(V *__restrict__ p, const V (&o)[VW])
+{
+    if constexpr (VW == 1) {
+        __builtin_nontemporal_store(o[0], p);
+    } else {
+        typedef V T __attribute__((ext_vector_type(VW)));
+        T b;
+#pragma unroll
+        for (int m = 0; m < VW; m++) b[m] = o[m];
+        __builtin_nontemporal_store(b, reinterpret_cast<T *>(p));
+    }
+}
+
 // A row of the grid as seen from a block: its first cell and its neighbour rows.
 struct Row {
     long base;      // index of cell (0, j, k)
@@ -321,11 +351,12 @@ __global__ __launch_bounds__(kKB) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
 }
 
 // Update + dot: y += alpha p, r -= alpha q, rr' = r.r, beta = rr'/rr, convergence flag.
-template <typename V, int VW>
-__global__ __launch_bounds__(kKB) void k_cg_upd(Dims d, int nblk, V *__restrict__ y,
-                                                const V *__restrict__ p, V *__restrict__ r,
-                                                const V *__restrict__ q, double *partials,
-                                                unsigned *counter, DevScalars *sc)
+// NT: all six streams with the non-temporal policy (the update of the reduced system,
+// whose arrays the next pass does not read first).
+template <typename V, int VW, bool NT>
+__device__ __forceinline__ void cg_upd_body(Dims d, int nblk, V *__restrict__ y, const V *__restrict__ p,
+                                            V *__restrict__ r, const V *__restrict__ q, double *partials,
+                                            unsigned *counter, DevScalars *sc)
 {
     if (sc->done) return;
     __shared__ double sh[kKB / 64];
@@ -335,18 +366,30 @@ __global__ __launch_bounds__(kKB) void k_cg_upd(Dims d, int nblk, V *__restrict_
     for_segments<VW>(d, nblk, [&](const Row &rw, int i) {
         const long c = rw.base + i;
         V yv[VW], pv[VW], rv[VW], qv[VW];
-        vload<V, VW>(y + c, yv);
-        vload<V, VW>(p + c, pv);
-        vload<V, VW>(r + c, rv);
-        vload<V, VW>(q + c, qv);
+        if constexpr (NT) {
+            vload_nt<V, VW>(y + c, yv);
+            vload_nt<V, VW>(p + c, pv);
+            vload_nt<V, VW>(r + c, rv);
+            vload_nt<V, VW>(q + c, qv);
+        } else {
+            vload<V, VW>(y + c, yv);
+            vload<V, VW>(p + c, pv);
+            vload<V, VW>(r + c, rv);
+            vload<V, VW>(q + c, qv);
+        }
 #pragma unroll
         for (int m = 0; m < VW; m++) {
             yv[m] = fma(alpha, pv[m], yv[m]);
             rv[m] = fma(-alpha, qv[m], rv[m]);
             acc += (double)rv[m] * (double)rv[m];
         }
-        vstore<V, VW>(y + c, yv);
-        vstore<V, VW>(r + c, rv);
+        if constexpr (NT) {
+            vstore_nt<V, VW>(y + c, yv);
+            vstore_nt<V, VW>(r + c, rv);
+        } else {
+            vstore<V, VW>(y + c, yv);
+            vstore<V, VW>(r + c, rv);
+        }
     });
     double bs = block_sum(acc, sh), tot;
     if (finish_reduce(bs, L, nblk, partials, counter, sh, &tot) && threadIdx.x == 0) {
@@ -356,6 +399,22 @@ __global__ __launch_bounds__(kKB) void k_cg_upd(Dims d, int nblk, V *__restrict_
         sc->iters += 1;
         if (tot <= sc->thresh2 || !(tot == tot)) sc->done = 1;
     }
+}
+
+template <typename V, int VW>
+__global__ __launch_bounds__(kKB) void k_cg_upd(Dims d, int nblk, V *__restrict__ y, const V *__restrict__ p,
+                                                V *__restrict__ r, const V *__restrict__ q, double *partials,
+                                                unsigned *counter, DevScalars *sc)
+{
+    cg_upd_body<V, VW, false>(d, nblk, y, p, r, q, partials, counter, sc);
+}
+
+template <typename V, int VW>
+__global__ __launch_bounds__(kKB) void k_cg_upd_nt(Dims d, int nblk, V *__restrict__ y, const V *__restrict__ p,
+                                                   V *__restrict__ r, const V *__restrict__ q, double *partials,
+                                                   unsigned *counter, DevScalars *sc)
+{
+    cg_upd_body<V, VW, true>(d, nblk, y, p, r, q, partials, counter, sc);
 }
 
 // Mixed mode, reliable update: r32 = float(r) from the float64 residual r = b - A y
@@ -971,44 +1030,47 @@ void launch_rb_black_apply(const Dims &dh, int nblk, const double *ab, const dou
                    u, x, sgn, out, partials, counter, sc, restart);
 }
 
-// The three passes of an iteration sweep the rows in alternating directions (red
-// forward on even iterations, black backward, update forward, the next red backward, ...)
-// so that each pass starts on what the previous one read and wrote last, which the
-// 256 MB Infinity Cache still holds: at 512x256x512 the black pass then takes 229 us
-// instead of 239 us (it rereads the red pass's six coefficient arrays and p and t), the
-// reduced mixed solve 0.899 s instead of 0.913 s.  The two passes of a full-system
-// iteration did not gain from it.
+// Sweep directions and the Infinity Cache (256 MB, which holds the last ~20 % of what a
+// pass at 512x256x512 touched): the red pass sweeps forward, the black pass backward, so
+// it starts on the rows whose p, t and six coefficient arrays the red pass touched last;
+// the update sweeps forward, starting on the black pass's last p and q, with
+// non-temporal streams, so it leaves the black pass's last rows -- the same coefficient
+// arrays and p -- in the cache for the next red pass, which starts there.  At
+// 512x256x512 (float, rocprofv3 medians): red 263 -> 245 us, black 239 -> 227 us,
+// update 144 -> 138 us against one direction for all three passes and plain streams;
+// the L2-miss traffic is the same.  (Non-temporal loads of t in the black pass are
+// slower: t is read again by the neighbouring rows, from L2.)
 template <typename V>
 static void rb_iter(const Dims &dh, int nblk, int nblk_upd, const V *ab, V *y, V *r, V *pold, V *pnew, V *q, V *t,
-                    double *partials, unsigned *counter, DevScalars *sc, hipStream_t st, const hipEvent_t *ev, int odd)
+                    double *partials, unsigned *counter, DevScalars *sc, hipStream_t st, const hipEvent_t *ev)
 {
     const int vw = pick_vw<V>(dh);
     Dims da = dh, db = dh;
-    da.rev = odd;
-    db.rev = !odd;
+    da.rev = 0;
+    db.rev = 1;
     if (ev) (void)hipEventRecord(ev[0], st);
     RT_DISPATCH_VW(V, vw, k_rb_red_dir, dim3(nblk), dim3(kKB), 0, st, da, nblk, ab, r, pold, pnew, t, sc);
     if (ev) (void)hipEventRecord(ev[3], st);
     RT_DISPATCH_VW(V, vw, k_rb_black_dir, dim3(nblk), dim3(kKB), 0, st, db, nblk, ab, (const V *)pnew, (const V *)t, q,
                    partials, counter, sc);
     if (ev) (void)hipEventRecord(ev[1], st);
-    RT_DISPATCH_VW(V, vw, k_cg_upd, dim3(nblk_upd), dim3(kKB), 0, st, da, nblk_upd, y, pnew, r, q, partials, counter,
-                   sc);
+    RT_DISPATCH_VW(V, vw, k_cg_upd_nt, dim3(nblk_upd), dim3(kKB), 0, st, da, nblk_upd, y, pnew, r, q, partials,
+                   counter, sc);
     if (ev) (void)hipEventRecord(ev[2], st);
 }
 
 void launch_rb_iter64(const Dims &dh, int nblk, int nblk_upd, const double *ab, double *y, double *r, double *pold,
                       double *pnew, double *q, double *t, double *partials, unsigned *counter, DevScalars *sc,
-                      hipStream_t st, const hipEvent_t *ev, int odd)
+                      hipStream_t st, const hipEvent_t *ev)
 {
-    rb_iter<double>(dh, nblk, nblk_upd, ab, y, r, pold, pnew, q, t, partials, counter, sc, st, ev, odd);
+    rb_iter<double>(dh, nblk, nblk_upd, ab, y, r, pold, pnew, q, t, partials, counter, sc, st, ev);
 }
 
 void launch_rb_iter32(const Dims &dh, int nblk, int nblk_upd, const float *ab, float *x, float *r, float *pold,
                       float *pnew, float *q, float *t, double *partials, unsigned *counter, DevScalars *sc,
-                      hipStream_t st, const hipEvent_t *ev, int odd)
+                      hipStream_t st, const hipEvent_t *ev)
 {
-    rb_iter<float>(dh, nblk, nblk_upd, ab, x, r, pold, pnew, q, t, partials, counter, sc, st, ev, odd);
+    rb_iter<float>(dh, nblk, nblk_upd, ab, x, r, pold, pnew, q, t, partials, counter, sc, st, ev);
 }
 
 // ------------------------------------------- one-workgroup reduced CG (small grids)

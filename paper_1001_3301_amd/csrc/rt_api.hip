@@ -840,9 +840,9 @@ rt_status solve_fp64_rb(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
             int m = std::min(every, o->max_iter - h->iters);
             int it_before = h->iters;
             bool sampled = false;
-            if (rt_status e = run_iters(ctx, o, 2, m, pold, pnew, [&](double *a, double *b, hipStream_t ss, const hipEvent_t *ev, int k) {
+            if (rt_status e = run_iters(ctx, o, 2, m, pold, pnew, [&](double *a, double *b, hipStream_t ss, const hipEvent_t *ev, int) {
                     launch_rb_iter64(dh, ctx->nblk, ctx->nblk_upd, ctx->rb_a, yb, rb, a, b, qb, tr, ctx->partials,
-                                     ctx->counter, ctx->sc, ss, ev, k & 1);
+                                     ctx->counter, ctx->sc, ss, ev);
                 }, &sampled))
                 return e;
             RT_HIP(ctx, hipGetLastError());
@@ -900,9 +900,9 @@ rt_status solve_mixed_rb(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st
         int m = std::min(every, o->max_iter - h->iters);
         int it_before = h->iters;
         bool sampled = false;
-        if (rt_status e = run_iters(ctx, o, 3, m, pold, pnew, [&](float *a, float *b, hipStream_t ss, const hipEvent_t *ev, int k) {
+        if (rt_status e = run_iters(ctx, o, 3, m, pold, pnew, [&](float *a, float *b, hipStream_t ss, const hipEvent_t *ev, int) {
                 launch_rb_iter32(dh, ctx->nblk, ctx->nblk_upd, ctx->rb_a32, x32, r32, a, b, q32, t32, ctx->partials,
-                                 ctx->counter, ctx->sc, ss, ev, k & 1);
+                                 ctx->counter, ctx->sc, ss, ev);
             }, &sampled))
             return e;
         RT_HIP(ctx, hipGetLastError());

@@ -223,13 +223,12 @@ void launch_rb_black_apply(const Dims &dh, int nblk, const double *ab, const dou
 int rb_block_cpt(const Dims &dh);
 bool launch_rb_cg_block(const Dims &dh, const double *ab, double *y, double *r, double *p, int m, DevScalars *sc,
                         hipStream_t st);
-// odd: the parity of the iteration (the passes alternate their sweep direction)
 void launch_rb_iter64(const Dims &dh, int nblk, int nblk_upd, const double *ab, double *y, double *r, double *pold,
                       double *pnew, double *q, double *t, double *partials, unsigned *counter, DevScalars *sc,
-                      hipStream_t st, const hipEvent_t *ev, int odd);
+                      hipStream_t st, const hipEvent_t *ev);
 void launch_rb_iter32(const Dims &dh, int nblk, int nblk_upd, const float *ab, float *x, float *r, float *pold,
                       float *pnew, float *q, float *t, double *partials, unsigned *counter, DevScalars *sc,
-                      hipStream_t st, const hipEvent_t *ev, int odd);
+                      hipStream_t st, const hipEvent_t *ev);
 // max_c |T_c - Told_c| / Told_c into *out (device); partials needs nblk entries.
 void launch_max_change(long n, int nblk, const double *T, const double *Told, double *partials,
                        unsigned *counter, double *out, hipStream_t st);
