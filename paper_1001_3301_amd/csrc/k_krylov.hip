@@ -678,32 +678,40 @@ void launch_resid(const Dims &d, int nblk, const double *a, const double *b, con
                    partials, counter, sc, restart);
 }
 
+// The direction pass alternates its sweep direction between iterations and the update
+// sweeps against it with non-temporal streams: each direction pass then starts on the
+// rows whose coefficients and vectors the previous one touched last, which the update
+// has not pushed out of the Infinity Cache, and the update starts on the direction
+// pass's last p and q.
 template <typename V>
 static void cg_iter(const Dims &d, int nblk, int nblk_upd, const V *a, V *y, V *r, V *pold, V *pnew, V *q,
-                    double *partials, unsigned *counter, DevScalars *sc, hipStream_t st, const hipEvent_t *ev)
+                    double *partials, unsigned *counter, DevScalars *sc, hipStream_t st, const hipEvent_t *ev, int odd)
 {
     const int vw = pick_vw<V>(d);
+    Dims dd = d, du = d;
+    dd.rev = odd;
+    du.rev = !odd;
     if (ev) (void)hipEventRecord(ev[0], st);
-    RT_DISPATCH_VW(V, vw, k_cg_dir, dim3(nblk), dim3(kKB), 0, st, d, nblk, a, r, pold, pnew, q, partials, counter,
+    RT_DISPATCH_VW(V, vw, k_cg_dir, dim3(nblk), dim3(kKB), 0, st, dd, nblk, a, r, pold, pnew, q, partials, counter,
                    sc);
     if (ev) (void)hipEventRecord(ev[1], st);
-    RT_DISPATCH_VW(V, vw, k_cg_upd, dim3(nblk_upd), dim3(kKB), 0, st, d, nblk_upd, y, pnew, r, q, partials, counter,
-                   sc);
+    RT_DISPATCH_VW(V, vw, k_cg_upd_nt, dim3(nblk_upd), dim3(kKB), 0, st, du, nblk_upd, y, pnew, r, q, partials,
+                   counter, sc);
     if (ev) (void)hipEventRecord(ev[2], st);
 }
 
 void launch_cg_iter64(const Dims &d, int nblk, int nblk_upd, const double *a, double *y, double *r, double *pold,
                       double *pnew, double *q, double *partials, unsigned *counter, DevScalars *sc,
-                      hipStream_t st, const hipEvent_t *ev)
+                      hipStream_t st, const hipEvent_t *ev, int odd)
 {
-    cg_iter<double>(d, nblk, nblk_upd, a, y, r, pold, pnew, q, partials, counter, sc, st, ev);
+    cg_iter<double>(d, nblk, nblk_upd, a, y, r, pold, pnew, q, partials, counter, sc, st, ev, odd);
 }
 
 void launch_cg_iter32(const Dims &d, int nblk, int nblk_upd, const float *a, float *x, float *r, float *pold,
                       float *pnew, float *q, double *partials, unsigned *counter, DevScalars *sc,
-                      hipStream_t st, const hipEvent_t *ev)
+                      hipStream_t st, const hipEvent_t *ev, int odd)
 {
-    cg_iter<float>(d, nblk, nblk_upd, a, x, r, pold, pnew, q, partials, counter, sc, st, ev);
+    cg_iter<float>(d, nblk, nblk_upd, a, x, r, pold, pnew, q, partials, counter, sc, st, ev, odd);
 }
 
 void launch_reliable(const Dims &d, int nblk, const double *r, float *r32, float *x32, double *partials,

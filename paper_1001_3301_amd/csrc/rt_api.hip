@@ -640,9 +640,9 @@ rt_status solve_fp64(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, do
         int m = std::min(every, o->max_iter - h->iters);
         int it_before = h->iters;
         bool sampled = false;
-        if (rt_status e = run_iters(ctx, o, 0, m, pold, pnew, [&](double *a, double *b, hipStream_t ss, const hipEvent_t *ev, int) {
+        if (rt_status e = run_iters(ctx, o, 0, m, pold, pnew, [&](double *a, double *b, hipStream_t ss, const hipEvent_t *ev, int k) {
                 launch_cg_iter64(d, ctx->nblk, ctx->nblk_upd, ctx->ahat, ctx->y, ctx->r, a, b, ctx->qv, ctx->partials,
-                                 ctx->counter, ctx->sc, ss, ev);
+                                 ctx->counter, ctx->sc, ss, ev, k & 1);
             }, &sampled))
             return e;
         RT_HIP(ctx, hipGetLastError());
@@ -707,9 +707,9 @@ rt_status solve_mixed(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, d
         int m = std::min(every, o->max_iter - h->iters);
         int it_before = h->iters;
         bool sampled = false;
-        if (rt_status e = run_iters(ctx, o, 1, m, pold, pnew, [&](float *a, float *b, hipStream_t ss, const hipEvent_t *ev, int) {
+        if (rt_status e = run_iters(ctx, o, 1, m, pold, pnew, [&](float *a, float *b, hipStream_t ss, const hipEvent_t *ev, int k) {
                 launch_cg_iter32(d, ctx->nblk, ctx->nblk_upd, ctx->ahat32, ctx->x32, ctx->r32, a, b, ctx->q32,
-                                 ctx->partials, ctx->counter, ctx->sc, ss, ev);
+                                 ctx->partials, ctx->counter, ctx->sc, ss, ev, k & 1);
             }, &sampled))
             return e;
         RT_HIP(ctx, hipGetLastError());

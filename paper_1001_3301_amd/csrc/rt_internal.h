@@ -242,12 +242,13 @@ void launch_resid(const Dims &d, int nblk, const double *a, const double *b, con
                   double *r, double *partials, unsigned *counter, DevScalars *sc, int restart, hipStream_t st);
 // One CG iteration (direction+operator kernel, then update kernel).  When ev is given,
 // ev[0], ev[1], ev[2] are recorded before, between and after the two kernels.
+// odd: the parity of the iteration (the direction pass alternates its sweep direction)
 void launch_cg_iter64(const Dims &d, int nblk, int nblk_upd, const double *a, double *y, double *r, double *pold,
                       double *pnew, double *q, double *partials, unsigned *counter, DevScalars *sc,
-                      hipStream_t st, const hipEvent_t *ev = nullptr);
+                      hipStream_t st, const hipEvent_t *ev, int odd);
 void launch_cg_iter32(const Dims &d, int nblk, int nblk_upd, const float *a, float *x, float *r, float *pold,
                       float *pnew, float *q, double *partials, unsigned *counter, DevScalars *sc,
-                      hipStream_t st, const hipEvent_t *ev = nullptr);
+                      hipStream_t st, const hipEvent_t *ev, int odd);
 void launch_reliable(const Dims &d, int nblk, const double *r, float *r32, float *x32, double *partials,
                      unsigned *counter, DevScalars *sc, int restart, hipStream_t st);
 void launch_fold(long n, const float *x32, double *y, hipStream_t st);
