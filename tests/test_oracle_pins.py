@@ -472,6 +472,100 @@ def test_force_components():
     assert np.max(np.abs(f[1, 1:-1] / ref - 1)) < 1e-13
 
 
+def _angular_force(nt, nph, chi_of, E_of, r_in=sy.AU, r_out=1.001 * sy.AU):
+    """Thermal force of the oracle on a thin shell (two radial cells) with kappa_R rho =
+    chi_of(theta_c, phi_c) and E^n = E = E_of(theta_c, phi_c), in the diffusion limit
+    (chi r >> 1, so R ~ 1e-8 and lambda = 1/3 to rounding).  Returns the (theta, phi)
+    force components and the cell-centre coordinates, shaped [k, j, i]."""
+    g = sy.make_grid(2, nt, nph, r_min=r_in, r_max=r_out)
+    op = sy.make_opacity(sy.frequencies(4))
+    P = _problem(g, op, dt=1e300)
+    kR = P.kappa_R(sy.T_BC)
+    tc = 0.5 * (g.th_face[1:] + g.th_face[:-1])
+    pc = 0.5 * (g.ph_face[1:] + g.ph_face[:-1])
+    rc = 0.5 * (g.r_face[1:] + g.r_face[:-1])
+    PP, TT, RR = np.meshgrid(pc, tc, rc, indexing="ij")
+    chi = chi_of(TT, PP)
+    E = E_of(TT, PP)
+    rho = (chi / kR).ravel()
+    T = np.full(P.n, sy.T_BC)
+    out = P.assemble(rho, T, E.ravel(), np.zeros(P.n))
+    f = P.force(rho, T, out["w"], E.ravel(), np.zeros(P.n)).reshape(4, nph, nt, 2)
+    return f[2], f[3], TT, PP, RR
+
+
+def _order(errs):
+    return [math.log2(errs[m] / errs[m + 1]) for m in range(len(errs) - 1)]
+
+
+def test_force_theta_component_converges_to_the_fld_flux():
+    """Eqs. 10, 11, 27 in the diffusion limit (lambda = 1/3): kappa_R rho F_theta / c
+    = -(1/3) (1/r) dE/dtheta at every cell, whatever chi(theta) is, because F = -c/(3 chi)
+    grad E.  With E = E0 (1 + 0.4 cos^2 theta) the limit is E0 0.4 sin(2 theta) / (3 r).
+    The face flux of the oracle is the weight of Eq. 11 over the polar face area times
+    the difference across the face, averaged over the two faces of the cell; a wrong
+    face area or the weight of the wrong face makes the error first order or O(1) in
+    the polar spacing (the clumpy chi(theta) makes the two faces' weights differ), so
+    the test asks for second order on cells with both faces inside the grid."""
+    E0 = A * sy.T_BC ** 4
+    chi_of = lambda t, p: 1e-6 * (1.0 + 0.6 * np.sin(3.0 * t) ** 2)
+    E_of = lambda t, p: E0 * (1.0 + 0.4 * np.cos(t) ** 2)
+    errs = []
+    for nt in (32, 64, 128, 256):
+        ft, fp, TT, PP, RR = _angular_force(nt, 1, chi_of, E_of)
+        exact = E0 * 0.4 * np.sin(2.0 * TT) / (3.0 * RR)
+        inner = slice(1, nt - 1)
+        errs.append(np.max(np.abs(ft[:, inner] - exact[:, inner])) / np.max(np.abs(exact)))
+        assert np.all(fp == 0.0)
+        # equatorial mirror: E and chi are symmetric, so f_theta is antisymmetric
+        assert np.max(np.abs(ft + ft[:, ::-1, :])) <= 1e-12 * np.max(np.abs(ft))
+    orders = _order(errs)
+    assert all(1.9 < o < 2.1 for o in orders), (errs, orders)
+    assert errs[-1] < 1e-3, errs
+
+
+def test_force_theta_cells_next_to_the_poles_see_one_face():
+    """No flux crosses a pole (zero-gradient boundary), so the cell next to it averages
+    its one inner face flux with zero: half of -(c / (3 chi_f)) dE / (r dtheta) across
+    that face, times chi_c / c."""
+    E0 = A * sy.T_BC ** 4
+    chi_of = lambda t, p: 1e-6 * (1.0 + 0.6 * np.sin(3.0 * t) ** 2)
+    E_of = lambda t, p: E0 * (1.0 + 0.4 * np.cos(t) ** 2)
+    nt = 32
+    ft, _, TT, PP, RR = _angular_force(nt, 1, chi_of, E_of)
+    t0, t1 = TT[0, 0, 0], TT[0, 1, 0]
+    for j0, j1, sgn in ((0, 1, 1.0), (nt - 1, nt - 2, -1.0)):
+        c0 = chi_of(TT[0, j0, 0], 0.0)
+        cf = 0.5 * (c0 + chi_of(TT[0, j1, 0], 0.0))
+        dE = E_of(TT[0, j1, 0], 0.0) - E_of(TT[0, j0, 0], 0.0)
+        for i in range(2):
+            F = -sgn * (C / (3.0 * cf)) * dE / (RR[0, 0, i] * (t1 - t0))
+            ref = c0 / C * 0.5 * F
+            assert abs(ft[0, j0, i] / ref - 1.0) < 1e-10, (j0, i)
+
+
+def test_force_phi_component_converges_to_the_fld_flux():
+    """As for theta: kappa_R rho F_phi / c = -(1/3) dE/dphi / (r sin theta) in the
+    diffusion limit.  E = E0 (1 + 0.3 cos phi + 0.1 sin 2 phi) and a clumpy chi(phi)
+    on N_phi = 32 ... 256 cells, periodic, so every cell has both faces; the theta
+    component vanishes (E does not depend on theta).  The azimuthal face area, the
+    centre distance r sin(theta) dphi and the choice of the neighbour's weight for the
+    inner face enter at first order, so second-order convergence pins them."""
+    E0 = A * sy.T_BC ** 4
+    chi_of = lambda t, p: 1e-6 * (1.0 + 0.5 * np.cos(2.0 * p + 0.3) ** 2)
+    E_of = lambda t, p: E0 * (1.0 + 0.3 * np.cos(p) + 0.1 * np.sin(2.0 * p))
+    errs = []
+    for nph in (32, 64, 128, 256):
+        ft, fp, TT, PP, RR = _angular_force(4, nph, chi_of, E_of)
+        dEdp = E0 * (-0.3 * np.sin(PP) + 0.2 * np.cos(2.0 * PP))
+        exact = -dEdp / (3.0 * RR * np.sin(TT))
+        errs.append(np.max(np.abs(fp - exact)) / np.max(np.abs(exact)))
+        assert np.max(np.abs(ft)) <= 1e-12 * np.max(np.abs(fp))
+    orders = _order(errs)
+    assert all(1.9 < o < 2.1 for o in orders), (errs, orders)
+    assert errs[-1] < 1e-3, errs
+
+
 # --------------------------------------------------------- paper's density table
 
 def test_density_normalisation_reproduces_paper_table():
