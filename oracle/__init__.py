@@ -16,15 +16,19 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _SRC_NN = os.path.join(_HERE, "oracle_nn.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so (serial, -O2, no FMA contraction)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-std=c99", "-Wall", "-o", tmp, _SRC, _SRC_NN, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile oracle.c into liboracle.so (serial, -O2, no FMA contraction) and the
+    same sources with OpenMP into liboracle_omp.so (the all-cores CPU baseline and the
+    oracle side of the tests on the largest grids)."""
+    for path, extra in ((_LIB, ["-Wno-unknown-pragmas"]), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                                   "-std=c99", "-Wall", *extra, "-o", tmp, _SRC, _SRC_NN, "-lm"])
+            os.replace(tmp, path)
     return _LIB
 
 
@@ -49,16 +53,17 @@ class _Fld(C.Structure):
                 ("Efloor", C.c_double)]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+def lib(parallel: bool = False):
+    """The serial oracle library, or (parallel=True) its OpenMP build."""
+    if parallel not in _libs:
+        path = _LIB_OMP if parallel else _LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < max(os.path.getmtime(_SRC),
                                                                    os.path.getmtime(_SRC_NN)):
             build()
-        L = C.CDLL(_LIB)
+        L = C.CDLL(path)
         P = C.POINTER
         dp = P(C.c_double)
         L.og_star_bins.argtypes = [C.c_double, C.c_int, dp, dp]
@@ -99,6 +104,9 @@ def lib():
         L.ognn_param_count.restype = C.c_long
         for f in ("ognn_cin", "ognn_cout", "ognn_taps"):
             getattr(L, f).argtypes = [ip]
+        L.ognn_forward_bf16.argtypes = [ip, ip, ip, dp, dp, dp]
+        L.ognn_bf16_round.argtypes = [C.c_double]
+        L.ognn_bf16_round.restype = C.c_double
         L.ognn_loss_grad.argtypes = [ip, ip, ip, dp, dp, dp, dp, dp]
         L.ognn_loss_grad.restype = C.c_double
         L.ognn_loss_grad_resid.argtypes = [ip, ip, ip, dp, dp, dp, dp, dp, dp]
@@ -108,8 +116,14 @@ def lib():
         L.ognn_adam.argtypes = [C.c_long, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double,
                                 C.c_double, ip]
         L.og_const_c.restype = C.c_double
-        _lib = L
-    return _lib
+        L.og_threads.restype = C.c_int
+        _libs[parallel] = L
+    return _libs[parallel]
+
+
+def threads(parallel: bool = True) -> int:
+    """Threads the (parallel) oracle's loops use."""
+    return lib(parallel).og_threads()
 
 
 def _f64(a):
@@ -125,7 +139,9 @@ class Problem:
     """Holds the ctypes views of grid / opacity / star / FLD parameters for one problem."""
 
     def __init__(self, r_face, th_face, ph_face, T_tab, kappa, kappa_P, kappa_R,
-                 R_star=None, F0=None, T_star=None, dt=1e9, c_V=None, T_bc=14.7, E_floor=None):
+                 R_star=None, F0=None, T_star=None, dt=1e9, c_V=None, T_bc=14.7, E_floor=None,
+                 parallel=False):
+        self.L = lib(parallel)
         self._keep = [_f64(x) for x in (r_face, th_face, ph_face, T_tab, kappa, kappa_P, kappa_R)]
         rf, tf, pf, Tt, kap, kP, kR = self._keep
         self.shape = (len(rf) - 1, len(tf) - 1, len(pf) - 1)
@@ -133,20 +149,20 @@ class Problem:
         self.g = _Grid(self.shape[0], self.shape[1], self.shape[2], _p(rf), _p(tf), _p(pf))
         self.op = _Opac(len(Tt), kap.shape[1], _p(Tt), _p(kap), _p(kP), _p(kR))
         self.nnu = kap.shape[1]
-        a = lib().og_const_a()
+        a = self.L.og_const_a()
         self.F0 = None if F0 is None else _f64(F0)
         self.st = _Star(R_star or 0.0, T_star or 0.0, _p(self.F0))
         self.fld = _Fld(dt, c_V if c_V is not None else 0.0, T_bc,
                         E_floor if E_floor is not None else a * 1.0)
 
     @classmethod
-    def from_workload(cls, wl, F0=None):
+    def from_workload(cls, wl, F0=None, parallel=False):
         if F0 is None:
             F0 = star_bins(wl.T_star, wl.opacity.nu)
         g, op = wl.grid, wl.opacity
         return cls(g.r_face, g.th_face, g.ph_face, op.T, op.kappa, op.kappa_P, op.kappa_R,
                    R_star=wl.R_star, F0=F0, T_star=wl.T_star, dt=wl.dt, c_V=wl.c_V,
-                   T_bc=wl.T_bc, E_floor=wl.E_floor)
+                   T_bc=wl.T_bc, E_floor=wl.E_floor, parallel=parallel)
 
     # --- per-step pieces -------------------------------------------------
     def raytrace(self, rho, T, want_faces=True, want_bins=False):
@@ -157,14 +173,14 @@ class Problem:
         nr, nt, npp = self.shape
         F = np.empty((nr + 1) * nt * npp) if want_faces else None
         Fnu = np.empty((nr + 1) * nt * npp * self.op.nnu) if want_bins else None
-        lib().og_raytrace(C.byref(self.g), C.byref(self.op), C.byref(self.st), _p(rho), _p(T),
+        self.L.og_raytrace(C.byref(self.g), C.byref(self.op), C.byref(self.st), _p(rho), _p(T),
                           _p(q), _p(S), _p(F), _p(Fnu))
         return (q, S, F, Fnu) if want_bins else (q, S, F)
 
     def energy(self, T, S):
         T, S = _f64(T).ravel(), _f64(S).ravel()
         E = np.empty(self.n)
-        lib().og_energy(C.byref(self.g), C.byref(self.op), C.byref(self.fld), _p(T), _p(S), _p(E))
+        self.L.og_energy(C.byref(self.g), C.byref(self.op), C.byref(self.fld), _p(T), _p(S), _p(E))
         return E
 
     def assemble(self, rho, T, En, q, Q=None):
@@ -173,7 +189,7 @@ class Problem:
         n = self.n
         out = dict(w=np.empty(3 * n), d=np.empty(n), b=np.empty(n), s=np.empty(n),
                    ahat=np.empty(3 * n), bhat=np.empty(n))
-        lib().og_assemble(C.byref(self.g), C.byref(self.op), C.byref(self.fld),
+        self.L.og_assemble(C.byref(self.g), C.byref(self.op), C.byref(self.fld),
                           *[_p(a) for a in args], _p(Qa), _p(out["w"]), _p(out["d"]),
                           _p(out["b"]), _p(out["s"]), _p(out["ahat"]), _p(out["bhat"]))
         return out
@@ -181,18 +197,18 @@ class Problem:
     def spmv(self, ahat, x):
         ahat, x = _f64(ahat).ravel(), _f64(x).ravel()
         y = np.empty(self.n)
-        lib().og_spmv(C.byref(self.g), _p(ahat), _p(x), _p(y))
+        self.L.og_spmv(C.byref(self.g), _p(ahat), _p(x), _p(y))
         return y
 
     def relres(self, ahat, bhat, y):
-        return lib().og_relres(C.byref(self.g), _p(_f64(ahat).ravel()), _p(_f64(bhat).ravel()),
+        return self.L.og_relres(C.byref(self.g), _p(_f64(ahat).ravel()), _p(_f64(bhat).ravel()),
                                _p(_f64(y).ravel()))
 
     def cg(self, ahat, bhat, y0, tol, max_iter):
         ahat, bhat = _f64(ahat).ravel(), _f64(bhat).ravel()
         y = _f64(y0).ravel().copy()
         it = C.c_int(0); rr = C.c_double(0)
-        st = lib().og_cg(C.byref(self.g), _p(ahat), _p(bhat), _p(y), tol, max_iter,
+        st = self.L.og_cg(C.byref(self.g), _p(ahat), _p(bhat), _p(y), tol, max_iter,
                          C.byref(it), C.byref(rr))
         return y, st, it.value, rr.value
 
@@ -201,14 +217,14 @@ class Problem:
         ahat, bhat = _f64(ahat).ravel(), _f64(bhat).ravel()
         y = _f64(y0).ravel().copy()
         it = C.c_int(0); rr = C.c_double(0)
-        st = lib().og_gmres(C.byref(self.g), _p(ahat), _p(bhat), _p(y), int(m), tol, max_iter,
+        st = self.L.og_gmres(C.byref(self.g), _p(ahat), _p(bhat), _p(y), int(m), tol, max_iter,
                             C.byref(it), C.byref(rr))
         return y, st, it.value, rr.value
 
     def dense_solve(self, ahat, bhat):
         ahat, bhat = _f64(ahat).ravel(), _f64(bhat).ravel()
         y = np.empty(self.n)
-        st = lib().og_dense_solve(C.byref(self.g), _p(ahat), _p(bhat), _p(y))
+        st = self.L.og_dense_solve(C.byref(self.g), _p(ahat), _p(bhat), _p(y))
         if st != 0:
             raise RuntimeError(f"dense solve failed ({st})")
         return y
@@ -216,13 +232,13 @@ class Problem:
     def newton(self, E, S, T_start):
         E, S = _f64(E).ravel(), _f64(S).ravel()
         T = _f64(T_start).ravel().copy()
-        lib().og_newton(C.byref(self.g), C.byref(self.op), _p(E), _p(S), _p(T))
+        self.L.og_newton(C.byref(self.g), C.byref(self.op), _p(E), _p(S), _p(T))
         return T
 
     def force(self, rho, T, w, E, q):
         out = np.empty(4 * self.n)
         args = [_f64(x).ravel() for x in (rho, T, w, E, q)]
-        lib().og_force(C.byref(self.g), C.byref(self.op), C.byref(self.fld),
+        self.L.og_force(C.byref(self.g), C.byref(self.op), C.byref(self.fld),
                        *[_p(a) for a in args], _p(out))
         return out
 
@@ -232,7 +248,7 @@ class Problem:
         E = np.empty(self.n)
         f = np.empty(4 * self.n) if want_force else None
         it = C.c_int(0); rr = C.c_double(0)
-        st = lib().og_step(C.byref(self.g), C.byref(self.op), C.byref(self.st), C.byref(self.fld),
+        st = self.L.og_step(C.byref(self.g), C.byref(self.op), C.byref(self.st), C.byref(self.fld),
                            _p(rho), _p(T), _p(E), _p(f), tol, max_iter, 2 if no_fld else int(dense),
                            C.byref(it), C.byref(rr))
         return dict(T=T, E=E, force=f, status=st, iters=it.value, relres=rr.value)
@@ -245,7 +261,7 @@ class Problem:
         T = _f64(T).ravel().copy()
         E = np.empty(self.n)
         ch = C.c_double(0)
-        k = lib().og_relax(C.byref(self.g), C.byref(self.op), C.byref(self.st), C.byref(self.fld), _p(rho),
+        k = self.L.og_relax(C.byref(self.g), C.byref(self.op), C.byref(self.st), C.byref(self.fld), _p(rho),
                            _p(T), _p(E), m, tol, max_iter, max_steps, tol_change, C.byref(ch))
         return T, E, k, ch.value
 
@@ -254,25 +270,25 @@ class Problem:
         rho, T = _f64(rho).ravel(), _f64(T).ravel()
         nr, nt, npp = self.shape
         tau = np.empty((nr + 1) * nt * npp)
-        lib().og_tau_rosseland(C.byref(self.g), C.byref(self.op), _p(rho), _p(T), _p(tau))
+        self.L.og_tau_rosseland(C.byref(self.g), C.byref(self.op), _p(rho), _p(T), _p(tau))
         return tau
 
     def gray_table(self, F):
         """(kappa_gray[n_T], sum F): the one-bin opacity table of gray irradiation."""
         F = _f64(F).ravel()
         kg = np.empty(len(self._keep[3]))
-        Fs = lib().og_gray_table(C.byref(self.op), _p(F), _p(kg))
+        Fs = self.L.og_gray_table(C.byref(self.op), _p(F), _p(kg))
         return kg, Fs
 
     # --- table lookups (for pins) ----------------------------------------
     def kappa_nu(self, T, b):
-        return lib().og_kappa_nu(C.byref(self.op), float(T), int(b))
+        return self.L.og_kappa_nu(C.byref(self.op), float(T), int(b))
 
     def kappa_P(self, T):
-        return lib().og_kappa_P(C.byref(self.op), float(T))
+        return self.L.og_kappa_P(C.byref(self.op), float(T))
 
     def kappa_R(self, T):
-        return lib().og_kappa_R(C.byref(self.op), float(T))
+        return self.L.og_kappa_R(C.byref(self.op), float(T))
 
 
 def star_bins(T_star, nu):
@@ -350,6 +366,20 @@ class NN:
     def layer_shapes():
         L = lib()
         return [(L.ognn_taps(l), L.ognn_cout(l), L.ognn_cin(l)) for l in range(11)]
+
+    @staticmethod
+    def forward_bf16(shape, params, X):
+        """U-Net forward with every activation stored as bf16 (ties to even), fp64
+        arithmetic otherwise: the network as the matrix-core kernels evaluate it."""
+        nr, nt, npp = shape
+        params = _f64(params).ravel(); X = _f64(X).ravel()
+        z = np.empty(nr * nt * npp)
+        lib().ognn_forward_bf16(nr, nt, npp, _p(params), _p(X), _p(z))
+        return z
+
+    @staticmethod
+    def bf16_round(x):
+        return lib().ognn_bf16_round(float(x))
 
     @staticmethod
     def loss_grad(shape, params, X, e):

@@ -9,6 +9,13 @@
  * table lookups and solvers are written out again here, in the paper's order, for a
  * reader to check against the paper by eye.  Nothing is blocked, fused or reordered.
  *
+ * The same source also builds with OpenMP (-fopenmp; the CPU baseline on all host
+ * cores, and the oracle side of the tests on the largest grids): the loops over
+ * radial columns and cells are split over threads, each cell computed exactly as in
+ * the serial build.  Only the sums over all cells (dot products, norms) change order
+ * there: fixed 4096-cell blocks summed in parallel, then the block sums in block order,
+ * so the result does not depend on the thread count.
+ *
  * Layout: cell (i, j, k) of an N_r x N_theta x N_phi spherical-polar grid has index
  * c = i + N_r (j + N_theta k) (r fastest).  Radial face i (at r_face[i], i = 0..N_r)
  * of column (j, k) has index i + (N_r + 1)(j + N_theta k).
@@ -48,6 +55,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* CGS constants (CODATA 2018). */
 #define OG_C 2.99792458e10
@@ -272,6 +282,7 @@ void og_raytrace(const og_grid *g, const og_opac *op, const og_star *st,
 {
     int nr = g->nr, nt = g->nt, np = g->np, nnu = op->nnu;
     double R2 = st->R * st->R;
+#pragma omp parallel for collapse(2) schedule(static)
     for (int k = 0; k < np; k++)
         for (int j = 0; j < nt; j++) {
             for (int i = 0; i < nr; i++) {
@@ -309,6 +320,7 @@ void og_energy(const og_grid *g, const og_opac *op, const og_fld *f,
                const double *T, const double *S, double *E)
 {
     long n = (long)g->nr * g->nt * g->np;
+#pragma omp parallel for schedule(static)
     for (long c = 0; c < n; c++) {
         double t = T[c];
         double e = OG_A * t * t * t * t - S[c] / og_kappa_P(op, t);
@@ -346,11 +358,13 @@ void og_assemble(const og_grid *g, const og_opac *op, const og_fld *f,
     int nr = g->nr, nt = g->nt, np = g->np;
     long n = (long)nr * nt * np;
     double *chi = (double *)malloc(sizeof(double) * n);
+#pragma omp parallel for schedule(static)
     for (long c = 0; c < n; c++) chi[c] = og_kappa_R(op, T[c]) * rho[c];
     double Eb = OG_A * pow(f->Tbc, 4);
     double *wr = w, *wt = w + n, *wp = w + 2 * n;
 
     /* outward face weights */
+#pragma omp parallel for collapse(2) schedule(static)
     for (int k = 0; k < np; k++)
         for (int j = 0; j < nt; j++)
             for (int i = 0; i < nr; i++) {
@@ -379,6 +393,7 @@ void og_assemble(const og_grid *g, const og_opac *op, const og_fld *f,
             }
 
     /* diagonal, rhs, Jacobi scale */
+#pragma omp parallel for collapse(2) schedule(static)
     for (int k = 0; k < np; k++)
         for (int j = 0; j < nt; j++)
             for (int i = 0; i < nr; i++) {
@@ -398,6 +413,7 @@ void og_assemble(const og_grid *g, const og_opac *op, const og_fld *f,
                 bhat[c] = s[c] * b[c];
             }
 
+#pragma omp parallel for collapse(2) schedule(static)
     for (int k = 0; k < np; k++)
         for (int j = 0; j < nt; j++)
             for (int i = 0; i < nr; i++) {
@@ -415,6 +431,7 @@ void og_spmv(const og_grid *g, const double *ahat, const double *x, double *y)
     int nr = g->nr, nt = g->nt, np = g->np;
     long n = (long)nr * nt * np;
     const double *ar = ahat, *at = ahat + n, *ap = ahat + 2 * n;
+#pragma omp parallel for collapse(2) schedule(static)
     for (int k = 0; k < np; k++)
         for (int j = 0; j < nt; j++)
             for (int i = 0; i < nr; i++) {
@@ -435,9 +452,26 @@ void og_spmv(const og_grid *g, const double *ahat, const double *x, double *y)
 
 static double dot(long n, const double *a, const double *b)
 {
+#ifdef _OPENMP
+    /* fixed blocks, block sums added in block order (independent of the thread count) */
+    const long B = 4096, nb = (n + B - 1) / B;
+    double *part = (double *)malloc(sizeof(double) * (nb > 0 ? nb : 1));
+#pragma omp parallel for schedule(static)
+    for (long m = 0; m < nb; m++) {
+        double s = 0.0;
+        long e = (m + 1) * B < n ? (m + 1) * B : n;
+        for (long i = m * B; i < e; i++) s += a[i] * b[i];
+        part[m] = s;
+    }
+    double s = 0.0;
+    for (long m = 0; m < nb; m++) s += part[m];
+    free(part);
+    return s;
+#else
     double s = 0.0;
     for (long i = 0; i < n; i++) s += a[i] * b[i];
     return s;
+#endif
 }
 
 /* ||bhat - Ahat y|| / ||bhat|| (reading R7). */
@@ -446,8 +480,9 @@ double og_relres(const og_grid *g, const double *ahat, const double *bhat, const
     long n = (long)g->nr * g->nt * g->np;
     double *t = (double *)malloc(sizeof(double) * n);
     og_spmv(g, ahat, y, t);
-    double rr = 0.0, bb = dot(n, bhat, bhat);
-    for (long c = 0; c < n; c++) { double r = bhat[c] - t[c]; rr += r * r; }
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < n; c++) t[c] = bhat[c] - t[c];
+    double rr = dot(n, t, t), bb = dot(n, bhat, bhat);
     free(t);
     return bb > 0 ? sqrt(rr / bb) : sqrt(rr);
 }
@@ -470,6 +505,7 @@ int og_cg(const og_grid *g, const double *ahat, const double *bhat, double *y,
     double bn = sqrt(dot(n, bhat, bhat));
     if (bn == 0.0) bn = 1.0;
     og_spmv(g, ahat, y, qv);
+#pragma omp parallel for schedule(static)
     for (long c = 0; c < n; c++) { r[c] = bhat[c] - qv[c]; p[c] = r[c]; }
     double rr = dot(n, r, r);
     int it = 0, status = 1;
@@ -479,6 +515,7 @@ int og_cg(const og_grid *g, const double *ahat, const double *bhat, double *y,
         it++;
         og_spmv(g, ahat, p, qv);
         double alpha = rr / dot(n, p, qv);
+#pragma omp parallel for schedule(static)
         for (long c = 0; c < n; c++) { y[c] += alpha * p[c]; r[c] -= alpha * qv[c]; }
         double rr1 = dot(n, r, r);
         if (it % 50 == 0 || sqrt(rr1) / bn <= tol) {
@@ -488,6 +525,7 @@ int og_cg(const og_grid *g, const double *ahat, const double *bhat, double *y,
             res = sqrt(rr1) / bn;
         double beta = rr1 / rr;
         rr = rr1;
+#pragma omp parallel for schedule(static)
         for (long c = 0; c < n; c++) p[c] = r[c] + beta * p[c];
     }
     if (status) res = og_relres(g, ahat, bhat, y);
@@ -639,6 +677,7 @@ static double g16(const og_opac *op, double E, double S, double t, double *dg)
 void og_newton(const og_grid *g, const og_opac *op, const double *E, const double *S, double *T)
 {
     long n = (long)g->nr * g->nt * g->np;
+#pragma omp parallel for schedule(dynamic, 4096)
     for (long c = 0; c < n; c++) {
         double e = E[c], s = S[c];
         double lo = pow(e / OG_A, 0.25), hi = -1.0;
@@ -686,6 +725,7 @@ void og_force(const og_grid *g, const og_opac *op, const og_fld *f, const double
     long n = (long)nr * nt * np;
     const double *wr = w, *wt = w + n, *wp = w + 2 * n;
     double Eb = OG_A * pow(f->Tbc, 4);
+#pragma omp parallel for collapse(2) schedule(static)
     for (int k = 0; k < np; k++)
         for (int j = 0; j < nt; j++)
             for (int i = 0; i < nr; i++) {
@@ -830,4 +870,14 @@ double og_gray_table(const og_opac *op, const double *F, double *kappa_gray)
         kappa_gray[k] = t / Fs;
     }
     return Fs;
+}
+
+/* Threads the oracle's parallel loops use (1 in the serial build). */
+int og_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -184,8 +184,33 @@ static void conv1x1(long n, const double *x, int cin, const double *w, const dou
     }
 }
 
-/* Forward pass: X [n0][16] -> z [n0]; keeps every activation in *A. */
-void ognn_forward(int nr, int nt, int np, const double *params, const double *X, ognn_acts *A, double *z)
+/* x rounded to the nearest bfloat16 (8 significant bits, ties to even), through the
+ * nearest float; infinities and NaN pass unchanged.  Models the bf16 storage of the
+ * network's activations (config: BF16 weights / activations, FP32 accumulation). */
+static double bf16_round(double x)
+{
+    float f = (float)x;
+    unsigned u;
+    memcpy(&u, &f, sizeof u);
+    if ((u & 0x7f800000u) == 0x7f800000u) return f;
+    u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    memcpy(&f, &u, sizeof f);
+    return f;
+}
+
+static void round_all(long n, double *x, int quant)
+{
+    if (!quant) return;
+    for (long i = 0; i < n; i++) x[i] = bf16_round(x[i]);
+}
+
+double ognn_bf16_round(double x) { return bf16_round(x); }
+
+/* Forward pass: X [n0][16] -> z [n0]; keeps every activation in *A.  quant != 0 stores
+ * every layer output (after the ReLU) and every pooled tensor as bf16, as the matrix-core
+ * kernels do; the 1x1 output layer stays unrounded. */
+static void forward_impl(int nr, int nt, int np, const double *params, const double *X, ognn_acts *A, double *z,
+                         int quant)
 {
     int r[3], t[3], p[3];
     long n[3];
@@ -204,24 +229,49 @@ void ognn_forward(int nr, int nt, int np, const double *params, const double *X,
 #define W(l) (params + ognn_param_offset(l))
 #define B(l) (params + ognn_param_offset(l) + (long)ognn_taps(l) * COUT[l] * CIN[l])
     ognn_conv_fwd(r[0], t[0], p[0], X, 16, W(0), B(0), 16, 1, A->a[0]);
+    round_all(n[0] * 16, A->a[0], quant);
     ognn_conv_fwd(r[0], t[0], p[0], A->a[0], 16, W(1), B(1), 16, 1, A->a[1]);
+    round_all(n[0] * 16, A->a[1], quant);
     ognn_pool(r[0], t[0], p[0], A->a[1], 16, A->p1);
+    round_all(n[1] * 16, A->p1, quant);
     ognn_conv_fwd(r[1], t[1], p[1], A->p1, 16, W(2), B(2), 32, 1, A->a[2]);
+    round_all(n[1] * 32, A->a[2], quant);
     ognn_conv_fwd(r[1], t[1], p[1], A->a[2], 32, W(3), B(3), 32, 1, A->a[3]);
+    round_all(n[1] * 32, A->a[3], quant);
     ognn_pool(r[1], t[1], p[1], A->a[3], 32, A->p2);
+    round_all(n[2] * 32, A->p2, quant);
     ognn_conv_fwd(r[2], t[2], p[2], A->p2, 32, W(4), B(4), 64, 1, A->a[4]);
+    round_all(n[2] * 64, A->a[4], quant);
     ognn_conv_fwd(r[2], t[2], p[2], A->a[4], 64, W(5), B(5), 64, 1, A->a[5]);
+    round_all(n[2] * 64, A->a[5], quant);
     ognn_up(r[1], t[1], p[1], A->a[5], 64, up6);
     concat(n[1], up6, 64, A->a[3], 32, A->c6);
     ognn_conv_fwd(r[1], t[1], p[1], A->c6, 96, W(6), B(6), 32, 1, A->a[6]);
+    round_all(n[1] * 32, A->a[6], quant);
     ognn_conv_fwd(r[1], t[1], p[1], A->a[6], 32, W(7), B(7), 32, 1, A->a[7]);
+    round_all(n[1] * 32, A->a[7], quant);
     ognn_up(r[0], t[0], p[0], A->a[7], 32, up8);
     concat(n[0], up8, 32, A->a[1], 16, A->c8);
     ognn_conv_fwd(r[0], t[0], p[0], A->c8, 48, W(8), B(8), 16, 1, A->a[8]);
+    round_all(n[0] * 16, A->a[8], quant);
     ognn_conv_fwd(r[0], t[0], p[0], A->a[8], 16, W(9), B(9), 16, 1, A->a[9]);
+    round_all(n[0] * 16, A->a[9], quant);
     conv1x1(n[0], A->a[9], 16, W(10), B(10), A->a[10]);
     memcpy(z, A->a[10], sizeof(double) * n[0]);
     free(up6); free(up8);
+}
+
+void ognn_forward(int nr, int nt, int np, const double *params, const double *X, ognn_acts *A, double *z)
+{
+    forward_impl(nr, nt, np, params, X, A, z, 0);
+}
+
+/* The forward pass with bf16 activations (forward_impl with quant = 1): z [n0]. */
+void ognn_forward_bf16(int nr, int nt, int np, const double *params, const double *X, double *z)
+{
+    ognn_acts A;
+    forward_impl(nr, nt, np, params, X, &A, z, 1);
+    ognn_free(&A);
 }
 
 /* dx *= (y > 0): ReLU backward from the layer output. */

@@ -191,3 +191,71 @@ def test_residual_loss_value_and_gradient():
         pm[idx] -= h
         fd = (NN.loss_grad_resid(shape, pp, X, rr, ahat)[0] - NN.loss_grad_resid(shape, pm, X, rr, ahat)[0]) / (2 * h)
         assert abs(fd - grad[idx]) <= 1e-5 * abs(grad[idx]) + 2e-9 * max(1.0, L), (idx, fd, grad[idx])
+
+
+def _bf16_numpy(x):
+    """Round to bfloat16 (ties to even) via the float32 bit pattern, in numpy."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_bf16_rounding_is_round_to_nearest_even():
+    """The oracle's bf16 rounding against a numpy bit-level round-to-nearest-even on
+    ties, near-ties, subnormals, both signs and the overflow to infinity."""
+    ulp = 2.0 ** -7
+    xs = [1.0, 1.0 + ulp / 2, 1.0 + 1.5 * ulp, 1.0 + ulp / 2 + 2 ** -20, -(3.0 + ulp), 1e-39, -2.5e-40,
+          3.3895e38, 3.4e38, 0.0]
+    xs += list(_rng(5).standard_normal(2000) * 10.0 ** _rng(6).uniform(-30, 30, 2000))
+    for x in xs:
+        assert NN.bf16_round(x) == _bf16_numpy(np.float32(x)) or (np.isinf(NN.bf16_round(x)) and
+                                                                   np.isinf(_bf16_numpy(np.float32(x))))
+    assert NN.bf16_round(1.0 + ulp / 2) == 1.0 and NN.bf16_round(1.0 + 1.5 * ulp) == 1.0 + 2 * ulp
+    assert np.isinf(NN.bf16_round(3.4e38))
+
+
+def test_bf16_forward_is_the_layer_chain_with_rounded_activations():
+    """The bf16-activation forward equals the composition of the oracle's own layers
+    with every stored activation rounded (numpy rounding), exactly; it equals the fp64
+    forward when every activation is already bf16-exact (small integers through
+    single-tap integer weights); and it stays within bf16 rounding of the fp64 forward."""
+    shape = (8, 8, 4)
+    n = 8 * 8 * 4
+    g = _rng(31)
+    p = _random_params(31)
+    X = _bf16_numpy(g.standard_normal(n * 16))
+    z = NN.forward_bf16(shape, p, X)
+    L = NN.layer_shapes()
+    W = lambda l: p[NN.param_offset(l):NN.param_offset(l) + L[l][0] * L[l][1] * L[l][2]]
+    B = lambda l: p[NN.param_offset(l) + L[l][0] * L[l][1] * L[l][2]:NN.param_offset(l + 1)]
+    s1, s2, s3 = shape, tuple(d // 2 for d in shape), tuple(d // 4 for d in shape)
+    q = _bf16_numpy
+    a0 = q(NN.conv_fwd(s1, X, 16, W(0), B(0), 16, True))
+    a1 = q(NN.conv_fwd(s1, a0, 16, W(1), B(1), 16, True))
+    p1 = q(NN.pool(s1, a1, 16))
+    a2 = q(NN.conv_fwd(s2, p1, 16, W(2), B(2), 32, True))
+    a3 = q(NN.conv_fwd(s2, a2, 32, W(3), B(3), 32, True))
+    p2 = q(NN.pool(s2, a3, 32))
+    a4 = q(NN.conv_fwd(s3, p2, 32, W(4), B(4), 64, True))
+    a5 = q(NN.conv_fwd(s3, a4, 64, W(5), B(5), 64, True))
+    c6 = np.concatenate([NN.up(s2, a5, 64).reshape(-1, 64), a3.reshape(-1, 32)], axis=1).ravel()
+    a6 = q(NN.conv_fwd(s2, c6, 96, W(6), B(6), 32, True))
+    a7 = q(NN.conv_fwd(s2, a6, 32, W(7), B(7), 32, True))
+    c8 = np.concatenate([NN.up(s1, a7, 32).reshape(-1, 32), a1.reshape(-1, 16)], axis=1).ravel()
+    a8 = q(NN.conv_fwd(s1, c8, 48, W(8), B(8), 16, True))
+    a9 = q(NN.conv_fwd(s1, a8, 16, W(9), B(9), 16, True))
+    ref = a9.reshape(n, 16) @ W(10) + B(10)[0]
+    assert np.max(np.abs(z - ref)) <= 1e-14 * np.max(np.abs(ref))
+    _, _, z64 = NN.loss_grad(shape, p, X, np.ones(n))
+    assert np.linalg.norm(z - z64) <= 0.05 * np.linalg.norm(z64)
+    # integer-valued activations: channel 0 through the fine level only
+    pi = np.zeros(NN.param_count())
+    for l, ci in ((0, 0), (1, 0), (8, 32), (9, 0)):
+        taps, cout, cin = L[l]
+        pi[NN.param_offset(l) + (13 * cout + 0) * cin + ci] = 2.0
+    pi[NN.param_offset(10)] = 1.0
+    Xi = np.zeros((n, 16))
+    Xi[:, 0] = g.integers(-8, 9, n)
+    zi = NN.forward_bf16(shape, pi, Xi.ravel())
+    _, _, zi64 = NN.loss_grad(shape, pi, Xi.ravel(), np.ones(n))
+    assert np.array_equal(zi, zi64) and np.array_equal(zi, 16.0 * np.maximum(Xi[:, 0], 0))

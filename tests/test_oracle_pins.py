@@ -688,3 +688,28 @@ def test_rosseland_depth_closed_form():
     ref = np.concatenate([np.cumsum(d[::-1])[::-1], [0.0]])
     tau = P.tau_rosseland(rho, T).reshape(2, 3, 41)
     assert np.max(np.abs(tau - ref) / np.maximum(ref, 1e-300)) < 1e-9
+
+
+def test_openmp_build_computes_the_serial_oracle():
+    """The OpenMP build of the same source (all-cores baseline, largest test grids):
+    cell-local results bitwise equal, sums over all cells (CG dots) in fixed blocks, so
+    a whole step agrees to rounding."""
+    wl = sy.make_workload("t", 40, 12, 6, 16, 10.0, clump_seed=4)
+    Ps = oracle.Problem.from_workload(wl)
+    Pp = oracle.Problem.from_workload(wl, parallel=True)
+    rho = wl.rho.ravel()
+    T = np.random.Generator(np.random.PCG64(8)).uniform(20.0, 400.0, Ps.n)
+    for a, b in zip(Ps.raytrace(rho, T), Pp.raytrace(rho, T)):
+        assert np.array_equal(a, b)
+    q, S, _ = Ps.raytrace(rho, T)
+    En = Ps.energy(T, S)
+    assert np.array_equal(En, Pp.energy(T, S))
+    oa, ob = Ps.assemble(rho, T, En, q), Pp.assemble(rho, T, En, q)
+    for k in oa:
+        assert np.array_equal(oa[k], ob[k]), k
+    assert np.array_equal(Ps.newton(En, S, T), Pp.newton(En, S, T))
+    T0 = Ps.newton(np.full(Ps.n, A * sy.T_BC ** 4), S, np.full(Ps.n, sy.T_BC))
+    sa, sb = Ps.step(rho, T0, tol=1e-12), Pp.step(rho, T0, tol=1e-12)
+    assert sa["status"] == 0 and sb["status"] == 0 and abs(sa["iters"] - sb["iters"]) <= 2
+    assert np.max(np.abs(sa["T"] / sb["T"] - 1)) < 1e-11
+    assert np.max(np.abs(sa["force"] - sb["force"])) <= 1e-9 * np.max(np.abs(sa["force"]))
