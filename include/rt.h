@@ -151,7 +151,9 @@ typedef struct {
     int iters;           /* Krylov iterations (inner iterations in mixed / learned modes) */
     int outer_iters;     /* float64 refinement steps (mixed / learned) */
     int precond_applies; /* network applications (learned) */
-    int fallback;        /* 1 if a learned or mixed solve finished with the float64 method */
+    int fallback;        /* 1 if a mixed solve's precision guard, or a learned solve's
+                            non-finite network output, handed the solve to the float64
+                            method (a failure of the faster method, not a wrong answer) */
     double relres;       /* final true relative residual, computed in float64 */
     double ms;           /* wall time of the solve (host clock, includes polls) */
     double ms_dir;       /* mean device time of one direction+operator kernel (sampled once per poll) */
@@ -162,6 +164,9 @@ typedef struct {
     double ms_black;     /* reduced solves: mean device time of the black pass alone (ms_dir -
                             ms_black is the red pass); precond = 1: the direction kernel
                             alone (ms_dir - ms_black is the block solve) */
+    int handover;        /* learned solves: 1 if the network budget (inner_max_iter
+                            applications) ran out above tol and the planned finish (float64
+                            CG, or the reduced mixed solve with reduce = 1) completed it */
 } rt_solve_stats;
 
 typedef struct {

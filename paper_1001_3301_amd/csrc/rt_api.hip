@@ -613,6 +613,20 @@ rt_status norm_b(rt_ctx *ctx, double &bb)
     return RT_OK;
 }
 
+// Zeroes the float64 and float32 direction buffers.  Every CG restart forms p = r +
+// 0 * p_old, which a non-finite p_old would poison, so a solve that continues after a
+// non-finite exit (the learned solve's fallback) or the next call after a failed one
+// starts from zero directions again, as at creation.
+rt_status reset_directions(rt_ctx *ctx)
+{
+    const size_t N = (size_t)ctx->d.n;
+    for (void *pz : {(void *)ctx->p0, (void *)ctx->p1})
+        RT_HIP(ctx, hipMemsetAsync(pz, 0, N * sizeof(double), ctx->stream));
+    for (void *pz : {(void *)ctx->p32a, (void *)ctx->p32b})
+        RT_HIP(ctx, hipMemsetAsync(pz, 0, N * sizeof(float), ctx->stream));
+    return RT_OK;
+}
+
 // Plain float64 CG on A^ (the method; also the fallback of the other modes and the
 // reference they are checked against).
 rt_status solve_fp64(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb)
@@ -1069,9 +1083,14 @@ rt_status solve_learned(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
     }
     if (fallback) {
         // keep what the float32 iterations gained (unless they went non-finite: then y is
-        // the iterate of the last reliable update), then finish with the float64 method
+        // the iterate of the last reliable update, and the direction buffers the network's
+        // output reached are cleared), then finish with the float64 method.  Running out
+        // of network applications is the planned hand-over (`handover`); `fallback`
+        // marks a network that failed (non-finite output).
         if (!nonfinite) launch_fold(d.n, ctx->x32, ctx->y, s);
-        st->fallback = 1;
+        else if (rt_status e = reset_directions(ctx)) return e;
+        if (nonfinite) st->fallback = 1;
+        else st->handover = 1;
         rt_solve_stats s64{};
         rt_solve_opts o64 = *o;
         o64.max_iter = std::max(1, o->max_iter - st->iters);
@@ -1241,13 +1260,7 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
     S->ms = clk.ms();
     if (status == RT_ENOCONV) return fail(ctx, status, "iteration limit reached");
     if (status == RT_ENONFINITE) {
-        // a restart forms p = r + 0 * p_old, which a non-finite p_old would poison: the
-        // direction buffers start from zero again, as at creation
-        const size_t N = (size_t)ctx->d.n;
-        for (void *pz : {(void *)ctx->p0, (void *)ctx->p1})
-            RT_HIP(ctx, hipMemsetAsync(pz, 0, N * sizeof(double), ctx->stream));
-        for (void *pz : {(void *)ctx->p32a, (void *)ctx->p32b})
-            RT_HIP(ctx, hipMemsetAsync(pz, 0, N * sizeof(float), ctx->stream));
+        if (rt_status e = reset_directions(ctx)) return e;
         return fail(ctx, status, "non-finite residual");
     }
     return status;

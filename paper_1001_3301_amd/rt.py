@@ -66,7 +66,8 @@ class SolveStats(C.Structure):
     _fields_ = [("status", C.c_int), ("iters", C.c_int), ("outer_iters", C.c_int),
                 ("precond_applies", C.c_int), ("fallback", C.c_int), ("relres", C.c_double),
                 ("ms", C.c_double), ("ms_dir", C.c_double), ("ms_upd", C.c_double),
-                ("kernel_samples", C.c_int), ("reduced", C.c_int), ("ms_black", C.c_double)]
+                ("kernel_samples", C.c_int), ("reduced", C.c_int), ("ms_black", C.c_double),
+                ("handover", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
