@@ -10,8 +10,9 @@ computes one by one:
   of cells around each sample with the global faces: every quantity of a cell depends
   only on cells at most two faces away and on the global boundary treatment, which the
   block reproduces (a block that touches r_in, r_out or a pole has that boundary);
-* the float64 solve through its true residual, recomputed with float64 arithmetic
-  outside the solver.
+* the whole grid against the oracle's own run (OpenMP build): the prepared state (ray
+  trace, Newton), the oracle's assembled system and its residual of every solve mode's
+  answer, and the oracle's Newton step from that answer against the GPU's temperature.
 """
 import numpy as np
 import pytest
@@ -166,48 +167,81 @@ def test_fullsize_assembly_and_force_cells(fullsize):
         assert np.max(np.abs(fg[1:] - fr[1:])) <= 1e-10 * mag, (i, j, k)
 
 
-def test_fullsize_solve_true_residual(fullsize):
+@pytest.fixture(scope="module")
+def oracle_c5(fullsize):
+    """The oracle's own prepared state and assembled system on the whole 512 x 256 x 512
+    grid (OpenMP build of the oracle, same inputs as the GPU: density and tables)."""
+    wl = fullsize[0]
+    print(f"\noracle at {CONFIG} with {oracle.threads()} threads", flush=True)
+    P = oracle.Problem.from_workload(wl, parallel=True)
+    rho = wl.rho.ravel()
+    T0 = np.full(P.n, wl.T_bc)
+    _, S, _ = P.raytrace(rho, T0, want_faces=False)
+    T0 = P.newton(np.full(P.n, A * wl.T_bc ** 4), S, T0)
+    q, S, _ = P.raytrace(rho, T0, want_faces=False)
+    En = P.energy(T0, S)
+    sysref = P.assemble(rho, T0, En, q)
+    for k in ("w", "d", "b"):
+        del sysref[k]
+    return P, dict(T0=T0, q=q, S=S, En=En, **sysref)
+
+
+def test_fullsize_prepared_state_whole_grid(fullsize, oracle_c5):
+    """Every cell of the prepared state against the oracle's: the ray trace at T_bc and
+    the Newton temperature (T0), then the ray trace at T0 (q, S) and E^n."""
     wl, ctx, F, st = fullsize
+    P, O = oracle_c5
+    assert _rel_each(F["T0"].cpu().numpy(), O["T0"]) < 1e-11
+    assert _rel_each(F["q"].cpu().numpy(), O["q"]) < 1e-11
+    assert _rel_each(F["S"].cpu().numpy(), O["S"]) < 1e-11
+    # E^n = a T^4 - S / kappa_P cancels terms up to 1e7 times larger than itself
+    terms = A * O["T0"] ** 4
+    assert np.all(np.abs(F["En"].cpu().numpy() - O["En"]) <= 1e-11 * terms)
+
+
+def _against_oracle(F, O, P, E, T1):
+    """The oracle's residual of the GPU's E on the oracle's assembled system, and the
+    oracle's Newton temperature from that E (with the oracle's S and T^n) against the
+    GPU's T, every cell."""
+    Eg = E.cpu().numpy()
+    res = P.relres(O["ahat"], O["bhat"], Eg / O["s"])
+    Tn = P.newton(Eg, O["S"], O["T0"])
+    return res, _rel_each(T1.cpu().numpy(), Tn)
+
+
+def test_fullsize_fp64_solve_against_oracle(fullsize, oracle_c5):
+    wl, ctx, F, st = fullsize
+    P, O = oracle_c5
     assert st["relres"] <= 1e-8
-    y = F["E"] / F["s"]
-    Ay = torch.empty_like(y)
-    ctx.spmv(y, Ay)  # float64 operator product (its parity is tested at small sizes)
-    r = F["bhat"] - Ay
-    relres = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(F["bhat"]))
-    assert relres <= 1.01e-8, relres
+    res, eT = _against_oracle(F, O, P, F["E"], F["T1"])
+    print(f"fp64: {st['iters']} iterations; oracle relres of the GPU's E {res:.3e}, Newton T {eT:.2e}")
+    assert res <= 1.01e-8, res
+    assert eT < 1e-10
     assert torch.isfinite(F["T1"]).all() and (F["T1"] > 0).all()
 
 
-def test_fullsize_mixed_solve_temperature(fullsize):
-    """The float32-inner / float64-refined solve at full size: its temperature against
-    the float64 solve's (both to the relative residual 1e-8)."""
+@pytest.mark.parametrize("mode", ["mixed", "fp64-rb", "mixed-rb"])
+def test_fullsize_solves_against_oracle(fullsize, oracle_c5, mode):
+    """The float32-inner / float64-refined solve and the red-black reduced solves
+    (float64 and mixed) at full size: the oracle's residual of each answer meets the
+    tolerance, the oracle's Newton step from it gives the GPU's temperature, and the
+    temperature agrees with the float64 solve's; the reduced solves need under 0.7 of
+    the full system's iterations."""
     from paper_1001_3301_amd import rt
     wl, ctx, F, st = fullsize
+    P, O = oracle_c5
     E = F["En"].clone()
-    rc, sm = ctx.solve(E, rt.solve_opts(rt.MODE_MIXED, tol=1e-8, max_iter=100000))
-    assert sm["relres"] <= 1e-8
+    m = rt.MODE_FP64 if mode.startswith("fp64") else rt.MODE_MIXED
+    rc, sr = ctx.solve(E, rt.solve_opts(m, tol=1e-8, max_iter=100000, reduce=int(mode.endswith("-rb"))))
+    assert sr["relres"] <= 1e-8 and sr["fallback"] == 0
+    if mode.endswith("-rb"):
+        assert sr["reduced"] == 1 and sr["iters"] < 0.7 * st["iters"], (sr["iters"], st["iters"])
     T = F["T0"].clone()
     ctx.temperature(E, F["S"], T)
-    assert float(((T - F["T1"]).abs() / F["T1"]).max()) <= 1e-6
-
-
-@pytest.mark.parametrize("mode", ["fp64", "mixed"])
-def test_fullsize_reduced_solve(fullsize, mode):
-    """The red-black reduced solves at full size: the full-system residual recomputed
-    outside the solver meets the tolerance, and the temperature agrees with the float64
-    solve's."""
-    from paper_1001_3301_amd import rt
-    wl, ctx, F, st = fullsize
-    E = F["En"].clone()
-    m = rt.MODE_FP64 if mode == "fp64" else rt.MODE_MIXED
-    rc, sr = ctx.solve(E, rt.solve_opts(m, tol=1e-8, max_iter=100000, reduce=1))
-    assert sr["reduced"] == 1 and sr["relres"] <= 1e-8
-    assert sr["iters"] < 0.7 * st["iters"], (sr["iters"], st["iters"])
-    y = E / F["s"]
-    Ay = torch.empty_like(y)
-    ctx.spmv(y, Ay)
-    relres = float(torch.linalg.vector_norm(F["bhat"] - Ay) / torch.linalg.vector_norm(F["bhat"]))
-    assert relres <= 1.05e-8, relres
-    T = F["T0"].clone()
-    ctx.temperature(E, F["S"], T)
-    assert float(((T - F["T1"]).abs() / F["T1"]).max()) <= 1e-6
+    res, eT = _against_oracle(F, O, P, E, T)
+    dT = float(((T - F["T1"]).abs() / F["T1"]).max())
+    print(f"{mode}: {sr['iters']} iterations; oracle relres of the GPU's E {res:.3e}, Newton T {eT:.2e}, "
+          f"T vs the float64 solve {dT:.2e}")
+    assert res <= 1.05e-8, res
+    assert eT < 1e-10
+    assert dT <= 1e-6
