@@ -5,12 +5,17 @@ a relative residual of 1e-8, Newton temperature update, radiative force) on the
 512x256x512-cell, 64-bin workload (tau550 = 100 with lognormal clumps, seed 5000,
 dt = 1e9 s).  Every timed step starts from the same prepared state (the temperature
 in equilibrium with the stellar irradiation and E = a T_bc^4), so the K timed steps do
-identical work.  The headline solve mode is timed first, then the plain float64 solve
-for comparison.  With --successive N the headline mode also runs N successive steps
-(temperature carried over), whose per-step iteration counts are reported: the system
-gets harder as the radiation field evolves.  Unless --no-main-loop, the main loop is
-also run to equilibrium (the run table's gray / frequency-dependent runs with and
-without diffusion) on a 2-D disk, reported under "main_iteration".
+identical work.  The headline solve mode is timed first (K steps after W warm-up
+steps), then the other modes for comparison (at most 3 steps after 1 warm-up step
+each).  The headline mode also runs --successive N steps (default 5) with the
+temperature carried over, reported per step (seconds and iterations) under
+"successive_steps": the system gets harder as the radiation field evolves.  Every
+mode's answer is checked against the oracle on the whole grid ("oracle_check": the
+oracle's own assembly and residual of the GPU's E, the oracle's Newton temperature from
+it).  Unless --no-main-loop, the main loop is also run to equilibrium (the run table's
+gray / frequency-dependent runs with and without diffusion) on a 2-D disk, reported
+under "main_iteration".  The CPU baseline times the oracle on one core (a phi-slab) and
+on all cores (the whole grid, OpenMP build of the same source).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -133,6 +138,74 @@ def train_network(rt, torch, sy, n_fields, epochs, seed=7):
     return net, info
 
 
+def prepared_system(ctx, torch, sy, wl):
+    """Assembles the first radiation step's system of workload wl on ctx (irradiation at
+    T_bc, Eq. 16 with E = a T_bc^4, then the step's ray trace, E^n and assembly) and
+    returns E^n and T^n (device)."""
+    n = ctx.n
+    rho = torch.tensor(wl.rho.ravel(), device="cuda")
+    T = torch.full((n,), wl.T_bc, dtype=torch.float64, device="cuda")
+    q = torch.empty(n, dtype=torch.float64, device="cuda")
+    S = torch.empty_like(q)
+    ctx.raytrace(rho, T, q, S)
+    ctx.temperature(torch.full((n,), sy.A_RAD * wl.T_bc ** 4, dtype=torch.float64, device="cuda"), S, T)
+    ctx.raytrace(rho, T, q, S)
+    En = torch.empty_like(q)
+    ctx.energy(T, S, En)
+    ctx.assemble(rho, T, En, q)
+    return En, T
+
+
+def c4_gain(rt, torch, sy, n_fields=200, eval_seeds=(10000, 10001, 10002, 10003, 10004), epochs=6,
+            fcg_budget=1500):
+    """The learned preconditioner's gain as the config states it: trained on n_fields
+    seeded clumpy 128x64x64 fields (tau550 log-uniform in [0.1, 100]), evaluated on unseen
+    seeds at 256x128x256 (tau550 = 100, 64 bins).  Per evaluation field, iterations and
+    seconds to the relative residual 1e-8 of: learned flexible CG (the trained network,
+    up to fcg_budget applications before the planned float64 finish), the same with an
+    untrained network of the same shape, Jacobi-preconditioned CG (float64; Jacobi FCG is
+    CG on the Jacobi-scaled system), and the benchmark's reduced solves with and without
+    five network applications in front (learned-rb vs mixed-rb)."""
+    t0 = time.perf_counter()
+    net, info = train_network(rt, torch, sy, n_fields, epochs)
+    untrained = rt.Net(seed=12345)
+    wl0 = sy.make_workload("c4-eval", 256, 128, 256, 64, 100.0, eval_seeds[0])
+    ctx = rt.Context.from_workload(wl0)
+    rows = []
+    modes = {"learned_fcg": (rt.MODE_LEARNED, net, fcg_budget, 0),
+             "untrained_fcg": (rt.MODE_LEARNED, untrained, fcg_budget, 0),
+             "jacobi_cg_fp64": (rt.MODE_FP64, None, 0, 0),
+             "learned_rb_5": (rt.MODE_LEARNED, net, 5, 1),
+             "mixed_rb": (rt.MODE_MIXED, None, 0, 1)}
+    for seed in eval_seeds:
+        wl = wl0 if seed == eval_seeds[0] else sy.make_workload("c4-eval", 256, 128, 256, 64, 100.0, seed)
+        En, _ = prepared_system(ctx, torch, sy, wl)
+        row = {"seed": seed}
+        for name, (m, nt, budget, red) in modes.items():
+            E = En.clone()
+            o = rt.solve_opts(m, tol=1e-8, max_iter=200000, net=nt, inner_max_iter=budget, reduce=red)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rc, st = ctx.solve(E, o, raise_on_error=False)
+            torch.cuda.synchronize()
+            row[name] = {"s": time.perf_counter() - t, "iters": st["iters"],
+                         "network_applications": st["precond_applies"], "handover": st["handover"],
+                         "fallback": st["fallback"], "relres": st["relres"], "status": rc}
+            log(f"c4 seed {seed} {name}: {row[name]}")
+        rows.append(row)
+
+    def med(name, key):
+        return statistics.median([r[name][key] for r in rows])
+    summary = {name: {"median_s": med(name, "s"), "median_iters": med(name, "iters"),
+                      "median_network_applications": med(name, "network_applications"),
+                      "reached_tol_without_handover": sum(1 for r in rows if r[name]["handover"] == 0)}
+               for name in modes}
+    return {"what": "config 4: network trained on 128x64x64 fields, evaluated on unseen seeds at 256x128x256, "
+                    "tau550 = 100, 64 bins; seconds and iterations to relative residual 1e-8",
+            "training": info, "fcg_budget": fcg_budget, "eval_seeds": list(eval_seeds), "summary": summary,
+            "fields": rows, "total_s": time.perf_counter() - t0}
+
+
 def unet_forward_ms(ctx, net, torch, reps=3):
     """Average duration of one network application on the context's grid (HIP events on
     the stream the kernels run on)."""
@@ -174,7 +247,8 @@ def run_mode(ctx, rt, torch, rho, T0, mode, steps, warmup, tol, inner_tol, max_i
         stats.append(st)
         log(f"[{mode}] step {k}: total {st['ms_total']:.1f} ms, raytrace {st['ms_raytrace']:.2f} ms, "
             f"solve {st['solve']['ms']:.1f} ms ({st['solve']['iters']} it, {st['solve']['outer_iters']} outer, "
-            f"{st['solve']['precond_applies']} network applications, fallback {st['solve']['fallback']}, "
+            f"{st['solve']['precond_applies']} network applications, handover {st['solve']['handover']}, "
+            f"fallback {st['solve']['fallback']}, "
             f"relres {st['solve']['relres']:.2e}, reduced {st['solve']['reduced']}), "
             f"dir {st['solve']['ms_dir']*1e3:.1f} us, black {st['solve']['ms_black']*1e3:.1f} us, "
             f"upd {st['solve']['ms_upd']*1e3:.1f} us")
@@ -190,10 +264,11 @@ def run_successive(ctx, rt, torch, rho, T0, mode, nsteps, tol, inner_tol, max_it
     for k in range(nsteps):
         rc, st = ctx.step(rho, T, E, opts, raise_on_error=False)
         s = st["solve"]
-        out.append({"iters": s["iters"], "solve_s": s["ms"] / 1e3, "relres": s["relres"],
-                    "fallback": s["fallback"], "status": rc})
-        log(f"[{mode}] successive step {k}: solve {s['ms']:.1f} ms, {s['iters']} it, relres {s['relres']:.2e}, "
-            f"status {rc}")
+        out.append({"step": k + 1, "iters": s["iters"], "solve_s": s["ms"] / 1e3, "step_s": st["ms_total"] / 1e3,
+                    "relres": s["relres"], "fallback": s["fallback"], "status": rc,
+                    "T_max": float(T.max()), "T_mean": float(T.mean())})
+        log(f"[{mode}] successive step {k + 1}: solve {s['ms']:.1f} ms, {s['iters']} it, relres {s['relres']:.2e}, "
+            f"fallback {s['fallback']}, status {rc}")
     return out
 
 
@@ -275,9 +350,27 @@ def rosseland_depth_rate(ctx, torch, rho, T, reps=5):
             "bytes": nbytes, "tau_R_midplane_r_in": float(tau.view(npp, nt, nr + 1)[0, nt // 2, 0])}
 
 
+def _host_info():
+    """nproc and the CPU model (lscpu) of the host the baseline ran on."""
+    import subprocess
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["nproc"] = int(subprocess.run(["nproc"], capture_output=True, text=True, timeout=10).stdout.strip())
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)",
+                             "CPU max MHz"):
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError, ValueError):
+        pass
+    return info
+
+
 def oracle_baseline(wl, gpu_fp64_iters, slab=16, cg_iters=1000):
-    """The oracle on a phi-slab of the workload: ray trace and a fixed number of CG
-    iterations, scaled to the full grid and to the GPU float64 iteration count."""
+    """The serial oracle (one core) on a phi-slab of the workload: ray trace, Newton,
+    assembly and a fixed number of CG iterations, scaled to the full grid and to the GPU
+    float64 iteration count."""
     import numpy as np
 
     import oracle
@@ -309,10 +402,53 @@ def oracle_baseline(wl, gpu_fp64_iters, slab=16, cg_iters=1000):
                 raytrace_gcell_nu=P.n * wl.opacity.kappa.shape[1] / t_rt / 1e9,
                 phases_s_full_grid={"raytrace": t_rt * scale, "assemble": t_as * scale, "newton": t_nw * scale,
                                     "cg_iteration": per_iter_full},
-                sample=f"oracle on a {g.shape[0]}x{g.shape[1]}x{slab} phi-slab of the workload "
+                sample=f"serial oracle on a {g.shape[0]}x{g.shape[1]}x{slab} phi-slab of the workload "
                        f"({P.n} cells, 1/{scale:.0f} of the grid): one ray trace ({t_rt:.1f} s) and "
                        f"{it} float64 CG iterations ({t_cg:.1f} s); solve s/step = time per iteration "
                        f"x {scale:.0f} x the GPU float64 iteration count ({gpu_fp64_iters})")
+
+
+def oracle_full_grid(wl, cg_iters=40):
+    """The OpenMP oracle on all host cores, whole grid: its own prepared state (ray trace
+    at T_bc, Newton with E = a T_bc^4), the step's ray trace, E^n and assembly, and
+    cg_iters float64 CG iterations, each phase timed.  Returns the oracle problem, its
+    state and the timings."""
+    import numpy as np
+
+    import oracle
+    from paper_1001_3301_amd import synth as sy
+    P = oracle.Problem.from_workload(wl, parallel=True)
+    rho = wl.rho.ravel()
+    tm = {}
+    t = time.perf_counter()
+    _, S, _ = P.raytrace(rho, np.full(P.n, wl.T_bc), want_faces=False)
+    tm["raytrace"] = time.perf_counter() - t
+    t = time.perf_counter()
+    T0 = P.newton(np.full(P.n, sy.A_RAD * wl.T_bc ** 4), S, np.full(P.n, wl.T_bc))
+    tm["newton"] = time.perf_counter() - t
+    q, S, _ = P.raytrace(rho, T0, want_faces=False)
+    En = P.energy(T0, S)
+    t = time.perf_counter()
+    sysd = P.assemble(rho, T0, En, q)
+    tm["assemble"] = time.perf_counter() - t
+    for k in ("w", "d", "b"):
+        del sysd[k]
+    t = time.perf_counter()
+    _, _, it, _ = P.cg(sysd["ahat"], sysd["bhat"], En / sysd["s"], 1e-30, cg_iters)
+    tm["cg_iteration"] = (time.perf_counter() - t) / max(it, 1)
+    return P, dict(T0=T0, S=S, q=q, En=En, **sysd), tm, oracle.threads()
+
+
+def oracle_check(P, O, E, T):
+    """The oracle's residual of the GPU's E on the oracle's own assembled system, and the
+    largest relative difference between the GPU's temperature and the oracle's Newton
+    step from that E (with the oracle's S and T^n), over every cell."""
+    import numpy as np
+    Eg = E.cpu().numpy()
+    res = P.relres(O["ahat"], O["bhat"], Eg / O["s"])
+    Tn = P.newton(Eg, O["S"], O["T0"])
+    Tg = T.cpu().numpy()
+    return {"oracle_relres": float(res), "T_vs_oracle_newton_max_rel": float(np.max(np.abs(Tg - Tn) / Tn))}
 
 
 def main():
@@ -334,8 +470,16 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=200000)
-    ap.add_argument("--successive", type=int, default=0,
+    ap.add_argument("--successive", type=int, default=5,
                     help="also run this many successive steps of the headline mode (not timed for value)")
+    ap.add_argument("--other-steps", type=int, default=3,
+                    help="timed steps of each non-headline mode (at most --steps; warm-up at most 1)")
+    ap.add_argument("--c4-gain", action="store_true",
+                    help="run only the config-4 gain evaluation (200 training fields at 128x64x64, unseen "
+                         "256x128x256 seeds) and print its JSON")
+    ap.add_argument("--c4-fields", type=int, default=200)
+    ap.add_argument("--no-oracle-check", action="store_true",
+                    help="skip the whole-grid oracle check of every mode's answer")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-main-loop", action="store_true", help="skip the main-loop runs to equilibrium")
     ap.add_argument("--launch", choices=list(LAUNCH), default="auto",
@@ -352,10 +496,14 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     from paper_1001_3301_amd import rt, synth as sy
     torch.cuda.set_device(0)
+    if args.c4_gain:
+        print(json.dumps(c4_gain(rt, torch, sy, n_fields=args.c4_fields, epochs=args.train_epochs)), flush=True)
+        return
     t = time.perf_counter()
     c = sy.CONFIGS[args.config]
     wl = sy.make_workload(args.config, c["nr"], c["nt"], c["nph"], c["n_nu"], c["taus"][-1],
@@ -397,9 +545,11 @@ def main():
                 net.save(args.save_net)
         log(f"network: {train_info}")
     results = {}
-    for mode in modes:
+    for mi, mode in enumerate(modes):
         budget = args.learned_rb_budget if mode == "learned-rb" else args.learned_budget
-        results[mode] = run_mode(ctx, rt, torch, rho, T0, mode, args.steps, args.warmup, args.tol,
+        steps = args.steps if mi == 0 else min(args.steps, args.other_steps)
+        warm = args.warmup if mi == 0 else min(args.warmup, 1)
+        results[mode] = run_mode(ctx, rt, torch, rho, T0, mode, steps, warm, args.tol,
                                  args.inner_tol, args.max_iter, net, budget)
 
     head = modes[0]
@@ -471,6 +621,7 @@ def main():
         fwd_ms = unet_forward_ms(ctx, net, torch)
         tflops = UNET_FLOP_PER_CELL * n / (fwd_ms / 1e3) / 1e12
         out["learned"] = {"mode": lm, "network_applications": Rl["precond_applies"], "fallback": Rl["fallback"],
+                          "handover": Rl["handover"],
                           "total_iters": Rl["iters"],
                           "budget": args.learned_rb_budget if lm == "learned-rb" else args.learned_budget,
                           "training": train_info, "unet_forward_ms": fwd_ms,
@@ -481,7 +632,8 @@ def main():
         for m in learned_modes[1:]:
             Rm = results[m]["stats"][-1]["solve"]
             out["learned"][m] = {"network_applications": Rm["precond_applies"], "total_iters": Rm["iters"],
-                                 "reduced_finish": Rm["reduced"]}
+                                 "reduced_finish": Rm["reduced"], "handover": Rm["handover"],
+                                 "fallback": Rm["fallback"]}
         if head.startswith("learned"):  # the network is the part of this mode the GPU is asked to run fast
             out["roofline"] = dict(out["learned"]["unet_roofline"], traffic=None)
     if "fp64" in modes:
@@ -494,21 +646,55 @@ def main():
                 out[f"E_rel_diff_{mode}_vs_fp64"] = float(((Rm["E"] - Ef).abs() / Ef.abs()).max())
                 out[f"thermal_force_diff_{mode}_vs_fp64"] = float(
                     (Rm["f"].view(4, -1)[1:] - ff[1:]).abs().max() / thermal)
-    if args.successive > 0:
-        out["successive_steps"] = run_successive(ctx, rt, torch, rho, T0, head, args.successive, args.tol,
-                                                 args.inner_tol, args.max_iter, net, args.learned_budget)
     out["rosseland_depth"] = rosseland_depth_rate(ctx, torch, rho, T0)
+    full = None
+    if not args.no_oracle_check or not args.no_cpu_baseline:
+        t = time.perf_counter()
+        full = oracle_full_grid(wl)
+        log(f"oracle on the whole grid ({full[3]} threads): {full[2]}, {time.perf_counter() - t:.1f} s")
+    if not args.no_oracle_check:
+        P, O = full[0], full[1]
+        chk = {"what": "the oracle's own prepared state and assembled system (OpenMP build, whole grid); for each "
+                       "mode the oracle's relative residual of the GPU's E and the largest relative difference "
+                       "between the GPU's temperature and the oracle's Newton step from that E",
+               "prepared_T_max_rel": float(np.max(np.abs(T0.cpu().numpy() - O["T0"]) / O["T0"]))}
+        for mode in modes:
+            chk[mode] = oracle_check(P, O, results[mode]["E"], results[mode]["T"])
+            log(f"oracle check {mode}: {chk[mode]}")
+        out["oracle_check"] = chk
+    for mode in modes:
+        del results[mode]["T"], results[mode]["E"], results[mode]["f"]
+    if args.successive > 0:
+        seq = run_successive(ctx, rt, torch, rho, T0, head, args.successive, args.tol, args.inner_tol,
+                             args.max_iter, net, args.learned_budget)
+        out["successive_steps"] = {
+            "what": f"{args.successive} successive radiation steps of the headline mode ({head}) at dt = "
+                    f"{wl.dt:g} s, each from the previous step's temperature (the timed steps above all "
+                    f"repeat step 1); solve seconds and iterations per step",
+            "mode": head, "steps": seq, "solve_s_total": sum(x["solve_s"] for x in seq),
+            "iters": [x["iters"] for x in seq]}
     if not args.no_main_loop:
         out["main_iteration"] = run_main_loop(rt, torch, sy)
     if not args.no_cpu_baseline:
         fp64_iters = out.get("fp64_iters_per_step", out["solve_iters_per_step"])
         t = time.perf_counter()
         cb = oracle_baseline(wl, fp64_iters)
-        log(f"cpu baseline took {time.perf_counter() - t:.1f} s")
-        out["cpu_baseline"] = {"value": cb["solve_s_per_step"], "unit": "s/step", "cores": 1,
-                               "kind": "oracle", "sample": cb["sample"],
-                               "raytrace_gcell_nu_per_s": cb["raytrace_gcell_nu"],
-                               "phases_s_full_grid": cb["phases_s_full_grid"]}
+        log(f"cpu baseline (one core) took {time.perf_counter() - t:.1f} s")
+        tm, thr = full[2], full[3]
+        host = _host_info()
+        out["cpu_baseline"] = {
+            "value": tm["cg_iteration"] * fp64_iters, "unit": "s/step", "cores": thr, "kind": "oracle",
+            "sample": f"OpenMP oracle on {thr} threads, whole {wl.grid.shape[0]}x{wl.grid.shape[1]}x"
+                      f"{wl.grid.shape[2]} grid: ray trace, Newton, assembly and 40 float64 CG iterations; "
+                      f"solve s/step = time per CG iteration x the GPU float64 iteration count ({fp64_iters}), "
+                      f"the plain method (the oracle has no reduced or mixed-precision solve)",
+            "phases_s": {"raytrace": tm["raytrace"], "newton": tm["newton"], "assemble": tm["assemble"],
+                         "cg_iteration": tm["cg_iteration"]},
+            "raytrace_gcell_nu_per_s": n * c["n_nu"] / tm["raytrace"] / 1e9,
+            "host": host,
+            "single_core": {"value": cb["solve_s_per_step"], "unit": "s/step", "cores": 1, "sample": cb["sample"],
+                            "raytrace_gcell_nu_per_s": cb["raytrace_gcell_nu"],
+                            "phases_s_full_grid": cb["phases_s_full_grid"]}}
     print(json.dumps(out), flush=True)
 
 
