@@ -422,6 +422,22 @@ rt_status rt_nn_conv3d_bwd_data(void *stream, int nr, int nt, int np, const floa
 /* Weight and bias gradients (fp32, dw[27][cout][c1+c2], db[cout]); cout <= 64; synchronises. */
 rt_status rt_nn_conv3d_bwd_weight(void *stream, int nr, int nt, int np, const float *dy, const void *yrelu, int cout,
                                   const void *x1, int c1, int up1, const void *x2, int c2, float *dw, float *db);
+/* rt_nn_conv3d_bwd_weight for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and arguments, with the per-block partial sums in a static device array of
+ * 8,388,608 floats (32 MiB, one copy per device, held until the process ends) instead
+ * of a buffer allocated per call.  Calls no hipMalloc / hipFree and does not
+ * synchronise: the work is enqueued on `stream`.  RT_EINVAL when the layer needs more
+ * partial sums than that: 27 * cout * (c1 + c2) floats per block of the weight-gradient
+ * grid (min(256, number of 32 x 2 x 2-cell tiles) blocks), and ceil(n / 2048) * cout for
+ * the bias; so every layer with cout * (c1 + c2) <= 1024 (16 x 16 ... 16 x 48, 32 x 32)
+ * fits at any grid size up to 268 M cells, wider ones only on grids of fewer tiles
+ * (64 x 64: at most 75).  Every call on a device shares that device's array: calls that
+ * overlap on one device (different streams without ordering, several host threads) race
+ * and must be serialised by the caller. */
+rt_status rt_nn_conv3d_bwd_weight_noalloc(void *stream, int nr, int nt, int np, const float *dy, const void *yrelu,
+                                          int cout, const void *x1, int c1, int up1, const void *x2, int c2, float *dw,
+                                          float *db);
 
 #ifdef __cplusplus
 }

@@ -6,7 +6,9 @@
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <string>
 
 #include "rt_internal.h"
 
@@ -508,6 +510,63 @@ rt_status rt_nn_conv3d_bwd_weight(void *stream, int nr, int nt, int np, const fl
     }
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
     (void)hipFree(part);
+    if (e != hipSuccess) return nfail(nullptr, RT_EDEVICE, hipGetErrorString(e));
+    return RT_OK;
+}
+
+// Scratch of rt_nn_conv3d_bwd_weight_noalloc: the per-block partial sums of the weight
+// gradient, then of the bias gradient (every float the kernels read is written first in
+// the same call, so nothing needs clearing).  Each device holds its own copy until the
+// process ends; host code uses the device address from hipGetSymbolAddress, never the
+// array's name.
+constexpr long kWgradScratchFloats = 8L << 20;  // 32 MiB
+static __device__ __align__(256) float scratch[kWgradScratchFloats];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch[kMaxDevices] = {};
+
+// The current device's address of `scratch`, looked up once per device.
+rt_status scratch_ptr(float **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return nfail(nullptr, RT_EDEVICE, "rt_nn_conv3d_bwd_weight_noalloc: no usable current device");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return nfail(nullptr, RT_EDEVICE, std::string("rt_nn_conv3d_bwd_weight_noalloc: hipGetSymbolAddress: ") +
+                                                  hipGetErrorString(e));
+        g_scratch[dev] = static_cast<float *>(p);
+    }
+    *out = g_scratch[dev];
+    return RT_OK;
+}
+}  // namespace
+
+rt_status rt_nn_conv3d_bwd_weight_noalloc(void *stream, int nr, int nt, int np, const float *dy, const void *yrelu,
+                                          int cout, const void *x1, int c1, int up1, const void *x2, int c2, float *dw,
+                                          float *db)
+{
+    if (nr < 1 || nt < 1 || np < 1 || !dy || cout % 16 || cout < 16 || cout > 64 || !x1 || c1 % 16 || c2 % 16 ||
+        c1 < 16 || (c2 && !x2) || !dw || !db || (up1 && (nr % 2 || nt % 2 || np % 2)))
+        return nfail(nullptr, RT_EINVAL, "rt_nn_conv3d_bwd_weight_noalloc: bad arguments");
+    Lv L{nr, nt, np, (long)nr * nt * np};
+    const long need = nn::wgrad_part_floats(L, cout, c1 + c2);
+    if (need > kWgradScratchFloats)
+        return nfail(nullptr, RT_EINVAL,
+                     "rt_nn_conv3d_bwd_weight_noalloc: the layer needs " + std::to_string(need) +
+                         " floats of partial sums, more than the " + std::to_string(kWgradScratchFloats) +
+                         " of the static scratch (use rt_nn_conv3d_bwd_weight)");
+    float *part = nullptr;
+    if (rt_status e = scratch_ptr(&part)) return e;
+    if (!conv_bwd_weight(L, dy, (const bf16 *)yrelu, cout, (const bf16 *)x1, c1, up1, (const bf16 *)x2, c2, part, dw,
+                         db, (hipStream_t)stream))
+        return nfail(nullptr, RT_EINVAL, "rt_nn_conv3d_bwd_weight_noalloc: unsupported channel counts");
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return nfail(nullptr, RT_EDEVICE, hipGetErrorString(e));
     return RT_OK;
 }

@@ -102,7 +102,8 @@ EXPORTS = ["rt_create", "rt_destroy", "rt_last_error", "rt_ncell", "rt_star_bin_
            "rt_net_get_params", "rt_net_get_grads", "rt_net_set_params", "rt_net_save", "rt_net_load",
            "rt_net_forward", "rt_net_apply", "rt_net_loss_grad", "rt_net_loss_grad_resid", "rt_net_adam", "rt_dataset_create",
            "rt_dataset_destroy", "rt_dataset_size", "rt_dataset_add", "rt_dataset_add_learned", "rt_net_train",
-           "rt_nn_conv3d_fwd", "rt_nn_conv3d_bwd_data", "rt_nn_conv3d_bwd_weight"]
+           "rt_nn_conv3d_fwd", "rt_nn_conv3d_bwd_data", "rt_nn_conv3d_bwd_weight",
+           "rt_nn_conv3d_bwd_weight_noalloc"]
 
 
 LOSS_ERROR, LOSS_RESIDUAL = 0, 1
@@ -188,6 +189,7 @@ def lib():
     L.rt_nn_conv3d_fwd.argtypes = [vp, ip, ip, ip, vp, ip, ip, vp, ip, vp, vp, ip, ip, vp, vp]
     L.rt_nn_conv3d_bwd_data.argtypes = [vp, ip, ip, ip, vp, vp, ip, vp, ip, vp, ip, vp]
     L.rt_nn_conv3d_bwd_weight.argtypes = [vp, ip, ip, ip, vp, vp, ip, vp, ip, ip, vp, ip, vp, vp]
+    L.rt_nn_conv3d_bwd_weight_noalloc.argtypes = [vp, ip, ip, ip, vp, vp, ip, vp, ip, ip, vp, ip, vp, vp]
     _lib = L
     return L
 
@@ -575,11 +577,14 @@ def nn_conv_bwd_data(shape, dy, yrelu, cout, wt, c1, d1, c2=0, d2=None):
         raise RtError(st, lib().rt_net_last_error(None).decode())
 
 
-def nn_conv_bwd_weight(shape, dy, yrelu, cout, x1, c1, up1, x2, c2, dw, db):
+def nn_conv_bwd_weight(shape, dy, yrelu, cout, x1, c1, up1, x2, c2, dw, db, noalloc=False):
+    """rt_nn_conv3d_bwd_weight, or (noalloc=True) its allocation-free variant, which only
+    enqueues on torch's current stream."""
     import torch
     nr, nt, npp = shape
-    st = lib().rt_nn_conv3d_bwd_weight(C.c_void_p(torch.cuda.current_stream().cuda_stream), nr, nt, npp, _vp(dy),
-                                       _vp(yrelu), cout, _vp(x1), c1, int(up1), _vp(x2), c2, _vp(dw), _vp(db))
+    fn = lib().rt_nn_conv3d_bwd_weight_noalloc if noalloc else lib().rt_nn_conv3d_bwd_weight
+    st = fn(C.c_void_p(torch.cuda.current_stream().cuda_stream), nr, nt, npp, _vp(dy), _vp(yrelu), cout, _vp(x1),
+            c1, int(up1), _vp(x2), c2, _vp(dw), _vp(db))
     if st != RT_OK:
         raise RtError(st, lib().rt_net_last_error(None).decode())
 
