@@ -208,20 +208,26 @@ def c4_gain(rt, torch, sy, n_fields=200, eval_seeds=(10000, 10001, 10002, 10003,
 
 def unet_forward_ms(ctx, net, torch, reps=3):
     """Average duration of one network application on the context's grid (HIP events on
-    the stream the kernels run on)."""
+    the stream the kernels run on): the forward pass on a prepared input (rt_net_forward)
+    and the preconditioner's action on a residual as the learned solve applies it
+    (rt_net_apply: the scaling reduction, the input built inside the first convolution,
+    the forward pass, the output scaled back)."""
     n = ctx.n
     X = (torch.randn(n * 16, device="cuda") * 0.5).to(torch.bfloat16)
+    r = torch.randn(n, device="cuda")
     z = torch.empty(n, dtype=torch.float32, device="cuda")
-    net.forward(ctx, X, z)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        net.forward(ctx, X, z)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    del X, z
-    return ms
+    out = {}
+    for name, fn in (("forward", lambda: net.forward(ctx, X, z)), ("apply", lambda: net.apply(ctx, r, z))):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / reps
+    del X, r, z
+    return out
 
 
 def run_mode(ctx, rt, torch, rho, T0, mode, steps, warmup, tol, inner_tol, max_iter, net=None, budget=0):
@@ -618,13 +624,14 @@ def main():
     if learned_modes:
         lm = learned_modes[0]
         Rl = results[lm]["stats"][-1]["solve"]
-        fwd_ms = unet_forward_ms(ctx, net, torch)
+        tm = unet_forward_ms(ctx, net, torch)
+        fwd_ms = tm["forward"]
         tflops = UNET_FLOP_PER_CELL * n / (fwd_ms / 1e3) / 1e12
         out["learned"] = {"mode": lm, "network_applications": Rl["precond_applies"], "fallback": Rl["fallback"],
                           "handover": Rl["handover"],
                           "total_iters": Rl["iters"],
                           "budget": args.learned_rb_budget if lm == "learned-rb" else args.learned_budget,
-                          "training": train_info, "unet_forward_ms": fwd_ms,
+                          "training": train_info, "unet_forward_ms": fwd_ms, "unet_apply_ms": tm["apply"],
                           "unet_roofline": {"kernel": "U-Net forward (k_conv_fwd and pooling, whole network)",
                                             "bound": "mfma", "achieved": tflops, "peak": PEAK_BF16_TFLOPS,
                                             "unit": "TFLOP/s", "frac": tflops / PEAK_BF16_TFLOPS,

@@ -550,15 +550,6 @@ __global__ void k_rms_scale(long n, const DevScalars *sc, double *scale)
     }
 }
 
-// z = zn * scale[1] (undo the input scaling; the network map is taken as positively
-// homogeneous of degree one).
-__global__ __launch_bounds__(kKB) void k_unscale(long n, const float *__restrict__ zn, const double *__restrict__ scale,
-                                                 float *__restrict__ z)
-{
-    long c = (long)blockIdx.x * kKB + threadIdx.x;
-    if (c < n) z[c] = (float)((double)zn[c] * scale[1]);
-}
-
 // y += x32 (float64 accumulation of the float32 partial solution).
 __global__ __launch_bounds__(kKB) void k_fold(long n, const float *__restrict__ x32, double *__restrict__ y)
 {
@@ -754,11 +745,6 @@ void launch_norm2_rr32(const Dims &d, int nblk, const float *x, double *partials
 void launch_rms_scale(long n, const DevScalars *sc, double *scale, hipStream_t st)
 {
     hipLaunchKernelGGL(k_rms_scale, dim3(1), dim3(64), 0, st, n, sc, scale);
-}
-
-void launch_unscale(long n, const float *zn, const double *scale, float *z, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_unscale, dim3((unsigned)((n + kKB - 1) / kKB)), dim3(kKB), 0, st, n, zn, scale, z);
 }
 
 void launch_fold(long n, const float *x32, double *y, hipStream_t st)

@@ -142,7 +142,7 @@ __device__ __forceinline__ unsigned pack_bf16(float a, float b)
 }
 
 // Body shared by the forward (sign = +1) and data-gradient (sign = -1: the output cell
-// whose tap reads this cell) convolutions.  load(idx, a, b, c, ch) returns 8 bf16
+// whose tap reads this cell) convolutions.  load(idx, a, b, c, ch, ok) returns 8 bf16
 // channels ch .. ch + 7 of input cell idx = (a, b, c); store(idx, ch, v) writes output
 // channels ch .. ch + 3.  w is [tap][cout][cin] in bf16.
 //
@@ -182,18 +182,19 @@ __device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__r
     for (int q = 0; q < PW; q++)
 #pragma unroll
         for (int t = 0; t < NT; t++) acc[q][t] = float4v{0.f, 0.f, 0.f, 0.f};
-    int s = 0;
-    bool first = true;
-    for (;;) {
-        // global loads of the item (tile, slice s), all issued before the LDS stores;
-        // cells outside the grid read cell 0 and are replaced by zeros
+    // the global loads of item (tile t, slice sl) into registers, all issued before the
+    // LDS stores; load(idx, a, b, c, ch, ok) returns 8 channels of cell (a, b, c), or
+    // zeros where !ok (cells outside the grid, which arrive as (0, 0, 0)).  A native
+    // vector type with compile-time indices, so the staging stays in registers (the HIP
+    // uint4 struct made the compiler keep such arrays in scratch memory).
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    auto fetch = [&](long t, int sl, u32x4 (&vv)[NL]) __attribute__((always_inline)) {
         // tile order: theta fastest, then phi, then r, so the blocks resident together
         // share their theta halos and the next wave of blocks finds its phi halo plane in L2
-        const int tj = (int)(tile % ntj), tk = (int)((tile / ntj) % ntk), tr = (int)(tile / ((long)ntj * ntk));
+        const int tj = (int)(t % ntj), tk = (int)((t / ntj) % ntk), tr = (int)(t / ((long)ntj * ntk));
         const int r0 = tr * kTR, j0 = tj * TJ, k0 = tk * TK;
-        uint4 v[NL];
-#pragma unroll
-        for (int u = 0; u < NL; u++) {
+        static_for<0, NL>([&](auto uc) __attribute__((always_inline)) {
+            constexpr int u = decltype(uc)::value;
             const int q = tid + u * kTB;
             const int cell = q >> 1, h = q & 1;
             const int hr = cell % T::HR, hj = (cell / T::HR) % T::HJ, hk = cell / (T::HR * T::HJ);
@@ -202,32 +203,50 @@ __device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__r
             const bool ok = q < T::cells * 2 && (unsigned)a < (unsigned)L.nr && (unsigned)b < (unsigned)L.nt &&
                             (unsigned)c < (unsigned)L.np;
             if (!ok) a = b = c = 0;
-            const uint4 x = load(a + (long)L.nr * (b + (long)L.nt * c), a, b, c, s * 16 + h * 8);
-            v[u] = ok ? x : make_uint4(0u, 0u, 0u, 0u);
-        }
-        __syncthreads();  // the previous item's MFMAs are done with the LDS tiles
-#pragma unroll
-        for (int u = 0; u < NL; u++) {
+            vv[u] = load(a + (long)L.nr * (b + (long)L.nt * c), a, b, c, sl * 16 + h * 8, ok);
+        });
+    };
+    auto put = [&](const u32x4 (&vv)[NL]) __attribute__((always_inline)) {
+        static_for<0, NL>([&](auto uc) __attribute__((always_inline)) {
+            constexpr int u = decltype(uc)::value;
             const int q = tid + u * kTB;
-            if (q < T::cells * 2) *reinterpret_cast<uint4 *>(lds + ((q & 1) * T::cells + (q >> 1)) * 16) = v[u];
+            if (q < T::cells * 2) *reinterpret_cast<u32x4 *>(lds + ((q & 1) * T::cells + (q >> 1)) * 16) = vv[u];
+        });
+    };
+    int s = 0;
+    bool first = true;
+    for (;;) {
+        const long cur = tile;
+        const int cs = s;
+        {
+            u32x4 v[NL];
+            fetch(cur, cs, v);
+            __syncthreads();  // the previous item's MFMAs are done with the LDS tiles
+            put(v);
         }
         if (first || nslice > 1) {
-            uint4 wr[NW];
+            // a native vector type, so all NW loads stay in registers and fly together
+            typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+            u32x4 wr[NW];
 #pragma unroll
             for (int u = 0; u < NW; u++) {
                 const int q = min(tid + u * kTB, 27 * NT * 32 - 1);
                 const int l32 = q & 31, tt = (q >> 5) % NT, tap = q / (32 * NT);
-                const int co = tt * 16 + (l32 & 15), ci = s * 16 + (l32 >> 4) * 8;
-                wr[u] = *reinterpret_cast<const uint4 *>(w + ((long)tap * cout + co) * cin + ci);
+                const int co = tt * 16 + (l32 & 15), ci = cs * 16 + (l32 >> 4) * 8;
+                wr[u] = *reinterpret_cast<const u32x4 *>(w + ((long)tap * cout + co) * cin + ci);
             }
 #pragma unroll
             for (int u = 0; u < NW; u++) {
                 const int q = tid + u * kTB;
-                if (q < 27 * NT * 32) *reinterpret_cast<uint4 *>(ws + q * 16) = wr[u];
+                if (q < 27 * NT * 32) *reinterpret_cast<u32x4 *>(ws + q * 16) = wr[u];
             }
         }
         first = false;
         __syncthreads();
+        if (++s == nslice) {
+            s = 0;
+            tile += per;
+        }
         // Tap pairs p = 0 .. 13, software-pipelined: the LDS fragments of pair p + 1 are
         // requested before the MFMAs of pair p are issued.
         auto frags = [&](auto pc, bf16x8 (&bf)[PW], bf16x8 (&af)[NT]) {
@@ -263,7 +282,9 @@ __device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__r
             mma(b1, a1);
             __builtin_amdgcn_sched_barrier(0);
         });
-        if (s == nslice - 1) {
+        if (cs == nslice - 1) {
+            const int tj = (int)(cur % ntj), tk = (int)((cur / ntj) % ntk), tr = (int)(cur / ((long)ntj * ntk));
+            const int r0 = tr * kTR, j0 = tj * TJ, k0 = tk * TK;
 #pragma unroll
             for (int q = 0; q < PW; q++) {
                 const int a = r0 + (q & 1) * 16 + (lane & 15), b = j0 + jw + (q >> 1), c = k0 + kw;
@@ -276,11 +297,7 @@ __device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__r
                 for (int t = 0; t < NT; t++) acc[q][t] = float4v{0.f, 0.f, 0.f, 0.f};
             }
         }
-        if (++s == nslice) {
-            s = 0;
-            tile += per;
-            if (tile >= t_end) break;
-        }
+        if (tile >= t_end) break;
     }
 }
 
@@ -294,25 +311,66 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     const bf16 *__restrict__ w, const float *__restrict__ bias, int relu, bf16 *__restrict__ y, float *__restrict__ yf)
 {
     const int cr = L.nr >> 1, ct = L.nt >> 1;
-    auto load = [&](long idx, int a, int b, int c, int ch) -> uint4 {
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    auto load = [&](long idx, int a, int b, int c, int ch, bool ok) -> u32x4 {
+        const bf16 *p;
         if (ch < c1) {
             const long e = up1 ? (a >> 1) + (long)cr * ((b >> 1) + (long)ct * (c >> 1)) : idx;
-            return *reinterpret_cast<const uint4 *>(x1 + e * c1 + ch);
+            p = x1 + e * c1 + ch;
+        } else {
+            p = x2 + idx * c2 + (ch - c1);
         }
-        return *reinterpret_cast<const uint4 *>(x2 + idx * c2 + (ch - c1));
+        const u32x4 x = *reinterpret_cast<const u32x4 *>(p);
+        return ok ? x : u32x4{0u, 0u, 0u, 0u};
     };
     const int cout = NT * 16;
-    auto store = [&](long idx, int co, const float4v &v) {
-        const float4 bb = bias ? *reinterpret_cast<const float4 *>(bias + co) : make_float4(0.f, 0.f, 0.f, 0.f);
-        float o[4] = {v[0] + bb.x, v[1] + bb.y, v[2] + bb.z, v[3] + bb.w};
-        if (relu) {
+    // the bias of this lane's output channels t 16 + 4 (lane / 16) .. + 3 of each output
+    // tile t, loaded once (the epilogue then waits for no memory)
+    float4 bsel[NT];
 #pragma unroll
-            for (int i = 0; i < 4; i++) o[i] = o[i] > 0.0f ? o[i] : (o[i] == o[i] ? 0.0f : o[i]);
+    for (int t = 0; t < NT; t++)
+        bsel[t] = bias ? *reinterpret_cast<const float4 *>(bias + t * 16 + 4 * ((threadIdx.x & 63) >> 4))
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
+    auto store = [&](long idx, int co, const float4v &v) {
+        const float4 bb = bsel[co >> 4];
+        float o[4] = {v[0] + bb.x, v[1] + bb.y, v[2] + bb.z, v[3] + bb.w};
+        if (relu) {  // a select, no branch; NaN passes (the comparison is false)
+#pragma unroll
+            for (int i = 0; i < 4; i++) o[i] = o[i] < 0.0f ? 0.0f : o[i];
         }
         if (y) *reinterpret_cast<uint2 *>(y + idx * cout + co) = make_uint2(pack_bf16(o[0], o[1]), pack_bf16(o[2], o[3]));
         if (yf) *reinterpret_cast<float4 *>(yf + idx * cout + co) = make_float4(o[0], o[1], o[2], o[3]);
     };
     conv_tiles<NT, TJ, TK, 1>(L, c1 + c2, w, load, store);
+}
+
+// Layer 0 of the preconditioner's application with its input built on the fly: channel
+// 0 is the residual r (fp32) times scale[0] (to unit RMS) rounded to bf16, channels 1..7
+// come from X (the operator features of k_features and zeros; X's own channel 0 is not
+// read), channels 8..15 are zero and not loaded.  The same operands, bit for bit, as
+// k_set_input followed by k_conv_fwd<1,4,4> on X, without writing X (16 output
+// channels, bias, ReLU, bf16 out).
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_conv_fwd_in(
+    Lv L, const bf16 *__restrict__ X, const float *__restrict__ r, const double *__restrict__ scale,
+    const bf16 *__restrict__ w, const float *__restrict__ bias, bf16 *__restrict__ y)
+{
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    const double sc = scale[0];
+    auto load = [&](long idx, int, int, int, int ch, bool ok) -> u32x4 {
+        if (ch != 0) return u32x4{0u, 0u, 0u, 0u};
+        u32x4 x = *reinterpret_cast<const u32x4 *>(X + idx * 16);
+        const unsigned r0 = f2bf((float)((double)r[idx] * sc));
+        x[0] = (x[0] & 0xFFFF0000u) | r0;
+        return ok ? x : u32x4{0u, 0u, 0u, 0u};
+    };
+    const float4 bb = *reinterpret_cast<const float4 *>(bias + 4 * ((threadIdx.x & 63) >> 4));
+    auto store = [&](long idx, int co, const float4v &v) {
+        float o[4] = {v[0] + bb.x, v[1] + bb.y, v[2] + bb.z, v[3] + bb.w};
+#pragma unroll
+        for (int i = 0; i < 4; i++) o[i] = o[i] < 0.0f ? 0.0f : o[i];
+        *reinterpret_cast<uint2 *>(y + idx * 16 + co) = make_uint2(pack_bf16(o[0], o[1]), pack_bf16(o[2], o[3]));
+    };
+    conv_tiles<1, 4, 4, 1>(L, 16, w, load, store);
 }
 
 // ------------------------------------------------------------ data gradient
@@ -328,7 +386,8 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     Lv L, const float *__restrict__ dy, const bf16 *__restrict__ yout, int cout, const bf16 *__restrict__ wt, int c1,
     float *__restrict__ d1, int c2, float *__restrict__ d2)
 {
-    auto load = [&](long idx, int, int, int, int ch) -> uint4 {
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    auto load = [&](long idx, int, int, int, int ch, bool ok) -> u32x4 {
         const float4 g0 = *reinterpret_cast<const float4 *>(dy + idx * cout + ch);
         const float4 g1 = *reinterpret_cast<const float4 *>(dy + idx * cout + ch + 4);
         float f[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
@@ -339,7 +398,8 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             for (int q = 0; q < 8; q++)
                 if (!(bf2f(h[q]) > 0.0f)) f[q] = 0.0f;
         }
-        return make_uint4(pack_bf16(f[0], f[1]), pack_bf16(f[2], f[3]), pack_bf16(f[4], f[5]), pack_bf16(f[6], f[7]));
+        const u32x4 r{pack_bf16(f[0], f[1]), pack_bf16(f[2], f[3]), pack_bf16(f[4], f[5]), pack_bf16(f[6], f[7])};
+        return ok ? r : u32x4{0u, 0u, 0u, 0u};
     };
     auto store = [&](long idx, int ci, const float4v &v) {
         const float4 o = make_float4(v[0], v[1], v[2], v[3]);
@@ -570,14 +630,21 @@ __global__ __launch_bounds__(kTB) void k_up_bwd(Lv Lc, int C, const float *__res
 
 // z = w . x + b over 16 channels (fp32 out).
 __global__ __launch_bounds__(kTB) void k_out_fwd(long n, const bf16 *__restrict__ x, const bf16 *__restrict__ w,
-                                                 const float *__restrict__ b, float *__restrict__ z)
+                                                 const float *__restrict__ b, const double *__restrict__ scale,
+                                                 float *__restrict__ z)
 {
     long c = (long)blockIdx.x * kTB + threadIdx.x;
     if (c >= n) return;
+    // the cell's 16 channels as two 16-byte loads
+    const uint4 u0 = *reinterpret_cast<const uint4 *>(x + c * 16), u1 = *reinterpret_cast<const uint4 *>(x + c * 16 + 8);
+    const unsigned wd[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
     float s = b[0];
 #pragma unroll
-    for (int q = 0; q < 16; q++) s += bf2f(w[q]) * bf2f(x[c * 16 + q]);
-    z[c] = s;
+    for (int q = 0; q < 16; q++) s += bf2f(w[q]) * bf2f((bf16)(q & 1 ? wd[q >> 1] >> 16 : wd[q >> 1] & 0xFFFFu));
+    // scale != nullptr: the preconditioner's output scaled back by scale[1] (the input was
+    // scaled by scale[0] = 1 / scale[1]; the map is taken as positively homogeneous of
+    // degree one)
+    z[c] = scale ? (float)((double)s * scale[1]) : s;
 }
 
 // dx[c][q] = w[q] gz[c]; per-block partials of dw[q] = sum gz x[q] and db = sum gz.
@@ -885,9 +952,21 @@ void launch_up_bwd(const Lv &Lc, int C, const float *dyf, float *dxc, hipStream_
     hipLaunchKernelGGL(k_up_bwd, dim3(nblk(Lc.n * C)), dim3(kTB), 0, s, Lc, C, dyf, dxc);
 }
 
-void launch_out_fwd(long n, const bf16 *x, const bf16 *w, const float *b, float *z, hipStream_t s)
+void launch_out_fwd(long n, const bf16 *x, const bf16 *w, const float *b, const double *scale, float *z,
+                    hipStream_t s)
 {
-    hipLaunchKernelGGL(k_out_fwd, dim3(nblk(n)), dim3(kTB), 0, s, n, x, w, b, z);
+    hipLaunchKernelGGL(k_out_fwd, dim3(nblk(n)), dim3(kTB), 0, s, n, x, w, b, scale, z);
+}
+
+void launch_conv_fwd_in(const Lv &L, const bf16 *X, const float *r, const double *scale, const bf16 *w,
+                        const float *b, bf16 *y, hipStream_t s)
+{
+    constexpr size_t lds = conv_lds_bytes<1, 4, 4>();
+    static const bool attr = hipFuncSetAttribute((const void *)k_conv_fwd_in,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
+    (void)attr;
+    hipLaunchKernelGGL(k_conv_fwd_in, dim3(conv_grid<4, 4>(L, (const void *)k_conv_fwd_in, lds)), dim3(kTB), lds, s, L,
+                       X, r, scale, w, b, y);
 }
 
 // 1x1 output layer backward: dx, and dw[16], db into dwb[17]; part holds ceil(n/2048)*17.
@@ -903,11 +982,6 @@ void launch_out_bwd(long n, const bf16 *x, const bf16 *w, const float *gz, float
 void launch_features(long n, const double *ahat, bf16 *X, hipStream_t s)
 {
     hipLaunchKernelGGL(k_features, dim3(nblk(n)), dim3(kTB), 0, s, n, ahat, X);
-}
-
-void launch_set_input(long n, const float *r, const double *scale, bf16 *X, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_set_input<float>, dim3(nblk(n)), dim3(kTB), 0, s, n, r, scale, X);
 }
 
 void launch_set_input(long n, const double *r, const double *scale, bf16 *X, hipStream_t s)

@@ -269,7 +269,6 @@ void launch_cg_upd32(const Dims &d, int nblk, float *x, const float *p, float *r
 void launch_rms_scale(long n, const DevScalars *sc, double *scale, hipStream_t st);
 void launch_norm2_rr32(const Dims &d, int nblk, const float *x, double *partials, unsigned *counter,
                        DevScalars *sc, hipStream_t st);
-void launch_unscale(long n, const float *zn, const double *scale, float *z, hipStream_t st);
 
 // U-Net kernels (k_unet.hip): bf16 tensors as raw 16-bit values.
 namespace nn {
@@ -288,11 +287,14 @@ long wgrad_part_floats(const Lv &L, int cout, int cin);
 void launch_pool(const Lv &Lc, int C, const bf16 *x, bf16 *y, hipStream_t s);
 void launch_pool_bwd_add(const Lv &Lf, int C, const float *dyc, float *dxf, hipStream_t s);
 void launch_up_bwd(const Lv &Lc, int C, const float *dyf, float *dxc, hipStream_t s);
-void launch_out_fwd(long n, const bf16 *x, const bf16 *w, const float *b, float *z, hipStream_t s);
+void launch_out_fwd(long n, const bf16 *x, const bf16 *w, const float *b, const double *scale, float *z,
+                    hipStream_t s);
+// Layer 0 of a preconditioner application with the scaled residual r as channel 0 of X.
+void launch_conv_fwd_in(const Lv &L, const bf16 *X, const float *r, const double *scale, const bf16 *w,
+                        const float *b, bf16 *y, hipStream_t s);
 void launch_out_bwd(long n, const bf16 *x, const bf16 *w, const float *gz, float *dx, float *part, float *dwb,
                     hipStream_t s);
 void launch_features(long n, const double *ahat, bf16 *X, hipStream_t s);
-void launch_set_input(long n, const float *r, const double *scale, bf16 *X, hipStream_t s);
 void launch_set_input(long n, const double *r, const double *scale, bf16 *X, hipStream_t s);
 void launch_loss(long n, const float *z, const float *e, double *part, double *res, float *gz, hipStream_t s);
 void launch_adam(long np_, float *p, const float *g, float *m, float *v, float lr, float b1, float b2, float eps,

@@ -190,15 +190,19 @@ bool conv_bwd_weight(const Lv &L, const float *dy, const bf16 *y, int cout, cons
 
 void pool(const Lv &Lc, int C, const bf16 *x, bf16 *y, hipStream_t s) { nn::launch_pool(Lc, C, x, y, s); }
 
-// Forward pass on the workspace input X -> z (fp32, unscaled network output).
-void forward(rt_net *N, hipStream_t s)
+// Forward pass on the workspace input X -> z (fp32, unscaled network output).  With r
+// and scale (a preconditioner application): channel 0 of the input is r scale[0], built
+// inside the first convolution, and the output scale[1] network(...) goes to zout.
+void forward(rt_net *N, hipStream_t s, const float *r = nullptr, const double *scale = nullptr,
+             float *zout = nullptr)
 {
     const Lv *L = N->lv;
     const bf16 *W = N->wb;
     const float *P = N->p;
 #define WL(l) (W + poff(l))
 #define BL(l) (P + poff(l) + wcount(l))
-    conv_fwd(L[0], N->X, 16, 0, nullptr, 0, WL(0), BL(0), 16, 1, N->a[0], nullptr, s);
+    if (r) nn::launch_conv_fwd_in(L[0], N->X, r, scale, WL(0), BL(0), N->a[0], s);
+    else conv_fwd(L[0], N->X, 16, 0, nullptr, 0, WL(0), BL(0), 16, 1, N->a[0], nullptr, s);
     conv_fwd(L[0], N->a[0], 16, 0, nullptr, 0, WL(1), BL(1), 16, 1, N->a[1], nullptr, s);
     pool(L[1], 16, N->a[1], N->p1, s);
     conv_fwd(L[1], N->p1, 16, 0, nullptr, 0, WL(2), BL(2), 32, 1, N->a[2], nullptr, s);
@@ -210,7 +214,8 @@ void forward(rt_net *N, hipStream_t s)
     conv_fwd(L[1], N->a[6], 32, 0, nullptr, 0, WL(7), BL(7), 32, 1, N->a[7], nullptr, s);
     conv_fwd(L[0], N->a[7], 32, 1, N->a[1], 16, WL(8), BL(8), 16, 1, N->a[8], nullptr, s);
     conv_fwd(L[0], N->a[8], 16, 0, nullptr, 0, WL(9), BL(9), 16, 1, N->a[9], nullptr, s);
-    nn::launch_out_fwd(L[0].n, N->a[9], WL(10), BL(10), N->z, s);
+    if (r) nn::launch_out_fwd(L[0].n, N->a[9], WL(10), BL(10), scale, zout, s);
+    else nn::launch_out_fwd(L[0].n, N->a[9], WL(10), BL(10), nullptr, N->z, s);
 }
 
 // Backward pass for dL/dz = N->gz: parameter gradients into N->g.
@@ -740,9 +745,7 @@ rt_status net_precond(rt_net *net, rt_ctx *ctx, const float *r, float *z)
     hipStream_t s = ctx->stream;
     const long n = ctx->d.n;
     launch_rms_scale(n, ctx->sc, ctx->nscale, s);
-    nn::launch_set_input(n, r, ctx->nscale, net->X, s);
-    forward(net, s);
-    launch_unscale(n, net->z, ctx->nscale, z, s);
+    forward(net, s, r, ctx->nscale, z);
     NN_HIP(net, hipGetLastError());
     return RT_OK;
 }
