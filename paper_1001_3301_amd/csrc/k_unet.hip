@@ -7,15 +7,19 @@
 // Tap t = (dk+1) 9 + (dj+1) 3 + (di+1); weights w[(t Cout + co) Cin + ci] (and a
 // transposed copy wt[(t Cin + ci) Cout + co] for the data gradient).
 //
-// Every 3x3x3 convolution is an implicit GEMM on v_mfma_f32_16x16x16_bf16: a wavefront
-// owns 16 cells (the M dimension) and all output channels (N, 16 per MFMA tile); K runs
-// over the 27 taps times the input channels in chunks of 16.  Lane l supplies
-// A[m = l%16][k = 4(l/16) .. +3] (4 consecutive channels of its cell's neighbour: one
-// 8-byte load in the channels-last layout), B[k = 4(l/16) .. +3][n = l%16] (4
-// consecutive input channels of one output channel's weights: one 8-byte load), and
-// receives D[m = 4(l/16) .. +3][n = l%16].  A decoder convolution reads two sources
-// (the nearest-neighbour upsampled coarse tensor and the skip tensor) directly, so the
-// upsampled/concatenated tensor is never materialised.
+// Every 3x3x3 convolution (forward and data gradient) is an LDS-tiled implicit GEMM on
+// v_mfma_f32_16x16x32_bf16 with the weights as A and the activations as B: M = 16
+// output channels of one output-channel tile, N = 16 cells of a radial row segment,
+// K = 32 = two taps x 16 input channels of one input slice.  Lane l supplies
+// A[m = l%16][k = 8(l/16) .. +7] (8 input channels of one tap for output channel l%16,
+// staged in LDS in this fragment order) and B[k = 8(l/16) .. +7][n = l%16] (8 channels
+// of cell l%16's neighbour through that tap, from the LDS tile), and receives
+// D[m = 4(l/16) .. +3][n = l%16]: 4 consecutive output channels of one cell, stored as
+// one vector (conv_tiles below).  The weight gradient is its own MFMA kernel
+// (k_conv_wgrad: M = output channels, N = input channels, K = 32 cells of a radial
+// row).  A decoder convolution reads two sources (the nearest-neighbour upsampled
+// coarse tensor and the skip tensor) directly, so the upsampled / concatenated tensor
+// is never materialised.
 #include <type_traits>
 
 #include "rt_internal.h"

@@ -141,7 +141,9 @@ __device__ __forceinline__ void exp_pair(double x, double &e, double &m)
     int k = (int)kf;
     double s = ldexp(1.0, -k);
     e = fma(s, p, s);
-    m = (k == 0) ? -p : fma(-s, p, 1.0 - s);
+    // 1 - e = -(s p + (s - 1)): s - 1 is exact (k >= 0 since x >= 0), so one rounding;
+    // for k = 0 it is -p exactly
+    m = -fma(s, p, s - 1.0);
 }
 
 // Orders LDS traffic between the lanes of one wavefront.
