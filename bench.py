@@ -64,7 +64,7 @@ MEASURED_TRAFFIC = {("k_cg_dir<float>", "clumpy-512x256x512-nu64"): 1.924e9,
 # profiles/raytrace_counters_clumpy-512x256x512-nu64.md), and the chip issues at most one
 # float64 wave-instruction per CU per cycle (4 SIMDs, 4 cycles per wave64 instruction):
 # 256 CUs x 2.4 GHz.
-RAYTRACE_VALU_PER_CELL = 57.3
+RAYTRACE_VALU_PER_CELL = 38.8
 PEAK_FP64_WAVE_INSTS = 256 * 2.4e9
 
 
@@ -597,7 +597,7 @@ def main():
                    "solve_mode": head, "tol": args.tol, "dt": wl.dt,
                    "step": "first step from the prepared state, repeated K times"},
         "raytrace_gcell_nu_per_s": statistics.median([n * c["n_nu"] / (x / 1e3) / 1e9 for x in rt_ms]),
-        "raytrace_roofline": {"kernel": "k_raytrace<false>", "bound": "alu",
+        "raytrace_roofline": {"kernel": "k_raytrace<false, false>", "bound": "alu",
                               "unit": "float64 VALU wave-instructions/s",
                               "achieved": RAYTRACE_VALU_PER_CELL * n / (statistics.median(rt_ms) / 1e3),
                               "peak": PEAK_FP64_WAVE_INSTS,

@@ -8,27 +8,53 @@
 // transmissions exp(-dtau), each from one range reduction together with
 // 1 - exp(-dtau)).  Per cell, the per-bin absorbed power Phi_b (1 - exp(-dtau_b)) (and,
 // when the face flux is asked for, the outgoing Phi_b) is parked in LDS; every 8 cells
-// (4 with the face flux) the wavefront transposes and sums them over bins, so q, S and
-// the face flux leave as coalesced r-contiguous stores.  The opacity table and the radial geometry factors of the column sit in LDS;
-// the column is read in segments of 512 cells, each lane loading T and rho of 8 cells
-// with coalesced loads and computing their table node, weight and rho dr, which the
-// wavefront broadcasts with readlane as it reaches each cell.
+// (4 with the face flux) the wavefront transposes and sums them over bins, and the
+// lane that owns each cell (below) scales its sum and stores it, so q, S and the face
+// flux leave as coalesced r-contiguous stores.
+//
+// The opacity table (rows of 64 bins whatever the bin count, so the two nodes of a
+// cell are one ds_read2 apart) and two radial factors of the column sit in LDS.  The
+// column is read in segments of 512 cells (256 with the face flux): lane l owns cells
+// l, l + 64, ... of the segment, loads their T and rho with coalesced loads and keeps
+// their table row, (1 - w) rho dr, w rho dr and the factor S / q; the wavefront
+// broadcasts the first three with readlane as it reaches each cell.
 #include "rt_internal.h"
 
 namespace rt {
 
-constexpr int kWavesPerBlock = 16; // columns per block
-constexpr int kSlots = 8;          // cells per lane in one segment
-constexpr int kSeg = 64 * kSlots;  // cells per segment of a column
-constexpr int kRed = 8;            // sums per transpose (8 lanes add each one)
+constexpr int kWavesPerBlock = 16;  // columns per block
+constexpr int kRed = 8;             // sums per transpose (8 lanes add each one)
+constexpr int kRowPad = 72;         // LDS doubles per sum row: 64 lanes + 8, so the
+                                    // eight rows read together fall in different banks
+constexpr int kTabRow = 64;         // LDS doubles per opacity-table row
 
 // Per-cell quantities of a segment, held by the lane that owns the cell (cell
-// seg0 + lane + 64 s in slot s) and broadcast with readlane when the wavefront reaches
-// it: the table row offset and weight, rho dr (floored).
+// seg0 + lane + 64 s in slot s): table row offset, the interpolation weights times
+// rho dr (floored), and S / q = dr / (rho dr c).
 struct CellSlot {
     int kofs;
-    double w, rdr;
+    double vr, wr, sq;
 };
+
+// Sum with the value of lane ^ X (X = 1, 2, 4): ds_swizzle in bit-mask mode (and 0x1f,
+// xor X), two 32-bit halves.
+template <int X>
+__device__ __forceinline__ double add_xor(double v)
+{
+    int2 t = *reinterpret_cast<int2 *>(&v);
+    t.x = __builtin_amdgcn_ds_swizzle(t.x, 0x1f | (X << 10));
+    t.y = __builtin_amdgcn_ds_swizzle(t.y, 0x1f | (X << 10));
+    return v + *reinterpret_cast<double *>(&t);
+}
+
+// v of the lane whose byte address (4 x lane) is addr.
+__device__ __forceinline__ double bpermute_d(int addr, double v)
+{
+    int2 t = *reinterpret_cast<int2 *>(&v);
+    t.x = __builtin_amdgcn_ds_bpermute(addr, t.x);
+    t.y = __builtin_amdgcn_ds_bpermute(addr, t.y);
+    return *reinterpret_cast<double *>(&t);
+}
 
 // kFace: also the total flux at every radial face, Fface when not NULL (the transpose
 // then sums 4 cells' absorbed power and 4 faces' flux; without it 8 cells' absorbed
@@ -44,19 +70,22 @@ __global__ __launch_bounds__(1024) void k_raytrace(
     double *__restrict__ q, double *__restrict__ S, double *__restrict__ Fface, double *__restrict__ Fnu)
 {
     constexpr int kChunk = kFace ? kRed / 2 : kRed;  // cells per transpose
+    constexpr int kSlots = kFace ? 4 : 8;            // cells per lane in one segment
+    constexpr int kSeg = 64 * kSlots;
     extern __shared__ double lds[];
-    double *tab = lds;                       // [nT][nnu]
-    double *Tt = tab + nT * nnu;             // [nT]
-    double *g_dr = Tt + nT;                  // [nr] dr
-    double *g_q = g_dr + nr;                 // [nr] 3 / shell volume
+    double *tab = lds;                       // [nT][kTabRow], bins >= nnu zero
+    double *Tt = tab + nT * kTabRow;         // [nT]
+    double *g_q = Tt + nT;                   // [nr] 3 / shell volume
     double *g_f = g_q + nr;                  // [nr] 1 / r_f^2 of the outer face
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double *red = g_f + nr + wave * (kRed * 64);  // [kRed][64] for this wave
+    double *red = g_f + nr + wave * (kRed * kRowPad);  // [kRed][kRowPad] for this wave
 
-    for (int t = threadIdx.x; t < nT * nnu; t += blockDim.x) tab[t] = kap_g[t];
+    for (int t = threadIdx.x; t < nT * kTabRow; t += blockDim.x) {
+        const int k = t / kTabRow, b = t % kTabRow;
+        tab[t] = b < nnu ? kap_g[k * nnu + b] : 0.0;
+    }
     for (int t = threadIdx.x; t < nT; t += blockDim.x) Tt[t] = Ttab[t];
     for (int t = threadIdx.x; t < nr; t += blockDim.x) {
-        g_dr[t] = dr[t];
         g_q[t] = 3.0 / shell[t];
         g_f[t] = 1.0 / rf2[t + 1];
     }
@@ -65,7 +94,6 @@ __global__ __launch_bounds__(1024) void k_raytrace(
     const long col = (long)blockIdx.x * kWavesPerBlock + wave;
     if (col >= ncol) return;  // no block-wide barrier below this point
     const bool active = lane < nnu;
-    const int lb = active ? lane : 0;
     const long cbase = col * nr;
     const long fbase = col * (nr + 1);
 
@@ -77,22 +105,27 @@ __global__ __launch_bounds__(1024) void k_raytrace(
         if (kBins && active) Fnu[fbase * nnu + lane] = Phi / rf2[0];
     }
 
-    const int s8 = lane >> 3, part = lane & 7;  // reduction roles: sum s8 of kRed, part of 8
+    // transpose roles: lane reads sum row `row` at bins part, part + 8, ...; the eight
+    // lanes of a row then add across (xor 1, 2, 4), and lane l0 + j takes row j's sum
+    const int row = lane >> 3, part = lane & 7;
+    const double *rd_lds = red + row * kRowPad + part;
     for (int seg0 = 0; seg0 < nr; seg0 += kSeg) {
-        // one coalesced batch of loads per segment: slot s holds cell seg0 + lane + 64 s
         CellSlot cs[kSlots];
 #pragma unroll
         for (int sl = 0; sl < kSlots; sl++) {
             const int i = seg0 + lane + 64 * sl;
-            const bool in = i < nr;
-            const int ic = in ? i : nr - 1;
+            const int ic = i < nr ? i : nr - 1;
             const long c = cbase + ic;
-            const double t = T[c], rh = rho[c];
+            const double t = T[c], rh = rho[c], d = dr[ic];
             int k;
-            lin_node(Tt, nT, t, k, cs[sl].w);
-            cs[sl].kofs = k * nnu;
-            const double v = rh * g_dr[ic];
-            cs[sl].rdr = v > 1e-250 ? v : 1e-250;  // keeps S = q / (rho c) finite as rho -> 0
+            double w;
+            lin_node(Tt, nT, t, k, w);
+            const double v = rh * d;
+            const double rdr = v > 1e-250 ? v : 1e-250;  // keeps S = q / (rho c) finite as rho -> 0
+            cs[sl].kofs = k * kTabRow;
+            cs[sl].vr = (1.0 - w) * rdr;
+            cs[sl].wr = w * rdr;
+            cs[sl].sq = d / (rdr * kC);
         }
 #pragma unroll
         for (int sl = 0; sl < kSlots; sl++) {
@@ -106,46 +139,40 @@ __global__ __launch_bounds__(1024) void k_raytrace(
                 for (int m = 0; m < kChunk; m++) {
                     if (m < ncell) {
                         const int ko = __builtin_amdgcn_readlane(cs[sl].kofs, l0 + m);
-                        const double w = readlane_d(cs[sl].w, l0 + m);
-                        const double rd = readlane_d(cs[sl].rdr, l0 + m);
-                        const double a0 = tab[ko + lb], a1 = tab[ko + nnu + lb];
+                        const double vr = readlane_d(cs[sl].vr, l0 + m);
+                        const double wr = readlane_d(cs[sl].wr, l0 + m);
+                        const double a0 = tab[ko + lane], a1 = tab[ko + kTabRow + lane];
                         double e, em;
-                        exp_pair(fma(w, a1 - a0, a0) * rd, e, em);
-                        red[m * 64 + lane] = Phi * em;   // absorbed, before the 3/shell factor
+                        exp_pair(fma(wr, a1, vr * a0), e, em);
+                        red[m * kRowPad + lane] = Phi * em;   // absorbed, before the 3/shell factor
                         Phi = Phi * e;
-                        if (kFace) red[(kChunk + m) * 64 + lane] = Phi;  // through the outer face
+                        if (kFace) red[(kChunk + m) * kRowPad + lane] = Phi;  // through the outer face
                         // per-bin flux at that face: one 64-bin row per face, bin fastest
                         if (kBins && active) Fnu[(fbase + i0 + m + 1) * nnu + lane] = Phi * g_f[i0 + m];
                     }
                 }
                 wave_sync();
-                // kRed sums over the 64 lanes: lane -> (sum s8, part), 8 values each
-                double acc = 0.0;
+                double acc = rd_lds[0];
 #pragma unroll
-                for (int t = 0; t < 8; t++) acc += red[s8 * 64 + part + 8 * t];
-                acc += __shfl_xor(acc, 1);
-                acc += __shfl_xor(acc, 2);
-                acc += __shfl_xor(acc, 4);
-                // rho dr of the chunk's cells, uniform per cell
-                double rd8[kChunk];
-#pragma unroll
-                for (int m = 0; m < kChunk; m++) rd8[m] = readlane_d(cs[sl].rdr, l0 + m);
+                for (int t = 1; t < 8; t++) acc += rd_lds[8 * t];
+                acc = add_xor<1>(acc);
+                acc = add_xor<2>(acc);
+                acc = add_xor<4>(acc);
+                // row j's sum to lane (l0 + j) mod 64: cells j < kChunk land on their
+                // owners; with the face flux, the faces' rows follow them, wrapping to
+                // lanes 0-3 after the slot's last chunk (with 8-cell chunks l0 is a
+                // multiple of 8 and j = lane & 7)
+                const int j = (lane - l0) & 63;
+                acc = bpermute_d(32 * (kFace ? (j & 7) : (lane & 7)), acc);
                 wave_sync();
-                if (part == 0) {
-                    const int mm = s8 < kChunk ? s8 : s8 - kChunk;
-                    const int i = i0 + mm;
-                    if (i < nr) {
-                        if (s8 < kChunk) {
-                            double rdm = rd8[0];
-#pragma unroll
-                            for (int m = 1; m < kChunk; m++) rdm = mm == m ? rd8[m] : rdm;
-                            const double qv = g_q[i] * acc;
-                            q[cbase + i] = qv;
-                            S[cbase + i] = qv * g_dr[i] / (rdm * kC);
-                        } else if (kFace && Fface) {
-                            Fface[fbase + i + 1] = acc * g_f[i];
-                        }
-                    }
+                if ((unsigned)j < (unsigned)ncell) {  // the owner of cell i0 + j
+                    const int i = i0 + j;
+                    const double qv = g_q[i] * acc;
+                    q[cbase + i] = qv;
+                    S[cbase + i] = qv * cs[sl].sq;
+                } else if (kFace && Fface && (unsigned)(j - kChunk) < (unsigned)ncell) {
+                    const int i = i0 + j - kChunk;
+                    Fface[fbase + i + 1] = acc * g_f[i];
                 }
             }
         }
@@ -175,9 +202,9 @@ void raytrace_prepare(size_t lds_bytes)
         (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
 
-size_t raytrace_lds_bytes(int nT, int nnu, int nr)
+size_t raytrace_lds_bytes(int nT, int /*nnu*/, int nr)
 {
-    return sizeof(double) * ((size_t)nT * nnu + nT + 3 * (size_t)nr + (size_t)kWavesPerBlock * kRed * 64);
+    return sizeof(double) * ((size_t)nT * kTabRow + nT + 2 * (size_t)nr + (size_t)kWavesPerBlock * kRed * kRowPad);
 }
 
 }  // namespace rt

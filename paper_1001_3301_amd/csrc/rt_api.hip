@@ -205,7 +205,7 @@ rt_status rt_create(rt_ctx **out, const rt_grid *g, int n_nu, void *stream)
     // the ray trace keeps the opacity table and three radial geometry factors per cell
     // of a column in LDS (160 KB per compute unit)
     if (raytrace_lds_bytes(kMaxT, kMaxNu, g->nr) > 160 * 1024)
-        return fail(nullptr, RT_EINVAL, "rt_create: N_r too large for the ray trace (at most 1322 radial cells)");
+        return fail(nullptr, RT_EINVAL, "rt_create: N_r too large for the ray trace (at most 1472 radial cells)");
     for (int i = 0; i < g->nr; i++)
         if (!(g->r_face[i + 1] > g->r_face[i]) || !(g->r_face[i] > 0.0))
             return fail(nullptr, RT_EINVAL, "rt_create: r_face must be positive and increasing");

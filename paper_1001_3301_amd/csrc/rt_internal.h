@@ -114,15 +114,17 @@ __device__ __forceinline__ double face_D(double chi_a, double chi_b, double Ea, 
 // with |r| <= ln2/2 (Cody-Waite split of ln2), p = expm1(-r) by its Taylor series to
 // degree 13 (truncation < 4e-18 relative on that interval), then e = 2^-k (1 + p) and
 // m = (1 - 2^-k) - 2^-k p, which keeps full relative accuracy for small and large x.
+// x is first clamped to 2000 (e underflows to 0 long before); the clamp is a minimum,
+// so a NaN x gives x = 2000.
 __device__ __forceinline__ void exp_pair(double x, double &e, double &m)
 {
     constexpr double kInvLn2 = 1.4426950408889634074;
     constexpr double kLn2Hi = 6.93147180369123816490e-01;
     constexpr double kLn2Lo = 1.90821492927058770002e-10;
-    x = x > 2000.0 ? 2000.0 : x;
-    double kf = rint(x * kInvLn2);
-    double r = fma(-kf, kLn2Hi, x);
-    r = fma(-kf, kLn2Lo, r);
+    x = fmin(x, 2000.0);
+    const double nk = rint(x * -kInvLn2);  // -k
+    double r = fma(nk, kLn2Hi, x);
+    r = fma(nk, kLn2Lo, r);
     double u = -r;
     double p = 1.0 / 6227020800.0;                 // 1/13!
     p = fma(p, u, 1.0 / 479001600.0);              // 1/12!
@@ -138,8 +140,7 @@ __device__ __forceinline__ void exp_pair(double x, double &e, double &m)
     p = fma(p, u, 0.5);                            // 1/2!
     p = fma(p, u, 1.0);
     p = p * u;                                     // expm1(u)
-    int k = (int)kf;
-    double s = ldexp(1.0, -k);
+    double s = ldexp(1.0, (int)nk);
     e = fma(s, p, s);
     // 1 - e = -(s p + (s - 1)): s - 1 is exact (k >= 0 since x >= 0), so one rounding;
     // for k = 0 it is -p exactly
