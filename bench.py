@@ -64,7 +64,7 @@ MEASURED_TRAFFIC = {("k_cg_dir<float>", "clumpy-512x256x512-nu64"): 1.924e9,
 # profiles/raytrace_counters_clumpy-512x256x512-nu64.md), and the chip issues at most one
 # float64 wave-instruction per CU per cycle (4 SIMDs, 4 cycles per wave64 instruction):
 # 256 CUs x 2.4 GHz.
-RAYTRACE_VALU_PER_CELL = 38.8
+RAYTRACE_VALU_PER_CELL = 31.3
 PEAK_FP64_WAVE_INSTS = 256 * 2.4e9
 
 

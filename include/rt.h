@@ -179,8 +179,8 @@ typedef struct {
 /* Creates a context for grid g and n_nu frequency bins, enqueuing on `stream`
  * (a hipStream_t; NULL = the default stream).  Allocates every workspace of the
  * radiation step (about 30 float64-equivalents per cell).  Select the device first
- * (hipSetDevice); the context stays on it.  RT_EINVAL for N_r > 1472 (the ray trace
- * keeps two radial factors per cell of a column in LDS). */
+ * (hipSetDevice); the context stays on it.  RT_EINVAL for N_r > 2944 (the ray trace's
+ * face flux keeps one radial factor per cell of a column in LDS beside the opacity table). */
 rt_status rt_create(rt_ctx **out, const rt_grid *g, int n_nu, void *stream);
 void rt_destroy(rt_ctx *ctx);
 /* Message of the last failing call on ctx (or of the last failing rt_create when ctx

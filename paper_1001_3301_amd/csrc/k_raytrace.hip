@@ -12,12 +12,14 @@
 // lane that owns each cell (below) scales its sum and stores it, so q, S and the face
 // flux leave as coalesced r-contiguous stores.
 //
-// The opacity table (rows of 64 bins whatever the bin count, so the two nodes of a
-// cell are one ds_read2 apart) and two radial factors of the column sit in LDS.  The
-// column is read in segments of 512 cells (256 with the face flux): lane l owns cells
-// l, l + 64, ... of the segment, loads their T and rho with coalesced loads and keeps
-// their table row, (1 - w) rho dr, w rho dr and the factor S / q; the wavefront
-// broadcasts the first three with readlane as it reaches each cell.
+// The opacity table sits in LDS in rows of 64 bins whatever the bin count, so the two
+// nodes of a cell are one ds_read2 apart.  The column is read in segments of 512 cells
+// (256 with the face flux): lane l owns cells l, l + 64, ... of the segment, loads
+// their T and rho with coalesced loads and keeps their table row, (1 - w) rho dr,
+// w rho dr and the factors q / sum and S / q.  As the wavefront reaches a cell it takes
+// the cell's table row by readlane and its two weights from a per-wave LDS copy of the
+// current 64 cells (one broadcast read; the face-flux variants use readlane for these
+// too), one cell ahead, so the LDS latency overlaps the current cell's arithmetic.
 #include "rt_internal.h"
 
 namespace rt {
@@ -30,10 +32,10 @@ constexpr int kTabRow = 64;         // LDS doubles per opacity-table row
 
 // Per-cell quantities of a segment, held by the lane that owns the cell (cell
 // seg0 + lane + 64 s in slot s): table row offset, the interpolation weights times
-// rho dr (floored), and S / q = dr / (rho dr c).
+// rho dr (floored), q / (sum over bins) = 3 / shell volume and S / q = dr / (rho dr c).
 struct CellSlot {
     int kofs;
-    double vr, wr, sq;
+    double vr, wr, qs, sq;
 };
 
 // Sum with the value of lane ^ X (X = 1, 2, 4): ds_swizzle in bit-mask mode (and 0x1f,
@@ -56,6 +58,11 @@ __device__ __forceinline__ double bpermute_d(int addr, double v)
     return *reinterpret_cast<double *>(&t);
 }
 
+// LDS layout, in doubles: [stage: kWavesPerBlock x 64 x 2, without the face flux]
+// [table: nT x kTabRow] [T nodes: nT] [sum rows: kWavesPerBlock x kRed x kRowPad]
+// [1 / r_f^2: nr, with the face flux].  The stage leads so its 16-byte pairs are aligned.
+__host__ __device__ constexpr size_t stage_doubles(bool face) { return face ? 0 : (size_t)kWavesPerBlock * 128; }
+
 // kFace: also the total flux at every radial face, Fface when not NULL (the transpose
 // then sums 4 cells' absorbed power and 4 faces' flux; without it 8 cells' absorbed
 // power).  kBins (with kFace): also the per-bin face flux Fnu.  Separate
@@ -72,23 +79,22 @@ __global__ __launch_bounds__(1024) void k_raytrace(
     constexpr int kChunk = kFace ? kRed / 2 : kRed;  // cells per transpose
     constexpr int kSlots = kFace ? 4 : 8;            // cells per lane in one segment
     constexpr int kSeg = 64 * kSlots;
+    constexpr bool kStage = !kFace;                  // weights by LDS broadcast
     extern __shared__ double lds[];
-    double *tab = lds;                       // [nT][kTabRow], bins >= nnu zero
-    double *Tt = tab + nT * kTabRow;         // [nT]
-    double *g_q = Tt + nT;                   // [nr] 3 / shell volume
-    double *g_f = g_q + nr;                  // [nr] 1 / r_f^2 of the outer face
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double *red = g_f + nr + wave * (kRed * kRowPad);  // [kRed][kRowPad] for this wave
+    double2 *stage = reinterpret_cast<double2 *>(lds) + wave * 64;  // [64] (vr, wr), kStage
+    double *tab = lds + stage_doubles(kFace);        // [nT][kTabRow], bins >= nnu zero
+    double *Tt = tab + nT * kTabRow;                 // [nT]
+    double *red = Tt + nT + wave * (kRed * kRowPad); // [kRed][kRowPad] for this wave
+    double *g_f = Tt + nT + kWavesPerBlock * kRed * kRowPad;  // [nr], kFace
 
     for (int t = threadIdx.x; t < nT * kTabRow; t += blockDim.x) {
         const int k = t / kTabRow, b = t % kTabRow;
         tab[t] = b < nnu ? kap_g[k * nnu + b] : 0.0;
     }
     for (int t = threadIdx.x; t < nT; t += blockDim.x) Tt[t] = Ttab[t];
-    for (int t = threadIdx.x; t < nr; t += blockDim.x) {
-        g_q[t] = 3.0 / shell[t];
-        g_f[t] = 1.0 / rf2[t + 1];
-    }
+    if (kFace)
+        for (int t = threadIdx.x; t < nr; t += blockDim.x) g_f[t] = 1.0 / rf2[t + 1];
     __syncthreads();
 
     const long col = (long)blockIdx.x * kWavesPerBlock + wave;
@@ -109,6 +115,7 @@ __global__ __launch_bounds__(1024) void k_raytrace(
     // lanes of a row then add across (xor 1, 2, 4), and lane l0 + j takes row j's sum
     const int row = lane >> 3, part = lane & 7;
     const double *rd_lds = red + row * kRowPad + part;
+    const double *tab_l = tab + lane;  // this lane's bin in every table row
     for (int seg0 = 0; seg0 < nr; seg0 += kSeg) {
         CellSlot cs[kSlots];
 #pragma unroll
@@ -116,7 +123,7 @@ __global__ __launch_bounds__(1024) void k_raytrace(
             const int i = seg0 + lane + 64 * sl;
             const int ic = i < nr ? i : nr - 1;
             const long c = cbase + ic;
-            const double t = T[c], rh = rho[c], d = dr[ic];
+            const double t = T[c], rh = rho[c], d = dr[ic], sh = shell[ic];
             int k;
             double w;
             lin_node(Tt, nT, t, k, w);
@@ -125,12 +132,34 @@ __global__ __launch_bounds__(1024) void k_raytrace(
             cs[sl].kofs = k * kTabRow;
             cs[sl].vr = (1.0 - w) * rdr;
             cs[sl].wr = w * rdr;
+            cs[sl].qs = 3.0 / sh;
             cs[sl].sq = d / (rdr * kC);
         }
 #pragma unroll
         for (int sl = 0; sl < kSlots; sl++) {
             const int sbase = seg0 + 64 * sl;
             if (sbase >= nr) break;
+            if (kStage) {  // this slot's weights to the wave's stage (earlier reads are done)
+                wave_sync();
+                stage[lane] = make_double2(cs[sl].vr, cs[sl].wr);
+                wave_sync();
+            }
+            // table entries and weights of cell l of the slot
+            double a0, a1, vr, wr;
+            auto fetch = [&](int l) {
+                const int ko = __builtin_amdgcn_readlane(cs[sl].kofs, l);
+                a0 = tab_l[ko];
+                a1 = tab_l[ko + kTabRow];
+                if (kStage) {
+                    const double2 p = stage[l];
+                    vr = p.x;
+                    wr = p.y;
+                } else {
+                    vr = readlane_d(cs[sl].vr, l);
+                    wr = readlane_d(cs[sl].wr, l);
+                }
+            };
+            fetch(0);
             for (int l0 = 0; l0 < 64; l0 += kChunk) {
                 const int i0 = sbase + l0;
                 if (i0 >= nr) break;
@@ -138,12 +167,12 @@ __global__ __launch_bounds__(1024) void k_raytrace(
 #pragma unroll
                 for (int m = 0; m < kChunk; m++) {
                     if (m < ncell) {
-                        const int ko = __builtin_amdgcn_readlane(cs[sl].kofs, l0 + m);
-                        const double vr = readlane_d(cs[sl].vr, l0 + m);
-                        const double wr = readlane_d(cs[sl].wr, l0 + m);
-                        const double a0 = tab[ko + lane], a1 = tab[ko + kTabRow + lane];
+                        const double dtau = fma(wr, a1, vr * a0);
+                        // the next cell's (after the slot's last cell, lane 0's again: in
+                        // range, and the next slot fetches afresh)
+                        fetch((l0 + m + 1) & 63);
                         double e, em;
-                        exp_pair(fma(wr, a1, vr * a0), e, em);
+                        exp_pair(dtau, e, em);
                         red[m * kRowPad + lane] = Phi * em;   // absorbed, before the 3/shell factor
                         Phi = Phi * e;
                         if (kFace) red[(kChunk + m) * kRowPad + lane] = Phi;  // through the outer face
@@ -166,8 +195,8 @@ __global__ __launch_bounds__(1024) void k_raytrace(
                 acc = bpermute_d(32 * (kFace ? (j & 7) : (lane & 7)), acc);
                 wave_sync();
                 if ((unsigned)j < (unsigned)ncell) {  // the owner of cell i0 + j
-                    const int i = i0 + j;
-                    const double qv = g_q[i] * acc;
+                    const int i = sbase + lane;         // = i0 + j
+                    const double qv = cs[sl].qs * acc;
                     q[cbase + i] = qv;
                     S[cbase + i] = qv * cs[sl].sq;
                 } else if (kFace && Fface && (unsigned)(j - kChunk) < (unsigned)ncell) {
@@ -185,7 +214,8 @@ void launch_raytrace(const Dims &d, const Opac &op, const Geo &g, const double *
 {
     long ncol = (long)d.nt * d.np;
     long nblk = (ncol + kWavesPerBlock - 1) / kWavesPerBlock;
-    size_t lds = raytrace_lds_bytes(op.nT, op.nnu, d.nr);
+    const bool face = Fnu || Fface;
+    size_t lds = raytrace_lds_bytes(op.nT, d.nr, face);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(64 * kWavesPerBlock), lds, st, d.nr, ncol, op.nnu, op.nT,
                            rho, T, op.T, op.kap, F0, R2, g.rf2, g.dr, g.shell, q, S, Fface, Fnu);
@@ -195,16 +225,18 @@ void launch_raytrace(const Dims &d, const Opac &op, const Geo &g, const double *
     else go(k_raytrace<false, false>);
 }
 
-void raytrace_prepare(size_t lds_bytes)
+void raytrace_prepare()
 {
+    // the whole LDS of a compute unit, so contexts with any column length can launch
     for (const void *k : {(const void *)k_raytrace<false, false>, (const void *)k_raytrace<true, false>,
                           (const void *)k_raytrace<true, true>})
-        (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
-size_t raytrace_lds_bytes(int nT, int /*nnu*/, int nr)
+size_t raytrace_lds_bytes(int nT, int nr, bool face)
 {
-    return sizeof(double) * ((size_t)nT * kTabRow + nT + 2 * (size_t)nr + (size_t)kWavesPerBlock * kRed * kRowPad);
+    return sizeof(double) * (stage_doubles(face) + (size_t)nT * kTabRow + nT +
+                             (size_t)kWavesPerBlock * kRed * kRowPad + (face ? (size_t)nr : 0));
 }
 
 }  // namespace rt

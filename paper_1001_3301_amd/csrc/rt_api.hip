@@ -12,7 +12,7 @@
 using namespace rt;
 
 namespace rt {
-void raytrace_prepare(size_t lds_bytes);
+void raytrace_prepare();
 }
 
 namespace {
@@ -202,10 +202,10 @@ rt_status rt_create(rt_ctx **out, const rt_grid *g, int n_nu, void *stream)
     if (n_nu < 1 || n_nu > kMaxNu) return fail(nullptr, RT_EINVAL, "rt_create: n_nu must be in [1, 64]");
     long n = (long)g->nr * g->nt * g->np;
     if (n > (1L << 40)) return fail(nullptr, RT_EINVAL, "rt_create: grid too large");
-    // the ray trace keeps the opacity table and three radial geometry factors per cell
-    // of a column in LDS (160 KB per compute unit)
-    if (raytrace_lds_bytes(kMaxT, kMaxNu, g->nr) > 160 * 1024)
-        return fail(nullptr, RT_EINVAL, "rt_create: N_r too large for the ray trace (at most 1472 radial cells)");
+    // the ray trace keeps the opacity table in LDS (160 KB per compute unit) and, for the
+    // face flux, one radial factor per cell of a column
+    if (raytrace_lds_bytes(kMaxT, g->nr, true) > 160 * 1024 || raytrace_lds_bytes(kMaxT, g->nr, false) > 160 * 1024)
+        return fail(nullptr, RT_EINVAL, "rt_create: N_r too large for the ray trace (at most 2944 radial cells)");
     for (int i = 0; i < g->nr; i++)
         if (!(g->r_face[i + 1] > g->r_face[i]) || !(g->r_face[i] > 0.0))
             return fail(nullptr, RT_EINVAL, "rt_create: r_face must be positive and increasing");
@@ -354,7 +354,7 @@ rt_status rt_create(rt_ctx **out, const rt_grid *g, int n_nu, void *stream)
     std::memset(ctx->h_sc, 0, sizeof(DevScalars));
     for (auto &e : ctx->ev)
         if (hipEventCreate(&e) != hipSuccess) return bail(RT_EDEVICE, "rt_create: event creation failed");
-    raytrace_prepare(raytrace_lds_bytes(kMaxT, kMaxNu, g->nr));
+    raytrace_prepare();
     *out = ctx;
     return RT_OK;
 }

@@ -111,9 +111,11 @@ __device__ __forceinline__ double face_D(double chi_a, double chi_b, double Ea, 
 }
 
 // e = exp(-x) and m = 1 - exp(-x) for x >= 0 from one range reduction: x = k ln2 + r
-// with |r| <= ln2/2 (Cody-Waite split of ln2), p = expm1(-r) by its Taylor series to
-// degree 13 (truncation < 4e-18 relative on that interval), then e = 2^-k (1 + p) and
-// m = (1 - 2^-k) - 2^-k p, which keeps full relative accuracy for small and large x.
+// with |r| <= ln2/2 (Cody-Waite split of ln2), p = expm1(u), u = -r, as u q(u) with q the
+// degree-10 polynomial closest to expm1(u)/u in relative error on that interval (Remez
+// exchange, csrc/expm1_minimax.py: error 1.8e-17), then e = 2^-k (1 + p) and
+// m = (1 - 2^-k) - 2^-k p, which keeps full relative accuracy for small and large x
+// (within 0.7 ulp for e and 1.01 ulp for m).
 // x is first clamped to 2000 (e underflows to 0 long before); the clamp is a minimum,
 // so a NaN x gives x = 2000.
 __device__ __forceinline__ void exp_pair(double x, double &e, double &m)
@@ -121,26 +123,30 @@ __device__ __forceinline__ void exp_pair(double x, double &e, double &m)
     constexpr double kInvLn2 = 1.4426950408889634074;
     constexpr double kLn2Hi = 6.93147180369123816490e-01;
     constexpr double kLn2Lo = 1.90821492927058770002e-10;
+    constexpr double kRound = 6755399441055744.0;  // 1.5 * 2^52: adding it rounds to an integer
     x = fmin(x, 2000.0);
-    const double nk = rint(x * -kInvLn2);  // -k
+    // -k = rint(-x / ln2), as t = -x / ln2 + 1.5 * 2^52 rounded once: the low word of t is
+    // -k as a 32-bit integer (|k| < 2^31) and t - 1.5 * 2^52 is -k exactly
+    const double t = fma(x, -kInvLn2, kRound);
+    const double nk = t - kRound;
     double r = fma(nk, kLn2Hi, x);
     r = fma(nk, kLn2Lo, r);
     double u = -r;
-    double p = 1.0 / 6227020800.0;                 // 1/13!
-    p = fma(p, u, 1.0 / 479001600.0);              // 1/12!
-    p = fma(p, u, 1.0 / 39916800.0);               // 1/11!
-    p = fma(p, u, 1.0 / 3628800.0);                // 1/10!
-    p = fma(p, u, 1.0 / 362880.0);                 // 1/9!
-    p = fma(p, u, 1.0 / 40320.0);                  // 1/8!
-    p = fma(p, u, 1.0 / 5040.0);                   // 1/7!
-    p = fma(p, u, 1.0 / 720.0);                    // 1/6!
-    p = fma(p, u, 1.0 / 120.0);                    // 1/5!
-    p = fma(p, u, 1.0 / 24.0);                     // 1/4!
-    p = fma(p, u, 1.0 / 6.0);                      // 1/3!
-    p = fma(p, u, 0.5);                            // 1/2!
+    // BEGIN expm1 minimax: q(u) coefficients, highest degree first
+    double p = 2.505209761119569e-08;
+    p = fma(p, u, 2.762626294187125e-07);
+    p = fma(p, u, 2.755741478642639e-06);
+    p = fma(p, u, 2.480150460177586e-05);
+    p = fma(p, u, 0.00019841269707470595);
+    p = fma(p, u, 0.001388888893225918);
+    p = fma(p, u, 0.008333333333397832);
+    p = fma(p, u, 0.041666666666573905);
+    p = fma(p, u, 0.16666666666666563);
+    p = fma(p, u, 0.5000000000000006);
     p = fma(p, u, 1.0);
+    // END expm1 minimax
     p = p * u;                                     // expm1(u)
-    double s = ldexp(1.0, (int)nk);
+    double s = ldexp(1.0, __double2loint(t));
     e = fma(s, p, s);
     // 1 - e = -(s p + (s - 1)): s - 1 is exact (k >= 0 since x >= 0), so one rounding;
     // for k = 0 it is -p exactly
@@ -185,7 +191,7 @@ struct Net;
 void launch_raytrace(const Dims &d, const Opac &op, const Geo &g, const double *F0, double R2,
                      const double *rho, const double *T, double *q, double *S, double *Fface,
                      double *Fnu, hipStream_t st);
-size_t raytrace_lds_bytes(int nT, int nnu, int nr);
+size_t raytrace_lds_bytes(int nT, int nr, bool face);
 void launch_energy(const Dims &d, const Opac &op, const double *T, const double *S, double Efloor,
                    double *E, hipStream_t st);
 void launch_assemble(const Dims &d, const Geo &g, const Opac &op, const double *rho, const double *T,

@@ -19,8 +19,10 @@ from _util import rel, initial_temperature
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-# ... and the longest columns the ray trace's LDS takes (N_r <= 1472)
+# ... and long columns: 1472 cells for whole steps (the oracle's dense solve), the
+# longest the ray trace's LDS takes (N_r <= 2944) for the ray trace
 SHAPES = [(2, 1, 1), (2, 3, 1), (4, 2, 2), (6, 1, 4), (10, 7, 2), (1472, 2, 1)]
+RT_SHAPES = SHAPES + [(2944, 2, 1)]
 
 
 def _d(x):
@@ -35,7 +37,7 @@ def _wl(shape):
     return sy.make_workload("edge", *shape, 4, 10.0, clump_seed=31)
 
 
-@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("shape", RT_SHAPES, ids=lambda s: "x".join(map(str, s)))
 def test_tiny_raytrace_parity(shape):
     from paper_1001_3301_amd import rt
     wl = _wl(shape)
@@ -59,10 +61,10 @@ def test_column_length_limit():
     """rt_create takes columns up to the ray trace's LDS limit and refuses longer ones."""
     from paper_1001_3301_amd import rt
     th, ph = np.array([0.4, 0.5]), np.array([0.0, 0.1])
-    rt.Context(np.linspace(1.0, 2.0, 1473), th, ph, 64).close()
+    rt.Context(np.linspace(1.0, 2.0, 2945), th, ph, 64).close()
     with pytest.raises(rt.RtError) as ei:
-        rt.Context(np.linspace(1.0, 2.0, 1474), th, ph, 64)
-    assert ei.value.status == rt.RT_EINVAL and "1472" in str(ei.value)
+        rt.Context(np.linspace(1.0, 2.0, 2946), th, ph, 64)
+    assert ei.value.status == rt.RT_EINVAL and "2944" in str(ei.value)
 
 
 MODES = {  # name: (mode, reduce, solve tol, T bar)
