@@ -65,6 +65,7 @@ MEASURED_TRAFFIC = {("k_cg_dir<float>", "clumpy-512x256x512-nu64"): 1.924e9,
 # float64 wave-instruction per CU per cycle (4 SIMDs, 4 cycles per wave64 instruction):
 # 256 CUs x 2.4 GHz.
 RAYTRACE_VALU_PER_CELL = 31.3
+RAYTRACE_ALG_INSTS_PER_CELL = 35.0
 PEAK_FP64_WAVE_INSTS = 256 * 2.4e9
 
 
@@ -603,7 +604,13 @@ def main():
                               "peak": PEAK_FP64_WAVE_INSTS,
                               "frac": RAYTRACE_VALU_PER_CELL * n / (statistics.median(rt_ms) / 1e3)
                               / PEAK_FP64_WAVE_INSTS,
-                              "valu_insts_per_cell": RAYTRACE_VALU_PER_CELL},
+                              "valu_insts_per_cell": RAYTRACE_VALU_PER_CELL,
+                              # the same bound priced on the algorithm's own count rather
+                              # than the instructions issued: one exp/expm1 pair and ~8 more
+                              # float64 operations per cell-bin, ~35 instructions
+                              "algorithmic_insts_per_cell": RAYTRACE_ALG_INSTS_PER_CELL,
+                              "algorithmic_frac": RAYTRACE_ALG_INSTS_PER_CELL * n / (statistics.median(rt_ms) / 1e3)
+                              / PEAK_FP64_WAVE_INSTS},
         "solve_iters_per_step": statistics.median([s["solve"]["iters"] for s in R["stats"]]),
         "kernel_ms": {"dir": ms_dir, "upd": ms_upd, "black": ms_black, "samples": samples},
     }
