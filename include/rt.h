@@ -411,7 +411,8 @@ rt_status rt_net_train(rt_ctx *ctx, rt_net *net, rt_dataset *ds, const rt_train_
  * enqueued on `stream`).  Forward: y = act(conv3x3x3([up?(x1), x2], w) + bias), x1 with
  * c1 channels on the level of y (up1 = 0) or on the 2x coarser level read through
  * nearest-neighbour upsampling (up1 = 1), x2 with c2 channels (may be 0); outputs bf16
- * y and/or fp32 yf (either may be NULL); c1, c2, cout multiples of 16, cout <= 64. */
+ * y and/or fp32 yf (either may be NULL); c1, c2, cout multiples of 16, cout <= 64.  The
+ * convolutions (and the network) take grids of fewer than 2^31 cells (RT_EINVAL). */
 rt_status rt_nn_conv3d_fwd(void *stream, int nr, int nt, int np, const void *x1, int c1, int up1, const void *x2,
                            int c2, const void *w, const float *bias, int cout, int relu, void *y, float *yf);
 /* Data gradient: d[x1|x2] = conv^T(dy masked by yrelu > 0 when yrelu != NULL) with the

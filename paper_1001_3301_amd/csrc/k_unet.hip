@@ -115,9 +115,12 @@ __device__ __forceinline__ void static_for(F &&f)
 //     one cell, stored as one vector.
 // Each wavefront owns Tile::per_wave row segments (adjacent in r and theta), so one A
 // fragment feeds that many MFMAs and one B fragment feeds NT output-channel tiles.
-// The LDS tile is stored half-major, xs[h][cell][8] with h the upper or lower 8
-// channels, so 8 lanes reading one half of 8 consecutive cells read 128 contiguous
-// bytes (conflict-free), and every fragment address is a per-lane base plus a
+// The LDS tile is stored cell-major, xs[cell][h][8] with h the lower or upper 8
+// channels (32 bytes per cell), so the 32 lanes of one tap in a fragment read 512
+// contiguous bytes and the other tap's 32 lanes another 512; measured on gfx950 this is
+// free of bank conflicts for every tap distance, where a half-major layout (halves a
+// tile apart) costs every fragment read a second pass.  The tile is written with
+// contiguous 16-byte stores, and every fragment address is a per-lane base plus a
 // compile-time offset for the segment and the tap.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -146,17 +149,22 @@ __device__ __forceinline__ unsigned pack_bf16(float a, float b)
 }
 
 // Body shared by the forward (sign = +1) and data-gradient (sign = -1: the output cell
-// whose tap reads this cell) convolutions.  load(idx, a, b, c, ch, ok) returns 8 bf16
-// channels ch .. ch + 7 of input cell idx = (a, b, c); store(idx, ch, v) writes output
-// channels ch .. ch + 3.  w is [tap][cout][cin] in bf16.
+// whose tap reads this cell) convolutions.  load(idx, a, b, c, ch) issues the loads of
+// 8 input channels ch .. ch + 7 of cell idx = (a, b, c) (cell 0 for cells outside the
+// grid, so every address is valid) and returns them raw; finish(raw, ok) turns them
+// into 8 bf16 operands, zeros where !ok, when the tile is written to LDS (so a load
+// issued ahead is not waited for early); store(idx, ch, v) writes output channels
+// ch .. ch + 3.  w is [tap][cout][cin] in bf16.  AHEAD: the next item's tile and
+// weights are loaded before this item's MFMAs.
 //
 // Blocks are persistent: gridDim.x is a multiple of 8 and block b serves the tiles of
 // one eighth of the tile sequence (XCD b % 8 under round-robin dispatch, so the
 // concurrently resident blocks of an XCD work on neighbouring tiles and share halos
 // in that XCD's L2; theta fastest, then phi, then r), stepping by gridDim.x / 8; a block
 // whose input is a single slice loads its weights once.
-template <int NT, int TJ, int TK, int SIGN, class Load, class Store>
-__device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__restrict__ w, Load load, Store store)
+template <int NT, int TJ, int TK, int SIGN, bool AHEAD, class Load, class Finish, class Store>
+__device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__restrict__ w, Load load, Finish finish,
+                                           Store store)
 {
     using T = Tile<TJ, TK>;
     constexpr int PW = T::per_wave;
@@ -166,12 +174,21 @@ __device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__r
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int cout = NT * 16;
     const int nslice = cin / 16;
+    // 32-bit tile, cell and element indices (the launchers take levels of fewer than 2^31
+    // cells); only a cell index times its channel count is formed in 64 bits
     const int ntr = (L.nr + kTR - 1) / kTR, ntj = (L.nt + TJ - 1) / TJ, ntk = (L.np + TK - 1) / TK;
-    const long ntiles = (long)ntr * ntj * ntk;
+    const int ntiles = ntr * ntj * ntk;
     const int per = gridDim.x >> 3, xcd = blockIdx.x & 7;
-    const long t_end = ntiles * (xcd + 1) / 8;
-    long tile = ntiles * xcd / 8 + (blockIdx.x >> 3);
+    const int t_end = (int)((long)ntiles * (xcd + 1) / 8);
+    int tile = (int)((long)ntiles * xcd / 8) + (blockIdx.x >> 3);
     if (tile >= t_end) return;  // uniform over the block
+    // tile t -> (tr, tj, tk): theta fastest, then phi, then r
+    auto decode = [&](int t, int &r0, int &j0, int &k0) __attribute__((always_inline)) {
+        const int q = t / ntj, tr = q / ntk;
+        j0 = (t - q * ntj) * TJ;
+        k0 = (q - tr * ntk) * TK;
+        r0 = tr * kTR;
+    };
     constexpr int NL = (T::cells * 2 + kTB - 1) / kTB;   // 16-byte tile loads per thread
     constexpr int NW = (27 * NT * 32 + kTB - 1) / kTB;   // 16-byte weight loads per thread
     // the zero weights of the padding tap 27
@@ -179,7 +196,7 @@ __device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__r
     // per-lane fragment bases: segment q of this wavefront is (rh = q & 1, jj = jw + q / 2, kw)
     const int g0 = wv * PW, jw = (g0 >> 1) % TJ, kw = (g0 >> 1) / TJ;
     const int half = (lane >> 4) & 1;
-    const int xbase = half * T::cells * 16 + (((kw + 1) * T::HJ + (jw + 1)) * T::HR + 1 + (lane & 15)) * 16;
+    const int xbase = (((kw + 1) * T::HJ + (jw + 1)) * T::HR + 1 + (lane & 15)) * 32 + half * 16;
     const int wbase = ((lane >> 5) * NT * 32 + (lane & 31)) * 16;
     float4v acc[PW][NT];
 #pragma unroll
@@ -192,11 +209,13 @@ __device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__r
     // vector type with compile-time indices, so the staging stays in registers (the HIP
     // uint4 struct made the compiler keep such arrays in scratch memory).
     typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-    auto fetch = [&](long t, int sl, u32x4 (&vv)[NL]) __attribute__((always_inline)) {
+    typedef decltype(load(0, 0, 0, 0, 0)) Raw;
+    auto fetch = [&](int t, int sl, Raw (&vv)[NL], unsigned &okm) __attribute__((always_inline)) {
+        okm = 0u;
         // tile order: theta fastest, then phi, then r, so the blocks resident together
         // share their theta halos and the next wave of blocks finds its phi halo plane in L2
-        const int tj = (int)(t % ntj), tk = (int)((t / ntj) % ntk), tr = (int)(t / ((long)ntj * ntk));
-        const int r0 = tr * kTR, j0 = tj * TJ, k0 = tk * TK;
+        int r0, j0, k0;
+        decode(t, r0, j0, k0);
         static_for<0, NL>([&](auto uc) __attribute__((always_inline)) {
             constexpr int u = decltype(uc)::value;
             const int q = tid + u * kTB;
@@ -207,43 +226,59 @@ __device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__r
             const bool ok = q < T::cells * 2 && (unsigned)a < (unsigned)L.nr && (unsigned)b < (unsigned)L.nt &&
                             (unsigned)c < (unsigned)L.np;
             if (!ok) a = b = c = 0;
-            vv[u] = load(a + (long)L.nr * (b + (long)L.nt * c), a, b, c, sl * 16 + h * 8, ok);
+            okm |= (unsigned)ok << u;
+            vv[u] = load(a + L.nr * (b + L.nt * c), a, b, c, sl * 16 + h * 8);
         });
     };
-    auto put = [&](const u32x4 (&vv)[NL]) __attribute__((always_inline)) {
+    auto put = [&](const Raw (&vv)[NL], unsigned okm) __attribute__((always_inline)) {
         static_for<0, NL>([&](auto uc) __attribute__((always_inline)) {
             constexpr int u = decltype(uc)::value;
             const int q = tid + u * kTB;
-            if (q < T::cells * 2) *reinterpret_cast<u32x4 *>(lds + ((q & 1) * T::cells + (q >> 1)) * 16) = vv[u];
+            if (q < T::cells * 2) *reinterpret_cast<u32x4 *>(lds + q * 16) = finish(vv[u], (okm >> u) & 1u);
         });
     };
+    // the weights of slice sl (all 27 taps, fragment order) into registers
+    auto fetch_w = [&](int sl, u32x4 (&wr)[NW]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < NW; u++) {
+            const int q = min(tid + u * kTB, 27 * NT * 32 - 1);
+            const int l32 = q & 31, tt = (q >> 5) % NT, tap = q / (32 * NT);
+            const int co = tt * 16 + (l32 & 15), ci = sl * 16 + (l32 >> 4) * 8;
+            wr[u] = *reinterpret_cast<const u32x4 *>(w + ((long)tap * cout + co) * cin + ci);
+        }
+    };
+    auto put_w = [&](const u32x4 (&wr)[NW]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < NW; u++) {
+            const int q = tid + u * kTB;
+            if (q < 27 * NT * 32) *reinterpret_cast<u32x4 *>(ws + q * 16) = wr[u];
+        }
+    };
+    // AHEAD (the forward convolutions with 16 output channels: the fine level, where the
+    // layer is bound by moving its activations): the next item's tile and weights are
+    // loaded into registers before this item's MFMAs, so their latency overlaps the
+    // matrix work; otherwise (the wider layers, at the register limit already, and the
+    // data gradient, whose loads are converted as they arrive) each item is loaded after
+    // the previous one's MFMAs.
+    constexpr bool kAhead = AHEAD;
+    Raw v[NL];
+    u32x4 wr[NW];
+    unsigned okm;
+    if (kAhead) {
+        fetch(tile, 0, v, okm);
+        fetch_w(0, wr);
+    }
     int s = 0;
     bool first = true;
     for (;;) {
-        const long cur = tile;
+        const int cur = tile;
         const int cs = s;
-        {
-            u32x4 v[NL];
-            fetch(cur, cs, v);
-            __syncthreads();  // the previous item's MFMAs are done with the LDS tiles
-            put(v);
-        }
+        if (!kAhead) fetch(cur, cs, v, okm);
+        __syncthreads();  // the previous item's MFMAs are done with the LDS tiles
+        put(v, okm);
         if (first || nslice > 1) {
-            // a native vector type, so all NW loads stay in registers and fly together
-            typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-            u32x4 wr[NW];
-#pragma unroll
-            for (int u = 0; u < NW; u++) {
-                const int q = min(tid + u * kTB, 27 * NT * 32 - 1);
-                const int l32 = q & 31, tt = (q >> 5) % NT, tap = q / (32 * NT);
-                const int co = tt * 16 + (l32 & 15), ci = cs * 16 + (l32 >> 4) * 8;
-                wr[u] = *reinterpret_cast<const u32x4 *>(w + ((long)tap * cout + co) * cin + ci);
-            }
-#pragma unroll
-            for (int u = 0; u < NW; u++) {
-                const int q = tid + u * kTB;
-                if (q < 27 * NT * 32) *reinterpret_cast<u32x4 *>(ws + q * 16) = wr[u];
-            }
+            if (!kAhead) fetch_w(cs, wr);
+            put_w(wr);
         }
         first = false;
         __syncthreads();
@@ -251,17 +286,21 @@ __device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__r
             s = 0;
             tile += per;
         }
+        if (kAhead && tile < t_end) {
+            fetch(tile, s, v, okm);
+            if (nslice > 1) fetch_w(s, wr);
+        }
         // Tap pairs p = 0 .. 13, software-pipelined: the LDS fragments of pair p + 1 are
         // requested before the MFMAs of pair p are issued.
         auto frags = [&](auto pc, bf16x8 (&bf)[PW], bf16x8 (&af)[NT]) {
             constexpr int p = decltype(pc)::value;
             constexpr int ta = 2 * p, tb = (2 * p + 1 < 27) ? 2 * p + 1 : 13;
-            constexpr int oa = SIGN * (((ta / 9 - 1) * T::HJ + ((ta / 3) % 3 - 1)) * T::HR + (ta % 3 - 1)) * 16;
-            constexpr int ob = SIGN * (((tb / 9 - 1) * T::HJ + ((tb / 3) % 3 - 1)) * T::HR + (tb % 3 - 1)) * 16;
+            constexpr int oa = SIGN * (((ta / 9 - 1) * T::HJ + ((ta / 3) % 3 - 1)) * T::HR + (ta % 3 - 1)) * 32;
+            constexpr int ob = SIGN * (((tb / 9 - 1) * T::HJ + ((tb / 3) % 3 - 1)) * T::HR + (tb % 3 - 1)) * 32;
             const char *xp = lds + xbase + ((lane < 32) ? oa : ob);
 #pragma unroll
             for (int q = 0; q < PW; q++)
-                bf[q] = *reinterpret_cast<const bf16x8 *>(xp + ((q >> 1) * T::HR + (q & 1) * 16) * 16);
+                bf[q] = *reinterpret_cast<const bf16x8 *>(xp + ((q >> 1) * T::HR + (q & 1) * 16) * 32);
             const char *wp = ws + wbase + 2 * p * NT * 32 * 16;
 #pragma unroll
             for (int t = 0; t < NT; t++) af[t] = *reinterpret_cast<const bf16x8 *>(wp + t * 32 * 16);
@@ -287,13 +326,13 @@ __device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__r
             __builtin_amdgcn_sched_barrier(0);
         });
         if (cs == nslice - 1) {
-            const int tj = (int)(cur % ntj), tk = (int)((cur / ntj) % ntk), tr = (int)(cur / ((long)ntj * ntk));
-            const int r0 = tr * kTR, j0 = tj * TJ, k0 = tk * TK;
+            int r0, j0, k0;
+            decode(cur, r0, j0, k0);
 #pragma unroll
             for (int q = 0; q < PW; q++) {
                 const int a = r0 + (q & 1) * 16 + (lane & 15), b = j0 + jw + (q >> 1), c = k0 + kw;
                 if (a < L.nr && b < L.nt && c < L.np) {
-                    const long idx = a + (long)L.nr * (b + (long)L.nt * c);
+                    const int idx = a + L.nr * (b + L.nt * c);
 #pragma unroll
                     for (int t = 0; t < NT; t++) store(idx, t * 16 + 4 * (lane >> 4), acc[q][t]);
                 }
@@ -310,23 +349,23 @@ __device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__r
 // (up1 = 1, read through nearest-neighbour upsampling); x2 (c2 channels, may be 0) on
 // the level of y.  Writes bf16 y and/or fp32 yf.
 template <int NT, int TJ, int TK>
-__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_conv_fwd(
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(NT == 1 ? 3 : 2, 8))) void k_conv_fwd(
     Lv L, const bf16 *__restrict__ x1, int c1, int up1, const bf16 *__restrict__ x2, int c2,
     const bf16 *__restrict__ w, const float *__restrict__ bias, int relu, bf16 *__restrict__ y, float *__restrict__ yf)
 {
     const int cr = L.nr >> 1, ct = L.nt >> 1;
     typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-    auto load = [&](long idx, int a, int b, int c, int ch, bool ok) -> u32x4 {
+    auto load = [&](int idx, int a, int b, int c, int ch) -> u32x4 {
         const bf16 *p;
         if (ch < c1) {
-            const long e = up1 ? (a >> 1) + (long)cr * ((b >> 1) + (long)ct * (c >> 1)) : idx;
-            p = x1 + e * c1 + ch;
+            const int e = up1 ? (a >> 1) + cr * ((b >> 1) + ct * (c >> 1)) : idx;
+            p = x1 + (size_t)e * c1 + ch;
         } else {
-            p = x2 + idx * c2 + (ch - c1);
+            p = x2 + (size_t)idx * c2 + (ch - c1);
         }
-        const u32x4 x = *reinterpret_cast<const u32x4 *>(p);
-        return ok ? x : u32x4{0u, 0u, 0u, 0u};
+        return *reinterpret_cast<const u32x4 *>(p);
     };
+    auto finish = [](const u32x4 &x, bool ok) -> u32x4 { return ok ? x : u32x4{0u, 0u, 0u, 0u}; };
     const int cout = NT * 16;
     // the bias of this lane's output channels t 16 + 4 (lane / 16) .. + 3 of each output
     // tile t, loaded once (the epilogue then waits for no memory)
@@ -335,17 +374,17 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     for (int t = 0; t < NT; t++)
         bsel[t] = bias ? *reinterpret_cast<const float4 *>(bias + t * 16 + 4 * ((threadIdx.x & 63) >> 4))
                        : make_float4(0.f, 0.f, 0.f, 0.f);
-    auto store = [&](long idx, int co, const float4v &v) {
+    auto store = [&](int idx, int co, const float4v &v) {
         const float4 bb = bsel[co >> 4];
         float o[4] = {v[0] + bb.x, v[1] + bb.y, v[2] + bb.z, v[3] + bb.w};
         if (relu) {  // a select, no branch; NaN passes (the comparison is false)
 #pragma unroll
             for (int i = 0; i < 4; i++) o[i] = o[i] < 0.0f ? 0.0f : o[i];
         }
-        if (y) *reinterpret_cast<uint2 *>(y + idx * cout + co) = make_uint2(pack_bf16(o[0], o[1]), pack_bf16(o[2], o[3]));
-        if (yf) *reinterpret_cast<float4 *>(yf + idx * cout + co) = make_float4(o[0], o[1], o[2], o[3]);
+        if (y) *reinterpret_cast<uint2 *>(y + (size_t)idx * cout + co) = make_uint2(pack_bf16(o[0], o[1]), pack_bf16(o[2], o[3]));
+        if (yf) *reinterpret_cast<float4 *>(yf + (size_t)idx * cout + co) = make_float4(o[0], o[1], o[2], o[3]);
     };
-    conv_tiles<NT, TJ, TK, 1>(L, c1 + c2, w, load, store);
+    conv_tiles<NT, TJ, TK, 1, false>(L, c1 + c2, w, load, finish, store);
 }
 
 // Layer 0 of the preconditioner's application with its input built on the fly: channel
@@ -354,27 +393,35 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 // read), channels 8..15 are zero and not loaded.  The same operands, bit for bit, as
 // k_set_input followed by k_conv_fwd<1,4,4> on X, without writing X (16 output
 // channels, bias, ReLU, bf16 out).
-__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_conv_fwd_in(
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_conv_fwd_in(
     Lv L, const bf16 *__restrict__ X, const float *__restrict__ r, const double *__restrict__ scale,
     const bf16 *__restrict__ w, const float *__restrict__ bias, bf16 *__restrict__ y)
 {
     typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
     const double sc = scale[0];
-    auto load = [&](long idx, int, int, int, int ch, bool ok) -> u32x4 {
-        if (ch != 0) return u32x4{0u, 0u, 0u, 0u};
-        u32x4 x = *reinterpret_cast<const u32x4 *>(X + idx * 16);
-        const unsigned r0 = f2bf((float)((double)r[idx] * sc));
-        x[0] = (x[0] & 0xFFFF0000u) | r0;
-        return ok ? x : u32x4{0u, 0u, 0u, 0u};
+    // both halves of a cell read its channels 0..7 (the same 16 bytes, so no extra
+    // traffic); the upper half is then zeroed when the tile is written
+    struct Raw {
+        u32x4 x;
+        float r;
+        int lower;
+    };
+    auto load = [&](int idx, int, int, int, int ch) -> Raw {
+        return Raw{*reinterpret_cast<const u32x4 *>(X + (size_t)idx * 16), r[idx], ch == 0};
+    };
+    auto finish = [&](const Raw &v, bool ok) -> u32x4 {
+        u32x4 x = v.x;
+        x[0] = (x[0] & 0xFFFF0000u) | f2bf((float)((double)v.r * sc));
+        return ok && v.lower ? x : u32x4{0u, 0u, 0u, 0u};
     };
     const float4 bb = *reinterpret_cast<const float4 *>(bias + 4 * ((threadIdx.x & 63) >> 4));
-    auto store = [&](long idx, int co, const float4v &v) {
+    auto store = [&](int idx, int co, const float4v &v) {
         float o[4] = {v[0] + bb.x, v[1] + bb.y, v[2] + bb.z, v[3] + bb.w};
 #pragma unroll
         for (int i = 0; i < 4; i++) o[i] = o[i] < 0.0f ? 0.0f : o[i];
-        *reinterpret_cast<uint2 *>(y + idx * 16 + co) = make_uint2(pack_bf16(o[0], o[1]), pack_bf16(o[2], o[3]));
+        *reinterpret_cast<uint2 *>(y + (size_t)idx * 16 + co) = make_uint2(pack_bf16(o[0], o[1]), pack_bf16(o[2], o[3]));
     };
-    conv_tiles<1, 4, 4, 1>(L, 16, w, load, store);
+    conv_tiles<1, 4, 4, 1, false>(L, 16, w, load, finish, store);
 }
 
 // ------------------------------------------------------------ data gradient
@@ -391,26 +438,26 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     float *__restrict__ d1, int c2, float *__restrict__ d2)
 {
     typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-    auto load = [&](long idx, int, int, int, int ch, bool ok) -> u32x4 {
-        const float4 g0 = *reinterpret_cast<const float4 *>(dy + idx * cout + ch);
-        const float4 g1 = *reinterpret_cast<const float4 *>(dy + idx * cout + ch + 4);
+    auto load = [&](int idx, int, int, int, int ch) -> u32x4 {
+        const float4 g0 = *reinterpret_cast<const float4 *>(dy + (size_t)idx * cout + ch);
+        const float4 g1 = *reinterpret_cast<const float4 *>(dy + (size_t)idx * cout + ch + 4);
         float f[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
         if (yout) {
-            const uint4 u = *reinterpret_cast<const uint4 *>(yout + idx * cout + ch);
+            const uint4 u = *reinterpret_cast<const uint4 *>(yout + (size_t)idx * cout + ch);
             const bf16 *h = reinterpret_cast<const bf16 *>(&u);
 #pragma unroll
             for (int q = 0; q < 8; q++)
                 if (!(bf2f(h[q]) > 0.0f)) f[q] = 0.0f;
         }
-        const u32x4 r{pack_bf16(f[0], f[1]), pack_bf16(f[2], f[3]), pack_bf16(f[4], f[5]), pack_bf16(f[6], f[7])};
-        return ok ? r : u32x4{0u, 0u, 0u, 0u};
+        return u32x4{pack_bf16(f[0], f[1]), pack_bf16(f[2], f[3]), pack_bf16(f[4], f[5]), pack_bf16(f[6], f[7])};
     };
-    auto store = [&](long idx, int ci, const float4v &v) {
+    auto finish = [](const u32x4 &x, bool ok) -> u32x4 { return ok ? x : u32x4{0u, 0u, 0u, 0u}; };
+    auto store = [&](int idx, int ci, const float4v &v) {
         const float4 o = make_float4(v[0], v[1], v[2], v[3]);
-        if (ci < c1) *reinterpret_cast<float4 *>(d1 + idx * c1 + ci) = o;
-        else *reinterpret_cast<float4 *>(d2 + idx * c2 + (ci - c1)) = o;
+        if (ci < c1) *reinterpret_cast<float4 *>(d1 + (size_t)idx * c1 + ci) = o;
+        else *reinterpret_cast<float4 *>(d2 + (size_t)idx * c2 + (ci - c1)) = o;
     };
-    conv_tiles<NT, TJ, TK, -1>(L, cout, wt, load, store);
+    conv_tiles<NT, TJ, TK, -1, false>(L, cout, wt, load, finish, store);
 }
 
 // -------------------------------------------------------- weight gradient

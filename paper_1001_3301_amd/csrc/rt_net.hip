@@ -119,6 +119,8 @@ rt_status ensure_ws(rt_net *net, int nr, int nt, int np, bool train)
     if (net->nr == nr && net->nt == nt && net->nph == np && (!train || net->train_ws)) return RT_OK;
     if (nr % 4 || nt % 4 || np % 4)
         return nfail(net, RT_EINVAL, "the network needs grid dimensions divisible by 4");
+    if ((long)nr * nt * np >= (1L << 31))
+        return nfail(net, RT_EINVAL, "the network needs fewer than 2^31 cells");
     free_list(net->ws);
     net->nr = nr; net->nt = nt; net->nph = np;
     net->train_ws = train;
@@ -477,7 +479,8 @@ rt_status rt_nn_conv3d_fwd(void *stream, int nr, int nt, int np, const void *x1,
                            int c2, const void *w, const float *bias, int cout, int relu, void *y, float *yf)
 {
     if (nr < 1 || nt < 1 || np < 1 || !x1 || c1 % 16 || c2 % 16 || c1 < 16 || (c2 && !x2) || !w || cout % 16 ||
-        cout < 16 || cout > 64 || (!y && !yf) || (up1 && (nr % 2 || nt % 2 || np % 2)))
+        cout < 16 || cout > 64 || (!y && !yf) || (up1 && (nr % 2 || nt % 2 || np % 2)) ||
+        (long)nr * nt * np >= (1L << 31))
         return nfail(nullptr, RT_EINVAL, "rt_nn_conv3d_fwd: bad arguments");
     Lv L{nr, nt, np, (long)nr * nt * np};
     conv_fwd(L, (const bf16 *)x1, c1, up1, (const bf16 *)x2, c2, (const bf16 *)w, bias, cout, relu, (bf16 *)y, yf,
@@ -490,7 +493,7 @@ rt_status rt_nn_conv3d_bwd_data(void *stream, int nr, int nt, int np, const floa
                                 const void *wt, int c1, float *d1, int c2, float *d2)
 {
     if (nr < 1 || nt < 1 || np < 1 || !dy || cout % 16 || cout < 16 || !wt || c1 % 16 || c2 % 16 || c1 < 16 || !d1 ||
-        (c2 && !d2) || ((c1 + c2) / 16 == 5) || (c1 + c2) > 96)
+        (c2 && !d2) || ((c1 + c2) / 16 == 5) || (c1 + c2) > 96 || (long)nr * nt * np >= (1L << 31))
         return nfail(nullptr, RT_EINVAL, "rt_nn_conv3d_bwd_data: bad arguments");
     Lv L{nr, nt, np, (long)nr * nt * np};
     conv_bwd_data(L, dy, (const bf16 *)yrelu, cout, (const bf16 *)wt, c1, d1, c2, d2, (hipStream_t)stream);
