@@ -134,7 +134,8 @@ typedef struct {
 
 typedef enum {
     RT_LAUNCH_AUTO = 0,   /* BLOCK where it applies, else GRAPH on grids of at most 4,194,304
-                             cells (where launches dominate), else DIRECT */
+                             cells (where launches dominate), else DIRECT; in rt_relax, with
+                             BLOCK, whole steps are replayed from one HIP graph */
     RT_LAUNCH_DIRECT = 1, /* every kernel launched from the host; the only choice that samples
                              the kernel times of rt_solve_stats */
     RT_LAUNCH_GRAPH = 2,  /* the chunks of iterations between convergence polls replayed from
@@ -307,7 +308,14 @@ typedef struct {
  * tol_change = 1e-4): rt_step until max_c |T^{n+1}_c - T^n_c| / T^n_c < tol_change or
  * max_steps steps.  T: start temperature in, the last iterate out; E: E^{n+1} of the
  * last step.  o->mode = RT_SOLVE_NONE runs the loop without diffusion.  Synchronises
- * once per step to read the change back.  Returns RT_ENOCONV when max_steps pass
+ * once per step to read the change back.  With o->launch = RT_LAUNCH_AUTO, a loop whose
+ * steps solve with the reduced float64 CG in one workgroup (RT_SOLVE_FP64, reduce = 1,
+ * at most 2048 black cells), or without diffusion, captures one step in a HIP graph at
+ * the start of the call and replays it every step (the solver's set-up on the device, one
+ * read-back per step); a step the replay cannot finish as the host-driven step would (a
+ * non-finite value, an iteration limit, a true residual above tol) is redone from its
+ * start temperature on that path, so the results are the same bits as with
+ * RT_LAUNCH_BLOCK, which launches every step from the host.  Returns RT_ENOCONV when max_steps pass
  * without reaching tol_change or a step's solve hits its limit (outputs hold the last
  * iterate), RT_ENONFINITE for a non-finite temperature.  Allocates one float64 field
  * on the context at its first call. */

@@ -1276,6 +1276,22 @@ __global__ __launch_bounds__(kSB) void k_rb_cg_block(Dims dh, const double *__re
     }
 }
 
+__global__ void k_solve_init(DevScalars *sc, double tol2)
+{
+    if (threadIdx.x != 0) return;
+    const double bb = sc->res2 == 0.0 ? 1.0 : sc->res2;
+    sc->bnorm2 = bb;
+    sc->thresh2 = tol2 * bb;
+    sc->done = 0;
+    sc->iters = 0;
+    sc->beta = 0.0;
+}
+
+void launch_solve_init(DevScalars *sc, double tol2, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(64), 0, st, sc, tol2);
+}
+
 int rb_block_cpt(const Dims &dh)
 {
     const long c = (dh.n + kSB - 1) / kSB;

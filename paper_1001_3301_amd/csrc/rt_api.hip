@@ -1314,6 +1314,104 @@ rt_status solve_fp64_from(rt_ctx *ctx, double tol, int max_iter, double *y, rt_s
     RT_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return status == RT_ENOCONV ? RT_OK : status;
 }
+
+// ------------------------------------------------------------- step graph
+//
+// A main-loop step whose solve is the reduced float64 CG in one workgroup (or that runs
+// without transport) is a fixed sequence of launches once the solver's host set-up (the
+// stopping threshold from ||b^||^2, read back) moves to the device: rt_relax captures it
+// in one HIP graph and replays the graph every step, reading the scalars back once.  The
+// launches are those of rt_step with that solve, in the same order and with the same
+// arguments, except that the host's loop over chunks of iterations becomes one block
+// launch followed by the true residual; where the host-driven loop would have decided
+// otherwise (a non-finite value, a chunk used up, a true residual above tol) the step is
+// redone on that path from the saved temperature, so the results are the same bits.
+bool step_graph_applies(const rt_ctx *ctx, const rt_solve_opts *o)
+{
+    if (o->launch != RT_LAUNCH_AUTO) return false;
+    if (o->mode == RT_SOLVE_NONE) return true;
+    return o->mode == RT_SOLVE_FP64 && o->reduce && o->precond == 0 && o->tol > 0.0 && o->tol < 1.0 &&
+           o->max_iter > 0 && rb_possible(ctx) && use_block(o, rb_half(ctx->d));
+}
+
+int step_graph_chunk(const rt_solve_opts *o) { return std::min(kBlockChunk, o->max_iter); }
+
+// The step's launches on ctx->stream (T^n saved to ctx->Tn, the change written to the
+// scalars); no host synchronisation.
+rt_status enqueue_step(rt_ctx *ctx, const rt_fld_params *p, const rt_solve_opts *o, const double *rho, double *T,
+                       double *E)
+{
+    const long n = ctx->d.n;
+    hipStream_t s = ctx->stream;
+    RT_HIP(ctx, hipMemcpyAsync(ctx->Tn, T, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (rt_status e = rt_raytrace(ctx, nullptr, nullptr, rho, T, ctx->q, ctx->S, nullptr, nullptr)) return e;
+    if (rt_status e = rt_energy(ctx, nullptr, p, T, ctx->S, ctx->En)) return e;
+    if (rt_status e = rt_fld_assemble(ctx, nullptr, p, rho, T, ctx->En, ctx->q, nullptr, nullptr)) return e;
+    if (o->mode == RT_SOLVE_NONE) {
+        launch_fill(n, ctx->Eb, E, s);
+    } else {
+        RT_HIP(ctx, hipMemcpyAsync(E, ctx->En, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        launch_norm2(ctx->d, ctx->nblk, ctx->bhat, ctx->partials, ctx->counter, ctx->sc, s);
+        launch_solve_init(ctx->sc, o->tol * o->tol, s);
+        launch_scale_div(n, ctx->s, E, ctx->y, s);  // y0 = E / s
+        // the buffers of solve_fp64_rb
+        const Dims dh = rb_half(ctx->d);
+        const long nh = dh.n;
+        double *rb = ctx->r, *tr = ctx->r + nh, *pold = ctx->p0, *yb = ctx->qv + nh, *rhs = ctx->p1;
+        if (rt_status e = rb_prepare(ctx, rhs, yb, rb)) return e;
+        rb_resid(ctx, rhs, yb, rb, tr, 1);
+        if (!launch_rb_cg_block(dh, ctx->rb_a, yb, rb, pold, step_graph_chunk(o), ctx->sc, s))
+            return fail(ctx, RT_EDEVICE, "one-workgroup CG: grid too large");
+        rb_resid(ctx, rhs, yb, rb, tr, 1);
+        if (rt_status e = rb_finish(ctx, rhs, yb, tr)) return e;
+        launch_scale_mul(n, ctx->s, ctx->y, E, s);  // E = s y
+    }
+    launch_newton(ctx->d, ctx->op, E, ctx->S, T, s);
+    double *dchange = reinterpret_cast<double *>(reinterpret_cast<char *>(ctx->sc) + offsetof(DevScalars, change));
+    launch_max_change(n, ctx->nblk, T, ctx->Tn, ctx->partials, ctx->counter, dchange, s);
+    RT_HIP(ctx, hipGetLastError());
+    return RT_OK;
+}
+
+// Captures enqueue_step on the context's capture stream (ctx->stream may be the legacy
+// default stream, which cannot be captured) and instantiates it.
+rt_status capture_step(rt_ctx *ctx, const rt_fld_params *p, const rt_solve_opts *o, const double *rho, double *T,
+                       double *E, hipGraphExec_t *ex)
+{
+    *ex = nullptr;
+    if (o->mode != RT_SOLVE_NONE && !ctx->rb_a) {  // rb_prepare's allocation, made before capturing
+        ctx->rb_a = dalloc<double>(ctx, 3 * ctx->d.n);
+        ctx->rb_a32 = dalloc<float>(ctx, 3 * ctx->d.n);
+        if (!ctx->rb_a || !ctx->rb_a32) return fail(ctx, RT_ENOMEM, "red-black split: out of device memory");
+    }
+    if (!ctx->cap_stream) RT_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    const hipStream_t saved = ctx->stream;
+    RT_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    ctx->stream = ctx->cap_stream;
+    const rt_status e = enqueue_step(ctx, p, o, rho, T, E);
+    ctx->stream = saved;
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (e != RT_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return e;
+    }
+    if (ec != hipSuccess || !g) return fail(ctx, RT_EDEVICE, std::string("step capture: ") + hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(ctx, RT_EDEVICE, std::string("step graph instantiation: ") + hipGetErrorString(ei));
+    return RT_OK;
+}
+
+// Whether the host-driven step would have ended as the replay did (scalars read back).
+bool step_graph_result_ok(const DevScalars *h, const rt_solve_opts *o)
+{
+    if (!isfin(h->change)) return false;
+    if (o->mode == RT_SOLVE_NONE) return true;
+    if (!isfin(h->bnorm2) || !isfin(h->rr) || !isfin(h->res2)) return false;
+    const double res = std::sqrt(h->res2 / h->bnorm2);
+    return h->iters < step_graph_chunk(o) && h->done && res <= o->tol;
+}
 }  // namespace rt
 
 extern "C" {
@@ -1449,21 +1547,64 @@ rt_status rt_relax(rt_ctx *ctx, const rt_opacity *op, const rt_star *st, const r
     Clock clk;
     hipStream_t s = ctx->stream;
     rt_status status = RT_OK;
+    DevScalars *h = ctx->h_sc;
+    // steps replayed from one captured graph where they can be (see step_graph_applies)
+    struct GraphGuard {
+        hipGraphExec_t g = nullptr;
+        ~GraphGuard() { if (g) (void)hipGraphExecDestroy(g); }
+    } guard;
+    hipGraphExec_t &gx = guard.g;
+    if (step_graph_applies(ctx, o)) {
+        if (op) { rt_status e = rt_set_opacity(ctx, op); if (e) return e; }
+        if (st) { rt_status e = rt_set_star(ctx, st); if (e) return e; }
+        RT_CHECK(ctx, ctx->have_opac, "no opacity table on the context");
+        RT_CHECK(ctx, ctx->have_star, "no star on the context");
+        if (rt_status e = check_fld(ctx, p)) return e;
+        if (rt_status e = capture_step(ctx, p, o, rho, T, E, &gx)) return e;
+    }
     for (int k = 0; k < max_steps; k++) {
-        RT_HIP(ctx, hipMemcpyAsync(ctx->Tn, T, n * sizeof(double), hipMemcpyDeviceToDevice, s));
         rt_step_stats ss{};
-        // the tables are uploaded by the first step only
-        status = rt_step(ctx, k == 0 ? op : nullptr, k == 0 ? st : nullptr, p, o, rho, T, E, nullptr, &ss);
+        bool replayed = false;
+        if (gx) {
+            RT_HIP(ctx, hipEventRecord(ctx->ev[0], s));
+            RT_HIP(ctx, hipGraphLaunch(gx, s));
+            RT_HIP(ctx, hipEventRecord(ctx->ev[5], s));
+            if (rt_status e = read_scalars(ctx)) return e;
+            if (step_graph_result_ok(h, o)) {
+                replayed = true;
+                float t05 = 0.0f;
+                (void)hipEventElapsedTime(&t05, ctx->ev[0], ctx->ev[5]);
+                ss.ms_total = t05;
+                if (o->mode != RT_SOLVE_NONE) {
+                    ss.solve.iters = h->iters;
+                    ss.solve.relres = std::sqrt(h->res2 / h->bnorm2);
+                    ss.solve.reduced = 1;
+                }
+            } else {
+                // the host-driven path decides this step: from the saved temperature,
+                // with directions as after a failed solve
+                RT_HIP(ctx, hipMemcpyAsync(T, ctx->Tn, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+                if (rt_status e = reset_directions(ctx)) return e;
+            }
+        }
+        if (!replayed) {
+            RT_HIP(ctx, hipMemcpyAsync(ctx->Tn, T, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            // the tables are uploaded by the first step only
+            const bool first = k == 0 && !gx;
+            status = rt_step(ctx, first ? op : nullptr, first ? st : nullptr, p, o, rho, T, E, nullptr, &ss);
+        }
         R->steps = k + 1;
         R->krylov_iters += ss.solve.iters;
         R->ms_device += ss.ms_total;
         R->last = ss;
         if (status != RT_OK) break;
-        double *dchange = reinterpret_cast<double *>(reinterpret_cast<char *>(ctx->sc) + offsetof(DevScalars, change));
-        launch_max_change(n, ctx->nblk, T, ctx->Tn, ctx->partials, ctx->counter, dchange, s);
-        RT_HIP(ctx, hipGetLastError());
-        if (rt_status e = read_scalars(ctx)) return e;
-        R->last_change = ctx->h_sc->change;
+        if (!replayed) {
+            double *dchange = reinterpret_cast<double *>(reinterpret_cast<char *>(ctx->sc) + offsetof(DevScalars, change));
+            launch_max_change(n, ctx->nblk, T, ctx->Tn, ctx->partials, ctx->counter, dchange, s);
+            RT_HIP(ctx, hipGetLastError());
+            if (rt_status e = read_scalars(ctx)) return e;
+        }
+        R->last_change = h->change;
         if (!isfin(R->last_change)) {
             status = fail(ctx, RT_ENONFINITE, "rt_relax: non-finite temperature");
             break;

@@ -181,6 +181,7 @@ struct DevScalars {
     double res2;     // last reduction of the residual kernel
     double inv_norm; // 1 / sqrt(res2)
     double change;   // largest relative temperature change of the last main iteration
+    double bnorm2;   // ||b^||^2 of the solve (1 when b^ = 0), set on the device by k_solve_init
     int done;
     int iters;
 };
@@ -245,6 +246,9 @@ void launch_max_change(long n, int nblk, const double *T, const double *Told, do
 // CG iteration launches its update kernel with nblk_upd blocks.
 void launch_spmv(const Dims &d, int nblk, const double *a, const double *x, double *y, hipStream_t st);
 void launch_spmv32(const Dims &d, int nblk, const float *a, const float *x, float *y, hipStream_t st);
+// The host's set-up of a float64 CG solve done on the device, after launch_norm2 of b^:
+// bnorm2 = res2 (1 when 0), thresh2 = tol2 bnorm2, done = iters = 0, beta = 0.
+void launch_solve_init(DevScalars *sc, double tol2, hipStream_t st);
 void launch_norm2(const Dims &d, int nblk, const double *x, double *partials, unsigned *counter,
                   DevScalars *sc, hipStream_t st);
 void launch_resid(const Dims &d, int nblk, const double *a, const double *b, const double *y,

@@ -183,3 +183,54 @@ def test_relax_fixed_point_conserves_luminosity(gray):
     # the balance is a small difference of the solve's large time terms: per-step solves
     # to 1e-10 leave it at a few 1e-5 (the oracle's own loop reaches 3e-5 here)
     assert abs(L_out / L_abs - 1) < 3e-4, (L_out / L_abs - 1, st["steps"])
+
+
+@pytest.mark.parametrize("mode", ["fp64-rb", "none"])
+def test_step_graph_replays_the_host_driven_steps_bit_for_bit(mode):
+    """With the default launch the main loop replays each step from one captured graph
+    (one read-back per step); launched step by step (RT_LAUNCH_BLOCK) it runs the same
+    kernels from the host.  Same step count, Krylov iterations and bits."""
+    from paper_1001_3301_amd import rt
+    wl = sy.make_workload("t", 64, 16, 1, 16, 100.0, dt=1e4)
+    ctx = rt.Context.from_workload(wl, gray=mode == "none")
+    out = {}
+    for launch in (rt.LAUNCH_AUTO, rt.LAUNCH_BLOCK):
+        if mode == "none":
+            opts = rt.solve_opts(rt.MODE_NONE, launch=launch)
+        else:
+            opts = rt.solve_opts(rt.MODE_FP64, tol=1e-10, reduce=1, launch=launch)
+        T = torch.full((ctx.n,), wl.T_bc, dtype=torch.float64, device="cuda")
+        E = torch.empty_like(T)
+        rc, st = ctx.relax(_d(wl.rho), T, E, opts, tol_change=1e-4, max_steps=5000)
+        torch.cuda.synchronize()
+        assert rc == rt.RT_OK
+        out[launch] = (T.clone(), E.clone(), st)
+    (Ta, Ea, sa), (Tb, Eb, sb) = out[rt.LAUNCH_AUTO], out[rt.LAUNCH_BLOCK]
+    assert sa["steps"] == sb["steps"] and sa["krylov_iters"] == sb["krylov_iters"]
+    assert sa["last_change"] == sb["last_change"]
+    assert torch.equal(Ta, Tb) and torch.equal(Ea, Eb)
+    if mode != "none":
+        assert sa["steps"] > 10 and sa["krylov_iters"] > 0
+        assert sa["last"]["solve"]["iters"] == sb["last"]["solve"]["iters"]
+        assert sa["last"]["solve"]["relres"] == sb["last"]["solve"]["relres"] <= 1e-10
+
+
+def test_step_graph_hands_a_step_it_cannot_finish_to_the_host_driven_path():
+    """A step whose solve needs more than its iteration limit is redone on the host-driven
+    path from the saved temperature, which reports it: the same status and bits as that
+    path alone."""
+    from paper_1001_3301_amd import rt
+    wl = sy.make_workload("t", 64, 16, 1, 16, 100.0, dt=1e4)
+    ctx = rt.Context.from_workload(wl)
+    out = {}
+    for launch in (rt.LAUNCH_AUTO, rt.LAUNCH_BLOCK):
+        T = torch.full((ctx.n,), wl.T_bc, dtype=torch.float64, device="cuda")
+        E = torch.empty_like(T)
+        opts = rt.solve_opts(rt.MODE_FP64, tol=1e-10, reduce=1, max_iter=5, launch=launch)
+        rc, st = ctx.relax(_d(wl.rho), T, E, opts, tol_change=1e-4, max_steps=10, raise_on_error=False)
+        torch.cuda.synchronize()
+        out[launch] = (rc, T.clone(), E.clone(), st)
+    (ra, Ta, Ea, sa), (rb, Tb, Eb, sb) = out[rt.LAUNCH_AUTO], out[rt.LAUNCH_BLOCK]
+    assert ra == rb == rt.RT_ENOCONV
+    assert sa["steps"] == sb["steps"] == 1 and sa["krylov_iters"] == sb["krylov_iters"] == 5
+    assert torch.equal(Ta, Tb) and torch.equal(Ea, Eb)
