@@ -344,11 +344,173 @@ __device__ __forceinline__ void conv_tiles(const Lv &L, int cin, const bf16 *__r
     }
 }
 
+// ------------------------------------------------- sliding-window convolution
+//
+// The 16 -> 16 channel layers of the fine level (one input slice) move little data per
+// MFMA, and measured on gfx950 the tiled kernel above is bound by the L2 -> L1 requests
+// a compute unit can keep in flight (L1 stalled on pending requests 65 % of the time),
+// not by HBM or the matrix cores: its 32 x 4 x 4 tiles load 2.4 halo cells per output
+// cell.  (Sharing each activation fragment between the three phi offsets, with rolling
+// accumulators per output plane, halves the LDS reads but needs more registers than three
+// wavefronts per SIMD allow, and measured slower.)  Here a block owns a column of kTR x TJ cells
+// (r x theta) over a chunk of kSlideP phi planes and walks it plane by plane, keeping the
+// three halo planes a step reads (k - 1, k, k + 1) in a ring in LDS: each step loads one
+// new (kTR + 2) x (TJ + 2) plane (1.33 halo cells per output cell with TJ = 8), the one
+// the next step needs, into registers before its own MFMAs so the latency overlaps them,
+// and the weights stay resident.  The MFMA fragments and their order are those of conv_tiles; only the phi
+// offset of a tap becomes the ring slot of its plane.
+constexpr int kSlideTJ = 8;   // theta rows of a block
+constexpr int kSlideP = 32;   // phi planes of a block
+
+template <int TJ>
+struct SlidePlane {
+    static constexpr int HR = kTR + 2, HJ = TJ + 2;
+    static constexpr int cells = HR * HJ;
+    static constexpr int bytes = cells * 32;  // cell-major, 32 bytes (16 bf16 channels) a cell
+    static constexpr int per_wave = 2 * TJ / 4;  // 16-cell row segments of a wavefront per plane
+    static_assert(TJ % 2 == 0, "a wavefront owns pairs of theta rows");
+};
+
+// LDS bytes of one block: the ring of three halo planes plus the weights (28 taps).
+template <int TJ>
+constexpr size_t slide_lds_bytes() { return 3 * (size_t)SlidePlane<TJ>::bytes + 28 * 512; }
+
+// Forward convolution with 16 input and 16 output channels; load / finish / store as
+// for conv_tiles.  Item i of the grid: theta tile fastest, then r tile, then phi chunk;
+// gridDim.x is a multiple of 8 and the items of one eighth run on one XCD (block b on
+// XCD b % 8), so the blocks resident together are neighbours in theta and r and share
+// their halos in that XCD's L2.
+template <int TJ, class Load, class Finish, class Store>
+__device__ __forceinline__ void conv_slide(const Lv &L, const bf16 *__restrict__ w, Load load, Finish finish,
+                                           Store store)
+{
+    using P = SlidePlane<TJ>;
+    constexpr int PW = P::per_wave;
+    extern __shared__ uint4 smem_u4[];
+    char *lds = reinterpret_cast<char *>(smem_u4);
+    char *ws = lds + 3 * P::bytes;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int ntr = (L.nr + kTR - 1) / kTR, ntj = (L.nt + TJ - 1) / TJ, nch = (L.np + kSlideP - 1) / kSlideP;
+    const int nitems = ntr * ntj * nch;
+    const int item = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    if (item >= nitems) return;  // uniform over the block
+    const int q0 = item / ntj, tj = item - q0 * ntj, chunk = q0 / ntr, tr = q0 - chunk * ntr;
+    const int r0 = tr * kTR, j0 = tj * TJ, k0 = chunk * kSlideP;
+    const int k1 = min(L.np, k0 + kSlideP);
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    // weights of all 27 taps in fragment order, and the zero tap 27 that pads the last pair
+    constexpr int NW = (27 * 32 + kTB - 1) / kTB;
+    if (tid < 32) *reinterpret_cast<u32x4 *>(ws + (27 * 32 + tid) * 16) = u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int u = 0; u < NW; u++) {
+        const int q = tid + u * kTB;
+        if (q < 27 * 32) {
+            const int l32 = q & 31, tap = q >> 5;
+            *reinterpret_cast<u32x4 *>(ws + q * 16) =
+                *reinterpret_cast<const u32x4 *>(w + (tap * 16 + (l32 & 15)) * 16 + (l32 >> 4) * 8);
+        }
+    }
+    // one halo plane p (phi index, wrapped): loads issued into registers, written to a ring
+    // slot later (zeros outside r and theta)
+    constexpr int NL = (P::cells * 2 + kTB - 1) / kTB;
+    typedef decltype(load(0, 0, 0, 0, 0)) Raw;
+    auto fetch = [&](int p, Raw (&vv)[NL], unsigned &okm) __attribute__((always_inline)) {
+        okm = 0u;
+        const int cp = p < 0 ? p + L.np : (p >= L.np ? p - L.np : p);
+        static_for<0, NL>([&](auto uc) __attribute__((always_inline)) {
+            constexpr int u = decltype(uc)::value;
+            const int q = tid + u * kTB;
+            const int cell = q >> 1, h = q & 1;
+            const int hr = cell % P::HR, hj = cell / P::HR;
+            int a = r0 + hr - 1, b = j0 + hj - 1, c = cp;
+            const bool ok = q < P::cells * 2 && (unsigned)a < (unsigned)L.nr && (unsigned)b < (unsigned)L.nt;
+            if (!ok) a = b = c = 0;
+            okm |= (unsigned)ok << u;
+            vv[u] = load(a + L.nr * (b + L.nt * c), a, b, c, h * 8);
+        });
+    };
+    auto put = [&](int slot, const Raw (&vv)[NL], unsigned okm) __attribute__((always_inline)) {
+        char *pl = lds + slot * P::bytes;
+        static_for<0, NL>([&](auto uc) __attribute__((always_inline)) {
+            constexpr int u = decltype(uc)::value;
+            const int q = tid + u * kTB;
+            if (q < P::cells * 2) *reinterpret_cast<u32x4 *>(pl + q * 16) = finish(vv[u], (okm >> u) & 1u);
+        });
+    };
+    // planes k0 - 1, k0, k0 + 1 in slots 0, 1, 2 (plane p lives in slot (p - k0 + 1) mod 3)
+    Raw v[NL];
+    unsigned okm;
+    fetch(k0 - 1, v, okm);
+    put(0, v, okm);
+    fetch(k0, v, okm);
+    put(1, v, okm);
+    fetch(k0 + 1, v, okm);
+    put(2, v, okm);
+    // fragment bases: segment q of this wavefront is (rh = q & 1, theta row 2 wv + q / 2)
+    const int half = (lane >> 4) & 1;
+    const int xl = (2 * wv * P::HR + (lane & 15)) * 32 + half * 16;
+    const int wbase = ((lane >> 5) * 32 + (lane & 31)) * 16;
+    // Step k: the loads of plane k + 2 are issued, the MFMAs of planes k - 1 .. k + 1 run,
+    // and after a barrier plane k + 2 replaces plane k - 1 in the ring, before this step's
+    // outputs are stored: the wait for its loads then finds nothing younger in flight
+    // (loads and stores share one counter, and conditional stores would make it wait for
+    // every store of the previous step).
+    __syncthreads();
+    for (int k = k0; k < k1; k++) {
+        const bool more = k + 2 <= k1;
+        if (more) fetch(k + 2, v, okm);  // in flight during the MFMAs
+        // ring slots of planes k - 1, k, k + 1 (taps with phi offset dk = 0, 1, 2)
+        const int sb0 = ((k - k0) % 3) * P::bytes, sb1 = ((k - k0 + 1) % 3) * P::bytes,
+                  sb2 = ((k - k0 + 2) % 3) * P::bytes;
+        float4v acc[PW];
+#pragma unroll
+        for (int q = 0; q < PW; q++) acc[q] = float4v{0.f, 0.f, 0.f, 0.f};
+        auto frags = [&](auto pc, bf16x8 (&bf)[PW], bf16x8 &af) {
+            constexpr int p = decltype(pc)::value;
+            constexpr int ta = 2 * p, tb = (2 * p + 1 < 27) ? 2 * p + 1 : 13;
+            constexpr int oa = (((ta / 3) % 3) * P::HR + ta % 3) * 32;
+            constexpr int ob = (((tb / 3) % 3) * P::HR + tb % 3) * 32;
+            const int sa = ta / 9 == 0 ? sb0 : (ta / 9 == 1 ? sb1 : sb2);
+            const int sbb = tb / 9 == 0 ? sb0 : (tb / 9 == 1 ? sb1 : sb2);
+            const char *xp = lds + xl + ((lane < 32) ? sa + oa : sbb + ob);
+#pragma unroll
+            for (int q = 0; q < PW; q++)
+                bf[q] = *reinterpret_cast<const bf16x8 *>(xp + ((q >> 1) * P::HR + (q & 1) * 16) * 32);
+            af = *reinterpret_cast<const bf16x8 *>(ws + wbase + 2 * p * 32 * 16);
+        };
+        auto mma = [&](const bf16x8 (&bf)[PW], const bf16x8 &af) {
+#pragma unroll
+            for (int q = 0; q < PW; q++) acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[q], acc[q], 0, 0, 0);
+        };
+        bf16x8 b0[PW], b1[PW], a0, a1;
+        frags(std::integral_constant<int, 0>{}, b0, a0);
+        static_for<0, 7>([&](auto i) {
+            constexpr int p = 2 * decltype(i)::value;
+            frags(std::integral_constant<int, p + 1>{}, b1, a1);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(b0, a0);
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (p + 2 < 14) frags(std::integral_constant<int, p + 2>{}, b0, a0);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(b1, a1);
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        __syncthreads();  // every wavefront is done with the slot of plane k - 1
+        if (more) put((k - k0) % 3, v, okm);
+#pragma unroll
+        for (int q = 0; q < PW; q++) {
+            const int a = r0 + (q & 1) * 16 + (lane & 15), b = j0 + 2 * wv + (q >> 1);
+            if (a < L.nr && b < L.nt) store(a + L.nr * (b + L.nt * k), 4 * (lane >> 4), acc[q]);
+        }
+        __syncthreads();  // plane k + 2 is in the ring for the next step
+    }
+}
+
 // y = act(conv([up?(x1), x2], w) + bias) with NT * 16 output channels.  x1 has c1
 // channels and lives on the level of y (up1 = 0) or on the next coarser level
 // (up1 = 1, read through nearest-neighbour upsampling); x2 (c2 channels, may be 0) on
 // the level of y.  Writes bf16 y and/or fp32 yf.
-template <int NT, int TJ, int TK>
+template <int NT, int TJ, int TK, bool SLIDE = false>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(NT == 1 ? 3 : 2, 8))) void k_conv_fwd(
     Lv L, const bf16 *__restrict__ x1, int c1, int up1, const bf16 *__restrict__ x2, int c2,
     const bf16 *__restrict__ w, const float *__restrict__ bias, int relu, bf16 *__restrict__ y, float *__restrict__ yf)
@@ -384,7 +546,8 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(NT == 1 ? 3
         if (y) *reinterpret_cast<uint2 *>(y + (size_t)idx * cout + co) = make_uint2(pack_bf16(o[0], o[1]), pack_bf16(o[2], o[3]));
         if (yf) *reinterpret_cast<float4 *>(yf + (size_t)idx * cout + co) = make_float4(o[0], o[1], o[2], o[3]);
     };
-    conv_tiles<NT, TJ, TK, 1, false>(L, c1 + c2, w, load, finish, store);
+    if constexpr (SLIDE) conv_slide<TJ>(L, w, load, finish, store);  // NT = 1, c1 + c2 = 16
+    else conv_tiles<NT, TJ, TK, 1, false>(L, c1 + c2, w, load, finish, store);
 }
 
 // Layer 0 of the preconditioner's application with its input built on the fly: channel
@@ -393,6 +556,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(NT == 1 ? 3
 // read), channels 8..15 are zero and not loaded.  The same operands, bit for bit, as
 // k_set_input followed by k_conv_fwd<1,4,4> on X, without writing X (16 output
 // channels, bias, ReLU, bf16 out).
+template <bool SLIDE>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_conv_fwd_in(
     Lv L, const bf16 *__restrict__ X, const float *__restrict__ r, const double *__restrict__ scale,
     const bf16 *__restrict__ w, const float *__restrict__ bias, bf16 *__restrict__ y)
@@ -421,7 +585,8 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         for (int i = 0; i < 4; i++) o[i] = o[i] < 0.0f ? 0.0f : o[i];
         *reinterpret_cast<uint2 *>(y + (size_t)idx * 16 + co) = make_uint2(pack_bf16(o[0], o[1]), pack_bf16(o[2], o[3]));
     };
-    conv_tiles<1, 4, 4, 1, false>(L, 16, w, load, finish, store);
+    if constexpr (SLIDE) conv_slide<kSlideTJ>(L, w, load, finish, store);
+    else conv_tiles<1, 4, 4, 1, false>(L, 16, w, load, finish, store);
 }
 
 // ------------------------------------------------------------ data gradient
@@ -897,6 +1062,25 @@ void launch_fwd_t(const Lv &L, const bf16 *x1, int c1, int up1, const bf16 *x2, 
                        c2, w, b, relu, y, yf);
 }
 
+// One block per (theta tile, r tile, phi chunk) of conv_slide, rounded up to a multiple of 8.
+unsigned slide_grid(const Lv &L)
+{
+    const long n = (long)((L.nr + kTR - 1) / kTR) * ((L.nt + kSlideTJ - 1) / kSlideTJ) *
+                   ((L.np + kSlideP - 1) / kSlideP);
+    return (unsigned)((n + 7) / 8 * 8);
+}
+
+void launch_fwd_slide(const Lv &L, const bf16 *x1, int c1, int up1, const bf16 *x2, int c2, const bf16 *w,
+                      const float *b, int relu, bf16 *y, float *yf, hipStream_t s)
+{
+    constexpr size_t lds = slide_lds_bytes<kSlideTJ>();
+    static const bool attr = hipFuncSetAttribute((const void *)k_conv_fwd<1, kSlideTJ, 1, true>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
+    (void)attr;
+    hipLaunchKernelGGL((k_conv_fwd<1, kSlideTJ, 1, true>), dim3(slide_grid(L)), dim3(kTB), lds, s, L, x1, c1, up1, x2,
+                       c2, w, b, relu, y, yf);
+}
+
 template <int NT, int TJ, int TK>
 void launch_bwd_t(const Lv &L, const float *dy, const bf16 *y, int cout, const bf16 *wt, int c1, float *d1, int c2,
                   float *d2, hipStream_t s)
@@ -916,7 +1100,10 @@ bool launch_conv_fwd(const Lv &L, const bf16 *x1, int c1, int up1, const bf16 *x
 {
     if ((c1 + c2) % 16 || c1 % 16) return false;
     switch (cout) {
-    case 16: launch_fwd_t<1, 4, 4>(L, x1, c1, up1, x2, c2, w, b, relu, y, yf, s); return true;
+    case 16:
+        if (c1 + c2 == 16) launch_fwd_slide(L, x1, c1, up1, x2, c2, w, b, relu, y, yf, s);
+        else launch_fwd_t<1, 4, 4>(L, x1, c1, up1, x2, c2, w, b, relu, y, yf, s);
+        return true;
     case 32: launch_fwd_t<2, 4, 4>(L, x1, c1, up1, x2, c2, w, b, relu, y, yf, s); return true;
     case 48: launch_fwd_t<3, 4, 2>(L, x1, c1, up1, x2, c2, w, b, relu, y, yf, s); return true;
     case 64: launch_fwd_t<4, 4, 2>(L, x1, c1, up1, x2, c2, w, b, relu, y, yf, s); return true;
@@ -1012,12 +1199,11 @@ void launch_out_fwd(long n, const bf16 *x, const bf16 *w, const float *b, const 
 void launch_conv_fwd_in(const Lv &L, const bf16 *X, const float *r, const double *scale, const bf16 *w,
                         const float *b, bf16 *y, hipStream_t s)
 {
-    constexpr size_t lds = conv_lds_bytes<1, 4, 4>();
-    static const bool attr = hipFuncSetAttribute((const void *)k_conv_fwd_in,
+    constexpr size_t lds = slide_lds_bytes<kSlideTJ>();
+    static const bool attr = hipFuncSetAttribute((const void *)k_conv_fwd_in<true>,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
     (void)attr;
-    hipLaunchKernelGGL(k_conv_fwd_in, dim3(conv_grid<4, 4>(L, (const void *)k_conv_fwd_in, lds)), dim3(kTB), lds, s, L,
-                       X, r, scale, w, b, y);
+    hipLaunchKernelGGL(k_conv_fwd_in<true>, dim3(slide_grid(L)), dim3(kTB), lds, s, L, X, r, scale, w, b, y);
 }
 
 // 1x1 output layer backward: dx, and dw[16], db into dwb[17]; part holds ceil(n/2048)*17.

@@ -75,6 +75,13 @@ FULL_TILE_CASES = [
     ((72, 10, 6), 32, 1, 16, 16),
 ]
 CONV_CASES_ALL = CONV_CASES + FULL_TILE_CASES
+# The 16 -> 16 forward convolutions walk phi in chunks of 32 planes with 32 x 8 cell
+# columns: 70 phi planes give two full chunks and a partial one (whose halo wraps to
+# plane 0), 18 theta rows two full and a partial theta tile; also with the upsampled input.
+SLIDE_CASES = [
+    ((72, 18, 70), 16, 0, 0, 16),
+    ((40, 12, 36), 16, 1, 0, 16),
+]
 
 
 def _conv_inputs(case, seed):
@@ -94,7 +101,7 @@ def _conv_inputs(case, seed):
     return n, x1, x2, w, b, xcat, cin
 
 
-@pytest.mark.parametrize("case", CONV_CASES_ALL, ids=[str(c) for c in CONV_CASES_ALL])
+@pytest.mark.parametrize("case", CONV_CASES_ALL + SLIDE_CASES, ids=[str(c) for c in CONV_CASES_ALL + SLIDE_CASES])
 def test_conv_forward_parity(case):
     from paper_1001_3301_amd import rt
     shape, c1, up1, c2, cout = case
