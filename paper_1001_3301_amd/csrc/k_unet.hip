@@ -589,6 +589,239 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     else conv_tiles<1, 4, 4, 1, false>(L, 16, w, load, finish, store);
 }
 
+// ------------------------------------------ sliding decoder convolution (fine level)
+//
+// The fine level's decoder layer: y = relu(conv([up(x1), x2], w) + bias) with x1 the 32
+// channels of level 1 read through nearest-neighbour upsampling, x2 the 16 skip channels
+// and 16 output channels.  A block of kDecWaves wavefronts owns a column of kTR x
+// kDecTJ cells (r x theta) over a chunk of kSlideP phi planes and walks it plane by
+// plane like conv_slide.  The skip channels keep conv_slide's ring of three fine halo
+// planes.  The upsampled channels are never expanded: the ring holds the coarse planes
+// themselves (an 18 x 10 cell halo plane covers the fine (kTR + 2) x (kDecTJ + 2)
+// plane), one new coarse plane every second step, and each fine cell's tap reads its
+// coarse parent.  For those channels K = 32 is one tap x the 32 channels (lanes 0..31
+// the first 16, lanes 32..63 the other 16), so 27 MFMAs per segment and no padding tap;
+// the skip channels use conv_slide's tap pairs.  Same operands and the same FP32 sums as
+// the tiled kernel, only ordered differently.
+constexpr int kDecWaves = 8;
+constexpr int kDecTB = 64 * kDecWaves;
+constexpr int kDecTJ = 2 * kDecWaves;  // theta rows of a block (two per wavefront)
+
+struct DecGeom {
+    static constexpr int HR = kTR + 2, HJ = kDecTJ + 2;     // fine halo plane
+    static constexpr int fine_bytes = HR * HJ * 32;         // 16 channels a cell
+    static constexpr int CR = kTR / 2 + 2, CJ = kDecTJ / 2 + 2;  // coarse halo plane
+    static constexpr int cslice_bytes = CR * CJ * 32;       // one 16-channel slice
+    static constexpr int coarse_bytes = 2 * cslice_bytes;
+    static constexpr int wskip_bytes = 28 * 32 * 16;        // tap pairs, zero tap 27
+    static constexpr int wup_bytes = 27 * 64 * 16;
+    static constexpr int lds = 3 * fine_bytes + 3 * coarse_bytes + wskip_bytes + wup_bytes;
+};
+
+__global__ __launch_bounds__(kDecTB) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_conv_fwd_dec(
+    Lv L, const bf16 *__restrict__ x1, const bf16 *__restrict__ x2, const bf16 *__restrict__ w,
+    const float *__restrict__ bias, int relu, bf16 *__restrict__ y, float *__restrict__ yf)
+{
+    using G = DecGeom;
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    extern __shared__ uint4 smem_u4[];
+    char *lds = reinterpret_cast<char *>(smem_u4);
+    char *cring = lds + 3 * G::fine_bytes;
+    char *wsk = cring + 3 * G::coarse_bytes;
+    char *wup = wsk + G::wskip_bytes;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int cr = L.nr >> 1, ct = L.nt >> 1, cp = L.np >> 1;
+    const int ntr = (L.nr + kTR - 1) / kTR, ntj = (L.nt + kDecTJ - 1) / kDecTJ, nch = (L.np + kSlideP - 1) / kSlideP;
+    const int nitems = ntr * ntj * nch;
+    const int item = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    if (item >= nitems) return;  // uniform over the block
+    const int q0 = item / ntj, tj = item - q0 * ntj, chunk = q0 / ntr, tr = q0 - chunk * ntr;
+    const int r0 = tr * kTR, j0 = tj * kDecTJ, k0 = chunk * kSlideP;  // all even
+    const int k1 = min(L.np, k0 + kSlideP);
+    const int c0 = (k0 >> 1) - 1;  // coarse plane c lives in ring slot (c - c0) mod 3
+    // weights: skip channels 32..47 as tap pairs [tap][co + 16 half], up channels 0..31 as
+    // [tap][co + 16 (ci / 8)]
+    if (tid < 32) *reinterpret_cast<u32x4 *>(wsk + (27 * 32 + tid) * 16) = u32x4{0u, 0u, 0u, 0u};
+    for (int q = tid; q < 27 * 32 + 27 * 64; q += kDecTB) {
+        if (q < 27 * 32) {
+            const int l32 = q & 31, tap = q >> 5;
+            *reinterpret_cast<u32x4 *>(wsk + q * 16) =
+                *reinterpret_cast<const u32x4 *>(w + (tap * 16 + (l32 & 15)) * 48 + 32 + (l32 >> 4) * 8);
+        } else {
+            const int u = q - 27 * 32, l64 = u & 63, tap = u >> 6;
+            *reinterpret_cast<u32x4 *>(wup + u * 16) =
+                *reinterpret_cast<const u32x4 *>(w + (tap * 16 + (l64 & 15)) * 48 + (l64 >> 4) * 8);
+        }
+    }
+    // fine skip plane p (wrapped in phi): 16-byte loads into registers, zeros outside r, theta
+    constexpr int NL = (G::HR * G::HJ * 2 + kDecTB - 1) / kDecTB;
+    auto fetch = [&](int p, u32x4 (&vv)[NL], unsigned &okm) __attribute__((always_inline)) {
+        okm = 0u;
+        const int pp = p < 0 ? p + L.np : (p >= L.np ? p - L.np : p);
+        static_for<0, NL>([&](auto uc) __attribute__((always_inline)) {
+            constexpr int u = decltype(uc)::value;
+            const int q = tid + u * kDecTB;
+            const int cell = q >> 1, h = q & 1;
+            const int hr = cell % G::HR, hj = cell / G::HR;
+            int a = r0 + hr - 1, b = j0 + hj - 1;
+            const bool ok = q < G::HR * G::HJ * 2 && (unsigned)a < (unsigned)L.nr && (unsigned)b < (unsigned)L.nt;
+            const int idx = ok ? a + L.nr * (b + L.nt * pp) : 0;
+            okm |= (unsigned)ok << u;
+            vv[u] = *reinterpret_cast<const u32x4 *>(x2 + (size_t)idx * 16 + h * 8);
+        });
+    };
+    auto put = [&](int slot, const u32x4 (&vv)[NL], unsigned okm) __attribute__((always_inline)) {
+        char *pl = lds + slot * G::fine_bytes;
+        static_for<0, NL>([&](auto uc) __attribute__((always_inline)) {
+            constexpr int u = decltype(uc)::value;
+            const int q = tid + u * kDecTB;
+            if (q < G::HR * G::HJ * 2)
+                *reinterpret_cast<u32x4 *>(pl + q * 16) = ((okm >> u) & 1u) ? vv[u] : u32x4{0u, 0u, 0u, 0u};
+        });
+    };
+    // coarse plane c (wrapped): 18 x 10 cells x 64 bytes, four 16-byte pieces a cell
+    // (slice s = piece / 2, half h = piece % 2) stored slice-major, 32 bytes a cell
+    constexpr int NC = (G::CR * G::CJ * 4 + kDecTB - 1) / kDecTB;
+    auto fetch_c = [&](int c, u32x4 (&vv)[NC], unsigned &okm) __attribute__((always_inline)) {
+        okm = 0u;
+        const int cc = c < 0 ? c + cp : (c >= cp ? c - cp : c);
+        static_for<0, NC>([&](auto uc) __attribute__((always_inline)) {
+            constexpr int u = decltype(uc)::value;
+            const int q = tid + u * kDecTB;
+            const int cell = q >> 2, piece = q & 3;
+            const int hr = cell % G::CR, hj = cell / G::CR;
+            const int a = (r0 >> 1) - 1 + hr, b = (j0 >> 1) - 1 + hj;
+            const bool ok = q < G::CR * G::CJ * 4 && (unsigned)a < (unsigned)cr && (unsigned)b < (unsigned)ct;
+            const int idx = ok ? a + cr * (b + ct * cc) : 0;
+            okm |= (unsigned)ok << u;
+            vv[u] = *reinterpret_cast<const u32x4 *>(x1 + (size_t)idx * 32 + piece * 8);
+        });
+    };
+    auto put_c = [&](int slot, const u32x4 (&vv)[NC], unsigned okm) __attribute__((always_inline)) {
+        char *pl = cring + slot * G::coarse_bytes;
+        static_for<0, NC>([&](auto uc) __attribute__((always_inline)) {
+            constexpr int u = decltype(uc)::value;
+            const int q = tid + u * kDecTB;
+            const int cell = q >> 2, piece = q & 3;
+            if (q < G::CR * G::CJ * 4)
+                *reinterpret_cast<u32x4 *>(pl + (piece >> 1) * G::cslice_bytes + cell * 32 + (piece & 1) * 16) =
+                    ((okm >> u) & 1u) ? vv[u] : u32x4{0u, 0u, 0u, 0u};
+        });
+    };
+    // prologue: fine planes k0 - 1 .. k0 + 1 in slots 0..2, coarse planes c0, c0 + 1
+    {
+        u32x4 v[NL];
+        unsigned okm;
+        fetch(k0 - 1, v, okm);
+        put(0, v, okm);
+        fetch(k0, v, okm);
+        put(1, v, okm);
+        fetch(k0 + 1, v, okm);
+        put(2, v, okm);
+        u32x4 vc[NC];
+        fetch_c(c0, vc, okm);
+        put_c(0, vc, okm);
+        fetch_c(c0 + 1, vc, okm);
+        put_c(1, vc, okm);
+    }
+    const float4 bb = bias ? *reinterpret_cast<const float4 *>(bias + 4 * (lane >> 4)) : make_float4(0.f, 0.f, 0.f, 0.f);
+    // fragment bases.  Skip (fine ring, conv_slide's layout): segment q of this wavefront is
+    // (rh = q & 1, theta row 2 wv + q / 2).  Up (coarse ring): lane l reads 8 channels
+    // (slice l / 32, half (l / 16) % 2) of the coarse parent of its cell's neighbour; the
+    // parent's r offset depends on the cell's parity (a per-lane base for each di), its
+    // theta offset on the segment's row and dj (compile-time).
+    constexpr int PW = 4;
+    const int e = lane & 15;
+    const int xl = (2 * wv * G::HR + e) * 32 + ((lane >> 4) & 1) * 16;
+    const int wbs = ((lane >> 5) * 32 + (lane & 31)) * 16;
+    const int cl = (lane >> 5) * G::cslice_bytes + ((lane >> 4) & 1) * 16 + (wv + 1) * G::CR * 32;
+    const int ub[3] = {cl + (((e - 1) >> 1) + 1) * 32, cl + ((e >> 1) + 1) * 32, cl + (((e + 1) >> 1) + 1) * 32};
+    u32x4 v[NL], vc[NC];
+    unsigned okm = 0u, okc = 0u;
+    __syncthreads();
+    for (int k = k0; k < k1; k++) {
+        const bool more = k + 2 <= k1;
+        const bool cmore = ((k & 1) == 0) && k + 1 < k1;
+        if (more) fetch(k + 2, v, okm);            // in flight during the MFMAs
+        if (cmore) fetch_c((k >> 1) + 1, vc, okc);
+        const int sb0 = ((k - k0) % 3) * G::fine_bytes, sb1 = ((k - k0 + 1) % 3) * G::fine_bytes,
+                  sb2 = ((k - k0 + 2) % 3) * G::fine_bytes;
+        // coarse ring slots of the planes under fine planes k - 1, k, k + 1
+        const int cs0 = (((k - 1) >> 1) - c0) % 3 * G::coarse_bytes, cs1 = ((k >> 1) - c0) % 3 * G::coarse_bytes,
+                  cs2 = (((k + 1) >> 1) - c0) % 3 * G::coarse_bytes;
+        float4v acc[PW];
+#pragma unroll
+        for (int q = 0; q < PW; q++) acc[q] = float4v{0.f, 0.f, 0.f, 0.f};
+        // group g < 27: up tap g; g >= 27: skip tap pair g - 27
+        auto frags = [&](auto gc, bf16x8 (&bf)[PW], bf16x8 &af) __attribute__((always_inline)) {
+            constexpr int g = decltype(gc)::value;
+            if constexpr (g < 27) {
+                constexpr int di = g % 3 - 1, dj = (g / 3) % 3 - 1, dk = g / 9;
+                const int cs = dk == 0 ? cs0 : (dk == 1 ? cs1 : cs2);
+                const char *xp = cring + cs + ub[di + 1];
+#pragma unroll
+                for (int q = 0; q < PW; q++) {
+                    const int off = ((q & 1) * 8 + ((((q >> 1) + dj) >> 1)) * G::CR) * 32;
+                    bf[q] = *reinterpret_cast<const bf16x8 *>(xp + off);
+                }
+                af = *reinterpret_cast<const bf16x8 *>(wup + (g * 64 + lane) * 16);
+            } else {
+                constexpr int p = g - 27;
+                constexpr int ta = 2 * p, tb = (2 * p + 1 < 27) ? 2 * p + 1 : 13;
+                constexpr int oa = (((ta / 3) % 3) * G::HR + ta % 3) * 32;
+                constexpr int ob = (((tb / 3) % 3) * G::HR + tb % 3) * 32;
+                const int sa = ta / 9 == 0 ? sb0 : (ta / 9 == 1 ? sb1 : sb2);
+                const int sbb = tb / 9 == 0 ? sb0 : (tb / 9 == 1 ? sb1 : sb2);
+                const char *xp = lds + xl + ((lane < 32) ? sa + oa : sbb + ob);
+#pragma unroll
+                for (int q = 0; q < PW; q++)
+                    bf[q] = *reinterpret_cast<const bf16x8 *>(xp + ((q >> 1) * G::HR + (q & 1) * 16) * 32);
+                af = *reinterpret_cast<const bf16x8 *>(wsk + wbs + 2 * p * 32 * 16);
+            }
+        };
+        auto mma = [&](const bf16x8 (&bf)[PW], const bf16x8 &af) __attribute__((always_inline)) {
+#pragma unroll
+            for (int q = 0; q < PW; q++) acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[q], acc[q], 0, 0, 0);
+        };
+        constexpr int NG = 27 + 14;
+        bf16x8 bA[PW], bB[PW], aA, aB;
+        frags(std::integral_constant<int, 0>{}, bA, aA);
+        static_for<0, NG>([&](auto gc) __attribute__((always_inline)) {
+            constexpr int g = decltype(gc)::value;
+            if constexpr (g % 2 == 0) {
+                if constexpr (g + 1 < NG) frags(std::integral_constant<int, g + 1>{}, bB, aB);
+                __builtin_amdgcn_sched_barrier(0);
+                mma(bA, aA);
+                __builtin_amdgcn_sched_barrier(0);
+            } else {
+                if constexpr (g + 1 < NG) frags(std::integral_constant<int, g + 1>{}, bA, aA);
+                __builtin_amdgcn_sched_barrier(0);
+                mma(bB, aB);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        });
+        __syncthreads();  // every wavefront is done with the slots being replaced
+        if (more) put((k - k0) % 3, v, okm);
+        if (cmore) put_c(((k >> 1) + 1 - c0) % 3, vc, okc);
+#pragma unroll
+        for (int q = 0; q < PW; q++) {
+            const int a = r0 + (q & 1) * 16 + e, b = j0 + 2 * wv + (q >> 1);
+            if (a < L.nr && b < L.nt) {
+                const size_t idx = (size_t)(a + L.nr * (b + L.nt * k));
+                const int co = 4 * (lane >> 4);
+                float o[4] = {acc[q][0] + bb.x, acc[q][1] + bb.y, acc[q][2] + bb.z, acc[q][3] + bb.w};
+                if (relu) {
+#pragma unroll
+                    for (int i = 0; i < 4; i++) o[i] = o[i] < 0.0f ? 0.0f : o[i];
+                }
+                if (y) *reinterpret_cast<uint2 *>(y + idx * 16 + co) = make_uint2(pack_bf16(o[0], o[1]), pack_bf16(o[2], o[3]));
+                if (yf) *reinterpret_cast<float4 *>(yf + idx * 16 + co) = make_float4(o[0], o[1], o[2], o[3]);
+            }
+        }
+        __syncthreads();  // the new planes are in the rings for the next step
+    }
+}
+
 // ------------------------------------------------------------ data gradient
 
 // dX = conv^T(dYm, w) for the concatenated input [up?(x1), x2] of a convolution with
@@ -793,22 +1026,37 @@ __global__ __launch_bounds__(kTB) void k_bias_parts(long n, int cout, const floa
 
 // ------------------------------------------------------- pooling / upsampling
 
-// 2x2x2 average pooling (bf16 in / out, fp32 arithmetic); coarse level Lc.
+// 2x2x2 average pooling (bf16 in / out, fp32 arithmetic, the 8 children summed in the
+// order r, theta, phi); coarse level Lc.  A thread owns 8 channels of one coarse cell:
+// eight 16-byte loads (the children, two by two adjacent in r) and one 16-byte store.
 __global__ __launch_bounds__(kTB) void k_pool(Lv Lc, int C, const bf16 *__restrict__ x, bf16 *__restrict__ y)
 {
-    long idx = (long)blockIdx.x * kTB + threadIdx.x;
-    if (idx >= Lc.n * C) return;
-    const long g = idx / C;
-    const int ch = (int)(idx % C);
+    const int ng = C >> 3;
+    const long idx = (long)blockIdx.x * kTB + threadIdx.x;
+    if (idx >= Lc.n * ng) return;
+    const long g = idx / ng;
+    const int ch = (int)(idx - g * ng) * 8;
     int I, J, K;
     cell_coords(Lc, g, I, J, K);
-    const int fr = 2 * Lc.nr, ft = 2 * Lc.nt;
-    float s = 0.0f;
+    const long fr = 2 * Lc.nr, ft = 2 * Lc.nt;
+    uint4 u[8];
+#pragma unroll
     for (int q = 0; q < 8; q++) {
-        long f = (2 * I + (q & 1)) + (long)fr * ((2 * J + ((q >> 1) & 1)) + (long)ft * (2 * K + (q >> 2)));
-        s += bf2f(x[f * C + ch]);
+        const long f = (2 * I + (q & 1)) + fr * ((2 * J + ((q >> 1) & 1)) + ft * (2 * K + (q >> 2)));
+        u[q] = *reinterpret_cast<const uint4 *>(x + f * C + ch);
     }
-    y[idx] = f2bf(s * 0.125f);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        const unsigned wd[4] = {u[q].x, u[q].y, u[q].z, u[q].w};
+#pragma unroll
+        for (int e = 0; e < 8; e++) s[e] += bf2f((bf16)(e & 1 ? wd[e >> 1] >> 16 : wd[e >> 1] & 0xFFFFu));
+    }
+    unsigned o[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++)
+        o[e] = (unsigned)f2bf(s[2 * e] * 0.125f) | ((unsigned)f2bf(s[2 * e + 1] * 0.125f) << 16);
+    *reinterpret_cast<uint4 *>(y + g * C + ch) = make_uint4(o[0], o[1], o[2], o[3]);
 }
 
 // dx_fine += dy_coarse / 8 (pooling adjoint), fine level Lf.
@@ -1081,6 +1329,20 @@ void launch_fwd_slide(const Lv &L, const bf16 *x1, int c1, int up1, const bf16 *
                        c2, w, b, relu, y, yf);
 }
 
+// One block per (theta tile, r tile, phi chunk) of k_conv_fwd_dec, rounded up to a
+// multiple of 8 (the fine level's dimensions are even: it has a coarser level).
+void launch_fwd_dec(const Lv &L, const bf16 *x1, const bf16 *x2, const bf16 *w, const float *b, int relu, bf16 *y,
+                    float *yf, hipStream_t s)
+{
+    constexpr size_t lds = DecGeom::lds;
+    static const bool attr = hipFuncSetAttribute((const void *)k_conv_fwd_dec, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds) == hipSuccess;
+    (void)attr;
+    const long n = (long)((L.nr + kTR - 1) / kTR) * ((L.nt + kDecTJ - 1) / kDecTJ) * ((L.np + kSlideP - 1) / kSlideP);
+    hipLaunchKernelGGL(k_conv_fwd_dec, dim3((unsigned)((n + 7) / 8 * 8)), dim3(kDecTB), lds, s, L, x1, x2, w, b, relu,
+                       y, yf);
+}
+
 template <int NT, int TJ, int TK>
 void launch_bwd_t(const Lv &L, const float *dy, const bf16 *y, int cout, const bf16 *wt, int c1, float *d1, int c2,
                   float *d2, hipStream_t s)
@@ -1102,6 +1364,7 @@ bool launch_conv_fwd(const Lv &L, const bf16 *x1, int c1, int up1, const bf16 *x
     switch (cout) {
     case 16:
         if (c1 + c2 == 16) launch_fwd_slide(L, x1, c1, up1, x2, c2, w, b, relu, y, yf, s);
+        else if (up1 && c1 == 32 && c2 == 16) launch_fwd_dec(L, x1, x2, w, b, relu, y, yf, s);
         else launch_fwd_t<1, 4, 4>(L, x1, c1, up1, x2, c2, w, b, relu, y, yf, s);
         return true;
     case 32: launch_fwd_t<2, 4, 4>(L, x1, c1, up1, x2, c2, w, b, relu, y, yf, s); return true;
@@ -1177,7 +1440,7 @@ bool launch_conv_bwd_weight(const Lv &L, const float *dy, const bf16 *y, int cou
 
 void launch_pool(const Lv &Lc, int C, const bf16 *x, bf16 *y, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pool, dim3(nblk(Lc.n * C)), dim3(kTB), 0, s, Lc, C, x, y);
+    hipLaunchKernelGGL(k_pool, dim3(nblk(Lc.n * (C / 8))), dim3(kTB), 0, s, Lc, C, x, y);  // C = 16 or 32
 }
 
 void launch_pool_bwd_add(const Lv &Lf, int C, const float *dyc, float *dxf, hipStream_t s)

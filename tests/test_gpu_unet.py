@@ -78,9 +78,15 @@ CONV_CASES_ALL = CONV_CASES + FULL_TILE_CASES
 # The 16 -> 16 forward convolutions walk phi in chunks of 32 planes with 32 x 8 cell
 # columns: 70 phi planes give two full chunks and a partial one (whose halo wraps to
 # plane 0), 18 theta rows two full and a partial theta tile; also with the upsampled input.
+# The fine decoder layer (up(32) + skip 16 -> 16) walks 32 x 16 columns over the same
+# chunks with the coarse planes in its ring: 40 x 36 x 68 crosses r tiles (32 + 8), theta
+# tiles (16 + 16 + 4) and phi chunks (32 + 32 + 4); 44 x 20 x 38 has odd coarse
+# dimensions (22 x 10 x 19) and a phi chunk of 6 planes.
 SLIDE_CASES = [
     ((72, 18, 70), 16, 0, 0, 16),
     ((40, 12, 36), 16, 1, 0, 16),
+    ((40, 36, 68), 32, 1, 16, 16),
+    ((44, 20, 38), 32, 1, 16, 16),
 ]
 
 
