@@ -87,13 +87,15 @@ _launch = 0
 
 def mode_opts(rt, mode, tol, max_iter, inner_tol, net=None, budget=0, restart=30):
     """Solve options of a bench mode; the suffix -rb solves the red-black reduced system,
-    -line preconditions float64 CG with the radial-line block Jacobi."""
-    base = mode.split("-")[0]
+    -line preconditions float64 CG with the radial-line block Jacobi; learned-fgmres runs
+    the network inside flexible GMRES(m) instead of flexible CG."""
+    parts = mode.split("-")
+    base = parts[0]
     m = {"fp64": rt.MODE_FP64, "mixed": rt.MODE_MIXED, "learned": rt.MODE_LEARNED, "gmres": rt.MODE_GMRES}[base]
     return rt.solve_opts(m, tol=tol, max_iter=max_iter, check_every=32, inner_tol=inner_tol,
                          inner_max_iter=budget if base == "learned" else 0, net=net if base == "learned" else None,
                          restart=restart, reduce=int(mode.endswith("-rb")), precond=int(mode.endswith("-line")),
-                         launch=_launch)
+                         launch=_launch, inner=rt.INNER_FGMRES if "fgmres" in parts else rt.INNER_FCG)
 
 
 def train_network(rt, torch, sy, n_fields, epochs, seed=7):
@@ -360,6 +362,42 @@ def rosseland_depth_rate(ctx, torch, rho, T, reps=5):
             "bytes": nbytes, "tau_R_midplane_r_in": float(tau.view(npp, nt, nr + 1)[0, nt // 2, 0])}
 
 
+def raytrace_mappings(ctx, rt, torch, rho, T, n_nu, reps=5):
+    """The step's ray trace with lanes on bins (k_raytrace) against lanes on radial cells
+    (k_raytrace_r), both through rt_raytrace_mapped, on the prepared state: mean ms per
+    launch over reps launches each (HIP events on the context's stream), the rate, and
+    the largest relative difference of their q and S."""
+    n = ctx.n
+    out = {}
+    res = {}
+    for name, mapping in (("lanes_bins", rt.LANES_BINS), ("lanes_cells", rt.LANES_CELLS)):
+        q = torch.empty(n, dtype=torch.float64, device="cuda")
+        S = torch.empty_like(q)
+        ctx.raytrace_mapped(mapping, rho, T, q, S)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            ctx.raytrace_mapped(mapping, rho, T, q, S)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        out[name] = {"ms": ms, "gcell_nu_per_s": n * n_nu / (ms / 1e3) / 1e9}
+        res[name] = (q, S)
+    (q1, S1), (q2, S2) = res["lanes_bins"], res["lanes_cells"]
+    relq = ((q2 - q1).abs() / q1.abs().clamp_min(1e-30 * float(q1.abs().max()))).max()
+    relS = ((S2 - S1).abs() / S1.abs().clamp_min(1e-30 * float(S1.abs().max()))).max()
+    out["kernels"] = {"lanes_bins": "k_raytrace<false, false>", "lanes_cells": "k_raytrace_r"}
+    out["q_max_rel_diff"] = float(relq)
+    out["S_max_rel_diff"] = float(relS)
+    out["cells_over_bins_time"] = out["lanes_cells"]["ms"] / out["lanes_bins"]["ms"]
+    nr = ctx.shape[0]
+    seg = -(-nr // 512)
+    out["step_uses"] = "lanes_cells" if 10 * nr >= 9 * 512 * seg else "lanes_bins"
+    del res, q1, S1, q2, S2
+    torch.cuda.empty_cache()
+    return out
+
+
 def _host_info():
     """nproc and the CPU model (lscpu) of the host the baseline ran on."""
     import subprocess
@@ -556,7 +594,7 @@ def main():
         log(f"network: {train_info}")
     results = {}
     for mi, mode in enumerate(modes):
-        budget = args.learned_rb_budget if mode == "learned-rb" else args.learned_budget
+        budget = args.learned_rb_budget if mode.startswith("learned") and mode.endswith("-rb") else args.learned_budget
         steps = args.steps if mi == 0 else min(args.steps, args.other_steps)
         warm = args.warmup if mi == 0 else min(args.warmup, 1)
         results[mode] = run_mode(ctx, rt, torch, rho, T0, mode, steps, warm, args.tol,
@@ -640,7 +678,7 @@ def main():
         out["learned"] = {"mode": lm, "network_applications": Rl["precond_applies"], "fallback": Rl["fallback"],
                           "handover": Rl["handover"],
                           "total_iters": Rl["iters"],
-                          "budget": args.learned_rb_budget if lm == "learned-rb" else args.learned_budget,
+                          "budget": args.learned_rb_budget if lm.endswith("-rb") else args.learned_budget,
                           "training": train_info, "unet_forward_ms": fwd_ms, "unet_apply_ms": tm["apply"],
                           "unet_roofline": {"kernel": "U-Net forward (k_conv_fwd and pooling, whole network)",
                                             "bound": "mfma", "achieved": tflops, "peak": PEAK_BF16_TFLOPS,
@@ -664,6 +702,8 @@ def main():
                 out[f"thermal_force_diff_{mode}_vs_fp64"] = float(
                     (Rm["f"].view(4, -1)[1:] - ff[1:]).abs().max() / thermal)
     out["rosseland_depth"] = rosseland_depth_rate(ctx, torch, rho, T0)
+    out["raytrace_mappings"] = raytrace_mappings(ctx, rt, torch, rho, T0, c["n_nu"])
+    log(f"ray trace mappings: {out['raytrace_mappings']}")
     full = None
     if not args.no_oracle_check or not args.no_cpu_baseline:
         t = time.perf_counter()

@@ -94,7 +94,9 @@ typedef enum {
                              float32 cycle needs over 2048 iterations for a tenfold drop,
                              or two cycles fail to halve the true residual (cond(A^) too
                              large for float32), float64 CG finishes (fallback = 1) */
-    RT_SOLVE_LEARNED = 2, /* refinement around flexible CG preconditioned by a network */
+    RT_SOLVE_LEARNED = 2, /* a Krylov method preconditioned by a network (flexible CG with
+                             float64 refinement, or flexible GMRES: see inner), then the
+                             planned finish once inner_max_iter applications are spent */
     RT_SOLVE_GMRES = 3,   /* restarted GMRES(m) on A^ in float64 (the paper's solver class,
                              Sect. "The generalized minimal residual method"; m = restart) */
     RT_SOLVE_NONE = 4     /* no diffusion: E^{n+1} = a T_bc^4 of the assembled system in every
@@ -130,7 +132,19 @@ typedef struct {
     int launch;          /* rt_launch: how the CG iterations of RT_SOLVE_FP64 / RT_SOLVE_MIXED
                             (reduced or not) reach the GPU; every choice computes the same
                             method, DIRECT and GRAPH bit for bit alike */
+    int inner;           /* rt_inner: the Krylov method of RT_SOLVE_LEARNED */
 } rt_solve_opts;
+
+typedef enum {
+    RT_INNER_FCG = 0,     /* flexible CG in float32 (Notay's FCG with one A-orthogonalisation)
+                             with float64 dots and reliable updates */
+    RT_INNER_FGMRES = 1   /* flexible GMRES(m) (Saad), m = restart: each Arnoldi step applies
+                             the network to the float32-rounded basis vector and keeps its
+                             answer z_j in a second basis; the Arnoldi process and the update
+                             y += Z z are float64.  One network application per iteration; a
+                             cycle that runs out of applications is closed with the steps
+                             taken, then the planned finish runs */
+} rt_inner;
 
 typedef enum {
     RT_LAUNCH_AUTO = 0,   /* BLOCK where it applies, else GRAPH on grids of at most 4,194,304
@@ -215,10 +229,32 @@ rt_status rt_set_star(rt_ctx *ctx, const rt_star *st);
  *              (Eqs. 17, 19), (N_r+1) N_theta N_phi n_nu with the bin fastest:
  *              F_face_nu[f * n_nu + b] for the face index f of F_face; or NULL (it is
  *              n_nu times the size of F_face: 34 GB at 512x256x512 with 64 bins).
+ * Without F_face and F_face_nu the mapping is chosen by the column length (see
+ * rt_raytrace_mapped); with either, q_star and S_abs come from lanes on bins.
  * op / st may be NULL to use the tables already on the context. */
 rt_status rt_raytrace(rt_ctx *ctx, const rt_opacity *op, const rt_star *st,
                       const double *rho, const double *T, double *q_star, double *S_abs,
                       double *F_face, double *F_face_nu);
+
+/* The two mappings of a radial column onto a 64-lane wavefront for q_star and S_abs
+ * (Eqs. 17-20 and 28-36, the definitions and device arrays of rt_raytrace):
+ *   RT_LANES_BINS   lanes on frequency bins, each walking the column cell by cell (the
+ *                   float64 transmission product in the oracle's order), the bin sums by
+ *                   a transpose through LDS;
+ *   RT_LANES_CELLS  lanes on radial cells (8 per lane, segments of 512 cells), the
+ *                   transmissions of each bin multiplied across the lanes by a scan, the
+ *                   sum over bins kept per cell.
+ * rt_raytrace without face fluxes uses RT_LANES_CELLS where the column fills its
+ * 512-cell segments to 90 % or more (it is the faster there), else RT_LANES_BINS; the
+ * face fluxes always come from RT_LANES_BINS.  The two agree up to the order of the
+ * float64 products and sums. */
+typedef enum { RT_LANES_BINS = 0, RT_LANES_CELLS = 1 } rt_raytrace_mapping;
+
+/* q_star and S_abs with the given mapping (to time the two against each other).  Uses the
+ * context's opacity table and star; RT_EINVAL if either is missing, a pointer is NULL or
+ * mapping is not an rt_raytrace_mapping. */
+rt_status rt_raytrace_mapped(rt_ctx *ctx, int mapping, const double *rho, const double *T, double *q_star,
+                             double *S_abs);
 
 /* Fig. 1 "Radiation Energy": E[n] = max(a T^4 - S_abs / kappa_P(T), E_floor). */
 rt_status rt_energy(rt_ctx *ctx, const rt_opacity *op, const rt_fld_params *p,

@@ -1507,6 +1507,30 @@ __global__ __launch_bounds__(kKB) void k_scale_into(long n, const double *__rest
     if (c < n) y[c] = s * x[c];
 }
 
+// y = float(x), and y = double(x): the basis vector a flexible GMRES hands to the network
+// (whose input and output are float32) and the network's answer taken back.
+__global__ __launch_bounds__(kKB) void k_d2f(long n, const double *__restrict__ x, float *__restrict__ y)
+{
+    const long c = (long)blockIdx.x * kKB + threadIdx.x;
+    if (c < n) y[c] = (float)x[c];
+}
+
+__global__ __launch_bounds__(kKB) void k_f2d(long n, const float *__restrict__ x, double *__restrict__ y)
+{
+    const long c = (long)blockIdx.x * kKB + threadIdx.x;
+    if (c < n) y[c] = (double)x[c];
+}
+
+void launch_d2f(long n, const double *x, float *y, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_d2f, dim3((unsigned)((n + kKB - 1) / kKB)), dim3(kKB), 0, st, n, x, y);
+}
+
+void launch_f2d(long n, const float *x, double *y, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_f2d, dim3((unsigned)((n + kKB - 1) / kKB)), dim3(kKB), 0, st, n, x, y);
+}
+
 void launch_mdot(const Dims &d, int nblk, const double *V, int k, const double *w, double *partials, double *out,
                  hipStream_t st)
 {

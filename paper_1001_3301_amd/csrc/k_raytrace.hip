@@ -208,9 +208,9 @@ __global__ __launch_bounds__(1024) void k_raytrace(
     }
 }
 
-void launch_raytrace(const Dims &d, const Opac &op, const Geo &g, const double *F0, double R2,
-                     const double *rho, const double *T, double *q, double *S, double *Fface,
-                     double *Fnu, hipStream_t st)
+void launch_raytrace_bins(const Dims &d, const Opac &op, const Geo &g, const double *F0, double R2,
+                          const double *rho, const double *T, double *q, double *S, double *Fface,
+                          double *Fnu, hipStream_t st)
 {
     long ncol = (long)d.nt * d.np;
     long nblk = (ncol + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -225,12 +225,24 @@ void launch_raytrace(const Dims &d, const Opac &op, const Geo &g, const double *
     else go(k_raytrace<false, false>);
 }
 
+// q and S alone: lanes on cells where the column fills its 512-cell segments to 90 % or
+// more (measured faster there: fewer instructions per cell and bin, no transpose), else
+// lanes on bins; the face fluxes always come from lanes on bins.
+void launch_raytrace(const Dims &d, const Opac &op, const Geo &g, const double *F0, double R2,
+                     const double *rho, const double *T, double *q, double *S, double *Fface,
+                     double *Fnu, hipStream_t st)
+{
+    if (!Fface && !Fnu && raytrace_cells_fit(d.nr)) launch_raytrace_r(d, op, g, F0, R2, rho, T, q, S, st);
+    else launch_raytrace_bins(d, op, g, F0, R2, rho, T, q, S, Fface, Fnu, st);
+}
+
 void raytrace_prepare()
 {
     // the whole LDS of a compute unit, so contexts with any column length can launch
     for (const void *k : {(const void *)k_raytrace<false, false>, (const void *)k_raytrace<true, false>,
                           (const void *)k_raytrace<true, true>})
         (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    raytrace_r_prepare();
 }
 
 size_t raytrace_lds_bytes(int nT, int nr, bool face)

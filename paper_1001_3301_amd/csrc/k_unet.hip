@@ -375,8 +375,9 @@ struct SlidePlane {
 template <int TJ>
 constexpr size_t slide_lds_bytes() { return 3 * (size_t)SlidePlane<TJ>::bytes + 28 * 512; }
 
-// Forward convolution with 16 input and 16 output channels; load / finish / store as
-// for conv_tiles.  Item i of the grid: theta tile fastest, then r tile, then phi chunk;
+// Forward convolution with 16 input and 16 output channels; load / finish as for
+// conv_tiles; store(idx, ch, v, ok) is called by every lane (ok false for cells outside
+// the grid, idx then 0), so an epilogue may exchange values between lanes.  Item i of the grid: theta tile fastest, then r tile, then phi chunk;
 // gridDim.x is a multiple of 8 and the items of one eighth run on one XCD (block b on
 // XCD b % 8), so the blocks resident together are neighbours in theta and r and share
 // their halos in that XCD's L2.
@@ -500,7 +501,8 @@ __device__ __forceinline__ void conv_slide(const Lv &L, const bf16 *__restrict__
 #pragma unroll
         for (int q = 0; q < PW; q++) {
             const int a = r0 + (q & 1) * 16 + (lane & 15), b = j0 + 2 * wv + (q >> 1);
-            if (a < L.nr && b < L.nt) store(a + L.nr * (b + L.nt * k), 4 * (lane >> 4), acc[q]);
+            const bool ok = a < L.nr && b < L.nt;
+            store(ok ? a + L.nr * (b + L.nt * k) : 0, 4 * (lane >> 4), acc[q], ok);
         }
         __syncthreads();  // plane k + 2 is in the ring for the next step
     }
@@ -546,7 +548,10 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(NT == 1 ? 3
         if (y) *reinterpret_cast<uint2 *>(y + (size_t)idx * cout + co) = make_uint2(pack_bf16(o[0], o[1]), pack_bf16(o[2], o[3]));
         if (yf) *reinterpret_cast<float4 *>(yf + (size_t)idx * cout + co) = make_float4(o[0], o[1], o[2], o[3]);
     };
-    if constexpr (SLIDE) conv_slide<TJ>(L, w, load, finish, store);  // NT = 1, c1 + c2 = 16
+    if constexpr (SLIDE)  // NT = 1, c1 + c2 = 16
+        conv_slide<TJ>(L, w, load, finish, [&](int idx, int co, const float4v &v, bool ok) {
+            if (ok) store(idx, co, v);
+        });
     else conv_tiles<NT, TJ, TK, 1, false>(L, c1 + c2, w, load, finish, store);
 }
 
@@ -585,8 +590,58 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         for (int i = 0; i < 4; i++) o[i] = o[i] < 0.0f ? 0.0f : o[i];
         *reinterpret_cast<uint2 *>(y + (size_t)idx * 16 + co) = make_uint2(pack_bf16(o[0], o[1]), pack_bf16(o[2], o[3]));
     };
-    if constexpr (SLIDE) conv_slide<kSlideTJ>(L, w, load, finish, store);
+    if constexpr (SLIDE)
+        conv_slide<kSlideTJ>(L, w, load, finish, [&](int idx, int co, const float4v &v, bool ok) {
+            if (ok) store(idx, co, v);
+        });
     else conv_tiles<1, 4, 4, 1, false>(L, 16, w, load, finish, store);
+}
+
+// The network's last two layers in one pass, for the forward passes whose activations
+// are not kept for a backward pass: h = relu(conv(x, w) + bias) (16 -> 16, the sliding
+// kernel) rounded to bf16, then z = wo . h + bo (the 1x1 output layer, fp32) instead of
+// writing h.  The same operands and the same fp32 operations in the same order as
+// k_conv_fwd followed by k_out_fwd, so z is bit for bit theirs.  Each lane ends with 4
+// channels of one cell; the cell's 16 channels are gathered into lanes 0..15 by
+// ds_bpermute, which every lane executes.
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_conv_fwd_head(
+    Lv L, const bf16 *__restrict__ x, const bf16 *__restrict__ w, const float *__restrict__ bias,
+    const bf16 *__restrict__ wo, const float *__restrict__ bo, const double *__restrict__ scale, float *__restrict__ z)
+{
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    auto load = [&](int idx, int, int, int, int ch) -> u32x4 {
+        return *reinterpret_cast<const u32x4 *>(x + (size_t)idx * 16 + ch);
+    };
+    auto finish = [](const u32x4 &v, bool ok) -> u32x4 { return ok ? v : u32x4{0u, 0u, 0u, 0u}; };
+    const int lane = threadIdx.x & 63, e = lane & 15;
+    const float4 bb = *reinterpret_cast<const float4 *>(bias + 4 * (lane >> 4));
+    float wof[16];
+#pragma unroll
+    for (int q = 0; q < 16; q++) wof[q] = bf2f(wo[q]);
+    const float b0 = bo[0];
+    const double sc = scale ? scale[1] : 1.0;
+    auto store = [&](int idx, int, const float4v &v, bool ok) {
+        float o[4] = {v[0] + bb.x, v[1] + bb.y, v[2] + bb.z, v[3] + bb.w};
+#pragma unroll
+        for (int i = 0; i < 4; i++) o[i] = o[i] < 0.0f ? 0.0f : o[i];
+        const unsigned d0 = pack_bf16(o[0], o[1]), d1 = pack_bf16(o[2], o[3]);
+        unsigned hv[8];
+        hv[0] = d0;
+        hv[1] = d1;
+#pragma unroll
+        for (int g = 1; g < 4; g++) {
+            hv[2 * g] = (unsigned)__builtin_amdgcn_ds_bpermute((e + 16 * g) * 4, (int)d0);
+            hv[2 * g + 1] = (unsigned)__builtin_amdgcn_ds_bpermute((e + 16 * g) * 4, (int)d1);
+        }
+        if (lane < 16 && ok) {
+            float s = b0;
+#pragma unroll
+            for (int q = 0; q < 16; q++)
+                s = fmaf(wof[q], bf2f((bf16)(q & 1 ? hv[q >> 1] >> 16 : hv[q >> 1] & 0xFFFFu)), s);
+            z[idx] = scale ? (float)((double)s * sc) : s;
+        }
+    };
+    conv_slide<kSlideTJ>(L, w, load, finish, store);
 }
 
 // ------------------------------------------ sliding decoder convolution (fine level)
@@ -1104,7 +1159,7 @@ __global__ __launch_bounds__(kTB) void k_out_fwd(long n, const bf16 *__restrict_
     const unsigned wd[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
     float s = b[0];
 #pragma unroll
-    for (int q = 0; q < 16; q++) s += bf2f(w[q]) * bf2f((bf16)(q & 1 ? wd[q >> 1] >> 16 : wd[q >> 1] & 0xFFFFu));
+    for (int q = 0; q < 16; q++) s = fmaf(bf2f(w[q]), bf2f((bf16)(q & 1 ? wd[q >> 1] >> 16 : wd[q >> 1] & 0xFFFFu)), s);
     // scale != nullptr: the preconditioner's output scaled back by scale[1] (the input was
     // scaled by scale[0] = 1 / scale[1]; the map is taken as positively homogeneous of
     // degree one)
@@ -1327,6 +1382,16 @@ void launch_fwd_slide(const Lv &L, const bf16 *x1, int c1, int up1, const bf16 *
     (void)attr;
     hipLaunchKernelGGL((k_conv_fwd<1, kSlideTJ, 1, true>), dim3(slide_grid(L)), dim3(kTB), lds, s, L, x1, c1, up1, x2,
                        c2, w, b, relu, y, yf);
+}
+
+void launch_conv_fwd_head(const Lv &L, const bf16 *x, const bf16 *w, const float *b, const bf16 *wo, const float *bo,
+                          const double *scale, float *z, hipStream_t s)
+{
+    constexpr size_t lds = slide_lds_bytes<kSlideTJ>();
+    static const bool attr = hipFuncSetAttribute((const void *)k_conv_fwd_head, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds) == hipSuccess;
+    (void)attr;
+    hipLaunchKernelGGL(k_conv_fwd_head, dim3(slide_grid(L)), dim3(kTB), lds, s, L, x, w, b, wo, bo, scale, z);
 }
 
 // One block per (theta tile, r tile, phi chunk) of k_conv_fwd_dec, rounded up to a

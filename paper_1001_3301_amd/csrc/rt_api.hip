@@ -454,6 +454,24 @@ rt_status rt_raytrace(rt_ctx *ctx, const rt_opacity *op, const rt_star *st, cons
     return RT_OK;
 }
 
+rt_status rt_raytrace_mapped(rt_ctx *ctx, int mapping, const double *rho, const double *T, double *q_star,
+                             double *S_abs)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    RT_CHECK(ctx, ctx->have_opac, "no opacity table on the context");
+    RT_CHECK(ctx, ctx->have_star, "no star on the context");
+    RT_CHECK(ctx, rho && T && q_star && S_abs, "rt_raytrace_mapped: NULL field pointer");
+    RT_CHECK(ctx, mapping == RT_LANES_BINS || mapping == RT_LANES_CELLS, "mapping must be an rt_raytrace_mapping");
+    if (mapping == RT_LANES_CELLS)
+        launch_raytrace_r(ctx->d, ctx->op, ctx->geo, ctx->F0, ctx->R_star * ctx->R_star, rho, T, q_star, S_abs,
+                          ctx->stream);
+    else
+        launch_raytrace_bins(ctx->d, ctx->op, ctx->geo, ctx->F0, ctx->R_star * ctx->R_star, rho, T, q_star, S_abs,
+                             nullptr, nullptr, ctx->stream);
+    RT_HIP(ctx, hipGetLastError());
+    return RT_OK;
+}
+
 rt_status rt_energy(rt_ctx *ctx, const rt_opacity *op, const rt_fld_params *p, const double *T, const double *S_abs,
                     double *E)
 {
@@ -1017,6 +1035,9 @@ rt_status solve_fp64_line(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *s
     return status;
 }
 
+rt_status solve_gmres(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb, rt_net *net = nullptr,
+                      int budget = 0, int *out = nullptr);
+
 // Learned mode: flexible CG (Notay's FCG with one A-orthogonalisation, since the
 // network is a nonlinear preconditioner) in float32 with float64 dots and the same
 // float64 reliable updates as the mixed mode; z = M(r) is the U-Net applied to the
@@ -1032,6 +1053,22 @@ rt_status solve_learned(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
     const double delta2 = 0.01;
     const int budget = o->inner_max_iter > 0 ? o->inner_max_iter : 400;
     if (rt_status e = net_prepare(net, ctx)) return fail(ctx, e, std::string("network: ") + rt_net_last_error(net));
+    rt_status status = RT_OK;
+    bool fallback = false, nonfinite = false;
+    const bool fgmres = o->inner == RT_INNER_FGMRES;
+    if (fgmres) {
+        // flexible GMRES(m) in float64 with the network as the right preconditioner; it
+        // updates y itself, so there is no float32 iterate to fold in afterwards
+        int out = 0;
+        status = solve_gmres(ctx, o, st, bb, net, budget, &out);
+        if (status == RT_ENONFINITE) {
+            status = RT_OK;
+            fallback = nonfinite = true;
+        } else if (status == RT_OK && out == 1) {
+            fallback = true;
+        }
+        if (status != RT_OK || !fallback) return status;
+    } else {
     h->iters = 0;
     h->done = 0;
     h->beta = 0.0;
@@ -1042,8 +1079,6 @@ rt_status solve_learned(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
     if (rt_status e = read_scalars(ctx)) return e;
     double res = std::sqrt(h->res2 / bb), rr_ref = h->res2;
     float *pold = ctx->p32a, *pnew = ctx->p32b;
-    rt_status status = RT_OK;
-    bool fallback = false, nonfinite = false;
     for (;;) {
         st->relres = res;
         if (!isfin(res)) { fallback = nonfinite = true; break; }
@@ -1076,8 +1111,9 @@ rt_status solve_learned(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
         }
     }
     st->iters = h->iters;
+    }
     if (fallback && !allow_fallback) {
-        if (!nonfinite) launch_fold(d.n, ctx->x32, ctx->y, s);
+        if (!nonfinite && !fgmres) launch_fold(d.n, ctx->x32, ctx->y, s);
         RT_HIP(ctx, hipGetLastError());
         return nonfinite ? RT_ENONFINITE : RT_OK;
     }
@@ -1087,8 +1123,11 @@ rt_status solve_learned(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
         // output reached are cleared), then finish with the float64 method.  Running out
         // of network applications is the planned hand-over (`handover`); `fallback`
         // marks a network that failed (non-finite output).
-        if (!nonfinite) launch_fold(d.n, ctx->x32, ctx->y, s);
-        else if (rt_status e = reset_directions(ctx)) return e;
+        if (!nonfinite) {
+            if (!fgmres) launch_fold(d.n, ctx->x32, ctx->y, s);
+        } else if (rt_status e = reset_directions(ctx)) {
+            return e;
+        }
         if (nonfinite) st->fallback = 1;
         else st->handover = 1;
         rt_solve_stats s64{};
@@ -1119,7 +1158,17 @@ rt_status solve_learned(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
 // deterministic batched reduction over the basis), Givens rotations of the Hessenberg
 // column on the host, |g_(j+1)| as the residual estimate; a cycle ends after m steps
 // or at the estimate tol, then y += V z (H z = g) and the true residual decides.
-rt_status solve_gmres(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb)
+//
+// With a network (flexible GMRES, Saad's FGMRES(m): right preconditioning by an
+// operator that may change from step to step): step j applies the network to v_j
+// (rounded to float32, scaled to unit RMS inside the application) and keeps the answer
+// z_j in a second basis Z; w = A^ z_j enters the Arnoldi process, and the cycle's update
+// is y += Z z, so |g_(j+1)| estimates the true residual of that update.  At most
+// `budget` network applications: when they run out the cycle is closed with the steps
+// taken (*out = 1); a non-finite network output ends the solve before it reaches y
+// (*out = 2, y keeps the previous cycle's iterate).
+rt_status solve_gmres(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb, rt_net *net, int budget,
+                      int *out)
 {
     const Dims &d = ctx->d;
     const long n = d.n;
@@ -1137,7 +1186,14 @@ rt_status solve_gmres(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, d
             if (!ctx->gm_part || !ctx->gm_coef) return fail(ctx, RT_ENOMEM, "GMRES workspace: out of device memory");
         }
     }
+    if (net && ctx->gmz_cap < m) {
+        ctx->gmZ = dalloc<double>(ctx, (size_t)m * n);
+        if (!ctx->gmZ) return fail(ctx, RT_ENOMEM, "flexible GMRES basis: out of device memory");
+        ctx->gmz_cap = m;
+    }
+    if (out) *out = 0;
     double *V = ctx->gmV;
+    double *Z = net ? ctx->gmZ : ctx->gmV;  // the vectors the update combines
     const double bn = std::sqrt(bb);
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), hc(kMaxBasis), h2(kMaxBasis);
     auto col = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
@@ -1145,6 +1201,7 @@ rt_status solve_gmres(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, d
     if (rt_status e = write_scalars(ctx)) return e;
     rt_status status = RT_OK;
     int it = 0;
+    bool spent = false;
     for (;;) {
         // r0 = b - A y, its norm; v_0 = r0 / beta
         launch_resid(d, ctx->nblk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials, ctx->counter, ctx->sc, 0, s);
@@ -1155,14 +1212,26 @@ rt_status solve_gmres(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, d
         if (!isfin(beta)) { status = RT_ENONFINITE; break; }
         if (st->relres <= o->tol) break;
         if (it >= o->max_iter) { status = RT_ENOCONV; break; }
+        if (spent) { if (out) *out = 1; break; }
         launch_scale_into(n, ctx->r, 1.0 / beta, V, s);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int k = 0;
         for (int j = 0; j < m && it < o->max_iter; j++) {
+            if (net && st->precond_applies >= budget) { spent = true; break; }
             it++;
             double *w = V + (size_t)(j + 1) * n;
-            launch_spmv(d, ctx->nblk, ctx->ahat, V + (size_t)j * n, w, s);
+            const double *src = V + (size_t)j * n;
+            if (net) {  // z_j = M(v_j)
+                launch_d2f(n, src, ctx->r32, s);
+                launch_norm2_rr32(d, ctx->nblk, ctx->r32, ctx->partials, ctx->counter, ctx->sc, s);
+                if (rt_status e = net_precond(net, ctx, ctx->r32, ctx->z32))
+                    return fail(ctx, e, std::string("network: ") + rt_net_last_error(net));
+                st->precond_applies++;
+                launch_f2d(n, ctx->z32, Z + (size_t)j * n, s);
+                src = Z + (size_t)j * n;
+            }
+            launch_spmv(d, ctx->nblk, ctx->ahat, src, w, s);
             for (int pass = 0; pass < 2; pass++) {  // CGS2
                 launch_mdot(d, ctx->nblk, V, j + 1, w, ctx->gm_part, ctx->gm_coef, s);
                 RT_HIP(ctx, hipMemcpyAsync(pass ? h2.data() : hc.data(), ctx->gm_coef, (j + 1) * sizeof(double),
@@ -1173,7 +1242,13 @@ rt_status solve_gmres(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, d
             RT_HIP(ctx, hipGetLastError());
             if (rt_status e = read_scalars(ctx)) return e;  // also completes the two copies above
             const double hn = std::sqrt(h->res2);
-            if (!isfin(hn)) { status = RT_ENONFINITE; break; }
+            bool fin = isfin(hn);
+            for (int i = 0; i <= j; i++) fin = fin && isfin(hc[i] + h2[i]);
+            if (!fin) {
+                status = RT_ENONFINITE;
+                if (net && out) *out = 2;
+                break;
+            }
             for (int i = 0; i <= j; i++) col(i, j) = hc[i] + h2[i];
             col(j + 1, j) = hn;
             if (hn > 0.0) launch_scale_into(n, w, 1.0 / hn, w, s);
@@ -1194,13 +1269,20 @@ rt_status solve_gmres(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, d
             if (std::fabs(g[j + 1]) / bn <= o->tol || hn == 0.0) break;
         }
         if (status != RT_OK) break;
+        if (k == 0) {  // no step taken: the network budget is spent (or the iteration
+            if (spent) {  // limit reached, which the next pass reports)
+                if (out) *out = 1;
+                break;
+            }
+            continue;
+        }
         for (int i = k - 1; i >= 0; i--) {  // H_k z = g_k
             double t = g[i];
             for (int l = i + 1; l < k; l++) t -= col(i, l) * g[l];
             g[i] = t / col(i, i);
         }
         RT_HIP(ctx, hipMemcpyAsync(ctx->gm_coef, g.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
-        launch_maxpy(n, V, k, ctx->gm_coef, 1.0, ctx->y, s);
+        launch_maxpy(n, Z, k, ctx->gm_coef, 1.0, ctx->y, s);
         RT_HIP(ctx, hipStreamSynchronize(s));  // g is reused by the next cycle
         st->outer_iters++;
     }
@@ -1229,6 +1311,7 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
                       o->mode == RT_SOLVE_GMRES,
              "unknown solve mode");
     RT_CHECK(ctx, o->mode != RT_SOLVE_LEARNED || o->net, "learned mode needs a network");
+    RT_CHECK(ctx, o->inner == RT_INNER_FCG || o->inner == RT_INNER_FGMRES, "inner must be an rt_inner value");
     RT_CHECK(ctx, o->launch >= RT_LAUNCH_AUTO && o->launch <= RT_LAUNCH_BLOCK,
              "rt_fld_solve: launch must be an rt_launch value");
     RT_CHECK(ctx, o->precond == 0 || (o->precond == 1 && o->mode == RT_SOLVE_FP64 && !o->reduce),

@@ -193,6 +193,15 @@ void launch_raytrace(const Dims &d, const Opac &op, const Geo &g, const double *
                      const double *rho, const double *T, double *q, double *S, double *Fface,
                      double *Fnu, hipStream_t st);
 size_t raytrace_lds_bytes(int nT, int nr, bool face);
+// The two mappings of a column onto a wavefront: lanes on bins (any outputs) and lanes on
+// radial cells (q and S; a multiplicative scan per bin).  launch_raytrace picks one.
+void launch_raytrace_bins(const Dims &d, const Opac &op, const Geo &g, const double *F0, double R2,
+                          const double *rho, const double *T, double *q, double *S, double *Fface,
+                          double *Fnu, hipStream_t st);
+void launch_raytrace_r(const Dims &d, const Opac &op, const Geo &g, const double *F0, double R2, const double *rho,
+                       const double *T, double *q, double *S, hipStream_t st);
+bool raytrace_cells_fit(int nr);  // the column fills its 512-cell segments to 90 % or more
+void raytrace_r_prepare();
 void launch_energy(const Dims &d, const Opac &op, const double *T, const double *S, double Efloor,
                    double *E, hipStream_t st);
 void launch_assemble(const Dims &d, const Geo &g, const Opac &op, const double *rho, const double *T,
@@ -272,6 +281,8 @@ void launch_mdot(const Dims &d, int nblk, const double *V, int k, const double *
                  hipStream_t st);
 void launch_maxpy(long n, const double *V, int k, const double *coef, double sign, double *w, hipStream_t st);
 void launch_scale_into(long n, const double *x, double s, double *y, hipStream_t st);
+void launch_d2f(long n, const double *x, float *y, hipStream_t st);
+void launch_f2d(long n, const float *x, double *y, hipStream_t st);
 // Flexible CG for the learned mode (float32 vectors, float64 dots).
 void launch_fcg_dir(const Dims &d, int nblk, const float *a, const float *z, const float *pold, const float *r,
                     float *pnew, float *q, double *partials, unsigned *counter, DevScalars *sc, hipStream_t st);
@@ -297,6 +308,10 @@ bool launch_conv_bwd_data(const Lv &L, const float *dy, const bf16 *y, int cout,
 bool launch_conv_bwd_weight(const Lv &L, const float *dy, const bf16 *y, int cout, const bf16 *x1, int c1, int up1,
                             const bf16 *x2, int c2, float *part, float *dw, float *db, hipStream_t s);
 long wgrad_part_floats(const Lv &L, int cout, int cin);
+// relu(conv(x, w) + b) (16 -> 16) followed by the 1x1 output layer z = wo . h + bo (times
+// scale[1] when scale != nullptr), without writing h; bit for bit the two layers' result.
+void launch_conv_fwd_head(const Lv &L, const bf16 *x, const bf16 *w, const float *b, const bf16 *wo, const float *bo,
+                          const double *scale, float *z, hipStream_t s);
 void launch_pool(const Lv &Lc, int C, const bf16 *x, bf16 *y, hipStream_t s);
 void launch_pool_bwd_add(const Lv &Lf, int C, const float *dyc, float *dxf, hipStream_t s);
 void launch_up_bwd(const Lv &Lc, int C, const float *dyf, float *dxc, hipStream_t s);
@@ -386,6 +401,9 @@ struct rt_ctx {
     // per-block partial inner products and the device copy of small coefficient arrays
     double *gmV = nullptr, *gm_part = nullptr, *gm_coef = nullptr;
     int gm_cap = 0;
+    // flexible GMRES: the preconditioned vectors Z (gmz_cap vectors of n)
+    double *gmZ = nullptr;
+    int gmz_cap = 0;
     unsigned *counter = nullptr;
     rt::DevScalars *sc = nullptr;   // device
     rt::DevScalars *h_sc = nullptr; // pinned host mirror

@@ -195,7 +195,9 @@ void pool(const Lv &Lc, int C, const bf16 *x, bf16 *y, hipStream_t s) { nn::laun
 // Forward pass on the workspace input X -> z (fp32, unscaled network output).  With r
 // and scale (a preconditioner application): channel 0 of the input is r scale[0], built
 // inside the first convolution, and the output scale[1] network(...) goes to zout.
-void forward(rt_net *N, hipStream_t s, const float *r = nullptr, const double *scale = nullptr,
+// keep: the last hidden activation is written for a backward pass; otherwise the last
+// convolution and the output layer run as one kernel (the same z, bit for bit).
+void forward(rt_net *N, hipStream_t s, bool keep, const float *r = nullptr, const double *scale = nullptr,
              float *zout = nullptr)
 {
     const Lv *L = N->lv;
@@ -215,9 +217,13 @@ void forward(rt_net *N, hipStream_t s, const float *r = nullptr, const double *s
     conv_fwd(L[1], N->a[5], 64, 1, N->a[3], 32, WL(6), BL(6), 32, 1, N->a[6], nullptr, s);
     conv_fwd(L[1], N->a[6], 32, 0, nullptr, 0, WL(7), BL(7), 32, 1, N->a[7], nullptr, s);
     conv_fwd(L[0], N->a[7], 32, 1, N->a[1], 16, WL(8), BL(8), 16, 1, N->a[8], nullptr, s);
-    conv_fwd(L[0], N->a[8], 16, 0, nullptr, 0, WL(9), BL(9), 16, 1, N->a[9], nullptr, s);
-    if (r) nn::launch_out_fwd(L[0].n, N->a[9], WL(10), BL(10), scale, zout, s);
-    else nn::launch_out_fwd(L[0].n, N->a[9], WL(10), BL(10), nullptr, N->z, s);
+    if (!keep) {
+        nn::launch_conv_fwd_head(L[0], N->a[8], WL(9), BL(9), WL(10), BL(10), r ? scale : nullptr, r ? zout : N->z, s);
+    } else {
+        conv_fwd(L[0], N->a[8], 16, 0, nullptr, 0, WL(9), BL(9), 16, 1, N->a[9], nullptr, s);
+        if (r) nn::launch_out_fwd(L[0].n, N->a[9], WL(10), BL(10), scale, zout, s);
+        else nn::launch_out_fwd(L[0].n, N->a[9], WL(10), BL(10), nullptr, N->z, s);
+    }
 }
 
 // Backward pass for dL/dz = N->gz: parameter gradients into N->g.
@@ -371,7 +377,7 @@ rt_status rt_net_forward(rt_ctx *ctx, rt_net *net, const void *X, float *z)
     if (rt_status e = ensure_ws(net, ctx->d.nr, ctx->d.nt, ctx->d.np, false)) return e;
     hipStream_t s = ctx->stream;
     NN_HIP(net, hipMemcpyAsync(net->X, X, net->lv[0].n * 16 * sizeof(bf16), hipMemcpyDeviceToDevice, s));
-    forward(net, s);
+    forward(net, s, false);
     NN_HIP(net, hipMemcpyAsync(z, net->z, net->lv[0].n * sizeof(float), hipMemcpyDeviceToDevice, s));
     NN_HIP(net, hipGetLastError());
     return RT_OK;
@@ -392,7 +398,7 @@ rt_status rt_net_loss_grad(rt_ctx *ctx, rt_net *net, const void *X, const float 
     if (rt_status er = ensure_ws(net, ctx->d.nr, ctx->d.nt, ctx->d.np, true)) return er;
     hipStream_t s = ctx->stream;
     NN_HIP(net, hipMemcpyAsync(net->X, X, net->lv[0].n * 16 * sizeof(bf16), hipMemcpyDeviceToDevice, s));
-    forward(net, s);
+    forward(net, s, true);
     loss(net, e, s);
     backward(net, s);
     if (z) NN_HIP(net, hipMemcpyAsync(z, net->z, net->lv[0].n * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -414,7 +420,7 @@ rt_status rt_net_loss_grad_resid(rt_ctx *ctx, rt_net *net, const void *X, const 
     hipStream_t s = ctx->stream;
     const long n = net->lv[0].n;
     NN_HIP(net, hipMemcpyAsync(net->X, X, n * 16 * sizeof(bf16), hipMemcpyDeviceToDevice, s));
-    forward(net, s);
+    forward(net, s, true);
     launch_spmv32(ctx->d, ctx->nblk, a32, net->z, net->rq, s);                    // A z
     nn::launch_loss(n, net->rq, r, net->lpart, net->lres, net->gq, s);           // L, dL/d(A z)
     launch_spmv32(ctx->d, ctx->nblk, a32, net->gq, net->gz, s);                   // dL/dz = A^T dL/d(A z)
@@ -748,7 +754,7 @@ rt_status net_precond(rt_net *net, rt_ctx *ctx, const float *r, float *z)
     hipStream_t s = ctx->stream;
     const long n = ctx->d.n;
     launch_rms_scale(n, ctx->sc, ctx->nscale, s);
-    forward(net, s, r, ctx->nscale, z);
+    forward(net, s, false, r, ctx->nscale, z);
     NN_HIP(net, hipGetLastError());
     return RT_OK;
 }

@@ -21,6 +21,8 @@ STATUS_NAMES = {0: "RT_OK", 1: "RT_EINVAL", 2: "RT_EDEVICE", 3: "RT_ENOMEM", 4: 
                 5: "RT_ENOCONV"}
 MODE_FP64, MODE_MIXED, MODE_LEARNED, MODE_GMRES, MODE_NONE = 0, 1, 2, 3, 4
 LAUNCH_AUTO, LAUNCH_DIRECT, LAUNCH_GRAPH, LAUNCH_BLOCK = 0, 1, 2, 3
+INNER_FCG, INNER_FGMRES = 0, 1
+LANES_BINS, LANES_CELLS = 0, 1
 
 dp = C.POINTER(C.c_double)
 
@@ -59,7 +61,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("check_every", C.c_int), ("inner_tol", C.c_double), ("inner_max_iter", C.c_int),
                 ("net", C.c_void_p), ("restart", C.c_int), ("reduce", C.c_int), ("precond", C.c_int),
-                ("launch", C.c_int)]
+                ("launch", C.c_int), ("inner", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -95,7 +97,7 @@ class RelaxStats(C.Structure):
 
 # Every symbol include/rt.h declares (checked by the tests).
 EXPORTS = ["rt_create", "rt_destroy", "rt_last_error", "rt_ncell", "rt_star_bin_flux",
-           "rt_set_opacity", "rt_set_star", "rt_raytrace", "rt_energy", "rt_fld_assemble",
+           "rt_set_opacity", "rt_set_star", "rt_raytrace", "rt_raytrace_mapped", "rt_energy", "rt_fld_assemble",
            "rt_spmv", "rt_fld_solve", "rt_temperature", "rt_force", "rt_step", "rt_step_fields",
            "rt_gray_table", "rt_relax", "rt_rosseland_depth", "rt_precond_apply",
            "rt_net_create", "rt_net_destroy", "rt_net_last_error", "rt_net_param_count",
@@ -146,6 +148,7 @@ def lib():
     L.rt_set_opacity.argtypes = [vp, P(Opacity)]
     L.rt_set_star.argtypes = [vp, P(Star)]
     L.rt_raytrace.argtypes = [vp, P(Opacity), P(Star), vp, vp, vp, vp, vp, vp]
+    L.rt_raytrace_mapped.argtypes = [vp, C.c_int, vp, vp, vp, vp]
     L.rt_energy.argtypes = [vp, P(Opacity), P(FldParams), vp, vp, vp]
     L.rt_fld_assemble.argtypes = [vp, P(Opacity), P(FldParams), vp, vp, vp, vp, vp, P(System)]
     L.rt_spmv.argtypes = [vp, vp, vp]
@@ -236,10 +239,10 @@ class GrayOpacity:
 
 
 def solve_opts(mode=MODE_FP64, tol=1e-8, max_iter=100000, check_every=32, inner_tol=1e-4,
-               inner_max_iter=0, net=None, restart=30, reduce=0, precond=0, launch=0) -> SolveOpts:
+               inner_max_iter=0, net=None, restart=30, reduce=0, precond=0, launch=0, inner=INNER_FCG) -> SolveOpts:
     nh = None if net is None else (net.h if isinstance(net, Net) else net)
     o = SolveOpts(mode, tol, max_iter, check_every, inner_tol, inner_max_iter, nh, restart, int(reduce),
-                  int(precond), int(launch))
+                  int(precond), int(launch), int(inner))
     o._net = net  # keeps the network alive as long as the options refer to it
     return o
 
@@ -335,6 +338,12 @@ class Context:
                 self._dev(F_face, nf, "F_face", allow_none=True),
                 self._dev(F_face_nu, nf * self.n_nu, "F_face_nu", allow_none=True)]
         self._chk(lib().rt_raytrace(self.h, None, None, *args))
+
+    def raytrace_mapped(self, mapping, rho, T, q, S):
+        """q and S of raytrace with lanes on bins (LANES_BINS) or on radial cells (LANES_CELLS)."""
+        self._chk(lib().rt_raytrace_mapped(self.h, int(mapping), self._dev(rho, self.n, "rho"),
+                                           self._dev(T, self.n, "T"), self._dev(q, self.n, "q"),
+                                           self._dev(S, self.n, "S")))
 
     def energy(self, T, S, E, params=None):
         p = params or self.params

@@ -79,6 +79,55 @@ def test_raytrace_c2_tau100_full():
     assert rel(_h(Ff), F0) < 1e-11
 
 
+# lanes = radial cells: 8 cells a lane, 512-cell segments; 1100 cells take three
+# segments (the last one partial, its flux carried over twice), 33 / 40 / 67 cells one
+# partial segment.
+LANES_CELLS_CASES = dict(CASES)
+LANES_CELLS_CASES["long-1100x3x2-nu16"] = lambda: sy.make_workload("long", 1100, 3, 2, 16, 30.0, clump_seed=7)
+LANES_CELLS_CASES["long-1024x2x2-nu64"] = lambda: sy.make_workload("long2", 1024, 2, 2, 64, 100.0, clump_seed=8)
+
+
+@pytest.mark.parametrize("case", list(LANES_CELLS_CASES))
+def test_raytrace_lanes_cells_parity(case):
+    """The ray trace with lanes on radial cells (a multiplicative scan per bin) against
+    the oracle, and against lanes on bins on the same inputs."""
+    from paper_1001_3301_amd import rt
+    wl = LANES_CELLS_CASES[case]()
+    P = oracle.Problem.from_workload(wl)
+    ctx = _ctx(wl)
+    T = seeded_temperature(P.n, 15, 10.0, 2500.0)
+    q0, S0, _ = P.raytrace(wl.rho, T, want_faces=False)
+    q, S, qv, Sv = (torch.empty(P.n, dtype=torch.float64, device="cuda") for _ in range(4))
+    ctx.raytrace_mapped(rt.LANES_CELLS, _d(wl.rho), _d(T), q, S)
+    ctx.raytrace_mapped(rt.LANES_BINS, _d(wl.rho), _d(T), qv, Sv)
+    torch.cuda.synchronize()
+    assert rel(_h(q), q0) < 1e-11
+    assert rel(_h(S), S0) < 1e-11
+    assert rel(_h(q), _h(qv)) < 1e-12
+
+
+@pytest.mark.parametrize("nr,cells", [(512, True), (1024, True), (470, True), (400, False), (600, False)])
+def test_raytrace_picks_the_mapping_by_column_length(nr, cells):
+    """rt_raytrace without face fluxes takes lanes on cells where the column fills its
+    512-cell segments to 90 % (the same bits as rt_raytrace_mapped with LANES_CELLS), else
+    lanes on bins; with the face flux it takes lanes on bins, whose q and S then agree
+    with the other mapping to rounding order."""
+    from paper_1001_3301_amd import rt
+    wl = sy.make_workload("len", nr, 3, 2, 32, 30.0, clump_seed=9)
+    ctx = _ctx(wl)
+    T = seeded_temperature(ctx.n, 16, 10.0, 2500.0)
+    q, S, qm, Sm, qf, Sf = (torch.empty(ctx.n, dtype=torch.float64, device="cuda") for _ in range(6))
+    Ff = torch.empty((nr + 1) * 3 * 2, dtype=torch.float64, device="cuda")
+    ctx.raytrace(_d(wl.rho), _d(T), q, S)
+    ctx.raytrace_mapped(rt.LANES_CELLS if cells else rt.LANES_BINS, _d(wl.rho), _d(T), qm, Sm)
+    ctx.raytrace(_d(wl.rho), _d(T), qf, Sf, Ff)
+    torch.cuda.synchronize()
+    assert torch.equal(q, qm) and torch.equal(S, Sm)
+    assert rel(_h(qf), _h(q)) < 1e-12 and rel(_h(Sf), _h(S)) < 1e-12
+    if not cells:
+        assert torch.equal(qf, q) and torch.equal(Sf, S)
+
+
 def test_energy_and_newton_parity():
     wl = small_workload()
     P = oracle.Problem.from_workload(wl)

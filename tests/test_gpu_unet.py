@@ -236,6 +236,26 @@ def test_network_forward_against_bf16_oracle_on_a_multi_tile_grid(seed):
     assert np.median(d) <= 2e-3
 
 
+def test_forward_with_fused_output_layer_equals_the_layer_by_layer_forward():
+    """rt_net_forward runs the last convolution and the 1x1 output layer as one kernel
+    (the hidden activation is not written); rt_net_loss_grad, which keeps that activation
+    for its backward pass, runs them as two.  z agrees bit for bit.  On 72 x 36 x 68 the
+    fine level spans full and partial r tiles, theta tiles and phi chunks."""
+    from paper_1001_3301_amd import rt
+    shape = (72, 36, 68)
+    n = 72 * 36 * 68
+    wl, ctx = _ctx_for(shape)
+    net = rt.Net(seed=5)
+    Xb = _net_input(n, 31)
+    z1 = torch.empty(n, dtype=torch.float32, device="cuda")
+    z2 = torch.empty(n, dtype=torch.float32, device="cuda")
+    net.forward(ctx, dev_bf16(Xb), z1)
+    net.loss_grad(ctx, dev_bf16(Xb), dev_f32(_rng(32).standard_normal(n)), z2)
+    a, b = z1.cpu().numpy(), z2.cpu().numpy()
+    assert np.all(np.isfinite(a)) and np.abs(a).max() > 0
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
 def test_adam_step_matches_formula():
     from paper_1001_3301_amd import rt
     shape = (8, 4, 4)
@@ -302,14 +322,15 @@ def test_training_lowers_the_loss_and_learned_solve_converges(tmp_path):
     assert float(((Tl - Tf).abs() / Tf).max()) < 1e-3
 
 
-def test_learned_solve_falls_back_when_the_network_blows_up():
+@pytest.mark.parametrize("inner", [0, 1], ids=["fcg", "fgmres"])
+def test_learned_solve_falls_back_when_the_network_blows_up(inner):
     from paper_1001_3301_amd import rt
     wl, ctx, rho, T, En, S = _small_problem(shape=(16, 8, 8))
     net = rt.Net(seed=2)
     p = net.get_params()
     net.set_params(np.full_like(p, 1e30))  # finite weights, overflowing activations
     E = En.clone()
-    rc, st = ctx.solve(E, rt.solve_opts(rt.MODE_LEARNED, tol=1e-8, net=net))
+    rc, st = ctx.solve(E, rt.solve_opts(rt.MODE_LEARNED, tol=1e-8, net=net, inner=inner))
     assert st["fallback"] == 1 and st["handover"] == 0 and st["relres"] <= 1e-8
     assert np.all(np.isfinite(E.cpu().numpy()))
 
@@ -553,7 +574,8 @@ def test_learned_solve_with_reduced_mixed_finish():
     assert float(((Tl - Tf).abs() / Tf).max()) < 1e-5
 
 
-def test_learned_solves_against_the_oracle_dense_solve():
+@pytest.mark.parametrize("inner", [0, 1], ids=["fcg", "fgmres"])
+def test_learned_solves_against_the_oracle_dense_solve(inner):
     """The learned solve (float64 finish) and the learned solve with the reduced mixed
     finish, with a briefly trained network, against the oracle on 32 x 8 x 8: the
     oracle's own assembly and residual of the GPU's answer meet the tolerance, and the
@@ -580,7 +602,7 @@ def test_learned_solves_against_the_oracle_dense_solve():
     for reduce, budget in ((0, 20), (1, 5)):
         E = En.clone()
         rc, sl = ctx.solve(E, rt.solve_opts(rt.MODE_LEARNED, tol=1e-8, net=net, inner_max_iter=budget,
-                                            reduce=reduce))
+                                            reduce=reduce, inner=inner))
         assert rc == rt.RT_OK and sl["fallback"] == 0 and sl["precond_applies"] >= 1
         Eg = E.cpu().numpy()
         res = P.relres(out["ahat"], out["bhat"], Eg / out["s"])
@@ -592,6 +614,85 @@ def test_learned_solves_against_the_oracle_dense_solve():
               f"oracle relres {res:.3e}, T err {eT:.2e}, E err {eE:.2e} vs the oracle's dense solve")
         assert res <= 1.05e-8
         assert eT <= 1e-3
+
+
+def _oracle_system(P, wl):
+    """The oracle's assembled system of the first step from T_bc (the state
+    _small_problem_sys prepares on the GPU)."""
+    rh = wl.rho.ravel()
+    To = np.full(P.n, wl.T_bc)
+    _, So, _ = P.raytrace(rh, To, want_faces=False)
+    To = P.newton(np.full(P.n, sy.A_RAD * wl.T_bc ** 4), So, To)
+    qo, So, _ = P.raytrace(rh, To, want_faces=False)
+    return P.assemble(rh, To, P.energy(To, So), qo)
+
+
+def _linear_path_params(c):
+    """Parameters of a network that maps its input channel 0 to c times itself: layer 0
+    splits x into relu(x) and relu(-x) (channels 0 and 1), layers 1, 8 (from the skip
+    connection) and 9 pass both on, the output layer takes c (relu(x) - relu(-x)) = c x.
+    Every value it passes is a bf16 of the input times +-1, so its only error is the
+    input's rounding to bf16: as a preconditioner it is c times the identity up to that
+    rounding."""
+    p = np.zeros(NN.param_count(), dtype=np.float32)
+    centre = 13
+    for l, co, ci, g in ((0, 0, 0, 1.0), (0, 1, 0, -1.0), (1, 0, 0, 1.0), (1, 1, 1, 1.0),
+                         (8, 0, 32, 1.0), (8, 1, 33, 1.0), (9, 0, 0, 1.0), (9, 1, 1, 1.0)):
+        taps, cout, cin = NN.layer_shapes()[l]
+        p[NN.param_offset(l) + (centre * cout + co) * cin + ci] = g
+    o = NN.param_offset(10)
+    p[o + 0], p[o + 1] = c, -c
+    return p
+
+
+def test_fgmres_with_a_scaled_identity_network_converges_like_gmres():
+    """Flexible GMRES(30) whose network is 3 x the identity (up to the bf16 rounding of its
+    input) against plain GMRES(30) on the same system: the same convergence (within 25 %
+    + 5 iterations), one application per iteration, no hand-over; the oracle's residual of
+    the answer meets the tolerance.  The update must combine the preconditioned vectors
+    Z: combining the Arnoldi basis instead would move y by a third of the step."""
+    import oracle
+    from paper_1001_3301_amd import rt
+    shape = (32, 8, 8)
+    wl, ctx, rho, T, En, S, sysv = _small_problem_sys(shape=shape, tau=10.0, seed=5)
+    net = rt.Net(seed=1)
+    net.set_params(_linear_path_params(3.0))
+    r = _rng(41).standard_normal(ctx.n).astype(np.float32)
+    z = torch.empty(ctx.n, dtype=torch.float32, device="cuda")
+    net.apply(ctx, dev_f32(r), z)
+    zr = z.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(zr - 3.0 * r)) <= 3.0 * 2.0 ** -8 * np.max(np.abs(r))
+    E_g = En.clone()
+    rc, sg = ctx.solve(E_g, rt.solve_opts(rt.MODE_GMRES, tol=1e-8, restart=30))
+    E = En.clone()
+    rc, sf = ctx.solve(E, rt.solve_opts(rt.MODE_LEARNED, tol=1e-8, net=net, inner_max_iter=100000, restart=30,
+                                        inner=rt.INNER_FGMRES))
+    print(f"GMRES(30) {sg['iters']} iterations; flexible GMRES(30) with 3 I: {sf['iters']} iterations, "
+          f"{sf['precond_applies']} applications, relres {sf['relres']:.3e}")
+    assert rc == rt.RT_OK and sf["handover"] == 0 and sf["fallback"] == 0
+    assert sf["precond_applies"] == sf["iters"]
+    assert sf["relres"] <= 1e-8
+    assert sf["iters"] <= 1.25 * sg["iters"] + 5
+    # the oracle's own residual of the GPU's answer, on the system the oracle assembles
+    P = oracle.Problem.from_workload(wl)
+    out = _oracle_system(P, wl)
+    assert P.relres(out["ahat"], out["bhat"], E.cpu().numpy() / out["s"]) <= 1.05e-8
+
+
+def test_fgmres_hands_over_when_the_budget_is_spent():
+    """inner_max_iter = 3 network applications: the cycle is closed after three flexible
+    GMRES steps and the planned finish (float64 CG; with reduce = 1 the reduced mixed
+    solve) meets the tolerance."""
+    from paper_1001_3301_amd import rt
+    wl, ctx, rho, T, En, S = _small_problem()
+    net = rt.Net(seed=3)
+    for reduce in (0, 1):
+        E = En.clone()
+        rc, sl = ctx.solve(E, rt.solve_opts(rt.MODE_LEARNED, tol=1e-8, net=net, inner_max_iter=3, reduce=reduce,
+                                            inner=rt.INNER_FGMRES))
+        assert sl["handover"] == 1 and sl["fallback"] == 0 and sl["precond_applies"] == 3
+        assert sl["relres"] <= 1e-8 and sl["reduced"] == reduce
+        assert np.all(np.isfinite(E.cpu().numpy()))
 
 
 def test_net_apply_is_the_scaled_forward_of_the_solver_input():
