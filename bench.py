@@ -58,14 +58,23 @@ MEASURED_TRAFFIC = {("k_cg_dir<float>", "clumpy-512x256x512-nu64"): 1.924e9,
                     ("k_rb_black_dir<double>", "clumpy-512x256x512-nu64"): 2.582e9}
 
 
-# The ray trace is bound by float64 instruction issue: a wavefront handles one cell per
-# step with its lanes on the bins, so VALU wave-instructions per cell is a property of the
-# kernel (rocprofv3 SQ_INSTS_VALU on the 512x256x512 workload,
+# The ray trace is bound by float64 instruction issue.  On this workload the step's ray
+# trace is k_raytrace_r (lanes on radial cells, 8 cells a lane: one VALU instruction of a
+# wavefront covers 64 cell-bins, so VALU wave-instructions per cell and bin is a property
+# of the kernel; rocprofv3 SQ_INSTS_VALU on the 512x256x512 workload,
 # profiles/raytrace_counters_clumpy-512x256x512-nu64.md), and the chip issues at most one
 # float64 wave-instruction per CU per cycle (4 SIMDs, 4 cycles per wave64 instruction):
-# 256 CUs x 2.4 GHz.
-RAYTRACE_VALU_PER_CELL = 31.3
+# 256 CUs x 2.4 GHz.  The algorithm itself needs ~35 float64 operations per cell and bin.
+# (Columns that do not fill their 512-cell segments to 90 % take lanes on bins,
+# k_raytrace<false, false>, 31.3 instructions per cell and bin.)
+RAYTRACE_KERNELS = {True: ("k_raytrace_r", 32.9), False: ("k_raytrace<false, false>", 31.3)}
 RAYTRACE_ALG_INSTS_PER_CELL = 35.0
+
+
+def raytrace_kernel(nr):
+    """(kernel name, VALU wave-instructions per cell and bin) of the step's ray trace."""
+    seg = -(-nr // 512)
+    return RAYTRACE_KERNELS[10 * nr >= 9 * 512 * seg]
 PEAK_FP64_WAVE_INSTS = 256 * 2.4e9
 
 
@@ -390,9 +399,7 @@ def raytrace_mappings(ctx, rt, torch, rho, T, n_nu, reps=5):
     out["q_max_rel_diff"] = float(relq)
     out["S_max_rel_diff"] = float(relS)
     out["cells_over_bins_time"] = out["lanes_cells"]["ms"] / out["lanes_bins"]["ms"]
-    nr = ctx.shape[0]
-    seg = -(-nr // 512)
-    out["step_uses"] = "lanes_cells" if 10 * nr >= 9 * 512 * seg else "lanes_bins"
+    out["step_uses"] = "lanes_cells" if raytrace_kernel(ctx.shape[0])[0] == "k_raytrace_r" else "lanes_bins"
     del res, q1, S1, q2, S2
     torch.cuda.empty_cache()
     return out
@@ -621,6 +628,7 @@ def main():
     else:
         dom_b, dom_ms, dom_cells = (bpc["dir"], ms_dir, n) if bpc else (0, 0.0, n)
     achieved = dom_b * dom_cells / (dom_ms / 1e3) / 1e9 if (bpc and dom_ms > 0) else 0.0
+    rt_kernel, rt_valu = raytrace_kernel(ctx.shape[0])
     out = {
         "metric": METRIC,
         "value": value,
@@ -639,13 +647,12 @@ def main():
                    "solve_mode": head, "tol": args.tol, "dt": wl.dt,
                    "step": "first step from the prepared state, repeated K times"},
         "raytrace_gcell_nu_per_s": statistics.median([n * c["n_nu"] / (x / 1e3) / 1e9 for x in rt_ms]),
-        "raytrace_roofline": {"kernel": "k_raytrace<false, false>", "bound": "alu",
+        "raytrace_roofline": {"kernel": rt_kernel, "bound": "alu",
                               "unit": "float64 VALU wave-instructions/s",
-                              "achieved": RAYTRACE_VALU_PER_CELL * n / (statistics.median(rt_ms) / 1e3),
+                              "achieved": rt_valu * n / (statistics.median(rt_ms) / 1e3),
                               "peak": PEAK_FP64_WAVE_INSTS,
-                              "frac": RAYTRACE_VALU_PER_CELL * n / (statistics.median(rt_ms) / 1e3)
-                              / PEAK_FP64_WAVE_INSTS,
-                              "valu_insts_per_cell": RAYTRACE_VALU_PER_CELL,
+                              "frac": rt_valu * n / (statistics.median(rt_ms) / 1e3) / PEAK_FP64_WAVE_INSTS,
+                              "valu_insts_per_cell": rt_valu,
                               # the same bound priced on the algorithm's own count rather
                               # than the instructions issued: one exp/expm1 pair and ~8 more
                               # float64 operations per cell-bin, ~35 instructions

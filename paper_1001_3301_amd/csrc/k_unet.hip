@@ -652,13 +652,14 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 // kDecTJ cells (r x theta) over a chunk of kSlideP phi planes and walks it plane by
 // plane like conv_slide.  The skip channels keep conv_slide's ring of three fine halo
 // planes.  The upsampled channels are never expanded: the ring holds the coarse planes
-// themselves (an 18 x 10 cell halo plane covers the fine (kTR + 2) x (kDecTJ + 2)
-// plane), one new coarse plane every second step, and each fine cell's tap reads its
-// coarse parent.  For those channels K = 32 is one tap x the 32 channels (lanes 0..31
+// themselves (a (kTR/2 + 2) x (kDecTJ/2 + 2) halo plane covers the fine (kTR + 2) x (kDecTJ + 2)
+// plane), one new coarse plane every second step (two slots: a fine step reads two coarse
+// planes, and the new one replaces the older after the step's MFMAs), and each fine
+// cell's tap reads its coarse parent.  For those channels K = 32 is one tap x the 32 channels (lanes 0..31
 // the first 16, lanes 32..63 the other 16), so 27 MFMAs per segment and no padding tap;
 // the skip channels use conv_slide's tap pairs.  Same operands and the same FP32 sums as
 // the tiled kernel, only ordered differently.
-constexpr int kDecWaves = 8;
+constexpr int kDecWaves = 12;
 constexpr int kDecTB = 64 * kDecWaves;
 constexpr int kDecTJ = 2 * kDecWaves;  // theta rows of a block (two per wavefront)
 
@@ -670,10 +671,10 @@ struct DecGeom {
     static constexpr int coarse_bytes = 2 * cslice_bytes;
     static constexpr int wskip_bytes = 28 * 32 * 16;        // tap pairs, zero tap 27
     static constexpr int wup_bytes = 27 * 64 * 16;
-    static constexpr int lds = 3 * fine_bytes + 3 * coarse_bytes + wskip_bytes + wup_bytes;
+    static constexpr int lds = 3 * fine_bytes + 2 * coarse_bytes + wskip_bytes + wup_bytes;
 };
 
-__global__ __launch_bounds__(kDecTB) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_conv_fwd_dec(
+__global__ __launch_bounds__(kDecTB) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_conv_fwd_dec(
     Lv L, const bf16 *__restrict__ x1, const bf16 *__restrict__ x2, const bf16 *__restrict__ w,
     const float *__restrict__ bias, int relu, bf16 *__restrict__ y, float *__restrict__ yf)
 {
@@ -682,7 +683,7 @@ __global__ __launch_bounds__(kDecTB) __attribute__((amdgpu_waves_per_eu(2, 8))) 
     extern __shared__ uint4 smem_u4[];
     char *lds = reinterpret_cast<char *>(smem_u4);
     char *cring = lds + 3 * G::fine_bytes;
-    char *wsk = cring + 3 * G::coarse_bytes;
+    char *wsk = cring + 2 * G::coarse_bytes;
     char *wup = wsk + G::wskip_bytes;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int cr = L.nr >> 1, ct = L.nt >> 1, cp = L.np >> 1;
@@ -693,7 +694,7 @@ __global__ __launch_bounds__(kDecTB) __attribute__((amdgpu_waves_per_eu(2, 8))) 
     const int q0 = item / ntj, tj = item - q0 * ntj, chunk = q0 / ntr, tr = q0 - chunk * ntr;
     const int r0 = tr * kTR, j0 = tj * kDecTJ, k0 = chunk * kSlideP;  // all even
     const int k1 = min(L.np, k0 + kSlideP);
-    const int c0 = (k0 >> 1) - 1;  // coarse plane c lives in ring slot (c - c0) mod 3
+    const int c0 = (k0 >> 1) - 1;  // coarse plane c lives in ring slot (c - c0) mod 2
     // weights: skip channels 32..47 as tap pairs [tap][co + 16 half], up channels 0..31 as
     // [tap][co + 16 (ci / 8)]
     if (tid < 32) *reinterpret_cast<u32x4 *>(wsk + (27 * 32 + tid) * 16) = u32x4{0u, 0u, 0u, 0u};
@@ -802,8 +803,8 @@ __global__ __launch_bounds__(kDecTB) __attribute__((amdgpu_waves_per_eu(2, 8))) 
         const int sb0 = ((k - k0) % 3) * G::fine_bytes, sb1 = ((k - k0 + 1) % 3) * G::fine_bytes,
                   sb2 = ((k - k0 + 2) % 3) * G::fine_bytes;
         // coarse ring slots of the planes under fine planes k - 1, k, k + 1
-        const int cs0 = (((k - 1) >> 1) - c0) % 3 * G::coarse_bytes, cs1 = ((k >> 1) - c0) % 3 * G::coarse_bytes,
-                  cs2 = (((k + 1) >> 1) - c0) % 3 * G::coarse_bytes;
+        const int cs0 = ((((k - 1) >> 1) - c0) & 1) * G::coarse_bytes, cs1 = (((k >> 1) - c0) & 1) * G::coarse_bytes,
+                  cs2 = ((((k + 1) >> 1) - c0) & 1) * G::coarse_bytes;
         float4v acc[PW];
 #pragma unroll
         for (int q = 0; q < PW; q++) acc[q] = float4v{0.f, 0.f, 0.f, 0.f};
@@ -857,7 +858,7 @@ __global__ __launch_bounds__(kDecTB) __attribute__((amdgpu_waves_per_eu(2, 8))) 
         });
         __syncthreads();  // every wavefront is done with the slots being replaced
         if (more) put((k - k0) % 3, v, okm);
-        if (cmore) put_c(((k >> 1) + 1 - c0) % 3, vc, okc);
+        if (cmore) put_c(((k >> 1) + 1 - c0) & 1, vc, okc);
 #pragma unroll
         for (int q = 0; q < PW; q++) {
             const int a = r0 + (q & 1) * 16 + e, b = j0 + 2 * wv + (q >> 1);
