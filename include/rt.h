@@ -459,6 +459,13 @@ rt_status rt_net_train(rt_ctx *ctx, rt_net *net, rt_dataset *ds, const rt_train_
  * convolutions (and the network) take grids of fewer than 2^31 cells (RT_EINVAL). */
 rt_status rt_nn_conv3d_fwd(void *stream, int nr, int nt, int np, const void *x1, int c1, int up1, const void *x2,
                            int c2, const void *w, const float *bias, int cout, int relu, void *y, float *yf);
+/* The U-Net's pooled layer in one pass: y = relu(conv3x3x3(x, w) + bias) with 16 input
+ * and 16 output channels (bf16 y[nr nt np][16]) and its 2x2x2 average pool on the 2x
+ * coarser level (bf16 yp[nr/2 nt/2 np/2][16], the children summed in fp32 in the order
+ * r, theta, phi); the same bits as rt_nn_conv3d_fwd followed by that pooling.  nr, nt,
+ * np even (RT_EINVAL otherwise, or for a NULL pointer). */
+rt_status rt_nn_conv3d_fwd_pool(void *stream, int nr, int nt, int np, const void *x, const void *w, const float *bias,
+                                void *y, void *yp);
 /* Data gradient: d[x1|x2] = conv^T(dy masked by yrelu > 0 when yrelu != NULL) with the
  * transposed weights wt[(tap * Cin + ci) * Cout + co]; fp32 outputs on the level of dy
  * (for an upsampled x1, the gradient of the upsampled tensor). */

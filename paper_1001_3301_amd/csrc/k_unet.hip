@@ -376,8 +376,10 @@ template <int TJ>
 constexpr size_t slide_lds_bytes() { return 3 * (size_t)SlidePlane<TJ>::bytes + 28 * 512; }
 
 // Forward convolution with 16 input and 16 output channels; load / finish as for
-// conv_tiles; store(idx, ch, v, ok) is called by every lane (ok false for cells outside
-// the grid, idx then 0), so an epilogue may exchange values between lanes.  Item i of the grid: theta tile fastest, then r tile, then phi chunk;
+// conv_tiles; store(idx, ch, v, ok, q, k) is called by every lane (ok false for cells
+// outside the grid, idx then 0), so an epilogue may exchange values between lanes; q is
+// the wavefront's segment (r half q & 1 of theta row 2 wv + q / 2) and k the phi plane,
+// in the order the segments and planes are finished.  Item i of the grid: theta tile fastest, then r tile, then phi chunk;
 // gridDim.x is a multiple of 8 and the items of one eighth run on one XCD (block b on
 // XCD b % 8), so the blocks resident together are neighbours in theta and r and share
 // their halos in that XCD's L2.
@@ -502,7 +504,7 @@ __device__ __forceinline__ void conv_slide(const Lv &L, const bf16 *__restrict__
         for (int q = 0; q < PW; q++) {
             const int a = r0 + (q & 1) * 16 + (lane & 15), b = j0 + 2 * wv + (q >> 1);
             const bool ok = a < L.nr && b < L.nt;
-            store(ok ? a + L.nr * (b + L.nt * k) : 0, 4 * (lane >> 4), acc[q], ok);
+            store(ok ? a + L.nr * (b + L.nt * k) : 0, 4 * (lane >> 4), acc[q], ok, q, k);
         }
         __syncthreads();  // plane k + 2 is in the ring for the next step
     }
@@ -549,7 +551,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(NT == 1 ? 3
         if (yf) *reinterpret_cast<float4 *>(yf + (size_t)idx * cout + co) = make_float4(o[0], o[1], o[2], o[3]);
     };
     if constexpr (SLIDE)  // NT = 1, c1 + c2 = 16
-        conv_slide<TJ>(L, w, load, finish, [&](int idx, int co, const float4v &v, bool ok) {
+        conv_slide<TJ>(L, w, load, finish, [&](int idx, int co, const float4v &v, bool ok, int, int) {
             if (ok) store(idx, co, v);
         });
     else conv_tiles<NT, TJ, TK, 1, false>(L, c1 + c2, w, load, finish, store);
@@ -591,7 +593,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         *reinterpret_cast<uint2 *>(y + (size_t)idx * 16 + co) = make_uint2(pack_bf16(o[0], o[1]), pack_bf16(o[2], o[3]));
     };
     if constexpr (SLIDE)
-        conv_slide<kSlideTJ>(L, w, load, finish, [&](int idx, int co, const float4v &v, bool ok) {
+        conv_slide<kSlideTJ>(L, w, load, finish, [&](int idx, int co, const float4v &v, bool ok, int, int) {
             if (ok) store(idx, co, v);
         });
     else conv_tiles<1, 4, 4, 1, false>(L, 16, w, load, finish, store);
@@ -620,7 +622,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     for (int q = 0; q < 16; q++) wof[q] = bf2f(wo[q]);
     const float b0 = bo[0];
     const double sc = scale ? scale[1] : 1.0;
-    auto store = [&](int idx, int, const float4v &v, bool ok) {
+    auto store = [&](int idx, int, const float4v &v, bool ok, int, int) {
         float o[4] = {v[0] + bb.x, v[1] + bb.y, v[2] + bb.z, v[3] + bb.w};
 #pragma unroll
         for (int i = 0; i < 4; i++) o[i] = o[i] < 0.0f ? 0.0f : o[i];
@@ -639,6 +641,57 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             for (int q = 0; q < 16; q++)
                 s = fmaf(wof[q], bf2f((bf16)(q & 1 ? hv[q >> 1] >> 16 : hv[q >> 1] & 0xFFFFu)), s);
             z[idx] = scale ? (float)((double)s * sc) : s;
+        }
+    };
+    conv_slide<kSlideTJ>(L, w, load, finish, store);
+}
+
+// y = relu(conv(x, w) + bias) (16 -> 16, the sliding kernel, bf16 out) and its 2x2x2
+// average pool yp on the next coarser level in the same pass (the fine level's second
+// layer, whose output is both the skip connection and the input of level 1).  The block
+// walks phi planes in pairs from an even plane, each wavefront owns a pair of theta rows
+// (an even one first) and the two cells of an r pair sit in lanes l and l ^ 1, so the
+// eight children of a coarse cell meet in the even lane as r, theta, phi advance: the
+// same bf16 values summed in fp32 in the same order as k_pool, hence the same bits.  Every
+// dimension of the level is even.
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_conv_fwd_pool(
+    Lv L, const bf16 *__restrict__ x, const bf16 *__restrict__ w, const float *__restrict__ bias,
+    bf16 *__restrict__ y, bf16 *__restrict__ yp)
+{
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    auto load = [&](int idx, int, int, int, int ch) -> u32x4 {
+        return *reinterpret_cast<const u32x4 *>(x + (size_t)idx * 16 + ch);
+    };
+    auto finish = [](const u32x4 &v, bool ok) -> u32x4 { return ok ? v : u32x4{0u, 0u, 0u, 0u}; };
+    const int lane = threadIdx.x & 63;
+    const float4 bb = *reinterpret_cast<const float4 *>(bias + 4 * (lane >> 4));
+    const int cr = L.nr >> 1, ct = L.nt >> 1;
+    float ps[2][4];  // the running sums of this lane's 4 channels, per r half of the segments
+    auto store = [&](int idx, int co, const float4v &v, bool ok, int q, int k) {
+        float o[4] = {v[0] + bb.x, v[1] + bb.y, v[2] + bb.z, v[3] + bb.w};
+#pragma unroll
+        for (int i = 0; i < 4; i++) o[i] = o[i] < 0.0f ? 0.0f : o[i];
+        const unsigned d0 = pack_bf16(o[0], o[1]), d1 = pack_bf16(o[2], o[3]);
+        if (ok) *reinterpret_cast<uint2 *>(y + (size_t)idx * 16 + co) = make_uint2(d0, d1);
+        const float h[4] = {bf2f((bf16)(d0 & 0xFFFFu)), bf2f((bf16)(d0 >> 16)), bf2f((bf16)(d1 & 0xFFFFu)),
+                            bf2f((bf16)(d1 >> 16))};
+        const int rh = q & 1;
+        if (q < 2 && (k & 1) == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; i++) ps[rh][i] = 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const float nb = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(h[i]), 0x041F));  // lane ^ 1
+            ps[rh][i] += h[i];
+            ps[rh][i] += nb;
+        }
+        if (q >= 2 && (k & 1) == 1 && (lane & 1) == 0 && ok) {
+            const int b = (idx / L.nr) % L.nt, a = idx % L.nr;
+            const size_t g = (size_t)((a >> 1) + cr * ((b >> 1) + ct * (k >> 1)));
+            *reinterpret_cast<uint2 *>(yp + g * 16 + co) =
+                make_uint2((unsigned)f2bf(ps[rh][0] * 0.125f) | ((unsigned)f2bf(ps[rh][1] * 0.125f) << 16),
+                           (unsigned)f2bf(ps[rh][2] * 0.125f) | ((unsigned)f2bf(ps[rh][3] * 0.125f) << 16));
         }
     };
     conv_slide<kSlideTJ>(L, w, load, finish, store);
@@ -1383,6 +1436,15 @@ void launch_fwd_slide(const Lv &L, const bf16 *x1, int c1, int up1, const bf16 *
     (void)attr;
     hipLaunchKernelGGL((k_conv_fwd<1, kSlideTJ, 1, true>), dim3(slide_grid(L)), dim3(kTB), lds, s, L, x1, c1, up1, x2,
                        c2, w, b, relu, y, yf);
+}
+
+void launch_conv_fwd_pool(const Lv &L, const bf16 *x, const bf16 *w, const float *b, bf16 *y, bf16 *yp, hipStream_t s)
+{
+    constexpr size_t lds = slide_lds_bytes<kSlideTJ>();
+    static const bool attr = hipFuncSetAttribute((const void *)k_conv_fwd_pool, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds) == hipSuccess;
+    (void)attr;
+    hipLaunchKernelGGL(k_conv_fwd_pool, dim3(slide_grid(L)), dim3(kTB), lds, s, L, x, w, b, y, yp);
 }
 
 void launch_conv_fwd_head(const Lv &L, const bf16 *x, const bf16 *w, const float *b, const bf16 *wo, const float *bo,

@@ -312,6 +312,9 @@ long wgrad_part_floats(const Lv &L, int cout, int cin);
 // scale[1] when scale != nullptr), without writing h; bit for bit the two layers' result.
 void launch_conv_fwd_head(const Lv &L, const bf16 *x, const bf16 *w, const float *b, const bf16 *wo, const float *bo,
                           const double *scale, float *z, hipStream_t s);
+// y = relu(conv(x, w) + b) (16 -> 16, bf16) and yp = its 2x2x2 average pool on the next
+// coarser level (16 channels), in one pass; bit for bit the two kernels' results.
+void launch_conv_fwd_pool(const Lv &L, const bf16 *x, const bf16 *w, const float *b, bf16 *y, bf16 *yp, hipStream_t s);
 void launch_pool(const Lv &Lc, int C, const bf16 *x, bf16 *y, hipStream_t s);
 void launch_pool_bwd_add(const Lv &Lf, int C, const float *dyc, float *dxf, hipStream_t s);
 void launch_up_bwd(const Lv &Lc, int C, const float *dyf, float *dxc, hipStream_t s);

@@ -207,8 +207,7 @@ void forward(rt_net *N, hipStream_t s, bool keep, const float *r = nullptr, cons
 #define BL(l) (P + poff(l) + wcount(l))
     if (r) nn::launch_conv_fwd_in(L[0], N->X, r, scale, WL(0), BL(0), N->a[0], s);
     else conv_fwd(L[0], N->X, 16, 0, nullptr, 0, WL(0), BL(0), 16, 1, N->a[0], nullptr, s);
-    conv_fwd(L[0], N->a[0], 16, 0, nullptr, 0, WL(1), BL(1), 16, 1, N->a[1], nullptr, s);
-    pool(L[1], 16, N->a[1], N->p1, s);
+    nn::launch_conv_fwd_pool(L[0], N->a[0], WL(1), BL(1), N->a[1], N->p1, s);  // layer 1 and its pooling
     conv_fwd(L[1], N->p1, 16, 0, nullptr, 0, WL(2), BL(2), 32, 1, N->a[2], nullptr, s);
     conv_fwd(L[1], N->a[2], 32, 0, nullptr, 0, WL(3), BL(3), 32, 1, N->a[3], nullptr, s);
     pool(L[2], 32, N->a[3], N->p2, s);
@@ -491,6 +490,18 @@ rt_status rt_nn_conv3d_fwd(void *stream, int nr, int nt, int np, const void *x1,
     Lv L{nr, nt, np, (long)nr * nt * np};
     conv_fwd(L, (const bf16 *)x1, c1, up1, (const bf16 *)x2, c2, (const bf16 *)w, bias, cout, relu, (bf16 *)y, yf,
              (hipStream_t)stream);
+    NN_HIP(nullptr, hipGetLastError());
+    return RT_OK;
+}
+
+rt_status rt_nn_conv3d_fwd_pool(void *stream, int nr, int nt, int np, const void *x, const void *w, const float *bias,
+                                void *y, void *yp)
+{
+    if (nr < 2 || nt < 2 || np < 2 || nr % 2 || nt % 2 || np % 2 || !x || !w || !bias || !y || !yp ||
+        (long)nr * nt * np >= (1L << 31))
+        return nfail(nullptr, RT_EINVAL, "rt_nn_conv3d_fwd_pool: bad arguments");
+    Lv L{nr, nt, np, (long)nr * nt * np};
+    nn::launch_conv_fwd_pool(L, (const bf16 *)x, (const bf16 *)w, bias, (bf16 *)y, (bf16 *)yp, (hipStream_t)stream);
     NN_HIP(nullptr, hipGetLastError());
     return RT_OK;
 }

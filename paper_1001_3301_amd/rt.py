@@ -104,7 +104,7 @@ EXPORTS = ["rt_create", "rt_destroy", "rt_last_error", "rt_ncell", "rt_star_bin_
            "rt_net_get_params", "rt_net_get_grads", "rt_net_set_params", "rt_net_save", "rt_net_load",
            "rt_net_forward", "rt_net_apply", "rt_net_loss_grad", "rt_net_loss_grad_resid", "rt_net_adam", "rt_dataset_create",
            "rt_dataset_destroy", "rt_dataset_size", "rt_dataset_add", "rt_dataset_add_learned", "rt_net_train",
-           "rt_nn_conv3d_fwd", "rt_nn_conv3d_bwd_data", "rt_nn_conv3d_bwd_weight",
+           "rt_nn_conv3d_fwd", "rt_nn_conv3d_fwd_pool", "rt_nn_conv3d_bwd_data", "rt_nn_conv3d_bwd_weight",
            "rt_nn_conv3d_bwd_weight_noalloc"]
 
 
@@ -190,6 +190,7 @@ def lib():
     L.rt_net_train.argtypes = [vp, vp, vp, P(TrainOpts), P(TrainStats)]
     ip = C.c_int
     L.rt_nn_conv3d_fwd.argtypes = [vp, ip, ip, ip, vp, ip, ip, vp, ip, vp, vp, ip, ip, vp, vp]
+    L.rt_nn_conv3d_fwd_pool.argtypes = [vp, ip, ip, ip, vp, vp, vp, vp, vp]
     L.rt_nn_conv3d_bwd_data.argtypes = [vp, ip, ip, ip, vp, vp, ip, vp, ip, vp, ip, vp]
     L.rt_nn_conv3d_bwd_weight.argtypes = [vp, ip, ip, ip, vp, vp, ip, vp, ip, ip, vp, ip, vp, vp]
     L.rt_nn_conv3d_bwd_weight_noalloc.argtypes = [vp, ip, ip, ip, vp, vp, ip, vp, ip, ip, vp, ip, vp, vp]
@@ -573,6 +574,16 @@ def nn_conv_fwd(shape, x1, c1, up1, x2, c2, w, b, cout, relu, y=None, yf=None):
     nr, nt, npp = shape
     st = lib().rt_nn_conv3d_fwd(C.c_void_p(torch.cuda.current_stream().cuda_stream), nr, nt, npp, _vp(x1), c1,
                                 int(up1), _vp(x2), c2, _vp(w), _vp(b), cout, int(relu), _vp(y), _vp(yf))
+    if st != RT_OK:
+        raise RtError(st, lib().rt_net_last_error(None).decode())
+
+
+def nn_conv_fwd_pool(shape, x, w, b, y, yp):
+    """16 -> 16 forward convolution with ReLU and its 2x2x2 average pool in one pass."""
+    import torch
+    nr, nt, npp = shape
+    st = lib().rt_nn_conv3d_fwd_pool(C.c_void_p(torch.cuda.current_stream().cuda_stream), nr, nt, npp, _vp(x),
+                                     _vp(w), _vp(b), _vp(y), _vp(yp))
     if st != RT_OK:
         raise RtError(st, lib().rt_net_last_error(None).decode())
 

@@ -120,6 +120,43 @@ def test_conv_forward_parity(case):
     assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
 
 
+def _pool_bits_host(shape, ybits):
+    """2x2x2 average of bf16 values (bits), summed in float32 in the order r, theta, phi and
+    rounded to bf16 (round to nearest even): the arithmetic of the network's pooling."""
+    nr, nt, npp = shape
+    yv = bits_to_f64(ybits).astype(np.float32).reshape(npp, nt, nr, 16)
+    s = np.zeros((npp // 2, nt // 2, nr // 2, 16), dtype=np.float32)
+    for q in range(8):
+        dr, dt, dp = q & 1, (q >> 1) & 1, q >> 2
+        s = (s + yv[dp::2, dt::2, dr::2]).astype(np.float32)
+    return bf16_bits((s * np.float32(0.125)).astype(np.float32)).reshape(-1)
+
+
+@pytest.mark.parametrize("shape", [(72, 18, 70), (40, 12, 36), (8, 4, 4)], ids=str)
+def test_conv_with_pooling_in_one_pass(shape):
+    """rt_nn_conv3d_fwd_pool: y the same bits as rt_nn_conv3d_fwd (16 -> 16, ReLU), its
+    pool the same bits as the 2x2x2 average of y in float32 (r, theta, phi order), and both
+    against the oracle (conv and pool of the same bf16 operands in float64).  72 x 18 x 70
+    crosses r and theta tiles and phi chunks (with a partial one)."""
+    from paper_1001_3301_amd import rt
+    case = (shape, 16, 0, 0, 16)
+    n, x1, x2, w, b, xcat, cin = _conv_inputs(case, 11)
+    nc = n // 8
+    y = torch.empty(n * 16, dtype=torch.bfloat16, device="cuda")
+    yp = torch.empty(nc * 16, dtype=torch.bfloat16, device="cuda")
+    y2 = torch.empty(n * 16, dtype=torch.bfloat16, device="cuda")
+    rt.nn_conv_fwd_pool(shape, dev_bf16(x1), dev_bf16(w), dev_f32(b), y, yp)
+    rt.nn_conv_fwd(shape, dev_bf16(x1), 16, 0, None, 0, dev_bf16(w), dev_f32(b), 16, True, y2, None)
+    yb = y.view(torch.int16).cpu().numpy().view(np.uint16)
+    assert np.array_equal(yb, y2.view(torch.int16).cpu().numpy().view(np.uint16))
+    pb = yp.view(torch.int16).cpu().numpy().view(np.uint16)
+    assert np.array_equal(pb, _pool_bits_host(shape, yb))
+    ref = NN.conv_fwd(shape, xcat, 16, bits_to_f64(w), b.astype(np.float64), 16, True)
+    refp = NN.pool(shape, ref, 16)
+    assert np.max(np.abs(bits_to_f64(yb) - ref)) <= 2.0 ** -8 * np.max(np.abs(ref))
+    assert np.max(np.abs(bits_to_f64(pb) - refp)) <= 2.0 ** -7 * np.max(np.abs(refp))
+
+
 @pytest.mark.parametrize("case", CONV_CASES_ALL, ids=[str(c) for c in CONV_CASES_ALL])
 def test_conv_backward_parity(case):
     from paper_1001_3301_amd import rt
