@@ -176,26 +176,34 @@ def c4_gain(rt, torch, sy, n_fields=200, eval_seeds=(10000, 10001, 10002, 10003,
     seconds to the relative residual 1e-8 of: learned flexible CG (the trained network,
     up to fcg_budget applications before the planned float64 finish), the same with an
     untrained network of the same shape, Jacobi-preconditioned CG (float64; Jacobi FCG is
-    CG on the Jacobi-scaled system), and the benchmark's reduced solves with and without
-    five network applications in front (learned-rb vs mixed-rb)."""
+    CG on the Jacobi-scaled system), the same three with flexible GMRES(30) (the network
+    as its right preconditioner; plain GMRES(30) on the Jacobi-scaled system), and the
+    benchmark's reduced solves with and without five network applications in front
+    (learned-rb vs mixed-rb)."""
     t0 = time.perf_counter()
     net, info = train_network(rt, torch, sy, n_fields, epochs)
     untrained = rt.Net(seed=12345)
     wl0 = sy.make_workload("c4-eval", 256, 128, 256, 64, 100.0, eval_seeds[0])
     ctx = rt.Context.from_workload(wl0)
     rows = []
-    modes = {"learned_fcg": (rt.MODE_LEARNED, net, fcg_budget, 0),
-             "untrained_fcg": (rt.MODE_LEARNED, untrained, fcg_budget, 0),
-             "jacobi_cg_fp64": (rt.MODE_FP64, None, 0, 0),
-             "learned_rb_5": (rt.MODE_LEARNED, net, 5, 1),
-             "mixed_rb": (rt.MODE_MIXED, None, 0, 1)}
+    FG = rt.INNER_FGMRES
+    modes = {"learned_fcg": (rt.MODE_LEARNED, net, fcg_budget, 0, rt.INNER_FCG),
+             "untrained_fcg": (rt.MODE_LEARNED, untrained, fcg_budget, 0, rt.INNER_FCG),
+             "jacobi_cg_fp64": (rt.MODE_FP64, None, 0, 0, rt.INNER_FCG),
+             "learned_fgmres": (rt.MODE_LEARNED, net, fcg_budget, 0, FG),
+             "untrained_fgmres": (rt.MODE_LEARNED, untrained, fcg_budget, 0, FG),
+             "jacobi_gmres_fp64": (rt.MODE_GMRES, None, 0, 0, rt.INNER_FCG),
+             "learned_rb_5": (rt.MODE_LEARNED, net, 5, 1, rt.INNER_FCG),
+             "mixed_rb": (rt.MODE_MIXED, None, 0, 1, rt.INNER_FCG)}
     for seed in eval_seeds:
         wl = wl0 if seed == eval_seeds[0] else sy.make_workload("c4-eval", 256, 128, 256, 64, 100.0, seed)
         En, _ = prepared_system(ctx, torch, sy, wl)
         row = {"seed": seed}
-        for name, (m, nt, budget, red) in modes.items():
+        for name, (m, nt, budget, red, inner) in modes.items():
             E = En.clone()
-            o = rt.solve_opts(m, tol=1e-8, max_iter=200000, net=nt, inner_max_iter=budget, reduce=red)
+            # plain restarted GMRES on an SPD system can take many times CG's iterations
+            o = rt.solve_opts(m, tol=1e-8, max_iter=20000 if m == rt.MODE_GMRES else 200000, net=nt,
+                              inner_max_iter=budget, reduce=red, restart=30, inner=inner)
             torch.cuda.synchronize()
             t = time.perf_counter()
             rc, st = ctx.solve(E, o, raise_on_error=False)
@@ -512,7 +520,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="clumpy-512x256x512-nu64")
-    ap.add_argument("--modes", default="mixed-rb,fp64,mixed,fp64-rb,learned,learned-rb",
+    ap.add_argument("--modes", default="mixed-rb,fp64,mixed,fp64-rb,learned,learned-rb,learned-fgmres-rb",
                     help="comma list; the first is the headline (suffix -rb: red-black reduced system)")
     ap.add_argument("--net", default="", help="load the network from this file instead of training it")
     ap.add_argument("--save-net", default="", help="save the trained network to this file")
