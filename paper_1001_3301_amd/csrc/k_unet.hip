@@ -784,8 +784,11 @@ __global__ __launch_bounds__(kDecTB) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         static_for<0, NL>([&](auto uc) __attribute__((always_inline)) {
             constexpr int u = decltype(uc)::value;
             const int q = tid + u * kDecTB;
+            const int cell = q >> 1, hr = cell % G::HR, hj = cell / G::HR;
+            const int pos = (hr & 1) ? G::HR / 2 + (hr >> 1) : (hr >> 1);  // even cells first
             if (q < G::HR * G::HJ * 2)
-                *reinterpret_cast<u32x4 *>(pl + q * 16) = ((okm >> u) & 1u) ? vv[u] : u32x4{0u, 0u, 0u, 0u};
+                *reinterpret_cast<u32x4 *>(pl + ((hj * G::HR + pos) * 2 + (q & 1)) * 16) =
+                    ((okm >> u) & 1u) ? vv[u] : u32x4{0u, 0u, 0u, 0u};
         });
     };
     // coarse plane c (wrapped): 18 x 10 cells x 64 bytes, four 16-byte pieces a cell
@@ -834,17 +837,17 @@ __global__ __launch_bounds__(kDecTB) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         put_c(1, vc, okm);
     }
     const float4 bb = bias ? *reinterpret_cast<const float4 *>(bias + 4 * (lane >> 4)) : make_float4(0.f, 0.f, 0.f, 0.f);
-    // fragment bases.  Skip (fine ring, conv_slide's layout): segment q of this wavefront is
-    // (rh = q & 1, theta row 2 wv + q / 2).  Up (coarse ring): lane l reads 8 channels
-    // (slice l / 32, half (l / 16) % 2) of the coarse parent of its cell's neighbour; the
-    // parent's r offset depends on the cell's parity (a per-lane base for each di), its
-    // theta offset on the segment's row and dj (compile-time).
+    // Fragment bases.  Segment q of this wavefront is the cells of parity s = q & 1 of the
+    // 32-cell radial row of theta row 2 wv + q / 2: lane l holds cell 2 (l % 16) + s.  So
+    // the 16 lanes of a fragment read 16 distinct coarse parents for every di (with lane =
+    // cell, pairs of lanes would read the same parent, which the LDS serves as a conflict),
+    // and in the fine ring, whose rows hold the even halo cells before the odd ones, 16
+    // consecutive cells: the offset of a tap is k + C(s, di) with k = l % 16, compile-time.
     constexpr int PW = 4;
-    const int e = lane & 15;
-    const int xl = (2 * wv * G::HR + e) * 32 + ((lane >> 4) & 1) * 16;
+    const int k16 = lane & 15;
+    const int xl = (2 * wv * G::HR + k16) * 32 + ((lane >> 4) & 1) * 16;
     const int wbs = ((lane >> 5) * 32 + (lane & 31)) * 16;
-    const int cl = (lane >> 5) * G::cslice_bytes + ((lane >> 4) & 1) * 16 + (wv + 1) * G::CR * 32;
-    const int ub[3] = {cl + (((e - 1) >> 1) + 1) * 32, cl + ((e >> 1) + 1) * 32, cl + (((e + 1) >> 1) + 1) * 32};
+    const int cl = (lane >> 5) * G::cslice_bytes + ((lane >> 4) & 1) * 16 + ((wv + 1) * G::CR + k16 + 1) * 32;
     u32x4 v[NL], vc[NC];
     unsigned okm = 0u, okc = 0u;
     __syncthreads();
@@ -861,30 +864,36 @@ __global__ __launch_bounds__(kDecTB) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         float4v acc[PW];
 #pragma unroll
         for (int q = 0; q < PW; q++) acc[q] = float4v{0.f, 0.f, 0.f, 0.f};
+        // halo position of the fine neighbour of cell 2 k + s through di, minus k
+        auto cpos = [](int s, int di) constexpr { return s == 0 ? (di == 0 ? G::HR / 2 : (di > 0 ? 1 : 0))
+                                                                 : (di == 0 ? 1 : G::HR / 2 + (di > 0 ? 1 : 0)); };
         // group g < 27: up tap g; g >= 27: skip tap pair g - 27
         auto frags = [&](auto gc, bf16x8 (&bf)[PW], bf16x8 &af) __attribute__((always_inline)) {
             constexpr int g = decltype(gc)::value;
             if constexpr (g < 27) {
                 constexpr int di = g % 3 - 1, dj = (g / 3) % 3 - 1, dk = g / 9;
-                const int cs = dk == 0 ? cs0 : (dk == 1 ? cs1 : cs2);
-                const char *xp = cring + cs + ub[di + 1];
-#pragma unroll
-                for (int q = 0; q < PW; q++) {
-                    const int off = ((q & 1) * 8 + ((((q >> 1) + dj) >> 1)) * G::CR) * 32;
+                const char *xp = cring + (dk == 0 ? cs0 : (dk == 1 ? cs1 : cs2)) + cl;
+                static_for<0, PW>([&](auto qc) __attribute__((always_inline)) {
+                    constexpr int q = decltype(qc)::value, sp = q & 1;
+                    // the coarse parent of fine cell 2 k + sp + di is k + (sp + di) >> 1
+                    constexpr int off = ((((q >> 1) + dj) >> 1) * G::CR + ((sp + di) >> 1)) * 32;
                     bf[q] = *reinterpret_cast<const bf16x8 *>(xp + off);
-                }
+                });
                 af = *reinterpret_cast<const bf16x8 *>(wup + (g * 64 + lane) * 16);
             } else {
                 constexpr int p = g - 27;
                 constexpr int ta = 2 * p, tb = (2 * p + 1 < 27) ? 2 * p + 1 : 13;
-                constexpr int oa = (((ta / 3) % 3) * G::HR + ta % 3) * 32;
-                constexpr int ob = (((tb / 3) % 3) * G::HR + tb % 3) * 32;
-                const int sa = ta / 9 == 0 ? sb0 : (ta / 9 == 1 ? sb1 : sb2);
-                const int sbb = tb / 9 == 0 ? sb0 : (tb / 9 == 1 ? sb1 : sb2);
-                const char *xp = lds + xl + ((lane < 32) ? sa + oa : sbb + ob);
-#pragma unroll
-                for (int q = 0; q < PW; q++)
-                    bf[q] = *reinterpret_cast<const bf16x8 *>(xp + ((q >> 1) * G::HR + (q & 1) * 16) * 32);
+                constexpr int dia = ta % 3 - 1, dib = tb % 3 - 1;
+                constexpr int ra = ((ta / 3) % 3) * G::HR * 32, rb = ((tb / 3) % 3) * G::HR * 32;
+                const int sa = (ta / 9 == 0 ? sb0 : (ta / 9 == 1 ? sb1 : sb2)) + ra;
+                const int sbb = (tb / 9 == 0 ? sb0 : (tb / 9 == 1 ? sb1 : sb2)) + rb;
+                // the two parities' bases (the tap pair's halves differ in di)
+                const char *x0 = lds + xl + ((lane < 32) ? sa + cpos(0, dia) * 32 : sbb + cpos(0, dib) * 32);
+                const char *x1 = lds + xl + ((lane < 32) ? sa + cpos(1, dia) * 32 : sbb + cpos(1, dib) * 32);
+                static_for<0, PW>([&](auto qc) __attribute__((always_inline)) {
+                    constexpr int q = decltype(qc)::value;
+                    bf[q] = *reinterpret_cast<const bf16x8 *>(((q & 1) ? x1 : x0) + (q >> 1) * G::HR * 32);
+                });
                 af = *reinterpret_cast<const bf16x8 *>(wsk + wbs + 2 * p * 32 * 16);
             }
         };
@@ -914,7 +923,7 @@ __global__ __launch_bounds__(kDecTB) __attribute__((amdgpu_waves_per_eu(3, 8))) 
         if (cmore) put_c(((k >> 1) + 1 - c0) & 1, vc, okc);
 #pragma unroll
         for (int q = 0; q < PW; q++) {
-            const int a = r0 + (q & 1) * 16 + e, b = j0 + 2 * wv + (q >> 1);
+            const int a = r0 + 2 * k16 + (q & 1), b = j0 + 2 * wv + (q >> 1);
             if (a < L.nr && b < L.nt) {
                 const size_t idx = (size_t)(a + L.nr * (b + L.nt * k));
                 const int co = 4 * (lane >> 4);
