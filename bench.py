@@ -65,9 +65,11 @@ MEASURED_TRAFFIC = {("k_cg_dir<float>", "clumpy-512x256x512-nu64"): 1.924e9,
 # profiles/raytrace_counters_clumpy-512x256x512-nu64.md), and the chip issues at most one
 # float64 wave-instruction per CU per cycle (4 SIMDs, 4 cycles per wave64 instruction):
 # 256 CUs x 2.4 GHz.  The algorithm itself needs ~35 float64 operations per cell and bin.
+# 31.0 is the count where the wavefront's cells all lie below dust sublimation (kappa_nu
+# from one table row per bin), as in the benchmark step; 32.9 with the interpolation.
 # (Columns that do not fill their 512-cell segments to 90 % take lanes on bins,
 # k_raytrace<false, false>, 31.3 instructions per cell and bin.)
-RAYTRACE_KERNELS = {True: ("k_raytrace_r", 32.9), False: ("k_raytrace<false, false>", 31.3)}
+RAYTRACE_KERNELS = {True: ("k_raytrace_r", 31.0), False: ("k_raytrace<false, false>", 31.3)}
 RAYTRACE_ALG_INSTS_PER_CELL = 35.0
 
 

@@ -20,6 +20,8 @@
 // The opacity table is in LDS bin-major, [bin][T node], so a cell's two interpolation
 // nodes are one ds_read2 apart, and the neighbouring cells of a column (nearby
 // temperatures) read the same or nearby words.
+#include <type_traits>
+
 #include "rt_internal.h"
 
 namespace rt {
@@ -58,7 +60,7 @@ __device__ __forceinline__ double exclusive_scan_mul(double v)
 }
 
 __global__ __launch_bounds__(64 * kRWaves) void k_raytrace_r(
-    int nr, long ncol, int nnu, int nT,
+    int nr, long ncol, int nnu, int nT, int kconst,
     const double *__restrict__ rho, const double *__restrict__ T,
     const double *__restrict__ Ttab, const double *__restrict__ kap_g,
     const double *__restrict__ F0, double R2,
@@ -84,8 +86,11 @@ __global__ __launch_bounds__(64 * kRWaves) void k_raytrace_r(
 
     for (int seg0 = 0; seg0 < nr; seg0 += kRSeg) {
         const int i0 = seg0 + kRCells * lane;  // this lane's first cell
+        // per cell: table node k and weight w, rho dr (floored); vr / wr hold rho dr and w
+        // until the wavefront knows whether all its cells lie in the T-independent rows
         int kofs[kRCells];
         double vr[kRCells], wr[kRCells], acc[kRCells];
+        bool cold = true;  // every node this lane's cells use is a T-independent row
 #pragma unroll
         for (int s = 0; s < kRCells; s++) {
             acc[s] = 0.0;
@@ -95,37 +100,55 @@ __global__ __launch_bounds__(64 * kRWaves) void k_raytrace_r(
                 int k;
                 double w;
                 lin_node(Tt, nT, t, k, w);
-                const double rdr = v > 1e-250 ? v : 1e-250;
                 kofs[s] = k;
-                vr[s] = (1.0 - w) * rdr;
-                wr[s] = w * rdr;
+                vr[s] = v > 1e-250 ? v : 1e-250;
+                wr[s] = w;
+                cold = cold && k + 1 < kconst;
             } else {  // beyond the column: transmission 1, nothing absorbed
                 kofs[s] = 0;
                 vr[s] = wr[s] = 0.0;
             }
         }
-        const bool last = seg0 + kRSeg >= nr;
-        for (int b = 0; b < nnu; b++) {
-            const double *tb = tab + b * nT;
-            double P = 1.0, a[kRCells];
+        // Below sublimation kappa_nu does not depend on T: where the whole wavefront's
+        // cells use only such rows, dtau = kappa_nu (row 0) x rho dr, one uniform table
+        // value per bin; otherwise the interpolation weights (1 - w) rho dr, w rho dr.
+        const bool fast = __all(cold);
+        if (!fast) {
 #pragma unroll
             for (int s = 0; s < kRCells; s++) {
-                const double dtau = fma(wr[s], tb[kofs[s] + 1], vr[s] * tb[kofs[s]]);
-                double e, m;
-                exp_pair(dtau, e, m);
-                a[s] = P * m;  // absorbed fraction of the flux entering this lane's cells
-                P = P * e;
-            }
-            const double X = exclusive_scan_mul(P);
-            const double C = readlane_d(carry, b);
-            const double G = C * X;  // flux of bin b entering this lane's first cell
-#pragma unroll
-            for (int s = 0; s < kRCells; s++) acc[s] = fma(G, a[s], acc[s]);
-            if (!last) {  // the bin's flux at the next segment's inner face, into lane b
-                const double through = readlane_d(X * P, 63);
-                if (lane == b) carry = C * through;
+                const double rdr = vr[s], w = wr[s];
+                vr[s] = (1.0 - w) * rdr;
+                wr[s] = w * rdr;
             }
         }
+        const bool last = seg0 + kRSeg >= nr;
+        auto bins = [&](auto fc) __attribute__((always_inline)) {
+            constexpr bool kFast = decltype(fc)::value;
+            for (int b = 0; b < nnu; b++) {
+                const double *tb = tab + b * nT;
+                const double kb = kFast ? tb[0] : 0.0;
+                double P = 1.0, a[kRCells];
+#pragma unroll
+                for (int s = 0; s < kRCells; s++) {
+                    const double dtau = kFast ? kb * vr[s] : fma(wr[s], tb[kofs[s] + 1], vr[s] * tb[kofs[s]]);
+                    double e, m;
+                    exp_pair(dtau, e, m);
+                    a[s] = P * m;  // absorbed fraction of the flux entering this lane's cells
+                    P = P * e;
+                }
+                const double X = exclusive_scan_mul(P);
+                const double C = readlane_d(carry, b);
+                const double G = C * X;  // flux of bin b entering this lane's first cell
+#pragma unroll
+                for (int s = 0; s < kRCells; s++) acc[s] = fma(G, a[s], acc[s]);
+                if (!last) {  // the bin's flux at the next segment's inner face, into lane b
+                    const double through = readlane_d(X * P, 63);
+                    if (lane == b) carry = C * through;
+                }
+            }
+        };
+        if (fast) bins(std::true_type{});
+        else bins(std::false_type{});
 #pragma unroll
         for (int s = 0; s < kRCells; s++) {
             const int i = i0 + s;
@@ -159,7 +182,7 @@ void launch_raytrace_r(const Dims &d, const Opac &op, const Geo &g, const double
     const long ncol = (long)d.nt * d.np;
     const long nblk = (ncol + kRWaves - 1) / kRWaves;
     hipLaunchKernelGGL(k_raytrace_r, dim3((unsigned)nblk), dim3(64 * kRWaves), raytrace_r_lds_bytes(op.nT, op.nnu), st,
-                       d.nr, ncol, op.nnu, op.nT, rho, T, op.T, op.kap, F0, R2, g.dr, g.shell, q, S);
+                       d.nr, ncol, op.nnu, op.nT, op.kconst, rho, T, op.T, op.kap, F0, R2, g.dr, g.shell, q, S);
 }
 
 }  // namespace rt

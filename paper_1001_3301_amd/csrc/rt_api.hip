@@ -293,6 +293,7 @@ rt_status rt_create(rt_ctx **out, const rt_grid *g, int n_nu, void *stream)
     O.lnP = O.lnT + kMaxT;
     O.lnR = O.lnP + kMaxT;
     O.nnu = n_nu;
+    O.kconst = 1;
 
     // fields, system, Krylov vectors
     size_t N = (size_t)n;
@@ -412,6 +413,12 @@ rt_status rt_set_opacity(rt_ctx *ctx, const rt_opacity *op)
     RT_HIP(ctx, hipMemcpy((void *)O.lnP, lnP.data(), nT * sizeof(double), hipMemcpyHostToDevice));
     RT_HIP(ctx, hipMemcpy((void *)O.lnR, lnR.data(), nT * sizeof(double), hipMemcpyHostToDevice));
     O.nT = nT;
+    // the leading temperature rows whose kappa_nu equal row 0's bit for bit (below dust
+    // sublimation kappa_nu does not depend on T): where every node a column's cells use
+    // lies in them, the ray trace takes kappa_nu from row 0
+    int kc = 1;
+    while (kc < nT && std::equal(op->kappa + (size_t)kc * nnu, op->kappa + (size_t)(kc + 1) * nnu, op->kappa)) kc++;
+    O.kconst = kc;
     ctx->nT = nT;
     ctx->h_opac.swap(pack);
     ctx->have_opac = true;

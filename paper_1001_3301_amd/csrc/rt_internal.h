@@ -53,6 +53,7 @@ struct Geo {
 // Opacity table on the device.
 struct Opac {
     int nT, nnu;
+    int kconst;          // rows 0 .. kconst-1 of kap are identical (kappa_nu independent of T there)
     const double *T;     // [nT]
     const double *kap;   // [nT][nnu]
     const double *kP;    // [nT] Planck means

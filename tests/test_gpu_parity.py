@@ -106,6 +106,31 @@ def test_raytrace_lanes_cells_parity(case):
     assert rel(_h(q), _h(qv)) < 1e-12
 
 
+@pytest.mark.parametrize("mix", ["cold", "hot-and-cold-columns"])
+def test_raytrace_below_sublimation_parity(mix):
+    """Lanes on cells where every node a wavefront's cells use is a row of the table below
+    dust sublimation (kappa_nu independent of T): dtau = kappa_nu (row 0) rho dr, one
+    table value per bin.  All columns below 1000 K, or every other theta row of columns
+    heated up to 2500 K (8 columns a block, so blocks hold both kinds of wavefront),
+    against the oracle at 1e-11, and against lanes on bins."""
+    from paper_1001_3301_amd import rt
+    wl = sy.make_workload("cold", 512, 6, 4, 64, 100.0, clump_seed=11)
+    P = oracle.Problem.from_workload(wl)
+    ctx = _ctx(wl)
+    T = seeded_temperature(P.n, 17, 10.0, 1000.0).reshape(4, 6, 512)
+    if mix != "cold":
+        T[:, 1::2, :] = seeded_temperature(T[:, 1::2, :].size, 18, 10.0, 2500.0).reshape(4, 3, 512)
+    T = T.ravel()
+    q0, S0, _ = P.raytrace(wl.rho, T, want_faces=False)
+    q, S, qv, Sv = (torch.empty(P.n, dtype=torch.float64, device="cuda") for _ in range(4))
+    ctx.raytrace_mapped(rt.LANES_CELLS, _d(wl.rho), _d(T), q, S)
+    ctx.raytrace_mapped(rt.LANES_BINS, _d(wl.rho), _d(T), qv, Sv)
+    torch.cuda.synchronize()
+    assert rel(_h(q), q0) < 1e-11
+    assert rel(_h(S), S0) < 1e-11
+    assert rel(_h(q), _h(qv)) < 1e-12
+
+
 @pytest.mark.parametrize("nr,cells", [(512, True), (1024, True), (470, True), (400, False), (600, False)])
 def test_raytrace_picks_the_mapping_by_column_length(nr, cells):
     """rt_raytrace without face fluxes takes lanes on cells where the column fills its
