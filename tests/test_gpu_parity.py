@@ -327,6 +327,24 @@ def test_error_paths():
     with pytest.raises(rt.RtError) as ei:
         ctx.solve(E, rt.solve_opts(rt.MODE_FP64, tol=2.0))
     assert ei.value.status == rt.RT_EINVAL
+    # an unknown inner method, an unknown ray-trace mapping, NULL fields of the mapped
+    # ray trace: RT_EINVAL, nothing launched
+    net = rt.Net(seed=1)
+    with pytest.raises(rt.RtError) as ei:
+        ctx.solve(E, rt.solve_opts(rt.MODE_LEARNED, tol=1e-8, net=net, inner=7))
+    assert ei.value.status == rt.RT_EINVAL
+    q = torch.empty(P.n, dtype=torch.float64, device="cuda")
+    for mapping in (-1, 2):
+        with pytest.raises(rt.RtError) as ei:
+            ctx.raytrace_mapped(mapping, _d(wl.rho), _d(T0), q, E)
+        assert ei.value.status == rt.RT_EINVAL
+    L = rt.lib()
+    assert L.rt_raytrace_mapped(ctx.h, rt.LANES_CELLS, None, None, None, None) == rt.RT_EINVAL
+    # the pooled convolution needs even dimensions and all its buffers
+    assert L.rt_nn_conv3d_fwd_pool(None, 9, 4, 4, None, None, None, None, None) == rt.RT_EINVAL
+    x = torch.zeros(8 * 4 * 4 * 16, dtype=torch.bfloat16, device="cuda")
+    assert L.rt_nn_conv3d_fwd_pool(None, 9, 4, 4, x.data_ptr(), x.data_ptr(), x.data_ptr(), x.data_ptr(),
+                                   x.data_ptr()) == rt.RT_EINVAL
 
 
 @pytest.mark.parametrize("case,m,tol", [("axisym-64x16x1-nu32", 10, 1e-14), ("ragged-67x13x5-nu61", 30, 1e-12)])
