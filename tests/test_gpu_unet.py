@@ -483,6 +483,44 @@ def test_learned_reduced_finish_recovers_from_a_network_that_overflows_on_its_se
     assert float(((Tl - Tf).abs() / Tf).max()) < 1e-5
 
 
+def test_fgmres_reduced_finish_recovers_from_a_network_that_overflows_on_its_second_application():
+    """Flexible GMRES with a network that is finite on the first Arnoldi vector and
+    overflows on the second: the cycle ends before its update reaches y, the reduced
+    finish starts from the previous iterate and meets the tolerance, and `fallback`
+    reports the failed network.  The threshold lies between the largest entries of the
+    two unit-RMS basis vectors, computed on the host from the GPU's assembled system
+    (v_1 is A z_0 made orthogonal to v_0, z_0 proportional to relu(v_0)).  The system is
+    one where the largest entry of v_1 exceeds that of v_0 (by a factor of about 1.9; on
+    the 16 x 8 x 8 systems it is the other way round)."""
+    from paper_1001_3301_amd import rt
+    wl, ctx, rho, T, En, S, sysv = _small_problem_sys(shape=(32, 8, 8), tau=10.0, seed=7)
+    st = ctx.system_tensors(sysv)
+    bh, s = st["bhat"].cpu().numpy(), st["s"].cpu().numpy()
+
+    def spmv(x):
+        y = torch.empty(ctx.n, dtype=torch.float64, device="cuda")
+        ctx.spmv(torch.tensor(x, device="cuda"), y)
+        return y.cpu().numpy()
+
+    n = ctx.n
+    r0 = bh - spmv(En.cpu().numpy() / s)
+    v0 = r0 / np.linalg.norm(r0)
+    w = spmv(np.maximum(v0, 0.0))
+    v1 = w - (w @ v0) * v0
+    v1 /= np.linalg.norm(v1)
+    M0, M1 = np.max(v0) * np.sqrt(n), np.max(v1) * np.sqrt(n)
+    assert M1 > 1.15 * M0, (M0, M1)  # room for the bf16 rounding of the input and the gain
+    net = rt.Net(seed=1)
+    net.set_params(_identity_path_params(3.39e38 / np.sqrt(M0 * M1), 1e-36))
+    E = En.clone()
+    rc, sl = ctx.solve(E, rt.solve_opts(rt.MODE_LEARNED, tol=1e-8, net=net, inner_max_iter=10, reduce=1,
+                                        inner=rt.INNER_FGMRES), raise_on_error=False)
+    assert sl["precond_applies"] == 2, sl  # the first application was finite
+    assert rc == rt.RT_OK and sl["fallback"] == 1 and sl["handover"] == 0 and sl["reduced"] == 1, sl
+    assert sl["relres"] <= 1e-8
+    assert np.all(np.isfinite(E.cpu().numpy()))
+
+
 def test_residual_loss_gradient_against_oracle():
     """rt_net_loss_grad_resid (forward, A z with the fp32 operator, loss, A^T, backward)
     against the oracle's residual-loss gradient on the same bf16 weights and operator."""
