@@ -98,14 +98,17 @@ _launch = 0
 
 def mode_opts(rt, mode, tol, max_iter, inner_tol, net=None, budget=0, restart=30):
     """Solve options of a bench mode; the suffix -rb solves the red-black reduced system,
-    -line preconditions float64 CG with the radial-line block Jacobi; learned-fgmres runs
-    the network inside flexible GMRES(m) instead of flexible CG."""
+    -line preconditions float64 CG with the radial-line block Jacobi, -mg with one
+    multigrid V-cycle per iteration; learned-fgmres runs the network inside flexible
+    GMRES(m) instead of flexible CG."""
     parts = mode.split("-")
     base = parts[0]
     m = {"fp64": rt.MODE_FP64, "mixed": rt.MODE_MIXED, "learned": rt.MODE_LEARNED, "gmres": rt.MODE_GMRES}[base]
-    return rt.solve_opts(m, tol=tol, max_iter=max_iter, check_every=32, inner_tol=inner_tol,
+    every = 8 if mode.endswith("-mg") else 32  # a multigrid iteration is several passes
+    return rt.solve_opts(m, tol=tol, max_iter=max_iter, check_every=every, inner_tol=inner_tol,
                          inner_max_iter=budget if base == "learned" else 0, net=net if base == "learned" else None,
-                         restart=restart, reduce=int(mode.endswith("-rb")), precond=int(mode.endswith("-line")),
+                         restart=restart, reduce=int(mode.endswith("-rb")),
+                         precond=1 if mode.endswith("-line") else (2 if mode.endswith("-mg") else 0),
                          launch=_launch, inner=rt.INNER_FGMRES if "fgmres" in parts else rt.INNER_FCG)
 
 

@@ -128,7 +128,9 @@ typedef struct {
                             default), 1 = CG preconditioned by the radial-line block Jacobi:
                             each radial row's tridiagonal block of A^ solved exactly (the
                             block-Jacobi class of the paper's solver set-up, Sect. "Numerical
-                            setup", as a comparator) */
+                            setup", as a comparator), 2 = CG preconditioned by one multigrid
+                            V-cycle per iteration (an extension, not in the paper: see
+                            rt_mg_apply; check_every defaults to 8 here) */
     int launch;          /* rt_launch: how the CG iterations of RT_SOLVE_FP64 / RT_SOLVE_MIXED
                             (reduced or not) reach the GPU; every choice computes the same
                             method, DIRECT and GRAPH bit for bit alike */
@@ -177,8 +179,9 @@ typedef struct {
     int reduced;         /* 1 if the red-black reduced system was solved (iters count its
                             iterations; ms_dir then covers its red and black passes) */
     double ms_black;     /* reduced solves: mean device time of the black pass alone (ms_dir -
-                            ms_black is the red pass); precond = 1: the direction kernel
-                            alone (ms_dir - ms_black is the block solve) */
+                            ms_black is the red pass); precond = 1 or 2: the direction
+                            kernel alone (ms_dir - ms_black is the block solve or the
+                            V-cycle) */
     int handover;        /* learned solves: 1 if the network budget (inner_max_iter
                             applications) ran out above tol and the planned finish (float64
                             CG, or the reduced mixed solve with reduce = 1) completed it */
@@ -321,6 +324,36 @@ rt_status rt_gray_table(const rt_opacity *op, const double *F_nu, double *kappa_
  * (precond = 1): per radial row, the tridiagonal block of A^ (unit diagonal, the radial
  * off-diagonals) solved exactly.  Device arrays of n; r and z must not overlap. */
 rt_status rt_precond_apply(rt_ctx *ctx, const double *r, double *z);
+
+/* The multigrid preconditioner of precond = 2 (an extension of the implicit solve of
+ * Eq. 15, not in the paper): z = M_mg r, one V-cycle for the current system.  Levels:
+ * A_0 = A^; A_(l+1) = P_l^T A_l P_l over aggregates of 1 x 2 x 2 cells (theta and phi
+ * pairs merged, the radius kept; a lone last row where a size is odd), with P_l[f, C] =
+ * B_f / Bc_C, B_0 = 1/s and Bc_C^2 the sum of B_f^2 over the aggregate; the last level
+ * is one radial line, solved exactly.  Smoother: x <- x + 0.8 M^-1 (b - A x), M the
+ * diagonal and phi couplings of each (r, theta) line (periodic).  Cycle: pre-smoothing
+ * from 0, restriction of the residual by P^T, the coarser cycle, prolongation by P,
+ * post-smoothing; float32 inside, set-up in float64 once per assembled system.  Device
+ * arrays of n; r and z must not overlap.  The hierarchy is allocated at the first use
+ * (about 90 bytes per cell). */
+rt_status rt_mg_apply(rt_ctx *ctx, const double *r, double *z);
+
+/* Device view of level `level` (0 = finest) of the current system's multigrid hierarchy
+ * (set up if needed): its sizes and float32 arrays in the field layout (r fastest, then
+ * theta, then phi) of that level.  dg is NULL on level 0 (unit diagonal), where ar / at /
+ * ap are A^'s float32 couplings; w (prolongation weights to the next level), the phi-line
+ * factors im, cp, q, g (per cell) and rho, kap (per (r, theta) line) are NULL on the last
+ * level.  Valid until the next assembly or rt_destroy. */
+typedef struct {
+    int levels;  /* number of levels */
+    int nr, nt, np;
+    long n;
+    const float *dg, *ar, *at, *ap;
+    const float *w;
+    const float *im, *cp, *q, *g;
+    const float *rho, *kap;
+} rt_mg_level_view;
+rt_status rt_mg_level(rt_ctx *ctx, int level, rt_mg_level_view *out);
 
 /* Diagnostic of Sect. "The Flux Limited Diffusion approximation" (Fig. 8): the optical
  * depth of the thermal emission integrated inward from the outer edge along each radial

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "rtmi")
 LIB = os.path.join(HERE, "librtmi.so")
 
-SOURCES = ["rt_api.hip", "k_raytrace.hip", "k_raytrace_r.hip", "k_fld.hip", "k_krylov.hip", "k_unet.hip", "rt_net.hip"]
+SOURCES = ["rt_api.hip", "k_raytrace.hip", "k_raytrace_r.hip", "k_fld.hip", "k_krylov.hip", "k_mg.hip", "k_unet.hip",
+           "rt_net.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("RTMI_ARCH", "gfx950")

@@ -1421,19 +1421,15 @@ void launch_line_solve(const Dims &d, int nblk, const double *a, const double *c
                        restart);
 }
 
-// One preconditioned CG iteration: z = M^-1 r (and beta), p = z + beta p_old, q = A^ p,
-// alpha; y, r update and r.r.
-void launch_pcg_line_iter(const Dims &d, int nblk, int nblk_upd, const double *a, const double *lc, const double *lim,
-                          double *y, double *r, double *z, double *pold, double *pnew, double *q, double *partials,
-                          unsigned *counter, DevScalars *sc, int restart, hipStream_t st, const hipEvent_t *ev)
+// The rest of a preconditioned CG iteration once z = M^-1 r and beta are known:
+// p = z + beta p_old, q = A^ p, alpha; y, r update and r.r.
+void launch_pcg_dir_upd(const Dims &d, int nblk, int nblk_upd, const double *a, const double *z, double *y, double *r,
+                        double *pold, double *pnew, double *q, double *partials, unsigned *counter, DevScalars *sc,
+                        hipStream_t st, const hipEvent_t *ev)
 {
     const int vw = pick_vw<double>(d);
-    if (ev) (void)hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(k_line_solve, dim3(nblk), dim3(kKB), 0, st, d, nblk, a, lc, lim, r, z, partials, counter, sc,
-                       restart);
-    if (ev) (void)hipEventRecord(ev[3], st);
-    RT_DISPATCH_VW(double, vw, k_cg_dir, dim3(nblk), dim3(kKB), 0, st, d, nblk, a, (const double *)z, pold, pnew, q,
-                   partials, counter, sc);
+    RT_DISPATCH_VW(double, vw, k_cg_dir, dim3(nblk), dim3(kKB), 0, st, d, nblk, a, z, pold, pnew, q, partials,
+                   counter, sc);
     if (ev) (void)hipEventRecord(ev[1], st);
     switch (vw) {
     case 8: hipLaunchKernelGGL(k_pcg_upd<8>, dim3(nblk_upd), dim3(kKB), 0, st, d, nblk_upd, y, pnew, r, q, partials,
@@ -1446,6 +1442,19 @@ void launch_pcg_line_iter(const Dims &d, int nblk, int nblk_upd, const double *a
                                 counter, sc); break;
     }
     if (ev) (void)hipEventRecord(ev[2], st);
+}
+
+// One preconditioned CG iteration: z = M^-1 r (and beta), p = z + beta p_old, q = A^ p,
+// alpha; y, r update and r.r.
+void launch_pcg_line_iter(const Dims &d, int nblk, int nblk_upd, const double *a, const double *lc, const double *lim,
+                          double *y, double *r, double *z, double *pold, double *pnew, double *q, double *partials,
+                          unsigned *counter, DevScalars *sc, int restart, hipStream_t st, const hipEvent_t *ev)
+{
+    if (ev) (void)hipEventRecord(ev[0], st);
+    hipLaunchKernelGGL(k_line_solve, dim3(nblk), dim3(kKB), 0, st, d, nblk, a, lc, lim, r, z, partials, counter, sc,
+                       restart);
+    if (ev) (void)hipEventRecord(ev[3], st);
+    launch_pcg_dir_upd(d, nblk, nblk_upd, a, z, y, r, pold, pnew, q, partials, counter, sc, st, ev);
 }
 
 // ---------------------------------------------------------------- GMRES(m)

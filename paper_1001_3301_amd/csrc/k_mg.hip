@@ -1,0 +1,624 @@
+// Multigrid preconditioner for CG on the Jacobi-scaled FLD operator A^ (the implicit
+// solve of Eq. 15).  Not part of the paper, which preconditions its Krylov solve by
+// block Jacobi: a V-cycle whose cost per CG iteration is a few sweeps over the grid
+// and whose iteration count grows slowly with the grid, where Jacobi CG's grows with
+// the number of cells along a line.
+//
+// Levels.  A_0 = A^ (unit diagonal; couplings ar / at / ap to the +r / +theta / +phi
+// neighbour, periodic in phi).  A_(l+1) = P_l^T A_l P_l with aggregates of 1 x 2 x 2
+// cells: the radius is never coarsened, because on heated, optically thin grids the
+// radial couplings of A^ become weak next to the angular ones and merging radial cells
+// then leaves a coarse space that misses the error; a lone last row where a size is
+// odd.  P_l[f, C] = B_f / Bc_C with B_0 = 1/s (the Jacobi scaling moves the unscaled
+// operator's near-null vector, the constants, to 1/s) and Bc_C^2 the sum of B_f^2 over
+// the aggregate, so each coarse level is again a 7-point operator, with a general
+// diagonal.  Coarsening stops at one radial line, whose inverse is stored densely.
+//
+// Smoother.  Damped block Jacobi on phi lines: M is the diagonal and phi couplings of
+// each (r, theta) line, x <- x + omega M^-1 (b - A x).  Near the poles the phi coupling
+// carries almost all of a row's weight, and a point smoother would leave the error that
+// is smooth along phi and rough across theta, which the coarse levels cannot represent
+// either.  Each periodic line matrix is M = T + u v^T (Sherman-Morrison, gamma = -M_00):
+// T tridiagonal, factored once per system; q = T^-1 u and g = T^-1 e_0 stored per line,
+// so that y_0 = g . rhs is summed during the forward sweep and the correction
+// y - (v.y / (1 + v.q)) q is applied during the backward sweep (two passes per sweep).
+//
+// Work layout: one thread per (r, theta) line walking phi, lanes on consecutive radii,
+// so every access of a step is one coalesced row segment.  The set-up runs in float64;
+// the V-cycle stores and computes in float32 (the outer CG keeps float64 vectors, dots
+// and the true residual).
+#include "rt_internal.h"
+
+namespace rt {
+
+constexpr int kMB = 256;  // threads per block of the multigrid kernels
+
+__device__ __forceinline__ long mg_cell(int nr, int nt, int i, int j, int k) { return i + (long)nr * (j + (long)nt * k); }
+
+// ----------------------------------------------------------------- set-up (float64)
+
+// 1 / s: the near-null vector of the finest level.
+__global__ __launch_bounds__(kMB) void k_mg_recip(long n, const double *__restrict__ s, double *__restrict__ B)
+{
+    const long c = (long)blockIdx.x * kMB + threadIdx.x;
+    if (c < n) B[c] = 1.0 / s[c];
+}
+
+struct MgSetLevel {
+    int nt, np;
+    const double *dg;  // nullptr: unit diagonal
+    const double *ar, *at, *ap, *B;
+};
+
+struct MgSetOut {
+    int nt, np;
+    double *dg, *ar, *at, *ap, *B;
+};
+
+__device__ __forceinline__ double mg_bc(int nr, const MgSetLevel &F, int i, int J, int K)
+{
+    const int ft = F.nt > 1 ? 2 : 1, fp = F.np > 1 ? 2 : 1;
+    double s = 0.0;
+    for (int k = fp * K; k < min(fp * K + fp, F.np); k++)
+        for (int j = ft * J; j < min(ft * J + ft, F.nt); j++) {
+            const double b = F.B[mg_cell(nr, F.nt, i, j, k)];
+            s += b * b;
+        }
+    return sqrt(s);
+}
+
+// One coarse cell per thread: its Galerkin row (diagonal and the three outward
+// couplings), its near-null entry, and the prolongation weights w_f = B_f / Bc of its
+// children.
+__global__ __launch_bounds__(kMB) void k_mg_coarsen(int nr, MgSetLevel F, MgSetOut C, float *__restrict__ w)
+{
+    const long nc = (long)nr * C.nt * C.np;
+    const long cc = (long)blockIdx.x * kMB + threadIdx.x;
+    if (cc >= nc) return;
+    const int i = (int)(cc % nr);
+    const long rest = cc / nr;
+    const int J = (int)(rest % C.nt), K = (int)(rest / C.nt);
+    const int ft = F.nt > 1 ? 2 : 1, fp = F.np > 1 ? 2 : 1;
+    const int j0 = ft * J, j1 = min(j0 + ft, F.nt), k0 = fp * K, k1 = min(k0 + fp, F.np);
+    const double bc = mg_bc(nr, F, i, J, K);
+    auto wf = [&](int j, int k) { return F.B[mg_cell(nr, F.nt, i, j, k)] / bc; };
+    double dg = 0.0;
+    for (int k = k0; k < k1; k++)
+        for (int j = j0; j < j1; j++) {
+            const long f = mg_cell(nr, F.nt, i, j, k);
+            const double wv = wf(j, k);
+            w[f] = (float)wv;
+            dg += (F.dg ? F.dg[f] : 1.0) * wv * wv;
+        }
+    // internal couplings, counted twice (a_fg and a_gf)
+    if (j1 - j0 == 2)
+        for (int k = k0; k < k1; k++) dg += 2.0 * F.at[mg_cell(nr, F.nt, i, j0, k)] * wf(j0, k) * wf(j0 + 1, k);
+    if (k1 - k0 == 2) {
+        for (int j = j0; j < j1; j++) dg += 2.0 * F.ap[mg_cell(nr, F.nt, i, j, k0)] * wf(j, k0) * wf(j, k0 + 1);
+        if (F.np == 2)  // the periodic coupling of two phi cells merged into one
+            for (int j = j0; j < j1; j++) dg += 2.0 * F.ap[mg_cell(nr, F.nt, i, j, 1)] * wf(j, 1) * wf(j, 0);
+    }
+    double ar = 0.0;
+    if (i + 1 < nr) {
+        const double bn = mg_bc(nr, F, i + 1, J, K);
+        for (int k = k0; k < k1; k++)
+            for (int j = j0; j < j1; j++) {
+                const long f = mg_cell(nr, F.nt, i, j, k);
+                ar += F.ar[f] * wf(j, k) * (F.B[f + 1] / bn);
+            }
+    }
+    double at = 0.0;
+    if (ft == 2 && j0 + 2 < F.nt) {  // from the last child row 2J+1 to row 2J+2
+        const double bn = mg_bc(nr, F, i, J + 1, K);
+        for (int k = k0; k < k1; k++) {
+            const long f = mg_cell(nr, F.nt, i, j0 + 1, k);
+            at += F.at[f] * wf(j0 + 1, k) * (F.B[f + nr] / bn);
+        }
+    }
+    double ap = 0.0;
+    if (fp == 2 && C.np >= 2) {  // from the last child plane towards the next aggregate
+        const int kl = k1 - 1, kn = (kl + 1) % F.np;
+        const double bn = mg_bc(nr, F, i, J, (K + 1) % C.np);
+        for (int j = j0; j < j1; j++)
+            ap += F.ap[mg_cell(nr, F.nt, i, j, kl)] * wf(j, kl) * (F.B[mg_cell(nr, F.nt, i, j, kn)] / bn);
+    }
+    C.dg[cc] = dg;
+    C.ar[cc] = ar;
+    C.at[cc] = at;
+    C.ap[cc] = ap;
+    C.B[cc] = bc;
+}
+
+struct MgLineOut {
+    float *im, *cp, *q, *g, *rho, *kap;
+};
+
+// Factors of each phi line's matrix M (one thread per (r, theta) line).  Lines of one
+// cell: 1 / M_00.  Two cells: the 2 x 2 matrix, whose off-diagonal is the sum of the
+// two couplings between them.  Three or more: T = M - u v^T with u = (gamma, 0, .., 0,
+// e_(m-1)), v = (1, 0, .., 0, e_(m-1) / gamma), gamma = -M_00, where e_(m-1) couples the
+// last cell to the first; Thomas factors 1 / m_k and c_k = e_k / m_k of T, and q = T^-1 u,
+// g = T^-1 e_0, rho = e_(m-1) / gamma, kap = 1 / (1 + q_0 + rho q_(m-1)).  tm and td are
+// float64 scratch of the level's size.
+__global__ __launch_bounds__(kMB) void k_mg_line_factor(int nr, MgSetLevel L, MgLineOut o, double *__restrict__ tm,
+                                                        double *__restrict__ td)
+{
+    const long lines = (long)nr * L.nt;
+    const long line = (long)blockIdx.x * kMB + threadIdx.x;
+    if (line >= lines) return;
+    const long plane = lines;
+    const int m = L.np;
+    auto dgv = [&](long c) { return L.dg ? L.dg[c] : 1.0; };
+    if (m == 1) {
+        o.im[line] = (float)(1.0 / dgv(line));
+        o.cp[line] = o.q[line] = o.g[line] = 0.0f;
+        o.rho[line] = o.kap[line] = 0.0f;
+        return;
+    }
+    if (m == 2) {
+        const long c1 = line + plane;
+        const double e = L.ap[line] + L.ap[c1];
+        const double m0 = dgv(line), m1 = dgv(c1) - e * e / m0;
+        o.im[line] = (float)(1.0 / m0);
+        o.im[c1] = (float)(1.0 / m1);
+        o.cp[line] = (float)(e / m0);
+        o.cp[c1] = 0.0f;
+        o.q[line] = o.q[c1] = o.g[line] = o.g[c1] = 0.0f;
+        o.rho[line] = o.kap[line] = 0.0f;
+        return;
+    }
+    const double d0 = dgv(line), gam = -d0;
+    const long cl = line + (long)(m - 1) * plane;
+    const double ew = L.ap[cl];  // couples the last cell to the first
+    // factor T: diagonal 2 d_0, d_k, d_(m-1) - ew^2 / gamma; off-diagonals e_k = ap_k
+    double mk = d0 - gam, eprev = 0.0;
+    for (int k = 0; k < m; k++) {
+        const long c = line + (long)k * plane;
+        if (k > 0) {
+            double t = dgv(c);
+            if (k == m - 1) t -= ew * ew / gam;
+            mk = t - eprev * eprev / mk;
+        }
+        tm[c] = 1.0 / mk;
+        o.im[c] = (float)(1.0 / mk);
+        const double e = (k < m - 1) ? L.ap[c] : 0.0;
+        o.cp[c] = (float)(e / mk);
+        eprev = e;
+    }
+    // two solves with T: u and e_0
+    double q0 = 0.0, qm = 0.0;
+    for (int s = 0; s < 2; s++) {
+        double dprev = 0.0;
+        eprev = 0.0;
+        for (int k = 0; k < m; k++) {
+            const long c = line + (long)k * plane;
+            const double rhs = s == 0 ? (k == 0 ? gam : (k == m - 1 ? ew : 0.0)) : (k == 0 ? 1.0 : 0.0);
+            dprev = (rhs - eprev * dprev) * tm[c];
+            td[c] = dprev;
+            eprev = (k < m - 1) ? L.ap[c] : 0.0;
+        }
+        double y = 0.0;
+        for (int k = m - 1; k >= 0; k--) {
+            const long c = line + (long)k * plane;
+            const double e = (k < m - 1) ? L.ap[c] : 0.0;
+            y = td[c] - e * tm[c] * y;
+            if (s == 0) {
+                o.q[c] = (float)y;
+                if (k == 0) q0 = y;
+                if (k == m - 1) qm = y;
+            } else {
+                o.g[c] = (float)y;
+            }
+        }
+    }
+    const double rho = ew / gam;
+    o.rho[line] = (float)rho;
+    o.kap[line] = (float)(1.0 / (1.0 + q0 + rho * qm));
+}
+
+// The coarsest level, one radial line (unit diagonal when dg is null): Thomas factors
+// (one thread), then the columns of its inverse (one thread per column, column-major).
+__global__ void k_mg_radial_factor(int nr, const double *__restrict__ dg, const double *__restrict__ ar,
+                                   double *__restrict__ im, double *__restrict__ cp)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double mk = dg ? dg[0] : 1.0;
+    for (int i = 0; i < nr; i++) {
+        if (i > 0) mk = (dg ? dg[i] : 1.0) - ar[i - 1] * ar[i - 1] / mk;
+        im[i] = 1.0 / mk;
+        cp[i] = (i + 1 < nr) ? ar[i] / mk : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kMB) void k_mg_radial_inverse(int nr, const double *__restrict__ ar,
+                                                           const double *__restrict__ im,
+                                                           const double *__restrict__ cp, double *__restrict__ inv)
+{
+    const int col = blockIdx.x * kMB + threadIdx.x;
+    if (col >= nr) return;
+    double *x = inv + (long)col * nr;
+    double d = 0.0;
+    for (int i = 0; i < nr; i++) {
+        const double rhs = i == col ? 1.0 : 0.0;
+        d = (rhs - (i > 0 ? ar[i - 1] : 0.0) * d) * im[i];
+        x[i] = d;
+    }
+    double y = 0.0;
+    for (int i = nr - 1; i >= 0; i--) {
+        y = x[i] - cp[i] * y;
+        x[i] = y;
+    }
+}
+
+// ------------------------------------------------------------------ V-cycle (float32)
+
+// A_l x at cell c = (i, j, k) of a level (unit diagonal when dg is null).  Cell indices
+// are 32-bit (the hierarchy is built for grids below 2^31 cells).
+__device__ __forceinline__ float mg_ax(const MgLevel &L, unsigned nr, const float *__restrict__ x, unsigned c,
+                                      unsigned i, unsigned j, unsigned k)
+{
+    const unsigned plane = nr * (unsigned)L.nt, np = (unsigned)L.np;
+    float v = (L.dg ? L.dg[c] : 1.0f) * x[c];
+    if (i + 1 < nr) v = fmaf(L.ar[c], x[c + 1], v);
+    if (i > 0) v = fmaf(L.ar[c - 1], x[c - 1], v);
+    if (j + 1 < (unsigned)L.nt) v = fmaf(L.at[c], x[c + nr], v);
+    if (j > 0) v = fmaf(L.at[c - nr], x[c - nr], v);
+    if (np > 1) {
+        const unsigned cp1 = k + 1 < np ? c + plane : c - (np - 1) * plane;
+        const unsigned cm1 = k > 0 ? c - plane : c + (np - 1) * plane;
+        v = fmaf(L.ap[c], x[cp1], v);
+        v = fmaf(L.ap[cm1], x[cm1], v);
+    }
+    return v;
+}
+
+// Block sum of a float64 per-thread value (valid in thread 0).
+__device__ __forceinline__ double mg_block_sum(double v, double *sh)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kMB / 64; w++) t += sh[w];
+    __syncthreads();
+    return t;
+}
+
+// r.z over the grid, reduced deterministically (block partials summed in block order by
+// the last block to finish), then the preconditioned CG scalars: beta = r.z / r.z_prev
+// (0 after a restart), rr = r.z for the direction kernel.
+__device__ __forceinline__ void mg_finish_dot(double acc, double *partials, unsigned *counter, DevScalars *sc,
+                                              int restart)
+{
+    __shared__ double sh[kMB / 64];
+    __shared__ int s_last;
+    const double bs = mg_block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = bs;
+        __threadfence();
+        const unsigned prev = atomicAdd(counter, 1u);
+        s_last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    double a = 0.0;
+    for (int t = threadIdx.x; t < (int)gridDim.x; t += kMB) a += partials[t];
+    a = mg_block_sum(a, sh);
+    if (threadIdx.x == 0) {
+        sc->beta = (restart || !(sc->rr > 0.0)) ? 0.0 : a / sc->rr;
+        sc->rr = a;
+        *counter = 0u;
+    }
+}
+
+// One damped block-Jacobi sweep on phi lines given its right-hand side: x = xin +
+// omega M^-1 rhs, where rhs = b - A xin (k_mg_resid) or, with ZERO (xin = 0), b itself
+// (float64 on the finest level: the CG residual).  The sweeps along a line are
+// sequential, so the loads of kMU consecutive steps are issued together before their
+// part of the recurrence (a step's latency is paid once per group, not per step).  DOT
+// (the last sweep of a cycle, finest level): x goes out as the float64 z, and r.z and
+// the CG scalars are formed on the way.  rhs may be L.dp: each step reads its entry
+// before the forward sweep overwrites it.
+constexpr int kMU = 8;
+
+template <bool ZERO, typename BT, bool DOT>
+__global__ __launch_bounds__(kMB) void k_mg_line(int nr, MgLevel L, const BT *rhs, const float *__restrict__ xin,
+                                                 float *__restrict__ xout, double *__restrict__ z,
+                                                 const double *__restrict__ r, float omega, double *partials,
+                                                 unsigned *counter, DevScalars *sc, int restart)
+{
+    if (sc && sc->done) return;
+    const long lines = (long)nr * L.nt;
+    const long line = (long)blockIdx.x * kMB + threadIdx.x;
+    const int m = L.np;
+    const long plane = lines;
+    double acc = 0.0;
+    if (line < lines) {
+        const float *__restrict__ im = L.im;
+        const float *__restrict__ cp = L.cp;
+        const float *__restrict__ qf = L.q;
+        const float *__restrict__ gf = L.g;
+        const float *__restrict__ ap = L.ap;
+        float *dp = L.dp;
+        const bool sm = m >= 3;  // Sherman-Morrison correction (periodic line of 3 or more)
+        const float e2 = m == 2 ? ap[line] + ap[line + plane] : 0.0f;
+        float d = 0.0f, eprev = 0.0f, sg = 0.0f;
+        for (int k0 = 0; k0 < m; k0 += kMU) {
+            float rv[kMU], imv[kMU], gv[kMU], apv[kMU];
+#pragma unroll
+            for (int u = 0; u < kMU; u++) {
+                const int k = k0 + u;
+                if (k < m) {
+                    const long c = line + (long)k * plane;
+                    rv[u] = (float)rhs[c];
+                    imv[u] = im[c];
+                    apv[u] = ap[c];
+                    gv[u] = sm ? gf[c] : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kMU; u++) {
+                const int k = k0 + u;
+                if (k < m) {
+                    d = (rv[u] - eprev * d) * imv[u];
+                    dp[line + (long)k * plane] = d;
+                    sg = fmaf(gv[u], rv[u], sg);
+                    eprev = sm ? apv[u] : e2;
+                }
+            }
+        }
+        const float fac = sm ? L.kap[line] * fmaf(L.rho[line], d, sg) : 0.0f;
+        float y = 0.0f;
+        for (int k0 = m - 1; k0 >= 0; k0 -= kMU) {
+            float dv[kMU], cv[kMU], qv[kMU], xv[kMU];
+            double rr[kMU];
+#pragma unroll
+            for (int u = 0; u < kMU; u++) {
+                const int k = k0 - u;
+                if (k >= 0) {
+                    const long c = line + (long)k * plane;
+                    dv[u] = dp[c];
+                    cv[u] = cp[c];
+                    qv[u] = sm ? qf[c] : 0.0f;
+                    xv[u] = ZERO ? 0.0f : xin[c];
+                    rr[u] = DOT ? r[c] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kMU; u++) {
+                const int k = k0 - u;
+                if (k >= 0) {
+                    y = dv[u] - cv[u] * y;
+                    const float delta = fmaf(-fac, qv[u], y);
+                    const float xn = fmaf(omega, delta, xv[u]);
+                    const long c = line + (long)k * plane;
+                    if (DOT) {
+                        z[c] = (double)xn;
+                        acc += rr[u] * (double)xn;
+                    } else {
+                        xout[c] = xn;
+                    }
+                }
+            }
+        }
+    }
+    if (DOT) mg_finish_dot(acc, partials, counter, sc, restart);
+}
+
+// rhs = b - A x' on one level, one cell per thread, where x' = x + P xc: the coarse
+// correction prolonged on the fly, at the cell and its six neighbours; x' goes to xo
+// for the sweep that follows.
+template <typename BT>
+__global__ __launch_bounds__(kMB) void k_mg_resid(int nr_, MgLevel F, int cnt_, const BT *__restrict__ b,
+                                                  const float *__restrict__ x, const float *__restrict__ xc,
+                                                  float *__restrict__ xo, float *__restrict__ rhs,
+                                                  const DevScalars *sc)
+{
+    if (sc && sc->done) return;
+    const unsigned nr = nr_, nt = F.nt, np = F.np, cnt = cnt_;
+    const unsigned f = blockIdx.x * kMB + threadIdx.x;
+    if (f >= (unsigned)F.n) return;
+    const unsigned i = f % nr, rest = f / nr;
+    const unsigned j = rest % nt, k = rest / nt;
+    const unsigned sj = nt > 1, sk = np > 1;
+    auto xv = [&](unsigned c, unsigned ii, unsigned jj, unsigned kk) {
+        return fmaf(F.w[c], xc[ii + nr * ((jj >> sj) + cnt * (kk >> sk))], x[c]);
+    };
+    const float x0 = xv(f, i, j, k);
+    float v = (F.dg ? F.dg[f] : 1.0f) * x0;
+    if (i + 1 < nr) v = fmaf(F.ar[f], xv(f + 1, i + 1, j, k), v);
+    if (i > 0) v = fmaf(F.ar[f - 1], xv(f - 1, i - 1, j, k), v);
+    if (j + 1 < nt) v = fmaf(F.at[f], xv(f + nr, i, j + 1, k), v);
+    if (j > 0) v = fmaf(F.at[f - nr], xv(f - nr, i, j - 1, k), v);
+    if (np > 1) {
+        const unsigned kp = k + 1 < np ? k + 1 : 0, km = k > 0 ? k - 1 : np - 1;
+        const unsigned cp1 = i + nr * (j + nt * kp), cm1 = i + nr * (j + nt * km);
+        v = fmaf(F.ap[f], xv(cp1, i, j, kp), v);
+        v = fmaf(F.ap[cm1], xv(cm1, i, j, km), v);
+    }
+    rhs[f] = (float)b[f] - v;
+    xo[f] = x0;
+}
+
+// The cycle's right-hand side in float32.
+__global__ __launch_bounds__(kMB) void k_mg_in(long n, const double *__restrict__ r, float *__restrict__ b,
+                                               const DevScalars *sc)
+{
+    if (sc && sc->done) return;
+    const long c = (long)blockIdx.x * kMB + threadIdx.x;
+    if (c < n) b[c] = (float)r[c];
+}
+
+// bc = P^T (b - A x) on the next level: one coarse cell per thread, the residuals of
+// its children weighted by w (b: float64 on the finest level, the CG residual).
+template <typename BT>
+__global__ __launch_bounds__(kMB) void k_mg_restrict(int nr_, MgLevel F, int cnt, int cnp, const BT *__restrict__ b,
+                                                     const float *__restrict__ x, float *__restrict__ bc,
+                                                     const DevScalars *sc)
+{
+    if (sc && sc->done) return;
+    const unsigned nr = nr_, nt = F.nt, np = F.np;
+    const unsigned cc = blockIdx.x * kMB + threadIdx.x;
+    if (cc >= nr * (unsigned)cnt * (unsigned)cnp) return;
+    const unsigned i = cc % nr, rest = cc / nr;
+    const unsigned J = rest % (unsigned)cnt, K = rest / (unsigned)cnt;
+    const unsigned ft = nt > 1 ? 2 : 1, fp = np > 1 ? 2 : 1;
+    const unsigned j1 = min(ft * J + ft, nt), k1 = min(fp * K + fp, np);
+    float acc = 0.0f;
+    for (unsigned k = fp * K; k < k1; k++)
+        for (unsigned j = ft * J; j < j1; j++) {
+            const unsigned f = i + nr * (j + nt * k);
+            acc = fmaf(F.w[f], (float)b[f] - mg_ax(F, nr, x, f, i, j, k), acc);
+        }
+    bc[cc] = acc;
+}
+
+// The coarsest level: x = A_L^-1 b by the stored inverse (symmetric; one block per row,
+// the row's products summed over the block in float64).
+__global__ __launch_bounds__(kMB) void k_mg_coarse(int nr, const double *__restrict__ inv, const float *__restrict__ b,
+                                                   float *__restrict__ x, const DevScalars *sc)
+{
+    if (sc && sc->done) return;
+    __shared__ double sh[kMB / 64];
+    const int row = blockIdx.x;
+    double acc = 0.0;
+    for (int col = threadIdx.x; col < nr; col += kMB) acc += inv[(long)row * nr + col] * (double)b[col];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kMB / 64; w++) t += sh[w];
+        x[row] = (float)t;
+    }
+}
+
+// A grid of one radial line: z = (double) x and r.z in one block (the cycle is the
+// coarsest solve alone).
+__global__ __launch_bounds__(kMB) void k_mg_out_line(int nr, const float *__restrict__ x, const double *__restrict__ r,
+                                                     double *__restrict__ z, DevScalars *sc, int restart)
+{
+    if (sc && sc->done) return;
+    __shared__ double sh[kMB / 64];
+    double acc = 0.0;
+    for (int c = threadIdx.x; c < nr; c += kMB) {
+        const double zv = (double)x[c];
+        z[c] = zv;
+        acc += r[c] * zv;
+    }
+    const double a = mg_block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        sc->beta = (restart || !(sc->rr > 0.0)) ? 0.0 : a / sc->rr;
+        sc->rr = a;
+    }
+}
+
+// ------------------------------------------------------------------ host side
+
+static unsigned mg_blocks(long n) { return (unsigned)((n + kMB - 1) / kMB); }
+
+void mg_shapes(int nt, int np, std::vector<std::pair<int, int>> &out)
+{
+    out.clear();
+    out.push_back({nt, np});
+    while ((long)nt * np > 1) {
+        nt = nt > 1 ? (nt + 1) / 2 : 1;
+        np = np > 1 ? (np + 1) / 2 : 1;
+        out.push_back({nt, np});
+    }
+}
+
+void launch_mg_setup(MgHier &h, const double *ahat, const double *s, hipStream_t st)
+{
+    const int nr = h.nr;
+    const int L = (int)h.lev.size() - 1;
+    const long n0 = h.lev[0].n;
+    hipLaunchKernelGGL(k_mg_recip, dim3(mg_blocks(n0)), dim3(kMB), 0, st, n0, s, h.B0);
+    for (int l = 0; l < L; l++) {
+        const MgLevel &F = h.lev[l];
+        const MgLevel &Cl = h.lev[l + 1];
+        MgSetLevel sf{F.nt, F.np, l == 0 ? nullptr : h.d64[l - 1].dg, l == 0 ? ahat : h.d64[l - 1].ar,
+                      l == 0 ? ahat + n0 : h.d64[l - 1].at, l == 0 ? ahat + 2 * n0 : h.d64[l - 1].ap,
+                      l == 0 ? h.B0 : h.d64[l - 1].B};
+        MgSetOut so{Cl.nt, Cl.np, h.d64[l].dg, h.d64[l].ar, h.d64[l].at, h.d64[l].ap, h.d64[l].B};
+        hipLaunchKernelGGL(k_mg_coarsen, dim3(mg_blocks(Cl.n)), dim3(kMB), 0, st, nr, sf, so, h.w[l]);
+        MgLineOut lo{h.im[l], h.cp[l], h.q[l], h.g[l], h.rho[l], h.kap[l]};
+        hipLaunchKernelGGL(k_mg_line_factor, dim3(mg_blocks((long)nr * F.nt)), dim3(kMB), 0, st, nr, sf, lo, h.t64a,
+                           h.t64b);
+        // the next level's operator in float32
+        launch_d2f(Cl.n, h.d64[l].dg, h.dg32[l], st);
+        launch_d2f(Cl.n, h.d64[l].ar, h.ar32[l], st);
+        launch_d2f(Cl.n, h.d64[l].at, h.at32[l], st);
+        launch_d2f(Cl.n, h.d64[l].ap, h.ap32[l], st);
+    }
+    // the coarsest line (the finest level itself when the grid is one radial line:
+    // unit diagonal)
+    const double *dgL = L == 0 ? nullptr : h.d64[L - 1].dg;
+    const double *arL = L == 0 ? ahat : h.d64[L - 1].ar;
+    hipLaunchKernelGGL(k_mg_radial_factor, dim3(1), dim3(64), 0, st, nr, dgL, arL, h.cim, h.ccp);
+    hipLaunchKernelGGL(k_mg_radial_inverse, dim3(mg_blocks(nr)), dim3(kMB), 0, st, nr, arL, h.cim, h.ccp, h.inv);
+}
+
+// One V-cycle on r (float64, n_0): z = M_mg r (float64), and the preconditioned CG
+// scalars from r.z (see mg_finish_dot).
+void launch_mg_vcycle(MgHier &h, const double *r, double *z, float omega, DevScalars *sc, int restart,
+                      hipStream_t st)
+{
+    const int nr = h.nr;
+    const int L = (int)h.lev.size() - 1;
+    const DevScalars *csc = sc;
+    if (L == 0) {  // one radial line: the exact solve
+        hipLaunchKernelGGL(k_mg_in, dim3(mg_blocks(h.lev[0].n)), dim3(kMB), 0, st, h.lev[0].n, r, h.lev[0].b, csc);
+        hipLaunchKernelGGL(k_mg_coarse, dim3(nr), dim3(kMB), 0, st, nr, (const double *)h.inv,
+                           (const float *)h.lev[0].b, h.lev[0].x2, csc);
+        hipLaunchKernelGGL(k_mg_out_line, dim3(1), dim3(kMB), 0, st, nr, (const float *)h.lev[0].x2, r, z, sc,
+                           restart);
+        return;
+    }
+    // down: pre-smoothing from zero, restriction of the residual
+    for (int l = 0; l < L; l++) {
+        MgLevel &F = h.lev[l];
+        const MgLevel &Cl = h.lev[l + 1];
+        const unsigned gl = mg_blocks((long)nr * F.nt);
+        if (l == 0) {
+            hipLaunchKernelGGL((k_mg_line<true, double, false>), dim3(gl), dim3(kMB), 0, st, nr, F, r,
+                               (const float *)nullptr, F.x, (double *)nullptr, (const double *)nullptr, omega,
+                               (double *)nullptr, (unsigned *)nullptr, sc, 0);
+            hipLaunchKernelGGL(k_mg_restrict<double>, dim3(mg_blocks(Cl.n)), dim3(kMB), 0, st, nr, F, Cl.nt, Cl.np,
+                               r, (const float *)F.x, Cl.b, csc);
+        } else {
+            hipLaunchKernelGGL((k_mg_line<true, float, false>), dim3(gl), dim3(kMB), 0, st, nr, F,
+                               (const float *)F.b, (const float *)nullptr, F.x, (double *)nullptr,
+                               (const double *)nullptr, omega, (double *)nullptr, (unsigned *)nullptr, sc, 0);
+            hipLaunchKernelGGL(k_mg_restrict<float>, dim3(mg_blocks(Cl.n)), dim3(kMB), 0, st, nr, F, Cl.nt, Cl.np,
+                               (const float *)F.b, (const float *)F.x, Cl.b, csc);
+        }
+    }
+    hipLaunchKernelGGL(k_mg_coarse, dim3(nr), dim3(kMB), 0, st, nr, (const double *)h.inv, (const float *)h.lev[L].b,
+                       h.lev[L].x2, csc);
+    // up: the residual with the prolonged correction, then post-smoothing from it
+    const float *xc = h.lev[L].x2;  // the coarser level's result
+    for (int l = L - 1; l >= 0; l--) {
+        MgLevel &F = h.lev[l];
+        const MgLevel &Cl = h.lev[l + 1];
+        const unsigned gl = mg_blocks((long)nr * F.nt);
+        if (l == 0) {
+            hipLaunchKernelGGL((k_mg_resid<double>), dim3(mg_blocks(F.n)), dim3(kMB), 0, st, nr, F, Cl.nt, r,
+                               (const float *)F.x, xc, F.x2, F.b, csc);
+            hipLaunchKernelGGL((k_mg_line<false, float, true>), dim3(gl), dim3(kMB), 0, st, nr, F,
+                               (const float *)F.b, (const float *)F.x2, (float *)nullptr, z, r, omega, h.part,
+                               h.cnt, sc, restart);
+        } else {
+            hipLaunchKernelGGL((k_mg_resid<float>), dim3(mg_blocks(F.n)), dim3(kMB), 0, st, nr, F, Cl.nt,
+                               (const float *)F.b, (const float *)F.x, xc, F.x2, F.dp, csc);
+            hipLaunchKernelGGL((k_mg_line<false, float, false>), dim3(gl), dim3(kMB), 0, st, nr, F,
+                               (const float *)F.dp, (const float *)F.x2, F.x, (double *)nullptr,
+                               (const double *)nullptr, omega, (double *)nullptr, (unsigned *)nullptr, sc, 0);
+            xc = F.x;
+        }
+    }
+}
+
+}  // namespace rt

@@ -368,6 +368,7 @@ void rt_destroy(rt_ctx *ctx)
     for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (void *p : ctx->allocs) (void)hipFree(p);
+    delete ctx->mg;
     if (ctx->h_sc) (void)hipHostFree(ctx->h_sc);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
@@ -512,6 +513,7 @@ rt_status rt_fld_assemble(rt_ctx *ctx, const rt_opacity *op, const rt_fld_params
     ctx->have_system = true;
     ctx->rb_ready = false;
     ctx->ln_ready = false;
+    if (ctx->mg) ctx->mg->ready = false;
     if (sys) {
         sys->n = ctx->d.n;
         sys->ahat = ctx->ahat;
@@ -1042,6 +1044,149 @@ rt_status solve_fp64_line(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *s
     return status;
 }
 
+// Multigrid hierarchy of the current system: allocated at the first use (levels from
+// the grid's theta and phi sizes down to one radial line), set up once per assembled
+// system.
+constexpr float kMgOmega = 0.8f;  // damping of the phi-line block-Jacobi smoother
+
+rt_status mg_prepare(rt_ctx *ctx)
+{
+    const Dims &d = ctx->d;
+    RT_CHECK(ctx, d.n < (1L << 31), "multigrid: grids of 2^31 cells or more are not supported");
+    if (!ctx->mg) {
+        auto *h = new MgHier();
+        h->nr = d.nr;
+        std::vector<std::pair<int, int>> sh;
+        mg_shapes(d.nt, d.np, sh);
+        const int L = (int)sh.size() - 1;
+        h->lev.resize(L + 1);
+        bool ok = true;
+        auto f32 = [&](long n) { float *p = dalloc<float>(ctx, n); ok = ok && p; return p; };
+        auto f64 = [&](long n) { double *p = dalloc<double>(ctx, n); ok = ok && p; return p; };
+        for (int l = 0; l <= L && ok; l++) {
+            MgLevel &v = h->lev[l];
+            v.nt = sh[l].first;
+            v.np = sh[l].second;
+            v.n = (long)d.nr * v.nt * v.np;
+            const long lines = (long)d.nr * v.nt;
+            if (l == 0) {
+                v.dg = nullptr;
+                v.ar = ctx->ahat32;
+                v.at = ctx->ahat32 + d.n;
+                v.ap = ctx->ahat32 + 2 * d.n;
+            } else {
+                h->d64.push_back(MgLevel64{f64(v.n), f64(v.n), f64(v.n), f64(v.n), f64(v.n)});
+                h->dg32.push_back(f32(v.n));
+                h->ar32.push_back(f32(v.n));
+                h->at32.push_back(f32(v.n));
+                h->ap32.push_back(f32(v.n));
+                v.dg = h->dg32.back();
+                v.ar = h->ar32.back();
+                v.at = h->at32.back();
+                v.ap = h->ap32.back();
+            }
+            if (l < L) {
+                h->w.push_back(f32(v.n));
+                h->im.push_back(f32(v.n));
+                h->cp.push_back(f32(v.n));
+                h->q.push_back(f32(v.n));
+                h->g.push_back(f32(v.n));
+                h->rho.push_back(f32(lines));
+                h->kap.push_back(f32(lines));
+                v.w = h->w.back();
+                v.im = h->im.back();
+                v.cp = h->cp.back();
+                v.q = h->q.back();
+                v.g = h->g.back();
+                v.rho = h->rho.back();
+                v.kap = h->kap.back();
+                v.x = f32(v.n);
+                v.dp = f32(v.n);
+            }
+            v.b = f32(v.n);
+            v.x2 = f32(v.n);
+        }
+        h->B0 = f64(d.n);
+        h->t64a = f64(d.n);
+        h->t64b = f64(d.n);
+        h->part = f64((long)((d.nr * (long)d.nt + 255) / 256));
+        h->cnt = dalloc<unsigned>(ctx, 1);
+        ok = ok && h->cnt;
+        if (h->cnt && hipMemset(h->cnt, 0, sizeof(unsigned)) != hipSuccess) ok = false;
+        h->cim = f64(d.nr);
+        h->ccp = f64(d.nr);
+        h->inv = f64((long)d.nr * d.nr);
+        if (!ctx->mg_z) ctx->mg_z = f64(d.n);
+        if (!ok) {
+            delete h;
+            return fail(ctx, RT_ENOMEM, "multigrid: out of device memory");
+        }
+        ctx->mg = h;
+    }
+    if (!ctx->mg->ready) {
+        launch_mg_setup(*ctx->mg, ctx->ahat, ctx->s, ctx->stream);
+        RT_HIP(ctx, hipGetLastError());
+        ctx->mg->ready = true;
+    }
+    return RT_OK;
+}
+
+// Float64 CG preconditioned by one multigrid V-cycle per iteration (float32 inside the
+// cycle; the iteration's dots, vectors and the true residual stay float64).
+rt_status solve_fp64_mg(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb)
+{
+    const Dims &d = ctx->d;
+    hipStream_t s = ctx->stream;
+    DevScalars *h = ctx->h_sc;
+    if (rt_status e = mg_prepare(ctx)) return e;
+    MgHier &mg = *ctx->mg;
+    h->thresh2 = o->tol * o->tol * bb;
+    h->done = 0;
+    h->iters = 0;
+    h->beta = 0.0;
+    if (rt_status e = write_scalars(ctx)) return e;
+    launch_resid(d, ctx->nblk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials, ctx->counter, ctx->sc, 1, s);
+    if (rt_status e = read_scalars(ctx)) return e;
+    double *pold = ctx->p0, *pnew = ctx->p1;
+    const int every = o->check_every > 0 ? o->check_every : 8;
+    rt_status status = RT_OK;
+    double res = std::sqrt(h->res2 / bb);
+    bool restart = true;
+    for (;;) {
+        st->relres = res;
+        if (!isfin(res)) { status = RT_ENONFINITE; break; }
+        if (res <= o->tol) break;
+        if (h->iters >= o->max_iter) { status = RT_ENOCONV; break; }
+        int m = std::min(every, o->max_iter - h->iters);
+        int it_before = h->iters;
+        for (int k = 0; k < m; k++) {
+            const hipEvent_t *ev = k == 0 ? &ctx->ev[8] : nullptr;
+            if (ev) (void)hipEventRecord(ev[0], s);
+            launch_mg_vcycle(mg, ctx->r, ctx->mg_z, kMgOmega, ctx->sc, restart && k == 0, s);
+            if (ev) (void)hipEventRecord(ev[3], s);
+            launch_pcg_dir_upd(d, ctx->nblk, ctx->nblk_upd, ctx->ahat, ctx->mg_z, ctx->y, ctx->r, pold, pnew, ctx->qv,
+                               ctx->partials, ctx->counter, ctx->sc, s, ev);
+            std::swap(pold, pnew);
+        }
+        restart = false;
+        RT_HIP(ctx, hipGetLastError());
+        if (rt_status e = read_scalars(ctx)) return e;
+        add_kernel_sample(ctx, st, true);
+        if ((h->iters - it_before) % 2 != m % 2) std::swap(pold, pnew);  // kernels that exited early
+        if (!isfin(h->res2)) { status = RT_ENONFINITE; st->relres = NAN; break; }
+        if (h->done || h->iters >= o->max_iter) {
+            launch_resid(d, ctx->nblk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials, ctx->counter,
+                         ctx->sc, 1, s);
+            if (rt_status e = read_scalars(ctx)) return e;
+            res = std::sqrt(h->res2 / bb);
+            restart = true;
+        }
+    }
+    st->iters = h->iters;
+    st->precond_applies = h->iters;
+    return status;
+}
+
 rt_status solve_gmres(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb, rt_net *net = nullptr,
                       int budget = 0, int *out = nullptr);
 
@@ -1321,8 +1466,8 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
     RT_CHECK(ctx, o->inner == RT_INNER_FCG || o->inner == RT_INNER_FGMRES, "inner must be an rt_inner value");
     RT_CHECK(ctx, o->launch >= RT_LAUNCH_AUTO && o->launch <= RT_LAUNCH_BLOCK,
              "rt_fld_solve: launch must be an rt_launch value");
-    RT_CHECK(ctx, o->precond == 0 || (o->precond == 1 && o->mode == RT_SOLVE_FP64 && !o->reduce),
-             "precond = 1 (radial-line block Jacobi) needs RT_SOLVE_FP64 without reduce");
+    RT_CHECK(ctx, o->precond == 0 || ((o->precond == 1 || o->precond == 2) && o->mode == RT_SOLVE_FP64 && !o->reduce),
+             "precond = 1 (radial-line block Jacobi) and 2 (multigrid) need RT_SOLVE_FP64 without reduce");
     rt_solve_stats local{};
     rt_solve_stats *S = st ? st : &local;
     *S = rt_solve_stats{};
@@ -1338,6 +1483,7 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
     rt_status status;
     const bool rb = o->reduce && rb_possible(ctx);
     if (o->mode == RT_SOLVE_FP64 && o->precond == 1) status = solve_fp64_line(ctx, o, S, bb);
+    else if (o->mode == RT_SOLVE_FP64 && o->precond == 2) status = solve_fp64_mg(ctx, o, S, bb);
     else if (o->mode == RT_SOLVE_FP64) status = rb ? solve_fp64_rb(ctx, o, S, bb) : solve_fp64(ctx, o, S, bb);
     else if (o->mode == RT_SOLVE_MIXED) status = rb ? solve_mixed_rb(ctx, o, S, bb) : solve_mixed(ctx, o, S, bb);
     else if (o->mode == RT_SOLVE_GMRES) status = solve_gmres(ctx, o, S, bb);
@@ -1603,6 +1749,51 @@ rt_status rt_precond_apply(rt_ctx *ctx, const double *r, double *z)
     launch_line_solve(ctx->d, ctx->nblk, ctx->ahat, ctx->ln_c, ctx->ln_im, r, z, ctx->partials, ctx->counter, ctx->sc,
                       1, ctx->stream);
     RT_HIP(ctx, hipGetLastError());
+    return RT_OK;
+}
+
+rt_status rt_mg_apply(rt_ctx *ctx, const double *r, double *z)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    RT_CHECK(ctx, ctx->have_system, "no assembled system");
+    RT_CHECK(ctx, r && z, "rt_mg_apply: NULL field pointer");
+    if (rt_status e = mg_prepare(ctx)) return e;
+    // the solver's own cycle (its r.z and scalars land in the context's scalars)
+    ctx->h_sc->done = 0;
+    ctx->h_sc->rr = 0.0;
+    if (rt_status e = write_scalars(ctx)) return e;
+    launch_mg_vcycle(*ctx->mg, r, z, kMgOmega, ctx->sc, 1, ctx->stream);
+    RT_HIP(ctx, hipGetLastError());
+    return RT_OK;
+}
+
+rt_status rt_mg_level(rt_ctx *ctx, int level, rt_mg_level_view *out)
+{
+    if (!ctx) return fail(nullptr, RT_EINVAL, "context is NULL");
+    RT_CHECK(ctx, ctx->have_system, "no assembled system");
+    RT_CHECK(ctx, out, "rt_mg_level: NULL view");
+    if (rt_status e = mg_prepare(ctx)) return e;
+    const MgHier &mg = *ctx->mg;
+    const int L = (int)mg.lev.size() - 1;
+    RT_CHECK(ctx, level >= 0 && level <= L, "rt_mg_level: level out of range");
+    const MgLevel &v = mg.lev[level];
+    *out = rt_mg_level_view{};
+    out->levels = L + 1;
+    out->nr = ctx->d.nr;
+    out->nt = v.nt;
+    out->np = v.np;
+    out->n = v.n;
+    out->dg = v.dg;
+    out->ar = v.ar;
+    out->at = v.at;
+    out->ap = v.ap;
+    out->w = v.w;
+    out->im = v.im;
+    out->cp = v.cp;
+    out->q = v.q;
+    out->g = v.g;
+    out->rho = v.rho;
+    out->kap = v.kap;
     return RT_OK;
 }
 

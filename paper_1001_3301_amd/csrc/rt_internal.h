@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/rt.h"
@@ -189,6 +190,36 @@ struct DevScalars {
 
 struct Net;
 
+// Multigrid preconditioner (k_mg.hip).  Level l of the hierarchy: n = N_r nt np cells;
+// operator dg / ar / at / ap (dg null: unit diagonal, the finest level A^), the
+// prolongation weights w to level l+1, the phi-line factors (im, cp, q, g per cell,
+// rho, kap per (r, theta) line) and the V-cycle's vectors.
+struct MgLevel {
+    int nt = 0, np = 0;
+    long n = 0;
+    const float *dg = nullptr, *ar = nullptr, *at = nullptr, *ap = nullptr;
+    const float *w = nullptr, *im = nullptr, *cp = nullptr, *q = nullptr, *g = nullptr;
+    const float *rho = nullptr, *kap = nullptr;
+    float *b = nullptr, *x = nullptr, *x2 = nullptr, *dp = nullptr;
+};
+
+struct MgLevel64 {
+    double *dg = nullptr, *ar = nullptr, *at = nullptr, *ap = nullptr, *B = nullptr;
+};
+
+struct MgHier {
+    int nr = 0;
+    std::vector<MgLevel> lev;    // 0 .. L (L: one radial line)
+    std::vector<MgLevel64> d64;  // levels 1 .. L in float64 (entry l - 1), built by the set-up
+    std::vector<float *> dg32, ar32, at32, ap32;                // levels 1 .. L in float32 (entry l - 1)
+    std::vector<float *> w, im, cp, q, g, rho, kap;           // levels 0 .. L - 1
+    double *B0 = nullptr, *t64a = nullptr, *t64b = nullptr;  // 1 / s, line-factor scratch (n_0 each)
+    double *cim = nullptr, *ccp = nullptr, *inv = nullptr;   // coarsest line: factors, inverse (N_r^2)
+    double *part = nullptr;                                   // r.z partial sums (one per line-sweep block)
+    unsigned *cnt = nullptr;                                  // their completion counter (0 between uses)
+    bool ready = false;                                      // set up for the current system
+};
+
 // ------------------------------------------------------------------ launchers
 void launch_raytrace(const Dims &d, const Opac &op, const Geo &g, const double *F0, double R2,
                      const double *rho, const double *T, double *q, double *S, double *Fface,
@@ -283,7 +314,19 @@ void launch_mdot(const Dims &d, int nblk, const double *V, int k, const double *
 void launch_maxpy(long n, const double *V, int k, const double *coef, double sign, double *w, hipStream_t st);
 void launch_scale_into(long n, const double *x, double s, double *y, hipStream_t st);
 void launch_d2f(long n, const double *x, float *y, hipStream_t st);
+// Multigrid: the level shapes (theta, phi sizes from the finest to one radial line),
+// the set-up of a system (float64 Galerkin levels, line factors, coarsest inverse) and
+// one V-cycle on r: z = M_mg r, with r.z and the CG scalars beta (0 when restart) and rr
+// = r.z written to sc (whose kernels do nothing once sc->done is set).
+void mg_shapes(int nt, int np, std::vector<std::pair<int, int>> &out);
+void launch_mg_setup(MgHier &h, const double *ahat, const double *s, hipStream_t st);
+void launch_mg_vcycle(MgHier &h, const double *r, double *z, float omega, DevScalars *sc, int restart,
+                      hipStream_t st);
 void launch_f2d(long n, const float *x, double *y, hipStream_t st);
+// The rest of a preconditioned CG iteration once z = M^-1 r and beta are known.
+void launch_pcg_dir_upd(const Dims &d, int nblk, int nblk_upd, const double *a, const double *z, double *y, double *r,
+                        double *pold, double *pnew, double *q, double *partials, unsigned *counter, DevScalars *sc,
+                        hipStream_t st, const hipEvent_t *ev);
 // Flexible CG for the learned mode (float32 vectors, float64 dots).
 void launch_fcg_dir(const Dims &d, int nblk, const float *a, const float *z, const float *pold, const float *r,
                     float *pnew, float *q, double *partials, unsigned *counter, DevScalars *sc, hipStream_t st);
@@ -414,4 +457,7 @@ struct rt_ctx {
     hipEvent_t ev[12] = {};
 
     rt::Net *net_scratch = nullptr;
+    // multigrid hierarchy, allocated at the first multigrid solve, set up once per system
+    rt::MgHier *mg = nullptr;
+    double *mg_z = nullptr;
 };

@@ -23,6 +23,7 @@ MODE_FP64, MODE_MIXED, MODE_LEARNED, MODE_GMRES, MODE_NONE = 0, 1, 2, 3, 4
 LAUNCH_AUTO, LAUNCH_DIRECT, LAUNCH_GRAPH, LAUNCH_BLOCK = 0, 1, 2, 3
 INNER_FCG, INNER_FGMRES = 0, 1
 LANES_BINS, LANES_CELLS = 0, 1
+PRECOND_JACOBI, PRECOND_LINE, PRECOND_MG = 0, 1, 2
 
 dp = C.POINTER(C.c_double)
 
@@ -55,6 +56,11 @@ class FldParams(C.Structure):
 class System(C.Structure):
     _fields_ = [("n", C.c_long), ("ahat", C.c_void_p), ("ahat32", C.c_void_p), ("s", C.c_void_p),
                 ("bhat", C.c_void_p), ("w", C.c_void_p), ("chi", C.c_void_p)]
+
+
+class MgLevelView(C.Structure):
+    _fields_ = [("levels", C.c_int), ("nr", C.c_int), ("nt", C.c_int), ("np", C.c_int), ("n", C.c_long)] + \
+        [(f, C.c_void_p) for f in ("dg", "ar", "at", "ap", "w", "im", "cp", "q", "g", "rho", "kap")]
 
 
 class SolveOpts(C.Structure):
@@ -99,7 +105,7 @@ class RelaxStats(C.Structure):
 EXPORTS = ["rt_create", "rt_destroy", "rt_last_error", "rt_ncell", "rt_star_bin_flux",
            "rt_set_opacity", "rt_set_star", "rt_raytrace", "rt_raytrace_mapped", "rt_energy", "rt_fld_assemble",
            "rt_spmv", "rt_fld_solve", "rt_temperature", "rt_force", "rt_step", "rt_step_fields",
-           "rt_gray_table", "rt_relax", "rt_rosseland_depth", "rt_precond_apply",
+           "rt_gray_table", "rt_relax", "rt_rosseland_depth", "rt_precond_apply", "rt_mg_apply", "rt_mg_level",
            "rt_net_create", "rt_net_destroy", "rt_net_last_error", "rt_net_param_count",
            "rt_net_get_params", "rt_net_get_grads", "rt_net_set_params", "rt_net_save", "rt_net_load",
            "rt_net_forward", "rt_net_apply", "rt_net_loss_grad", "rt_net_loss_grad_resid", "rt_net_adam", "rt_dataset_create",
@@ -161,6 +167,8 @@ def lib():
     L.rt_gray_table.argtypes = [P(Opacity), dp, dp, dp, dp]
     L.rt_rosseland_depth.argtypes = [vp, P(Opacity), vp, vp, vp]
     L.rt_precond_apply.argtypes = [vp, vp, vp]
+    L.rt_mg_apply.argtypes = [vp, vp, vp]
+    L.rt_mg_level.argtypes = [vp, C.c_int, C.POINTER(MgLevelView)]
     L.rt_relax.argtypes = [vp, P(Opacity), P(Star), P(FldParams), P(SolveOpts), vp, vp, vp, C.c_double,
                            C.c_int, P(RelaxStats)]
     fp = P(C.c_float)
@@ -405,6 +413,28 @@ class Context:
     def precond_apply(self, r, z):
         """rt_precond_apply: z = M^-1 r, radial-line block Jacobi of the current system."""
         self._chk(lib().rt_precond_apply(self.h, self._dev(r, self.n, "r"), self._dev(z, self.n, "z")))
+
+    def mg_apply(self, r, z):
+        """rt_mg_apply: z = M_mg r, one multigrid V-cycle of the current system."""
+        self._chk(lib().rt_mg_apply(self.h, self._dev(r, self.n, "r"), self._dev(z, self.n, "z")))
+
+    def mg_level(self, level):
+        """rt_mg_level: copies of one level's float32 arrays (None where the view has none)."""
+        torch = self._torch
+        v = MgLevelView()
+        self._chk(lib().rt_mg_level(self.h, int(level), C.byref(v)))
+        lines = v.nr * v.nt
+        out = dict(levels=v.levels, nr=v.nr, nt=v.nt, np=v.np, n=v.n)
+        for f in ("dg", "ar", "at", "ap", "w", "im", "cp", "q", "g", "rho", "kap"):
+            ptr = getattr(v, f)
+            if not ptr:
+                out[f] = None
+                continue
+            cnt = lines if f in ("rho", "kap") else v.n
+            t = torch.empty(cnt, dtype=torch.float32, device="cuda")
+            _memcpy_d2d(t.data_ptr(), ptr, cnt * 4)
+            out[f] = t
+        return out
 
     def rosseland_depth(self, rho, T, tau):
         """rt_rosseland_depth: inward tau_R at the radial faces ((N_r + 1) per column)."""
