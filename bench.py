@@ -7,9 +7,10 @@ dt = 1e9 s).  Every timed step starts from the same prepared state (the temperat
 in equilibrium with the stellar irradiation and E = a T_bc^4), so the K timed steps do
 identical work.  The headline solve mode is timed first (K steps after W warm-up
 steps), then the other modes for comparison (at most 3 steps after 1 warm-up step
-each).  The headline mode also runs --successive N steps (default 5) with the
+each).  The headline mode also runs --successive N steps with the
 temperature carried over, reported per step (seconds and iterations) under
-"successive_steps": the system gets harder as the radiation field evolves.  Every
+"successive_steps" (default 50, the 50 coupled steps of the full-scale configuration):
+the system gets harder as the radiation field evolves.  Every
 mode's answer is checked against the oracle on the whole grid ("oracle_check": the
 oracle's own assembly and residual of the GPU's E, the oracle's Newton temperature from
 it).  Unless --no-main-loop, the main loop is also run to equilibrium (the run table's
@@ -40,11 +41,21 @@ PEAK_HBM_GBS = 8000.0
 # inputs at the black cells and every face coefficient once, writes p at the black cells
 # and t at the red cells (20 / 40 B); the black pass reads p, t and every face
 # coefficient once and writes q (18 / 36 B); the update streams six half-size arrays.
+# A multigrid-preconditioned CG iteration (fp64-mg), algorithmic bytes per cell of the
+# finest level: the V-cycle's float32 kernels there (pre-sweep 40: r, im, ap, g, dp out
+# and back, cp, q, x out; restriction 29: r, x, w, three couplings, 1/4 of a coarse
+# write; residual with the prolonged correction 37: r, x, w, 1/4 of the coarse result,
+# three couplings, rhs and x' out; last sweep 52: rhs, im, ap, g, dp out and back, cp, q,
+# x', r, z out), the float64 direction (56) and update (48) kernels, and the coarser
+# levels, a third of the finest level's cells at ~150 bytes each.
+MG_ITER_BYTES_PER_CELL = 40 + 29 + 37 + 52 + 56 + 48 + 50
 BYTES_PER_CELL = {"fp64": {"dir": 7 * 8, "upd": 6 * 8}, "mixed": {"dir": 7 * 4, "upd": 6 * 4},
                   "fp64-rb": {"dir": 76, "upd": 24, "red": 40, "black": 36},
-                  "mixed-rb": {"dir": 38, "upd": 12, "red": 20, "black": 18}}
+                  "mixed-rb": {"dir": 38, "upd": 12, "red": 20, "black": 18},
+                  "fp64-mg": {"cg_dir": 7 * 8, "upd": 6 * 8, "iteration": MG_ITER_BYTES_PER_CELL}}
 KERNEL_NAMES = {"fp64": "k_cg_dir<double>", "mixed": "k_cg_dir<float>", "fp64-rb": ("k_rb_red_dir<double>",
-                "k_rb_black_dir<double>"), "mixed-rb": ("k_rb_red_dir<float>", "k_rb_black_dir<float>")}
+                "k_rb_black_dir<double>"), "mixed-rb": ("k_rb_red_dir<float>", "k_rb_black_dir<float>"),
+                "fp64-mg": "k_cg_dir<double>"}
 # HBM bytes per launch of these kernels on the 512x256x512 workload, from rocprofv3
 # FETCH_SIZE (x2.0, calibrated on a kernel of known size) + WRITE_SIZE; the summary with
 # the commands is profiles/solver_kernels_clumpy-512x256x512-nu64.md.  Set to None when
@@ -525,7 +536,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="clumpy-512x256x512-nu64")
-    ap.add_argument("--modes", default="mixed-rb,fp64,mixed,fp64-rb,learned,learned-rb,learned-fgmres-rb",
+    ap.add_argument("--modes", default="fp64-mg,mixed-rb,fp64,mixed,fp64-rb,learned,learned-rb,learned-fgmres-rb",
                     help="comma list; the first is the headline (suffix -rb: red-black reduced system)")
     ap.add_argument("--net", default="", help="load the network from this file instead of training it")
     ap.add_argument("--save-net", default="", help="save the trained network to this file")
@@ -538,8 +549,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=200000)
-    ap.add_argument("--successive", type=int, default=5,
-                    help="also run this many successive steps of the headline mode (not timed for value)")
+    ap.add_argument("--successive", type=int, default=50,
+                    help="also run this many successive steps of the headline mode (not timed for value; "
+                         "50 x ~0.5 s with the multigrid headline, far longer with a Jacobi-CG headline)")
     ap.add_argument("--other-steps", type=int, default=3,
                     help="timed steps of each non-headline mode (at most --steps; warm-up at most 1)")
     ap.add_argument("--c4-gain", action="store_true",
@@ -633,7 +645,11 @@ def main():
     # the dominant kernel: the direction kernel, or the longer of the red and black passes
     # of a reduced solve (bytes per half-grid cell = twice the per-full-cell figure)
     kname = KERNEL_NAMES.get(head)
-    if bpc and "black" in bpc:
+    if bpc and "iteration" in bpc:
+        # multigrid CG: the float64 direction kernel is the longest launch of an iteration
+        # (ms_black times it alone; ms_dir - ms_black is the V-cycle)
+        dom_b, dom_ms, dom_cells = bpc["cg_dir"], ms_black, n
+    elif bpc and "black" in bpc:
         ms_red = ms_dir - ms_black
         red_dom = ms_red > ms_black
         dom_b, dom_ms, dom_cells = (2 * bpc["red"], ms_red, n // 2) if red_dom else (2 * bpc["black"], ms_black, n // 2)
@@ -653,7 +669,8 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "mixed": "f32+f64", "learned": "bf16+f32+f64", "gmres": "f64"}[head.split("-")[0]],
+        "dtype": "f64+f32" if head.endswith("-mg") else
+                 {"fp64": "f64", "mixed": "f32+f64", "learned": "bf16+f32+f64", "gmres": "f64"}[head.split("-")[0]],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {wl.grid.shape[0]}x{wl.grid.shape[1]}x{wl.grid.shape[2]} cells, "
                                f"{c['n_nu']} bins, tau550={wl.tau550:g}, clumps seed {c['seeds'][-1]}",
@@ -681,10 +698,11 @@ def main():
                            "traffic": MEASURED_TRAFFIC.get((kname, args.config)), "bytes_per_cell": dom_b,
                            "cells_per_launch": dom_cells}
         if ms_dir > 0 and ms_upd > 0:
-            # one whole Krylov iteration (both kernels): its algorithmic bytes over the two launch times
-            it_gbs = (bpc["dir"] + bpc["upd"]) * n / ((ms_dir + ms_upd) / 1e3) / 1e9
+            # one whole Krylov iteration (all its kernels): its algorithmic bytes over the launch times
+            it_b = bpc["iteration"] if "iteration" in bpc else bpc["dir"] + bpc["upd"]
+            it_gbs = it_b * n / ((ms_dir + ms_upd) / 1e3) / 1e9
             out["krylov_iteration"] = {"achieved": it_gbs, "unit": "GB/s", "frac": it_gbs / PEAK_HBM_GBS,
-                                       "bytes_per_cell": bpc["dir"] + bpc["upd"]}
+                                       "bytes_per_cell": it_b, "ms": ms_dir + ms_upd}
     for mode in modes[1:]:
         Rm = results[mode]
         out[f"{mode}_solve_s_per_step"] = statistics.median([s["solve"]["ms"] / 1e3 for s in Rm["stats"]])
@@ -764,7 +782,7 @@ def main():
             "sample": f"OpenMP oracle on {thr} threads, whole {wl.grid.shape[0]}x{wl.grid.shape[1]}x"
                       f"{wl.grid.shape[2]} grid: ray trace, Newton, assembly and 40 float64 CG iterations; "
                       f"solve s/step = time per CG iteration x the GPU float64 iteration count ({fp64_iters}), "
-                      f"the plain method (the oracle has no reduced or mixed-precision solve)",
+                      f"the plain method (the oracle has no reduced, mixed-precision or multigrid solve)",
             "phases_s": {"raytrace": tm["raytrace"], "newton": tm["newton"], "assemble": tm["assemble"],
                          "cg_iteration": tm["cg_iteration"]},
             "raytrace_gcell_nu_per_s": n * c["n_nu"] / tm["raytrace"] / 1e9,
