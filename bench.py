@@ -49,13 +49,19 @@ PEAK_HBM_GBS = 8000.0
 # x', r, z out), the float64 direction (56) and update (48) kernels, and the coarser
 # levels, a third of the finest level's cells at ~150 bytes each.
 MG_ITER_BYTES_PER_CELL = 40 + 29 + 37 + 52 + 56 + 48 + 50
+# The float32 flexible-CG variant (mixed-mg): the same cycle on a float32 residual (4
+# bytes less in each of the first three kernels, the last sweep writes a float32 z and
+# reads no r: 40), flexible-CG beta 8 (z, q), direction 32 (three couplings, z, p_old,
+# r; p and q out), update 24 (x, p, r, q; x and r out).
+MG32_ITER_BYTES_PER_CELL = 36 + 25 + 33 + 40 + 8 + 32 + 24 + 50
 BYTES_PER_CELL = {"fp64": {"dir": 7 * 8, "upd": 6 * 8}, "mixed": {"dir": 7 * 4, "upd": 6 * 4},
                   "fp64-rb": {"dir": 76, "upd": 24, "red": 40, "black": 36},
                   "mixed-rb": {"dir": 38, "upd": 12, "red": 20, "black": 18},
-                  "fp64-mg": {"cg_dir": 7 * 8, "upd": 6 * 8, "iteration": MG_ITER_BYTES_PER_CELL}}
+                  "fp64-mg": {"cg_dir": 7 * 8, "upd": 6 * 8, "iteration": MG_ITER_BYTES_PER_CELL},
+                  "mixed-mg": {"cg_dir": 32, "upd": 24, "iteration": MG32_ITER_BYTES_PER_CELL}}
 KERNEL_NAMES = {"fp64": "k_cg_dir<double>", "mixed": "k_cg_dir<float>", "fp64-rb": ("k_rb_red_dir<double>",
                 "k_rb_black_dir<double>"), "mixed-rb": ("k_rb_red_dir<float>", "k_rb_black_dir<float>"),
-                "fp64-mg": "k_cg_dir<double>"}
+                "fp64-mg": "k_cg_dir<double>", "mixed-mg": "k_fcg_dir<4>"}
 # HBM bytes per launch of these kernels on the 512x256x512 workload, from rocprofv3
 # FETCH_SIZE (x2.0, calibrated on a kernel of known size) + WRITE_SIZE; the summary with
 # the commands is profiles/solver_kernels_clumpy-512x256x512-nu64.md.  Set to None when
@@ -669,7 +675,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32" if head.endswith("-mg") else
+        "dtype": ("f64+f32" if head.startswith("fp64") else "f32+f64") if head.endswith("-mg") else
                  {"fp64": "f64", "mixed": "f32+f64", "learned": "bf16+f32+f64", "gmres": "f64"}[head.split("-")[0]],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {wl.grid.shape[0]}x{wl.grid.shape[1]}x{wl.grid.shape[2]} cells, "

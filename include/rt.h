@@ -124,13 +124,16 @@ typedef struct {
                             N_phi is even or 1, else the full system is solved.
                             RT_SOLVE_LEARNED: 1 = the finish after the network budget is
                             the reduced mixed solve instead of full-system float64 CG */
-    int precond;         /* RT_SOLVE_FP64 without reduce: 0 = the Jacobi scaling alone (the
-                            default), 1 = CG preconditioned by the radial-line block Jacobi:
-                            each radial row's tridiagonal block of A^ solved exactly (the
-                            block-Jacobi class of the paper's solver set-up, Sect. "Numerical
-                            setup", as a comparator), 2 = CG preconditioned by one multigrid
-                            V-cycle per iteration (an extension, not in the paper: see
-                            rt_mg_apply; check_every defaults to 8 here) */
+    int precond;         /* without reduce: 0 = the Jacobi scaling alone (the default),
+                            1 (RT_SOLVE_FP64) = CG preconditioned by the radial-line block
+                            Jacobi: each radial row's tridiagonal block of A^ solved exactly
+                            (the block-Jacobi class of the paper's solver set-up, Sect.
+                            "Numerical setup", as a comparator), 2 = one multigrid V-cycle
+                            per iteration (an extension, not in the paper: see rt_mg_apply):
+                            RT_SOLVE_FP64 runs float64 CG with it (check_every defaults to 8
+                            there), RT_SOLVE_MIXED flexible CG in float32 with float64 dots
+                            and reliable updates (a non-finite float32 state hands over to
+                            the float64 form: fallback = 1) */
     int launch;          /* rt_launch: how the CG iterations of RT_SOLVE_FP64 / RT_SOLVE_MIXED
                             (reduced or not) reach the GPU; every choice computes the same
                             method, DIRECT and GRAPH bit for bit alike */

@@ -27,6 +27,8 @@
 // so every access of a step is one coalesced row segment.  The set-up runs in float64;
 // the V-cycle stores and computes in float32 (the outer CG keeps float64 vectors, dots
 // and the true residual).
+#include <type_traits>
+
 #include "rt_internal.h"
 
 namespace rt {
@@ -443,7 +445,8 @@ __global__ __launch_bounds__(kMB) void k_mg_resid(int nr_, MgLevel F, int cnt_, 
 }
 
 // The cycle's right-hand side in float32.
-__global__ __launch_bounds__(kMB) void k_mg_in(long n, const double *__restrict__ r, float *__restrict__ b,
+template <typename RT>
+__global__ __launch_bounds__(kMB) void k_mg_in(long n, const RT *__restrict__ r, float *__restrict__ b,
                                                const DevScalars *sc)
 {
     if (sc && sc->done) return;
@@ -561,20 +564,25 @@ void launch_mg_setup(MgHier &h, const double *ahat, const double *s, hipStream_t
     hipLaunchKernelGGL(k_mg_radial_inverse, dim3(mg_blocks(nr)), dim3(kMB), 0, st, nr, arL, h.cim, h.ccp, h.inv);
 }
 
-// One V-cycle on r (float64, n_0): z = M_mg r (float64), and the preconditioned CG
-// scalars from r.z (see mg_finish_dot).
-void launch_mg_vcycle(MgHier &h, const double *r, double *z, float omega, DevScalars *sc, int restart,
+// One V-cycle on r (n_0 values): z = M_mg r, either in float64 (z64, with r.z and the
+// preconditioned CG scalars formed on the way, see mg_finish_dot) or in float32 (z32).
+template <typename RT>
+static void mg_vcycle(MgHier &h, const RT *r, double *z64, float *z32, float omega, DevScalars *sc, int restart,
                       hipStream_t st)
 {
     const int nr = h.nr;
     const int L = (int)h.lev.size() - 1;
     const DevScalars *csc = sc;
     if (L == 0) {  // one radial line: the exact solve
-        hipLaunchKernelGGL(k_mg_in, dim3(mg_blocks(h.lev[0].n)), dim3(kMB), 0, st, h.lev[0].n, r, h.lev[0].b, csc);
+        hipLaunchKernelGGL(k_mg_in<RT>, dim3(mg_blocks(h.lev[0].n)), dim3(kMB), 0, st, h.lev[0].n, r, h.lev[0].b,
+                           csc);
+        float *x = z64 ? h.lev[0].x2 : z32;
         hipLaunchKernelGGL(k_mg_coarse, dim3(nr), dim3(kMB), 0, st, nr, (const double *)h.inv,
-                           (const float *)h.lev[0].b, h.lev[0].x2, csc);
-        hipLaunchKernelGGL(k_mg_out_line, dim3(1), dim3(kMB), 0, st, nr, (const float *)h.lev[0].x2, r, z, sc,
-                           restart);
+                           (const float *)h.lev[0].b, x, csc);
+        if constexpr (std::is_same<RT, double>::value)
+            if (z64)
+                hipLaunchKernelGGL(k_mg_out_line, dim3(1), dim3(kMB), 0, st, nr, (const float *)x, r, z64, sc,
+                                   restart);
         return;
     }
     // down: pre-smoothing from zero, restriction of the residual
@@ -583,11 +591,11 @@ void launch_mg_vcycle(MgHier &h, const double *r, double *z, float omega, DevSca
         const MgLevel &Cl = h.lev[l + 1];
         const unsigned gl = mg_blocks((long)nr * F.nt);
         if (l == 0) {
-            hipLaunchKernelGGL((k_mg_line<true, double, false>), dim3(gl), dim3(kMB), 0, st, nr, F, r,
+            hipLaunchKernelGGL((k_mg_line<true, RT, false>), dim3(gl), dim3(kMB), 0, st, nr, F, r,
                                (const float *)nullptr, F.x, (double *)nullptr, (const double *)nullptr, omega,
                                (double *)nullptr, (unsigned *)nullptr, sc, 0);
-            hipLaunchKernelGGL(k_mg_restrict<double>, dim3(mg_blocks(Cl.n)), dim3(kMB), 0, st, nr, F, Cl.nt, Cl.np,
-                               r, (const float *)F.x, Cl.b, csc);
+            hipLaunchKernelGGL(k_mg_restrict<RT>, dim3(mg_blocks(Cl.n)), dim3(kMB), 0, st, nr, F, Cl.nt, Cl.np, r,
+                               (const float *)F.x, Cl.b, csc);
         } else {
             hipLaunchKernelGGL((k_mg_line<true, float, false>), dim3(gl), dim3(kMB), 0, st, nr, F,
                                (const float *)F.b, (const float *)nullptr, F.x, (double *)nullptr,
@@ -605,11 +613,20 @@ void launch_mg_vcycle(MgHier &h, const double *r, double *z, float omega, DevSca
         const MgLevel &Cl = h.lev[l + 1];
         const unsigned gl = mg_blocks((long)nr * F.nt);
         if (l == 0) {
-            hipLaunchKernelGGL((k_mg_resid<double>), dim3(mg_blocks(F.n)), dim3(kMB), 0, st, nr, F, Cl.nt, r,
+            hipLaunchKernelGGL((k_mg_resid<RT>), dim3(mg_blocks(F.n)), dim3(kMB), 0, st, nr, F, Cl.nt, r,
                                (const float *)F.x, xc, F.x2, F.b, csc);
-            hipLaunchKernelGGL((k_mg_line<false, float, true>), dim3(gl), dim3(kMB), 0, st, nr, F,
-                               (const float *)F.b, (const float *)F.x2, (float *)nullptr, z, r, omega, h.part,
-                               h.cnt, sc, restart);
+            bool wrote = false;
+            if constexpr (std::is_same<RT, double>::value)
+                if (z64) {
+                    hipLaunchKernelGGL((k_mg_line<false, float, true>), dim3(gl), dim3(kMB), 0, st, nr, F,
+                                       (const float *)F.b, (const float *)F.x2, (float *)nullptr, z64, r, omega,
+                                       h.part, h.cnt, sc, restart);
+                    wrote = true;
+                }
+            if (!wrote)
+                hipLaunchKernelGGL((k_mg_line<false, float, false>), dim3(gl), dim3(kMB), 0, st, nr, F,
+                                   (const float *)F.b, (const float *)F.x2, z32, (double *)nullptr,
+                                   (const double *)nullptr, omega, (double *)nullptr, (unsigned *)nullptr, sc, 0);
         } else {
             hipLaunchKernelGGL((k_mg_resid<float>), dim3(mg_blocks(F.n)), dim3(kMB), 0, st, nr, F, Cl.nt,
                                (const float *)F.b, (const float *)F.x, xc, F.x2, F.dp, csc);
@@ -619,6 +636,17 @@ void launch_mg_vcycle(MgHier &h, const double *r, double *z, float omega, DevSca
             xc = F.x;
         }
     }
+}
+
+void launch_mg_vcycle(MgHier &h, const double *r, double *z, float omega, DevScalars *sc, int restart,
+                      hipStream_t st)
+{
+    mg_vcycle<double>(h, r, z, nullptr, omega, sc, restart, st);
+}
+
+void launch_mg_vcycle32(MgHier &h, const float *r, float *z, float omega, DevScalars *sc, hipStream_t st)
+{
+    mg_vcycle<float>(h, r, nullptr, z, omega, sc, 0, st);
 }
 
 }  // namespace rt

@@ -1187,6 +1187,81 @@ rt_status solve_fp64_mg(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
     return status;
 }
 
+// Flexible CG in float32 preconditioned by one V-cycle per iteration (the float32
+// machinery of the learned mode: float64 dots, float64 reliable updates whenever r.r
+// has fallen a hundredfold); a non-finite float32 state hands the solve to the float64
+// multigrid CG from the last reliable iterate.
+rt_status solve_mixed_mg(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb)
+{
+    const Dims &d = ctx->d;
+    hipStream_t s = ctx->stream;
+    DevScalars *h = ctx->h_sc;
+    if (rt_status e = mg_prepare(ctx)) return e;
+    MgHier &mg = *ctx->mg;
+    const double delta2 = 0.01;
+    h->iters = 0;
+    h->done = 0;
+    h->beta = 0.0;
+    h->thresh2 = o->tol * o->tol * bb;
+    if (rt_status e = write_scalars(ctx)) return e;
+    launch_resid(d, ctx->nblk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials, ctx->counter, ctx->sc, 0, s);
+    launch_reliable(d, ctx->nblk, ctx->r, ctx->r32, ctx->x32, ctx->partials, ctx->counter, ctx->sc, 1, s);
+    if (rt_status e = read_scalars(ctx)) return e;
+    double res = std::sqrt(h->res2 / bb), rr_ref = h->res2;
+    float *pold = ctx->p32a, *pnew = ctx->p32b;
+    rt_status status = RT_OK;
+    bool nonfinite = false;
+    int applies = 0;
+    for (;;) {
+        st->relres = res;
+        if (!isfin(res)) { nonfinite = true; break; }
+        if (res <= o->tol) break;
+        if (h->iters >= o->max_iter) { status = RT_ENOCONV; break; }
+        const bool sample = applies % 8 == 0;
+        if (sample) (void)hipEventRecord(ctx->ev[8], s);
+        launch_mg_vcycle32(mg, ctx->r32, ctx->z32, kMgOmega, ctx->sc, s);
+        applies++;
+        if (applies > 1) launch_fcg_beta(d, ctx->nblk, ctx->z32, ctx->q32, ctx->partials, ctx->counter, ctx->sc, s);
+        if (sample) (void)hipEventRecord(ctx->ev[11], s);
+        launch_fcg_dir(d, ctx->nblk, ctx->ahat32, ctx->z32, pold, ctx->r32, pnew, ctx->q32, ctx->partials,
+                       ctx->counter, ctx->sc, s);
+        if (sample) (void)hipEventRecord(ctx->ev[9], s);
+        launch_cg_upd32(d, ctx->nblk_upd, ctx->x32, pnew, ctx->r32, ctx->q32, ctx->partials, ctx->counter, ctx->sc, s);
+        if (sample) (void)hipEventRecord(ctx->ev[10], s);
+        std::swap(pold, pnew);
+        RT_HIP(ctx, hipGetLastError());
+        if (rt_status e = read_scalars(ctx)) return e;
+        if (sample) add_kernel_sample(ctx, st, true);
+        if (!isfin(h->rr) || !isfin(h->alpha)) { nonfinite = true; break; }
+        if (h->done || h->rr <= delta2 * rr_ref || h->iters >= o->max_iter) {
+            launch_fold(d.n, ctx->x32, ctx->y, s);
+            launch_resid(d, ctx->nblk, ctx->ahat, ctx->bhat, ctx->y, ctx->r, ctx->partials, ctx->counter,
+                         ctx->sc, 0, s);
+            launch_reliable(d, ctx->nblk, ctx->r, ctx->r32, ctx->x32, ctx->partials, ctx->counter, ctx->sc, 0, s);
+            RT_HIP(ctx, hipGetLastError());
+            if (rt_status e = read_scalars(ctx)) return e;
+            res = std::sqrt(h->res2 / bb);
+            rr_ref = h->res2;
+            st->outer_iters++;
+        }
+    }
+    st->iters = h->iters;
+    st->precond_applies = applies;
+    if (nonfinite) {
+        if (rt_status e = reset_directions(ctx)) return e;
+        st->fallback = 1;
+        rt_solve_stats s64{};
+        rt_solve_opts o64 = *o;
+        o64.mode = RT_SOLVE_FP64;
+        o64.max_iter = std::max(1, o->max_iter - st->iters);
+        status = solve_fp64_mg(ctx, &o64, &s64, bb);
+        st->iters += s64.iters;
+        st->precond_applies += s64.precond_applies;
+        st->relres = s64.relres;
+    }
+    return status;
+}
+
 rt_status solve_gmres(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb, rt_net *net = nullptr,
                       int budget = 0, int *out = nullptr);
 
@@ -1466,8 +1541,10 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
     RT_CHECK(ctx, o->inner == RT_INNER_FCG || o->inner == RT_INNER_FGMRES, "inner must be an rt_inner value");
     RT_CHECK(ctx, o->launch >= RT_LAUNCH_AUTO && o->launch <= RT_LAUNCH_BLOCK,
              "rt_fld_solve: launch must be an rt_launch value");
-    RT_CHECK(ctx, o->precond == 0 || ((o->precond == 1 || o->precond == 2) && o->mode == RT_SOLVE_FP64 && !o->reduce),
-             "precond = 1 (radial-line block Jacobi) and 2 (multigrid) need RT_SOLVE_FP64 without reduce");
+    RT_CHECK(ctx, o->precond == 0 || (o->precond == 1 && o->mode == RT_SOLVE_FP64 && !o->reduce) ||
+                      (o->precond == 2 && (o->mode == RT_SOLVE_FP64 || o->mode == RT_SOLVE_MIXED) && !o->reduce),
+             "precond = 1 (radial-line block Jacobi) needs RT_SOLVE_FP64, precond = 2 (multigrid) RT_SOLVE_FP64 "
+             "or RT_SOLVE_MIXED, both without reduce");
     rt_solve_stats local{};
     rt_solve_stats *S = st ? st : &local;
     *S = rt_solve_stats{};
@@ -1484,6 +1561,7 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
     const bool rb = o->reduce && rb_possible(ctx);
     if (o->mode == RT_SOLVE_FP64 && o->precond == 1) status = solve_fp64_line(ctx, o, S, bb);
     else if (o->mode == RT_SOLVE_FP64 && o->precond == 2) status = solve_fp64_mg(ctx, o, S, bb);
+    else if (o->mode == RT_SOLVE_MIXED && o->precond == 2) status = solve_mixed_mg(ctx, o, S, bb);
     else if (o->mode == RT_SOLVE_FP64) status = rb ? solve_fp64_rb(ctx, o, S, bb) : solve_fp64(ctx, o, S, bb);
     else if (o->mode == RT_SOLVE_MIXED) status = rb ? solve_mixed_rb(ctx, o, S, bb) : solve_mixed(ctx, o, S, bb);
     else if (o->mode == RT_SOLVE_GMRES) status = solve_gmres(ctx, o, S, bb);

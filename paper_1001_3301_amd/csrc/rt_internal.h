@@ -322,6 +322,8 @@ void mg_shapes(int nt, int np, std::vector<std::pair<int, int>> &out);
 void launch_mg_setup(MgHier &h, const double *ahat, const double *s, hipStream_t st);
 void launch_mg_vcycle(MgHier &h, const double *r, double *z, float omega, DevScalars *sc, int restart,
                       hipStream_t st);
+// The same cycle on a float32 residual, z in float32 (no dot).
+void launch_mg_vcycle32(MgHier &h, const float *r, float *z, float omega, DevScalars *sc, hipStream_t st);
 void launch_f2d(long n, const float *x, double *y, hipStream_t st);
 // The rest of a preconditioned CG iteration once z = M^-1 r and beta are known.
 void launch_pcg_dir_upd(const Dims &d, int nblk, int nblk_upd, const double *a, const double *z, double *y, double *r,

@@ -151,12 +151,36 @@ def test_multigrid_solve_on_a_clumpy_grid_meets_the_oracle_residual():
     assert 10 * st["iters"] <= st2["iters"]
 
 
+@pytest.mark.parametrize("case", ["ragged-61x13x5-nu61", "axisym-64x16x1-nu32", "phi3-20x7x3", "line-33x1x1"])
+def test_float32_multigrid_solve_against_dense_oracle(case):
+    """Flexible CG in float32 with one V-cycle per iteration and float64 reliable updates
+    (RT_SOLVE_MIXED, precond = 2) to 1e-10 (the bounds of the mixed solve's own test):
+    the oracle's residual of the answer, the temperature of Eq. 16 within 1e-8 of the
+    oracle's dense solve, and no more iterations than the float64 multigrid CG needs
+    plus a fifth."""
+    from paper_1001_3301_amd import rt
+    wl = CASES[case]()
+    P, ctx, T, S, En, ref, sysv = _system(wl)
+    E = _d(En)
+    rc, st = ctx.solve(E, rt.solve_opts(rt.MODE_MIXED, tol=1e-10, max_iter=2000, precond=rt.PRECOND_MG))
+    E2 = _d(En)
+    rc2, st2 = ctx.solve(E2, rt.solve_opts(rt.MODE_FP64, tol=1e-10, max_iter=2000, precond=rt.PRECOND_MG))
+    yd = P.dense_solve(ref["ahat"], ref["bhat"])
+    print(f"{case}: float32 FCG {st['iters']} iterations ({st['outer_iters']} reliable updates), "
+          f"float64 CG {st2['iters']}")
+    assert st["relres"] <= 1e-10 and st["fallback"] == 0
+    assert st["precond_applies"] == st["iters"]
+    assert P.relres(ref["ahat"], ref["bhat"], _h(E) / ref["s"]) <= 1.01e-10
+    assert rel(P.newton(_h(E), S, T), P.newton(yd * ref["s"], S, T)) < 1e-8
+    assert st["iters"] <= 1.2 * st2["iters"] + 2
+
+
 def test_multigrid_rejects_other_modes():
     from paper_1001_3301_amd import rt
     wl = CASES["phi3-20x7x3"]()
     P, ctx, T, S, En, ref, sysv = _system(wl)
-    for o in (rt.solve_opts(rt.MODE_MIXED, precond=2), rt.solve_opts(rt.MODE_FP64, precond=2, reduce=1),
-              rt.solve_opts(rt.MODE_FP64, precond=3)):
+    for o in (rt.solve_opts(rt.MODE_GMRES, precond=2), rt.solve_opts(rt.MODE_FP64, precond=2, reduce=1),
+              rt.solve_opts(rt.MODE_MIXED, precond=2, reduce=1), rt.solve_opts(rt.MODE_FP64, precond=3)):
         rc, st = ctx.solve(_d(En), o, raise_on_error=False)
         assert rc == rt.RT_EINVAL
     with pytest.raises(Exception):
