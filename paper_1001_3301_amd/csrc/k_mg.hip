@@ -27,6 +27,7 @@
 // so every access of a step is one coalesced row segment.  The set-up runs in float64;
 // the V-cycle stores and computes in float32 (the outer CG keeps float64 vectors, dots
 // and the true residual).
+#include <algorithm>
 #include <type_traits>
 
 #include "rt_internal.h"
@@ -287,31 +288,52 @@ __device__ __forceinline__ double mg_block_sum(double v, double *sh)
     return t;
 }
 
-// r.z over the grid, reduced deterministically (block partials summed in block order by
-// the last block to finish), then the preconditioned CG scalars: beta = r.z / r.z_prev
-// (0 after a restart), rr = r.z for the direction kernel.
-__device__ __forceinline__ void mg_finish_dot(double acc, double *partials, unsigned *counter, DevScalars *sc,
-                                              int restart)
+// Two float64 sums over the grid, reduced deterministically: block partials (pairs)
+// summed in block order by the last block to finish, which returns true (totals valid
+// in thread 0) and clears the counter for the next use.
+__device__ __forceinline__ bool mg_reduce2(double a, double b, double *partials, unsigned *counter, double *ta,
+                                           double *tb)
 {
     __shared__ double sh[kMB / 64];
     __shared__ int s_last;
-    const double bs = mg_block_sum(acc, sh);
+    const double ba = mg_block_sum(a, sh), bb = mg_block_sum(b, sh);
     if (threadIdx.x == 0) {
-        partials[blockIdx.x] = bs;
+        partials[2 * blockIdx.x] = ba;
+        partials[2 * blockIdx.x + 1] = bb;
         __threadfence();
         const unsigned prev = atomicAdd(counter, 1u);
         s_last = prev == gridDim.x - 1;
     }
     __syncthreads();
-    if (!s_last) return;
+    if (!s_last) return false;
     __threadfence();
-    double a = 0.0;
-    for (int t = threadIdx.x; t < (int)gridDim.x; t += kMB) a += partials[t];
-    a = mg_block_sum(a, sh);
+    double x = 0.0, y = 0.0;
+    for (int t = threadIdx.x; t < (int)gridDim.x; t += kMB) {
+        x += partials[2 * t];
+        y += partials[2 * t + 1];
+    }
+    x = mg_block_sum(x, sh);
+    y = mg_block_sum(y, sh);
     if (threadIdx.x == 0) {
-        sc->beta = (restart || !(sc->rr > 0.0)) ? 0.0 : a / sc->rr;
-        sc->rr = a;
+        *ta = x;
+        *tb = y;
         *counter = 0u;
+    }
+    return true;
+}
+
+// The outer CG's scalars from r.z and z.q_old: rr = r.z (alpha = rr / p.q in the
+// direction kernel) and the flexible-CG beta = -(z.q_old) / (p_old.q_old) (0 after a
+// restart), which equals the classical r.z / r.z_prev for a fixed preconditioner and
+// keeps the directions conjugate when the preconditioner varies (the K-cycle's inner
+// Krylov steps make it nonlinear).
+__device__ __forceinline__ void mg_finish_dot(double rz, double zq, double *partials, unsigned *counter,
+                                              DevScalars *sc, int restart)
+{
+    double a, b;
+    if (mg_reduce2(rz, zq, partials, counter, &a, &b) && threadIdx.x == 0) {
+        sc->beta = (restart || !(sc->pq != 0.0)) ? 0.0 : -b / sc->pq;
+        sc->rr = a;
     }
 }
 
@@ -328,15 +350,16 @@ constexpr int kMU = 8;
 template <bool ZERO, typename BT, bool DOT>
 __global__ __launch_bounds__(kMB) void k_mg_line(int nr, MgLevel L, const BT *rhs, const float *__restrict__ xin,
                                                  float *__restrict__ xout, double *__restrict__ z,
-                                                 const double *__restrict__ r, float omega, double *partials,
-                                                 unsigned *counter, DevScalars *sc, int restart)
+                                                 const double *__restrict__ r, const double *__restrict__ qold,
+                                                 float omega, double *partials, unsigned *counter, DevScalars *sc,
+                                                 int restart)
 {
     if (sc && sc->done) return;
     const long lines = (long)nr * L.nt;
     const long line = (long)blockIdx.x * kMB + threadIdx.x;
     const int m = L.np;
     const long plane = lines;
-    double acc = 0.0;
+    double acc = 0.0, acq = 0.0;
     if (line < lines) {
         const float *__restrict__ im = L.im;
         const float *__restrict__ cp = L.cp;
@@ -375,7 +398,7 @@ __global__ __launch_bounds__(kMB) void k_mg_line(int nr, MgLevel L, const BT *rh
         float y = 0.0f;
         for (int k0 = m - 1; k0 >= 0; k0 -= kMU) {
             float dv[kMU], cv[kMU], qv[kMU], xv[kMU];
-            double rr[kMU];
+            double rr[kMU], qo[kMU];
 #pragma unroll
             for (int u = 0; u < kMU; u++) {
                 const int k = k0 - u;
@@ -386,6 +409,7 @@ __global__ __launch_bounds__(kMB) void k_mg_line(int nr, MgLevel L, const BT *rh
                     qv[u] = sm ? qf[c] : 0.0f;
                     xv[u] = ZERO ? 0.0f : xin[c];
                     rr[u] = DOT ? r[c] : 0.0;
+                    qo[u] = DOT ? qold[c] : 0.0;
                 }
             }
 #pragma unroll
@@ -399,6 +423,7 @@ __global__ __launch_bounds__(kMB) void k_mg_line(int nr, MgLevel L, const BT *rh
                     if (DOT) {
                         z[c] = (double)xn;
                         acc += rr[u] * (double)xn;
+                        acq += qo[u] * (double)xn;
                     } else {
                         xout[c] = xn;
                     }
@@ -406,7 +431,7 @@ __global__ __launch_bounds__(kMB) void k_mg_line(int nr, MgLevel L, const BT *rh
             }
         }
     }
-    if (DOT) mg_finish_dot(acc, partials, counter, sc, restart);
+    if (DOT) mg_finish_dot(acc, acq, partials, counter, sc, restart);
 }
 
 // rhs = b - A x' on one level, one cell per thread, where x' = x + P xc: the coarse
@@ -518,6 +543,83 @@ __global__ __launch_bounds__(kMB) void k_mg_out_line(int nr, const float *__rest
     }
 }
 
+// ------------------------------------------------- K-cycle: flexible CG on a level
+
+// The coarse correction of a K-cycle level is two steps of flexible CG on A_l, each
+// preconditioned by the cycle from that level (Notay's K-cycle): x = alpha_1 p_1 +
+// alpha_2 p_2 with p_1 = z_1, p_2 = z_2 + beta p_1, beta = -(z_2.q_1) / (p_1.q_1), q =
+// A_l p, alpha = (p.r) / (p.q), r the level's residual.  Float32 vectors, float64
+// dots; the scalars stay on the device (ks[0] = p.q, ks[1] = alpha, ks[2] = beta).
+constexpr int kKcBlocks = 1024;  // grid of the K-cycle kernels (grid-stride loops)
+
+// p = z + beta p_old (p = z when FIRST), q = A_l p, then p.q and p.r: alpha.
+template <bool FIRST>
+__global__ __launch_bounds__(kMB) void k_kc_dir(int nr_, MgLevel F, const float *__restrict__ z,
+                                                const float *__restrict__ pold, float *__restrict__ pnew,
+                                                float *__restrict__ q, const float *__restrict__ r, double *ks,
+                                                double *partials, unsigned *counter, const DevScalars *sc)
+{
+    if (sc && sc->done) return;
+    const unsigned nr = nr_, nt = F.nt, np = F.np, n = (unsigned)F.n;
+    const float beta = FIRST ? 0.0f : (float)ks[2];
+    auto pv = [&](unsigned c) { return FIRST ? z[c] : fmaf(beta, pold[c], z[c]); };
+    double apq = 0.0, apr = 0.0;
+    for (unsigned f = blockIdx.x * kMB + threadIdx.x; f < n; f += gridDim.x * kMB) {
+        const unsigned i = f % nr, rest = f / nr;
+        const unsigned j = rest % nt, k = rest / nt;
+        const float p0 = pv(f);
+        float v = (F.dg ? F.dg[f] : 1.0f) * p0;
+        if (i + 1 < nr) v = fmaf(F.ar[f], pv(f + 1), v);
+        if (i > 0) v = fmaf(F.ar[f - 1], pv(f - 1), v);
+        if (j + 1 < nt) v = fmaf(F.at[f], pv(f + nr), v);
+        if (j > 0) v = fmaf(F.at[f - nr], pv(f - nr), v);
+        if (np > 1) {
+            const unsigned kp = k + 1 < np ? k + 1 : 0, km = k > 0 ? k - 1 : np - 1;
+            const unsigned cp1 = i + nr * (j + nt * kp), cm1 = i + nr * (j + nt * km);
+            v = fmaf(F.ap[f], pv(cp1), v);
+            v = fmaf(F.ap[cm1], pv(cm1), v);
+        }
+        pnew[f] = p0;
+        q[f] = v;
+        apq += (double)p0 * (double)v;
+        apr += (double)p0 * (double)r[f];
+    }
+    double pq, pr;
+    if (mg_reduce2(apq, apr, partials, counter, &pq, &pr) && threadIdx.x == 0) {
+        ks[0] = pq;
+        ks[1] = pq != 0.0 ? pr / pq : 0.0;
+    }
+}
+
+// x = alpha p (FIRST) or x += alpha p; r -= alpha q unless LAST.
+template <bool FIRST, bool LAST>
+__global__ __launch_bounds__(kMB) void k_kc_upd(long n_, float *__restrict__ x, const float *__restrict__ p,
+                                                const float *__restrict__ q, float *__restrict__ r, const double *ks,
+                                                const DevScalars *sc)
+{
+    if (sc && sc->done) return;
+    const unsigned n = (unsigned)n_;
+    const float a = (float)ks[1];
+    for (unsigned f = blockIdx.x * kMB + threadIdx.x; f < n; f += gridDim.x * kMB) {
+        x[f] = FIRST ? a * p[f] : fmaf(a, p[f], x[f]);
+        if (!LAST) r[f] = fmaf(-a, q[f], r[f]);
+    }
+}
+
+// beta = -(z.q) / (p.q) for the second step.
+__global__ __launch_bounds__(kMB) void k_kc_beta(long n_, const float *__restrict__ z, const float *__restrict__ q,
+                                                 double *ks, double *partials, unsigned *counter,
+                                                 const DevScalars *sc)
+{
+    if (sc && sc->done) return;
+    const unsigned n = (unsigned)n_;
+    double a = 0.0;
+    for (unsigned f = blockIdx.x * kMB + threadIdx.x; f < n; f += gridDim.x * kMB) a += (double)z[f] * (double)q[f];
+    double zq, unused;
+    if (mg_reduce2(a, 0.0, partials, counter, &zq, &unused) && threadIdx.x == 0)
+        ks[2] = ks[0] != 0.0 ? -zq / ks[0] : 0.0;
+}
+
 // ------------------------------------------------------------------ host side
 
 static unsigned mg_blocks(long n) { return (unsigned)((n + kMB - 1) / kMB); }
@@ -564,89 +666,132 @@ void launch_mg_setup(MgHier &h, const double *ahat, const double *s, hipStream_t
     hipLaunchKernelGGL(k_mg_radial_inverse, dim3(mg_blocks(nr)), dim3(kMB), 0, st, nr, arL, h.cim, h.ccp, h.inv);
 }
 
-// One V-cycle on r (n_0 values): z = M_mg r, either in float64 (z64, with r.z and the
-// preconditioned CG scalars formed on the way, see mg_finish_dot) or in float32 (z32).
+// The cycle as launched: pre-sweep from zero, restriction, the coarse correction
+// (the coarsest solve, a K-cycle step pair on the K levels, else the cycle one level
+// down), the residual with the prolonged correction, post-sweep.
+struct MgRun {
+    MgHier &h;
+    float omega;
+    DevScalars *sc;
+    hipStream_t st;
+};
+
+static void mg_solve_level(MgRun &R, int l, float *b, float *out);
+
+// The cycle from level l >= 1 on b (not modified), result in out.
+static void mg_cycle(MgRun &R, int l, const float *b, float *out)
+{
+    MgHier &h = R.h;
+    const int nr = h.nr;
+    MgLevel &F = h.lev[l];
+    MgLevel &C = h.lev[l + 1];
+    const unsigned gl = mg_blocks((long)nr * F.nt);
+    hipLaunchKernelGGL((k_mg_line<true, float, false>), dim3(gl), dim3(kMB), 0, R.st, nr, F, b, (const float *)nullptr,
+                       F.x, (double *)nullptr, (const double *)nullptr, (const double *)nullptr, R.omega,
+                       (double *)nullptr, (unsigned *)nullptr, R.sc, 0);
+    hipLaunchKernelGGL(k_mg_restrict<float>, dim3(mg_blocks(C.n)), dim3(kMB), 0, R.st, nr, F, C.nt, C.np, b,
+                       (const float *)F.x, C.b, (const DevScalars *)R.sc);
+    mg_solve_level(R, l + 1, C.b, C.xr);
+    hipLaunchKernelGGL((k_mg_resid<float>), dim3(mg_blocks(F.n)), dim3(kMB), 0, R.st, nr, F, C.nt, b,
+                       (const float *)F.x, (const float *)C.xr, F.x2, F.dp, (const DevScalars *)R.sc);
+    hipLaunchKernelGGL((k_mg_line<false, float, false>), dim3(gl), dim3(kMB), 0, R.st, nr, F, (const float *)F.dp,
+                       (const float *)F.x2, out, (double *)nullptr, (const double *)nullptr, (const double *)nullptr,
+                       R.omega, (double *)nullptr, (unsigned *)nullptr, R.sc, 0);
+}
+
+// Two flexible-CG steps on level l with the cycle as preconditioner; b is the level's
+// residual and is updated in place.
+static void mg_kcycle(MgRun &R, int l, float *b, float *out)
+{
+    MgHier &h = R.h;
+    MgLevel &F = h.lev[l];
+    const int nr = h.nr;
+    MgKLevel &K = h.kl[l];
+    const DevScalars *csc = R.sc;
+    const unsigned gk = (unsigned)std::min<long>(mg_blocks(F.n), kKcBlocks);
+    mg_cycle(R, l, b, K.z);
+    hipLaunchKernelGGL(k_kc_dir<true>, dim3(gk), dim3(kMB), 0, R.st, nr, F, (const float *)K.z, (const float *)nullptr,
+                       K.p1, K.q, (const float *)b, K.ks, h.kpart, h.kcnt, csc);
+    hipLaunchKernelGGL((k_kc_upd<true, false>), dim3(gk), dim3(kMB), 0, R.st, F.n, out, (const float *)K.p1,
+                       (const float *)K.q, b, (const double *)K.ks, csc);
+    mg_cycle(R, l, b, K.z);
+    hipLaunchKernelGGL(k_kc_beta, dim3(gk), dim3(kMB), 0, R.st, F.n, (const float *)K.z, (const float *)K.q, K.ks,
+                       h.kpart, h.kcnt, csc);
+    hipLaunchKernelGGL(k_kc_dir<false>, dim3(gk), dim3(kMB), 0, R.st, nr, F, (const float *)K.z,
+                       (const float *)K.p1, K.p2, K.q, (const float *)b, K.ks, h.kpart, h.kcnt, csc);
+    hipLaunchKernelGGL((k_kc_upd<false, true>), dim3(gk), dim3(kMB), 0, R.st, F.n, out, (const float *)K.p2,
+                       (const float *)K.q, b, (const double *)K.ks, csc);
+}
+
+static void mg_solve_level(MgRun &R, int l, float *b, float *out)
+{
+    MgHier &h = R.h;
+    const int L = (int)h.lev.size() - 1;
+    if (l == L)
+        hipLaunchKernelGGL(k_mg_coarse, dim3(h.nr), dim3(kMB), 0, R.st, h.nr, (const double *)h.inv, (const float *)b,
+                           out, (const DevScalars *)R.sc);
+    else if (h.kl[l].z)
+        mg_kcycle(R, l, b, out);
+    else
+        mg_cycle(R, l, b, out);
+}
+
+// The preconditioner on the outer residual r (n_0 values): z = M_mg r, either in float64
+// (z64, with r.z and z.q_old formed on the way for the outer CG, see mg_finish_dot) or
+// in float32 (z32).
 template <typename RT>
-static void mg_vcycle(MgHier &h, const RT *r, double *z64, float *z32, float omega, DevScalars *sc, int restart,
-                      hipStream_t st)
+static void mg_vcycle(MgHier &h, const RT *r, double *z64, const double *qold, float *z32, float omega,
+                      DevScalars *sc, int restart, hipStream_t st)
 {
     const int nr = h.nr;
     const int L = (int)h.lev.size() - 1;
     const DevScalars *csc = sc;
+    MgRun R{h, omega, sc, st};
+    MgLevel &F = h.lev[0];
     if (L == 0) {  // one radial line: the exact solve
-        hipLaunchKernelGGL(k_mg_in<RT>, dim3(mg_blocks(h.lev[0].n)), dim3(kMB), 0, st, h.lev[0].n, r, h.lev[0].b,
+        hipLaunchKernelGGL(k_mg_in<RT>, dim3(mg_blocks(F.n)), dim3(kMB), 0, st, F.n, r, F.b, csc);
+        float *x = z64 ? F.x2 : z32;
+        hipLaunchKernelGGL(k_mg_coarse, dim3(nr), dim3(kMB), 0, st, nr, (const double *)h.inv, (const float *)F.b, x,
                            csc);
-        float *x = z64 ? h.lev[0].x2 : z32;
-        hipLaunchKernelGGL(k_mg_coarse, dim3(nr), dim3(kMB), 0, st, nr, (const double *)h.inv,
-                           (const float *)h.lev[0].b, x, csc);
         if constexpr (std::is_same<RT, double>::value)
             if (z64)
                 hipLaunchKernelGGL(k_mg_out_line, dim3(1), dim3(kMB), 0, st, nr, (const float *)x, r, z64, sc,
                                    restart);
         return;
     }
-    // down: pre-smoothing from zero, restriction of the residual
-    for (int l = 0; l < L; l++) {
-        MgLevel &F = h.lev[l];
-        const MgLevel &Cl = h.lev[l + 1];
-        const unsigned gl = mg_blocks((long)nr * F.nt);
-        if (l == 0) {
-            hipLaunchKernelGGL((k_mg_line<true, RT, false>), dim3(gl), dim3(kMB), 0, st, nr, F, r,
-                               (const float *)nullptr, F.x, (double *)nullptr, (const double *)nullptr, omega,
-                               (double *)nullptr, (unsigned *)nullptr, sc, 0);
-            hipLaunchKernelGGL(k_mg_restrict<RT>, dim3(mg_blocks(Cl.n)), dim3(kMB), 0, st, nr, F, Cl.nt, Cl.np, r,
-                               (const float *)F.x, Cl.b, csc);
-        } else {
-            hipLaunchKernelGGL((k_mg_line<true, float, false>), dim3(gl), dim3(kMB), 0, st, nr, F,
-                               (const float *)F.b, (const float *)nullptr, F.x, (double *)nullptr,
-                               (const double *)nullptr, omega, (double *)nullptr, (unsigned *)nullptr, sc, 0);
-            hipLaunchKernelGGL(k_mg_restrict<float>, dim3(mg_blocks(Cl.n)), dim3(kMB), 0, st, nr, F, Cl.nt, Cl.np,
-                               (const float *)F.b, (const float *)F.x, Cl.b, csc);
+    MgLevel &C = h.lev[1];
+    const unsigned gl = mg_blocks((long)nr * F.nt);
+    hipLaunchKernelGGL((k_mg_line<true, RT, false>), dim3(gl), dim3(kMB), 0, st, nr, F, r, (const float *)nullptr, F.x,
+                       (double *)nullptr, (const double *)nullptr, (const double *)nullptr, omega, (double *)nullptr,
+                       (unsigned *)nullptr, sc, 0);
+    hipLaunchKernelGGL(k_mg_restrict<RT>, dim3(mg_blocks(C.n)), dim3(kMB), 0, st, nr, F, C.nt, C.np, r,
+                       (const float *)F.x, C.b, csc);
+    mg_solve_level(R, 1, C.b, C.xr);
+    hipLaunchKernelGGL((k_mg_resid<RT>), dim3(mg_blocks(F.n)), dim3(kMB), 0, st, nr, F, C.nt, r, (const float *)F.x,
+                       (const float *)C.xr, F.x2, F.b, csc);
+    bool wrote = false;
+    if constexpr (std::is_same<RT, double>::value)
+        if (z64) {
+            hipLaunchKernelGGL((k_mg_line<false, float, true>), dim3(gl), dim3(kMB), 0, st, nr, F, (const float *)F.b,
+                               (const float *)F.x2, (float *)nullptr, z64, r, qold, omega, h.part, h.cnt, sc,
+                               restart);
+            wrote = true;
         }
-    }
-    hipLaunchKernelGGL(k_mg_coarse, dim3(nr), dim3(kMB), 0, st, nr, (const double *)h.inv, (const float *)h.lev[L].b,
-                       h.lev[L].x2, csc);
-    // up: the residual with the prolonged correction, then post-smoothing from it
-    const float *xc = h.lev[L].x2;  // the coarser level's result
-    for (int l = L - 1; l >= 0; l--) {
-        MgLevel &F = h.lev[l];
-        const MgLevel &Cl = h.lev[l + 1];
-        const unsigned gl = mg_blocks((long)nr * F.nt);
-        if (l == 0) {
-            hipLaunchKernelGGL((k_mg_resid<RT>), dim3(mg_blocks(F.n)), dim3(kMB), 0, st, nr, F, Cl.nt, r,
-                               (const float *)F.x, xc, F.x2, F.b, csc);
-            bool wrote = false;
-            if constexpr (std::is_same<RT, double>::value)
-                if (z64) {
-                    hipLaunchKernelGGL((k_mg_line<false, float, true>), dim3(gl), dim3(kMB), 0, st, nr, F,
-                                       (const float *)F.b, (const float *)F.x2, (float *)nullptr, z64, r, omega,
-                                       h.part, h.cnt, sc, restart);
-                    wrote = true;
-                }
-            if (!wrote)
-                hipLaunchKernelGGL((k_mg_line<false, float, false>), dim3(gl), dim3(kMB), 0, st, nr, F,
-                                   (const float *)F.b, (const float *)F.x2, z32, (double *)nullptr,
-                                   (const double *)nullptr, omega, (double *)nullptr, (unsigned *)nullptr, sc, 0);
-        } else {
-            hipLaunchKernelGGL((k_mg_resid<float>), dim3(mg_blocks(F.n)), dim3(kMB), 0, st, nr, F, Cl.nt,
-                               (const float *)F.b, (const float *)F.x, xc, F.x2, F.dp, csc);
-            hipLaunchKernelGGL((k_mg_line<false, float, false>), dim3(gl), dim3(kMB), 0, st, nr, F,
-                               (const float *)F.dp, (const float *)F.x2, F.x, (double *)nullptr,
-                               (const double *)nullptr, omega, (double *)nullptr, (unsigned *)nullptr, sc, 0);
-            xc = F.x;
-        }
-    }
+    if (!wrote)
+        hipLaunchKernelGGL((k_mg_line<false, float, false>), dim3(gl), dim3(kMB), 0, st, nr, F, (const float *)F.b,
+                           (const float *)F.x2, z32, (double *)nullptr, (const double *)nullptr,
+                           (const double *)nullptr, omega, (double *)nullptr, (unsigned *)nullptr, sc, 0);
 }
 
-void launch_mg_vcycle(MgHier &h, const double *r, double *z, float omega, DevScalars *sc, int restart,
-                      hipStream_t st)
+void launch_mg_vcycle(MgHier &h, const double *r, double *z, const double *qold, float omega, DevScalars *sc,
+                      int restart, hipStream_t st)
 {
-    mg_vcycle<double>(h, r, z, nullptr, omega, sc, restart, st);
+    mg_vcycle<double>(h, r, z, qold, nullptr, omega, sc, restart, st);
 }
 
 void launch_mg_vcycle32(MgHier &h, const float *r, float *z, float omega, DevScalars *sc, hipStream_t st)
 {
-    mg_vcycle<float>(h, r, nullptr, z, omega, sc, 0, st);
+    mg_vcycle<float>(h, r, nullptr, nullptr, z, omega, sc, 0, st);
 }
 
 }  // namespace rt

@@ -1048,6 +1048,7 @@ rt_status solve_fp64_line(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *s
 // the grid's theta and phi sizes down to one radial line), set up once per assembled
 // system.
 constexpr float kMgOmega = 0.8f;  // damping of the phi-line block-Jacobi smoother
+constexpr int kMgKLevels = 2;      // levels 1 .. kMgKLevels take K-cycle steps (when not the last)
 
 rt_status mg_prepare(rt_ctx *ctx)
 {
@@ -1105,11 +1106,21 @@ rt_status mg_prepare(rt_ctx *ctx)
             }
             v.b = f32(v.n);
             v.x2 = f32(v.n);
+            if (l > 0) v.xr = f32(v.n);
         }
+        h->kl.resize(L + 1);
+        for (int l = 1; l <= kMgKLevels && l < L && ok; l++) {
+            const long nl = h->lev[l].n;
+            h->kl[l] = MgKLevel{f32(nl), f32(nl), f32(nl), f32(nl), f64(4)};
+        }
+        h->kpart = f64(2 * 1024);
+        h->kcnt = dalloc<unsigned>(ctx, 1);
+        ok = ok && h->kcnt;
+        if (h->kcnt && hipMemset(h->kcnt, 0, sizeof(unsigned)) != hipSuccess) ok = false;
         h->B0 = f64(d.n);
         h->t64a = f64(d.n);
         h->t64b = f64(d.n);
-        h->part = f64((long)((d.nr * (long)d.nt + 255) / 256));
+        h->part = f64(2 * (long)((d.nr * (long)d.nt + 255) / 256));  // pairs, one per line-sweep block
         h->cnt = dalloc<unsigned>(ctx, 1);
         ok = ok && h->cnt;
         if (h->cnt && hipMemset(h->cnt, 0, sizeof(unsigned)) != hipSuccess) ok = false;
@@ -1131,8 +1142,8 @@ rt_status mg_prepare(rt_ctx *ctx)
     return RT_OK;
 }
 
-// Float64 CG preconditioned by one multigrid V-cycle per iteration (float32 inside the
-// cycle; the iteration's dots, vectors and the true residual stay float64).
+// Float64 flexible CG preconditioned by one multigrid cycle per iteration (float32 inside
+// the cycle; the iteration's dots, vectors and the true residual stay float64).
 rt_status solve_fp64_mg(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st, double bb)
 {
     const Dims &d = ctx->d;
@@ -1162,7 +1173,7 @@ rt_status solve_fp64_mg(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
         for (int k = 0; k < m; k++) {
             const hipEvent_t *ev = k == 0 ? &ctx->ev[8] : nullptr;
             if (ev) (void)hipEventRecord(ev[0], s);
-            launch_mg_vcycle(mg, ctx->r, ctx->mg_z, kMgOmega, ctx->sc, restart && k == 0, s);
+            launch_mg_vcycle(mg, ctx->r, ctx->mg_z, ctx->qv, kMgOmega, ctx->sc, restart && k == 0, s);
             if (ev) (void)hipEventRecord(ev[3], s);
             launch_pcg_dir_upd(d, ctx->nblk, ctx->nblk_upd, ctx->ahat, ctx->mg_z, ctx->y, ctx->r, pold, pnew, ctx->qv,
                                ctx->partials, ctx->counter, ctx->sc, s, ev);
@@ -1840,7 +1851,7 @@ rt_status rt_mg_apply(rt_ctx *ctx, const double *r, double *z)
     ctx->h_sc->done = 0;
     ctx->h_sc->rr = 0.0;
     if (rt_status e = write_scalars(ctx)) return e;
-    launch_mg_vcycle(*ctx->mg, r, z, kMgOmega, ctx->sc, 1, ctx->stream);
+    launch_mg_vcycle(*ctx->mg, r, z, ctx->qv, kMgOmega, ctx->sc, 1, ctx->stream);
     RT_HIP(ctx, hipGetLastError());
     return RT_OK;
 }

@@ -201,14 +201,25 @@ struct MgLevel {
     const float *w = nullptr, *im = nullptr, *cp = nullptr, *q = nullptr, *g = nullptr;
     const float *rho = nullptr, *kap = nullptr;
     float *b = nullptr, *x = nullptr, *x2 = nullptr, *dp = nullptr;
+    float *xr = nullptr;  // the level's coarse-correction result (levels 1 .. L)
 };
 
 struct MgLevel64 {
     double *dg = nullptr, *ar = nullptr, *at = nullptr, *ap = nullptr, *B = nullptr;
 };
 
+// A level with K-cycle steps (two flexible-CG steps per coarse correction): its
+// search vectors and device scalars (p.q, alpha, beta); z is null on other levels.
+struct MgKLevel {
+    float *z = nullptr, *p1 = nullptr, *p2 = nullptr, *q = nullptr;
+    double *ks = nullptr;
+};
+
 struct MgHier {
     int nr = 0;
+    std::vector<MgKLevel> kl;    // per level (K-cycle buffers where used)
+    double *kpart = nullptr;     // K-cycle reduction partials (pairs)
+    unsigned *kcnt = nullptr;    // their counter (0 between uses)
     std::vector<MgLevel> lev;    // 0 .. L (L: one radial line)
     std::vector<MgLevel64> d64;  // levels 1 .. L in float64 (entry l - 1), built by the set-up
     std::vector<float *> dg32, ar32, at32, ap32;                // levels 1 .. L in float32 (entry l - 1)
@@ -316,12 +327,12 @@ void launch_scale_into(long n, const double *x, double s, double *y, hipStream_t
 void launch_d2f(long n, const double *x, float *y, hipStream_t st);
 // Multigrid: the level shapes (theta, phi sizes from the finest to one radial line),
 // the set-up of a system (float64 Galerkin levels, line factors, coarsest inverse) and
-// one V-cycle on r: z = M_mg r, with r.z and the CG scalars beta (0 when restart) and rr
-// = r.z written to sc (whose kernels do nothing once sc->done is set).
+// one cycle on r: z = M_mg r, with rr = r.z and the flexible-CG beta = -(z.qold) / pq
+// (0 when restart) written to sc (whose kernels do nothing once sc->done is set).
 void mg_shapes(int nt, int np, std::vector<std::pair<int, int>> &out);
 void launch_mg_setup(MgHier &h, const double *ahat, const double *s, hipStream_t st);
-void launch_mg_vcycle(MgHier &h, const double *r, double *z, float omega, DevScalars *sc, int restart,
-                      hipStream_t st);
+void launch_mg_vcycle(MgHier &h, const double *r, double *z, const double *qold, float omega, DevScalars *sc,
+                      int restart, hipStream_t st);
 // The same cycle on a float32 residual, z in float32 (no dot).
 void launch_mg_vcycle32(MgHier &h, const float *r, float *z, float omega, DevScalars *sc, hipStream_t st);
 void launch_f2d(long n, const float *x, double *y, hipStream_t st);

@@ -13,8 +13,12 @@ itself, independently of the HIP code, so that its pieces can be compared one by
   sum of B_f^2 over the aggregate.  Coarsening stops at a single radial line.
 * smoother: damped block Jacobi on phi lines (the diagonal and phi couplings of each
   (r, theta) line, periodic), x <- x + omega M^-1 (b - A x).
-* V-cycle: pre-smoothing from zero, the residual restricted by P^T, the coarse cycle,
-  its correction prolonged by P, post-smoothing; the coarsest line is solved exactly.
+* cycle: pre-smoothing from zero, the residual restricted by P^T, the coarse
+  correction, prolonged by P, post-smoothing; the coarsest line is solved exactly.  The
+  coarse correction of levels 1 and 2 (the K levels, when not the last) is two steps of
+  flexible CG on that level preconditioned by the cycle from it (Notay's K-cycle):
+  x = a1 p1 + a2 p2, p1 = z1, p2 = z2 + beta p1, beta = -(z2.q1)/(p1.q1), q = A p,
+  a = (p.r)/(p.q); elsewhere the cycle one level down (a V-cycle).
 
 Arrays are (n_phi, n_theta, n_r), r fastest, as the device layout.
 """
@@ -173,7 +177,7 @@ def radial_solve(lv, b):
 
 
 class Hierarchy:
-    def __init__(self, shape, ahat, s, omega=0.8, dtype=np.float64):
+    def __init__(self, shape, ahat, s, omega=0.8, dtype=np.float64, klevels=(1, 2)):
         nr, nt, nph = shape
         n = nr * nt * nph
         a = np.asarray(ahat, dtype=np.float64).reshape(3, nph, nt, nr)
@@ -189,6 +193,7 @@ class Hierarchy:
             self.w.append(w)
         self.omega = omega
         self.dtype = dtype
+        self.klevels = tuple(l for l in klevels if 0 < l < len(self.levels) - 1)
         if dtype != np.float64:
             cast = lambda d: {k: (v.astype(dtype) if isinstance(v, np.ndarray) else v) for k, v in d.items()}
             self.levels = [cast(l) for l in self.levels]
@@ -213,12 +218,34 @@ class Hierarchy:
         return self.w[l] * _up(_up(xc, 1, ft, ntf), 0, fp, npf)
 
     def vcycle(self, b, l=0):
+        """The cycle from level l on b."""
         if l == len(self.levels) - 1:
             return radial_solve(self.levels[l], b).astype(self.dtype)
         x = self.smooth(l, None, b)
         bc = self.restrict(l, b - spmv(self.levels[l], x))
-        x = x + self.prolong(l, self.vcycle(bc, l + 1))
+        xc = self.kstep(l + 1, bc) if (l + 1) in self.klevels else self.vcycle(bc, l + 1)
+        x = x + self.prolong(l, xc)
         return self.smooth(l, x, b)
+
+    def kstep(self, l, b):
+        """Two flexible-CG steps on level l, each preconditioned by the cycle from l."""
+        lv = self.levels[l]
+        dot = lambda u, v: float(np.sum(u.astype(np.float64) * v.astype(np.float64)))
+        r = b.copy()
+        z = self.vcycle(r, l)
+        p = z
+        q = spmv(lv, p)
+        pq = dot(p, q)
+        a = self.dtype(dot(p, r) / pq)
+        x = a * p
+        r = r - a * q
+        z = self.vcycle(r, l)
+        beta = self.dtype(-dot(z, q) / pq)
+        p = z + beta * p
+        q = spmv(lv, p)
+        pq = dot(p, q)
+        a = self.dtype(dot(p, r) / pq)
+        return x + a * p
 
     def apply(self, r):
         """z = M_mg r for a flat residual (r fastest)."""

@@ -124,9 +124,10 @@ def test_line_solve_is_the_inverse_of_the_phi_line_matrix(nph):
 
 @pytest.mark.parametrize("shape", [(6, 4, 8), (5, 7, 5), (7, 6, 1)])
 def test_vcycle_is_symmetric_positive_definite(shape):
-    """CG needs a symmetric positive definite preconditioner: u.M v = v.M u, u.M u > 0."""
+    """Without K-cycle steps the cycle is a fixed linear operator, and CG needs it
+    symmetric positive definite: u.M v = v.M u, u.M u > 0."""
     a, s = _random_operator(shape, 9)
-    H = mg_ref.Hierarchy(shape, a, s)
+    H = mg_ref.Hierarchy(shape, a, s, klevels=())
     r = _rng(10)
     n = int(np.prod(shape))
     for _ in range(4):
@@ -134,6 +135,28 @@ def test_vcycle_is_symmetric_positive_definite(shape):
         Mu, Mv = H.apply(u), H.apply(v)
         assert abs(u @ Mv - v @ Mu) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(Mv)
         assert u @ Mu > 0
+
+
+@pytest.mark.parametrize("shape", [(6, 16, 8), (5, 9, 12)])
+def test_kcycle_step_is_the_galerkin_projection_on_its_two_directions(shape):
+    """Two CG steps with a fixed SPD preconditioner M from zero give the A-orthogonal
+    projection of A^-1 b on span{z1, z2} (z1 = M b, z2 = M (b - a1 A z1)): checked against
+    the 2 x 2 Galerkin system solved densely, on a level whose own cycle is linear (the
+    K level's preconditioner is the V-cycle below it)."""
+    a, s = _random_operator(shape, 13)
+    H = mg_ref.Hierarchy(shape, a, s, klevels=(1,))
+    assert H.klevels == (1,)
+    lv = H.levels[1]
+    A = _csr(lv).toarray()
+    b = _rng(14).standard_normal(lv["dg"].shape)
+    x = H.kstep(1, b)
+    M = lambda v: H.vcycle(v, 1)
+    z1 = M(b)
+    a1 = (z1.ravel() @ b.ravel()) / (z1.ravel() @ A @ z1.ravel())
+    z2 = M(b - a1 * (A @ z1.ravel()).reshape(b.shape))
+    V = np.stack([z1.ravel(), z2.ravel()], axis=1)
+    c = np.linalg.solve(V.T @ A @ V, V.T @ b.ravel())
+    assert np.allclose(x.ravel(), V @ c, rtol=1e-10, atol=1e-12 * np.abs(V @ c).max())
 
 
 def test_vcycle_on_one_radial_line_is_the_exact_solve():
@@ -157,10 +180,26 @@ def _pcg(A, b, M, tol=1e-8, maxit=3000):
     return maxit, x
 
 
+def _fcg(A, b, M, tol=1e-8, maxit=3000):
+    """Flexible CG (beta = -(z.q_old)/(p_old.q_old)), as the solver runs it."""
+    x = np.zeros_like(b); r = b.copy(); bn = np.linalg.norm(b); p = q = pq = None
+    for it in range(1, maxit + 1):
+        z = M(r)
+        p = z.copy() if p is None else z - (z @ q) / pq * p
+        q = A @ p
+        pq = p @ q
+        al = (p @ r) / pq
+        x += al * p; r -= al * q
+        if np.linalg.norm(r) <= tol * bn:
+            return it, x
+    return maxit, x
+
+
 def test_cg_with_the_vcycle_on_an_oracle_system():
     """On the system the oracle assembles for a clumpy 32 x 16 x 32 grid, CG with one
     V-cycle per iteration meets 1e-8 in at most 25 iterations (Jacobi CG takes about ten
-    times as many), in float64 and with the cycle in float32."""
+    times as many), in float64 and with the cycle in float32; flexible CG with the
+    K-cycle in at most 15."""
     import oracle
     from paper_1001_3301_amd import synth as sy
     shape = (32, 16, 32)
@@ -172,13 +211,18 @@ def test_cg_with_the_vcycle_on_an_oracle_system():
     To = P.newton(np.full(P.n, sy.A_RAD * wl.T_bc ** 4), So, To)
     qo, So, _ = P.raytrace(rh, To, want_faces=False)
     out = P.assemble(rh, To, P.energy(To, So), qo)
-    H = mg_ref.Hierarchy(shape, out["ahat"], out["s"])
+    H = mg_ref.Hierarchy(shape, out["ahat"], out["s"], klevels=())
     A = _csr(H.levels[0])
     b = out["bhat"]
     it_cg, _ = _pcg(A, b, lambda r: r)
     for dt in (np.float64, np.float32):
-        Hd = mg_ref.Hierarchy(shape, out["ahat"], out["s"], dtype=dt)
+        Hd = mg_ref.Hierarchy(shape, out["ahat"], out["s"], dtype=dt, klevels=())
         it, x = _pcg(A, b, Hd.apply)
         assert it <= 25, (dt, it, it_cg)
         assert P.relres(out["ahat"], b, x) <= 1e-8
     assert it_cg >= 5 * it
+    Hk = mg_ref.Hierarchy(shape, out["ahat"], out["s"], dtype=np.float32)
+    assert Hk.klevels == (1, 2)
+    itk, x = _fcg(A, b, Hk.apply)
+    assert itk <= 15 and itk < it, (itk, it)
+    assert P.relres(out["ahat"], b, x) <= 1e-8
