@@ -42,13 +42,17 @@ PEAK_HBM_GBS = 8000.0
 # and t at the red cells (20 / 40 B); the black pass reads p, t and every face
 # coefficient once and writes q (18 / 36 B); the update streams six half-size arrays.
 # A multigrid-preconditioned CG iteration (fp64-mg), algorithmic bytes per cell of the
-# finest level: the V-cycle's float32 kernels there (pre-sweep 40: r, im, ap, g, dp out
+# finest level.  There: the cycle's float32 kernels (pre-sweep 40: r, im, ap, g, dp out
 # and back, cp, q, x out; restriction 29: r, x, w, three couplings, 1/4 of a coarse
 # write; residual with the prolonged correction 37: r, x, w, 1/4 of the coarse result,
-# three couplings, rhs and x' out; last sweep 52: rhs, im, ap, g, dp out and back, cp, q,
-# x', r, z out), the float64 direction (56) and update (48) kernels, and the coarser
-# levels, a third of the finest level's cells at ~150 bytes each.
-MG_ITER_BYTES_PER_CELL = 40 + 29 + 37 + 52 + 56 + 48 + 50
+# three couplings, rhs and x' out; last sweep 60: rhs, im, ap, g, dp out and back, cp, q,
+# x', r, q_old, z out) and the float64 direction (56) and update (48) kernels: 270.  A
+# cycle on a coarser level moves ~142 bytes per cell of that level (its couplings and
+# diagonal, float32 right-hand side); levels 1 and 2 take K-cycle steps (two cycles and
+# two flexible-CG steps of 96 bytes per cell on level 1; four cycles and two step pairs
+# on level 2; the levels below are visited four times): 95, 48 and ~12 bytes per
+# finest-level cell.
+MG_ITER_BYTES_PER_CELL = 270 + 95 + 48 + 12
 # The float32 flexible-CG variant (mixed-mg): the same cycle on a float32 residual (4
 # bytes less in each of the first three kernels, the last sweep writes a float32 z and
 # reads no r: 40), flexible-CG beta 8 (z, q), direction 32 (three couplings, z, p_old,

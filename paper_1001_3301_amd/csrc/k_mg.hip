@@ -546,78 +546,119 @@ __global__ __launch_bounds__(kMB) void k_mg_out_line(int nr, const float *__rest
 // ------------------------------------------------- K-cycle: flexible CG on a level
 
 // The coarse correction of a K-cycle level is two steps of flexible CG on A_l, each
-// preconditioned by the cycle from that level (Notay's K-cycle): x = alpha_1 p_1 +
-// alpha_2 p_2 with p_1 = z_1, p_2 = z_2 + beta p_1, beta = -(z_2.q_1) / (p_1.q_1), q =
-// A_l p, alpha = (p.r) / (p.q), r the level's residual.  Float32 vectors, float64
-// dots; the scalars stay on the device (ks[0] = p.q, ks[1] = alpha, ks[2] = beta).
+// preconditioned by the cycle from that level (Notay's K-cycle): x = a_1 p_1 + a_2 p_2
+// with p_1 = z_1, p_2 = z_2 + beta p_1, beta = -(z_2.q_1) / (p_1.q_1), q = A_l p, a =
+// (p.r) / (p.q), r the level's residual.  Since q_2 = A z_2 + beta q_1, one stencil pass
+// over z_2 gives every product the second step needs (z.Az, z.q_1, p_1.Az, z.r, p_1.r,
+// with p_1.q_1 from the first step), and the step needs no pass to form p_2 or q_2: the
+// level's result is x = a_1 z_1 + a_2 (z_2 + beta z_1).  Float32 vectors, float64 dots,
+// scalars on the device (ks[0] = p_1.q_1, ks[1] = a, ks[2] = beta).
 constexpr int kKcBlocks = 1024;  // grid of the K-cycle kernels (grid-stride loops)
+constexpr int kKcSums = 5;       // products reduced by the second step's stencil pass
 
-// p = z + beta p_old (p = z when FIRST), q = A_l p, then p.q and p.r: alpha.
+// N float64 sums over the grid, reduced deterministically as mg_reduce2 (partials hold
+// N per block).
+template <int N>
+__device__ __forceinline__ bool mg_reduce(const double (&v)[N], double *partials, unsigned *counter, double (&t)[N])
+{
+    __shared__ double sh[kMB / 64];
+    __shared__ int s_last;
+    double bs[N];
+#pragma unroll
+    for (int u = 0; u < N; u++) bs[u] = mg_block_sum(v[u], sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int u = 0; u < N; u++) partials[N * blockIdx.x + u] = bs[u];
+        __threadfence();
+        const unsigned prev = atomicAdd(counter, 1u);
+        s_last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __threadfence();
+    double a[N];
+#pragma unroll
+    for (int u = 0; u < N; u++) a[u] = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kMB)
+#pragma unroll
+        for (int u = 0; u < N; u++) a[u] += partials[N * b + u];
+#pragma unroll
+    for (int u = 0; u < N; u++) t[u] = mg_block_sum(a[u], sh);
+    if (threadIdx.x == 0) *counter = 0u;
+    return true;
+}
+
+// A z on a level and the step's products; FIRST writes q_1 = A z_1 and sets a_1, the
+// second step sets beta and a_2 from its five products.
 template <bool FIRST>
-__global__ __launch_bounds__(kMB) void k_kc_dir(int nr_, MgLevel F, const float *__restrict__ z,
-                                                const float *__restrict__ pold, float *__restrict__ pnew,
-                                                float *__restrict__ q, const float *__restrict__ r, double *ks,
-                                                double *partials, unsigned *counter, const DevScalars *sc)
+__global__ __launch_bounds__(kMB) void k_kc_az(int nr_, MgLevel F, const float *__restrict__ z,
+                                               const float *__restrict__ p1, const float *__restrict__ q1,
+                                               const float *__restrict__ r, float *__restrict__ qout, double *ks,
+                                               double *partials, unsigned *counter, const DevScalars *sc)
 {
     if (sc && sc->done) return;
     const unsigned nr = nr_, nt = F.nt, np = F.np, n = (unsigned)F.n;
-    const float beta = FIRST ? 0.0f : (float)ks[2];
-    auto pv = [&](unsigned c) { return FIRST ? z[c] : fmaf(beta, pold[c], z[c]); };
-    double apq = 0.0, apr = 0.0;
+    double acc[kKcSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (unsigned f = blockIdx.x * kMB + threadIdx.x; f < n; f += gridDim.x * kMB) {
         const unsigned i = f % nr, rest = f / nr;
         const unsigned j = rest % nt, k = rest / nt;
-        const float p0 = pv(f);
-        float v = (F.dg ? F.dg[f] : 1.0f) * p0;
-        if (i + 1 < nr) v = fmaf(F.ar[f], pv(f + 1), v);
-        if (i > 0) v = fmaf(F.ar[f - 1], pv(f - 1), v);
-        if (j + 1 < nt) v = fmaf(F.at[f], pv(f + nr), v);
-        if (j > 0) v = fmaf(F.at[f - nr], pv(f - nr), v);
+        const float z0 = z[f];
+        float v = (F.dg ? F.dg[f] : 1.0f) * z0;
+        if (i + 1 < nr) v = fmaf(F.ar[f], z[f + 1], v);
+        if (i > 0) v = fmaf(F.ar[f - 1], z[f - 1], v);
+        if (j + 1 < nt) v = fmaf(F.at[f], z[f + nr], v);
+        if (j > 0) v = fmaf(F.at[f - nr], z[f - nr], v);
         if (np > 1) {
             const unsigned kp = k + 1 < np ? k + 1 : 0, km = k > 0 ? k - 1 : np - 1;
             const unsigned cp1 = i + nr * (j + nt * kp), cm1 = i + nr * (j + nt * km);
-            v = fmaf(F.ap[f], pv(cp1), v);
-            v = fmaf(F.ap[cm1], pv(cm1), v);
+            v = fmaf(F.ap[f], z[cp1], v);
+            v = fmaf(F.ap[cm1], z[cm1], v);
         }
-        pnew[f] = p0;
-        q[f] = v;
-        apq += (double)p0 * (double)v;
-        apr += (double)p0 * (double)r[f];
+        const double zd = z0, vd = v, rd = r[f];
+        acc[0] += zd * vd;
+        acc[1] += zd * rd;
+        if (FIRST) {
+            qout[f] = v;
+        } else {
+            const double pd = p1[f];
+            acc[2] += zd * (double)q1[f];
+            acc[3] += pd * vd;
+            acc[4] += pd * rd;
+        }
     }
-    double pq, pr;
-    if (mg_reduce2(apq, apr, partials, counter, &pq, &pr) && threadIdx.x == 0) {
-        ks[0] = pq;
-        ks[1] = pq != 0.0 ? pr / pq : 0.0;
+    double t[kKcSums];
+    if (mg_reduce<kKcSums>(acc, partials, counter, t) && threadIdx.x == 0) {
+        if (FIRST) {  // p_1 = z_1, q_1 = A z_1
+            ks[0] = t[0];
+            ks[1] = t[0] != 0.0 ? t[1] / t[0] : 0.0;
+        } else {
+            const double pq1 = ks[0];
+            const double beta = pq1 != 0.0 ? -t[2] / pq1 : 0.0;
+            const double pq = t[0] + beta * (t[2] + t[3]) + beta * beta * pq1;  // p_2.q_2
+            const double pr = t[1] + beta * t[4];                                // p_2.r
+            ks[2] = beta;
+            ks[1] = pq != 0.0 ? pr / pq : 0.0;
+        }
     }
 }
 
-// x = alpha p (FIRST) or x += alpha p; r -= alpha q unless LAST.
-template <bool FIRST, bool LAST>
-__global__ __launch_bounds__(kMB) void k_kc_upd(long n_, float *__restrict__ x, const float *__restrict__ p,
-                                                const float *__restrict__ q, float *__restrict__ r, const double *ks,
-                                                const DevScalars *sc)
+// FIRST: x = a_1 z_1, r -= a_1 q_1.  Second step: x += a_2 (z_2 + beta z_1).
+template <bool FIRST>
+__global__ __launch_bounds__(kMB) void k_kc_upd(long n_, float *__restrict__ x, const float *__restrict__ z,
+                                                const float *__restrict__ p1, const float *__restrict__ q1,
+                                                float *__restrict__ r, const double *ks, const DevScalars *sc)
 {
     if (sc && sc->done) return;
     const unsigned n = (unsigned)n_;
-    const float a = (float)ks[1];
+    const float a = (float)ks[1], beta = (float)ks[2];
     for (unsigned f = blockIdx.x * kMB + threadIdx.x; f < n; f += gridDim.x * kMB) {
-        x[f] = FIRST ? a * p[f] : fmaf(a, p[f], x[f]);
-        if (!LAST) r[f] = fmaf(-a, q[f], r[f]);
+        if (FIRST) {
+            x[f] = a * z[f];
+            r[f] = fmaf(-a, q1[f], r[f]);
+        } else {
+            x[f] = fmaf(a, fmaf(beta, p1[f], z[f]), x[f]);
+        }
     }
-}
-
-// beta = -(z.q) / (p.q) for the second step.
-__global__ __launch_bounds__(kMB) void k_kc_beta(long n_, const float *__restrict__ z, const float *__restrict__ q,
-                                                 double *ks, double *partials, unsigned *counter,
-                                                 const DevScalars *sc)
-{
-    if (sc && sc->done) return;
-    const unsigned n = (unsigned)n_;
-    double a = 0.0;
-    for (unsigned f = blockIdx.x * kMB + threadIdx.x; f < n; f += gridDim.x * kMB) a += (double)z[f] * (double)q[f];
-    double zq, unused;
-    if (mg_reduce2(a, 0.0, partials, counter, &zq, &unused) && threadIdx.x == 0)
-        ks[2] = ks[0] != 0.0 ? -zq / ks[0] : 0.0;
 }
 
 // ------------------------------------------------------------------ host side
@@ -700,7 +741,7 @@ static void mg_cycle(MgRun &R, int l, const float *b, float *out)
 }
 
 // Two flexible-CG steps on level l with the cycle as preconditioner; b is the level's
-// residual and is updated in place.
+// residual and is updated in place.  K.p1 holds z_1 (= p_1), K.q A z_1, K.z z_2.
 static void mg_kcycle(MgRun &R, int l, float *b, float *out)
 {
     MgHier &h = R.h;
@@ -709,18 +750,16 @@ static void mg_kcycle(MgRun &R, int l, float *b, float *out)
     MgKLevel &K = h.kl[l];
     const DevScalars *csc = R.sc;
     const unsigned gk = (unsigned)std::min<long>(mg_blocks(F.n), kKcBlocks);
+    mg_cycle(R, l, b, K.p1);
+    hipLaunchKernelGGL(k_kc_az<true>, dim3(gk), dim3(kMB), 0, R.st, nr, F, (const float *)K.p1, (const float *)nullptr,
+                       (const float *)nullptr, (const float *)b, K.q, K.ks, h.kpart, h.kcnt, csc);
+    hipLaunchKernelGGL(k_kc_upd<true>, dim3(gk), dim3(kMB), 0, R.st, F.n, out, (const float *)K.p1,
+                       (const float *)nullptr, (const float *)K.q, b, (const double *)K.ks, csc);
     mg_cycle(R, l, b, K.z);
-    hipLaunchKernelGGL(k_kc_dir<true>, dim3(gk), dim3(kMB), 0, R.st, nr, F, (const float *)K.z, (const float *)nullptr,
-                       K.p1, K.q, (const float *)b, K.ks, h.kpart, h.kcnt, csc);
-    hipLaunchKernelGGL((k_kc_upd<true, false>), dim3(gk), dim3(kMB), 0, R.st, F.n, out, (const float *)K.p1,
-                       (const float *)K.q, b, (const double *)K.ks, csc);
-    mg_cycle(R, l, b, K.z);
-    hipLaunchKernelGGL(k_kc_beta, dim3(gk), dim3(kMB), 0, R.st, F.n, (const float *)K.z, (const float *)K.q, K.ks,
-                       h.kpart, h.kcnt, csc);
-    hipLaunchKernelGGL(k_kc_dir<false>, dim3(gk), dim3(kMB), 0, R.st, nr, F, (const float *)K.z,
-                       (const float *)K.p1, K.p2, K.q, (const float *)b, K.ks, h.kpart, h.kcnt, csc);
-    hipLaunchKernelGGL((k_kc_upd<false, true>), dim3(gk), dim3(kMB), 0, R.st, F.n, out, (const float *)K.p2,
-                       (const float *)K.q, b, (const double *)K.ks, csc);
+    hipLaunchKernelGGL(k_kc_az<false>, dim3(gk), dim3(kMB), 0, R.st, nr, F, (const float *)K.z, (const float *)K.p1,
+                       (const float *)K.q, (const float *)b, (float *)nullptr, K.ks, h.kpart, h.kcnt, csc);
+    hipLaunchKernelGGL(k_kc_upd<false>, dim3(gk), dim3(kMB), 0, R.st, F.n, out, (const float *)K.z,
+                       (const float *)K.p1, (const float *)nullptr, b, (const double *)K.ks, csc);
 }
 
 static void mg_solve_level(MgRun &R, int l, float *b, float *out)

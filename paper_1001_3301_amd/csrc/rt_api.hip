@@ -1111,9 +1111,9 @@ rt_status mg_prepare(rt_ctx *ctx)
         h->kl.resize(L + 1);
         for (int l = 1; l <= kMgKLevels && l < L && ok; l++) {
             const long nl = h->lev[l].n;
-            h->kl[l] = MgKLevel{f32(nl), f32(nl), f32(nl), f32(nl), f64(4)};
+            h->kl[l] = MgKLevel{f32(nl), f32(nl), f32(nl), f64(4)};
         }
-        h->kpart = f64(2 * 1024);
+        h->kpart = f64(8 * 1024);  // five sums for each of at most 1024 blocks
         h->kcnt = dalloc<unsigned>(ctx, 1);
         ok = ok && h->kcnt;
         if (h->kcnt && hipMemset(h->kcnt, 0, sizeof(unsigned)) != hipSuccess) ok = false;

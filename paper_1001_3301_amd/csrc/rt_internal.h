@@ -208,17 +208,18 @@ struct MgLevel64 {
     double *dg = nullptr, *ar = nullptr, *at = nullptr, *ap = nullptr, *B = nullptr;
 };
 
-// A level with K-cycle steps (two flexible-CG steps per coarse correction): its
-// search vectors and device scalars (p.q, alpha, beta); z is null on other levels.
+// A level with K-cycle steps (two flexible-CG steps per coarse correction): the two
+// preconditioned vectors, A z_1 and the device scalars (p.q, alpha, beta); z is null on
+// other levels.
 struct MgKLevel {
-    float *z = nullptr, *p1 = nullptr, *p2 = nullptr, *q = nullptr;
+    float *z = nullptr, *p1 = nullptr, *q = nullptr;
     double *ks = nullptr;
 };
 
 struct MgHier {
     int nr = 0;
     std::vector<MgKLevel> kl;    // per level (K-cycle buffers where used)
-    double *kpart = nullptr;     // K-cycle reduction partials (pairs)
+    double *kpart = nullptr;     // K-cycle reduction partials (five per block)
     unsigned *kcnt = nullptr;    // their counter (0 between uses)
     std::vector<MgLevel> lev;    // 0 .. L (L: one radial line)
     std::vector<MgLevel64> d64;  // levels 1 .. L in float64 (entry l - 1), built by the set-up
