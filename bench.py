@@ -57,15 +57,19 @@ MG_ITER_BYTES_PER_CELL = 270 + 95 + 48 + 12
 # bytes less in each of the first three kernels, the last sweep writes a float32 z and
 # reads no r: 40), flexible-CG beta 8 (z, q), direction 32 (three couplings, z, p_old,
 # r; p and q out), update 24 (x, p, r, q; x and r out).
-MG32_ITER_BYTES_PER_CELL = 36 + 25 + 33 + 40 + 8 + 32 + 24 + 50
+MG32_ITER_BYTES_PER_CELL = 36 + 25 + 33 + 40 + 8 + 32 + 24 + 95 + 48 + 12
+# The plain V-cycle (fp64-mgv): the finest level as above, the coarser levels once
+# each (~50).
+MGV_ITER_BYTES_PER_CELL = 270 + 50
 BYTES_PER_CELL = {"fp64": {"dir": 7 * 8, "upd": 6 * 8}, "mixed": {"dir": 7 * 4, "upd": 6 * 4},
                   "fp64-rb": {"dir": 76, "upd": 24, "red": 40, "black": 36},
                   "mixed-rb": {"dir": 38, "upd": 12, "red": 20, "black": 18},
                   "fp64-mg": {"cg_dir": 7 * 8, "upd": 6 * 8, "iteration": MG_ITER_BYTES_PER_CELL},
-                  "mixed-mg": {"cg_dir": 32, "upd": 24, "iteration": MG32_ITER_BYTES_PER_CELL}}
+                  "mixed-mg": {"cg_dir": 32, "upd": 24, "iteration": MG32_ITER_BYTES_PER_CELL},
+                  "fp64-mgv": {"cg_dir": 7 * 8, "upd": 6 * 8, "iteration": MGV_ITER_BYTES_PER_CELL}}
 KERNEL_NAMES = {"fp64": "k_cg_dir<double>", "mixed": "k_cg_dir<float>", "fp64-rb": ("k_rb_red_dir<double>",
                 "k_rb_black_dir<double>"), "mixed-rb": ("k_rb_red_dir<float>", "k_rb_black_dir<float>"),
-                "fp64-mg": "k_cg_dir<double>", "mixed-mg": "k_fcg_dir<4>"}
+                "fp64-mg": "k_cg_dir<double>", "mixed-mg": "k_fcg_dir<4>", "fp64-mgv": "k_cg_dir<double>"}
 # HBM bytes per launch of these kernels on the 512x256x512 workload, from rocprofv3
 # FETCH_SIZE (x2.0, calibrated on a kernel of known size) + WRITE_SIZE; the summary with
 # the commands is profiles/solver_kernels_clumpy-512x256x512-nu64.md.  Set to None when
@@ -120,16 +124,18 @@ _launch = 0
 def mode_opts(rt, mode, tol, max_iter, inner_tol, net=None, budget=0, restart=30):
     """Solve options of a bench mode; the suffix -rb solves the red-black reduced system,
     -line preconditions float64 CG with the radial-line block Jacobi, -mg with one
-    multigrid V-cycle per iteration; learned-fgmres runs the network inside flexible
-    GMRES(m) instead of flexible CG."""
+    multigrid cycle per iteration (K-cycle steps on levels 1 and 2), -mgv with a plain
+    V-cycle; learned-fgmres runs the network inside flexible GMRES(m) instead of
+    flexible CG."""
     parts = mode.split("-")
     base = parts[0]
     m = {"fp64": rt.MODE_FP64, "mixed": rt.MODE_MIXED, "learned": rt.MODE_LEARNED, "gmres": rt.MODE_GMRES}[base]
-    every = 8 if mode.endswith("-mg") else 32  # a multigrid iteration is several passes
+    every = 8 if mode.endswith(("-mg", "-mgv")) else 32  # a multigrid iteration is several passes
     return rt.solve_opts(m, tol=tol, max_iter=max_iter, check_every=every, inner_tol=inner_tol,
                          inner_max_iter=budget if base == "learned" else 0, net=net if base == "learned" else None,
                          restart=restart, reduce=int(mode.endswith("-rb")),
-                         precond=1 if mode.endswith("-line") else (2 if mode.endswith("-mg") else 0),
+                         precond=1 if mode.endswith("-line") else (2 if mode.endswith(("-mg", "-mgv")) else 0),
+                         cycle=rt.CYCLE_V if mode.endswith("-mgv") else rt.CYCLE_K,
                          launch=_launch, inner=rt.INNER_FGMRES if "fgmres" in parts else rt.INNER_FCG)
 
 
@@ -546,7 +552,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="clumpy-512x256x512-nu64")
-    ap.add_argument("--modes", default="fp64-mg,mixed-rb,fp64,mixed,fp64-rb,learned,learned-rb,learned-fgmres-rb",
+    ap.add_argument("--modes", default="fp64-mg,fp64-mgv,mixed-rb,fp64,mixed,fp64-rb,learned,learned-rb,"
+                                       "learned-fgmres-rb",
                     help="comma list; the first is the headline (suffix -rb: red-black reduced system)")
     ap.add_argument("--net", default="", help="load the network from this file instead of training it")
     ap.add_argument("--save-net", default="", help="save the trained network to this file")
@@ -562,6 +569,8 @@ def main():
     ap.add_argument("--successive", type=int, default=50,
                     help="also run this many successive steps of the headline mode (not timed for value; "
                          "50 x ~0.5 s with the multigrid headline, far longer with a Jacobi-CG headline)")
+    ap.add_argument("--successive-also", default="fp64-mgv",
+                    help="comma list of further modes that also run the successive steps")
     ap.add_argument("--other-steps", type=int, default=3,
                     help="timed steps of each non-headline mode (at most --steps; warm-up at most 1)")
     ap.add_argument("--c4-gain", action="store_true",
@@ -679,7 +688,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("f64+f32" if head.startswith("fp64") else "f32+f64") if head.endswith("-mg") else
+        "dtype": ("f64+f32" if head.startswith("fp64") else "f32+f64") if head.endswith(("-mg", "-mgv")) else
                  {"fp64": "f64", "mixed": "f32+f64", "learned": "bf16+f32+f64", "gmres": "f64"}[head.split("-")[0]],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {wl.grid.shape[0]}x{wl.grid.shape[1]}x{wl.grid.shape[2]} cells, "
@@ -770,14 +779,17 @@ def main():
     for mode in modes:
         del results[mode]["T"], results[mode]["E"], results[mode]["f"]
     if args.successive > 0:
-        seq = run_successive(ctx, rt, torch, rho, T0, head, args.successive, args.tol, args.inner_tol,
-                             args.max_iter, net, args.learned_budget)
-        out["successive_steps"] = {
-            "what": f"{args.successive} successive radiation steps of the headline mode ({head}) at dt = "
-                    f"{wl.dt:g} s, each from the previous step's temperature (the timed steps above all "
-                    f"repeat step 1); solve seconds and iterations per step",
-            "mode": head, "steps": seq, "solve_s_total": sum(x["solve_s"] for x in seq),
-            "iters": [x["iters"] for x in seq]}
+        also = [m.strip() for m in args.successive_also.split(",") if m.strip() and m.strip() != head]
+        for k, smode in enumerate([head] + also):
+            seq = run_successive(ctx, rt, torch, rho, T0, smode, args.successive, args.tol, args.inner_tol,
+                                 args.max_iter, net, args.learned_budget)
+            key = "successive_steps" if k == 0 else f"successive_steps_{smode}"
+            out[key] = {
+                "what": f"{args.successive} successive radiation steps of the {'headline ' if k == 0 else ''}mode "
+                        f"{smode} at dt = {wl.dt:g} s, each from the previous step's temperature (the timed steps "
+                        f"above all repeat step 1); solve seconds and iterations per step",
+                "mode": smode, "steps": seq, "solve_s_total": sum(x["solve_s"] for x in seq),
+                "iters": [x["iters"] for x in seq]}
     if not args.no_main_loop:
         out["main_iteration"] = run_main_loop(rt, torch, sy)
     if not args.no_cpu_baseline:

@@ -138,6 +138,9 @@ typedef struct {
                             (reduced or not) reach the GPU; every choice computes the same
                             method, DIRECT and GRAPH bit for bit alike */
     int inner;           /* rt_inner: the Krylov method of RT_SOLVE_LEARNED */
+    int cycle;           /* precond = 2: 0 = the coarse corrections of levels 1 and 2 are
+                            two flexible-CG steps each (K-cycle, the default), 1 = plain
+                            V-cycle (cheaper per iteration, more iterations) */
 } rt_solve_opts;
 
 typedef enum {

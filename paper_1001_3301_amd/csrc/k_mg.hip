@@ -769,7 +769,7 @@ static void mg_solve_level(MgRun &R, int l, float *b, float *out)
     if (l == L)
         hipLaunchKernelGGL(k_mg_coarse, dim3(h.nr), dim3(kMB), 0, R.st, h.nr, (const double *)h.inv, (const float *)b,
                            out, (const DevScalars *)R.sc);
-    else if (h.kl[l].z)
+    else if (l <= h.kmax && h.kl[l].z)
         mg_kcycle(R, l, b, out);
     else
         mg_cycle(R, l, b, out);

@@ -1151,6 +1151,7 @@ rt_status solve_fp64_mg(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
     DevScalars *h = ctx->h_sc;
     if (rt_status e = mg_prepare(ctx)) return e;
     MgHier &mg = *ctx->mg;
+    mg.kmax = o->cycle == 1 ? 0 : kMgKLevels;
     h->thresh2 = o->tol * o->tol * bb;
     h->done = 0;
     h->iters = 0;
@@ -1209,6 +1210,7 @@ rt_status solve_mixed_mg(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st
     DevScalars *h = ctx->h_sc;
     if (rt_status e = mg_prepare(ctx)) return e;
     MgHier &mg = *ctx->mg;
+    mg.kmax = o->cycle == 1 ? 0 : kMgKLevels;
     const double delta2 = 0.01;
     h->iters = 0;
     h->done = 0;
@@ -1550,6 +1552,7 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
              "unknown solve mode");
     RT_CHECK(ctx, o->mode != RT_SOLVE_LEARNED || o->net, "learned mode needs a network");
     RT_CHECK(ctx, o->inner == RT_INNER_FCG || o->inner == RT_INNER_FGMRES, "inner must be an rt_inner value");
+    RT_CHECK(ctx, o->cycle == 0 || o->cycle == 1, "cycle must be 0 (K-cycle) or 1 (V-cycle)");
     RT_CHECK(ctx, o->launch >= RT_LAUNCH_AUTO && o->launch <= RT_LAUNCH_BLOCK,
              "rt_fld_solve: launch must be an rt_launch value");
     RT_CHECK(ctx, o->precond == 0 || (o->precond == 1 && o->mode == RT_SOLVE_FP64 && !o->reduce) ||
@@ -1848,6 +1851,7 @@ rt_status rt_mg_apply(rt_ctx *ctx, const double *r, double *z)
     RT_CHECK(ctx, r && z, "rt_mg_apply: NULL field pointer");
     if (rt_status e = mg_prepare(ctx)) return e;
     // the solver's own cycle (its r.z and scalars land in the context's scalars)
+    ctx->mg->kmax = kMgKLevels;
     ctx->h_sc->done = 0;
     ctx->h_sc->rr = 0.0;
     if (rt_status e = write_scalars(ctx)) return e;

@@ -219,6 +219,7 @@ struct MgKLevel {
 struct MgHier {
     int nr = 0;
     std::vector<MgKLevel> kl;    // per level (K-cycle buffers where used)
+    int kmax = 0;                // levels 1 .. kmax take K-cycle steps in the next cycles
     double *kpart = nullptr;     // K-cycle reduction partials (five per block)
     unsigned *kcnt = nullptr;    // their counter (0 between uses)
     std::vector<MgLevel> lev;    // 0 .. L (L: one radial line)

@@ -24,6 +24,7 @@ LAUNCH_AUTO, LAUNCH_DIRECT, LAUNCH_GRAPH, LAUNCH_BLOCK = 0, 1, 2, 3
 INNER_FCG, INNER_FGMRES = 0, 1
 LANES_BINS, LANES_CELLS = 0, 1
 PRECOND_JACOBI, PRECOND_LINE, PRECOND_MG = 0, 1, 2
+CYCLE_K, CYCLE_V = 0, 1
 
 dp = C.POINTER(C.c_double)
 
@@ -67,7 +68,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("check_every", C.c_int), ("inner_tol", C.c_double), ("inner_max_iter", C.c_int),
                 ("net", C.c_void_p), ("restart", C.c_int), ("reduce", C.c_int), ("precond", C.c_int),
-                ("launch", C.c_int), ("inner", C.c_int)]
+                ("launch", C.c_int), ("inner", C.c_int), ("cycle", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -248,10 +249,11 @@ class GrayOpacity:
 
 
 def solve_opts(mode=MODE_FP64, tol=1e-8, max_iter=100000, check_every=32, inner_tol=1e-4,
-               inner_max_iter=0, net=None, restart=30, reduce=0, precond=0, launch=0, inner=INNER_FCG) -> SolveOpts:
+               inner_max_iter=0, net=None, restart=30, reduce=0, precond=0, launch=0, inner=INNER_FCG,
+               cycle=CYCLE_K) -> SolveOpts:
     nh = None if net is None else (net.h if isinstance(net, Net) else net)
     o = SolveOpts(mode, tol, max_iter, check_every, inner_tol, inner_max_iter, nh, restart, int(reduce),
-                  int(precond), int(launch), int(inner))
+                  int(precond), int(launch), int(inner), int(cycle))
     o._net = net  # keeps the network alive as long as the options refer to it
     return o
 
