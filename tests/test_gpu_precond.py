@@ -85,6 +85,6 @@ def test_line_preconditioner_rejects_other_modes():
     wl = CASES["thick-40x9x4-nu64"]()
     P, ctx, T, S, En, ref = _system(wl)
     for o in (rt.solve_opts(rt.MODE_MIXED, precond=1), rt.solve_opts(rt.MODE_FP64, precond=1, reduce=1),
-              rt.solve_opts(rt.MODE_FP64, precond=2)):
+              rt.solve_opts(rt.MODE_FP64, precond=3)):
         rc, _ = ctx.solve(_d(En), o, raise_on_error=False)
         assert rc == rt.RT_EINVAL
