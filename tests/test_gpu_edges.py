@@ -7,7 +7,8 @@ Every kernel of the step runs at these sizes with most of its threads idle or cl
 the ray trace (one partial segment per column), the assembly's boundary faces, the
 Krylov kernels with every neighbour a boundary (full system from graphs, the reduced
 system in one workgroup and from graphs in float32, GMRES(30) whose Krylov space fills
-up within one cycle), Newton and the force.
+up within one cycle, the multigrid CG with hierarchies of one to three levels), Newton
+and the force.
 """
 import numpy as np
 import pytest
@@ -67,13 +68,18 @@ def test_column_length_limit():
     assert ei.value.status == rt.RT_EINVAL and "2944" in str(ei.value)
 
 
-MODES = {  # name: (mode, reduce, solve tol, T bar)
+MODES = {  # name: (mode, reduce, solve tol, T bar[, further solve options])
     "fp64": (0, 0, 1e-12, 1e-11),
     "fp64-rb": (0, 1, 1e-12, 1e-11),
     "mixed-rb": (1, 1, 1e-12, 1e-9),
     # GMRES(30): on the smallest grids the Krylov space fills up within a cycle; solved
     # to 1e-13, since its 1e-12 residual leaves T 1.6e-11 off on the 1472-cell columns
     "gmres": (3, 0, 1e-13, 1e-11),
+    # the multigrid CG: hierarchies of one to three levels, lines of one, two and four
+    # phi cells, single theta rows, the coarsest line of 1472 cells
+    "fp64-mg": (0, 0, 1e-12, 1e-11, dict(precond=2)),
+    "fp64-mgv": (0, 0, 1e-12, 1e-11, dict(precond=2, cycle=1)),
+    "mixed-mg": (1, 0, 1e-12, 1e-9, dict(precond=2)),
 }
 
 
@@ -81,7 +87,8 @@ MODES = {  # name: (mode, reduce, solve tol, T bar)
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
 def test_tiny_step_parity(shape, mode):
     from paper_1001_3301_amd import rt
-    m, rb, tol, bar = MODES[mode]
+    m, rb, tol, bar = MODES[mode][:4]
+    extra = MODES[mode][4] if len(MODES[mode]) > 4 else {}
     wl = _wl(shape)
     P = oracle.Problem.from_workload(wl)
     ctx = rt.Context.from_workload(wl)
@@ -90,7 +97,7 @@ def test_tiny_step_parity(shape, mode):
     Td = _d(T0)
     E = torch.empty(P.n, dtype=torch.float64, device="cuda")
     f = torch.empty(4 * P.n, dtype=torch.float64, device="cuda")
-    rc, st = ctx.step(_d(wl.rho), Td, E, rt.solve_opts(m, tol=tol, max_iter=100000, reduce=rb), f_rad=f)
+    rc, st = ctx.step(_d(wl.rho), Td, E, rt.solve_opts(m, tol=tol, max_iter=100000, reduce=rb, **extra), f_rad=f)
     assert rc == 0 and st["solve"]["relres"] <= tol
     assert st["solve"]["reduced"] == rb
     assert rel(_h(Td), ref["T"]) < bar
