@@ -245,3 +245,28 @@ def test_fullsize_solves_against_oracle(fullsize, oracle_c5, mode):
     assert res <= 1.05e-8, res
     assert eT < 1e-10
     assert dT <= 1e-6
+
+
+@pytest.mark.parametrize("cycle", ["K", "V"])
+def test_fullsize_multigrid_solves_against_oracle(fullsize, oracle_c5, cycle):
+    """The multigrid-preconditioned float64 CG at full size, with K-cycle steps on levels
+    1 and 2 or a plain V-cycle: the oracle's residual of the answer meets the tolerance,
+    the oracle's Newton step from it gives the GPU's temperature, the temperature agrees
+    with the float64 Jacobi-CG solve's, in a small fraction of its iterations."""
+    from paper_1001_3301_amd import rt
+    wl, ctx, F, st = fullsize
+    P, O = oracle_c5
+    E = F["En"].clone()
+    rc, sr = ctx.solve(E, rt.solve_opts(rt.MODE_FP64, tol=1e-8, max_iter=100000, precond=rt.PRECOND_MG,
+                                        cycle=rt.CYCLE_K if cycle == "K" else rt.CYCLE_V))
+    assert sr["relres"] <= 1e-8 and sr["fallback"] == 0
+    assert sr["iters"] <= (40 if cycle == "K" else 120), sr["iters"]
+    T = F["T0"].clone()
+    ctx.temperature(E, F["S"], T)
+    res, eT = _against_oracle(F, O, P, E, T)
+    dT = float(((T - F["T1"]).abs() / F["T1"]).max())
+    print(f"multigrid {cycle}-cycle: {sr['iters']} iterations (Jacobi CG {st['iters']}); oracle relres of the "
+          f"GPU's E {res:.3e}, Newton T {eT:.2e}, T vs the float64 Jacobi-CG solve {dT:.2e}")
+    assert res <= 1.05e-8, res
+    assert eT < 1e-10
+    assert dT <= 1e-6
