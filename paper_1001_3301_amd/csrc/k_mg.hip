@@ -553,48 +553,28 @@ __global__ __launch_bounds__(kMB) void k_mg_out_line(int nr, const float *__rest
 // with p_1.q_1 from the first step), and the step needs no pass to form p_2 or q_2: the
 // level's result is x = a_1 z_1 + a_2 (z_2 + beta z_1).  Float32 vectors, float64 dots,
 // scalars on the device (ks[0] = p_1.q_1, ks[1] = a, ks[2] = beta).
-constexpr int kKcBlocks = 1024;  // grid of the K-cycle kernels (grid-stride loops)
+constexpr int kKcBlocks = 4096;  // most blocks of the K-cycle kernels (grid-stride loops)
 constexpr int kKcSums = 5;       // products reduced by the second step's stencil pass
 
-// N float64 sums over the grid, reduced deterministically as mg_reduce2 (partials hold
-// N per block).
+// Block sums of N per-thread values written to partials[N * block + u] (no atomics or
+// fences: the finishing kernel that reads them starts after this kernel has ended).
 template <int N>
-__device__ __forceinline__ bool mg_reduce(const double (&v)[N], double *partials, unsigned *counter, double (&t)[N])
+__device__ __forceinline__ void mg_block_partials(const double (&v)[N], double *partials)
 {
     __shared__ double sh[kMB / 64];
-    __shared__ int s_last;
-    double bs[N];
 #pragma unroll
-    for (int u = 0; u < N; u++) bs[u] = mg_block_sum(v[u], sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int u = 0; u < N; u++) partials[N * blockIdx.x + u] = bs[u];
-        __threadfence();
-        const unsigned prev = atomicAdd(counter, 1u);
-        s_last = prev == gridDim.x - 1;
+    for (int u = 0; u < N; u++) {
+        const double b = mg_block_sum(v[u], sh);
+        if (threadIdx.x == 0) partials[N * blockIdx.x + u] = b;
     }
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();
-    double a[N];
-#pragma unroll
-    for (int u = 0; u < N; u++) a[u] = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kMB)
-#pragma unroll
-        for (int u = 0; u < N; u++) a[u] += partials[N * b + u];
-#pragma unroll
-    for (int u = 0; u < N; u++) t[u] = mg_block_sum(a[u], sh);
-    if (threadIdx.x == 0) *counter = 0u;
-    return true;
 }
 
-// A z on a level and the step's products; FIRST writes q_1 = A z_1 and sets a_1, the
-// second step sets beta and a_2 from its five products.
+// A z on a level and the step's products, as block partials; FIRST writes q_1 = A z_1.
 template <bool FIRST>
 __global__ __launch_bounds__(kMB) void k_kc_az(int nr_, MgLevel F, const float *__restrict__ z,
                                                const float *__restrict__ p1, const float *__restrict__ q1,
-                                               const float *__restrict__ r, float *__restrict__ qout, double *ks,
-                                               double *partials, unsigned *counter, const DevScalars *sc)
+                                               const float *__restrict__ r, float *__restrict__ qout,
+                                               double *partials, const DevScalars *sc)
 {
     if (sc && sc->done) return;
     const unsigned nr = nr_, nt = F.nt, np = F.np, n = (unsigned)F.n;
@@ -626,8 +606,26 @@ __global__ __launch_bounds__(kMB) void k_kc_az(int nr_, MgLevel F, const float *
             acc[4] += pd * rd;
         }
     }
+    mg_block_partials<kKcSums>(acc, partials);
+}
+
+// The step's scalars from the partials of k_kc_az (one block; the blocks' partials are
+// summed in block order): FIRST sets a_1, the second step beta and a_2 from its five
+// products.
+template <bool FIRST>
+__global__ __launch_bounds__(kMB) void k_kc_fin(int nblk, const double *__restrict__ partials, double *ks,
+                                                const DevScalars *sc)
+{
+    if (sc && sc->done) return;
+    __shared__ double sh[kMB / 64];
     double t[kKcSums];
-    if (mg_reduce<kKcSums>(acc, partials, counter, t) && threadIdx.x == 0) {
+#pragma unroll
+    for (int u = 0; u < kKcSums; u++) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kMB) a += partials[kKcSums * b + u];
+        t[u] = mg_block_sum(a, sh);
+    }
+    if (threadIdx.x == 0) {
         if (FIRST) {  // p_1 = z_1, q_1 = A z_1
             ks[0] = t[0];
             ks[1] = t[0] != 0.0 ? t[1] / t[0] : 0.0;
@@ -749,15 +747,17 @@ static void mg_kcycle(MgRun &R, int l, float *b, float *out)
     const int nr = h.nr;
     MgKLevel &K = h.kl[l];
     const DevScalars *csc = R.sc;
-    const unsigned gk = (unsigned)std::min<long>(mg_blocks(F.n), kKcBlocks);
+    const unsigned gk = (unsigned)std::min<long>((F.n + 4 * kMB - 1) / (4 * kMB), kKcBlocks);  // >= 4 cells a thread
     mg_cycle(R, l, b, K.p1);
     hipLaunchKernelGGL(k_kc_az<true>, dim3(gk), dim3(kMB), 0, R.st, nr, F, (const float *)K.p1, (const float *)nullptr,
-                       (const float *)nullptr, (const float *)b, K.q, K.ks, h.kpart, h.kcnt, csc);
+                       (const float *)nullptr, (const float *)b, K.q, h.kpart, csc);
+    hipLaunchKernelGGL(k_kc_fin<true>, dim3(1), dim3(kMB), 0, R.st, (int)gk, (const double *)h.kpart, K.ks, csc);
     hipLaunchKernelGGL(k_kc_upd<true>, dim3(gk), dim3(kMB), 0, R.st, F.n, out, (const float *)K.p1,
                        (const float *)nullptr, (const float *)K.q, b, (const double *)K.ks, csc);
     mg_cycle(R, l, b, K.z);
     hipLaunchKernelGGL(k_kc_az<false>, dim3(gk), dim3(kMB), 0, R.st, nr, F, (const float *)K.z, (const float *)K.p1,
-                       (const float *)K.q, (const float *)b, (float *)nullptr, K.ks, h.kpart, h.kcnt, csc);
+                       (const float *)K.q, (const float *)b, (float *)nullptr, h.kpart, csc);
+    hipLaunchKernelGGL(k_kc_fin<false>, dim3(1), dim3(kMB), 0, R.st, (int)gk, (const double *)h.kpart, K.ks, csc);
     hipLaunchKernelGGL(k_kc_upd<false>, dim3(gk), dim3(kMB), 0, R.st, F.n, out, (const float *)K.z,
                        (const float *)K.p1, (const float *)nullptr, b, (const double *)K.ks, csc);
 }

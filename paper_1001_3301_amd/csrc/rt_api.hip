@@ -1113,10 +1113,7 @@ rt_status mg_prepare(rt_ctx *ctx)
             const long nl = h->lev[l].n;
             h->kl[l] = MgKLevel{f32(nl), f32(nl), f32(nl), f64(4)};
         }
-        h->kpart = f64(8 * 1024);  // five sums for each of at most 1024 blocks
-        h->kcnt = dalloc<unsigned>(ctx, 1);
-        ok = ok && h->kcnt;
-        if (h->kcnt && hipMemset(h->kcnt, 0, sizeof(unsigned)) != hipSuccess) ok = false;
+        h->kpart = f64(8 * 4096);  // five sums for each of at most 4096 blocks
         h->B0 = f64(d.n);
         h->t64a = f64(d.n);
         h->t64b = f64(d.n);

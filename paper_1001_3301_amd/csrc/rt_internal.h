@@ -221,7 +221,6 @@ struct MgHier {
     std::vector<MgKLevel> kl;    // per level (K-cycle buffers where used)
     int kmax = 0;                // levels 1 .. kmax take K-cycle steps in the next cycles
     double *kpart = nullptr;     // K-cycle reduction partials (five per block)
-    unsigned *kcnt = nullptr;    // their counter (0 between uses)
     std::vector<MgLevel> lev;    // 0 .. L (L: one radial line)
     std::vector<MgLevel64> d64;  // levels 1 .. L in float64 (entry l - 1), built by the set-up
     std::vector<float *> dg32, ar32, at32, ap32;                // levels 1 .. L in float32 (entry l - 1)
