@@ -128,8 +128,8 @@ typedef struct {
                             1 (RT_SOLVE_FP64) = CG preconditioned by the radial-line block
                             Jacobi: each radial row's tridiagonal block of A^ solved exactly
                             (the block-Jacobi class of the paper's solver set-up, Sect.
-                            "Numerical setup", as a comparator), 2 = one multigrid V-cycle
-                            per iteration (an extension, not in the paper: see rt_mg_apply):
+                            "Numerical setup", as a comparator), 2 = one multigrid cycle per
+                            iteration (an extension, not in the paper: see rt_mg_apply):
                             RT_SOLVE_FP64 runs float64 CG with it (check_every defaults to 8
                             there), RT_SOLVE_MIXED flexible CG in float32 with float64 dots
                             and reliable updates (a non-finite float32 state hands over to
@@ -332,16 +332,21 @@ rt_status rt_gray_table(const rt_opacity *op, const double *F_nu, double *kappa_
 rt_status rt_precond_apply(rt_ctx *ctx, const double *r, double *z);
 
 /* The multigrid preconditioner of precond = 2 (an extension of the implicit solve of
- * Eq. 15, not in the paper): z = M_mg r, one V-cycle for the current system.  Levels:
+ * Eq. 15, not in the paper): z = M_mg r, one cycle for the current system, with the
+ * K-cycle steps of cycle = 0 (the solver's default).  Levels:
  * A_0 = A^; A_(l+1) = P_l^T A_l P_l over aggregates of 1 x 2 x 2 cells (theta and phi
  * pairs merged, the radius kept; a lone last row where a size is odd), with P_l[f, C] =
  * B_f / Bc_C, B_0 = 1/s and Bc_C^2 the sum of B_f^2 over the aggregate; the last level
  * is one radial line, solved exactly.  Smoother: x <- x + 0.8 M^-1 (b - A x), M the
  * diagonal and phi couplings of each (r, theta) line (periodic).  Cycle: pre-smoothing
- * from 0, restriction of the residual by P^T, the coarser cycle, prolongation by P,
- * post-smoothing; float32 inside, set-up in float64 once per assembled system.  Device
+ * from 0, restriction of the residual by P^T, the coarse correction, prolongation by P,
+ * post-smoothing; the coarse correction is the cycle one level down (V-cycle), or on
+ * levels 1 and 2 two flexible-CG steps preconditioned by the cycle from that level
+ * (K-cycle: x = a_1 z_1 + a_2 (z_2 + beta z_1), beta = -(z_2.A z_1)/(z_1.A z_1), a =
+ * p.r / p.A p), which makes the preconditioner nonlinear: the solver's outer CG is the
+ * flexible one.  Float32 inside, set-up in float64 once per assembled system.  Device
  * arrays of n; r and z must not overlap.  The hierarchy is allocated at the first use
- * (about 90 bytes per cell). */
+ * (about 100 bytes per cell). */
 rt_status rt_mg_apply(rt_ctx *ctx, const double *r, double *z);
 
 /* Device view of level `level` (0 = finest) of the current system's multigrid hierarchy
