@@ -48,16 +48,16 @@ PEAK_HBM_GBS = 8000.0
 # three couplings, rhs and x' out; last sweep 60: rhs, im, ap, g, dp out and back, cp, q,
 # x', r, q_old, z out) and the float64 direction (56) and update (48) kernels: 270.  A
 # cycle on a coarser level moves ~142 bytes per cell of that level (its couplings and
-# diagonal, float32 right-hand side); levels 1 and 2 take K-cycle steps (two cycles and
+# diagonal, float32 right-hand side); levels 1 to 3 take K-cycle steps (two cycles and
 # two flexible-CG steps of 96 bytes per cell on level 1; four cycles and two step pairs
-# on level 2; the levels below are visited four times): 95, 48 and ~12 bytes per
-# finest-level cell.
-MG_ITER_BYTES_PER_CELL = 270 + 95 + 48 + 12
+# on level 2; eight cycles and four step pairs on level 3; the levels below are visited
+# eight times): 95, 48, 24 and ~6 bytes per finest-level cell.
+MG_ITER_BYTES_PER_CELL = 270 + 95 + 48 + 24 + 6
 # The float32 flexible-CG variant (mixed-mg): the same cycle on a float32 residual (4
 # bytes less in each of the first three kernels, the last sweep writes a float32 z and
 # reads no r: 40), flexible-CG beta 8 (z, q), direction 32 (three couplings, z, p_old,
 # r; p and q out), update 24 (x, p, r, q; x and r out).
-MG32_ITER_BYTES_PER_CELL = 36 + 25 + 33 + 40 + 8 + 32 + 24 + 95 + 48 + 12
+MG32_ITER_BYTES_PER_CELL = 36 + 25 + 33 + 40 + 8 + 32 + 24 + 95 + 48 + 24 + 6
 # The plain V-cycle (fp64-mgv): the finest level as above, the coarser levels once
 # each (~50).
 MGV_ITER_BYTES_PER_CELL = 270 + 50
@@ -124,7 +124,7 @@ _launch = 0
 def mode_opts(rt, mode, tol, max_iter, inner_tol, net=None, budget=0, restart=30):
     """Solve options of a bench mode; the suffix -rb solves the red-black reduced system,
     -line preconditions float64 CG with the radial-line block Jacobi, -mg with one
-    multigrid cycle per iteration (K-cycle steps on levels 1 and 2), -mgv with a plain
+    multigrid cycle per iteration (K-cycle steps on levels 1 to 3), -mgv with a plain
     V-cycle; learned-fgmres runs the network inside flexible GMRES(m) instead of
     flexible CG."""
     parts = mode.split("-")

@@ -138,9 +138,11 @@ typedef struct {
                             (reduced or not) reach the GPU; every choice computes the same
                             method, DIRECT and GRAPH bit for bit alike */
     int inner;           /* rt_inner: the Krylov method of RT_SOLVE_LEARNED */
-    int cycle;           /* precond = 2: 0 = the coarse corrections of levels 1 and 2 are
-                            two flexible-CG steps each (K-cycle, the default), 1 = plain
-                            V-cycle (cheaper per iteration, more iterations) */
+    int cycle;           /* precond = 2: 0 = the coarse corrections of levels 1 to 3 are two
+                            flexible-CG steps each (K-cycle, the default), 1 = plain V-cycle
+                            (cheaper per iteration, more iterations), n = 2..8: K-cycle
+                            steps on levels 1 to n (each level deeper doubles the visits to
+                            the levels below it) */
 } rt_solve_opts;
 
 typedef enum {
@@ -333,7 +335,7 @@ rt_status rt_precond_apply(rt_ctx *ctx, const double *r, double *z);
 
 /* The multigrid preconditioner of precond = 2 (an extension of the implicit solve of
  * Eq. 15, not in the paper): z = M_mg r, one cycle for the current system, with the
- * K-cycle steps of cycle = 0 (the solver's default).  Levels:
+ * K-cycle steps of cycle = 0 (levels 1 to 3, the solver's default).  Levels:
  * A_0 = A^; A_(l+1) = P_l^T A_l P_l over aggregates of 1 x 2 x 2 cells (theta and phi
  * pairs merged, the radius kept; a lone last row where a size is odd), with P_l[f, C] =
  * B_f / Bc_C, B_0 = 1/s and Bc_C^2 the sum of B_f^2 over the aggregate; the last level
@@ -341,7 +343,7 @@ rt_status rt_precond_apply(rt_ctx *ctx, const double *r, double *z);
  * diagonal and phi couplings of each (r, theta) line (periodic).  Cycle: pre-smoothing
  * from 0, restriction of the residual by P^T, the coarse correction, prolongation by P,
  * post-smoothing; the coarse correction is the cycle one level down (V-cycle), or on
- * levels 1 and 2 two flexible-CG steps preconditioned by the cycle from that level
+ * levels 1 to 3 two flexible-CG steps preconditioned by the cycle from that level
  * (K-cycle: x = a_1 z_1 + a_2 (z_2 + beta z_1), beta = -(z_2.A z_1)/(z_1.A z_1), a =
  * p.r / p.A p), which makes the preconditioner nonlinear: the solver's outer CG is the
  * flexible one.  Float32 inside, set-up in float64 once per assembled system.  Device

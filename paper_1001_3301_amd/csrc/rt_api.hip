@@ -1048,7 +1048,12 @@ rt_status solve_fp64_line(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *s
 // the grid's theta and phi sizes down to one radial line), set up once per assembled
 // system.
 constexpr float kMgOmega = 0.8f;  // damping of the phi-line block-Jacobi smoother
-constexpr int kMgKLevels = 2;      // levels 1 .. kMgKLevels take K-cycle steps (when not the last)
+constexpr int kMgKLevels = 3;      // default: levels 1 .. kMgKLevels take K-cycle steps (when not the last)
+constexpr int kMgKMax = 8;         // the deepest level a solve may ask K-cycle steps of
+
+// The K-cycle depth a solve asks for: cycle 0 the default, 1 none (V-cycle), n >= 2
+// levels 1 .. n.
+int mg_kmax(const rt_solve_opts *o) { return o->cycle == 0 ? kMgKLevels : (o->cycle == 1 ? 0 : o->cycle); }
 
 rt_status mg_prepare(rt_ctx *ctx)
 {
@@ -1109,7 +1114,7 @@ rt_status mg_prepare(rt_ctx *ctx)
             if (l > 0) v.xr = f32(v.n);
         }
         h->kl.resize(L + 1);
-        for (int l = 1; l <= kMgKLevels && l < L && ok; l++) {
+        for (int l = 1; l <= kMgKMax && l < L && ok; l++) {
             const long nl = h->lev[l].n;
             h->kl[l] = MgKLevel{f32(nl), f32(nl), f32(nl), f64(4)};
         }
@@ -1148,7 +1153,7 @@ rt_status solve_fp64_mg(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st,
     DevScalars *h = ctx->h_sc;
     if (rt_status e = mg_prepare(ctx)) return e;
     MgHier &mg = *ctx->mg;
-    mg.kmax = o->cycle == 1 ? 0 : kMgKLevels;
+    mg.kmax = mg_kmax(o);
     h->thresh2 = o->tol * o->tol * bb;
     h->done = 0;
     h->iters = 0;
@@ -1207,7 +1212,7 @@ rt_status solve_mixed_mg(rt_ctx *ctx, const rt_solve_opts *o, rt_solve_stats *st
     DevScalars *h = ctx->h_sc;
     if (rt_status e = mg_prepare(ctx)) return e;
     MgHier &mg = *ctx->mg;
-    mg.kmax = o->cycle == 1 ? 0 : kMgKLevels;
+    mg.kmax = mg_kmax(o);
     const double delta2 = 0.01;
     h->iters = 0;
     h->done = 0;
@@ -1549,7 +1554,8 @@ rt_status rt_fld_solve(rt_ctx *ctx, const rt_solve_opts *o, double *E, rt_solve_
              "unknown solve mode");
     RT_CHECK(ctx, o->mode != RT_SOLVE_LEARNED || o->net, "learned mode needs a network");
     RT_CHECK(ctx, o->inner == RT_INNER_FCG || o->inner == RT_INNER_FGMRES, "inner must be an rt_inner value");
-    RT_CHECK(ctx, o->cycle == 0 || o->cycle == 1, "cycle must be 0 (K-cycle) or 1 (V-cycle)");
+    RT_CHECK(ctx, o->cycle >= 0 && o->cycle <= kMgKMax,
+             "cycle must be 0 (K-cycle steps on levels 1-3), 1 (V-cycle) or 2..8 (K-cycle steps on levels 1..cycle)");
     RT_CHECK(ctx, o->launch >= RT_LAUNCH_AUTO && o->launch <= RT_LAUNCH_BLOCK,
              "rt_fld_solve: launch must be an rt_launch value");
     RT_CHECK(ctx, o->precond == 0 || (o->precond == 1 && o->mode == RT_SOLVE_FP64 && !o->reduce) ||

@@ -24,7 +24,7 @@ LAUNCH_AUTO, LAUNCH_DIRECT, LAUNCH_GRAPH, LAUNCH_BLOCK = 0, 1, 2, 3
 INNER_FCG, INNER_FGMRES = 0, 1
 LANES_BINS, LANES_CELLS = 0, 1
 PRECOND_JACOBI, PRECOND_LINE, PRECOND_MG = 0, 1, 2
-CYCLE_K, CYCLE_V = 0, 1
+CYCLE_K, CYCLE_V = 0, 1  # cycle = n >= 2: K-cycle steps on levels 1 .. n
 
 dp = C.POINTER(C.c_double)
 

@@ -15,7 +15,7 @@ itself, independently of the HIP code, so that its pieces can be compared one by
   (r, theta) line, periodic), x <- x + omega M^-1 (b - A x).
 * cycle: pre-smoothing from zero, the residual restricted by P^T, the coarse
   correction, prolonged by P, post-smoothing; the coarsest line is solved exactly.  The
-  coarse correction of levels 1 and 2 (the K levels, when not the last) is two steps of
+  coarse correction of levels 1 to 3 (the K levels, when not the last) is two steps of
   flexible CG on that level preconditioned by the cycle from it (Notay's K-cycle):
   x = a1 p1 + a2 p2, p1 = z1, p2 = z2 + beta p1, beta = -(z2.q1)/(p1.q1), q = A p,
   a = (p.r)/(p.q); elsewhere the cycle one level down (a V-cycle).
@@ -177,7 +177,7 @@ def radial_solve(lv, b):
 
 
 class Hierarchy:
-    def __init__(self, shape, ahat, s, omega=0.8, dtype=np.float64, klevels=(1, 2)):
+    def __init__(self, shape, ahat, s, omega=0.8, dtype=np.float64, klevels=(1, 2, 3)):
         nr, nt, nph = shape
         n = nr * nt * nph
         a = np.asarray(ahat, dtype=np.float64).reshape(3, nph, nt, nr)

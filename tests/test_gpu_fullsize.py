@@ -250,7 +250,7 @@ def test_fullsize_solves_against_oracle(fullsize, oracle_c5, mode):
 @pytest.mark.parametrize("cycle", ["K", "V"])
 def test_fullsize_multigrid_solves_against_oracle(fullsize, oracle_c5, cycle):
     """The multigrid-preconditioned float64 CG at full size, with K-cycle steps on levels
-    1 and 2 or a plain V-cycle: the oracle's residual of the answer meets the tolerance,
+    1 to 3 or a plain V-cycle: the oracle's residual of the answer meets the tolerance,
     the oracle's Newton step from it gives the GPU's temperature, the temperature agrees
     with the float64 Jacobi-CG solve's, in a small fraction of its iterations."""
     from paper_1001_3301_amd import rt

@@ -110,12 +110,12 @@ def test_vcycle_matches_the_reference_cycle(case):
     assert d <= bound, (d, bound)
 
 
-@pytest.mark.parametrize("cycle", ["K", "V"])
+@pytest.mark.parametrize("cycle", ["K", "V", "K5"])
 @pytest.mark.parametrize("case", ["ragged-61x13x5-nu61", "axisym-64x16x1-nu32", "thick-40x9x4-nu64",
                                   "phi2-24x6x2", "phi3-20x7x3", "line-33x1x1"])
 def test_multigrid_solve_against_dense_oracle(case, cycle):
-    """CG with one multigrid cycle per iteration (K-cycle steps on levels 1 and 2, or a
-    plain V-cycle) to 1e-13 against the oracle's dense Cholesky solve of the scaled system
+    """CG with one multigrid cycle per iteration (K-cycle steps on levels 1 to 3 or 1 to 5,
+    or a plain V-cycle) to 1e-13 against the oracle's dense Cholesky solve of the scaled system
     (the bounds of the other float64 solves' dense tests): the oracle's residual of the
     answer, the scaled solution within 1e-8, the temperature of Eq. 16 within 1e-11."""
     from paper_1001_3301_amd import rt
@@ -123,7 +123,7 @@ def test_multigrid_solve_against_dense_oracle(case, cycle):
     P, ctx, T, S, En, ref, sysv = _system(wl)
     E = _d(En)
     rc, st = ctx.solve(E, rt.solve_opts(rt.MODE_FP64, tol=1e-13, max_iter=2000, precond=rt.PRECOND_MG,
-                                        cycle=rt.CYCLE_K if cycle == "K" else rt.CYCLE_V))
+                                        cycle={"K": rt.CYCLE_K, "V": rt.CYCLE_V, "K5": 5}[cycle]))
     yd = P.dense_solve(ref["ahat"], ref["bhat"])
     assert st["relres"] <= 1e-13
     assert st["iters"] <= 60, st
@@ -183,7 +183,7 @@ def test_multigrid_rejects_other_modes():
     P, ctx, T, S, En, ref, sysv = _system(wl)
     for o in (rt.solve_opts(rt.MODE_GMRES, precond=2), rt.solve_opts(rt.MODE_FP64, precond=2, reduce=1),
               rt.solve_opts(rt.MODE_MIXED, precond=2, reduce=1), rt.solve_opts(rt.MODE_FP64, precond=3),
-              rt.solve_opts(rt.MODE_FP64, precond=2, cycle=2)):
+              rt.solve_opts(rt.MODE_FP64, precond=2, cycle=9), rt.solve_opts(rt.MODE_FP64, precond=2, cycle=-1)):
         rc, st = ctx.solve(_d(En), o, raise_on_error=False)
         assert rc == rt.RT_EINVAL
     with pytest.raises(Exception):

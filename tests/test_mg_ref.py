@@ -199,7 +199,7 @@ def test_cg_with_the_vcycle_on_an_oracle_system():
     """On the system the oracle assembles for a clumpy 32 x 16 x 32 grid, CG with one
     V-cycle per iteration meets 1e-8 in at most 25 iterations (Jacobi CG takes about ten
     times as many), in float64 and with the cycle in float32; flexible CG with the
-    K-cycle in at most 15."""
+    K-cycle in at most 12."""
     import oracle
     from paper_1001_3301_amd import synth as sy
     shape = (32, 16, 32)
@@ -222,7 +222,7 @@ def test_cg_with_the_vcycle_on_an_oracle_system():
         assert P.relres(out["ahat"], b, x) <= 1e-8
     assert it_cg >= 5 * it
     Hk = mg_ref.Hierarchy(shape, out["ahat"], out["s"], dtype=np.float32)
-    assert Hk.klevels == (1, 2)
+    assert Hk.klevels == (1, 2, 3)
     itk, x = _fcg(A, b, Hk.apply)
-    assert itk <= 15 and itk < it, (itk, it)
+    assert itk <= 12 and itk < it, (itk, it)
     assert P.relres(out["ahat"], b, x) <= 1e-8
