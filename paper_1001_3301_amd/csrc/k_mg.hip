@@ -1,8 +1,8 @@
 // Multigrid preconditioner for CG on the Jacobi-scaled FLD operator A^ (the implicit
 // solve of Eq. 15).  Not part of the paper, which preconditions its Krylov solve by
-// block Jacobi: a V-cycle whose cost per CG iteration is a few sweeps over the grid
-// and whose iteration count grows slowly with the grid, where Jacobi CG's grows with
-// the number of cells along a line.
+// block Jacobi: a cycle whose cost per CG iteration is a few sweeps over the grid and
+// whose iteration count grows slowly with the grid, where Jacobi CG's grows with the
+// number of cells along a line.
 //
 // Levels.  A_0 = A^ (unit diagonal; couplings ar / at / ap to the +r / +theta / +phi
 // neighbour, periodic in phi).  A_(l+1) = P_l^T A_l P_l with aggregates of 1 x 2 x 2
@@ -23,10 +23,16 @@
 // so that y_0 = g . rhs is summed during the forward sweep and the correction
 // y - (v.y / (1 + v.q)) q is applied during the backward sweep (two passes per sweep).
 //
+// Cycle.  Pre-sweep from zero, restriction of the residual, the coarse correction,
+// its prolongation (inside the residual kernel of the post-sweep), post-sweep.  The
+// coarse correction is the cycle one level down (V-cycle) or, on the K levels (1 to 3
+// by default), two flexible-CG steps on that level preconditioned by the cycle from it
+// (K-cycle): the preconditioner is then nonlinear, and the outer CG flexible.
+//
 // Work layout: one thread per (r, theta) line walking phi, lanes on consecutive radii,
 // so every access of a step is one coalesced row segment.  The set-up runs in float64;
-// the V-cycle stores and computes in float32 (the outer CG keeps float64 vectors, dots
-// and the true residual).
+// the cycle stores and computes in float32 with float64 dots (the outer CG keeps
+// float64 vectors, dots and the true residual).
 #include <algorithm>
 #include <type_traits>
 
