@@ -261,26 +261,6 @@ __global__ __launch_bounds__(kMB) void k_mg_radial_inverse(int nr, const double 
 
 // ------------------------------------------------------------------ V-cycle (float32)
 
-// A_l x at cell c = (i, j, k) of a level (unit diagonal when dg is null).  Cell indices
-// are 32-bit (the hierarchy is built for grids below 2^31 cells).
-__device__ __forceinline__ float mg_ax(const MgLevel &L, unsigned nr, const float *__restrict__ x, unsigned c,
-                                      unsigned i, unsigned j, unsigned k)
-{
-    const unsigned plane = nr * (unsigned)L.nt, np = (unsigned)L.np;
-    float v = (L.dg ? L.dg[c] : 1.0f) * x[c];
-    if (i + 1 < nr) v = fmaf(L.ar[c], x[c + 1], v);
-    if (i > 0) v = fmaf(L.ar[c - 1], x[c - 1], v);
-    if (j + 1 < (unsigned)L.nt) v = fmaf(L.at[c], x[c + nr], v);
-    if (j > 0) v = fmaf(L.at[c - nr], x[c - nr], v);
-    if (np > 1) {
-        const unsigned cp1 = k + 1 < np ? c + plane : c - (np - 1) * plane;
-        const unsigned cm1 = k > 0 ? c - plane : c + (np - 1) * plane;
-        v = fmaf(L.ap[c], x[cp1], v);
-        v = fmaf(L.ap[cm1], x[cm1], v);
-    }
-    return v;
-}
-
 // Block sum of a float64 per-thread value (valid in thread 0).
 __device__ __forceinline__ double mg_block_sum(double v, double *sh)
 {
@@ -440,39 +420,97 @@ __global__ __launch_bounds__(kMB) void k_mg_line(int nr, MgLevel L, const BT *rh
     if (DOT) mg_finish_dot(acc, acq, partials, counter, sc, restart);
 }
 
-// rhs = b - A x' on one level, one cell per thread, where x' = x + P xc: the coarse
-// correction prolonged on the fly, at the cell and its six neighbours; x' goes to xo
-// for the sweep that follows.
+// The block's place in the launch with each XCD dealt a contiguous range: consecutive
+// blocks go to the eight XCDs in turn, so block id is taken as the (id / 8)-th block of
+// XCD id % 8 (a bijection on [0, gridDim.x) for any grid size).
+__device__ __forceinline__ unsigned mg_xcd_block()
+{
+    const unsigned id = blockIdx.x, nb = gridDim.x;
+    const unsigned q = nb >> 3, rm = nb & 7, x = id & 7;
+    return x * q + min(x, rm) + (id >> 3);
+}
+
+// rhs = b - A x' on one level, where x' = x + P xc: the coarse correction prolonged on
+// the fly, at the cell and its six neighbours; x' goes to xo for the sweep that
+// follows.  Each thread walks kc consecutive phi planes of one (r, theta) line,
+// carrying x' and the phi coupling of the previous and current planes in registers, so
+// a phi plane is read once per walk instead of three times; the loads of kRU steps are
+// issued together.  Each XCD takes a contiguous range of blocks (chunk-major, line
+// blocks in order), so the theta neighbours, a few blocks away, are read through the
+// same L2.  The sums are formed in the order of the 7-point product (diagonal, +r, -r,
+// +theta, -theta, +phi, -phi).
+constexpr int kRU = 4;
+
 template <typename BT>
-__global__ __launch_bounds__(kMB) void k_mg_resid(int nr_, MgLevel F, int cnt_, const BT *__restrict__ b,
+__global__ __launch_bounds__(kMB) void k_mg_resid(int nr_, MgLevel F, int cnt_, int kc_, const BT *__restrict__ b,
                                                   const float *__restrict__ x, const float *__restrict__ xc,
                                                   float *__restrict__ xo, float *__restrict__ rhs,
                                                   const DevScalars *sc)
 {
     if (sc && sc->done) return;
-    const unsigned nr = nr_, nt = F.nt, np = F.np, cnt = cnt_;
-    const unsigned f = blockIdx.x * kMB + threadIdx.x;
-    if (f >= (unsigned)F.n) return;
-    const unsigned i = f % nr, rest = f / nr;
-    const unsigned j = rest % nt, k = rest / nt;
+    const unsigned nr = nr_, nt = F.nt, np = F.np, cnt = cnt_, kc = kc_;
+    const unsigned plane = nr * nt, nlb = (plane + kMB - 1) / kMB;
+    const unsigned lid = mg_xcd_block();
+    const unsigned ch = lid / nlb, line = (lid - ch * nlb) * kMB + threadIdx.x;
+    if (line >= plane) return;
+    const unsigned k0 = ch * kc, k1 = min(k0 + kc, np);
+    const unsigned i = line % nr, j = line / nr;
     const unsigned sj = nt > 1, sk = np > 1;
+    const float *__restrict__ w = F.w;
     auto xv = [&](unsigned c, unsigned ii, unsigned jj, unsigned kk) {
-        return fmaf(F.w[c], xc[ii + nr * ((jj >> sj) + cnt * (kk >> sk))], x[c]);
+        return fmaf(w[c], xc[ii + nr * ((jj >> sj) + cnt * (kk >> sk))], x[c]);
     };
-    const float x0 = xv(f, i, j, k);
-    float v = (F.dg ? F.dg[f] : 1.0f) * x0;
-    if (i + 1 < nr) v = fmaf(F.ar[f], xv(f + 1, i + 1, j, k), v);
-    if (i > 0) v = fmaf(F.ar[f - 1], xv(f - 1, i - 1, j, k), v);
-    if (j + 1 < nt) v = fmaf(F.at[f], xv(f + nr, i, j + 1, k), v);
-    if (j > 0) v = fmaf(F.at[f - nr], xv(f - nr, i, j - 1, k), v);
-    if (np > 1) {
-        const unsigned kp = k + 1 < np ? k + 1 : 0, km = k > 0 ? k - 1 : np - 1;
-        const unsigned cp1 = i + nr * (j + nt * kp), cm1 = i + nr * (j + nt * km);
-        v = fmaf(F.ap[f], xv(cp1, i, j, kp), v);
-        v = fmaf(F.ap[cm1], xv(cm1, i, j, km), v);
+    // neighbours clamped to the cell itself on the boundary faces (loaded, not used)
+    const unsigned ip = i + 1 < nr ? i + 1 : i, im = i > 0 ? i - 1 : i;
+    const unsigned jp = j + 1 < nt ? j + 1 : j, jm = j > 0 ? j - 1 : j;
+    const unsigned dip = ip - i, dim = i - im, djp = (jp - j) * nr, djm = (j - jm) * nr;
+    const unsigned km0 = k0 > 0 ? k0 - 1 : np - 1;
+    float xm = xv(line + plane * km0, i, j, km0);
+    float apm = F.ap[line + plane * km0];
+    float x0 = xv(line + plane * k0, i, j, k0);
+    for (unsigned kb = k0; kb < k1; kb += kRU) {
+        float xp[kRU], xrp[kRU], xrm[kRU], xtp[kRU], xtm[kRU];
+        float arp[kRU], arm[kRU], atp[kRU], atm[kRU], apf[kRU], dgv[kRU], bv[kRU];
+#pragma unroll
+        for (int u = 0; u < kRU; u++) {
+            const unsigned k = min(kb + u, k1 - 1);
+            const unsigned f = line + plane * k;
+            const unsigned kp = k + 1 < np ? k + 1 : 0;
+            xp[u] = xv(line + plane * kp, i, j, kp);
+            xrp[u] = xv(f + dip, ip, j, k);
+            xrm[u] = xv(f - dim, im, j, k);
+            xtp[u] = xv(f + djp, i, jp, k);
+            xtm[u] = xv(f - djm, i, jm, k);
+            arp[u] = F.ar[f];
+            arm[u] = F.ar[f - dim];
+            atp[u] = F.at[f];
+            atm[u] = F.at[f - djm];
+            apf[u] = F.ap[f];
+            dgv[u] = F.dg ? F.dg[f] : 1.0f;
+            bv[u] = (float)b[f];
+        }
+#pragma unroll
+        for (int u = 0; u < kRU; u++) {
+            const unsigned k = kb + u;
+            if (k < k1) {
+                const unsigned f = line + plane * k;
+                float v = dgv[u] * x0;
+                if (i + 1 < nr) v = fmaf(arp[u], xrp[u], v);
+                if (i > 0) v = fmaf(arm[u], xrm[u], v);
+                if (j + 1 < nt) v = fmaf(atp[u], xtp[u], v);
+                if (j > 0) v = fmaf(atm[u], xtm[u], v);
+                if (np > 1) {
+                    v = fmaf(apf[u], xp[u], v);
+                    v = fmaf(apm, xm, v);
+                }
+                rhs[f] = bv[u] - v;
+                xo[f] = x0;
+                xm = x0;
+                x0 = xp[u];
+                apm = apf[u];
+            }
+        }
     }
-    rhs[f] = (float)b[f] - v;
-    xo[f] = x0;
 }
 
 // The cycle's right-hand side in float32.
@@ -485,28 +523,100 @@ __global__ __launch_bounds__(kMB) void k_mg_in(long n, const RT *__restrict__ r,
     if (c < n) b[c] = (float)r[c];
 }
 
-// bc = P^T (b - A x) on the next level: one coarse cell per thread, the residuals of
-// its children weighted by w (b: float64 on the finest level, the CG residual).
+// bc = P^T (b - A x) on the next level: the residuals of a coarse cell's children
+// weighted by w and summed phi plane by phi plane, theta row by row (b: float64 on the
+// finest level, the CG residual).  Each thread walks the fine phi planes under kc
+// consecutive coarse planes of one coarse (r, theta) line, its one or two child rows
+// side by side, carrying x and the phi coupling of the previous and current planes in
+// registers as the residual kernel does; blocks are dealt to the XCDs the same way.
 template <typename BT>
-__global__ __launch_bounds__(kMB) void k_mg_restrict(int nr_, MgLevel F, int cnt, int cnp, const BT *__restrict__ b,
+__global__ __launch_bounds__(kMB) void k_mg_restrict(int nr_, MgLevel F, int cnt_, int kc_, const BT *__restrict__ b,
                                                      const float *__restrict__ x, float *__restrict__ bc,
                                                      const DevScalars *sc)
 {
     if (sc && sc->done) return;
-    const unsigned nr = nr_, nt = F.nt, np = F.np;
-    const unsigned cc = blockIdx.x * kMB + threadIdx.x;
-    if (cc >= nr * (unsigned)cnt * (unsigned)cnp) return;
-    const unsigned i = cc % nr, rest = cc / nr;
-    const unsigned J = rest % (unsigned)cnt, K = rest / (unsigned)cnt;
-    const unsigned ft = nt > 1 ? 2 : 1, fp = np > 1 ? 2 : 1;
-    const unsigned j1 = min(ft * J + ft, nt), k1 = min(fp * K + fp, np);
+    const unsigned nr = nr_, nt = F.nt, np = F.np, cnt = cnt_, kc = kc_;
+    const unsigned cplane = nr * cnt, nlb = (cplane + kMB - 1) / kMB, plane = nr * nt;
+    const unsigned lid = mg_xcd_block();
+    const unsigned ch = lid / nlb, cl = (lid - ch * nlb) * kMB + threadIdx.x;
+    if (cl >= cplane) return;
+    const unsigned i = cl % nr, J = cl / nr;
+    const unsigned sk = np > 1, ft = nt > 1 ? 2 : 1;
+    const unsigned j0 = ft * J, nj = (ft == 2 && j0 + 1 < nt) ? 2 : 1;
+    const unsigned k0 = (ch * kc) << sk, k1 = min((ch * kc + kc) << sk, np);
+    const unsigned dip = i + 1 < nr ? 1 : 0, dim = i > 0 ? 1 : 0;
+    // the child rows (a lone row repeated: loaded, not used)
+    unsigned jr[2], ln[2], djp[2], djm[2];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        jr[r] = min(j0 + r, nt - 1);
+        ln[r] = i + nr * jr[r];
+        djp[r] = jr[r] + 1 < nt ? nr : 0;
+        djm[r] = jr[r] > 0 ? nr : 0;
+    }
+    const unsigned km0 = k0 > 0 ? k0 - 1 : np - 1;
+    float xm[2], apm[2], x0[2];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        xm[r] = x[ln[r] + plane * km0];
+        apm[r] = F.ap[ln[r] + plane * km0];
+        x0[r] = x[ln[r] + plane * k0];
+    }
     float acc = 0.0f;
-    for (unsigned k = fp * K; k < k1; k++)
-        for (unsigned j = ft * J; j < j1; j++) {
-            const unsigned f = i + nr * (j + nt * k);
-            acc = fmaf(F.w[f], (float)b[f] - mg_ax(F, nr, x, f, i, j, k), acc);
+    for (unsigned kb = k0; kb < k1; kb += kRU) {
+        float xp[kRU][2], xrp[kRU][2], xrm[kRU][2], xtp[kRU][2], xtm[kRU][2];
+        float arp[kRU][2], arm[kRU][2], atp[kRU][2], atm[kRU][2], apf[kRU][2], dgv[kRU][2], bv[kRU][2], wv[kRU][2];
+#pragma unroll
+        for (int u = 0; u < kRU; u++) {
+            const unsigned k = min(kb + u, k1 - 1);
+            const unsigned kp = k + 1 < np ? k + 1 : 0;
+#pragma unroll
+            for (int r = 0; r < 2; r++) {
+                const unsigned f = ln[r] + plane * k;
+                xp[u][r] = x[ln[r] + plane * kp];
+                xrp[u][r] = x[f + dip];
+                xrm[u][r] = x[f - dim];
+                xtp[u][r] = x[f + djp[r]];
+                xtm[u][r] = x[f - djm[r]];
+                arp[u][r] = F.ar[f];
+                arm[u][r] = F.ar[f - dim];
+                atp[u][r] = F.at[f];
+                atm[u][r] = F.at[f - djm[r]];
+                apf[u][r] = F.ap[f];
+                dgv[u][r] = F.dg ? F.dg[f] : 1.0f;
+                bv[u][r] = (float)b[f];
+                wv[u][r] = F.w[f];
+            }
         }
-    bc[cc] = acc;
+#pragma unroll
+        for (int u = 0; u < kRU; u++) {
+            const unsigned k = kb + u;
+            if (k < k1) {
+#pragma unroll
+                for (int r = 0; r < 2; r++) {
+                    if (r < (int)nj) {
+                        float v = dgv[u][r] * x0[r];
+                        if (dip) v = fmaf(arp[u][r], xrp[u][r], v);
+                        if (dim) v = fmaf(arm[u][r], xrm[u][r], v);
+                        if (djp[r]) v = fmaf(atp[u][r], xtp[u][r], v);
+                        if (djm[r]) v = fmaf(atm[u][r], xtm[u][r], v);
+                        if (np > 1) {
+                            v = fmaf(apf[u][r], xp[u][r], v);
+                            v = fmaf(apm[r], xm[r], v);
+                        }
+                        acc = fmaf(wv[u][r], bv[u][r] - v, acc);
+                    }
+                    xm[r] = x0[r];
+                    x0[r] = xp[u][r];
+                    apm[r] = apf[u][r];
+                }
+                if (k + 1 == k1 || ((k + 1) >> sk) != (k >> sk)) {
+                    bc[i + nr * (J + cnt * (k >> sk))] = acc;
+                    acc = 0.0f;
+                }
+            }
+        }
+    }
 }
 
 // The coarsest level: x = A_L^-1 b by the stored inverse (symmetric; one block per row,
@@ -669,6 +779,31 @@ __global__ __launch_bounds__(kMB) void k_kc_upd(long n_, float *__restrict__ x, 
 
 static unsigned mg_blocks(long n) { return (unsigned)((n + kMB - 1) / kMB); }
 
+// The residual's phi planes per thread: 16 on the large levels (4M cells or more, at
+// least 256K threads), else kRU (one batch of loads, the latency of one cell).
+static unsigned mg_resid_planes(long cells) { return cells >= (1L << 22) ? 16u : (unsigned)kRU; }
+
+// The restriction's coarse phi planes per thread: 8 (16 fine planes) on the large
+// levels, else 2 (one batch of kRU fine planes).
+template <typename BT>
+static void launch_mg_restrict(int nr, const MgLevel &F, const MgLevel &C, const BT *b, const float *x, float *bc,
+                               const DevScalars *sc, hipStream_t st)
+{
+    const unsigned kc = F.n >= (1L << 22) ? 8u : 2u;
+    const unsigned nb = mg_blocks((long)nr * C.nt) * (unsigned)((C.np + kc - 1) / kc);
+    hipLaunchKernelGGL((k_mg_restrict<BT>), dim3(nb), dim3(kMB), 0, st, nr, F, C.nt, (int)kc, b, x, bc, sc);
+}
+
+template <typename BT>
+static void launch_mg_resid(int nr, const MgLevel &F, int cnt, const BT *b, const float *x, const float *xc, float *xo,
+                            float *rhs, const DevScalars *sc, hipStream_t st)
+{
+    const long lines = (long)nr * F.nt;
+    const unsigned kc = mg_resid_planes(F.n);
+    const unsigned nb = mg_blocks(lines) * (unsigned)((F.np + kc - 1) / kc);
+    hipLaunchKernelGGL((k_mg_resid<BT>), dim3(nb), dim3(kMB), 0, st, nr, F, cnt, (int)kc, b, x, xc, xo, rhs, sc);
+}
+
 void mg_shapes(int nt, int np, std::vector<std::pair<int, int>> &out)
 {
     out.clear();
@@ -734,11 +869,9 @@ static void mg_cycle(MgRun &R, int l, const float *b, float *out)
     hipLaunchKernelGGL((k_mg_line<true, float, false>), dim3(gl), dim3(kMB), 0, R.st, nr, F, b, (const float *)nullptr,
                        F.x, (double *)nullptr, (const double *)nullptr, (const double *)nullptr, R.omega,
                        (double *)nullptr, (unsigned *)nullptr, R.sc, 0);
-    hipLaunchKernelGGL(k_mg_restrict<float>, dim3(mg_blocks(C.n)), dim3(kMB), 0, R.st, nr, F, C.nt, C.np, b,
-                       (const float *)F.x, C.b, (const DevScalars *)R.sc);
+    launch_mg_restrict<float>(nr, F, C, b, F.x, C.b, R.sc, R.st);
     mg_solve_level(R, l + 1, C.b, C.xr);
-    hipLaunchKernelGGL((k_mg_resid<float>), dim3(mg_blocks(F.n)), dim3(kMB), 0, R.st, nr, F, C.nt, b,
-                       (const float *)F.x, (const float *)C.xr, F.x2, F.dp, (const DevScalars *)R.sc);
+    launch_mg_resid<float>(nr, F, C.nt, b, F.x, C.xr, F.x2, F.dp, R.sc, R.st);
     hipLaunchKernelGGL((k_mg_line<false, float, false>), dim3(gl), dim3(kMB), 0, R.st, nr, F, (const float *)F.dp,
                        (const float *)F.x2, out, (double *)nullptr, (const double *)nullptr, (const double *)nullptr,
                        R.omega, (double *)nullptr, (unsigned *)nullptr, R.sc, 0);
@@ -809,11 +942,9 @@ static void mg_vcycle(MgHier &h, const RT *r, double *z64, const double *qold, f
     hipLaunchKernelGGL((k_mg_line<true, RT, false>), dim3(gl), dim3(kMB), 0, st, nr, F, r, (const float *)nullptr, F.x,
                        (double *)nullptr, (const double *)nullptr, (const double *)nullptr, omega, (double *)nullptr,
                        (unsigned *)nullptr, sc, 0);
-    hipLaunchKernelGGL(k_mg_restrict<RT>, dim3(mg_blocks(C.n)), dim3(kMB), 0, st, nr, F, C.nt, C.np, r,
-                       (const float *)F.x, C.b, csc);
+    launch_mg_restrict<RT>(nr, F, C, r, F.x, C.b, csc, st);
     mg_solve_level(R, 1, C.b, C.xr);
-    hipLaunchKernelGGL((k_mg_resid<RT>), dim3(mg_blocks(F.n)), dim3(kMB), 0, st, nr, F, C.nt, r, (const float *)F.x,
-                       (const float *)C.xr, F.x2, F.b, csc);
+    launch_mg_resid<RT>(nr, F, C.nt, r, F.x, C.xr, F.x2, F.b, csc, st);
     bool wrote = false;
     if constexpr (std::is_same<RT, double>::value)
         if (z64) {
