@@ -686,40 +686,80 @@ __device__ __forceinline__ void mg_block_partials(const double (&v)[N], double *
 }
 
 // A z on a level and the step's products, as block partials; FIRST writes q_1 = A z_1.
+// The work is cut as in the residual kernel, a thread walking kc phi planes of one
+// (r, theta) line with the phi neighbours in registers, and the blocks loop over these
+// units (line block, chunk) when there are more than gridDim.x of them.
 template <bool FIRST>
-__global__ __launch_bounds__(kMB) void k_kc_az(int nr_, MgLevel F, const float *__restrict__ z,
+__global__ __launch_bounds__(kMB) void k_kc_az(int nr_, MgLevel F, int kc_, const float *__restrict__ z,
                                                const float *__restrict__ p1, const float *__restrict__ q1,
                                                const float *__restrict__ r, float *__restrict__ qout,
                                                double *partials, const DevScalars *sc)
 {
     if (sc && sc->done) return;
-    const unsigned nr = nr_, nt = F.nt, np = F.np, n = (unsigned)F.n;
+    const unsigned nr = nr_, nt = F.nt, np = F.np, kc = kc_;
+    const unsigned plane = nr * nt, nlb = (plane + kMB - 1) / kMB, units = nlb * ((np + kc - 1) / kc);
     double acc[kKcSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (unsigned f = blockIdx.x * kMB + threadIdx.x; f < n; f += gridDim.x * kMB) {
-        const unsigned i = f % nr, rest = f / nr;
-        const unsigned j = rest % nt, k = rest / nt;
-        const float z0 = z[f];
-        float v = (F.dg ? F.dg[f] : 1.0f) * z0;
-        if (i + 1 < nr) v = fmaf(F.ar[f], z[f + 1], v);
-        if (i > 0) v = fmaf(F.ar[f - 1], z[f - 1], v);
-        if (j + 1 < nt) v = fmaf(F.at[f], z[f + nr], v);
-        if (j > 0) v = fmaf(F.at[f - nr], z[f - nr], v);
-        if (np > 1) {
-            const unsigned kp = k + 1 < np ? k + 1 : 0, km = k > 0 ? k - 1 : np - 1;
-            const unsigned cp1 = i + nr * (j + nt * kp), cm1 = i + nr * (j + nt * km);
-            v = fmaf(F.ap[f], z[cp1], v);
-            v = fmaf(F.ap[cm1], z[cm1], v);
-        }
-        const double zd = z0, vd = v, rd = r[f];
-        acc[0] += zd * vd;
-        acc[1] += zd * rd;
-        if (FIRST) {
-            qout[f] = v;
-        } else {
-            const double pd = p1[f];
-            acc[2] += zd * (double)q1[f];
-            acc[3] += pd * vd;
-            acc[4] += pd * rd;
+    for (unsigned uid = mg_xcd_block(); uid < units; uid += gridDim.x) {
+        const unsigned ch = uid / nlb, line = (uid - ch * nlb) * kMB + threadIdx.x;
+        if (line >= plane) continue;
+        const unsigned k0 = ch * kc, k1 = min(k0 + kc, np);
+        const unsigned i = line % nr, j = line / nr;
+        const unsigned dip = i + 1 < nr ? 1 : 0, dim = i > 0 ? 1 : 0;
+        const unsigned djp = j + 1 < nt ? nr : 0, djm = j > 0 ? nr : 0;
+        const unsigned km0 = k0 > 0 ? k0 - 1 : np - 1;
+        float zm = z[line + plane * km0], apm = F.ap[line + plane * km0], z0 = z[line + plane * k0];
+        for (unsigned kb = k0; kb < k1; kb += kRU) {
+            float zp[kRU], zrp[kRU], zrm[kRU], ztp[kRU], ztm[kRU];
+            float arp[kRU], arm[kRU], atp[kRU], atm[kRU], apf[kRU], dgv[kRU], rv[kRU], pv[kRU], qv[kRU];
+#pragma unroll
+            for (int u = 0; u < kRU; u++) {
+                const unsigned k = min(kb + u, k1 - 1);
+                const unsigned f = line + plane * k;
+                const unsigned kp = k + 1 < np ? k + 1 : 0;
+                zp[u] = z[line + plane * kp];
+                zrp[u] = z[f + dip];
+                zrm[u] = z[f - dim];
+                ztp[u] = z[f + djp];
+                ztm[u] = z[f - djm];
+                arp[u] = F.ar[f];
+                arm[u] = F.ar[f - dim];
+                atp[u] = F.at[f];
+                atm[u] = F.at[f - djm];
+                apf[u] = F.ap[f];
+                dgv[u] = F.dg ? F.dg[f] : 1.0f;
+                rv[u] = r[f];
+                pv[u] = FIRST ? 0.0f : p1[f];
+                qv[u] = FIRST ? 0.0f : q1[f];
+            }
+#pragma unroll
+            for (int u = 0; u < kRU; u++) {
+                const unsigned k = kb + u;
+                if (k < k1) {
+                    float v = dgv[u] * z0;
+                    if (dip) v = fmaf(arp[u], zrp[u], v);
+                    if (dim) v = fmaf(arm[u], zrm[u], v);
+                    if (djp) v = fmaf(atp[u], ztp[u], v);
+                    if (djm) v = fmaf(atm[u], ztm[u], v);
+                    if (np > 1) {
+                        v = fmaf(apf[u], zp[u], v);
+                        v = fmaf(apm, zm, v);
+                    }
+                    const double zd = z0, vd = v, rd = rv[u];
+                    acc[0] += zd * vd;
+                    acc[1] += zd * rd;
+                    if (FIRST) {
+                        qout[line + plane * k] = v;
+                    } else {
+                        const double pd = pv[u];
+                        acc[2] += zd * (double)qv[u];
+                        acc[3] += pd * vd;
+                        acc[4] += pd * rd;
+                    }
+                    zm = z0;
+                    z0 = zp[u];
+                    apm = apf[u];
+                }
+            }
         }
     }
     mg_block_partials<kKcSums>(acc, partials);
@@ -887,16 +927,18 @@ static void mg_kcycle(MgRun &R, int l, float *b, float *out)
     MgKLevel &K = h.kl[l];
     const DevScalars *csc = R.sc;
     const unsigned gk = (unsigned)std::min<long>((F.n + 4 * kMB - 1) / (4 * kMB), kKcBlocks);  // >= 4 cells a thread
+    const unsigned kc = mg_resid_planes(F.n);
+    const unsigned ga = (unsigned)std::min<long>((long)mg_blocks((long)nr * F.nt) * ((F.np + kc - 1) / kc), kKcBlocks);
     mg_cycle(R, l, b, K.p1);
-    hipLaunchKernelGGL(k_kc_az<true>, dim3(gk), dim3(kMB), 0, R.st, nr, F, (const float *)K.p1, (const float *)nullptr,
-                       (const float *)nullptr, (const float *)b, K.q, h.kpart, csc);
-    hipLaunchKernelGGL(k_kc_fin<true>, dim3(1), dim3(kMB), 0, R.st, (int)gk, (const double *)h.kpart, K.ks, csc);
+    hipLaunchKernelGGL(k_kc_az<true>, dim3(ga), dim3(kMB), 0, R.st, nr, F, (int)kc, (const float *)K.p1,
+                       (const float *)nullptr, (const float *)nullptr, (const float *)b, K.q, h.kpart, csc);
+    hipLaunchKernelGGL(k_kc_fin<true>, dim3(1), dim3(kMB), 0, R.st, (int)ga, (const double *)h.kpart, K.ks, csc);
     hipLaunchKernelGGL(k_kc_upd<true>, dim3(gk), dim3(kMB), 0, R.st, F.n, out, (const float *)K.p1,
                        (const float *)nullptr, (const float *)K.q, b, (const double *)K.ks, csc);
     mg_cycle(R, l, b, K.z);
-    hipLaunchKernelGGL(k_kc_az<false>, dim3(gk), dim3(kMB), 0, R.st, nr, F, (const float *)K.z, (const float *)K.p1,
-                       (const float *)K.q, (const float *)b, (float *)nullptr, h.kpart, csc);
-    hipLaunchKernelGGL(k_kc_fin<false>, dim3(1), dim3(kMB), 0, R.st, (int)gk, (const double *)h.kpart, K.ks, csc);
+    hipLaunchKernelGGL(k_kc_az<false>, dim3(ga), dim3(kMB), 0, R.st, nr, F, (int)kc, (const float *)K.z,
+                       (const float *)K.p1, (const float *)K.q, (const float *)b, (float *)nullptr, h.kpart, csc);
+    hipLaunchKernelGGL(k_kc_fin<false>, dim3(1), dim3(kMB), 0, R.st, (int)ga, (const double *)h.kpart, K.ks, csc);
     hipLaunchKernelGGL(k_kc_upd<false>, dim3(gk), dim3(kMB), 0, R.st, F.n, out, (const float *)K.z,
                        (const float *)K.p1, (const float *)nullptr, b, (const double *)K.ks, csc);
 }
