@@ -29,8 +29,10 @@
 // by default), two flexible-CG steps on that level preconditioned by the cycle from it
 // (K-cycle): the preconditioner is then nonlinear, and the outer CG flexible.
 //
-// Work layout: one thread per (r, theta) line walking phi, lanes on consecutive radii,
-// so every access of a step is one coalesced row segment.  The set-up runs in float64;
+// Work layout: lanes on consecutive radii, so every access of a step is one coalesced
+// row segment.  The sweeps give a thread a whole (r, theta) line walking phi; the
+// residual, the restriction and the K-step stencil pass a run of phi planes of a line,
+// with the phi neighbours carried in registers.  The set-up runs in float64;
 // the cycle stores and computes in float32 with float64 dots (the outer CG keeps
 // float64 vectors, dots and the true residual).
 #include <algorithm>
@@ -773,15 +775,25 @@ __global__ __launch_bounds__(kMB) void k_kc_fin(int nblk, const double *__restri
                                                 const DevScalars *sc)
 {
     if (sc && sc->done) return;
-    __shared__ double sh[kMB / 64];
-    double t[kKcSums];
+    __shared__ double sh[kKcSums][kMB / 64];
+    double a[kKcSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += kMB)
+#pragma unroll
+        for (int u = 0; u < kKcSums; u++) a[u] += partials[kKcSums * b + u];
+    // the five block sums together (one barrier), each as mg_block_sum forms it
 #pragma unroll
     for (int u = 0; u < kKcSums; u++) {
-        double a = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += kMB) a += partials[kKcSums * b + u];
-        t[u] = mg_block_sum(a, sh);
+        for (int o = 32; o > 0; o >>= 1) a[u] += __shfl_xor(a[u], o);
+        if ((threadIdx.x & 63) == 0) sh[u][threadIdx.x >> 6] = a[u];
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        double t[kKcSums];
+#pragma unroll
+        for (int u = 0; u < kKcSums; u++) {
+            t[u] = 0.0;
+            for (int w = 0; w < kMB / 64; w++) t[u] += sh[u][w];
+        }
         if (FIRST) {  // p_1 = z_1, q_1 = A z_1
             ks[0] = t[0];
             ks[1] = t[0] != 0.0 ? t[1] / t[0] : 0.0;
