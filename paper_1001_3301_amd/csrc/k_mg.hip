@@ -151,6 +151,8 @@ struct MgLineOut {
 // last cell to the first; Thomas factors 1 / m_k and c_k = e_k / m_k of T, and q = T^-1 u,
 // g = T^-1 e_0, rho = e_(m-1) / gamma, kap = 1 / (1 + q_0 + rho q_(m-1)).  tm and td are
 // float64 scratch of the level's size.
+constexpr int kFU = 8;  // steps whose loads the set-up walks issue together
+
 __global__ __launch_bounds__(kMB) void k_mg_line_factor(int nr, MgSetLevel L, MgLineOut o, double *__restrict__ tm,
                                                         double *__restrict__ td)
 {
@@ -181,44 +183,86 @@ __global__ __launch_bounds__(kMB) void k_mg_line_factor(int nr, MgSetLevel L, Mg
     const double d0 = dgv(line), gam = -d0;
     const long cl = line + (long)(m - 1) * plane;
     const double ew = L.ap[cl];  // couples the last cell to the first
+    // Each pass is a sequential walk along the line; the loads of kFU consecutive steps
+    // are issued together before their part of the recurrence.
     // factor T: diagonal 2 d_0, d_k, d_(m-1) - ew^2 / gamma; off-diagonals e_k = ap_k
     double mk = d0 - gam, eprev = 0.0;
-    for (int k = 0; k < m; k++) {
-        const long c = line + (long)k * plane;
-        if (k > 0) {
-            double t = dgv(c);
-            if (k == m - 1) t -= ew * ew / gam;
-            mk = t - eprev * eprev / mk;
+    for (int k0 = 0; k0 < m; k0 += kFU) {
+        double dv[kFU], av[kFU];
+#pragma unroll
+        for (int u = 0; u < kFU; u++) {
+            const long c = line + (long)min(k0 + u, m - 1) * plane;
+            dv[u] = dgv(c);
+            av[u] = L.ap[c];
         }
-        tm[c] = 1.0 / mk;
-        o.im[c] = (float)(1.0 / mk);
-        const double e = (k < m - 1) ? L.ap[c] : 0.0;
-        o.cp[c] = (float)(e / mk);
-        eprev = e;
+#pragma unroll
+        for (int u = 0; u < kFU; u++) {
+            const int k = k0 + u;
+            if (k < m) {
+                const long c = line + (long)k * plane;
+                if (k > 0) {
+                    double t = dv[u];
+                    if (k == m - 1) t -= ew * ew / gam;
+                    mk = t - eprev * eprev / mk;
+                }
+                tm[c] = 1.0 / mk;
+                o.im[c] = (float)(1.0 / mk);
+                const double e = (k < m - 1) ? av[u] : 0.0;
+                o.cp[c] = (float)(e / mk);
+                eprev = e;
+            }
+        }
     }
     // two solves with T: u and e_0
     double q0 = 0.0, qm = 0.0;
     for (int s = 0; s < 2; s++) {
         double dprev = 0.0;
         eprev = 0.0;
-        for (int k = 0; k < m; k++) {
-            const long c = line + (long)k * plane;
-            const double rhs = s == 0 ? (k == 0 ? gam : (k == m - 1 ? ew : 0.0)) : (k == 0 ? 1.0 : 0.0);
-            dprev = (rhs - eprev * dprev) * tm[c];
-            td[c] = dprev;
-            eprev = (k < m - 1) ? L.ap[c] : 0.0;
+        for (int k0 = 0; k0 < m; k0 += kFU) {
+            double tv[kFU], av[kFU];
+#pragma unroll
+            for (int u = 0; u < kFU; u++) {
+                const long c = line + (long)min(k0 + u, m - 1) * plane;
+                tv[u] = tm[c];
+                av[u] = L.ap[c];
+            }
+#pragma unroll
+            for (int u = 0; u < kFU; u++) {
+                const int k = k0 + u;
+                if (k < m) {
+                    const long c = line + (long)k * plane;
+                    const double rhs = s == 0 ? (k == 0 ? gam : (k == m - 1 ? ew : 0.0)) : (k == 0 ? 1.0 : 0.0);
+                    dprev = (rhs - eprev * dprev) * tv[u];
+                    td[c] = dprev;
+                    eprev = (k < m - 1) ? av[u] : 0.0;
+                }
+            }
         }
         double y = 0.0;
-        for (int k = m - 1; k >= 0; k--) {
-            const long c = line + (long)k * plane;
-            const double e = (k < m - 1) ? L.ap[c] : 0.0;
-            y = td[c] - e * tm[c] * y;
-            if (s == 0) {
-                o.q[c] = (float)y;
-                if (k == 0) q0 = y;
-                if (k == m - 1) qm = y;
-            } else {
-                o.g[c] = (float)y;
+        for (int k0 = m - 1; k0 >= 0; k0 -= kFU) {
+            double dv[kFU], tv[kFU], av[kFU];
+#pragma unroll
+            for (int u = 0; u < kFU; u++) {
+                const long c = line + (long)max(k0 - u, 0) * plane;
+                dv[u] = td[c];
+                tv[u] = tm[c];
+                av[u] = L.ap[c];
+            }
+#pragma unroll
+            for (int u = 0; u < kFU; u++) {
+                const int k = k0 - u;
+                if (k >= 0) {
+                    const long c = line + (long)k * plane;
+                    const double e = (k < m - 1) ? av[u] : 0.0;
+                    y = dv[u] - e * tv[u] * y;
+                    if (s == 0) {
+                        o.q[c] = (float)y;
+                        if (k == 0) q0 = y;
+                        if (k == m - 1) qm = y;
+                    } else {
+                        o.g[c] = (float)y;
+                    }
+                }
             }
         }
     }
